@@ -1,0 +1,418 @@
+/*
+ * lforacle.c -- reference implementation (oracle) of one laplacianFoam time step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the GPU library it checks.
+ *
+ * What it computes (Section 5.1, Eq. 1 and Listing 1 of the paper; readings of
+ * what the paper leaves unstated are marked READING):
+ *   one implicit-Euler step of  dT/dt - div(DT grad T) = 0  on a finite-volume
+ *   mesh given in OpenFOAM face addressing (Section 4: owner / neighbour lists,
+ *   face normal from owner to neighbour), assembled into an LDU matrix
+ *   (diag, upper, lower = upper, source, per-boundary-face internal and
+ *   boundary coefficients) and solved by the preconditioned conjugate gradient
+ *   method with a diagonal or DIC preconditioner (Sections 5.1 and 6: PCG with
+ *   the diagonal preconditioner).
+ *
+ * Style: plain loops in the order the definitions state them, IEEE binary64,
+ * compiled with -O2 -ffp-contract=off -fno-fast-math, single thread.  Every
+ * sum runs sequentially in ascending index order.  No blocking, fusion or
+ * reordering.
+ *
+ * Parity pins (checked by the CPU tests, not by this file): dense brute-force
+ * stencil assembly on small boxes, numpy LU solve, 1-cell and 2-cell closed
+ * forms, the exact steady linear profile, the exact discrete decay of a cosine
+ * mode, the O(dx^2 + dt) decay of a sine mode, heat conservation, matrix
+ * symmetry / row sums / diagonal dominance, and PCG special cases.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <time.h>
+
+#define LFO_OK 0
+#define LFO_EINVAL (-1)
+#define LFO_ENOMEM (-3)
+
+#define BC_ZERO_GRADIENT 0
+#define BC_FIXED_VALUE 1
+
+#define PC_DIAGONAL 0
+#define PC_DIC 1
+
+typedef struct {
+    double initial_residual;
+    double final_residual;
+    int32_t n_iter;
+    int32_t converged;
+    int32_t singular;
+    int32_t pad;
+    double assemble_s;
+    double solve_s;
+} lfo_stats;
+
+static double now_s(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry (once per mesh).  READING: Gauss linear "corrected" Laplacian,   */
+/* whose orthogonal part uses delta_f = 1/max(n.d, 0.05|d|) with n the unit  */
+/* face normal and d = C_N - C_P; on boundary faces delta_b = 1/(n.(C_f-C_P)).*/
+/* ------------------------------------------------------------------------ */
+int lfo_face_geometry(int32_t n_faces, const int32_t *owner, const int32_t *neighbour,
+                      const double *cell_centre, const double *face_area,
+                      double *mag_sf, double *delta)
+{
+    for (int32_t f = 0; f < n_faces; ++f) {
+        const double *S = face_area + 3 * (size_t)f;
+        double m = sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+        double nx = S[0] / m, ny = S[1] / m, nz = S[2] / m;
+        const double *P = cell_centre + 3 * (size_t)owner[f];
+        const double *N = cell_centre + 3 * (size_t)neighbour[f];
+        double dx = N[0] - P[0], dy = N[1] - P[1], dz = N[2] - P[2];
+        double nd = nx * dx + ny * dy + nz * dz;
+        double dmag = sqrt(dx * dx + dy * dy + dz * dz);
+        double lim = 0.05 * dmag;
+        mag_sf[f] = m;
+        delta[f] = 1.0 / (nd > lim ? nd : lim);
+    }
+    return LFO_OK;
+}
+
+int lfo_bface_geometry(int32_t n_bfaces, const int32_t *bface_cell, const double *cell_centre,
+                       const double *bface_area, const double *bface_centre,
+                       double *bmag_sf, double *bdelta)
+{
+    for (int32_t b = 0; b < n_bfaces; ++b) {
+        const double *S = bface_area + 3 * (size_t)b;
+        double m = sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+        double nx = S[0] / m, ny = S[1] / m, nz = S[2] / m;
+        const double *P = cell_centre + 3 * (size_t)bface_cell[b];
+        const double *F = bface_centre + 3 * (size_t)b;
+        double dx = F[0] - P[0], dy = F[1] - P[1], dz = F[2] - P[2];
+        double nd = nx * dx + ny * dy + nz * dz;
+        bmag_sf[b] = m;
+        bdelta[b] = 1.0 / nd;
+    }
+    return LFO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Assembly of TEqn = ddt(T) - laplacian(DT, T)  (Listing 1).               */
+/*  laplacian (Gauss): lapU_f = delta_f * (DT*|S_f|); lap diag by negated  */
+/*   sum over the faces of each cell in face order; fixedValue boundary face */
+/*   b: internalCoeff = -(DT|S_b|) delta_b, boundaryCoeff = -(DT|S_b|)       */
+/*   (delta_b T_b); zeroGradient contributes nothing.                        */
+/*  ddt (READING: implicit Euler): diag (1/dt) V, source ((1/dt) T_old) V.  */
+/*  TEqn = ddt - laplacian, then the solve adds the boundary internal        */
+/*  coefficients to diag and the boundary coefficients to source.            */
+/* ------------------------------------------------------------------------ */
+int lfo_assemble(int32_t n_cells, int32_t n_faces, const int32_t *owner,
+                 const int32_t *neighbour, const double *cell_volume, const double *mag_sf,
+                 const double *delta, int32_t n_patches, const int32_t *patch_start,
+                 const int32_t *patch_type, const double *patch_value,
+                 const int32_t *bface_cell, const double *bmag_sf, const double *bdelta,
+                 double DT, double dt, const double *T_old,
+                 double *diag, double *upper, double *source,
+                 double *diag_b, double *source_b, double *int_coeff, double *bou_coeff)
+{
+    if (n_cells < 0 || n_faces < 0 || !(dt > 0.0))
+        return LFO_EINVAL;
+    double *lap_diag = (double *)malloc(sizeof(double) * (size_t)(n_cells > 0 ? n_cells : 1));
+    if (!lap_diag)
+        return LFO_ENOMEM;
+
+    /* laplacian: upper and negSumDiag */
+    for (int32_t c = 0; c < n_cells; ++c)
+        lap_diag[c] = 0.0;
+    for (int32_t f = 0; f < n_faces; ++f) {
+        double gamma_mag_sf = DT * mag_sf[f];
+        double lap_upper = delta[f] * gamma_mag_sf;
+        upper[f] = -lap_upper; /* TEqn upper = 0 - laplacian upper */
+        lap_diag[owner[f]] -= lap_upper; /* lower = upper (symmetric) */
+        lap_diag[neighbour[f]] -= lap_upper;
+    }
+
+    /* ddt (Euler) minus laplacian */
+    double rdt = 1.0 / dt;
+    for (int32_t c = 0; c < n_cells; ++c) {
+        double ddt_diag = rdt * cell_volume[c];
+        diag[c] = ddt_diag - lap_diag[c];
+        source[c] = (rdt * T_old[c]) * cell_volume[c];
+    }
+    free(lap_diag);
+
+    /* boundary coefficients of TEqn (= 0 - laplacian's) */
+    for (int32_t p = 0; p < n_patches; ++p) {
+        for (int32_t b = patch_start[p]; b < patch_start[p + 1]; ++b) {
+            if (patch_type[p] == BC_FIXED_VALUE) {
+                double gamma_b = DT * bmag_sf[b];
+                double lap_ic = gamma_b * (-bdelta[b]);
+                double lap_bc = -(gamma_b * (bdelta[b] * patch_value[p]));
+                int_coeff[b] = 0.0 - lap_ic;
+                bou_coeff[b] = 0.0 - lap_bc;
+            } else {
+                int_coeff[b] = 0.0;
+                bou_coeff[b] = 0.0;
+            }
+        }
+    }
+
+    /* solve-time matrix: add boundary diag and source, patch order, face order */
+    for (int32_t c = 0; c < n_cells; ++c) {
+        diag_b[c] = diag[c];
+        source_b[c] = source[c];
+    }
+    for (int32_t p = 0; p < n_patches; ++p) {
+        if (patch_type[p] != BC_FIXED_VALUE)
+            continue;
+        for (int32_t b = patch_start[p]; b < patch_start[p + 1]; ++b) {
+            diag_b[bface_cell[b]] += int_coeff[b];
+            source_b[bface_cell[b]] += bou_coeff[b];
+        }
+    }
+    return LFO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* LDU matrix-vector product: y = A x, diag first, then faces ascending.    */
+/* ------------------------------------------------------------------------ */
+int lfo_amul(int32_t n_cells, int32_t n_faces, const int32_t *owner, const int32_t *neighbour,
+             const double *diag, const double *upper, const double *x, double *y)
+{
+    for (int32_t c = 0; c < n_cells; ++c)
+        y[c] = diag[c] * x[c];
+    for (int32_t f = 0; f < n_faces; ++f) {
+        y[neighbour[f]] += upper[f] * x[owner[f]]; /* lower = upper */
+        y[owner[f]] += upper[f] * x[neighbour[f]];
+    }
+    return LFO_OK;
+}
+
+/* row sums of A: diag plus the off-diagonal coefficients of each row */
+int lfo_sum_a(int32_t n_cells, int32_t n_faces, const int32_t *owner, const int32_t *neighbour,
+              const double *diag, const double *upper, double *sum_a)
+{
+    for (int32_t c = 0; c < n_cells; ++c)
+        sum_a[c] = diag[c];
+    for (int32_t f = 0; f < n_faces; ++f) {
+        sum_a[owner[f]] += upper[f]; /* lower coefficient of row owner */
+        sum_a[neighbour[f]] += upper[f];
+    }
+    return LFO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Preconditioners.                                                          */
+/*  diagonal: rD = 1/diag, w = rD r.                                         */
+/*  DIC (READING: the classic diagonal incomplete Cholesky, Barrett et al.   */
+/*  "Templates", 1994): rD_c = diag_c - sum over lower faces (upper^2)/rD_l, */
+/*  in face order, then rD = 1/rD; apply w = rD r, a forward sweep           */
+/*  w_u -= rD_u upper w_l (faces ascending), a backward sweep                */
+/*  w_l -= rD_l upper w_u (faces descending).                                */
+/* ------------------------------------------------------------------------ */
+int lfo_dic_rd(int32_t n_cells, int32_t n_faces, const int32_t *owner, const int32_t *neighbour,
+               const double *diag, const double *upper, double *rd)
+{
+    for (int32_t c = 0; c < n_cells; ++c)
+        rd[c] = diag[c];
+    for (int32_t f = 0; f < n_faces; ++f)
+        rd[neighbour[f]] -= upper[f] * upper[f] / rd[owner[f]];
+    for (int32_t c = 0; c < n_cells; ++c)
+        rd[c] = 1.0 / rd[c];
+    return LFO_OK;
+}
+
+static void precondition(int pc, int32_t n_cells, int32_t n_faces, const int32_t *owner,
+                         const int32_t *neighbour, const double *upper, const double *rd,
+                         const double *r, double *w)
+{
+    for (int32_t c = 0; c < n_cells; ++c)
+        w[c] = rd[c] * r[c];
+    if (pc != PC_DIC)
+        return;
+    for (int32_t f = 0; f < n_faces; ++f)
+        w[neighbour[f]] -= rd[neighbour[f]] * upper[f] * w[owner[f]];
+    for (int32_t f = n_faces - 1; f >= 0; --f)
+        w[owner[f]] -= rd[owner[f]] * upper[f] * w[neighbour[f]];
+}
+
+int lfo_precondition(int pc, int32_t n_cells, int32_t n_faces, const int32_t *owner,
+                     const int32_t *neighbour, const double *upper, const double *rd,
+                     const double *r, double *w)
+{
+    precondition(pc, n_cells, n_faces, owner, neighbour, upper, rd, r, w);
+    return LFO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* PCG (READING: OpenFOAM's PCG semantics).                                  */
+/*  r = b - A x0;  normFactor = sum_c(|Ax0_c - pA_c| + |b_c - pA_c|) + 1e-20 */
+/*  with pA = (row sums of A) * mean(x0);  res = sum|r| / normFactor.        */
+/*  Converged iff res < tol or (relTol > 1e-20 and res < relTol res0).       */
+/*  Checked before the loop and after each iteration (the check after an     */
+/*  iteration is skipped once maxIter is reached).  Singular iff             */
+/*  |wApA|/normFactor < 1e-300, which ends the loop without counting the     */
+/*  iteration.                                                                */
+/* ------------------------------------------------------------------------ */
+static int check_conv(double res, double res0, double tol, double rel_tol)
+{
+    return (res < tol) || (rel_tol > 1e-20 && res < rel_tol * res0);
+}
+
+int lfo_pcg(int32_t n_cells, int32_t n_faces, const int32_t *owner, const int32_t *neighbour,
+            const double *diag, const double *upper, const double *b, double *x,
+            int pc, double tol, double rel_tol, int32_t max_iter, int32_t min_iter,
+            lfo_stats *st)
+{
+    size_t n = (size_t)(n_cells > 0 ? n_cells : 1);
+    double *wA = (double *)malloc(sizeof(double) * n);
+    double *rA = (double *)malloc(sizeof(double) * n);
+    double *pA = (double *)malloc(sizeof(double) * n);
+    double *rD = (double *)malloc(sizeof(double) * n);
+    if (!wA || !rA || !pA || !rD) {
+        free(wA); free(rA); free(pA); free(rD);
+        return LFO_ENOMEM;
+    }
+    st->n_iter = 0;
+    st->converged = 0;
+    st->singular = 0;
+
+    lfo_amul(n_cells, n_faces, owner, neighbour, diag, upper, x, wA);
+    for (int32_t c = 0; c < n_cells; ++c)
+        rA[c] = b[c] - wA[c];
+
+    /* normalisation factor */
+    lfo_sum_a(n_cells, n_faces, owner, neighbour, diag, upper, pA);
+    double sum_x = 0.0;
+    for (int32_t c = 0; c < n_cells; ++c)
+        sum_x += x[c];
+    double x_avg = sum_x / (double)n_cells;
+    for (int32_t c = 0; c < n_cells; ++c)
+        pA[c] *= x_avg;
+    double norm_factor = 0.0;
+    for (int32_t c = 0; c < n_cells; ++c)
+        norm_factor += fabs(wA[c] - pA[c]) + fabs(b[c] - pA[c]);
+    norm_factor += 1e-20;
+
+    double sum_mag = 0.0;
+    for (int32_t c = 0; c < n_cells; ++c)
+        sum_mag += fabs(rA[c]);
+    st->initial_residual = sum_mag / norm_factor;
+    st->final_residual = st->initial_residual;
+    st->converged = check_conv(st->final_residual, st->initial_residual, tol, rel_tol);
+
+    if (min_iter > 0 || !st->converged) {
+        if (pc == PC_DIC) {
+            lfo_dic_rd(n_cells, n_faces, owner, neighbour, diag, upper, rD);
+        } else {
+            for (int32_t c = 0; c < n_cells; ++c)
+                rD[c] = 1.0 / diag[c];
+        }
+        double wArA = 1e20, wArA_old;
+        for (;;) {
+            wArA_old = wArA;
+            precondition(pc, n_cells, n_faces, owner, neighbour, upper, rD, rA, wA);
+            wArA = 0.0;
+            for (int32_t c = 0; c < n_cells; ++c)
+                wArA += wA[c] * rA[c];
+            if (st->n_iter == 0) {
+                for (int32_t c = 0; c < n_cells; ++c)
+                    pA[c] = wA[c];
+            } else {
+                double beta = wArA / wArA_old;
+                for (int32_t c = 0; c < n_cells; ++c)
+                    pA[c] = wA[c] + beta * pA[c];
+            }
+            lfo_amul(n_cells, n_faces, owner, neighbour, diag, upper, pA, wA);
+            double wApA = 0.0;
+            for (int32_t c = 0; c < n_cells; ++c)
+                wApA += wA[c] * pA[c];
+            if (fabs(wApA) / norm_factor < 1e-300) {
+                st->singular = 1;
+                break;
+            }
+            double alpha = wArA / wApA;
+            for (int32_t c = 0; c < n_cells; ++c) {
+                x[c] += alpha * pA[c];
+                rA[c] -= alpha * wA[c];
+            }
+            sum_mag = 0.0;
+            for (int32_t c = 0; c < n_cells; ++c)
+                sum_mag += fabs(rA[c]);
+            st->final_residual = sum_mag / norm_factor;
+            ++st->n_iter;
+            if (st->n_iter < max_iter)
+                st->converged = check_conv(st->final_residual, st->initial_residual, tol,
+                                           rel_tol);
+            if (!((st->n_iter < max_iter && !st->converged) || st->n_iter < min_iter))
+                break;
+        }
+    }
+    free(wA); free(rA); free(pA); free(rD);
+    return LFO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Time loop (Listing 1 with one non-orthogonal pass and empty fvOptions):  */
+/* per step assemble, solve from x0 = T_old, commit T_new = x.              */
+/* ------------------------------------------------------------------------ */
+int lfo_run(int32_t n_cells, int32_t n_faces, const int32_t *owner, const int32_t *neighbour,
+            const double *cell_volume, const double *cell_centre, const double *face_area,
+            int32_t n_patches, const int32_t *patch_start, const int32_t *patch_type,
+            const double *patch_value, const int32_t *bface_cell, const double *bface_area,
+            const double *bface_centre, double DT, double dt, int32_t n_steps, int pc,
+            double tol, double rel_tol, int32_t max_iter, int32_t min_iter,
+            double *T, lfo_stats *stats)
+{
+    if (n_cells <= 0 || n_faces < 0 || n_patches < 0 || n_steps < 0 || !(dt > 0.0))
+        return LFO_EINVAL;
+    int32_t n_b = patch_start[n_patches];
+    size_t nc = (size_t)n_cells, nf = (size_t)(n_faces > 0 ? n_faces : 1);
+    size_t nb = (size_t)(n_b > 0 ? n_b : 1);
+    double *mag_sf = (double *)malloc(sizeof(double) * nf);
+    double *delta = (double *)malloc(sizeof(double) * nf);
+    double *bmag_sf = (double *)malloc(sizeof(double) * nb);
+    double *bdelta = (double *)malloc(sizeof(double) * nb);
+    double *diag = (double *)malloc(sizeof(double) * nc);
+    double *upper = (double *)malloc(sizeof(double) * nf);
+    double *source = (double *)malloc(sizeof(double) * nc);
+    double *diag_b = (double *)malloc(sizeof(double) * nc);
+    double *source_b = (double *)malloc(sizeof(double) * nc);
+    double *ic = (double *)malloc(sizeof(double) * nb);
+    double *bc = (double *)malloc(sizeof(double) * nb);
+    int rc = LFO_OK;
+    if (!mag_sf || !delta || !bmag_sf || !bdelta || !diag || !upper || !source || !diag_b ||
+        !source_b || !ic || !bc) {
+        rc = LFO_ENOMEM;
+        goto done;
+    }
+    lfo_face_geometry(n_faces, owner, neighbour, cell_centre, face_area, mag_sf, delta);
+    lfo_bface_geometry(n_b, bface_cell, cell_centre, bface_area, bface_centre, bmag_sf, bdelta);
+    for (int32_t s = 0; s < n_steps; ++s) {
+        double t0 = now_s();
+        rc = lfo_assemble(n_cells, n_faces, owner, neighbour, cell_volume, mag_sf, delta,
+                          n_patches, patch_start, patch_type, patch_value, bface_cell, bmag_sf,
+                          bdelta, DT, dt, T, diag, upper, source, diag_b, source_b, ic, bc);
+        if (rc != LFO_OK)
+            goto done;
+        double t1 = now_s();
+        rc = lfo_pcg(n_cells, n_faces, owner, neighbour, diag_b, upper, source_b, T, pc, tol,
+                     rel_tol, max_iter, min_iter, &stats[s]);
+        if (rc != LFO_OK)
+            goto done;
+        double t2 = now_s();
+        stats[s].assemble_s = t1 - t0;
+        stats[s].solve_s = t2 - t1;
+    }
+done:
+    free(mag_sf); free(delta); free(bmag_sf); free(bdelta); free(diag); free(upper);
+    free(source); free(diag_b); free(source_b); free(ic); free(bc);
+    return rc;
+}

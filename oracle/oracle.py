@@ -1,0 +1,201 @@
+"""ctypes wrapper of the C oracle (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg use this
+module.  It loads ``liblforacle.so`` built from ``lforacle.c`` by ``build.py``.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblforacle.so")
+
+PC_DIAGONAL = 0
+PC_DIC = 1
+BC_ZERO_GRADIENT = 0
+BC_FIXED_VALUE = 1
+
+
+class Stats(C.Structure):
+    _fields_ = [("initial_residual", C.c_double), ("final_residual", C.c_double),
+                ("n_iter", C.c_int32), ("converged", C.c_int32), ("singular", C.c_int32),
+                ("pad", C.c_int32), ("assemble_s", C.c_double), ("solve_s", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        _lib = C.CDLL(LIB_PATH)
+    return _lib
+
+
+def _p(a, dtype):
+    assert a.dtype == dtype and a.flags.c_contiguous, (a.dtype, dtype)
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def face_geometry(mesh):
+    F = mesh.n_faces
+    mag = np.empty(F)
+    dlt = np.empty(F)
+    own, nei = _i32(mesh.owner), _i32(mesh.neighbour)
+    cc, sf = _f64(mesh.cell_centre), _f64(mesh.face_area)
+    lib().lfo_face_geometry(C.c_int32(F), _p(own, np.int32), _p(nei, np.int32),
+                            _p(cc, np.float64), _p(sf, np.float64), _p(mag, np.float64),
+                            _p(dlt, np.float64))
+    return mag, dlt
+
+
+def bface_geometry(mesh):
+    B = mesh.n_bfaces
+    mag = np.empty(B)
+    dlt = np.empty(B)
+    bc_ = _i32(mesh.bface_cell)
+    cc, ba, bcn = _f64(mesh.cell_centre), _f64(mesh.bface_area), _f64(mesh.bface_centre)
+    lib().lfo_bface_geometry(C.c_int32(B), _p(bc_, np.int32), _p(cc, np.float64),
+                             _p(ba, np.float64), _p(bcn, np.float64), _p(mag, np.float64),
+                             _p(dlt, np.float64))
+    return mag, dlt
+
+
+def _patch_arrays(mesh, bcs):
+    if len(bcs) != mesh.n_patches:
+        raise ValueError("one boundary condition per patch is required")
+    types = np.asarray([int(t) for t, _ in bcs], dtype=np.int32)
+    vals = np.asarray([float(v) for _, v in bcs], dtype=np.float64)
+    return _i32(mesh.patch_start), types, vals
+
+
+def assemble(mesh, bcs, DT, dt, T_old):
+    """Return dict with diag, upper, source, diag_b, source_b, int_coeff, bou_coeff."""
+    N, F, B = mesh.n_cells, mesh.n_faces, mesh.n_bfaces
+    mag, dlt = face_geometry(mesh)
+    bmag, bdlt = bface_geometry(mesh)
+    ps, pt, pv = _patch_arrays(mesh, bcs)
+    out = {k: np.empty(N) for k in ("diag", "source", "diag_b", "source_b")}
+    out["upper"] = np.empty(F)
+    out["int_coeff"] = np.empty(B)
+    out["bou_coeff"] = np.empty(B)
+    own, nei, vol = _i32(mesh.owner), _i32(mesh.neighbour), _f64(mesh.cell_volume)
+    bcell = _i32(mesh.bface_cell)
+    T_old = _f64(T_old)
+    rc = lib().lfo_assemble(
+        C.c_int32(N), C.c_int32(F), _p(own, np.int32), _p(nei, np.int32), _p(vol, np.float64),
+        _p(mag, np.float64), _p(dlt, np.float64), C.c_int32(mesh.n_patches), _p(ps, np.int32),
+        _p(pt, np.int32), _p(pv, np.float64), _p(bcell, np.int32), _p(bmag, np.float64),
+        _p(bdlt, np.float64), C.c_double(DT), C.c_double(dt), _p(T_old, np.float64),
+        _p(out["diag"], np.float64), _p(out["upper"], np.float64), _p(out["source"], np.float64),
+        _p(out["diag_b"], np.float64), _p(out["source_b"], np.float64),
+        _p(out["int_coeff"], np.float64), _p(out["bou_coeff"], np.float64))
+    if rc != 0:
+        raise ValueError(f"oracle assemble failed: {rc}")
+    return out
+
+
+def amul(mesh, diag, upper, x):
+    N, F = mesh.n_cells, mesh.n_faces
+    y = np.empty(N)
+    own, nei = _i32(mesh.owner), _i32(mesh.neighbour)
+    diag, upper, x = _f64(diag), _f64(upper), _f64(x)
+    lib().lfo_amul(C.c_int32(N), C.c_int32(F), _p(own, np.int32), _p(nei, np.int32),
+                   _p(diag, np.float64), _p(upper, np.float64), _p(x, np.float64),
+                   _p(y, np.float64))
+    return y
+
+
+def sum_a(mesh, diag, upper):
+    N, F = mesh.n_cells, mesh.n_faces
+    y = np.empty(N)
+    own, nei = _i32(mesh.owner), _i32(mesh.neighbour)
+    diag, upper = _f64(diag), _f64(upper)
+    lib().lfo_sum_a(C.c_int32(N), C.c_int32(F), _p(own, np.int32), _p(nei, np.int32),
+                    _p(diag, np.float64), _p(upper, np.float64), _p(y, np.float64))
+    return y
+
+
+def dic_rd(mesh, diag, upper):
+    N, F = mesh.n_cells, mesh.n_faces
+    rd = np.empty(N)
+    own, nei = _i32(mesh.owner), _i32(mesh.neighbour)
+    diag, upper = _f64(diag), _f64(upper)
+    lib().lfo_dic_rd(C.c_int32(N), C.c_int32(F), _p(own, np.int32), _p(nei, np.int32),
+                     _p(diag, np.float64), _p(upper, np.float64), _p(rd, np.float64))
+    return rd
+
+
+def precondition(mesh, pc, upper, rd, r):
+    N, F = mesh.n_cells, mesh.n_faces
+    w = np.empty(N)
+    own, nei = _i32(mesh.owner), _i32(mesh.neighbour)
+    upper, rd, r = _f64(upper), _f64(rd), _f64(r)
+    lib().lfo_precondition(C.c_int(pc), C.c_int32(N), C.c_int32(F), _p(own, np.int32),
+                           _p(nei, np.int32), _p(upper, np.float64), _p(rd, np.float64),
+                           _p(r, np.float64), _p(w, np.float64))
+    return w
+
+
+def pcg(mesh, diag, upper, b, x0, pc=PC_DIAGONAL, tol=1e-9, rel_tol=0.0, max_iter=1000,
+        min_iter=0):
+    """Solve A x = b from x0; returns (x, stats dict)."""
+    N, F = mesh.n_cells, mesh.n_faces
+    x = np.array(x0, dtype=np.float64, copy=True)
+    st = Stats()
+    own, nei = _i32(mesh.owner), _i32(mesh.neighbour)
+    diag, upper, b = _f64(diag), _f64(upper), _f64(b)
+    rc = lib().lfo_pcg(C.c_int32(N), C.c_int32(F), _p(own, np.int32), _p(nei, np.int32),
+                       _p(diag, np.float64), _p(upper, np.float64), _p(b, np.float64),
+                       _p(x, np.float64), C.c_int(pc), C.c_double(tol), C.c_double(rel_tol),
+                       C.c_int32(max_iter), C.c_int32(min_iter), C.byref(st))
+    if rc != 0:
+        raise ValueError(f"oracle pcg failed: {rc}")
+    return x, st.as_dict()
+
+
+def run(mesh, bcs, DT, dt, n_steps, T0, pc=PC_DIAGONAL, tol=1e-9, rel_tol=0.0, max_iter=1000,
+        min_iter=0, keep_all=False):
+    """Run n_steps time steps from T0.  Returns (T_final, [stats], [T per step] or None)."""
+    N, F = mesh.n_cells, mesh.n_faces
+    own, nei = _i32(mesh.owner), _i32(mesh.neighbour)
+    vol, cc, sf = _f64(mesh.cell_volume), _f64(mesh.cell_centre), _f64(mesh.face_area)
+    ps, pt, pv = _patch_arrays(mesh, bcs)
+    bcell, ba, bcn = _i32(mesh.bface_cell), _f64(mesh.bface_area), _f64(mesh.bface_centre)
+    T = np.array(T0, dtype=np.float64, copy=True)
+    snaps = [] if keep_all else None
+    stats_all = []
+    steps_per_call = 1 if keep_all else n_steps
+    done = 0
+    while done < n_steps:
+        k = min(steps_per_call, n_steps - done)
+        st = (Stats * max(k, 1))()
+        rc = lib().lfo_run(
+            C.c_int32(N), C.c_int32(F), _p(own, np.int32), _p(nei, np.int32), _p(vol, np.float64),
+            _p(cc, np.float64), _p(sf, np.float64), C.c_int32(mesh.n_patches), _p(ps, np.int32),
+            _p(pt, np.int32), _p(pv, np.float64), _p(bcell, np.int32), _p(ba, np.float64),
+            _p(bcn, np.float64), C.c_double(DT), C.c_double(dt), C.c_int32(k), C.c_int(pc),
+            C.c_double(tol), C.c_double(rel_tol), C.c_int32(max_iter), C.c_int32(min_iter),
+            _p(T, np.float64), st)
+        if rc != 0:
+            raise ValueError(f"oracle run failed: {rc}")
+        stats_all.extend(s.as_dict() for s in st[:k])
+        if keep_all:
+            snaps.append(T.copy())
+        done += k
+    return T, stats_all, snaps
