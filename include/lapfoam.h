@@ -1,0 +1,197 @@
+/*
+ * lapfoam.h -- C interface of the MI355X (gfx950) laplacianFoam hot path.
+ *
+ * The library advances  dT/dt - div(DT grad T) = 0  (Eq. 1 of the paper with an
+ * empty source term) by implicit-Euler time steps on a finite-volume mesh given
+ * in OpenFOAM face addressing (Section 4: per internal face an owner and a
+ * neighbour cell, face area vector pointing owner -> neighbour; boundary faces
+ * grouped into patches).  Each step assembles
+ *      TEqn = fvm::ddt(T) - fvm::laplacian(DT, T)            (Listing 1)
+ * into an LDU matrix (diag, upper, lower = upper, source and per-boundary-face
+ * internal / boundary coefficients) and solves it with the preconditioned
+ * conjugate gradient method (Sections 5.1 and 6: PCG with the diagonal
+ * preconditioner; a DIC preconditioner on red-black numbered meshes is also
+ * offered).  Cell-parallel loops use the atomic-free "list of lists"
+ * addressing of Section 5.2 (ownerStart / losort / losortStart and the
+ * boundary face lists of each cell), built on the GPU.
+ *
+ * Conventions (all entry points):
+ *  - Every function returns an lf_status; 0 is success.  On error nothing
+ *    observable is half-written unless stated, and lf_last_error() returns a
+ *    message (per thread, valid until the next failing call on that thread).
+ *  - Device memory comes only from the caller: each handle lives in a
+ *    caller-owned device workspace whose exact size the *_workspace_bytes
+ *    functions return.  The library never allocates device memory, so a
+ *    caller can budget HBM exactly.  The workspace must stay allocated and
+ *    untouched until the handle is destroyed.  Workspaces must be 256-byte
+ *    aligned.
+ *  - Host arrays passed in are read during the call only; the caller keeps
+ *    ownership.
+ *  - `stream` is a hipStream_t (passed as void*; NULL = the default stream).
+ *    All device work of a handle is ordered on the stream given at creation.
+ *  - Handles are not thread-safe; distinct handles may be used from distinct
+ *    threads.  Calls that overlap on one handle are undefined.
+ *  - Integers are int32 (cell and face counts below 2^31), reals IEEE binary64
+ *    unless stated.
+ */
+#ifndef LAPFOAM_H
+#define LAPFOAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lf_status;
+#define LF_OK 0
+#define LF_EINVAL (-1)      /* bad argument (NULL, negative size, dt <= 0, ...) */
+#define LF_EMESH (-2)       /* mesh fails validation (see lf_mesh_create) */
+#define LF_ENOMEM (-3)      /* workspace too small or misaligned; host allocation failed */
+#define LF_EBUDGET (-4)     /* batch: request does not fit the device-memory budget */
+#define LF_EDEVICE (-5)     /* a HIP runtime call failed */
+#define LF_ESTATE (-6)      /* call not valid in the handle's current state */
+#define LF_ENONFINITE (-7)  /* a non-finite value appeared in the solve */
+
+#define LF_BC_ZERO_GRADIENT 0
+#define LF_BC_FIXED_VALUE 1
+
+#define LF_PC_DIAGONAL 0   /* w = r / diag (stored as reciprocal, Section 6) */
+#define LF_PC_DIC 1        /* diagonal incomplete Cholesky; needs a two-colour
+                              numbering: every face's owner < every face's
+                              neighbour (all "red" cells before all "black") */
+
+#define LF_PREC_FP64 0     /* everything in binary64 */
+#define LF_PREC_MIXED 1    /* FP64 outer residual and update, FP32 inner PCG
+                              (coefficients, vectors, SpMV) with FP64 dot
+                              products, alpha and beta (iterative refinement) */
+
+/* Mesh in OpenFOAM face addressing (host pointers). */
+typedef struct lf_mesh_desc {
+    int32_t n_cells;            /* N >= 1 */
+    int32_t n_faces;            /* F >= 0 internal faces */
+    int32_t n_patches;          /* P >= 0 */
+    int32_t reserved;
+    const int32_t *owner;       /* [F] owner cell of each internal face */
+    const int32_t *neighbour;   /* [F] neighbour cell; owner < neighbour and faces
+                                   sorted by (owner, neighbour): upper-triangular order */
+    const double *cell_volume;  /* [N] V_c > 0 */
+    const double *cell_centre;  /* [3N] C_c, xyz interleaved */
+    const double *face_area;    /* [3F] S_f, |S_f| = face area, owner -> neighbour */
+    const double *face_centre;  /* [3F] C_f; may be NULL (not used by this path) */
+    const int32_t *patch_start; /* [P+1] boundary faces of patch p are
+                                   [patch_start[p], patch_start[p+1]); patch_start[0] = 0 */
+    const int32_t *bface_cell;  /* [B] cell of each boundary face, B = patch_start[P] */
+    const double *bface_area;   /* [3B] outward S_b */
+    const double *bface_centre; /* [3B] C_b */
+} lf_mesh_desc;
+
+/* Boundary condition of one patch. */
+typedef struct lf_patch_bc {
+    int32_t type;               /* LF_BC_ZERO_GRADIENT or LF_BC_FIXED_VALUE */
+    int32_t reserved;
+    double value;               /* fixed value T_b (ignored for zeroGradient) */
+} lf_patch_bc;
+
+typedef struct lf_solver_opts {
+    double tol;                 /* absolute tolerance on the normalised residual */
+    double rel_tol;             /* relative tolerance (0 = off) */
+    int32_t max_iter;           /* iteration cap (OpenFOAM default 1000) */
+    int32_t min_iter;           /* minimum iterations (default 0) */
+    int32_t precond;            /* LF_PC_* */
+    int32_t precision;          /* LF_PREC_* */
+    int32_t iters_per_check;    /* PCG iterations enqueued between host checks of the
+                                   convergence flag; 0 = adaptive */
+    int32_t use_graph;          /* 1: replay captured HIP graphs, 0: plain launches */
+    double inner_tol;           /* LF_PREC_MIXED: inner FP32 solve stops when its
+                                   residual falls by this factor (0 = default 1e-4) */
+    int32_t max_outer;          /* LF_PREC_MIXED: refinement passes cap (0 = 50) */
+    int32_t block_cells;        /* cells per workgroup chunk tuning knob (0 = auto) */
+} lf_solver_opts;
+
+/* Per time step results. */
+typedef struct lf_solve_stats {
+    double initial_residual;    /* normalised residual of x0 = T_old */
+    double final_residual;      /* normalised residual at exit */
+    int32_t n_iter;             /* PCG iterations performed (mixed: inner total) */
+    int32_t converged;          /* 1 if the last convergence check passed */
+    int32_t singular;           /* 1 if |p.Ap| / normFactor < 1e-300 ended the solve */
+    int32_t nonfinite;          /* 1 if a NaN/Inf residual or p.Ap appeared */
+    int32_t n_outer;            /* mixed: refinement passes (FP64: 1) */
+    int32_t reserved;
+    double assemble_ms;         /* device time of the assembly (events) */
+    double solve_ms;            /* device time of the solve (events) */
+} lf_solve_stats;
+
+typedef struct lf_mesh lf_mesh;
+typedef struct lf_problem lf_problem;
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *lf_last_error(void);
+
+/* Fills *opts with the defaults: tol 1e-9, rel_tol 0, max_iter 1000, min_iter 0,
+   diagonal preconditioner, FP64, adaptive checks, graphs on. */
+lf_status lf_default_opts(lf_solver_opts *opts);
+
+/* ---- mesh (once per mesh) ------------------------------------------------
+ * Validation (LF_EMESH): every owner/neighbour/face cell index in [0, N);
+ * owner < neighbour; faces strictly increasing in (owner, neighbour); every
+ * face orthogonal (|S x d| <= 1e-9 |S||d|, d = C_N - C_P, S.d > 0: no
+ * non-orthogonal correction is implemented); boundary faces outward
+ * (S_b.(C_b - C_P) > 0); V > 0.
+ * The device copy holds the addressing (Section 5.2 lists of lists: per cell
+ * its owned faces, its lower faces in ascending face order, its boundary
+ * faces in ascending boundary-face order) and the geometry factors
+ * |S_f|, delta_f = 1/max(n.d, 0.05|d|), |S_b|, delta_b = 1/(n.(C_b - C_P)). */
+size_t lf_mesh_workspace_bytes(const lf_mesh_desc *desc);
+lf_status lf_mesh_create(const lf_mesh_desc *desc, void *dev_workspace, size_t workspace_bytes,
+                         void *stream, lf_mesh **out);
+lf_status lf_mesh_destroy(lf_mesh *mesh);   /* NULL-safe; does not free the workspace */
+
+/* Test hook: copies the device addressing to host arrays (any may be NULL):
+ * owner_start[N+1] (faces owned by c are [owner_start[c], owner_start[c+1])),
+ * losort[F], losort_start[N+1] (faces whose neighbour is c are
+ * losort[losort_start[c] .. losort_start[c+1]) in ascending order),
+ * bface_start[N+1], bface_list[B] (boundary faces of each cell, ascending). */
+lf_status lf_mesh_get_addressing(const lf_mesh *mesh, int32_t *owner_start, int32_t *losort,
+                                 int32_t *losort_start, int32_t *bface_start,
+                                 int32_t *bface_list);
+
+/* ---- problem: mesh + boundary conditions + DT + dt + solver ------------- */
+size_t lf_problem_workspace_bytes(const lf_mesh *mesh, const lf_solver_opts *opts);
+/* bcs[n_patches]; DT >= 0 finite; dt > 0 finite.  LF_PC_DIC on a mesh without
+ * the two-colour property returns LF_EINVAL.  T starts at 0: set it with
+ * lf_set_T before stepping. */
+lf_status lf_problem_create(const lf_mesh *mesh, const lf_patch_bc *bcs, double DT, double dt,
+                            const lf_solver_opts *opts, void *dev_workspace,
+                            size_t workspace_bytes, void *stream, lf_problem **out);
+lf_status lf_problem_destroy(lf_problem *problem);  /* NULL-safe */
+
+/* T[N]: on_device = 1 means a device pointer (copied on the handle's stream),
+ * 0 a host pointer (synchronous).  lf_set_T rejects non-finite values. */
+lf_status lf_set_T(lf_problem *problem, const double *T, int32_t on_device);
+lf_status lf_get_T(lf_problem *problem, double *T, int32_t on_device);
+
+/* Advance n_steps time steps.  stats[n_steps] (host, may be NULL).
+ * Per step: assemble TEqn from the current T, solve from x0 = T, T = x.
+ * Non-convergence is reported in stats, not as an error.  A non-finite
+ * residual stops the call with LF_ENONFINITE after that step's stats. */
+lf_status lf_step(lf_problem *problem, int32_t n_steps, lf_solve_stats *stats);
+
+/* ---- test hooks ------------------------------------------------------------ */
+/* Assemble TEqn from the current T (no solve).  Then lf_get_matrix copies, to
+ * host arrays (any may be NULL): diag[N] and source[N] of TEqn, upper[F],
+ * diag_b[N] / source_b[N] (with the boundary internal / boundary coefficients
+ * added, i.e. the matrix the solver sees), int_coeff[B], bou_coeff[B]. */
+lf_status lf_assemble(lf_problem *problem);
+lf_status lf_get_matrix(lf_problem *problem, double *diag, double *upper, double *source,
+                        double *diag_b, double *source_b, double *int_coeff, double *bou_coeff);
+/* y = A x with the last assembled solve-time matrix (diag_b, upper); x, y device
+ * pointers of N doubles, ordered on the handle's stream. */
+lf_status lf_amul(lf_problem *problem, const double *x, double *y);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LAPFOAM_H */

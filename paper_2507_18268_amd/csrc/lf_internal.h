@@ -1,0 +1,97 @@
+// Internal declarations of the lapfoam HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lapfoam.h"
+
+namespace lf {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define LF_HIP(call)                                                               \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            ::lf::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),  \
+                            __FILE__, __LINE__);                                   \
+            return LF_EDEVICE;                                                     \
+        }                                                                          \
+    } while (0)
+
+#define LF_TRY(expr)                     \
+    do {                                 \
+        lf_status s_ = (expr);           \
+        if (s_ != LF_OK) return s_;      \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// workspace carving: a bump allocator over caller memory.  With base == nullptr
+// it only counts, which is how the *_workspace_bytes functions size things.
+// ---------------------------------------------------------------------------
+constexpr size_t kAlign = 256;
+
+struct Carver {
+    char *base;
+    size_t used = 0;
+    explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+    template <class T>
+    T *take(size_t count) {
+        used = (used + kAlign - 1) / kAlign * kAlign;
+        T *p = base ? reinterpret_cast<T *>(base + used) : nullptr;
+        used += sizeof(T) * (count ? count : 1);
+        return p;
+    }
+    size_t bytes() const { return (used + kAlign - 1) / kAlign * kAlign; }
+};
+
+// ---------------------------------------------------------------------------
+// launch geometry shared by the cell-parallel kernels
+// ---------------------------------------------------------------------------
+constexpr int kBlock = 256;        // threads per workgroup (4 waves of 64)
+constexpr int kMaxGrid = 1024;     // workgroups per cell-parallel launch (upper bound)
+constexpr int kNumXcd = 8;         // MI355X: 8 accelerator complex dies
+
+struct CellGrid {
+    int32_t n;        // cells
+    int32_t grid;     // workgroups launched
+    int32_t chunk;    // cells per workgroup (contiguous)
+};
+CellGrid make_cell_grid(int32_t n, int32_t block_cells);
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+}  // namespace lf
+
+struct lf_mesh {
+    int32_t N = 0, F = 0, P = 0, B = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool two_colour = false;    // max owner < min neighbour
+    int32_t n_red = 0;          // first black cell when two_colour
+    std::vector<int32_t> patch_start;   // host copy [P+1]
+    // device arrays (inside the caller's workspace)
+    int32_t *owner = nullptr, *neighbour = nullptr;       // [F]
+    int32_t *owner_start = nullptr;                       // [N+1]
+    int32_t *losort = nullptr, *losort_start = nullptr;   // [F], [N+1]
+    int32_t *bface_start = nullptr, *bface_list = nullptr;   // [N+1], [B]
+    int32_t *bface_cell = nullptr, *bface_patch = nullptr;   // [B]
+    int32_t *row_start = nullptr;                         // [N+1] = losort_start + owner_start
+    int32_t *col = nullptr, *face_of = nullptr;           // [2F] row-ordered off-diagonals
+    double *V = nullptr;                                  // [N]
+    double *mag_sf = nullptr, *delta = nullptr;           // [F]
+    double *bmag_sf = nullptr, *bdelta = nullptr;         // [B]
+    size_t ws_bytes = 0;
+};
+
+struct lf_problem;   // defined in lf_problem.h

@@ -1,0 +1,505 @@
+// Mesh ingest: validation (host), the atomic-free "list of lists" addressing of
+// Section 5.2 (GPU), the row-ordered off-diagonal layout used by every
+// cell-parallel kernel (GPU) and the once-per-mesh geometry factors (GPU).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "lf_internal.h"
+
+namespace lf {
+
+// ---------------------------------------------------------------------------
+// errors (thread-local message)
+// ---------------------------------------------------------------------------
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+void clear_error() { g_err[0] = '\0'; }
+
+CellGrid make_cell_grid(int32_t n, int32_t block_cells) {
+    CellGrid g;
+    g.n = n;
+    int64_t per = block_cells > 0 ? block_cells : kBlock;
+    int64_t grid = (static_cast<int64_t>(n) + per - 1) / per;
+    if (block_cells <= 0) grid = std::min<int64_t>(grid, kMaxGrid);
+    grid = std::max<int64_t>(1, std::min<int64_t>(grid, kMaxGrid));
+    if (grid >= kNumXcd) grid = grid / kNumXcd * kNumXcd;   // whole number per XCD
+    g.grid = static_cast<int32_t>(grid);
+    g.chunk = static_cast<int32_t>((static_cast<int64_t>(n) + grid - 1) / grid);
+    return g;
+}
+
+// ---------------------------------------------------------------------------
+// integer kernels for the addressing build
+// ---------------------------------------------------------------------------
+__global__ void k_fill_i32(int32_t *a, int32_t n, int32_t v) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+// start[c] = first index i with key[i] >= c, for c in [0, n]; key sorted ascending.
+__global__ void k_lower_bound_starts(const int32_t *__restrict__ key, int32_t m,
+                                     int32_t *__restrict__ start, int32_t n) {
+    int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c > n) return;
+    int32_t lo = 0, hi = m;
+    while (lo < hi) {
+        int32_t mid = lo + (hi - lo) / 2;
+        if (key[mid] < c) lo = mid + 1; else hi = mid;
+    }
+    start[c] = lo;
+}
+
+__global__ void k_histogram(const int32_t *__restrict__ key, int32_t m, int32_t *__restrict__ cnt) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < m) atomicAdd(&cnt[key[i]], 1);
+}
+
+// exclusive scan of cnt[n] into out[n+1] (out[n] = total), three passes
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ int32_t block_exclusive_scan(int32_t v, int32_t *total) {
+    __shared__ int32_t s[kBlock];
+    int t = threadIdx.x;
+    s[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        int32_t add = (t >= off) ? s[t - off] : 0;
+        __syncthreads();
+        s[t] += add;
+        __syncthreads();
+    }
+    int32_t incl = s[t];
+    *total = s[kBlock - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_tile_sums(const int32_t *__restrict__ cnt, int32_t n,
+                                                        int32_t *__restrict__ tile_sum) {
+    int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
+    int32_t v = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+        int64_t i = base + threadIdx.x * kScanItems + j;
+        if (i < n) v += cnt[i];
+    }
+    int32_t tot;
+    block_exclusive_scan(v, &tot);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_tile_offsets(int32_t *tile_sum, int32_t nt) {
+    int32_t carry = 0;
+    for (int32_t base = 0; base < nt; base += kBlock) {
+        int32_t i = base + threadIdx.x;
+        int32_t v = i < nt ? tile_sum[i] : 0;
+        int32_t tot;
+        int32_t ex = block_exclusive_scan(v, &tot);
+        if (i < nt) tile_sum[i] = ex + carry;
+        carry += tot;
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_apply(const int32_t *__restrict__ cnt, int32_t n,
+                                                    const int32_t *__restrict__ tile_off,
+                                                    int32_t *__restrict__ out) {
+    int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
+    int32_t loc[kScanItems];
+    int32_t v = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+        int64_t i = base + j;
+        loc[j] = i < n ? cnt[i] : 0;
+        v += loc[j];
+    }
+    int32_t tot;
+    int32_t run = block_exclusive_scan(v, &tot) + tile_off[blockIdx.x];
+    for (int j = 0; j < kScanItems; ++j) {
+        int64_t i = base + j;
+        if (i < n) out[i] = run;
+        run += loc[j];
+        if (i == n - 1) out[n] = run;
+    }
+}
+
+// place item i at start[key[i]] + slot (slot from an atomic counter), then
+// sort each segment ascending so the result is the stable order.
+__global__ void k_place(const int32_t *__restrict__ key, int32_t m, const int32_t *__restrict__ start,
+                        int32_t *__restrict__ fill, int32_t *__restrict__ list) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    int32_t c = key[i];
+    int32_t slot = atomicAdd(&fill[c], 1);
+    list[start[c] + slot] = static_cast<int32_t>(i);
+}
+
+__global__ void k_sort_segments(const int32_t *__restrict__ start, int32_t n, int32_t *__restrict__ list) {
+    int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    int32_t b = start[c], e = start[c + 1];
+    for (int32_t i = b + 1; i < e; ++i) {
+        int32_t v = list[i];
+        int32_t j = i - 1;
+        while (j >= b && list[j] > v) {
+            list[j + 1] = list[j];
+            --j;
+        }
+        list[j + 1] = v;
+    }
+}
+
+// Row-ordered off-diagonal layout: row c lists its lower faces (ascending, the
+// faces where c is the neighbour; column = owner) then its owned faces
+// (ascending; column = neighbour).  On an upper-triangular mesh this is the
+// order in which a sequential face loop visits row c.
+__global__ void k_rows(int32_t n, const int32_t *__restrict__ owner, const int32_t *__restrict__ neighbour,
+                       const int32_t *__restrict__ owner_start, const int32_t *__restrict__ losort,
+                       const int32_t *__restrict__ losort_start, int32_t *__restrict__ row_start,
+                       int32_t *__restrict__ col, int32_t *__restrict__ face_of) {
+    int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c > n) return;
+    int32_t e = losort_start[c] + owner_start[c];
+    row_start[c] = e;
+    if (c == n) return;
+    for (int32_t i = losort_start[c]; i < losort_start[c + 1]; ++i) {
+        int32_t f = losort[i];
+        col[e] = owner[f];
+        face_of[e] = f;
+        ++e;
+    }
+    for (int32_t f = owner_start[c]; f < owner_start[c + 1]; ++f) {
+        col[e] = neighbour[f];
+        face_of[e] = f;
+        ++e;
+    }
+}
+
+// Geometry factors (Gauss linear corrected Laplacian, orthogonal part):
+// |S_f| and delta_f = 1/max(n.d, 0.05|d|), n = S_f/|S_f|, d = C_N - C_P.
+__global__ void k_face_geometry(int32_t f0, int32_t m, const int32_t *__restrict__ owner,
+                                const int32_t *__restrict__ neighbour, const double *__restrict__ C,
+                                const double *__restrict__ S, double *__restrict__ mag_sf,
+                                double *__restrict__ delta) {
+    int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    int64_t f = f0 + j;
+    double sx = S[3 * j], sy = S[3 * j + 1], sz = S[3 * j + 2];
+    double mag = sqrt(sx * sx + sy * sy + sz * sz);
+    double nx = sx / mag, ny = sy / mag, nz = sz / mag;
+    const double *P = C + 3 * static_cast<int64_t>(owner[f]);
+    const double *Q = C + 3 * static_cast<int64_t>(neighbour[f]);
+    double dx = Q[0] - P[0], dy = Q[1] - P[1], dz = Q[2] - P[2];
+    double nd = nx * dx + ny * dy + nz * dz;
+    double dmag = sqrt(dx * dx + dy * dy + dz * dz);
+    double lim = 0.05 * dmag;
+    mag_sf[f] = mag;
+    delta[f] = 1.0 / (nd > lim ? nd : lim);
+}
+
+// boundary: |S_b| and delta_b = 1/(n_b.(C_b - C_P))
+__global__ void k_bface_geometry(int32_t nb, const int32_t *__restrict__ bcell, const double *__restrict__ C,
+                                 const double *__restrict__ S, const double *__restrict__ Cb,
+                                 double *__restrict__ bmag, double *__restrict__ bdelta) {
+    int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    double sx = S[3 * b], sy = S[3 * b + 1], sz = S[3 * b + 2];
+    double mag = sqrt(sx * sx + sy * sy + sz * sz);
+    double nx = sx / mag, ny = sy / mag, nz = sz / mag;
+    const double *P = C + 3 * static_cast<int64_t>(bcell[b]);
+    double dx = Cb[3 * b] - P[0], dy = Cb[3 * b + 1] - P[1], dz = Cb[3 * b + 2] - P[2];
+    double nd = nx * dx + ny * dy + nz * dz;
+    bmag[b] = mag;
+    bdelta[b] = 1.0 / nd;
+}
+
+static inline unsigned blocks_for(int64_t n) {
+    return static_cast<unsigned>((std::max<int64_t>(n, 1) + kBlock - 1) / kBlock);
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+static constexpr int64_t kGeomChunk = 1 << 22;   // faces staged per geometry pass
+
+struct MeshScratch {
+    int32_t *cnt;        // [N+1]
+    int32_t *tile;       // scan tile sums
+    double *C;           // [3N]
+    double *S;           // [3*chunk]
+    double *bS, *bC;     // [3B]
+};
+
+static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, lf_mesh *m, MeshScratch *s) {
+    size_t n1 = static_cast<size_t>(N) + 1;
+    auto *owner = cv.take<int32_t>(F);
+    auto *neighbour = cv.take<int32_t>(F);
+    auto *owner_start = cv.take<int32_t>(n1);
+    auto *losort = cv.take<int32_t>(F);
+    auto *losort_start = cv.take<int32_t>(n1);
+    auto *bface_start = cv.take<int32_t>(n1);
+    auto *bface_list = cv.take<int32_t>(B);
+    auto *bface_cell = cv.take<int32_t>(B);
+    auto *bface_patch = cv.take<int32_t>(B);
+    auto *row_start = cv.take<int32_t>(n1);
+    auto *col = cv.take<int32_t>(2 * static_cast<size_t>(F));
+    auto *face_of = cv.take<int32_t>(2 * static_cast<size_t>(F));
+    auto *V = cv.take<double>(N);
+    auto *mag_sf = cv.take<double>(F);
+    auto *delta = cv.take<double>(F);
+    auto *bmag = cv.take<double>(B);
+    auto *bdelta = cv.take<double>(B);
+    size_t tiles = (n1 + kScanTile - 1) / kScanTile + 1;
+    MeshScratch sc;
+    sc.cnt = cv.take<int32_t>(n1);
+    sc.tile = cv.take<int32_t>(tiles);
+    sc.C = cv.take<double>(3 * static_cast<size_t>(N));
+    sc.S = cv.take<double>(3 * static_cast<size_t>(std::min<int64_t>(std::max(F, 1), kGeomChunk)));
+    sc.bS = cv.take<double>(3 * static_cast<size_t>(B));
+    sc.bC = cv.take<double>(3 * static_cast<size_t>(B));
+    if (m) {
+        m->owner = owner; m->neighbour = neighbour; m->owner_start = owner_start;
+        m->losort = losort; m->losort_start = losort_start; m->bface_start = bface_start;
+        m->bface_list = bface_list; m->bface_cell = bface_cell; m->bface_patch = bface_patch;
+        m->row_start = row_start; m->col = col; m->face_of = face_of; m->V = V;
+        m->mag_sf = mag_sf; m->delta = delta; m->bmag_sf = bmag; m->bdelta = bdelta;
+    }
+    if (s) *s = sc;
+}
+
+// ---------------------------------------------------------------------------
+// host validation
+// ---------------------------------------------------------------------------
+static lf_status validate(const lf_mesh_desc *d, int32_t *B_out, bool *two_colour, int32_t *n_red) {
+    if (!d) { set_error("mesh desc is NULL"); return LF_EINVAL; }
+    const int32_t N = d->n_cells, F = d->n_faces, P = d->n_patches;
+    if (N < 1 || F < 0 || P < 0) { set_error("bad sizes N=%d F=%d P=%d", N, F, P); return LF_EINVAL; }
+    if (!d->cell_volume || !d->cell_centre || (F > 0 && (!d->owner || !d->neighbour || !d->face_area)) ||
+        !d->patch_start) {
+        set_error("NULL mesh array");
+        return LF_EINVAL;
+    }
+    if (d->patch_start[0] != 0) { set_error("patch_start[0] must be 0"); return LF_EMESH; }
+    for (int32_t p = 0; p < P; ++p)
+        if (d->patch_start[p + 1] < d->patch_start[p]) { set_error("patch_start not monotone"); return LF_EMESH; }
+    const int32_t B = d->patch_start[P];
+    if (B > 0 && (!d->bface_cell || !d->bface_area || !d->bface_centre)) {
+        set_error("NULL boundary array");
+        return LF_EINVAL;
+    }
+    for (int32_t c = 0; c < N; ++c)
+        if (!(d->cell_volume[c] > 0.0) || !std::isfinite(d->cell_volume[c])) {
+            set_error("cell %d: volume %g not positive/finite", c, d->cell_volume[c]);
+            return LF_EMESH;
+        }
+    for (int64_t i = 0; i < 3 * static_cast<int64_t>(N); ++i)
+        if (!std::isfinite(d->cell_centre[i])) { set_error("non-finite cell centre"); return LF_EMESH; }
+    int32_t max_owner = -1, min_nei = N;
+    for (int32_t f = 0; f < F; ++f) {
+        int32_t o = d->owner[f], n = d->neighbour[f];
+        if (o < 0 || o >= N || n < 0 || n >= N) { set_error("face %d: cell index out of range", f); return LF_EMESH; }
+        if (o >= n) { set_error("face %d: owner %d >= neighbour %d", f, o, n); return LF_EMESH; }
+        if (f > 0) {
+            int32_t po = d->owner[f - 1], pn = d->neighbour[f - 1];
+            if (o < po || (o == po && n <= pn)) {
+                set_error("face %d: faces not in upper-triangular (owner, neighbour) order", f);
+                return LF_EMESH;
+            }
+        }
+        max_owner = std::max(max_owner, o);
+        min_nei = std::min(min_nei, n);
+        const double *S = d->face_area + 3 * static_cast<int64_t>(f);
+        const double *A = d->cell_centre + 3 * static_cast<int64_t>(o);
+        const double *Q = d->cell_centre + 3 * static_cast<int64_t>(n);
+        double dx = Q[0] - A[0], dy = Q[1] - A[1], dz = Q[2] - A[2];
+        double cx = S[1] * dz - S[2] * dy, cy = S[2] * dx - S[0] * dz, cz = S[0] * dy - S[1] * dx;
+        double s2 = S[0] * S[0] + S[1] * S[1] + S[2] * S[2];
+        double d2 = dx * dx + dy * dy + dz * dz;
+        double sd = S[0] * dx + S[1] * dy + S[2] * dz;
+        if (!(s2 > 0.0) || !(d2 > 0.0) || !std::isfinite(s2) || !(sd > 0.0) ||
+            cx * cx + cy * cy + cz * cz > 1e-18 * s2 * d2) {
+            set_error("face %d: degenerate, inward or non-orthogonal face", f);
+            return LF_EMESH;
+        }
+    }
+    for (int32_t b = 0; b < B; ++b) {
+        int32_t c = d->bface_cell[b];
+        if (c < 0 || c >= N) { set_error("boundary face %d: cell out of range", b); return LF_EMESH; }
+        const double *S = d->bface_area + 3 * static_cast<int64_t>(b);
+        const double *Cb = d->bface_centre + 3 * static_cast<int64_t>(b);
+        const double *A = d->cell_centre + 3 * static_cast<int64_t>(c);
+        double sd = S[0] * (Cb[0] - A[0]) + S[1] * (Cb[1] - A[1]) + S[2] * (Cb[2] - A[2]);
+        if (!(sd > 0.0) || !std::isfinite(sd)) {
+            set_error("boundary face %d: not outward or degenerate", b);
+            return LF_EMESH;
+        }
+    }
+    *B_out = B;
+    *two_colour = F > 0 && max_owner < min_nei;
+    *n_red = F > 0 ? min_nei : N;
+    return LF_OK;
+}
+
+static lf_status exclusive_scan(const int32_t *cnt, int32_t n, int32_t *out, int32_t *tile,
+                                hipStream_t s) {
+    int32_t nt = (n + kScanTile - 1) / kScanTile;
+    if (n == 0) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, s, out, 1, 0);
+        LF_HIP(hipGetLastError());
+        return LF_OK;
+    }
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3(nt), dim3(kBlock), 0, s, cnt, n, tile);
+    hipLaunchKernelGGL(k_scan_tile_offsets, dim3(1), dim3(kBlock), 0, s, tile, nt);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(kBlock), 0, s, cnt, n, tile, out);
+    LF_HIP(hipGetLastError());
+    return LF_OK;
+}
+
+// stable grouping of items 0..m-1 by key (key in [0, n)): start[n+1], list[m]
+static lf_status group_by_key(const int32_t *key, int32_t m, int32_t n, int32_t *start, int32_t *list,
+                              int32_t *cnt, int32_t *tile, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n + 1)), dim3(kBlock), 0, s, cnt, n + 1, 0);
+    if (m > 0) hipLaunchKernelGGL(k_histogram, dim3(blocks_for(m)), dim3(kBlock), 0, s, key, m, cnt);
+    LF_TRY(exclusive_scan(cnt, n, start, tile, s));
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n + 1)), dim3(kBlock), 0, s, cnt, n + 1, 0);
+    if (m > 0) {
+        hipLaunchKernelGGL(k_place, dim3(blocks_for(m)), dim3(kBlock), 0, s, key, m, start, cnt, list);
+        hipLaunchKernelGGL(k_sort_segments, dim3(blocks_for(n)), dim3(kBlock), 0, s, start, n, list);
+    }
+    LF_HIP(hipGetLastError());
+    return LF_OK;
+}
+
+}  // namespace lf
+
+using namespace lf;
+
+extern "C" {
+
+const char *lf_last_error(void) { return g_err; }
+
+size_t lf_mesh_workspace_bytes(const lf_mesh_desc *d) {
+    if (!d || d->n_cells < 1 || d->n_faces < 0 || d->n_patches < 0 || !d->patch_start) return 0;
+    Carver cv(nullptr);
+    carve_mesh(cv, d->n_cells, d->n_faces, d->patch_start[d->n_patches], nullptr, nullptr);
+    return cv.bytes();
+}
+
+lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void *stream, lf_mesh **out) {
+    clear_error();
+    if (!out) { set_error("out is NULL"); return LF_EINVAL; }
+    *out = nullptr;
+    int32_t B = 0, n_red = 0;
+    bool two_colour = false;
+    LF_TRY(validate(d, &B, &two_colour, &n_red));
+    const int32_t N = d->n_cells, F = d->n_faces, P = d->n_patches;
+    Carver dry(nullptr);
+    carve_mesh(dry, N, F, B, nullptr, nullptr);
+    if (!ws || ws_bytes < dry.bytes() || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) {
+        set_error("mesh workspace too small or misaligned: need %zu bytes, 256-aligned", dry.bytes());
+        return LF_ENOMEM;
+    }
+    lf_mesh *m = new (std::nothrow) lf_mesh();
+    if (!m) { set_error("host allocation failed"); return LF_ENOMEM; }
+    m->N = N; m->F = F; m->P = P; m->B = B;
+    m->two_colour = two_colour;
+    m->n_red = n_red;
+    m->stream = static_cast<hipStream_t>(stream);
+    m->patch_start.assign(d->patch_start, d->patch_start + P + 1);
+    m->ws_bytes = dry.bytes();
+    if (hipGetDevice(&m->device) != hipSuccess) { delete m; set_error("hipGetDevice failed"); return LF_EDEVICE; }
+    Carver cv(ws);
+    MeshScratch sc;
+    carve_mesh(cv, N, F, B, m, &sc);
+    hipStream_t s = m->stream;
+
+    auto fail = [&](lf_status st) { delete m; return st; };
+    std::vector<int32_t> bpatch(static_cast<size_t>(B));
+    for (int32_t p = 0; p < P; ++p)
+        for (int32_t b = d->patch_start[p]; b < d->patch_start[p + 1]; ++b) bpatch[b] = p;
+
+#define LF_HIPM(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            set_error("%s failed: %s", #call, hipGetErrorString(e_));                   \
+            return fail(LF_EDEVICE);                                                    \
+        }                                                                               \
+    } while (0)
+
+    if (F > 0) {
+        LF_HIPM(hipMemcpyAsync(m->owner, d->owner, sizeof(int32_t) * F, hipMemcpyHostToDevice, s));
+        LF_HIPM(hipMemcpyAsync(m->neighbour, d->neighbour, sizeof(int32_t) * F, hipMemcpyHostToDevice, s));
+    }
+    LF_HIPM(hipMemcpyAsync(m->V, d->cell_volume, sizeof(double) * N, hipMemcpyHostToDevice, s));
+    LF_HIPM(hipMemcpyAsync(sc.C, d->cell_centre, sizeof(double) * 3 * static_cast<size_t>(N),
+                           hipMemcpyHostToDevice, s));
+    if (B > 0) {
+        LF_HIPM(hipMemcpyAsync(m->bface_cell, d->bface_cell, sizeof(int32_t) * B, hipMemcpyHostToDevice, s));
+        LF_HIPM(hipMemcpyAsync(m->bface_patch, bpatch.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice, s));
+        LF_HIPM(hipMemcpyAsync(sc.bS, d->bface_area, sizeof(double) * 3 * static_cast<size_t>(B),
+                               hipMemcpyHostToDevice, s));
+        LF_HIPM(hipMemcpyAsync(sc.bC, d->bface_centre, sizeof(double) * 3 * static_cast<size_t>(B),
+                               hipMemcpyHostToDevice, s));
+    }
+
+    // lists of lists (Section 5.2): owned faces, lower faces, boundary faces per cell
+    hipLaunchKernelGGL(k_lower_bound_starts, dim3(blocks_for(static_cast<int64_t>(N) + 1)), dim3(kBlock), 0, s,
+                       m->owner, F, m->owner_start, N);
+    lf_status st = group_by_key(m->neighbour, F, N, m->losort_start, m->losort, sc.cnt, sc.tile, s);
+    if (st != LF_OK) return fail(st);
+    st = group_by_key(m->bface_cell, B, N, m->bface_start, m->bface_list, sc.cnt, sc.tile, s);
+    if (st != LF_OK) return fail(st);
+    hipLaunchKernelGGL(k_rows, dim3(blocks_for(static_cast<int64_t>(N) + 1)), dim3(kBlock), 0, s, N, m->owner,
+                       m->neighbour, m->owner_start, m->losort, m->losort_start, m->row_start, m->col,
+                       m->face_of);
+
+    // geometry factors, faces staged in chunks
+    for (int64_t f0 = 0; f0 < F; f0 += kGeomChunk) {
+        int32_t cnt = static_cast<int32_t>(std::min<int64_t>(kGeomChunk, F - f0));
+        LF_HIPM(hipMemcpyAsync(sc.S, d->face_area + 3 * f0, sizeof(double) * 3 * static_cast<size_t>(cnt),
+                               hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_face_geometry, dim3(blocks_for(cnt)), dim3(kBlock), 0, s, static_cast<int32_t>(f0),
+                           cnt, m->owner, m->neighbour, sc.C, sc.S, m->mag_sf, m->delta);
+    }
+    if (B > 0)
+        hipLaunchKernelGGL(k_bface_geometry, dim3(blocks_for(B)), dim3(kBlock), 0, s, B, m->bface_cell, sc.C,
+                           sc.bS, sc.bC, m->bmag_sf, m->bdelta);
+    LF_HIPM(hipGetLastError());
+    LF_HIPM(hipStreamSynchronize(s));
+#undef LF_HIPM
+    *out = m;
+    return LF_OK;
+}
+
+lf_status lf_mesh_destroy(lf_mesh *m) {
+    delete m;
+    return LF_OK;
+}
+
+lf_status lf_mesh_get_addressing(const lf_mesh *m, int32_t *owner_start, int32_t *losort, int32_t *losort_start,
+                                 int32_t *bface_start, int32_t *bface_list) {
+    clear_error();
+    if (!m) { set_error("mesh is NULL"); return LF_EINVAL; }
+    hipStream_t s = m->stream;
+    size_t n1 = static_cast<size_t>(m->N) + 1;
+    if (owner_start) LF_HIP(hipMemcpyAsync(owner_start, m->owner_start, 4 * n1, hipMemcpyDeviceToHost, s));
+    if (losort && m->F) LF_HIP(hipMemcpyAsync(losort, m->losort, 4 * static_cast<size_t>(m->F), hipMemcpyDeviceToHost, s));
+    if (losort_start) LF_HIP(hipMemcpyAsync(losort_start, m->losort_start, 4 * n1, hipMemcpyDeviceToHost, s));
+    if (bface_start) LF_HIP(hipMemcpyAsync(bface_start, m->bface_start, 4 * n1, hipMemcpyDeviceToHost, s));
+    if (bface_list && m->B) LF_HIP(hipMemcpyAsync(bface_list, m->bface_list, 4 * static_cast<size_t>(m->B), hipMemcpyDeviceToHost, s));
+    LF_HIP(hipStreamSynchronize(s));
+    return LF_OK;
+}
+
+}  // extern "C"

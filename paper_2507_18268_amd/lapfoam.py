@@ -1,0 +1,352 @@
+"""Python binding of liblapfoam.so (the C interface declared in include/lapfoam.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  PyTorch provides device memory (the caller-owned workspaces) and the
+stream.  If the library is missing the import fails: there is no fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblapfoam.so")
+
+LF_OK = 0
+LF_EINVAL = -1
+LF_EMESH = -2
+LF_ENOMEM = -3
+LF_EBUDGET = -4
+LF_EDEVICE = -5
+LF_ESTATE = -6
+LF_ENONFINITE = -7
+
+LF_BC_ZERO_GRADIENT = 0
+LF_BC_FIXED_VALUE = 1
+LF_PC_DIAGONAL = 0
+LF_PC_DIC = 1
+LF_PREC_FP64 = 0
+LF_PREC_MIXED = 1
+
+_STATUS = {0: "LF_OK", -1: "LF_EINVAL", -2: "LF_EMESH", -3: "LF_ENOMEM", -4: "LF_EBUDGET",
+           -5: "LF_EDEVICE", -6: "LF_ESTATE", -7: "LF_ENONFINITE"}
+
+
+class LapfoamError(RuntimeError):
+    def __init__(self, status, func, msg):
+        self.status = status
+        super().__init__(f"{func}: {_STATUS.get(status, status)}: {msg}")
+
+
+class lf_mesh_desc(C.Structure):
+    _fields_ = [("n_cells", C.c_int32), ("n_faces", C.c_int32), ("n_patches", C.c_int32),
+                ("reserved", C.c_int32), ("owner", C.c_void_p), ("neighbour", C.c_void_p),
+                ("cell_volume", C.c_void_p), ("cell_centre", C.c_void_p),
+                ("face_area", C.c_void_p), ("face_centre", C.c_void_p),
+                ("patch_start", C.c_void_p), ("bface_cell", C.c_void_p),
+                ("bface_area", C.c_void_p), ("bface_centre", C.c_void_p)]
+
+
+class lf_patch_bc(C.Structure):
+    _fields_ = [("type", C.c_int32), ("reserved", C.c_int32), ("value", C.c_double)]
+
+
+class lf_solver_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("rel_tol", C.c_double), ("max_iter", C.c_int32),
+                ("min_iter", C.c_int32), ("precond", C.c_int32), ("precision", C.c_int32),
+                ("iters_per_check", C.c_int32), ("use_graph", C.c_int32),
+                ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("block_cells", C.c_int32)]
+
+
+class lf_solve_stats(C.Structure):
+    _fields_ = [("initial_residual", C.c_double), ("final_residual", C.c_double),
+                ("n_iter", C.c_int32), ("converged", C.c_int32), ("singular", C.c_int32),
+                ("nonfinite", C.c_int32), ("n_outer", C.c_int32), ("reserved", C.c_int32),
+                ("assemble_ms", C.c_double), ("solve_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib = None
+
+_SIGS = {
+    "lf_last_error": (C.c_char_p, []),
+    "lf_default_opts": (C.c_int32, [C.POINTER(lf_solver_opts)]),
+    "lf_mesh_workspace_bytes": (C.c_size_t, [C.POINTER(lf_mesh_desc)]),
+    "lf_mesh_create": (C.c_int32, [C.POINTER(lf_mesh_desc), C.c_void_p, C.c_size_t, C.c_void_p,
+                                   C.POINTER(C.c_void_p)]),
+    "lf_mesh_destroy": (C.c_int32, [C.c_void_p]),
+    "lf_mesh_get_addressing": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 5),
+    "lf_problem_workspace_bytes": (C.c_size_t, [C.c_void_p, C.POINTER(lf_solver_opts)]),
+    "lf_problem_create": (C.c_int32, [C.c_void_p, C.POINTER(lf_patch_bc), C.c_double, C.c_double,
+                                      C.POINTER(lf_solver_opts), C.c_void_p, C.c_size_t,
+                                      C.c_void_p, C.POINTER(C.c_void_p)]),
+    "lf_problem_destroy": (C.c_int32, [C.c_void_p]),
+    "lf_set_T": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "lf_get_T": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "lf_step": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "lf_assemble": (C.c_int32, [C.c_void_p]),
+    "lf_get_matrix": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 7),
+    "lf_amul": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+}
+
+
+def lib():
+    """Load liblapfoam.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status, func):
+    if status != LF_OK:
+        raise LapfoamError(status, func, lib().lf_last_error().decode())
+
+
+def _ptr(a):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+# --------------------------------------------------------------------------
+# same-name thin wrappers
+# --------------------------------------------------------------------------
+def lf_last_error():
+    return lib().lf_last_error().decode()
+
+
+def lf_default_opts():
+    o = lf_solver_opts()
+    _check(lib().lf_default_opts(C.byref(o)), "lf_default_opts")
+    return o
+
+
+def lf_mesh_workspace_bytes(desc):
+    return int(lib().lf_mesh_workspace_bytes(C.byref(desc)))
+
+
+def lf_mesh_create(desc, ws_ptr, ws_bytes, stream):
+    h = C.c_void_p()
+    _check(lib().lf_mesh_create(C.byref(desc), C.c_void_p(ws_ptr), C.c_size_t(ws_bytes),
+                                C.c_void_p(stream), C.byref(h)), "lf_mesh_create")
+    return h
+
+
+def lf_mesh_destroy(h):
+    _check(lib().lf_mesh_destroy(h), "lf_mesh_destroy")
+
+
+def lf_mesh_get_addressing(h, owner_start=None, losort=None, losort_start=None,
+                           bface_start=None, bface_list=None):
+    _check(lib().lf_mesh_get_addressing(h, _ptr(owner_start), _ptr(losort), _ptr(losort_start),
+                                        _ptr(bface_start), _ptr(bface_list)),
+           "lf_mesh_get_addressing")
+
+
+def lf_problem_workspace_bytes(mesh_h, opts):
+    return int(lib().lf_problem_workspace_bytes(mesh_h, C.byref(opts)))
+
+
+def lf_problem_create(mesh_h, bcs, DT, dt, opts, ws_ptr, ws_bytes, stream):
+    h = C.c_void_p()
+    _check(lib().lf_problem_create(mesh_h, bcs, C.c_double(DT), C.c_double(dt), C.byref(opts),
+                                   C.c_void_p(ws_ptr), C.c_size_t(ws_bytes), C.c_void_p(stream),
+                                   C.byref(h)), "lf_problem_create")
+    return h
+
+
+def lf_problem_destroy(h):
+    _check(lib().lf_problem_destroy(h), "lf_problem_destroy")
+
+
+def lf_set_T(h, ptr, on_device):
+    _check(lib().lf_set_T(h, C.c_void_p(ptr), C.c_int32(on_device)), "lf_set_T")
+
+
+def lf_get_T(h, ptr, on_device):
+    _check(lib().lf_get_T(h, C.c_void_p(ptr), C.c_int32(on_device)), "lf_get_T")
+
+
+def lf_step(h, n_steps, stats_array=None):
+    st = stats_array if stats_array is not None else None
+    status = lib().lf_step(h, C.c_int32(n_steps), st)
+    return status
+
+
+def lf_assemble(h):
+    _check(lib().lf_assemble(h), "lf_assemble")
+
+
+def lf_get_matrix(h, diag=None, upper=None, source=None, diag_b=None, source_b=None,
+                  int_coeff=None, bou_coeff=None):
+    _check(lib().lf_get_matrix(h, _ptr(diag), _ptr(upper), _ptr(source), _ptr(diag_b),
+                               _ptr(source_b), _ptr(int_coeff), _ptr(bou_coeff)),
+           "lf_get_matrix")
+
+
+def lf_amul(h, x_ptr, y_ptr):
+    _check(lib().lf_amul(h, C.c_void_p(x_ptr), C.c_void_p(y_ptr)), "lf_amul")
+
+
+# --------------------------------------------------------------------------
+# convenience handles holding their torch workspaces
+# --------------------------------------------------------------------------
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("lapfoam needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Mesh:
+    """Device copy of a mesh (OpenFOAM face addressing) in a torch workspace.
+
+    `m` has the fields of lf_mesh_desc as numpy arrays: n_cells, n_faces,
+    owner, neighbour, cell_volume, cell_centre [N,3], face_area [F,3],
+    patch_start, bface_cell, bface_area [B,3], bface_centre [B,3]
+    (face_centre optional).
+    """
+
+    def __init__(self, m, stream=None):
+        torch = _torch()
+        self._keep = dict(
+            owner=np.ascontiguousarray(m.owner, dtype=np.int32),
+            neighbour=np.ascontiguousarray(m.neighbour, dtype=np.int32),
+            cell_volume=np.ascontiguousarray(m.cell_volume, dtype=np.float64),
+            cell_centre=np.ascontiguousarray(m.cell_centre, dtype=np.float64),
+            face_area=np.ascontiguousarray(m.face_area, dtype=np.float64),
+            patch_start=np.ascontiguousarray(m.patch_start, dtype=np.int32),
+            bface_cell=np.ascontiguousarray(m.bface_cell, dtype=np.int32),
+            bface_area=np.ascontiguousarray(m.bface_area, dtype=np.float64),
+            bface_centre=np.ascontiguousarray(m.bface_centre, dtype=np.float64))
+        k = self._keep
+        self.n_cells = int(m.n_cells)
+        self.n_faces = int(m.n_faces)
+        self.n_patches = int(k["patch_start"].size - 1)
+        self.n_bfaces = int(k["patch_start"][-1])
+        d = lf_mesh_desc()
+        d.n_cells, d.n_faces, d.n_patches = self.n_cells, self.n_faces, self.n_patches
+        for name in ("owner", "neighbour", "cell_volume", "cell_centre", "face_area",
+                     "patch_start", "bface_cell", "bface_area", "bface_centre"):
+            setattr(d, name, k[name].ctypes.data)
+        d.face_centre = None
+        self.desc = d
+        self.ws_bytes = lf_mesh_workspace_bytes(d)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device="cuda")
+        assert self.ws.data_ptr() % 256 == 0
+        self.stream = _stream_ptr(stream)
+        self.h = lf_mesh_create(d, self.ws.data_ptr(), self.ws_bytes, self.stream)
+        del self._keep   # host arrays were read during the call only
+
+    def addressing(self):
+        N, F, B = self.n_cells, self.n_faces, self.n_bfaces
+        out = dict(owner_start=np.empty(N + 1, np.int32), losort=np.empty(max(F, 1), np.int32),
+                   losort_start=np.empty(N + 1, np.int32), bface_start=np.empty(N + 1, np.int32),
+                   bface_list=np.empty(max(B, 1), np.int32))
+        lf_mesh_get_addressing(self.h, **out)
+        out["losort"] = out["losort"][:F]
+        out["bface_list"] = out["bface_list"][:B]
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            lf_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_opts(tol=1e-9, rel_tol=0.0, max_iter=1000, min_iter=0, precond=LF_PC_DIAGONAL,
+              precision=LF_PREC_FP64, iters_per_check=0, use_graph=1, inner_tol=0.0, max_outer=0,
+              block_cells=0):
+    o = lf_default_opts()
+    o.tol, o.rel_tol, o.max_iter, o.min_iter = tol, rel_tol, max_iter, min_iter
+    o.precond, o.precision, o.iters_per_check, o.use_graph = precond, precision, iters_per_check, use_graph
+    o.inner_tol, o.max_outer, o.block_cells = inner_tol, max_outer, block_cells
+    return o
+
+
+class Problem:
+    """Mesh + boundary conditions + DT + dt + solver options, with field T."""
+
+    def __init__(self, mesh, bcs, DT, dt, opts=None, stream=None):
+        torch = _torch()
+        self.mesh = mesh
+        self.opts = opts if opts is not None else make_opts()
+        arr = (lf_patch_bc * max(len(bcs), 1))()
+        for i, (t, v) in enumerate(bcs):
+            arr[i].type, arr[i].value = int(t), float(v)
+        self.ws_bytes = lf_problem_workspace_bytes(mesh.h, self.opts)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device="cuda")
+        assert self.ws.data_ptr() % 256 == 0
+        self.stream = _stream_ptr(stream) if stream is not None else mesh.stream
+        self.h = lf_problem_create(mesh.h, arr, DT, dt, self.opts, self.ws.data_ptr(),
+                                   self.ws_bytes, self.stream)
+
+    def set_T(self, T):
+        if hasattr(T, "data_ptr"):
+            lf_set_T(self.h, T.data_ptr(), 1)
+        else:
+            a = np.ascontiguousarray(T, dtype=np.float64)
+            lf_set_T(self.h, a.ctypes.data, 0)
+
+    def get_T(self, out=None):
+        if out is not None and hasattr(out, "data_ptr"):
+            lf_get_T(self.h, out.data_ptr(), 1)
+            return out
+        a = np.empty(self.mesh.n_cells, np.float64)
+        lf_get_T(self.h, a.ctypes.data, 0)
+        return a
+
+    def step(self, n_steps=1, check=True):
+        stats = (lf_solve_stats * max(n_steps, 1))()
+        status = lf_step(self.h, n_steps, stats)
+        if check:
+            _check(status, "lf_step")
+        return [s.as_dict() for s in stats[:n_steps]], status
+
+    def assemble(self):
+        lf_assemble(self.h)
+
+    def matrix(self):
+        N, F, B = self.mesh.n_cells, self.mesh.n_faces, self.mesh.n_bfaces
+        out = dict(diag=np.empty(N), upper=np.empty(max(F, 1)), source=np.empty(N),
+                   diag_b=np.empty(N), source_b=np.empty(N), int_coeff=np.empty(max(B, 1)),
+                   bou_coeff=np.empty(max(B, 1)))
+        lf_get_matrix(self.h, **out)
+        out["upper"] = out["upper"][:F]
+        out["int_coeff"] = out["int_coeff"][:B]
+        out["bou_coeff"] = out["bou_coeff"][:B]
+        return out
+
+    def amul(self, x, y):
+        lf_amul(self.h, x.data_ptr(), y.data_ptr())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lf_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

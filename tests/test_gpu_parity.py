@@ -1,0 +1,225 @@
+"""GPU path vs the oracle, element by element, through the C ABI.
+
+Bars: integer addressing bit-exact; assembled coefficients within 1e-14
+relative; T within 1e-8 max relative error at every step; PCG iterations
+within +-1; Amul bitwise when fed the same matrix (same operation order, no
+FMA contraction on either side).
+"""
+import numpy as np
+import pytest
+
+import synth
+from synth import FIXED_VALUE, ZERO_GRADIENT
+from tests.gpu_common import lapfoam, run_gpu, max_rel
+
+pytestmark = pytest.mark.gpu
+
+COEF_TOL = 1e-14
+T_TOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def L():
+    return lapfoam()
+
+
+def _meshes():
+    base = synth.box_mesh(7, 5, 3, z_ratio=4.0)                 # 105 cells: ragged tail
+    yield "natural_7x5x3", base
+    yield "random_7x5x3", synth.renumber(base, synth.random_permutation(base.n_cells, 2))
+    yield "redblack_6x6x4", synth.renumber(synth.box_mesh(6, 6, 4),
+                                           synth.red_black_numbering(synth.box_mesh(6, 6, 4))[0])
+    yield "line_9", synth.box_mesh(9, 1, 1)
+    yield "one_cell", synth.box_mesh(1, 1, 1)
+    g = synth.box_mesh(24, 20, 18, z_ratio=10.0)                 # several workgroups
+    yield "graded_24x20x18", g
+    yield "random_24x20x18", synth.renumber(g, synth.random_permutation(g.n_cells, 1))
+
+
+@pytest.mark.parametrize("name,mesh", list(_meshes()), ids=[n for n, _ in _meshes()])
+def test_addressing_is_exact(L, name, mesh):
+    """Section 5.2 lists of lists against their definitions (bit-exact)."""
+    m = L.Mesh(mesh)
+    a = m.addressing()
+    N = mesh.n_cells
+    own, nei = mesh.owner.astype(np.int64), mesh.neighbour.astype(np.int64)
+    assert np.array_equal(a["owner_start"], np.searchsorted(own, np.arange(N + 1), side="left"))
+    assert np.array_equal(a["losort"], np.argsort(nei, kind="stable"))
+    assert np.array_equal(a["losort_start"],
+                          np.concatenate(([0], np.cumsum(np.bincount(nei, minlength=N)))))
+    bc = mesh.bface_cell.astype(np.int64)
+    assert np.array_equal(a["bface_list"], np.argsort(bc, kind="stable"))
+    assert np.array_equal(a["bface_start"],
+                          np.concatenate(([0], np.cumsum(np.bincount(bc, minlength=N)))))
+    m.close()
+
+
+BCS_MIXED = [(FIXED_VALUE, 273.0), (FIXED_VALUE, 573.0), (ZERO_GRADIENT, 0.0),
+             (FIXED_VALUE, 400.0), (ZERO_GRADIENT, 0.0), (FIXED_VALUE, 300.0)]
+
+
+@pytest.mark.parametrize("name,mesh", list(_meshes()), ids=[n for n, _ in _meshes()])
+def test_matrix_matches_oracle(L, oracle, name, mesh):
+    T0 = synth.initial_field(mesh.n_cells, 5)
+    DT, dt = 3e-3, 2e-3
+    m = L.Mesh(mesh)
+    P = L.Problem(m, BCS_MIXED, DT, dt)
+    P.set_T(T0)
+    P.assemble()
+    g = P.matrix()
+    o = oracle.assemble(mesh, BCS_MIXED, DT, dt, T0)
+    for k in ("diag", "upper", "source", "diag_b", "source_b", "int_coeff", "bou_coeff"):
+        if o[k].size == 0:
+            continue
+        scale = np.maximum(np.abs(o[k]), 1e-300)
+        err = np.max(np.abs(g[k] - o[k]) / scale)
+        assert err <= COEF_TOL, (k, err)
+    P.close()
+    m.close()
+
+
+def test_matrix_is_bitwise_equal_to_oracle(L, oracle):
+    """Same operation order and no contraction: the coefficients agree bit for bit."""
+    mesh = synth.box_mesh(24, 20, 18, z_ratio=10.0)
+    T0 = synth.initial_field(mesh.n_cells, 6)
+    m = L.Mesh(mesh)
+    P = L.Problem(m, BCS_MIXED, 1e-3, 1e-3)
+    P.set_T(T0)
+    P.assemble()
+    g = P.matrix()
+    o = oracle.assemble(mesh, BCS_MIXED, 1e-3, 1e-3, T0)
+    for k in ("diag", "upper", "source", "diag_b", "source_b", "int_coeff", "bou_coeff"):
+        assert np.array_equal(g[k], o[k]), k
+    P.close()
+    m.close()
+
+
+@pytest.mark.parametrize("name,mesh", list(_meshes()), ids=[n for n, _ in _meshes()])
+def test_amul_bitwise(L, oracle, name, mesh):
+    import torch
+    T0 = synth.initial_field(mesh.n_cells, 7)
+    m = L.Mesh(mesh)
+    P = L.Problem(m, BCS_MIXED, 1e-3, 1e-3)
+    P.set_T(T0)
+    P.assemble()
+    g = P.matrix()
+    x = np.random.default_rng(3).uniform(-1.0, 1.0, mesh.n_cells)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.empty_like(xd)
+    P.amul(xd, yd)
+    torch.cuda.synchronize()
+    y = yd.cpu().numpy()
+    y_ref = oracle.amul(mesh, g["diag_b"], g["upper"], x)
+    assert np.array_equal(y, y_ref)
+    P.close()
+    m.close()
+
+
+CASES = [
+    # name, config, n override, steps, precond
+    ("plain_32", "plain_32", None, 20, 0),
+    ("graded_24", "graded_256", 24, 6, 0),
+    ("permuted_20", "permuted_192", 20, 6, 0),
+    ("dic_redblack_16", "graded_256_dic", 16, 6, 1),
+    ("dic_redblack_odd_9", "graded_256_dic", 9, 4, 1),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_steps_match_oracle(L, oracle, case):
+    name, cfg, n, steps, pc = case
+    p = synth.build_config(cfg, n=n, steps=steps)
+    Tg, sg = run_gpu(L, p.mesh, p.bcs, p.DT, p.dt, p.T0, steps, precond=pc)
+    To, so, snaps = oracle.run(p.mesh, p.bcs, p.DT, p.dt, steps, p.T0, pc=pc, keep_all=True)
+    for s in range(steps):
+        assert max_rel(Tg[s], snaps[s]) <= T_TOL, (s, max_rel(Tg[s], snaps[s]))
+        assert abs(sg[s]["n_iter"] - so[s]["n_iter"]) <= 1, (s, sg[s], so[s])
+        assert sg[s]["converged"] == 1 and so[s]["converged"] == 1
+        assert abs(sg[s]["initial_residual"] - so[s]["initial_residual"]) <= \
+            1e-10 * so[s]["initial_residual"]
+        assert sg[s]["final_residual"] < 1e-9
+        assert sg[s]["singular"] == 0 and sg[s]["nonfinite"] == 0
+
+
+EDGE = [
+    ("one_cell", lambda: synth.box_mesh(1, 1, 1, lengths=(0.5, 0.25, 2.0)), synth.fixed_x_bcs(), 0.7, 0.3, {}),
+    ("two_cells", lambda: synth.box_mesh(2, 1, 1), synth.fixed_x_bcs(), 0.2, 0.1, {}),
+    ("line_33", lambda: synth.box_mesh(33, 1, 1), synth.fixed_x_bcs(), 0.05, 0.01, {}),
+    ("all_zero_gradient", lambda: synth.box_mesh(9, 7, 5, z_ratio=3.0), synth.all_zero_gradient(), 1e-2, 1e-2, {}),
+    ("zero_DT", lambda: synth.box_mesh(8, 8, 8), synth.fixed_x_bcs(), 0.0, 1e-3, {}),
+    ("max_iter_1", lambda: synth.box_mesh(10, 10, 10), synth.fixed_x_bcs(), 1e-2, 1e-2, dict(max_iter=1)),
+    ("min_iter_7", lambda: synth.box_mesh(10, 10, 10), synth.fixed_x_bcs(), 1e-3, 1e-3, dict(min_iter=7)),
+    ("rel_tol", lambda: synth.box_mesh(10, 10, 10), synth.fixed_x_bcs(), 1e-2, 1e-2, dict(rel_tol=1e-3)),
+    ("tiny_chunks", lambda: synth.box_mesh(13, 11, 9, z_ratio=2.0), synth.fixed_x_bcs(), 1e-2, 1e-2,
+     dict(block_cells=7)),
+    ("no_graph", lambda: synth.box_mesh(13, 11, 9), synth.fixed_x_bcs(), 1e-2, 1e-2, dict(use_graph=0)),
+    ("check_every_iter", lambda: synth.box_mesh(13, 11, 9), synth.fixed_x_bcs(), 1e-2, 1e-2,
+     dict(iters_per_check=1)),
+]
+
+
+@pytest.mark.parametrize("case", EDGE, ids=[c[0] for c in EDGE])
+def test_edge_cases_match_oracle(L, oracle, case):
+    name, mk, bcs, DT, dt, opts = case
+    mesh = mk()
+    T0 = synth.initial_field(mesh.n_cells, 13)
+    steps = 3
+    oo = {k: v for k, v in opts.items() if k in ("max_iter", "min_iter", "rel_tol")}
+    Tg, sg = run_gpu(L, mesh, bcs, DT, dt, T0, steps, **opts)
+    To, so, snaps = oracle.run(mesh, bcs, DT, dt, steps, T0, keep_all=True, **oo)
+    for s in range(steps):
+        assert max_rel(Tg[s], snaps[s]) <= T_TOL, (name, s)
+        assert abs(sg[s]["n_iter"] - so[s]["n_iter"]) <= 1, (name, s, sg[s], so[s])
+        assert sg[s]["converged"] == so[s]["converged"], (name, s, sg[s], so[s])
+    if name == "zero_DT":
+        assert all(s["n_iter"] == 0 for s in sg)
+    if name == "max_iter_1":
+        assert all(s["n_iter"] == 1 and s["converged"] == 0 for s in sg)
+    if name == "min_iter_7":
+        assert all(s["n_iter"] >= 7 for s in sg)
+
+
+def test_determinism_and_graph_equivalence(L):
+    """No atomics in floating point: two runs, with or without graphs, are bitwise equal."""
+    p = synth.build_config("permuted_192", n=22, steps=4)
+    a, sa = run_gpu(L, p.mesh, p.bcs, p.DT, p.dt, p.T0, 4)
+    b, sb = run_gpu(L, p.mesh, p.bcs, p.DT, p.dt, p.T0, 4)
+    c, sc = run_gpu(L, p.mesh, p.bcs, p.DT, p.dt, p.T0, 4, use_graph=0, iters_per_check=3)
+    for s in range(4):
+        assert np.array_equal(a[s], b[s]) and np.array_equal(a[s], c[s])
+        for k in ("n_iter", "initial_residual", "final_residual"):
+            assert sa[s][k] == sb[s][k] == sc[s][k]
+
+
+def test_multi_step_call_equals_single_steps(L):
+    p = synth.build_config("graded_256", n=16, steps=5)
+    a, _ = run_gpu(L, p.mesh, p.bcs, p.DT, p.dt, p.T0, 5)
+    b, _ = run_gpu(L, p.mesh, p.bcs, p.DT, p.dt, p.T0, 5, keep_all=False)
+    assert np.array_equal(a[-1], b[-1])
+
+
+def test_set_T_rejects_nonfinite(L):
+    import torch
+    mesh = synth.box_mesh(4, 4, 4)
+    m = L.Mesh(mesh)
+    P = L.Problem(m, synth.fixed_x_bcs(), 1e-3, 1e-3)
+    bad = np.full(mesh.n_cells, 300.0)
+    bad[5] = np.nan
+    with pytest.raises(L.LapfoamError):
+        P.set_T(bad)
+    bad_d = torch.from_numpy(bad).cuda()
+    with pytest.raises(L.LapfoamError):
+        P.set_T(bad_d)
+    P.set_T(torch.full((mesh.n_cells,), 300.0, dtype=torch.float64, device="cuda"))
+    assert np.all(P.get_T() == 300.0)
+    P.close()
+    m.close()
+
+
+def test_dic_refused_without_two_colours(L):
+    mesh = synth.box_mesh(4, 4, 4)
+    m = L.Mesh(mesh)
+    with pytest.raises(L.LapfoamError) as e:
+        L.Problem(m, synth.fixed_x_bcs(), 1e-3, 1e-3, L.make_opts(precond=L.LF_PC_DIC))
+    assert e.value.status == L.LF_EINVAL
+    m.close()
