@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Throughput of the laplacianFoam hot path on one MI355X.
+
+A step is one implicit-Euler time step of the 256^3 z-graded box (expansion
+ratio 10, fixedValue 273/573 K on the x walls, zeroGradient elsewhere,
+DT = 1e-3, dt = 1e-3): assembly of ddt(T) - laplacian(DT, T) into the LDU
+matrix and its PCG solve (diagonal preconditioner, normalised residual 1e-9),
+FP64.  The metric is cell-PCG-iterations per second over the timed steps
+(cells x PCG iterations / wall time of the whole steps, assembly included).
+
+Inputs are resident in HBM before the timed region; warmup steps run first,
+then T is reset to T0 so the timed steps are steps 1..K of the workload.
+
+Also reported: the dominant kernel's roofline (algorithmic bytes per launch /
+average device duration, from HIP events on the library's stream during a
+separate pass over the same steps), HBM traffic from rocprofv3 counters when
+the kernel is unchanged since they were taken, and the oracle's rate on a
+bounded sample on the host CPU.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-PCG-iters/sec + Amul/PCG HBM GB/s (% peak), FP64 vs mixed @1e-8; p99"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+KERNEL_SOURCES = ["paper_2507_18268_amd/csrc/lf_pcg.hip", "paper_2507_18268_amd/csrc/lf_kernels.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_amul_dot_graded256.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def amul_bytes(n_cells, n_faces, value_bytes=8):
+    """Algorithmic bytes of one LDU product: x, diag and Ax once per cell, the
+    coefficient and the two face addresses (int32) once per face."""
+    return 3 * value_bytes * n_cells + (value_bytes + 8) * n_faces
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q / 100.0
+    lo = int(k)
+    hi = min(lo + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def cpu_baseline(p, budget_s):
+    """The oracle (single thread, FP64) on the first step(s) of the same workload."""
+    from oracle import oracle
+    steps, solve_s, iters = 0, 0.0, 0
+    T = p.T0.copy()
+    t_start = time.perf_counter()
+    while steps < p.steps:
+        T, st, _ = oracle.run(p.mesh, p.bcs, p.DT, p.dt, 1, T)
+        steps += 1
+        solve_s += st[0]["solve_s"]
+        iters += st[0]["n_iter"]
+        if time.perf_counter() - t_start > budget_s:
+            break
+    return {"value": p.mesh.n_cells * iters / solve_s, "unit": "cell-PCG-iters/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"first {steps} time step(s) of the same workload, PCG solve time only, "
+                      f"{iters} iterations, {solve_s:.2f} s, one host thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="graded_256")
+    ap.add_argument("--n", type=int, default=None, help="override the cube side (testing only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-roofline-pass", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (for counter scaling)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    if args.copy_calibration:
+        n = 64 << 20                      # 64 Mi doubles = 512 MiB each way
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": n * 8, "launches": 5}))
+        return
+
+    import synth
+    from paper_2507_18268_amd import lapfoam as L
+
+    t = time.perf_counter()
+    p = synth.build_config(args.config, n=args.n)
+    N, F = p.mesh.n_cells, p.mesh.n_faces
+    log(f"[bench] {args.config}: {N} cells, {F} faces, mesh generated in {time.perf_counter() - t:.1f} s")
+    precond = L.LF_PC_DIC if p.precond == "dic" else L.LF_PC_DIAGONAL
+    precision = L.LF_PREC_MIXED if p.precision == "mixed" else L.LF_PREC_FP64
+    opts = L.make_opts(tol=synth.TOL, rel_tol=synth.REL_TOL, max_iter=synth.MAX_ITER,
+                       precond=precond, precision=precision)
+    t = time.perf_counter()
+    mesh = L.Mesh(p.mesh)
+    prob = L.Problem(mesh, p.bcs, p.DT, p.dt, opts)
+    T0 = torch.from_numpy(p.T0).cuda()
+    torch.cuda.synchronize()
+    log(f"[bench] device mesh + problem ready in {time.perf_counter() - t:.1f} s "
+        f"(workspaces {mesh.ws_bytes / 2**30:.2f} + {prob.ws_bytes / 2**30:.2f} GiB)")
+
+    prob.set_T(T0)
+    if args.warmup > 0:
+        prob.step(args.warmup)
+    prob.set_T(T0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats, _ = prob.step(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log(f"[bench] timed {args.steps} steps in {wall:.3f} s")
+
+    iters = [s["n_iter"] for s in stats]
+    total_iters = sum(iters)
+    value = N * total_iters / wall
+    solve_s = sum(s["solve_ms"] for s in stats) / 1e3
+    step_ms = [s["assemble_ms"] + s["solve_ms"] for s in stats]
+    ok = all(s["converged"] == 1 for s in stats)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-PCG-iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if precision == L.LF_PREC_FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {round(N ** (1 / 3))}^3 box, z expansion ratio "
+                               f"{synth.CONFIGS[args.config]['z_ratio']}, DT={p.DT}, dt={p.dt}, "
+                               f"implicit Euler, PCG {p.precond}, tol {synth.TOL}",
+                   "n_cells": N, "n_faces": F, "precision": p.precision},
+        "iters_per_step_mean": total_iters / len(stats),
+        "solver_only_cell_iters_per_s": N * total_iters / solve_s if solve_s > 0 else None,
+        "assemble_ms_mean": sum(s["assemble_ms"] for s in stats) / len(stats),
+        "p50_step_ms": percentile(step_ms, 50), "p99_step_ms": percentile(step_ms, 99),
+        "all_converged": ok,
+    }
+
+    if not args.no_roofline_pass:
+        prob.set_T(T0)
+        prob.profile(True)
+        prob.step(args.steps)
+        torch.cuda.synchronize()
+        prof = prob.profile_read()
+        prob.profile(False)
+        kernels = {k: {"avg_us": 1e3 * ms / n, "launches": n} for k, (ms, n) in prof.items()}
+        out["kernel_avg_us"] = kernels
+        dom = max(prof, key=lambda k: prof[k][0])
+        ka = kernels["amul_dot"]
+        per_launch = amul_bytes(N, F)
+        achieved = per_launch / (ka["avg_us"] * 1e-6) / 1e9
+        roof = {"kernel": "k_amul_dot (q = A p with p.q partials)", "bound": "hbm",
+                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "algorithmic_bytes_per_launch": per_launch,
+                "avg_launch_us": ka["avg_us"], "largest_total_time_kernel": dom}
+        if os.path.exists(TRAFFIC_FILE):
+            with open(TRAFFIC_FILE) as f:
+                tr = json.load(f)
+            if tr.get("source_sha256") == kernel_source_hash() and tr.get("n_cells") == N:
+                roof["traffic"] = tr["hbm_bytes_per_launch"]
+        out["roofline"] = roof
+        # whole-iteration view: the three kernels of one PCG iteration
+        it_us = sum(kernels[k]["avg_us"] for k in ("amul_dot", "update", "direction") if k in kernels)
+        out["pcg_iteration_us"] = it_us
+
+    if not args.no_cpu_baseline:
+        log("[bench] oracle on the host ...")
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_budget)
+
+    prob.close()
+    mesh.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

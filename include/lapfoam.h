@@ -191,6 +191,33 @@ lf_status lf_get_matrix(lf_problem *problem, double *diag, double *upper, double
  * pointers of N doubles, ordered on the handle's stream. */
 lf_status lf_amul(lf_problem *problem, const double *x, double *y);
 
+/* ---- per-kernel device timing (diagnostics) ------------------------------
+ * When enabled, lf_step records a HIP event pair around every kernel launch on
+ * the handle's stream (plain launches instead of graphs, and a convergence
+ * check after every iteration so that no launch is a no-op) and accumulates
+ * the device time of each kernel class.  lf_profile_read copies, for class k in
+ * [0, n_classes), the accumulated milliseconds to total_ms[k] and the launch
+ * count to launches[k] (either may be NULL); lf_profile_enable(p, 1) also
+ * clears the accumulators. */
+#define LF_K_ASSEMBLE 0      /* cell-parallel TEqn assembly */
+#define LF_K_SETUP1 1        /* wA = A x0, r = b - wA, row sums, rD */
+#define LF_K_SETUP2 2        /* normalisation factor terms, first w.r */
+#define LF_K_DIRECTION 3     /* convergence decision + p = w + beta p */
+#define LF_K_AMUL_DOT 4      /* q = A p, p.q partials */
+#define LF_K_UPDATE 5        /* x += alpha p, r -= alpha q, |r| and w.r partials */
+#define LF_K_DIC_RD 6        /* DIC diagonal */
+#define LF_K_DIC_FORWARD 7   /* DIC forward sweep (black rows) */
+#define LF_K_DIC_BACKWARD 8  /* DIC backward sweep (red rows) + w.r partials */
+#define LF_K_MIXED_RESIDUAL 9   /* mixed: FP64 residual r = b - A T, |r| partials */
+#define LF_K_MIXED_CORRECT 10   /* mixed: T += d, FP32 copies */
+#define LF_K_INNER_DIRECTION 11 /* mixed: FP32 direction update */
+#define LF_K_INNER_AMUL_DOT 12  /* mixed: FP32 q = A p, FP64 p.q partials */
+#define LF_K_INNER_UPDATE 13    /* mixed: FP32 update, FP64 partials */
+#define LF_K_MIXED_PREP 14      /* mixed: FP32 coefficients */
+#define LF_NUM_KERNEL_CLASSES 16
+lf_status lf_profile_enable(lf_problem *problem, int32_t on);
+lf_status lf_profile_read(lf_problem *problem, int32_t n_classes, double *total_ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

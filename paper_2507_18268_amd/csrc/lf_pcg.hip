@@ -407,13 +407,13 @@ static lf_status launch_assemble(lf_problem *P, bool full, hipStream_t s) {
     const lf_mesh *m = P->mesh;
     const double rdt = 1.0 / P->dt;
     if (full)
-        hipLaunchKernelGGL(k_assemble<true>, cell_grid(P), dim3(kBlock), 0, s, P->sp, rdt, P->DT, m->row_start,
+        LF_LAUNCH(P, LF_K_ASSEMBLE, s, k_assemble<true>, cell_grid(P), dim3(kBlock), 0, s, P->sp, rdt, P->DT, m->row_start,
                            m->face_of, m->owner_start, m->mag_sf, m->delta, m->bface_start, m->bface_list,
                            m->bface_patch, m->bmag_sf, m->bdelta, P->patch_type, P->patch_value, m->V, P->T,
                            P->coef, P->upper, P->diag, P->source, P->diagB, P->srcB, P->int_coeff,
                            P->bou_coeff);
     else
-        hipLaunchKernelGGL(k_assemble<false>, cell_grid(P), dim3(kBlock), 0, s, P->sp, rdt, P->DT, m->row_start,
+        LF_LAUNCH(P, LF_K_ASSEMBLE, s, k_assemble<false>, cell_grid(P), dim3(kBlock), 0, s, P->sp, rdt, P->DT, m->row_start,
                            m->face_of, m->owner_start, m->mag_sf, m->delta, m->bface_start, m->bface_list,
                            m->bface_patch, m->bmag_sf, m->bdelta, P->patch_type, P->patch_value, m->V, P->T,
                            P->coef, P->upper, P->diag, P->source, P->diagB, P->srcB, P->int_coeff,
@@ -425,18 +425,18 @@ static lf_status launch_assemble(lf_problem *P, bool full, hipStream_t s) {
 static lf_status launch_setup(lf_problem *P, hipStream_t s) {
     const lf_mesh *m = P->mesh;
     const bool diag_pc = P->opts.precond == LF_PC_DIAGONAL;
-    hipLaunchKernelGGL(k_setup1, cell_grid(P), dim3(kBlock), 0, s, P->sp, diag_pc ? 1 : 0, P->diagB, P->coef,
+    LF_LAUNCH(P, LF_K_SETUP1, s, k_setup1, cell_grid(P), dim3(kBlock), 0, s, P->sp, diag_pc ? 1 : 0, P->diagB, P->coef,
                        m->row_start, m->col, P->T, P->srcB, P->q, P->r, P->sumA, P->rD, P->part, P->state);
     if (!diag_pc) {
-        hipLaunchKernelGGL(k_dic_rd, cell_grid(P), dim3(kBlock), 0, s, P->sp, P->diagB, P->coef, m->row_start,
+        LF_LAUNCH(P, LF_K_DIC_RD, s, k_dic_rd, cell_grid(P), dim3(kBlock), 0, s, P->sp, P->diagB, P->coef, m->row_start,
                            m->col, m->owner_start, P->rD);
     }
-    hipLaunchKernelGGL(k_setup2, cell_grid(P), dim3(kBlock), 0, s, P->sp, diag_pc ? 1 : 0, P->sumA, P->q,
+    LF_LAUNCH(P, LF_K_SETUP2, s, k_setup2, cell_grid(P), dim3(kBlock), 0, s, P->sp, diag_pc ? 1 : 0, P->sumA, P->q,
                        P->srcB, P->rD, P->r, P->part);
     if (!diag_pc) {
-        hipLaunchKernelGGL(k_dic_forward, cell_grid(P), dim3(kBlock), 0, s, P->sp, P->coef, m->row_start, m->col,
+        LF_LAUNCH(P, LF_K_DIC_FORWARD, s, k_dic_forward, cell_grid(P), dim3(kBlock), 0, s, P->sp, P->coef, m->row_start, m->col,
                            m->owner_start, P->rD, P->r, P->w, P->state);
-        hipLaunchKernelGGL(k_dic_backward, cell_grid(P), dim3(kBlock), 0, s, P->sp, P->coef, m->row_start,
+        LF_LAUNCH(P, LF_K_DIC_BACKWARD, s, k_dic_backward, cell_grid(P), dim3(kBlock), 0, s, P->sp, P->coef, m->row_start,
                            m->col, m->owner_start, P->rD, P->r, P->w, P->part, P->state);
     }
     LF_HIP(hipGetLastError());
@@ -445,10 +445,10 @@ static lf_status launch_setup(lf_problem *P, hipStream_t s) {
 
 static void launch_direction(lf_problem *P, hipStream_t s) {
     if (P->opts.precond == LF_PC_DIAGONAL)
-        hipLaunchKernelGGL(k_direction<true>, cell_grid(P), dim3(kBlock), 0, s, P->sp, P->rD, P->r, P->w, P->p,
+        LF_LAUNCH(P, LF_K_DIRECTION, s, k_direction<true>, cell_grid(P), dim3(kBlock), 0, s, P->sp, P->rD, P->r, P->w, P->p,
                            P->part, P->state);
     else
-        hipLaunchKernelGGL(k_direction<false>, cell_grid(P), dim3(kBlock), 0, s, P->sp, P->rD, P->r, P->w, P->p,
+        LF_LAUNCH(P, LF_K_DIRECTION, s, k_direction<false>, cell_grid(P), dim3(kBlock), 0, s, P->sp, P->rD, P->r, P->w, P->p,
                            P->part, P->state);
 }
 
@@ -457,22 +457,34 @@ static void launch_direction(lf_problem *P, hipStream_t s) {
 static lf_status launch_iteration(lf_problem *P, hipStream_t s) {
     const lf_mesh *m = P->mesh;
     const bool diag_pc = P->opts.precond == LF_PC_DIAGONAL;
-    hipLaunchKernelGGL(k_amul_dot, cell_grid(P), dim3(kBlock), 0, s, P->sp, P->diagB, P->coef, m->row_start,
+    LF_LAUNCH(P, LF_K_AMUL_DOT, s, k_amul_dot, cell_grid(P), dim3(kBlock), 0, s, P->sp, P->diagB, P->coef, m->row_start,
                        m->col, P->p, P->q, P->part, P->state);
     if (diag_pc) {
-        hipLaunchKernelGGL(k_update<true>, cell_grid(P), dim3(kBlock), 0, s, P->sp, P->T, P->p, P->q, P->r, P->rD,
+        LF_LAUNCH(P, LF_K_UPDATE, s, k_update<true>, cell_grid(P), dim3(kBlock), 0, s, P->sp, P->T, P->p, P->q, P->r, P->rD,
                            P->part, P->state);
     } else {
-        hipLaunchKernelGGL(k_update<false>, cell_grid(P), dim3(kBlock), 0, s, P->sp, P->T, P->p, P->q, P->r,
+        LF_LAUNCH(P, LF_K_UPDATE, s, k_update<false>, cell_grid(P), dim3(kBlock), 0, s, P->sp, P->T, P->p, P->q, P->r,
                            P->rD, P->part, P->state);
-        hipLaunchKernelGGL(k_dic_forward, cell_grid(P), dim3(kBlock), 0, s, P->sp, P->coef, m->row_start, m->col,
+        LF_LAUNCH(P, LF_K_DIC_FORWARD, s, k_dic_forward, cell_grid(P), dim3(kBlock), 0, s, P->sp, P->coef, m->row_start, m->col,
                            m->owner_start, P->rD, P->r, P->w, P->state);
-        hipLaunchKernelGGL(k_dic_backward, cell_grid(P), dim3(kBlock), 0, s, P->sp, P->coef, m->row_start,
+        LF_LAUNCH(P, LF_K_DIC_BACKWARD, s, k_dic_backward, cell_grid(P), dim3(kBlock), 0, s, P->sp, P->coef, m->row_start,
                            m->col, m->owner_start, P->rD, P->r, P->w, P->part, P->state);
     }
     launch_direction(P, s);
     LF_HIP(hipGetLastError());
     return LF_OK;
+}
+
+void prof_flush(lf_problem *P) {
+    for (const auto &r : P->prof_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            P->prof_ms[r.cls] += ms;
+            P->prof_n[r.cls] += 1;
+        }
+    }
+    P->prof_pending.clear();
+    P->ev_used = 0;
 }
 
 static lf_status get_iter_graph(lf_problem *P, int lg) {
@@ -494,7 +506,7 @@ static lf_status get_iter_graph(lf_problem *P, int lg) {
 
 static lf_status launch_iterations(lf_problem *P, int32_t k) {
     hipStream_t s = P->stream;
-    if (!P->opts.use_graph) {
+    if (!P->opts.use_graph || P->prof_on) {
         for (int32_t i = 0; i < k; ++i) LF_TRY(launch_iteration(P, s));
         return LF_OK;
     }
@@ -513,8 +525,8 @@ static lf_status solve_fp64(lf_problem *P, lf_solve_stats *out) {
     LF_TRY(launch_setup(P, s));
     launch_direction(P, s);
     LF_HIP(hipGetLastError());
-    int32_t k = P->opts.iters_per_check > 0 ? P->opts.iters_per_check
-                                           : std::max<int32_t>(1, P->last_iters > 0 ? P->last_iters : 8);
+    const int32_t fixed_k = P->prof_on ? 1 : P->opts.iters_per_check;
+    int32_t k = fixed_k > 0 ? fixed_k : std::max<int32_t>(1, P->last_iters > 0 ? P->last_iters : 8);
     int32_t launched = 0;
     for (;;) {
         k = std::min<int32_t>(k, std::max<int32_t>(1, P->sp.max_iter + 1 - launched));
@@ -523,12 +535,13 @@ static lf_status solve_fp64(lf_problem *P, lf_solve_stats *out) {
         LF_HIP(hipMemcpyAsync(P->h_state, P->state, sizeof(PcgState), hipMemcpyDeviceToHost, s));
         LF_HIP(hipEventRecord(P->ev[2], s));
         LF_HIP(hipEventSynchronize(P->ev[2]));
+        prof_flush(P);
         if (P->h_state->done) break;
         if (launched > P->sp.max_iter + P->sp.min_iter + 8) {
             set_error("solver state never reached done after %d iterations", launched);
             return LF_ESTATE;
         }
-        if (P->opts.iters_per_check <= 0) k = std::max<int32_t>(2, k / 2);
+        if (fixed_k <= 0) k = std::max<int32_t>(2, k / 2);
     }
     const PcgState &h = *P->h_state;
     out->initial_residual = h.res0;
@@ -663,6 +676,7 @@ lf_status lf_problem_destroy(lf_problem *P) {
     if (P->g_prologue) (void)hipGraphExecDestroy(P->g_prologue);
     if (P->capture_stream) (void)hipStreamDestroy(P->capture_stream);
     for (auto &e : P->ev) if (e) (void)hipEventDestroy(e);
+    for (auto &e : P->ev_pool) if (e) (void)hipEventDestroy(e);
     if (P->h_state) (void)hipHostFree(P->h_state);
     delete P;
     return LF_OK;
@@ -734,6 +748,26 @@ lf_status lf_amul(lf_problem *P, const double *x, double *y) {
     hipLaunchKernelGGL(k_amul, cell_grid(P), dim3(kBlock), 0, P->stream, P->sp, P->diagB, P->coef, m->row_start,
                        m->col, x, y);
     LF_HIP(hipGetLastError());
+    return LF_OK;
+}
+
+lf_status lf_profile_enable(lf_problem *P, int32_t on) {
+    clear_error();
+    if (!P) { set_error("NULL problem"); return LF_EINVAL; }
+    P->prof_on = on != 0;
+    for (int k = 0; k < LF_NUM_KERNEL_CLASSES; ++k) { P->prof_ms[k] = 0.0; P->prof_n[k] = 0; }
+    P->prof_pending.clear();
+    P->ev_used = 0;
+    return LF_OK;
+}
+
+lf_status lf_profile_read(lf_problem *P, int32_t n, double *total_ms, int64_t *launches) {
+    clear_error();
+    if (!P || n < 0) { set_error("bad argument"); return LF_EINVAL; }
+    for (int32_t k = 0; k < n; ++k) {
+        if (total_ms) total_ms[k] = k < LF_NUM_KERNEL_CLASSES ? P->prof_ms[k] : 0.0;
+        if (launches) launches[k] = k < LF_NUM_KERNEL_CLASSES ? P->prof_n[k] : 0;
+    }
     return LF_OK;
 }
 

@@ -74,4 +74,52 @@ struct lf_problem {
     int32_t last_iters = 0;
     bool assembled = false;
     size_t ws_bytes = 0;
+    // per-kernel device timing (diagnostics)
+    bool prof_on = false;
+    double prof_ms[LF_NUM_KERNEL_CLASSES] = {};
+    int64_t prof_n[LF_NUM_KERNEL_CLASSES] = {};
+    struct ProfRec { int cls; hipEvent_t a, b; };
+    std::vector<ProfRec> prof_pending;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
 };
+
+namespace lf {
+// Records an event pair around one kernel launch when timing is on and the
+// launch goes to the handle's own stream (never inside a graph capture).
+struct ProfScope {
+    lf_problem *P;
+    int cls;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    bool on;
+    hipEvent_t get() {
+        if (P->ev_used == P->ev_pool.size()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            P->ev_pool.push_back(e);
+        }
+        return P->ev_pool[P->ev_used++];
+    }
+    ProfScope(lf_problem *P_, int cls_, hipStream_t s_) : P(P_), cls(cls_), s(s_) {
+        on = P->prof_on && s == P->stream;
+        if (on) {
+            a = get();
+            on = a && hipEventRecord(a, s) == hipSuccess;
+        }
+    }
+    ~ProfScope() {
+        if (!on) return;
+        hipEvent_t b = get();
+        if (b && hipEventRecord(b, s) == hipSuccess) P->prof_pending.push_back({cls, a, b});
+    }
+};
+// accumulate the recorded pairs (call after the stream has been synchronised)
+void prof_flush(lf_problem *P);
+}  // namespace lf
+
+#define LF_LAUNCH(P, cls, s, ...)                  \
+    do {                                           \
+        ::lf::ProfScope ps_((P), (cls), (s));       \
+        hipLaunchKernelGGL(__VA_ARGS__);           \
+    } while (0)

@@ -89,7 +89,13 @@ _SIGS = {
     "lf_assemble": (C.c_int32, [C.c_void_p]),
     "lf_get_matrix": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 7),
     "lf_amul": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lf_profile_enable": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "lf_profile_read": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
 }
+
+KERNEL_CLASSES = ["assemble", "setup1", "setup2", "direction", "amul_dot", "update", "dic_rd",
+                  "dic_forward", "dic_backward", "mixed_residual", "mixed_correct",
+                  "inner_direction", "inner_amul_dot", "inner_update", "mixed_prep", "reserved15"]
 
 
 def lib():
@@ -194,6 +200,18 @@ def lf_get_matrix(h, diag=None, upper=None, source=None, diag_b=None, source_b=N
 
 def lf_amul(h, x_ptr, y_ptr):
     _check(lib().lf_amul(h, C.c_void_p(x_ptr), C.c_void_p(y_ptr)), "lf_amul")
+
+
+def lf_profile_enable(h, on):
+    _check(lib().lf_profile_enable(h, C.c_int32(1 if on else 0)), "lf_profile_enable")
+
+
+def lf_profile_read(h, n=16):
+    ms = np.zeros(n, np.float64)
+    cnt = np.zeros(n, np.int64)
+    _check(lib().lf_profile_read(h, C.c_int32(n), C.c_void_p(ms.ctypes.data),
+                                 C.c_void_p(cnt.ctypes.data)), "lf_profile_read")
+    return ms, cnt
 
 
 # --------------------------------------------------------------------------
@@ -339,6 +357,14 @@ class Problem:
 
     def amul(self, x, y):
         lf_amul(self.h, x.data_ptr(), y.data_ptr())
+
+    def profile(self, on=True):
+        lf_profile_enable(self.h, on)
+
+    def profile_read(self):
+        ms, cnt = lf_profile_read(self.h, len(KERNEL_CLASSES))
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(KERNEL_CLASSES)
+                if cnt[i] > 0}
 
     def close(self):
         if getattr(self, "h", None):
