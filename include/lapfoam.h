@@ -107,7 +107,7 @@ typedef struct lf_solver_opts {
     double inner_tol;           /* LF_PREC_MIXED: inner FP32 solve stops when its
                                    residual falls by this factor (0 = default 1e-4) */
     int32_t max_outer;          /* LF_PREC_MIXED: refinement passes cap (0 = 50) */
-    int32_t block_cells;        /* cells per workgroup chunk tuning knob (0 = auto) */
+    int32_t block_cells;        /* reserved, 0 */
 } lf_solver_opts;
 
 /* Per time step results. */
@@ -199,12 +199,13 @@ lf_status lf_amul(lf_problem *problem, const double *x, double *y);
  * [0, n_classes), the accumulated milliseconds to total_ms[k] and the launch
  * count to launches[k] (either may be NULL); lf_profile_enable(p, 1) also
  * clears the accumulators. */
-#define LF_K_ASSEMBLE 0      /* cell-parallel TEqn assembly */
-#define LF_K_SETUP1 1        /* wA = A x0, r = b - wA, row sums, rD */
-#define LF_K_SETUP2 2        /* normalisation factor terms, first w.r */
-#define LF_K_DIRECTION 3     /* convergence decision + p = w + beta p */
+#define LF_K_ASSEMBLE 0      /* cell-parallel TEqn assembly fused with A x0, r0,
+                                normalisation terms and the first w.r */
+#define LF_K_SETUP1 1        /* partial sums of x0 (mean for the normalisation) */
+#define LF_K_COMMIT 2        /* last pending x += alpha p of a solve */
+#define LF_K_DIRECTION 3     /* p = w + beta p, deferred x += alpha p */
 #define LF_K_AMUL_DOT 4      /* q = A p, p.q partials */
-#define LF_K_UPDATE 5        /* x += alpha p, r -= alpha q, |r| and w.r partials */
+#define LF_K_UPDATE 5        /* r -= alpha q, |r| and w.r partials */
 #define LF_K_DIC_RD 6        /* DIC diagonal */
 #define LF_K_DIC_FORWARD 7   /* DIC forward sweep (black rows) */
 #define LF_K_DIC_BACKWARD 8  /* DIC backward sweep (red rows) + w.r partials */
@@ -214,6 +215,7 @@ lf_status lf_amul(lf_problem *problem, const double *x, double *y);
 #define LF_K_INNER_AMUL_DOT 12  /* mixed: FP32 q = A p, FP64 p.q partials */
 #define LF_K_INNER_UPDATE 13    /* mixed: FP32 update, FP64 partials */
 #define LF_K_MIXED_PREP 14      /* mixed: FP32 coefficients */
+#define LF_K_FINALIZE 15        /* one-workgroup reductions and scalar decisions */
 #define LF_NUM_KERNEL_CLASSES 16
 lf_status lf_profile_enable(lf_problem *problem, int32_t on);
 lf_status lf_profile_read(lf_problem *problem, int32_t n_classes, double *total_ms, int64_t *launches);

@@ -1,0 +1,245 @@
+// C interface of the problem handle (see include/lapfoam.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "lf_solver.h"
+
+using namespace lf;
+
+extern "C" {
+
+lf_status lf_default_opts(lf_solver_opts *o) {
+    if (!o) return LF_EINVAL;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-9;
+    o->rel_tol = 0.0;
+    o->max_iter = 1000;
+    o->min_iter = 0;
+    o->precond = LF_PC_DIAGONAL;
+    o->precision = LF_PREC_FP64;
+    o->iters_per_check = 0;
+    o->use_graph = 1;
+    o->inner_tol = 0.0;
+    o->max_outer = 0;
+    o->block_cells = 0;
+    return LF_OK;
+}
+
+size_t lf_problem_workspace_bytes(const lf_mesh *m, const lf_solver_opts *o) {
+    if (!m) return 0;
+    lf_solver_opts d;
+    lf_default_opts(&d);
+    Carver cv(nullptr);
+    carve_problem(cv, m, o ? *o : d, nullptr);
+    return cv.bytes();
+}
+
+lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT, double dt,
+                            const lf_solver_opts *o, void *ws, size_t ws_bytes, void *stream, lf_problem **out) {
+    clear_error();
+    if (!out) { set_error("out is NULL"); return LF_EINVAL; }
+    *out = nullptr;
+    if (!m) { set_error("mesh is NULL"); return LF_EINVAL; }
+    if (m->P > 0 && !bcs) { set_error("bcs is NULL"); return LF_EINVAL; }
+    if (!(DT >= 0.0) || !std::isfinite(DT)) { set_error("DT must be finite and >= 0"); return LF_EINVAL; }
+    if (!(dt > 0.0) || !std::isfinite(dt)) { set_error("dt must be finite and > 0"); return LF_EINVAL; }
+    lf_solver_opts opts;
+    if (o) opts = *o; else lf_default_opts(&opts);
+    if (opts.max_iter < 0 || opts.min_iter < 0 || !std::isfinite(opts.tol) || !std::isfinite(opts.rel_tol)) {
+        set_error("bad solver options");
+        return LF_EINVAL;
+    }
+    if (opts.precond != LF_PC_DIAGONAL && opts.precond != LF_PC_DIC) { set_error("unknown preconditioner"); return LF_EINVAL; }
+    if (opts.precision != LF_PREC_FP64 && opts.precision != LF_PREC_MIXED) { set_error("unknown precision"); return LF_EINVAL; }
+    if (opts.precond == LF_PC_DIC && m->F > 0 && !m->two_colour) {
+        set_error("DIC needs a two-colour numbering (every owner < every neighbour)");
+        return LF_EINVAL;
+    }
+    if (opts.precond == LF_PC_DIC && opts.precision == LF_PREC_MIXED) {
+        set_error("the mixed-precision form uses the diagonal preconditioner");
+        return LF_EINVAL;
+    }
+    for (int32_t p = 0; p < m->P; ++p) {
+        if (bcs[p].type != LF_BC_ZERO_GRADIENT && bcs[p].type != LF_BC_FIXED_VALUE) {
+            set_error("patch %d: unknown boundary condition type %d", p, bcs[p].type);
+            return LF_EINVAL;
+        }
+        if (bcs[p].type == LF_BC_FIXED_VALUE && !std::isfinite(bcs[p].value)) {
+            set_error("patch %d: fixed value not finite", p);
+            return LF_EINVAL;
+        }
+    }
+    Carver dry(nullptr);
+    carve_problem(dry, m, opts, nullptr);
+    if (!ws || ws_bytes < dry.bytes() || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) {
+        set_error("problem workspace too small or misaligned: need %zu bytes, 256-aligned", dry.bytes());
+        return LF_ENOMEM;
+    }
+    int dev = 0;
+    LF_HIP(hipGetDevice(&dev));
+    if (dev != m->device) { set_error("problem created on device %d, mesh on %d", dev, m->device); return LF_EINVAL; }
+    lf_problem *P = new (std::nothrow) lf_problem();
+    if (!P) { set_error("host allocation failed"); return LF_ENOMEM; }
+    P->mesh = m;
+    P->opts = opts;
+    P->DT = DT;
+    P->dt = dt;
+    P->stream = static_cast<hipStream_t>(stream);
+    P->sp.tol = opts.tol;
+    P->sp.rel_tol = opts.rel_tol;
+    P->sp.max_iter = opts.max_iter;
+    P->sp.min_iter = opts.min_iter;
+    P->sp.n = m->N;
+    P->sp.grid = cell_blocks(m->N);
+    P->sp.n_red = m->two_colour ? m->n_red : m->N;
+    P->bcs.assign(bcs, bcs + m->P);
+    P->ws_bytes = dry.bytes();
+    Carver cv(ws);
+    carve_problem(cv, m, opts, P);
+    auto fail = [&](lf_status st) { lf_problem_destroy(P); return st; };
+    std::vector<int32_t> pt(std::max<int32_t>(m->P, 1), 0);
+    std::vector<double> pv(std::max<int32_t>(m->P, 1), 0.0);
+    for (int32_t p = 0; p < m->P; ++p) { pt[p] = bcs[p].type; pv[p] = bcs[p].value; }
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&P->h_state), sizeof(PcgState), hipHostMallocDefault);
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipEventCreate(&P->ev[i]);
+    if (e == hipSuccess) e = hipMemcpyAsync(P->patch_type, pt.data(), sizeof(int32_t) * pt.size(), hipMemcpyHostToDevice, P->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(P->patch_value, pv.data(), sizeof(double) * pv.size(), hipMemcpyHostToDevice, P->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(P->T, 0, sizeof(double) * m->N, P->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(P->state, 0, sizeof(PcgState), P->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(P->part, 0, sizeof(double) * kNumPart * P->sp.grid, P->stream);
+    // padding entries of the row layout keep coefficient 0 for good
+    if (e == hipSuccess) e = hipMemsetAsync(P->coef, 0, sizeof(double) * static_cast<size_t>(m->n_entries), P->stream);
+    if (e == hipSuccess && P->coef32)
+        e = hipMemsetAsync(P->coef32, 0, sizeof(float) * static_cast<size_t>(m->n_entries), P->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+    if (e != hipSuccess) { set_error("problem setup failed: %s", hipGetErrorString(e)); return fail(LF_EDEVICE); }
+    *out = P;
+    return LF_OK;
+}
+
+lf_status lf_problem_destroy(lf_problem *P) {
+    if (!P) return LF_OK;
+    for (auto &g : P->g_iter) if (g) (void)hipGraphExecDestroy(g);
+    if (P->capture_stream) (void)hipStreamDestroy(P->capture_stream);
+    for (auto &e : P->ev) if (e) (void)hipEventDestroy(e);
+    for (auto &e : P->ev_pool) if (e) (void)hipEventDestroy(e);
+    if (P->h_state) (void)hipHostFree(P->h_state);
+    delete P;
+    return LF_OK;
+}
+
+lf_status lf_set_T(lf_problem *P, const double *T, int32_t on_device) {
+    clear_error();
+    if (!P || !T) { set_error("NULL argument"); return LF_EINVAL; }
+    const int32_t N = P->mesh->N;
+    if (!on_device) {
+        for (int32_t c = 0; c < N; ++c)
+            if (!std::isfinite(T[c])) { set_error("T[%d] is not finite", c); return LF_EINVAL; }
+        LF_HIP(hipMemcpyAsync(P->T, T, sizeof(double) * N, hipMemcpyHostToDevice, P->stream));
+        LF_HIP(hipStreamSynchronize(P->stream));
+        return LF_OK;
+    }
+    bool ok = false;
+    LF_TRY(check_finite_device(P, T, &ok));
+    if (!ok) { set_error("T holds a non-finite value"); return LF_EINVAL; }
+    LF_HIP(hipMemcpyAsync(P->T, T, sizeof(double) * N, hipMemcpyDeviceToDevice, P->stream));
+    return LF_OK;
+}
+
+lf_status lf_get_T(lf_problem *P, double *T, int32_t on_device) {
+    clear_error();
+    if (!P || !T) { set_error("NULL argument"); return LF_EINVAL; }
+    const int32_t N = P->mesh->N;
+    LF_HIP(hipMemcpyAsync(T, P->T, sizeof(double) * N, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                          P->stream));
+    if (!on_device) LF_HIP(hipStreamSynchronize(P->stream));
+    return LF_OK;
+}
+
+lf_status lf_assemble(lf_problem *P) {
+    clear_error();
+    if (!P) { set_error("NULL problem"); return LF_EINVAL; }
+    LF_TRY(launch_assemble(P, true, P->stream));
+    P->assembled = true;
+    return LF_OK;
+}
+
+lf_status lf_get_matrix(lf_problem *P, double *diag, double *upper, double *source, double *diag_b,
+                        double *source_b, double *int_coeff, double *bou_coeff) {
+    clear_error();
+    if (!P) { set_error("NULL problem"); return LF_EINVAL; }
+    if (!P->assembled) { set_error("call lf_assemble first"); return LF_ESTATE; }
+    const lf_mesh *m = P->mesh;
+    hipStream_t s = P->stream;
+    const size_t N = m->N, F = m->F, B = m->B;
+    if (diag) LF_HIP(hipMemcpyAsync(diag, P->diag, 8 * N, hipMemcpyDeviceToHost, s));
+    if (source) LF_HIP(hipMemcpyAsync(source, P->source, 8 * N, hipMemcpyDeviceToHost, s));
+    if (diag_b) LF_HIP(hipMemcpyAsync(diag_b, P->diagB, 8 * N, hipMemcpyDeviceToHost, s));
+    if (source_b) LF_HIP(hipMemcpyAsync(source_b, P->srcB, 8 * N, hipMemcpyDeviceToHost, s));
+    if (upper && F) LF_HIP(hipMemcpyAsync(upper, P->upper, 8 * F, hipMemcpyDeviceToHost, s));
+    if (int_coeff && B) LF_HIP(hipMemcpyAsync(int_coeff, P->int_coeff, 8 * B, hipMemcpyDeviceToHost, s));
+    if (bou_coeff && B) LF_HIP(hipMemcpyAsync(bou_coeff, P->bou_coeff, 8 * B, hipMemcpyDeviceToHost, s));
+    LF_HIP(hipStreamSynchronize(s));
+    return LF_OK;
+}
+
+lf_status lf_amul(lf_problem *P, const double *x, double *y) {
+    clear_error();
+    if (!P || !x || !y) { set_error("NULL argument"); return LF_EINVAL; }
+    if (!P->assembled) { set_error("call lf_assemble first"); return LF_ESTATE; }
+    return launch_amul_hook(P, x, y);
+}
+
+lf_status lf_profile_enable(lf_problem *P, int32_t on) {
+    clear_error();
+    if (!P) { set_error("NULL problem"); return LF_EINVAL; }
+    P->prof_on = on != 0;
+    for (int k = 0; k < LF_NUM_KERNEL_CLASSES; ++k) { P->prof_ms[k] = 0.0; P->prof_n[k] = 0; }
+    P->prof_pending.clear();
+    P->ev_used = 0;
+    return LF_OK;
+}
+
+lf_status lf_profile_read(lf_problem *P, int32_t n, double *total_ms, int64_t *launches) {
+    clear_error();
+    if (!P || n < 0) { set_error("bad argument"); return LF_EINVAL; }
+    for (int32_t k = 0; k < n; ++k) {
+        if (total_ms) total_ms[k] = k < LF_NUM_KERNEL_CLASSES ? P->prof_ms[k] : 0.0;
+        if (launches) launches[k] = k < LF_NUM_KERNEL_CLASSES ? P->prof_n[k] : 0;
+    }
+    return LF_OK;
+}
+
+lf_status lf_step(lf_problem *P, int32_t n_steps, lf_solve_stats *stats) {
+    clear_error();
+    if (!P || n_steps < 0) { set_error("bad argument"); return LF_EINVAL; }
+    hipStream_t s = P->stream;
+    for (int32_t i = 0; i < n_steps; ++i) {
+        lf_solve_stats st;
+        std::memset(&st, 0, sizeof(st));
+        LF_HIP(hipEventRecord(P->ev[0], s));
+        LF_TRY(launch_assemble_setup(P, s));
+        LF_HIP(hipEventRecord(P->ev[1], s));
+        P->assembled = true;
+        if (P->opts.precision == LF_PREC_MIXED) {
+            LF_TRY(solve_mixed(P, &st));
+        } else {
+            LF_TRY(solve_fp64(P, &st));
+        }
+        float a_ms = 0.f, s_ms = 0.f;
+        LF_HIP(hipEventElapsedTime(&a_ms, P->ev[0], P->ev[1]));
+        LF_HIP(hipEventElapsedTime(&s_ms, P->ev[1], P->ev[2]));
+        st.assemble_ms = a_ms;
+        st.solve_ms = s_ms;
+        P->last_iters = st.n_iter;
+        if (stats) stats[i] = st;
+        if (st.nonfinite) { set_error("non-finite residual in step %d", i); return LF_ENONFINITE; }
+    }
+    return LF_OK;
+}
+
+}  // extern "C"

@@ -57,16 +57,12 @@ struct Carver {
 // ---------------------------------------------------------------------------
 // launch geometry shared by the cell-parallel kernels
 // ---------------------------------------------------------------------------
-constexpr int kBlock = 256;        // threads per workgroup (4 waves of 64)
-constexpr int kMaxGrid = 1024;     // workgroups per cell-parallel launch (upper bound)
+constexpr int kBlock = 256;        // threads per workgroup of the mesh-build kernels
+constexpr int kCellBlock = 512;    // threads per workgroup of the per-step kernels (one row each)
+constexpr int kFinBlock = 1024;    // threads of the one-workgroup reduction kernels
 constexpr int kNumXcd = 8;         // MI355X: 8 accelerator complex dies
-
-struct CellGrid {
-    int32_t n;        // cells
-    int32_t grid;     // workgroups launched
-    int32_t chunk;    // cells per workgroup (contiguous)
-};
-CellGrid make_cell_grid(int32_t n, int32_t block_cells);
+constexpr int kSlice = 64;         // rows per slice of the sliced row layout
+constexpr int kMaxRowLen = 255;    // entries per row (stored as uint8)
 
 // ---------------------------------------------------------------------------
 // handles
@@ -86,8 +82,15 @@ struct lf_mesh {
     int32_t *losort = nullptr, *losort_start = nullptr;   // [F], [N+1]
     int32_t *bface_start = nullptr, *bface_list = nullptr;   // [N+1], [B]
     int32_t *bface_cell = nullptr, *bface_patch = nullptr;   // [B]
-    int32_t *row_start = nullptr;                         // [N+1] = losort_start + owner_start
-    int32_t *col = nullptr, *face_of = nullptr;           // [2F] row-ordered off-diagonals
+    // Sliced row layout ("SELL-64"): rows grouped in slices of 64 consecutive
+    // cells (one wavefront); slice s holds width_s entry columns stored
+    // column-major, entry j of the row in lane l at soff[s] + 64 j + l.  A row's
+    // entries are its lower faces (ascending) then its owned faces (ascending).
+    int32_t n_slices = 0;
+    int64_t n_entries = 0;
+    int32_t *soff = nullptr;                              // [n_slices+1]
+    int32_t *scol = nullptr, *sface = nullptr;            // [n_entries]
+    uint8_t *rlen = nullptr;                              // [N] entries of each row
     double *V = nullptr;                                  // [N]
     double *mag_sf = nullptr, *delta = nullptr;           // [F]
     double *bmag_sf = nullptr, *bdelta = nullptr;         // [B]

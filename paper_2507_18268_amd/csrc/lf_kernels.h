@@ -1,4 +1,4 @@
-// Device helpers shared by the cell-parallel kernels.
+// Device helpers shared by the per-step kernels.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -6,29 +6,6 @@
 #include "lf_problem.h"
 
 namespace lf {
-
-// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
-// XCD b % 8).  Remap so that XCD x owns the contiguous logical range
-// [x*G/8, (x+1)*G/8): neighbouring cells (and on box meshes the +-n and +-n^2
-// neighbours) are then read through the same XCD's L2.
-__device__ __forceinline__ int32_t logical_block() {
-    const int32_t g = static_cast<int32_t>(gridDim.x);
-    const int32_t b = static_cast<int32_t>(blockIdx.x);
-    if (g >= kNumXcd && (g % kNumXcd) == 0) return (b % kNumXcd) * (g / kNumXcd) + b / kNumXcd;
-    return b;
-}
-
-struct CellRange {
-    int32_t begin, end;
-};
-
-__device__ __forceinline__ CellRange cell_range(int32_t n, int32_t chunk, int32_t L) {
-    int64_t b = static_cast<int64_t>(L) * chunk;
-    int64_t e = b + chunk;
-    if (e > n) e = n;
-    if (b > n) b = n;
-    return {static_cast<int32_t>(b), static_cast<int32_t>(e)};
-}
 
 // Sum over a wavefront of 64 lanes by xor butterflies; every lane ends with the
 // same value because each pairwise sum is commutative.
@@ -38,10 +15,11 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Sum of NQ values over the workgroup, result in every thread; fixed order.
-template <int NQ>
+// Sum of NQ values over a workgroup of BS threads, result in every thread;
+// fixed order (wave butterflies, then the wave sums in wave order).
+template <int BS, int NQ>
 __device__ __forceinline__ void block_sum(double (&v)[NQ]) {
-    constexpr int kWaves = kBlock / 64;
+    constexpr int kWaves = BS / 64;
     __shared__ double red[NQ][kWaves];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -61,59 +39,109 @@ __device__ __forceinline__ void block_sum(double (&v)[NQ]) {
     __syncthreads();
 }
 
-// Second stage of a two-stage reduction: every workgroup sums the G per-
-// workgroup partials of each slot in the same fixed order.
+// first stage: the workgroup's partial sums go to part[slot * G + blockIdx.x]
 template <int NQ>
-__device__ __forceinline__ void reduce_partials(const double *__restrict__ part, const int (&slot)[NQ],
-                                                int32_t G, double (&out)[NQ]) {
+__device__ __forceinline__ void write_partials(double *__restrict__ part, int32_t G, const int (&slot)[NQ],
+                                               double (&v)[NQ]) {
+    block_sum<kCellBlock, NQ>(v);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) part[slot[q] * G + blockIdx.x] = v[q];
+    }
+}
+
+// second stage (one workgroup of kFinBlock threads): fixed-order sums.  Thread
+// t adds part[t], part[t + 1024], ... in that order; the loads are issued in
+// groups of 8 so the serial chain waits once per group, not once per load.
+template <int NQ>
+__device__ __forceinline__ void reduce_partials(const double *__restrict__ part, int32_t G, const int (&slot)[NQ],
+                                                double (&out)[NQ]) {
+    constexpr int kU = 8;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
+        const double *__restrict__ src = part + static_cast<int64_t>(slot[q]) * G;
         double s = 0.0;
-        for (int32_t i = threadIdx.x; i < G; i += kBlock) s += part[slot[q] * kMaxGrid + i];
+        for (int32_t i0 = threadIdx.x; i0 < G; i0 += kU * kFinBlock) {
+            double v[kU];
+#pragma unroll
+            for (int j = 0; j < kU; ++j) {
+                const int32_t i = i0 + j * kFinBlock;
+                v[j] = i < G ? src[i] : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < kU; ++j) s += v[j];
+        }
         out[q] = s;
     }
-    block_sum<NQ>(out);
-}
-
-template <int NQ>
-__device__ __forceinline__ void write_partials(double *__restrict__ part, const int (&slot)[NQ],
-                                               double (&v)[NQ], int32_t L) {
-    block_sum<NQ>(v);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) part[slot[q] * kMaxGrid + L] = v[q];
-    }
-}
-
-// Snapshot of the solver state taken by one thread and shared through LDS, so
-// every thread of a workgroup acts on the same values even while workgroup 0
-// of the same kernel updates the state.
-struct StateView {
-    int32_t done, n_iter, converged;
-    double nf, res0, wArA_cur, wArA_prev;
-};
-
-__device__ __forceinline__ StateView load_state(const PcgState *st) {
-    __shared__ StateView sv;
-    if (threadIdx.x == 0) {
-        StateView v;
-        v.done = st->done;
-        v.n_iter = st->n_iter;
-        v.converged = st->converged;
-        v.nf = st->nf;
-        v.res0 = st->res0;
-        v.wArA_cur = st->wArA_cur;
-        v.wArA_prev = st->wArA_slot[(v.n_iter - 1) & 1];
-        sv = v;
-    }
-    __syncthreads();
-    StateView v = sv;
-    __syncthreads();
-    return v;
+    block_sum<kFinBlock, NQ>(out);
 }
 
 __device__ __forceinline__ bool check_conv(double res, double res0, double tol, double rel_tol) {
     return (res < tol) || (rel_tol > 1e-20 && res < rel_tol * res0);
+}
+
+// ---------------------------------------------------------------------------
+// Rows of the sliced layout: entry j of row c at soff[c/64] + 64 j + c%64.
+// Consecutive lanes hold consecutive rows, so each entry access of a
+// wavefront is one contiguous 64-element load.  The slice width is the same
+// for every lane of a wavefront, so the unrolled variants below load all of a
+// row's entries first and then use them in order (padding entries are loaded
+// but skipped: j >= len).
+// ---------------------------------------------------------------------------
+struct MeshRows {
+    const int32_t *__restrict__ soff;
+    const int32_t *__restrict__ scol;
+    const int32_t *__restrict__ sface;
+    const uint8_t *__restrict__ rlen;
+};
+
+// acc + sum_j a_j x[col_j] over the row's entries in order
+template <int W, class T, class A>
+__device__ __forceinline__ A row_dot_w(int32_t base, int32_t len, const int32_t *__restrict__ scol,
+                                       const T *__restrict__ coef, const T *__restrict__ x, A acc) {
+    int32_t col[W];
+    T a[W], xv[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        col[j] = scol[base + kSlice * j];
+        a[j] = coef[base + kSlice * j];
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j) xv[j] = x[col[j]];
+#pragma unroll
+    for (int j = 0; j < W; ++j)
+        if (j < len) acc += a[j] * xv[j];
+    return acc;
+}
+
+template <class T, class A>
+__device__ __forceinline__ A row_dot(const MeshRows &mr, int32_t c, const T *__restrict__ coef,
+                                     const T *__restrict__ x, A acc) {
+    const int32_t s = c >> 6;
+    const int32_t o0 = mr.soff[s];
+    const int32_t base = o0 + (c & (kSlice - 1));
+    const int32_t width = (mr.soff[s + 1] - o0) >> 6;
+    const int32_t len = mr.rlen[c];
+    switch (width) {
+        case 0: return acc;
+        case 1: return row_dot_w<1>(base, len, mr.scol, coef, x, acc);
+        case 2: return row_dot_w<2>(base, len, mr.scol, coef, x, acc);
+        case 3: return row_dot_w<3>(base, len, mr.scol, coef, x, acc);
+        case 4: return row_dot_w<4>(base, len, mr.scol, coef, x, acc);
+        case 5: return row_dot_w<5>(base, len, mr.scol, coef, x, acc);
+        case 6: return row_dot_w<6>(base, len, mr.scol, coef, x, acc);
+        case 7: return row_dot_w<7>(base, len, mr.scol, coef, x, acc);
+        case 8: return row_dot_w<8>(base, len, mr.scol, coef, x, acc);
+        default: {
+            int32_t idx = base;
+            for (int32_t j = 0; j < len; ++j, idx += kSlice) acc += coef[idx] * x[mr.scol[idx]];
+            return acc;
+        }
+    }
+}
+
+__device__ __forceinline__ int32_t row_base(const MeshRows &mr, int32_t c) {
+    return mr.soff[c >> 6] + (c & (kSlice - 1));
 }
 
 }  // namespace lf

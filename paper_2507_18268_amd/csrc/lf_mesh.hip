@@ -26,19 +26,6 @@ void set_error(const char *fmt, ...) {
 }
 void clear_error() { g_err[0] = '\0'; }
 
-CellGrid make_cell_grid(int32_t n, int32_t block_cells) {
-    CellGrid g;
-    g.n = n;
-    int64_t per = block_cells > 0 ? block_cells : kBlock;
-    int64_t grid = (static_cast<int64_t>(n) + per - 1) / per;
-    if (block_cells <= 0) grid = std::min<int64_t>(grid, kMaxGrid);
-    grid = std::max<int64_t>(1, std::min<int64_t>(grid, kMaxGrid));
-    if (grid >= kNumXcd) grid = grid / kNumXcd * kNumXcd;   // whole number per XCD
-    g.grid = static_cast<int32_t>(grid);
-    g.chunk = static_cast<int32_t>((static_cast<int64_t>(n) + grid - 1) / grid);
-    return g;
-}
-
 // ---------------------------------------------------------------------------
 // integer kernels for the addressing build
 // ---------------------------------------------------------------------------
@@ -159,29 +146,37 @@ __global__ void k_sort_segments(const int32_t *__restrict__ start, int32_t n, in
     }
 }
 
-// Row-ordered off-diagonal layout: row c lists its lower faces (ascending, the
-// faces where c is the neighbour; column = owner) then its owned faces
-// (ascending; column = neighbour).  On an upper-triangular mesh this is the
-// order in which a sequential face loop visits row c.
-__global__ void k_rows(int32_t n, const int32_t *__restrict__ owner, const int32_t *__restrict__ neighbour,
-                       const int32_t *__restrict__ owner_start, const int32_t *__restrict__ losort,
-                       const int32_t *__restrict__ losort_start, int32_t *__restrict__ row_start,
-                       int32_t *__restrict__ col, int32_t *__restrict__ face_of) {
+// Sliced row layout: row c lists its lower faces (ascending, the faces where c
+// is the neighbour; column = owner) then its owned faces (ascending; column =
+// neighbour).  On an upper-triangular mesh this is the order in which a
+// sequential face loop visits row c.  Entry j of row c (slice s = c/64, lane
+// l = c%64) sits at soff[s] + 64 j + l; entries past the row's length are
+// padding (column = c, face = 0, coefficient 0): kernels may load them but
+// never use them.
+__global__ void k_sell_fill(int32_t n, const int32_t *__restrict__ owner, const int32_t *__restrict__ neighbour,
+                            const int32_t *__restrict__ owner_start, const int32_t *__restrict__ losort,
+                            const int32_t *__restrict__ losort_start, const int32_t *__restrict__ soff,
+                            int32_t *__restrict__ scol, int32_t *__restrict__ sface, uint8_t *__restrict__ rlen) {
     int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (c > n) return;
-    int32_t e = losort_start[c] + owner_start[c];
-    row_start[c] = e;
-    if (c == n) return;
-    for (int32_t i = losort_start[c]; i < losort_start[c + 1]; ++i) {
-        int32_t f = losort[i];
-        col[e] = owner[f];
-        face_of[e] = f;
-        ++e;
+    if (c >= n) return;
+    const int32_t s = static_cast<int32_t>(c / kSlice), lane = static_cast<int32_t>(c % kSlice);
+    const int32_t width = (soff[s + 1] - soff[s]) / kSlice;
+    int32_t idx = soff[s] + lane, j = 0;
+    // the host sized every slice from the same face counts; the j < width
+    // guards only keep a disagreement from writing outside the slice
+    for (int32_t i = losort_start[c]; i < losort_start[c + 1] && j < width; ++i, ++j, idx += kSlice) {
+        const int32_t f = losort[i];
+        scol[idx] = owner[f];
+        sface[idx] = f;
     }
-    for (int32_t f = owner_start[c]; f < owner_start[c + 1]; ++f) {
-        col[e] = neighbour[f];
-        face_of[e] = f;
-        ++e;
+    for (int32_t f = owner_start[c]; f < owner_start[c + 1] && j < width; ++f, ++j, idx += kSlice) {
+        scol[idx] = neighbour[f];
+        sface[idx] = f;
+    }
+    rlen[c] = static_cast<uint8_t>(j);
+    for (; j < width; ++j, idx += kSlice) {
+        scol[idx] = static_cast<int32_t>(c);
+        sface[idx] = 0;
     }
 }
 
@@ -240,8 +235,9 @@ struct MeshScratch {
     double *bS, *bC;     // [3B]
 };
 
-static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, lf_mesh *m, MeshScratch *s) {
+static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, lf_mesh *m, MeshScratch *s) {
     size_t n1 = static_cast<size_t>(N) + 1;
+    const int32_t ns = (N + kSlice - 1) / kSlice;
     auto *owner = cv.take<int32_t>(F);
     auto *neighbour = cv.take<int32_t>(F);
     auto *owner_start = cv.take<int32_t>(n1);
@@ -251,9 +247,10 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, lf_mesh *m, 
     auto *bface_list = cv.take<int32_t>(B);
     auto *bface_cell = cv.take<int32_t>(B);
     auto *bface_patch = cv.take<int32_t>(B);
-    auto *row_start = cv.take<int32_t>(n1);
-    auto *col = cv.take<int32_t>(2 * static_cast<size_t>(F));
-    auto *face_of = cv.take<int32_t>(2 * static_cast<size_t>(F));
+    auto *soff = cv.take<int32_t>(static_cast<size_t>(ns) + 1);
+    auto *scol = cv.take<int32_t>(static_cast<size_t>(E));
+    auto *sface = cv.take<int32_t>(static_cast<size_t>(E));
+    auto *rlen = cv.take<uint8_t>(N);
     auto *V = cv.take<double>(N);
     auto *mag_sf = cv.take<double>(F);
     auto *delta = cv.take<double>(F);
@@ -271,10 +268,39 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, lf_mesh *m, 
         m->owner = owner; m->neighbour = neighbour; m->owner_start = owner_start;
         m->losort = losort; m->losort_start = losort_start; m->bface_start = bface_start;
         m->bface_list = bface_list; m->bface_cell = bface_cell; m->bface_patch = bface_patch;
-        m->row_start = row_start; m->col = col; m->face_of = face_of; m->V = V;
-        m->mag_sf = mag_sf; m->delta = delta; m->bmag_sf = bmag; m->bdelta = bdelta;
+        m->n_slices = ns; m->n_entries = E; m->soff = soff; m->scol = scol; m->sface = sface; m->rlen = rlen;
+        m->V = V; m->mag_sf = mag_sf; m->delta = delta; m->bmag_sf = bmag; m->bdelta = bdelta;
     }
     if (s) *s = sc;
+}
+
+// Slice offsets of the row layout from the row lengths (faces per cell),
+// counted on the host from the owner/neighbour lists: this only sizes the
+// workspace; the entries themselves are filled on the GPU.
+static lf_status plan_slices(const lf_mesh_desc *d, std::vector<int32_t> *soff, int64_t *E) {
+    const int32_t N = d->n_cells, F = d->n_faces;
+    std::vector<int32_t> len(static_cast<size_t>(N), 0);
+    for (int32_t f = 0; f < F; ++f) {
+        const int32_t o = d->owner[f], n = d->neighbour[f];
+        if (o >= 0 && o < N) ++len[o];
+        if (n >= 0 && n < N) ++len[n];
+    }
+    const int32_t ns = (N + kSlice - 1) / kSlice;
+    if (soff) soff->assign(static_cast<size_t>(ns) + 1, 0);
+    int64_t total = 0;
+    for (int32_t s = 0; s < ns; ++s) {
+        int32_t w = 0;
+        for (int32_t c = s * kSlice; c < std::min(N, (s + 1) * kSlice); ++c) w = std::max(w, len[c]);
+        if (w > kMaxRowLen) {
+            set_error("cell with %d faces: rows longer than %d are not supported", w, kMaxRowLen);
+            return LF_EMESH;
+        }
+        total += static_cast<int64_t>(w) * kSlice;
+        if (total > INT32_MAX) { set_error("mesh too large for 32-bit entry offsets"); return LF_EMESH; }
+        if (soff) (*soff)[s + 1] = static_cast<int32_t>(total);
+    }
+    *E = total;
+    return LF_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -390,8 +416,11 @@ const char *lf_last_error(void) { return g_err; }
 
 size_t lf_mesh_workspace_bytes(const lf_mesh_desc *d) {
     if (!d || d->n_cells < 1 || d->n_faces < 0 || d->n_patches < 0 || !d->patch_start) return 0;
+    if (d->n_faces > 0 && (!d->owner || !d->neighbour)) return 0;
+    int64_t E = 0;
+    if (plan_slices(d, nullptr, &E) != LF_OK) return 0;
     Carver cv(nullptr);
-    carve_mesh(cv, d->n_cells, d->n_faces, d->patch_start[d->n_patches], nullptr, nullptr);
+    carve_mesh(cv, d->n_cells, d->n_faces, d->patch_start[d->n_patches], E, nullptr, nullptr);
     return cv.bytes();
 }
 
@@ -403,8 +432,11 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
     bool two_colour = false;
     LF_TRY(validate(d, &B, &two_colour, &n_red));
     const int32_t N = d->n_cells, F = d->n_faces, P = d->n_patches;
+    std::vector<int32_t> soff_h;
+    int64_t E = 0;
+    LF_TRY(plan_slices(d, &soff_h, &E));
     Carver dry(nullptr);
-    carve_mesh(dry, N, F, B, nullptr, nullptr);
+    carve_mesh(dry, N, F, B, E, nullptr, nullptr);
     if (!ws || ws_bytes < dry.bytes() || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) {
         set_error("mesh workspace too small or misaligned: need %zu bytes, 256-aligned", dry.bytes());
         return LF_ENOMEM;
@@ -420,7 +452,7 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
     if (hipGetDevice(&m->device) != hipSuccess) { delete m; set_error("hipGetDevice failed"); return LF_EDEVICE; }
     Carver cv(ws);
     MeshScratch sc;
-    carve_mesh(cv, N, F, B, m, &sc);
+    carve_mesh(cv, N, F, B, E, m, &sc);
     hipStream_t s = m->stream;
 
     auto fail = [&](lf_status st) { delete m; return st; };
@@ -441,6 +473,7 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
         LF_HIPM(hipMemcpyAsync(m->owner, d->owner, sizeof(int32_t) * F, hipMemcpyHostToDevice, s));
         LF_HIPM(hipMemcpyAsync(m->neighbour, d->neighbour, sizeof(int32_t) * F, hipMemcpyHostToDevice, s));
     }
+    LF_HIPM(hipMemcpyAsync(m->soff, soff_h.data(), sizeof(int32_t) * soff_h.size(), hipMemcpyHostToDevice, s));
     LF_HIPM(hipMemcpyAsync(m->V, d->cell_volume, sizeof(double) * N, hipMemcpyHostToDevice, s));
     LF_HIPM(hipMemcpyAsync(sc.C, d->cell_centre, sizeof(double) * 3 * static_cast<size_t>(N),
                            hipMemcpyHostToDevice, s));
@@ -460,9 +493,8 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
     if (st != LF_OK) return fail(st);
     st = group_by_key(m->bface_cell, B, N, m->bface_start, m->bface_list, sc.cnt, sc.tile, s);
     if (st != LF_OK) return fail(st);
-    hipLaunchKernelGGL(k_rows, dim3(blocks_for(static_cast<int64_t>(N) + 1)), dim3(kBlock), 0, s, N, m->owner,
-                       m->neighbour, m->owner_start, m->losort, m->losort_start, m->row_start, m->col,
-                       m->face_of);
+    hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, m->owner, m->neighbour,
+                       m->owner_start, m->losort, m->losort_start, m->soff, m->scol, m->sface, m->rlen);
 
     // geometry factors, faces staged in chunks
     for (int64_t f0 = 0; f0 < F; f0 += kGeomChunk) {

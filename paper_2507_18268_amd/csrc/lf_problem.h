@@ -5,7 +5,9 @@
 
 namespace lf {
 
-// Slots of the per-workgroup partial sums (deterministic two-stage reductions).
+// Slots of the per-workgroup partial sums (deterministic two-stage reductions:
+// every cell-parallel workgroup writes its partial, a one-workgroup kernel
+// sums them in a fixed order).
 enum PartialSlot : int {
     kPartSumX = 0,   // sum of x0 (mean for the normalisation factor)
     kPartSumR = 1,   // sum |r|
@@ -15,16 +17,17 @@ enum PartialSlot : int {
     kNumPart = 5
 };
 
-// Solver state on the device.  Written only by workgroup 0 of a kernel; every
-// workgroup recomputes the same scalars from the same partials, so no
-// workgroup ever waits for another inside a kernel.
+// Solver state on the device.  Written only by the one-workgroup reduction
+// kernels; the cell-parallel kernels only read it.
 struct PcgState {
     double nf;            // normalisation factor
     double res0;          // initial normalised residual
     double res;           // current normalised residual
-    double wArA_cur;      // w.r of the current iteration (read by the update kernel)
-    double wArA_slot[2];  // w.r by iteration parity (read by the next direction update)
-    double alpha;         // last step length (diagnostics)
+    double wArA;          // w.r of the current iteration
+    double alpha;         // step length of the current iteration
+    double beta;          // direction coefficient of the next iteration
+    double x_avg;         // mean of x0
+    double pad;
     int32_t n_iter;
     int32_t done;
     int32_t converged;
@@ -33,13 +36,15 @@ struct PcgState {
     int32_t flag;         // scratch flag (input checks)
 };
 
+constexpr int kMaxGraphLog = 6;   // largest captured block: 64 iterations
+
 struct SolverParams {
     double tol, rel_tol;
     int32_t max_iter, min_iter;
     int32_t n;            // cells
-    int32_t chunk;        // cells per workgroup
-    int32_t grid;         // workgroups
+    int32_t grid;         // workgroups of a cell-parallel launch (= partials per slot)
     int32_t n_red;        // DIC: first black cell
+    int32_t pad;
 };
 
 }  // namespace lf
@@ -49,28 +54,27 @@ struct lf_problem {
     lf_solver_opts opts{};
     double DT = 0, dt = 0;
     hipStream_t stream = nullptr;
-    lf::CellGrid grid{};
     lf::SolverParams sp{};
     std::vector<lf_patch_bc> bcs;
     // device arrays (caller workspace)
     int32_t *patch_type = nullptr;
     double *patch_value = nullptr;
     double *T = nullptr;                       // [N] the field; PCG solves in place
-    double *r = nullptr, *p = nullptr, *q = nullptr, *w = nullptr, *rD = nullptr, *sumA = nullptr;
+    double *r = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr, *w = nullptr, *rD = nullptr;
     double *diag = nullptr, *source = nullptr, *diagB = nullptr, *srcB = nullptr;
-    double *upper = nullptr, *coef = nullptr;  // [F] face order, [2F] row order
+    double *upper = nullptr, *coef = nullptr;  // [F] face order, [n_entries] row layout
     double *int_coeff = nullptr, *bou_coeff = nullptr;
-    double *part = nullptr;                    // [kNumPart][kMaxGrid]
+    double *part = nullptr;                    // [kNumPart][grid]
     lf::PcgState *state = nullptr;
     // mixed precision (FP32 inner solve)
     float *coef32 = nullptr, *diag32 = nullptr, *rD32 = nullptr;
     float *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
+    double *Tsave = nullptr;
     // host side
     lf::PcgState *h_state = nullptr;           // pinned
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     hipStream_t capture_stream = nullptr;
-    hipGraphExec_t g_iter[8] = {};             // (KA, KU, KP) x 2^i
-    hipGraphExec_t g_prologue = nullptr;
+    hipGraphExec_t g_iter[lf::kMaxGraphLog + 1] = {};   // 2^i PCG iterations
     int32_t last_iters = 0;
     bool assembled = false;
     size_t ws_bytes = 0;

@@ -93,9 +93,9 @@ _SIGS = {
     "lf_profile_read": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
 }
 
-KERNEL_CLASSES = ["assemble", "setup1", "setup2", "direction", "amul_dot", "update", "dic_rd",
+KERNEL_CLASSES = ["assemble", "sum_x", "commit", "direction", "amul_dot", "update", "dic_rd",
                   "dic_forward", "dic_backward", "mixed_residual", "mixed_correct",
-                  "inner_direction", "inner_amul_dot", "inner_update", "mixed_prep", "reserved15"]
+                  "inner_direction", "inner_amul_dot", "inner_update", "mixed_prep", "finalize"]
 
 
 def lib():
