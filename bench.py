@@ -80,6 +80,75 @@ def cpu_baseline(p, budget_s):
                       f"{iters} iterations, {solve_s:.2f} s, one host thread"}
 
 
+def run_mixed(L, torch, p, mesh, prob64, T0, args):
+    """Precision form on the same workload: timed like the FP64 run, then an
+    untimed pass stepping both forms side by side for the per-step error."""
+    N = p.mesh.n_cells
+    opts = L.make_opts(tol=prob64.opts.tol, rel_tol=prob64.opts.rel_tol,
+                       max_iter=prob64.opts.max_iter, precision=L.LF_PREC_MIXED,
+                       inner_tol=args.inner_tol)
+    pm = L.Problem(mesh, p.bcs, p.DT, p.dt, opts)
+    pm.set_T(T0)
+    if args.warmup > 0:
+        pm.step(args.warmup)
+    pm.set_T(T0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats, _ = pm.step(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    inner = sum(s["n_iter"] for s in stats)
+    # kernel profile of the same steps
+    pm.set_T(T0)
+    pm.profile(True)
+    pm.step(args.steps)
+    torch.cuda.synchronize()
+    prof = pm.profile_read()
+    pm.profile(False)
+    # per-step error on the same system (each step starts from the precision
+    # form's own T_n): against the FP64 path at the same tolerance (itself
+    # checked against the oracle), and against an FP64 solve of that system
+    # converged to round-off (tol 1e-13), for both forms
+    ref_opts = L.make_opts(tol=1e-13, rel_tol=0.0, max_iter=prob64.opts.max_iter)
+    pref = L.Problem(mesh, p.bcs, p.DT, p.dt, ref_opts)
+    a = torch.empty(N, dtype=torch.float64, device="cuda")
+    b = torch.empty(N, dtype=torch.float64, device="cuda")
+    t = torch.empty(N, dtype=torch.float64, device="cuda")
+    pm.set_T(T0)
+    n_acc = min(args.steps, args.accuracy_steps)
+    e_mf, e_mt, e_ft = [], [], []
+    for _ in range(n_acc):
+        pm.get_T(a)
+        prob64.set_T(a)
+        pref.set_T(a)
+        pm.step(1)
+        prob64.step(1)
+        pref.step(1)
+        pm.get_T(a)
+        prob64.get_T(b)
+        pref.get_T(t)
+        e_mf.append(float(((a - b).abs() / b.abs()).max()))
+        e_mt.append(float(((a - t).abs() / t.abs()).max()))
+        e_ft.append(float(((b - t).abs() / t.abs()).max()))
+    pref.close()
+    pm.close()
+    return {"value_cell_steps_per_s": N * args.steps / wall, "inner_tol": opts.inner_tol,
+            "kernel_avg_us": {k: {"avg_us": 1e3 * ms / n, "launches": n} for k, (ms, n) in prof.items()},
+            "accuracy_steps": n_acc,
+            "max_rel_T_err_vs_converged_fp64_max": max(e_mt),
+            "fp64_at_tol_max_rel_T_err_vs_converged_fp64_max": max(e_ft),
+            "max_rel_T_err_vs_converged_fp64_first_steps": e_mt[:5],
+            "fp64_at_tol_err_vs_converged_first_steps": e_ft[:5],
+            "ms_per_step": wall * 1e3 / args.steps,
+            "inner_iters_per_step_mean": inner / len(stats),
+            "outer_passes_per_step_mean": sum(s["n_outer"] for s in stats) / len(stats),
+            "inner_cell_iters_per_s": N * inner / wall,
+            "all_converged": all(s["converged"] == 1 for s in stats),
+            "max_rel_T_err_vs_fp64_at_tol_max": max(e_mf),
+            "max_rel_T_err_vs_fp64_at_tol_first_steps": e_mf[:5],
+            "speedup_vs_fp64_time_to_tol": None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +159,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-roofline-pass", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--accuracy-steps", type=int, default=20)
+    ap.add_argument("--inner-tol", type=float, default=0.0, help="mixed: inner reduction (0 = default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()
@@ -197,6 +269,10 @@ def main():
         # whole-iteration view: the three kernels of one PCG iteration
         it_us = sum(kernels[k]["avg_us"] for k in ("amul_dot", "update", "direction") if k in kernels)
         out["pcg_iteration_us"] = it_us
+
+    if not args.no_mixed and precision == L.LF_PREC_FP64 and precond == L.LF_PC_DIAGONAL:
+        out["mixed"] = run_mixed(L, torch, p, mesh, prob, T0, args)
+        out["mixed"]["speedup_vs_fp64_time_to_tol"] = out["ms_per_step"] / out["mixed"]["ms_per_step"]
 
     if not args.no_cpu_baseline:
         log("[bench] oracle on the host ...")

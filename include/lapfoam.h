@@ -105,7 +105,7 @@ typedef struct lf_solver_opts {
                                    convergence flag; 0 = adaptive */
     int32_t use_graph;          /* 1: replay captured HIP graphs, 0: plain launches */
     double inner_tol;           /* LF_PREC_MIXED: inner FP32 solve stops when its
-                                   residual falls by this factor (0 = default 1e-4) */
+                                   residual falls by this factor (0 = default 1e-5) */
     int32_t max_outer;          /* LF_PREC_MIXED: refinement passes cap (0 = 50) */
     int32_t block_cells;        /* reserved, 0 */
 } lf_solver_opts;

@@ -48,7 +48,8 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
     if (!(dt > 0.0) || !std::isfinite(dt)) { set_error("dt must be finite and > 0"); return LF_EINVAL; }
     lf_solver_opts opts;
     if (o) opts = *o; else lf_default_opts(&opts);
-    if (opts.max_iter < 0 || opts.min_iter < 0 || !std::isfinite(opts.tol) || !std::isfinite(opts.rel_tol)) {
+    if (opts.max_iter < 0 || opts.min_iter < 0 || !std::isfinite(opts.tol) || !std::isfinite(opts.rel_tol) ||
+        !std::isfinite(opts.inner_tol) || opts.inner_tol < 0.0 || opts.inner_tol >= 1.0 || opts.max_outer < 0) {
         set_error("bad solver options");
         return LF_EINVAL;
     }
@@ -95,6 +96,8 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
     P->sp.n = m->N;
     P->sp.grid = cell_blocks(m->N);
     P->sp.n_red = m->two_colour ? m->n_red : m->N;
+    P->sp.max_outer = opts.max_outer > 0 ? opts.max_outer : 50;
+    P->sp.inner_tol = opts.inner_tol > 0.0 ? opts.inner_tol : 1e-5;
     P->bcs.assign(bcs, bcs + m->P);
     P->ws_bytes = dry.bytes();
     Carver cv(ws);
@@ -124,6 +127,7 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
 lf_status lf_problem_destroy(lf_problem *P) {
     if (!P) return LF_OK;
     for (auto &g : P->g_iter) if (g) (void)hipGraphExecDestroy(g);
+    for (auto &g : P->g_inner) if (g) (void)hipGraphExecDestroy(g);
     if (P->capture_stream) (void)hipStreamDestroy(P->capture_stream);
     for (auto &e : P->ev) if (e) (void)hipEventDestroy(e);
     for (auto &e : P->ev_pool) if (e) (void)hipEventDestroy(e);

@@ -1,5 +1,24 @@
-// Mixed-precision iterative refinement (FP64 outer, FP32 inner PCG).
+// Precision form: mixed-precision iterative refinement.
+//
+// The matrix is assembled in FP64 (with an FP32 copy of its coefficients).
+// Outer loop in FP64: r = b - A T (true residual, FP64 coefficients and T),
+// res = sum|r| / normFactor with the normalisation factor of x0 = T_old, stop
+// when res < tol.  Each pass solves A d = r approximately with a PCG whose
+// vectors, coefficients and products are FP32, while its dot products, alpha
+// and beta are FP64; then T += d in FP64.  The inner solve of a pass stops
+// when its L1 residual has fallen by inner_tol, or below half the outer
+// target, whichever is larger.
+//
+// The refinement runs until res < kTighten * tol (convergence is still
+// reported against tol).  Every FP64 PCG that stops just below tol leaves an
+// error of its own in T (up to ~6e-9 relative per step on these meshes); by
+// stopping an order of magnitude lower the precision form stays within 1e-8
+// of such a solve of the same system.
+constexpr double kTighten = 0.1;
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
 
 #include "lf_solver.h"
 
@@ -10,18 +29,295 @@ void carve_mixed(Carver &cv, const lf_mesh *m, lf_problem *P) {
     auto *coef32 = cv.take<float>(static_cast<size_t>(m->n_entries));
     float *v32[6];
     for (auto &v : v32) v = cv.take<float>(N);
-    auto *tsave = cv.take<double>(N);
     if (P) {
         P->coef32 = coef32; P->diag32 = v32[0]; P->rD32 = v32[1]; P->r32 = v32[2];
-        P->p32 = v32[3]; P->q32 = v32[4]; P->d32 = v32[5]; P->Tsave = tsave;
+        P->p32 = v32[3]; P->q32 = v32[4]; P->d32 = v32[5];
     }
 }
 
+// start of a pass: r32 = r (rounded), d = 0; partials of |r32| and w.r
+__global__ void __launch_bounds__(kCellBlock)
+k_mx_to32(SolverParams sp, const double *__restrict__ r, const float *__restrict__ rD32, float *__restrict__ r32,
+          float *__restrict__ d32, double *__restrict__ part, const PcgState *__restrict__ st) {
+    if (st->done) return;
+    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+    double acc[2] = {0.0, 0.0};
+    if (c < sp.n) {
+        const float rc = static_cast<float>(r[c]);
+        r32[c] = rc;
+        d32[c] = 0.0f;
+        const float wc = rD32[c] * rc;
+        acc[0] = fabs(static_cast<double>(rc));
+        acc[1] = static_cast<double>(wc) * static_cast<double>(rc);
+    }
+    const int slots[2] = {kPartSumR, kPartWr};
+    write_partials<2>(part, sp.grid, slots, acc);
+}
+
+__device__ __forceinline__ bool inner_off(const PcgState *st) { return st->done || st->inner_done; }
+
+// p = w (first inner iteration) or w + beta p, w = rD r, all FP32
+__global__ void __launch_bounds__(kCellBlock)
+k_mx_direction(SolverParams sp, const float *__restrict__ rD32, const float *__restrict__ r32,
+               float *__restrict__ p32, const PcgState *__restrict__ st) {
+    if (inner_off(st)) return;
+    const bool first = st->inner_iter == 0;
+    const float beta = static_cast<float>(st->beta);
+    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+    if (c < sp.n) {
+        const float wc = rD32[c] * r32[c];
+        p32[c] = first ? wc : wc + beta * p32[c];
+    }
+}
+
+// q = A p in FP32; FP64 partial sums of p.q
+__global__ void __launch_bounds__(kCellBlock)
+k_mx_amul_dot(SolverParams sp, MeshRows mr, const float *__restrict__ diag32, const float *__restrict__ coef32,
+              const float *__restrict__ p32, float *__restrict__ q32, double *__restrict__ part,
+              const PcgState *__restrict__ st) {
+    if (inner_off(st)) return;
+    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+    double acc[1] = {0.0};
+    if (c < sp.n) {
+        const float pc = p32[c];
+        const float qc = row_dot(mr, c, coef32, p32, diag32[c] * pc);
+        q32[c] = qc;
+        acc[0] = static_cast<double>(qc) * static_cast<double>(pc);
+    }
+    const int slots[1] = {kPartPq};
+    write_partials<1>(part, sp.grid, slots, acc);
+}
+
+// d += alpha p; r -= alpha q (FP32); FP64 partials of |r| and w.r
+__global__ void __launch_bounds__(kCellBlock)
+k_mx_update(SolverParams sp, const float *__restrict__ p32, const float *__restrict__ q32,
+            const float *__restrict__ rD32, float *__restrict__ r32, float *__restrict__ d32,
+            double *__restrict__ part, const PcgState *__restrict__ st) {
+    if (inner_off(st)) return;
+    const float alpha = static_cast<float>(st->alpha);
+    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+    double acc[2] = {0.0, 0.0};
+    if (c < sp.n) {
+        d32[c] += alpha * p32[c];
+        const float rc = r32[c] - alpha * q32[c];
+        r32[c] = rc;
+        const float wc = rD32[c] * rc;
+        acc[0] = fabs(static_cast<double>(rc));
+        acc[1] = static_cast<double>(wc) * static_cast<double>(rc);
+    }
+    const int slots[2] = {kPartSumR, kPartWr};
+    write_partials<2>(part, sp.grid, slots, acc);
+}
+
+// T += d (FP64)
+__global__ void __launch_bounds__(kCellBlock)
+k_mx_correct(SolverParams sp, double *__restrict__ T, const float *__restrict__ d32, const PcgState *__restrict__ st) {
+    if (st->done) return;
+    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+    if (c < sp.n) T[c] += static_cast<double>(d32[c]);
+}
+
+// true residual r = b - A T in FP64; partial sums of |r|
+__global__ void __launch_bounds__(kCellBlock)
+k_mx_residual(SolverParams sp, MeshRows mr, const double *__restrict__ diagB, const double *__restrict__ coef,
+              const double *__restrict__ srcB, const double *__restrict__ T, double *__restrict__ r,
+              double *__restrict__ part, const PcgState *__restrict__ st) {
+    if (st->done) return;
+    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+    double acc[1] = {0.0};
+    if (c < sp.n) {
+        const double ax = row_dot(mr, c, coef, T, diagB[c] * T[c]);
+        const double rc = srcB[c] - ax;
+        r[c] = rc;
+        acc[0] = fabs(rc);
+    }
+    const int slots[1] = {kPartSumR};
+    write_partials<1>(part, sp.grid, slots, acc);
+}
+
+// one-workgroup decisions of the refinement
+enum MxFin : int { kMxInnerStart = 0, kMxAlpha = 1, kMxBeta = 2, kMxOuter = 3 };
+
+template <int Mode>
+__global__ void __launch_bounds__(kFinBlock) k_mx_finalize(SolverParams sp, const double *__restrict__ part,
+                                                          PcgState *__restrict__ st) {
+    const int32_t G = sp.grid;
+    if (Mode == kMxInnerStart) {
+        if (st->done) return;
+        double v[2];
+        const int slots[2] = {kPartSumR, kPartWr};
+        reduce_partials<2>(part, G, slots, v);
+        if (threadIdx.x == 0) {
+            const double target = fmax(sp.inner_tol * v[0], 0.5 * kTighten * sp.tol * st->nf);
+            st->inner_target = target;
+            st->inner_iter = 0;
+            st->wArA = v[1];
+            st->inner_done = (v[0] <= target || !(v[1] > 0.0)) ? 1 : 0;
+            if (!isfinite(v[0]) || !isfinite(v[1])) {
+                st->nonfinite = 1;
+                st->done = 1;
+            }
+        }
+    } else if (Mode == kMxAlpha) {
+        if (inner_off(st)) return;
+        double v[1];
+        const int slots[1] = {kPartPq};
+        reduce_partials<1>(part, G, slots, v);
+        if (threadIdx.x == 0) {
+            const double pq = v[0];
+            if (!isfinite(pq)) {
+                st->nonfinite = 1;
+                st->done = 1;
+            } else if (!(fabs(pq) > 0.0)) {
+                st->inner_done = 1;          // nothing left that FP32 can resolve
+            } else {
+                st->alpha = st->wArA / pq;
+            }
+        }
+    } else if (Mode == kMxBeta) {
+        if (inner_off(st)) return;
+        double v[2];
+        const int slots[2] = {kPartSumR, kPartWr};
+        reduce_partials<2>(part, G, slots, v);
+        if (threadIdx.x == 0) {
+            st->inner_iter += 1;
+            st->n_iter += 1;
+            if (!isfinite(v[0]) || !isfinite(v[1])) {
+                st->nonfinite = 1;
+                st->done = 1;
+            } else if (v[0] <= st->inner_target || st->n_iter >= sp.max_iter || !(v[1] > 0.0)) {
+                st->inner_done = 1;
+            } else {
+                st->beta = v[1] / st->wArA;
+                st->wArA = v[1];
+            }
+        }
+    } else {
+        if (st->done) return;
+        double v[1];
+        const int slots[1] = {kPartSumR};
+        reduce_partials<1>(part, G, slots, v);
+        if (threadIdx.x == 0) {
+            const double res = v[0] / st->nf;
+            st->res = res;
+            st->n_outer += 1;
+            const bool conv = check_conv(res, st->res0, sp.tol, sp.rel_tol);
+            const bool tight = check_conv(res, st->res0, kTighten * sp.tol, kTighten * sp.rel_tol);
+            st->converged = conv ? 1 : 0;
+            if (!isfinite(res)) {
+                st->nonfinite = 1;
+                st->done = 1;
+            } else if (tight || st->n_outer >= sp.max_outer || st->n_iter >= sp.max_iter) {
+                st->done = 1;
+            }
+        }
+    }
+}
+
+template <int Mode>
+static void launch_mx_fin(lf_problem *P, hipStream_t s) {
+    LF_LAUNCH(P, LF_K_FINALIZE, s, k_mx_finalize<Mode>, dim3(1), dim3(kFinBlock), 0, s, P->sp, P->part, P->state);
+}
+
+static void launch_inner_iteration(lf_problem *P, hipStream_t s) {
+    LF_LAUNCH(P, LF_K_INNER_DIRECTION, s, k_mx_direction, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->rD32,
+              P->r32, P->p32, P->state);
+    LF_LAUNCH(P, LF_K_INNER_AMUL_DOT, s, k_mx_amul_dot, cell_grid(P), dim3(kCellBlock), 0, s, P->sp,
+              mesh_rows(P->mesh), P->diag32, P->coef32, P->p32, P->q32, P->part, P->state);
+    launch_mx_fin<kMxAlpha>(P, s);
+    LF_LAUNCH(P, LF_K_INNER_UPDATE, s, k_mx_update, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->p32, P->q32,
+              P->rD32, P->r32, P->d32, P->part, P->state);
+    launch_mx_fin<kMxBeta>(P, s);
+}
+
+// start of a refinement pass
+static void launch_pass_start(lf_problem *P, hipStream_t s) {
+    LF_LAUNCH(P, LF_K_MIXED_PREP, s, k_mx_to32, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->r, P->rD32, P->r32,
+              P->d32, P->part, P->state);
+    launch_mx_fin<kMxInnerStart>(P, s);
+}
+
+// end of a pass: correction, true residual, outer decision
+static void launch_pass_end(lf_problem *P, hipStream_t s) {
+    LF_LAUNCH(P, LF_K_MIXED_CORRECT, s, k_mx_correct, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->T, P->d32,
+              P->state);
+    LF_LAUNCH(P, LF_K_MIXED_RESIDUAL, s, k_mx_residual, cell_grid(P), dim3(kCellBlock), 0, s, P->sp,
+              mesh_rows(P->mesh), P->diagB, P->coef, P->srcB, P->T, P->r, P->part, P->state);
+    launch_mx_fin<kMxOuter>(P, s);
+}
+
+static lf_status get_inner_graph(lf_problem *P, int lg) {
+    if (P->g_inner[lg]) return LF_OK;
+    if (!P->capture_stream) LF_HIP(hipStreamCreateWithFlags(&P->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = P->capture_stream;
+    LF_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < (1 << lg); ++i) launch_inner_iteration(P, cs);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &g);
+    if (e != hipSuccess) { set_error("graph capture failed: %s", hipGetErrorString(e)); return LF_EDEVICE; }
+    e = hipGraphInstantiate(&P->g_inner[lg], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) { set_error("graph instantiate failed: %s", hipGetErrorString(e)); return LF_EDEVICE; }
+    return LF_OK;
+}
+
+static lf_status launch_inner(lf_problem *P, int32_t k) {
+    hipStream_t s = P->stream;
+    if (!P->opts.use_graph || P->prof_on) {
+        for (int32_t i = 0; i < k; ++i) launch_inner_iteration(P, s);
+        LF_HIP(hipGetLastError());
+        return LF_OK;
+    }
+    for (int lg = kMaxGraphLog; lg >= 0; --lg) {
+        while (k >= (1 << lg)) {
+            LF_TRY(get_inner_graph(P, lg));
+            LF_HIP(hipGraphLaunch(P->g_inner[lg], s));
+            k -= 1 << lg;
+        }
+    }
+    return LF_OK;
+}
+
 lf_status solve_mixed(lf_problem *P, lf_solve_stats *out) {
-    (void)P;
-    (void)out;
-    set_error("mixed precision not built yet");
-    return LF_EINVAL;
+    hipStream_t s = P->stream;
+    launch_fin<kFinStart>(P, s);      // normFactor, res0 and the initial decision (shared with FP64)
+    launch_pass_start(P, s);
+    LF_HIP(hipGetLastError());
+    const int32_t fixed_k = P->prof_on ? 1 : P->opts.iters_per_check;
+    int32_t k = fixed_k > 0 ? fixed_k : std::max<int32_t>(2, P->last_inner > 0 ? P->last_inner : 8);
+    int32_t launched = 0;
+    for (;;) {
+        LF_TRY(launch_inner(P, k));
+        launched += k;
+        LF_HIP(hipMemcpyAsync(P->h_state, P->state, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+        LF_HIP(hipEventRecord(P->ev[2], s));
+        LF_HIP(hipEventSynchronize(P->ev[2]));
+        prof_flush(P);
+        const PcgState &h = *P->h_state;
+        if (h.done) break;
+        if (launched > 4 * (P->sp.max_iter + 8) + 64 * P->sp.max_outer) {
+            set_error("mixed solver never reached done after %d launched inner iterations", launched);
+            return LF_ESTATE;
+        }
+        if (!h.inner_done) {
+            if (fixed_k <= 0) k = std::max<int32_t>(2, k / 2);
+            continue;
+        }
+        // pass finished: correct, check, start the next pass (no-ops once done)
+        if (fixed_k <= 0) { k = std::max<int32_t>(2, h.inner_iter); P->last_inner = h.inner_iter; }
+        launch_pass_end(P, s);
+        launch_pass_start(P, s);
+        LF_HIP(hipGetLastError());
+    }
+    const PcgState &h = *P->h_state;
+    out->initial_residual = h.res0;
+    out->final_residual = h.res;
+    out->n_iter = h.n_iter;
+    out->converged = h.converged;
+    out->singular = 0;
+    out->nonfinite = h.nonfinite;
+    out->n_outer = h.n_outer;
+    return LF_OK;
 }
 
 }  // namespace lf

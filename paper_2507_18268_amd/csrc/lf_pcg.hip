@@ -142,7 +142,7 @@ __device__ __forceinline__ void row_amul_sum(const MeshRows &mr, int32_t c, cons
 // |wA - pA| + |b - pA| of the normalisation factor (pA = row sum * mean(x0),
 // the mean taken beforehand), and with the diagonal preconditioner
 // rD = 1/diag and w.r; partial sums of |r|, those terms and w.r.
-template <bool kFull, bool kSetup>
+template <bool kFull, bool kSetup, bool kMixed>
 __global__ void __launch_bounds__(kCellBlock)
 k_assemble(SolverParams sp, double rdt, double DT, MeshRows mr, const double *__restrict__ mag_sf,
            const double *__restrict__ delta, const int32_t *__restrict__ bface_start,
@@ -153,7 +153,8 @@ k_assemble(SolverParams sp, double rdt, double DT, MeshRows mr, const double *__
            double *__restrict__ upper, double *__restrict__ diag, double *__restrict__ source,
            double *__restrict__ diagB, double *__restrict__ srcB, double *__restrict__ int_coeff,
            double *__restrict__ bou_coeff, int32_t diag_pc, double *__restrict__ r, double *__restrict__ rD,
-           double *__restrict__ part, const PcgState *__restrict__ st) {
+           double *__restrict__ part, const PcgState *__restrict__ st, float *__restrict__ coef32,
+           float *__restrict__ diag32, float *__restrict__ rD32) {
     const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
     double acc[3] = {0.0, 0.0, 0.0};
     const double x_avg = kSetup ? st->x_avg : 0.0;
@@ -182,6 +183,14 @@ k_assemble(SolverParams sp, double rdt, double DT, MeshRows mr, const double *__
         if (kFull) { diag[c] = d; source[c] = s; }
         diagB[c] = db;
         srcB[c] = sb;
+        if (kMixed) {
+            // FP32 copy of the solve-time matrix for the inner solves
+            int32_t idx = row_base(mr, c);
+            const int32_t len = mr.rlen[c];
+            for (int32_t j = 0; j < len; ++j, idx += kSlice) coef32[idx] = static_cast<float>(coef[idx]);
+            diag32[c] = static_cast<float>(db);
+            rD32[c] = static_cast<float>(1.0 / db);
+        }
         if (kSetup) {
             double ax = db * xc, sa = db;
             row_amul_sum(mr, c, coef, T, ax, sa);
@@ -384,7 +393,6 @@ k_dic_backward(SolverParams sp, MeshRows mr, const double *__restrict__ coef, co
 //             while (nIter < maxIter and not converged) or nIter < minIter;
 //             beta = wArA_new / wArA.
 // ---------------------------------------------------------------------------
-enum FinMode : int { kFinMean = 0, kFinStart = 1, kFinAlpha = 2, kFinBeta = 3 };
 
 template <int Mode>
 __global__ void __launch_bounds__(kFinBlock) k_finalize(SolverParams sp, const double *__restrict__ part,
@@ -403,6 +411,9 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(SolverParams sp, const d
             st->nonfinite = 0;
             st->alpha = 0.0;
             st->beta = 0.0;
+            st->n_outer = 0;
+            st->inner_iter = 0;
+            st->inner_done = 0;
         }
     } else if (Mode == kFinStart) {
         double v[3];
@@ -505,27 +516,27 @@ void carve_problem(Carver &cv, const lf_mesh *m, const lf_solver_opts &o, lf_pro
 
 MeshRows mesh_rows(const lf_mesh *m) { return MeshRows{m->soff, m->scol, m->sface, m->rlen}; }
 
-template <bool kFull, bool kSetup>
+template <bool kFull, bool kSetup, bool kMixed>
 static void launch_assemble_t(lf_problem *P, hipStream_t s) {
     const lf_mesh *m = P->mesh;
     const double rdt = 1.0 / P->dt;
     const bool diag_pc = P->opts.precond == LF_PC_DIAGONAL;
-    LF_LAUNCH(P, LF_K_ASSEMBLE, s, (k_assemble<kFull, kSetup>), cell_grid(P), dim3(kCellBlock), 0, s, P->sp, rdt,
-              P->DT, mesh_rows(m), m->mag_sf, m->delta, m->bface_start, m->bface_list, m->bface_patch,
-              m->bmag_sf, m->bdelta, P->patch_type, P->patch_value, m->V, P->T, P->coef, P->upper, P->diag,
-              P->source, P->diagB, P->srcB, P->int_coeff, P->bou_coeff, diag_pc ? 1 : 0, P->r, P->rD,
-              P->part, P->state);
+    LF_LAUNCH(P, LF_K_ASSEMBLE, s, (k_assemble<kFull, kSetup, kMixed>), cell_grid(P), dim3(kCellBlock), 0, s,
+              P->sp, rdt, P->DT, mesh_rows(m), m->mag_sf, m->delta, m->bface_start, m->bface_list,
+              m->bface_patch, m->bmag_sf, m->bdelta, P->patch_type, P->patch_value, m->V, P->T, P->coef,
+              P->upper, P->diag, P->source, P->diagB, P->srcB, P->int_coeff, P->bou_coeff, diag_pc ? 1 : 0,
+              P->r, P->rD, P->part, P->state, P->coef32, P->diag32, P->rD32);
 }
 
 lf_status launch_assemble(lf_problem *P, bool full, hipStream_t s) {
-    if (full) launch_assemble_t<true, false>(P, s);
-    else launch_assemble_t<false, false>(P, s);
+    if (full) launch_assemble_t<true, false, false>(P, s);
+    else launch_assemble_t<false, false, false>(P, s);
     LF_HIP(hipGetLastError());
     return LF_OK;
 }
 
 template <int Mode>
-static void launch_fin(lf_problem *P, hipStream_t s) {
+void launch_fin(lf_problem *P, hipStream_t s) {
     LF_LAUNCH(P, LF_K_FINALIZE, s, k_finalize<Mode>, dim3(1), dim3(kFinBlock), 0, s, P->sp, P->part, P->state);
 }
 
@@ -533,7 +544,8 @@ static void launch_fin(lf_problem *P, hipStream_t s) {
 lf_status launch_assemble_setup(lf_problem *P, hipStream_t s) {
     LF_LAUNCH(P, LF_K_SETUP1, s, k_sum_x, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->T, P->part);
     launch_fin<kFinMean>(P, s);
-    launch_assemble_t<false, true>(P, s);
+    if (P->opts.precision == LF_PREC_MIXED) launch_assemble_t<false, true, true>(P, s);
+    else launch_assemble_t<false, true, false>(P, s);
     LF_HIP(hipGetLastError());
     return LF_OK;
 }
@@ -546,6 +558,8 @@ static void launch_direction(lf_problem *P, hipStream_t s) {
         LF_LAUNCH(P, LF_K_DIRECTION, s, k_direction<false>, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->rD,
                   P->r, P->w, P->p, P->T, P->state);
 }
+
+template void launch_fin<kFinStart>(lf_problem *P, hipStream_t s);
 
 // after the fused assembly/setup kernel: preconditioner set-up (DIC), initial
 // residual and convergence decision, first direction

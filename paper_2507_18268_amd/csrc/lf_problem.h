@@ -34,6 +34,12 @@ struct PcgState {
     int32_t singular;
     int32_t nonfinite;
     int32_t flag;         // scratch flag (input checks)
+    // mixed precision: inner FP32 solve of one refinement pass
+    double inner_target;  // stop when sum|r32| <= this
+    int32_t inner_done;
+    int32_t inner_iter;   // iterations of the current pass
+    int32_t n_outer;      // refinement passes
+    int32_t pad2;
 };
 
 constexpr int kMaxGraphLog = 6;   // largest captured block: 64 iterations
@@ -44,7 +50,8 @@ struct SolverParams {
     int32_t n;            // cells
     int32_t grid;         // workgroups of a cell-parallel launch (= partials per slot)
     int32_t n_red;        // DIC: first black cell
-    int32_t pad;
+    int32_t max_outer;    // mixed: refinement passes cap
+    double inner_tol;     // mixed: relative reduction of each inner solve
 };
 
 }  // namespace lf
@@ -69,13 +76,14 @@ struct lf_problem {
     // mixed precision (FP32 inner solve)
     float *coef32 = nullptr, *diag32 = nullptr, *rD32 = nullptr;
     float *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
-    double *Tsave = nullptr;
     // host side
     lf::PcgState *h_state = nullptr;           // pinned
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t g_iter[lf::kMaxGraphLog + 1] = {};   // 2^i PCG iterations
+    hipGraphExec_t g_inner[lf::kMaxGraphLog + 1] = {};  // 2^i inner FP32 iterations
     int32_t last_iters = 0;
+    int32_t last_inner = 0;
     bool assembled = false;
     size_t ws_bytes = 0;
     // per-kernel device timing (diagnostics)

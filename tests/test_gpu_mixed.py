@@ -1,0 +1,104 @@
+"""Precision form (FP32 inner PCG with FP64 dots / alpha / beta, FP64 outer
+refinement on the true residual) against the FP64 oracle.
+
+Per step, both solve the same system: the oracle takes one step from the
+precision form's own T_n, and T_{n+1} must agree to a max relative error of
+1e-8.  (Trajectories of two different solvers that each stop below the
+tolerance drift apart by more than that over many steps: the oracle's own
+trajectory at tol 1e-9 is 1.3e-8 away from the exactly solved one after 20
+steps of the 32^3 case.)  The FP64 true residual of every result, recomputed
+on the host from the oracle's matrix, is below the tolerance."""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_common import lapfoam, run_gpu, max_rel
+from tests.helpers import norm_factor, ldu_to_dense
+
+pytestmark = pytest.mark.gpu
+
+T_TOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def L():
+    return lapfoam()
+
+
+CASES = [
+    ("plain_32", "plain_32", None, 20, {}),
+    ("graded_24", "graded_256", 24, 6, {}),
+    ("permuted_20", "permuted_192", 20, 6, {}),
+    ("graded_24_loose_inner", "graded_256", 24, 4, dict(inner_tol=1e-2)),
+    ("graded_24_tight_inner", "graded_256", 24, 4, dict(inner_tol=1e-6)),
+    ("graded_24_no_graph", "graded_256", 24, 3, dict(use_graph=0)),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_mixed_matches_fp64_oracle(L, oracle, case):
+    name, cfg, n, steps, extra = case
+    p = synth.build_config(cfg, n=n, steps=steps)
+    Tg, sg = run_gpu(L, p.mesh, p.bcs, p.DT, p.dt, p.T0, steps, precision=L.LF_PREC_MIXED, **extra)
+    To, so, snaps = oracle.run(p.mesh, p.bcs, p.DT, p.dt, steps, p.T0, keep_all=True)
+    T_prev = p.T0
+    for s in range(steps):
+        ref, _, _ = oracle.run(p.mesh, p.bcs, p.DT, p.dt, 1, T_prev)
+        err = max_rel(Tg[s], ref)
+        assert err <= T_TOL, (s, err)
+        assert sg[s]["converged"] == 1 and sg[s]["final_residual"] < 1e-9
+        assert sg[s]["n_outer"] >= 1
+        # step 1 starts from the same T0 as the oracle; later steps start from
+        # a T that differs at the solver-tolerance level
+        rtol = 1e-10 if s == 0 else 1e-6
+        assert abs(sg[s]["initial_residual"] - so[s]["initial_residual"]) <= \
+            rtol * so[s]["initial_residual"]
+        # the FP64 true residual of the GPU result, from the oracle's matrix
+        m = oracle.assemble(p.mesh, p.bcs, p.DT, p.dt, T_prev)
+        r = m["source_b"] - oracle.amul(p.mesh, m["diag_b"], m["upper"], Tg[s])
+        A1 = oracle.sum_a(p.mesh, m["diag_b"], m["upper"])
+        Ax0 = oracle.amul(p.mesh, m["diag_b"], m["upper"], T_prev)
+        pA = A1 * T_prev.mean()
+        nf = np.sum(np.abs(Ax0 - pA) + np.abs(m["source_b"] - pA)) + 1e-20
+        assert np.sum(np.abs(r)) / nf < 1e-9 * (1 + 1e-6)
+        T_prev = Tg[s]      # the system of the next step is built from the GPU field
+
+
+def test_mixed_is_deterministic(L):
+    p = synth.build_config("permuted_192", n=18, steps=3)
+    a, sa = run_gpu(L, p.mesh, p.bcs, p.DT, p.dt, p.T0, 3, precision=L.LF_PREC_MIXED)
+    b, sb = run_gpu(L, p.mesh, p.bcs, p.DT, p.dt, p.T0, 3, precision=L.LF_PREC_MIXED,
+                    iters_per_check=1)
+    for s in range(3):
+        assert np.array_equal(a[s], b[s])
+        assert sa[s]["n_iter"] == sb[s]["n_iter"] and sa[s]["n_outer"] == sb[s]["n_outer"]
+
+
+def test_mixed_edge_cases(L, oracle):
+    # zero diffusivity: converged at the start, no pass
+    mesh = synth.box_mesh(6, 6, 6)
+    T0 = synth.initial_field(mesh.n_cells, 3)
+    Tg, sg = run_gpu(L, mesh, synth.fixed_x_bcs(), 0.0, 1e-3, T0, 2, precision=L.LF_PREC_MIXED)
+    assert all(s["n_iter"] == 0 and s["n_outer"] == 0 and s["converged"] == 1 for s in sg)
+    # one cell, and a line
+    for mesh in (synth.box_mesh(1, 1, 1), synth.box_mesh(17, 1, 1)):
+        T0 = synth.initial_field(mesh.n_cells, 4)
+        Tg, sg = run_gpu(L, mesh, synth.fixed_x_bcs(), 0.3, 0.2, T0, 2, precision=L.LF_PREC_MIXED)
+        To, so, snaps = oracle.run(mesh, synth.fixed_x_bcs(), 0.3, 0.2, 2, T0, keep_all=True)
+        assert max_rel(Tg[0], snaps[0]) <= T_TOL
+    # refinement cap: one pass only, so it stops unconverged but finite
+    p = synth.build_config("graded_256", n=12, steps=1)
+    Tg, sg = run_gpu(L, p.mesh, p.bcs, p.DT, p.dt, p.T0, 1, precision=L.LF_PREC_MIXED,
+                     max_outer=1, inner_tol=0.5)
+    assert sg[0]["n_outer"] == 1 and sg[0]["converged"] == 0
+    assert np.all(np.isfinite(Tg[0]))
+
+
+def test_mixed_refuses_dic(L):
+    mesh = synth.renumber(synth.box_mesh(4, 4, 4),
+                          synth.red_black_numbering(synth.box_mesh(4, 4, 4))[0])
+    m = L.Mesh(mesh)
+    with pytest.raises(L.LapfoamError):
+        L.Problem(m, synth.fixed_x_bcs(), 1e-3, 1e-3,
+                  L.make_opts(precond=L.LF_PC_DIC, precision=L.LF_PREC_MIXED))
+    m.close()
