@@ -191,6 +191,39 @@ lf_status lf_get_matrix(lf_problem *problem, double *diag, double *upper, double
  * pointers of N doubles, ordered on the handle's stream. */
 lf_status lf_amul(lf_problem *problem, const double *x, double *y);
 
+/* ---- batched form -------------------------------------------------------
+ * Many independent problems (each its own mesh, boundary conditions, DT, dt
+ * and T; created with LF_PREC_MIXED and the diagonal preconditioner) advanced
+ * by one persistent kernel: each workgroup takes the next problem of the task
+ * table, in the order given, and runs all n_steps steps of it alone (assembly,
+ * then the precision form's refinement with workgroup-level reductions).  A
+ * problem's result does not depend on the other problems of the launch or on
+ * n_workgroups; it depends on block_threads (the summation order inside the
+ * workgroup).  Each step stops when the FP64 normalised residual is below a
+ * tenth of tol (converged is reported against tol), like LF_PREC_MIXED.
+ * The batch workspace holds the task table, a counter and the statistics. */
+typedef struct lf_batch lf_batch;
+size_t lf_batch_workspace_bytes(int32_t max_tasks, int32_t max_steps);
+lf_status lf_batch_create(int32_t max_tasks, int32_t max_steps, void *dev_workspace,
+                          size_t workspace_bytes, void *stream, lf_batch **out);
+lf_status lf_batch_destroy(lf_batch *batch);     /* NULL-safe; waits for a launch in flight */
+/* Enqueue on the batch's stream and return at once.  problems[n], n <= max_tasks,
+ * n_steps <= max_steps, block_threads in {256, 512, 1024}, n_workgroups <= 0
+ * means one per problem.  snapshots (may be NULL; entries may be NULL): for
+ * problem i a device buffer of n_steps * N_i doubles that receives T after
+ * each step, step-major.  The problems' T must be set (and any work on their
+ * own streams finished) before the call; they must not be used until the
+ * launch has finished (lf_batch_poll / lf_batch_wait).  LF_ESTATE if the
+ * previous launch has not finished. */
+lf_status lf_batch_launch(lf_batch *batch, int32_t n, lf_problem *const *problems,
+                          double *const *snapshots, int32_t n_steps, int32_t block_threads,
+                          int32_t n_workgroups);
+lf_status lf_batch_poll(lf_batch *batch, int32_t *finished);   /* *finished = 1 when done */
+lf_status lf_batch_wait(lf_batch *batch);
+/* After the launch finished: stats[n * n_steps] (problem-major) and the device
+ * time of the launch in milliseconds (either may be NULL). */
+lf_status lf_batch_stats(lf_batch *batch, lf_solve_stats *stats, double *elapsed_ms);
+
 /* ---- per-kernel device timing (diagnostics) ------------------------------
  * When enabled, lf_step records a HIP event pair around every kernel launch on
  * the handle's stream (plain launches instead of graphs, and a convergence

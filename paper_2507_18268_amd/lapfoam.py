@@ -89,6 +89,15 @@ _SIGS = {
     "lf_assemble": (C.c_int32, [C.c_void_p]),
     "lf_get_matrix": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 7),
     "lf_amul": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lf_batch_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
+    "lf_batch_create": (C.c_int32, [C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                                    C.POINTER(C.c_void_p)]),
+    "lf_batch_destroy": (C.c_int32, [C.c_void_p]),
+    "lf_batch_launch": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                    C.c_int32, C.c_int32]),
+    "lf_batch_poll": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "lf_batch_wait": (C.c_int32, [C.c_void_p]),
+    "lf_batch_stats": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "lf_profile_enable": (C.c_int32, [C.c_void_p, C.c_int32]),
     "lf_profile_read": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
 }
@@ -212,6 +221,50 @@ def lf_profile_read(h, n=16):
     _check(lib().lf_profile_read(h, C.c_int32(n), C.c_void_p(ms.ctypes.data),
                                  C.c_void_p(cnt.ctypes.data)), "lf_profile_read")
     return ms, cnt
+
+
+def lf_batch_workspace_bytes(max_tasks, max_steps):
+    return int(lib().lf_batch_workspace_bytes(C.c_int32(max_tasks), C.c_int32(max_steps)))
+
+
+def lf_batch_create(max_tasks, max_steps, ws_ptr, ws_bytes, stream):
+    h = C.c_void_p()
+    _check(lib().lf_batch_create(C.c_int32(max_tasks), C.c_int32(max_steps), C.c_void_p(ws_ptr),
+                                 C.c_size_t(ws_bytes), C.c_void_p(stream), C.byref(h)),
+           "lf_batch_create")
+    return h
+
+
+def lf_batch_destroy(h):
+    _check(lib().lf_batch_destroy(h), "lf_batch_destroy")
+
+
+def lf_batch_launch(h, problem_handles, snapshot_ptrs, n_steps, block_threads, n_workgroups=0):
+    n = len(problem_handles)
+    arr = (C.c_void_p * n)(*[ph.value for ph in problem_handles])
+    snaps = None
+    if snapshot_ptrs is not None:
+        snaps = (C.c_void_p * n)(*[int(p) if p else None for p in snapshot_ptrs])
+    _check(lib().lf_batch_launch(h, C.c_int32(n), arr, snaps, C.c_int32(n_steps),
+                                 C.c_int32(block_threads), C.c_int32(n_workgroups)),
+           "lf_batch_launch")
+
+
+def lf_batch_poll(h):
+    f = C.c_int32(0)
+    _check(lib().lf_batch_poll(h, C.byref(f)), "lf_batch_poll")
+    return bool(f.value)
+
+
+def lf_batch_wait(h):
+    _check(lib().lf_batch_wait(h), "lf_batch_wait")
+
+
+def lf_batch_stats(h, n, n_steps):
+    st = (lf_solve_stats * max(n * n_steps, 1))()
+    ms = C.c_double(0.0)
+    _check(lib().lf_batch_stats(h, st, C.byref(ms)), "lf_batch_stats")
+    return [[st[i * n_steps + k].as_dict() for k in range(n_steps)] for i in range(n)], ms.value
 
 
 # --------------------------------------------------------------------------
@@ -369,6 +422,46 @@ class Problem:
     def close(self):
         if getattr(self, "h", None):
             lf_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Persistent batched solver launches (one workgroup per problem at a time)."""
+
+    def __init__(self, max_tasks, max_steps, stream=None):
+        torch = _torch()
+        self.max_tasks, self.max_steps = max_tasks, max_steps
+        self.ws_bytes = lf_batch_workspace_bytes(max_tasks, max_steps)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device="cuda")
+        self.stream_obj = stream
+        self.stream = _stream_ptr(stream)
+        self.h = lf_batch_create(max_tasks, max_steps, self.ws.data_ptr(), self.ws_bytes, self.stream)
+        self._n = 0
+        self._steps = 0
+
+    def launch(self, problems, n_steps, block_threads=512, n_workgroups=0, snapshots=None):
+        ptrs = None if snapshots is None else [s.data_ptr() if s is not None else 0 for s in snapshots]
+        lf_batch_launch(self.h, [p.h for p in problems], ptrs, n_steps, block_threads, n_workgroups)
+        self._n, self._steps = len(problems), n_steps
+
+    def poll(self):
+        return lf_batch_poll(self.h)
+
+    def wait(self):
+        lf_batch_wait(self.h)
+
+    def stats(self):
+        return lf_batch_stats(self.h, self._n, self._steps)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lf_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):
