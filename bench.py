@@ -149,6 +149,67 @@ def run_mixed(L, torch, p, mesh, prob64, T0, args):
             "speedup_vs_fp64_time_to_tol": None}
 
 
+def run_serving(L, torch, args):
+    """512 parametric requests (side log-uniform in [16, 96], DT log-uniform in
+    [1e-4, 1e-2], dt = 1e-3, 10 steps, snapshots of every step returned):
+    first all arriving at once (saturated throughput), then Poisson arrivals
+    at fractions of that rate.  Meshes are resident before the clock starts."""
+    import synth
+    from paper_2507_18268_amd import serve as S
+    from paper_2507_18268_amd import autotune
+    base = synth.request_stream(args.serve_requests, rate=1.0)
+    host_meshes = {}
+
+    def mesh_for_side(n):
+        if n not in host_meshes:
+            host_meshes[n] = synth.box_mesh(n, n, n)
+        return host_meshes[n]
+
+    def requests(rate):
+        rs = synth.request_stream(args.serve_requests, rate=rate) if rate else base
+        return [S.Request(rid=r.rid, n=r.n, DT=r.DT, dt=r.dt, steps=r.steps,
+                          T0=synth.initial_field(r.n ** 3, r.seed), bcs=synth.fixed_x_bcs(),
+                          arrival=(r.arrival if rate else 0.0)) for r in rs]
+
+    tuning = autotune.load()
+    out = {"workload": f"{args.serve_requests} requests, side log-uniform [16,96], DT log-uniform "
+                       f"[1e-4,1e-2], dt 1e-3, 10 steps, snapshots returned, mixed FP32/FP64 "
+                       f"batched kernel", "tuning": tuning["block_threads"] if tuning else None,
+           "budget_GiB": args.serve_budget_gib, "slots": args.serve_slots}
+    sides = sorted({r.n for r in base})
+    cells = sum(r.n ** 3 for r in base)
+
+    def one(rate, label):
+        srv = S.Server(mesh_for_side, int(args.serve_budget_gib * 2 ** 30), n_slots=args.serve_slots,
+                       slot_capacity=args.serve_capacity, max_steps=10, tuning=tuning)
+        for n in sides:
+            srv.preload_mesh(n)
+        torch.cuda.synchronize()
+        reqs = requests(rate)
+        done = srv.run(reqs, poll_s=0.0)
+        summ = S.summarize(done)
+        summ["rejected"] = len(srv.rejected)
+        summ["all_converged"] = all(all(s["converged"] == 1 for s in r.stats) for r in done)
+        srv.close()
+        log(f"[bench] serving {label}: {summ.get('solves_per_s', 0):.1f} solves/s, "
+            f"p50 {summ.get('p50_latency_s', 0) * 1e3:.1f} ms, p99 {summ.get('p99_latency_s', 0) * 1e3:.1f} ms")
+        return summ
+
+    one(None, "warm-up")
+    sat = one(None, "saturated")
+    sat["cell_steps_per_s"] = cells * 10 * sat["solves_per_s"] / len(base)
+    out["saturated"] = sat
+    rate_sat = sat["solves_per_s"]
+    fracs = [0.25, 0.5, 1.0, 2.0, 4.0] if args.serve_sweep else [0.5]
+    out["poisson"] = []
+    for f in fracs:
+        summ = one(f * rate_sat, f"poisson {f}x")
+        summ["offered_rate"] = f * rate_sat
+        summ["fraction_of_saturated"] = f
+        out["poisson"].append(summ)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,6 +223,13 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--accuracy-steps", type=int, default=20)
     ap.add_argument("--inner-tol", type=float, default=0.0, help="mixed: inner reduction (0 = default)")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-only", action="store_true")
+    ap.add_argument("--serve-sweep", action="store_true", help="Poisson rates 0.25x..4x of saturated")
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-capacity", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()
@@ -190,6 +258,10 @@ def main():
 
     import synth
     from paper_2507_18268_amd import lapfoam as L
+
+    if args.serve_only:
+        print(json.dumps({"serving": run_serving(L, torch, args)}), flush=True)
+        return
 
     t = time.perf_counter()
     p = synth.build_config(args.config, n=args.n)
@@ -273,6 +345,9 @@ def main():
     if not args.no_mixed and precision == L.LF_PREC_FP64 and precond == L.LF_PC_DIAGONAL:
         out["mixed"] = run_mixed(L, torch, p, mesh, prob, T0, args)
         out["mixed"]["speedup_vs_fp64_time_to_tol"] = out["ms_per_step"] / out["mixed"]["ms_per_step"]
+
+    if not args.no_serve:
+        out["serving"] = run_serving(L, torch, args)
 
     if not args.no_cpu_baseline:
         log("[bench] oracle on the host ...")

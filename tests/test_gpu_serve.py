@@ -1,0 +1,95 @@
+"""Serving loop: continuous batching with HBM-budget admission.
+
+Every request's snapshots are the same alone and in a mix (bitwise: each
+problem is solved inside one workgroup with fixed-order sums and the workgroup
+size depends only on the request's size), a deliberately small budget still
+serves everything, and the answers match the oracle's solve of each step.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_common import lapfoam, max_rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    return lapfoam()
+
+
+_MESHES = {}
+
+
+def mesh_for_side(n):
+    if n not in _MESHES:
+        _MESHES[n] = synth.box_mesh(n, n, n)
+    return _MESHES[n]
+
+
+def make_requests(k, seed=3, lo=6, hi=20, steps=4, rate=None):
+    from paper_2507_18268_amd.serve import Request
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    for i in range(k):
+        n = int(rng.integers(lo, hi + 1))
+        DT = float(np.exp(rng.uniform(np.log(1e-4), np.log(1e-2))))
+        if rate:
+            t += float(rng.exponential(1.0 / rate))
+        out.append(Request(rid=i, n=n, DT=DT, dt=1e-3, steps=steps,
+                           T0=synth.initial_field(n ** 3, 5000 + i), bcs=synth.fixed_x_bcs(),
+                           arrival=t))
+    return out
+
+
+TUNING = {"block_threads": [256, 256, 512, 512, 1024, 1024]}
+
+
+def serve(L, reqs, budget=8 << 30, slots=3, cap=5):
+    from paper_2507_18268_amd.serve import Server
+    srv = Server(mesh_for_side, budget, n_slots=slots, slot_capacity=cap, max_steps=4, tuning=TUNING)
+    done = srv.run(reqs, poll_s=0.0)
+    assert srv.used == sum(srv.mesh_bytes.values())      # every request's memory returned
+    srv.close()
+    return {r.rid: r for r in done}, srv
+
+
+def test_alone_equals_in_mix_and_matches_oracle(L, oracle):
+    reqs = make_requests(14, rate=400.0)
+    mix, _ = serve(L, reqs)
+    assert len(mix) == 14 and all(r.error is None for r in mix.values())
+    for rid in (0, 5, 13):
+        alone, _ = serve(L, [make_requests(14, rate=400.0)[rid]], slots=1, cap=1)
+        assert np.array_equal(alone[rid].snapshots, mix[rid].snapshots)
+    for rid in (1, 7):
+        r = mix[rid]
+        mesh = mesh_for_side(r.n)
+        T_prev = r.T0
+        for s in range(r.steps):
+            ref, _, _ = oracle.run(mesh, r.bcs, r.DT, r.dt, 1, T_prev)
+            assert max_rel(r.snapshots[s], ref) <= 1e-8
+            assert r.stats[s]["converged"] == 1
+            T_prev = r.snapshots[s]
+
+
+def test_small_budget_still_serves_everything(L):
+    reqs = make_requests(10, seed=4, lo=8, hi=14)
+    big, _ = serve(L, reqs)
+    # room for the meshes of a couple of sides and about two requests at a time
+    reqs2 = make_requests(10, seed=4, lo=8, hi=14)
+    small, srv = serve(L, reqs2, budget=24 << 20, slots=2, cap=2)
+    assert len(small) == 10
+    for rid in big:
+        assert np.array_equal(big[rid].snapshots, small[rid].snapshots)
+
+
+def test_request_larger_than_budget_is_rejected(L):
+    from paper_2507_18268_amd.serve import Server
+    reqs = make_requests(3, seed=5, lo=10, hi=12)
+    srv = Server(mesh_for_side, 1 << 16, n_slots=1, slot_capacity=2, max_steps=4, tuning=TUNING)
+    done = srv.run(reqs, poll_s=0.0)
+    assert not done and len(srv.rejected) == 3
+    assert all("budget" in r.error for r in srv.rejected)
+    srv.close()
