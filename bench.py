@@ -51,6 +51,22 @@ def amul_bytes(n_cells, n_faces, value_bytes=8):
     return 3 * value_bytes * n_cells + (value_bytes + 8) * n_faces
 
 
+def layout_bytes(mesh, layout_name, value_bytes=8):
+    """Bytes one LDU product must move in the layout it runs in: p, diag and Ap
+    per cell plus, for the band layout, one coefficient per band slot (no
+    indices); for the row layout, per stored entry its coefficient and int32
+    column, and one uint8 row length per cell."""
+    import numpy as np
+    N = mesh.n_cells
+    if layout_name == "bands":
+        K = np.unique(mesh.neighbour.astype(np.int64) - mesh.owner).size
+        return 3 * value_bytes * N + value_bytes * K * N
+    rl = np.bincount(mesh.owner, minlength=N) + np.bincount(mesh.neighbour, minlength=N)
+    pad = (-N) % 64
+    E = int(np.concatenate([rl, np.zeros(pad, rl.dtype)]).reshape(-1, 64).max(axis=1).sum()) * 64
+    return 3 * value_bytes * N + (value_bytes + 4) * E + N
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -276,8 +292,9 @@ def main():
     prob = L.Problem(mesh, p.bcs, p.DT, p.dt, opts)
     T0 = torch.from_numpy(p.T0).cuda()
     torch.cuda.synchronize()
+    layout_name = "bands" if prob.layout() == L.LF_LAYOUT_BANDS else "rows"
     log(f"[bench] device mesh + problem ready in {time.perf_counter() - t:.1f} s "
-        f"(workspaces {mesh.ws_bytes / 2**30:.2f} + {prob.ws_bytes / 2**30:.2f} GiB)")
+        f"(workspaces {mesh.ws_bytes / 2**30:.2f} + {prob.ws_bytes / 2**30:.2f} GiB, {layout_name} layout)")
 
     prob.set_T(T0)
     if args.warmup > 0:
@@ -306,7 +323,7 @@ def main():
         "config": {"workload": f"{args.config}: {round(N ** (1 / 3))}^3 box, z expansion ratio "
                                f"{synth.CONFIGS[args.config]['z_ratio']}, DT={p.DT}, dt={p.dt}, "
                                f"implicit Euler, PCG {p.precond}, tol {synth.TOL}",
-                   "n_cells": N, "n_faces": F, "precision": p.precision},
+                   "n_cells": N, "n_faces": F, "precision": p.precision, "layout": layout_name},
         "iters_per_step_mean": total_iters / len(stats),
         "solver_only_cell_iters_per_s": N * total_iters / solve_s if solve_s > 0 else None,
         "assemble_ms_mean": sum(s["assemble_ms"] for s in stats) / len(stats),
@@ -332,6 +349,11 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                 "algorithmic_bytes_per_launch": per_launch,
                 "avg_launch_us": ka["avg_us"], "largest_total_time_kernel": dom}
+        lb = layout_bytes(p.mesh, layout_name)
+        roof["layout"] = layout_name
+        roof["layout_bytes_per_launch"] = lb
+        roof["layout_GBps"] = lb / (ka["avg_us"] * 1e-6) / 1e9
+        roof["layout_frac"] = roof["layout_GBps"] / HBM_PEAK_GBS
         if os.path.exists(TRAFFIC_FILE):
             with open(TRAFFIC_FILE) as f:
                 tr = json.load(f)

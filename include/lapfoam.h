@@ -62,6 +62,15 @@ typedef int32_t lf_status;
                               numbering: every face's owner < every face's
                               neighbour (all "red" cells before all "black") */
 
+#define LF_LAYOUT_AUTO 0   /* bands when the mesh has the band form and the
+                              preconditioner is diagonal, else rows */
+#define LF_LAYOUT_ROWS 1   /* sliced row layout from the lists of lists: any
+                              mesh; each coefficient stored in both its rows */
+#define LF_LAYOUT_BANDS 2  /* band layout: meshes whose internal faces take at
+                              most 4 distinct offsets neighbour - owner (a
+                              structured numbering); each coefficient stored
+                              once, no column indices; diagonal PC only */
+
 #define LF_PREC_FP64 0     /* everything in binary64 */
 #define LF_PREC_MIXED 1    /* FP64 outer residual and update, FP32 inner PCG
                               (coefficients, vectors, SpMV) with FP64 dot
@@ -107,7 +116,10 @@ typedef struct lf_solver_opts {
     double inner_tol;           /* LF_PREC_MIXED: inner FP32 solve stops when its
                                    residual falls by this factor (0 = default 1e-5) */
     int32_t max_outer;          /* LF_PREC_MIXED: refinement passes cap (0 = 50) */
-    int32_t block_cells;        /* reserved, 0 */
+    int32_t layout;             /* LF_LAYOUT_* of the coefficients (default AUTO).
+                                   Results do not depend on it beyond the sign
+                                   of exact zeros: both layouts sum a row's
+                                   entries in the same order */
 } lf_solver_opts;
 
 /* Per time step results. */
@@ -168,6 +180,10 @@ lf_status lf_problem_create(const lf_mesh *mesh, const lf_patch_bc *bcs, double 
                             size_t workspace_bytes, void *stream, lf_problem **out);
 lf_status lf_problem_destroy(lf_problem *problem);  /* NULL-safe */
 
+/* The coefficient layout the problem resolved to: LF_LAYOUT_ROWS or
+ * LF_LAYOUT_BANDS (never AUTO). */
+lf_status lf_problem_layout(const lf_problem *problem, int32_t *layout);
+
 /* T[N]: on_device = 1 means a device pointer (copied on the handle's stream),
  * 0 a host pointer (synchronous).  lf_set_T rejects non-finite values. */
 lf_status lf_set_T(lf_problem *problem, const double *T, int32_t on_device);
@@ -187,13 +203,15 @@ lf_status lf_step(lf_problem *problem, int32_t n_steps, lf_solve_stats *stats);
 lf_status lf_assemble(lf_problem *problem);
 lf_status lf_get_matrix(lf_problem *problem, double *diag, double *upper, double *source,
                         double *diag_b, double *source_b, double *int_coeff, double *bou_coeff);
-/* y = A x with the last assembled solve-time matrix (diag_b, upper); x, y device
+/* y = A x with the last assembled solve-time matrix (diag_b, upper), in the
+ * problem's layout and order of the solver's products; x, y device
  * pointers of N doubles, ordered on the handle's stream. */
 lf_status lf_amul(lf_problem *problem, const double *x, double *y);
 
 /* ---- batched form -------------------------------------------------------
  * Many independent problems (each its own mesh, boundary conditions, DT, dt
- * and T; created with LF_PREC_MIXED and the diagonal preconditioner) advanced
+ * and T; created with LF_PREC_MIXED, the diagonal preconditioner and
+ * LF_LAYOUT_ROWS; other problems give LF_EINVAL) advanced
  * by one persistent kernel: each workgroup takes the next problem of the task
  * table, in the order given, and runs all n_steps steps of it alone (assembly,
  * then the precision form's refinement with workgroup-level reductions).  A

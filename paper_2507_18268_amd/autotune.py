@@ -57,7 +57,7 @@ def measure(side, bs, copies=64, steps=3, seed=0):
     probs = []
     for i in range(copies):
         P = L.Problem(m, synth.fixed_x_bcs(), 1e-3 * (1 + i % 7), 1e-3,
-                      L.make_opts(precision=L.LF_PREC_MIXED))
+                      L.make_opts(precision=L.LF_PREC_MIXED, layout=L.LF_LAYOUT_ROWS))
         P.set_T(synth.initial_field(mesh.n_cells, seed + i))
         probs.append(P)
     b = L.Batch(copies, steps)

@@ -24,7 +24,7 @@ lf_status lf_default_opts(lf_solver_opts *o) {
     o->use_graph = 1;
     o->inner_tol = 0.0;
     o->max_outer = 0;
-    o->block_cells = 0;
+    o->layout = LF_LAYOUT_AUTO;
     return LF_OK;
 }
 
@@ -59,6 +59,15 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
         set_error("DIC needs a two-colour numbering (every owner < every neighbour)");
         return LF_EINVAL;
     }
+    if (opts.layout != LF_LAYOUT_AUTO && opts.layout != LF_LAYOUT_ROWS && opts.layout != LF_LAYOUT_BANDS) {
+        set_error("unknown layout %d", opts.layout);
+        return LF_EINVAL;
+    }
+    if (opts.layout == LF_LAYOUT_BANDS && (m->n_bands == 0 || opts.precond != LF_PC_DIAGONAL)) {
+        set_error(m->n_bands == 0 ? "the band layout needs a mesh whose faces take at most %d offsets"
+                                  : "the band layout is for the diagonal preconditioner (%d)", kMaxBands);
+        return LF_EINVAL;
+    }
     if (opts.precond == LF_PC_DIC && opts.precision == LF_PREC_MIXED) {
         set_error("the mixed-precision form uses the diagonal preconditioner");
         return LF_EINVAL;
@@ -89,6 +98,7 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
     P->DT = DT;
     P->dt = dt;
     P->stream = static_cast<hipStream_t>(stream);
+    P->banded = use_bands(m, opts);
     P->sp.tol = opts.tol;
     P->sp.rel_tol = opts.rel_tol;
     P->sp.max_iter = opts.max_iter;
@@ -114,10 +124,11 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
     if (e == hipSuccess) e = hipMemsetAsync(P->T, 0, sizeof(double) * m->N, P->stream);
     if (e == hipSuccess) e = hipMemsetAsync(P->state, 0, sizeof(PcgState), P->stream);
     if (e == hipSuccess) e = hipMemsetAsync(P->part, 0, sizeof(double) * kNumPart * P->sp.grid, P->stream);
-    // padding entries of the row layout keep coefficient 0 for good
-    if (e == hipSuccess) e = hipMemsetAsync(P->coef, 0, sizeof(double) * static_cast<size_t>(m->n_entries), P->stream);
-    if (e == hipSuccess && P->coef32)
-        e = hipMemsetAsync(P->coef32, 0, sizeof(float) * static_cast<size_t>(m->n_entries), P->stream);
+    // padding entries of the row layout keep coefficient 0 for good; band
+    // slots without a face are written as 0 by every assembly
+    const size_t slots = coef_slots(m, P->banded);
+    if (e == hipSuccess) e = hipMemsetAsync(P->coef, 0, sizeof(double) * slots, P->stream);
+    if (e == hipSuccess && P->coef32) e = hipMemsetAsync(P->coef32, 0, sizeof(float) * slots, P->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
     if (e != hipSuccess) { set_error("problem setup failed: %s", hipGetErrorString(e)); return fail(LF_EDEVICE); }
     *out = P;
@@ -133,6 +144,13 @@ lf_status lf_problem_destroy(lf_problem *P) {
     for (auto &e : P->ev_pool) if (e) (void)hipEventDestroy(e);
     if (P->h_state) (void)hipHostFree(P->h_state);
     delete P;
+    return LF_OK;
+}
+
+lf_status lf_problem_layout(const lf_problem *P, int32_t *layout) {
+    clear_error();
+    if (!P || !layout) { set_error("NULL argument"); return LF_EINVAL; }
+    *layout = P->banded ? LF_LAYOUT_BANDS : LF_LAYOUT_ROWS;
     return LF_OK;
 }
 

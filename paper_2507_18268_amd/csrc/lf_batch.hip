@@ -341,6 +341,10 @@ lf_status lf_batch_launch(lf_batch *b, int32_t n, lf_problem *const *problems, d
             set_error("problem %d: the batched form needs LF_PREC_MIXED with the diagonal preconditioner", i);
             return LF_EINVAL;
         }
+        if (P->banded) {
+            set_error("problem %d: the batched form uses the row layout (create it with LF_LAYOUT_ROWS)", i);
+            return LF_EINVAL;
+        }
         if (P->mesh->device != b->device) { set_error("problem %d lives on another device", i); return LF_EINVAL; }
         const lf_mesh *m = P->mesh;
         BatchTask &t = b->h_tasks[i];

@@ -63,6 +63,13 @@ constexpr int kFinBlock = 1024;    // threads of the one-workgroup reduction ker
 constexpr int kNumXcd = 8;         // MI355X: 8 accelerator complex dies
 constexpr int kSlice = 64;         // rows per slice of the sliced row layout
 constexpr int kMaxRowLen = 255;    // entries per row (stored as uint8)
+constexpr int kMaxBands = 4;       // distinct neighbour - owner offsets of the band layout
+
+// the band offsets of a mesh, passed to kernels by value
+struct BandOffsets {
+    int32_t k;
+    int32_t d[kMaxBands];
+};
 
 // ---------------------------------------------------------------------------
 // handles
@@ -91,6 +98,14 @@ struct lf_mesh {
     int32_t *soff = nullptr;                              // [n_slices+1]
     int32_t *scol = nullptr, *sface = nullptr;            // [n_entries]
     uint8_t *rlen = nullptr;                              // [N] entries of each row
+    // Band layout, when every internal face's offset neighbour - owner is one
+    // of n_bands values band_d[0] < ... < band_d[n_bands-1] (a structured
+    // numbering): the face (c, c + band_d[k]) has slot k*N + c, and the
+    // geometry factors of each slot are stored there (0 where the face does
+    // not exist).  n_bands = 0 when the mesh has no such form.
+    int32_t n_bands = 0;
+    int32_t band_d[lf::kMaxBands] = {0, 0, 0, 0};
+    double *band_mag_sf = nullptr, *band_delta = nullptr; // [n_bands*N]
     double *V = nullptr;                                  // [N]
     double *mag_sf = nullptr, *delta = nullptr;           // [F]
     double *bmag_sf = nullptr, *bdelta = nullptr;         // [B]

@@ -144,4 +144,64 @@ __device__ __forceinline__ int32_t row_base(const MeshRows &mr, int32_t c) {
     return mr.soff[c >> 6] + (c & (kSlice - 1));
 }
 
+// ---------------------------------------------------------------------------
+// The two coefficient layouts of the per-step kernels.
+//
+// SellLayout: the sliced row layout above; each off-diagonal coefficient is
+// stored in both of its rows, with its column index.
+//
+// BandLayout<K>: for meshes whose faces take only K offsets d_0 < ... <
+// d_{K-1} (neighbour = owner + d_k), the coefficient of face (c, c + d_k) is
+// stored once, at k*n + c (0 where that face does not exist).  Row c's
+// entries are then the faces (c - d_k, c) for k = K-1 .. 0 (its lower faces,
+// ascending column) followed by (c, c + d_k) for k = 0 .. K-1 (its owned
+// faces, ascending column): the order of the sliced layout, so both layouts
+// give the same sums (an absent face adds a zero term).  Columns are implicit
+// and every access of a wavefront is contiguous.
+// ---------------------------------------------------------------------------
+struct SellLayout {
+    MeshRows mr;
+    const double *__restrict__ mag_sf;   // [F]
+    const double *__restrict__ delta;    // [F]
+};
+
+template <int K>
+struct BandLayout {
+    int32_t n;
+    int32_t d[K];
+    const double *__restrict__ mag_sf;   // [K n], 0 where the face does not exist
+    const double *__restrict__ delta;    // [K n]
+};
+
+template <class T, class A>
+__device__ __forceinline__ A layout_dot(const SellLayout &L, int32_t c, const T *__restrict__ coef,
+                                        const T *__restrict__ x, A acc) {
+    return row_dot(L.mr, c, coef, x, acc);
+}
+
+// acc + sum over the row's entries (order above) of a_j x[col_j]
+template <int K, class T, class A>
+__device__ __forceinline__ A layout_dot(const BandLayout<K> &L, int32_t c, const T *__restrict__ coef,
+                                        const T *__restrict__ x, A acc) {
+    T a[2 * K], xv[2 * K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int k = K - 1 - j;
+        const bool ok = c >= L.d[k];
+        const int32_t col = ok ? c - L.d[k] : c;
+        const T v = coef[static_cast<int64_t>(k) * L.n + col];
+        a[j] = ok ? v : T(0);
+        xv[j] = x[col];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int32_t col = c < L.n - L.d[k] ? c + L.d[k] : c;
+        a[K + k] = coef[static_cast<int64_t>(k) * L.n + c];
+        xv[K + k] = x[col];
+    }
+#pragma unroll
+    for (int j = 0; j < 2 * K; ++j) acc += a[j] * xv[j];
+    return acc;
+}
+
 }  // namespace lf

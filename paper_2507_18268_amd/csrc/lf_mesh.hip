@@ -218,6 +218,31 @@ __global__ void k_bface_geometry(int32_t nb, const int32_t *__restrict__ bcell, 
     bdelta[b] = 1.0 / nd;
 }
 
+// Band layout: the geometry factors of face f go to slot k*N + owner, k the
+// index of its offset neighbour - owner among the mesh's band offsets (slots
+// without a face keep the zeros written beforehand).
+__global__ void k_fill_f64(double *a, int64_t n, double v) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+__global__ void k_band_fill(int32_t F, int32_t N, BandOffsets bo, const int32_t *__restrict__ owner,
+                            const int32_t *__restrict__ neighbour, const double *__restrict__ mag_sf,
+                            const double *__restrict__ delta, double *__restrict__ band_mag_sf,
+                            double *__restrict__ band_delta) {
+    int64_t f = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    const int32_t o = owner[f];
+    const int32_t off = neighbour[f] - o;
+    for (int32_t k = 0; k < bo.k; ++k) {
+        if (bo.d[k] == off) {
+            const int64_t slot = static_cast<int64_t>(k) * N + o;
+            band_mag_sf[slot] = mag_sf[f];
+            band_delta[slot] = delta[f];
+        }
+    }
+}
+
 static inline unsigned blocks_for(int64_t n) {
     return static_cast<unsigned>((std::max<int64_t>(n, 1) + kBlock - 1) / kBlock);
 }
@@ -235,7 +260,8 @@ struct MeshScratch {
     double *bS, *bC;     // [3B]
 };
 
-static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, lf_mesh *m, MeshScratch *s) {
+static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, int32_t K, lf_mesh *m,
+                       MeshScratch *s) {
     size_t n1 = static_cast<size_t>(N) + 1;
     const int32_t ns = (N + kSlice - 1) / kSlice;
     auto *owner = cv.take<int32_t>(F);
@@ -256,6 +282,11 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, l
     auto *delta = cv.take<double>(F);
     auto *bmag = cv.take<double>(B);
     auto *bdelta = cv.take<double>(B);
+    double *band_mag = nullptr, *band_delta = nullptr;
+    if (K > 0) {
+        band_mag = cv.take<double>(static_cast<size_t>(K) * N);
+        band_delta = cv.take<double>(static_cast<size_t>(K) * N);
+    }
     size_t tiles = (n1 + kScanTile - 1) / kScanTile + 1;
     MeshScratch sc;
     sc.cnt = cv.take<int32_t>(n1);
@@ -270,6 +301,7 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, l
         m->bface_list = bface_list; m->bface_cell = bface_cell; m->bface_patch = bface_patch;
         m->n_slices = ns; m->n_entries = E; m->soff = soff; m->scol = scol; m->sface = sface; m->rlen = rlen;
         m->V = V; m->mag_sf = mag_sf; m->delta = delta; m->bmag_sf = bmag; m->bdelta = bdelta;
+        m->band_mag_sf = band_mag; m->band_delta = band_delta;
     }
     if (s) *s = sc;
 }
@@ -301,6 +333,31 @@ static lf_status plan_slices(const lf_mesh_desc *d, std::vector<int32_t> *soff, 
     }
     *E = total;
     return LF_OK;
+}
+
+// Band form: the distinct offsets neighbour - owner of the internal faces,
+// ascending, when there are at most kMaxBands of them (a structured
+// numbering, e.g. i + nx (j + ny k) on a block of hexahedra); else 0 bands.
+static BandOffsets plan_bands(const lf_mesh_desc *d) {
+    BandOffsets bo{};
+    const int32_t F = d->n_faces;
+    if (F <= 0 || !d->owner || !d->neighbour) return bo;
+    int32_t k = 0;
+    int32_t v[kMaxBands] = {0, 0, 0, 0};
+    for (int32_t f = 0; f < F; ++f) {
+        const int64_t off = static_cast<int64_t>(d->neighbour[f]) - d->owner[f];
+        if (off <= 0 || off > INT32_MAX) return bo;
+        bool seen = false;
+        for (int32_t j = 0; j < k; ++j) seen = seen || v[j] == off;
+        if (!seen) {
+            if (k == kMaxBands) return bo;
+            v[k++] = static_cast<int32_t>(off);
+        }
+    }
+    std::sort(v, v + k);
+    bo.k = k;
+    for (int32_t j = 0; j < k; ++j) bo.d[j] = v[j];
+    return bo;
 }
 
 // ---------------------------------------------------------------------------
@@ -419,8 +476,9 @@ size_t lf_mesh_workspace_bytes(const lf_mesh_desc *d) {
     if (d->n_faces > 0 && (!d->owner || !d->neighbour)) return 0;
     int64_t E = 0;
     if (plan_slices(d, nullptr, &E) != LF_OK) return 0;
+    const BandOffsets bo = plan_bands(d);
     Carver cv(nullptr);
-    carve_mesh(cv, d->n_cells, d->n_faces, d->patch_start[d->n_patches], E, nullptr, nullptr);
+    carve_mesh(cv, d->n_cells, d->n_faces, d->patch_start[d->n_patches], E, bo.k, nullptr, nullptr);
     return cv.bytes();
 }
 
@@ -435,8 +493,9 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
     std::vector<int32_t> soff_h;
     int64_t E = 0;
     LF_TRY(plan_slices(d, &soff_h, &E));
+    const BandOffsets bo = plan_bands(d);
     Carver dry(nullptr);
-    carve_mesh(dry, N, F, B, E, nullptr, nullptr);
+    carve_mesh(dry, N, F, B, E, bo.k, nullptr, nullptr);
     if (!ws || ws_bytes < dry.bytes() || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) {
         set_error("mesh workspace too small or misaligned: need %zu bytes, 256-aligned", dry.bytes());
         return LF_ENOMEM;
@@ -446,13 +505,15 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
     m->N = N; m->F = F; m->P = P; m->B = B;
     m->two_colour = two_colour;
     m->n_red = n_red;
+    m->n_bands = bo.k;
+    for (int32_t k = 0; k < bo.k; ++k) m->band_d[k] = bo.d[k];
     m->stream = static_cast<hipStream_t>(stream);
     m->patch_start.assign(d->patch_start, d->patch_start + P + 1);
     m->ws_bytes = dry.bytes();
     if (hipGetDevice(&m->device) != hipSuccess) { delete m; set_error("hipGetDevice failed"); return LF_EDEVICE; }
     Carver cv(ws);
     MeshScratch sc;
-    carve_mesh(cv, N, F, B, E, m, &sc);
+    carve_mesh(cv, N, F, B, E, bo.k, m, &sc);
     hipStream_t s = m->stream;
 
     auto fail = [&](lf_status st) { delete m; return st; };
@@ -503,6 +564,13 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
                                hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_face_geometry, dim3(blocks_for(cnt)), dim3(kBlock), 0, s, static_cast<int32_t>(f0),
                            cnt, m->owner, m->neighbour, sc.C, sc.S, m->mag_sf, m->delta);
+    }
+    if (bo.k > 0) {
+        const int64_t slots = static_cast<int64_t>(bo.k) * N;
+        hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(slots)), dim3(kBlock), 0, s, m->band_mag_sf, slots, 0.0);
+        hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(slots)), dim3(kBlock), 0, s, m->band_delta, slots, 0.0);
+        hipLaunchKernelGGL(k_band_fill, dim3(blocks_for(F)), dim3(kBlock), 0, s, F, N, bo, m->owner, m->neighbour,
+                           m->mag_sf, m->delta, m->band_mag_sf, m->band_delta);
     }
     if (B > 0)
         hipLaunchKernelGGL(k_bface_geometry, dim3(blocks_for(B)), dim3(kBlock), 0, s, B, m->bface_cell, sc.C,

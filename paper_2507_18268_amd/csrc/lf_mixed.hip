@@ -24,9 +24,9 @@ constexpr double kTighten = 0.1;
 
 namespace lf {
 
-void carve_mixed(Carver &cv, const lf_mesh *m, lf_problem *P) {
+void carve_mixed(Carver &cv, const lf_mesh *m, bool banded, lf_problem *P) {
     const size_t N = m->N;
-    auto *coef32 = cv.take<float>(static_cast<size_t>(m->n_entries));
+    auto *coef32 = cv.take<float>(coef_slots(m, banded));
     float *v32[6];
     for (auto &v : v32) v = cv.take<float>(N);
     if (P) {
@@ -71,8 +71,9 @@ k_mx_direction(SolverParams sp, const float *__restrict__ rD32, const float *__r
 }
 
 // q = A p in FP32; FP64 partial sums of p.q
+template <class Lay>
 __global__ void __launch_bounds__(kCellBlock)
-k_mx_amul_dot(SolverParams sp, MeshRows mr, const float *__restrict__ diag32, const float *__restrict__ coef32,
+k_mx_amul_dot(SolverParams sp, Lay L, const float *__restrict__ diag32, const float *__restrict__ coef32,
               const float *__restrict__ p32, float *__restrict__ q32, double *__restrict__ part,
               const PcgState *__restrict__ st) {
     if (inner_off(st)) return;
@@ -80,7 +81,7 @@ k_mx_amul_dot(SolverParams sp, MeshRows mr, const float *__restrict__ diag32, co
     double acc[1] = {0.0};
     if (c < sp.n) {
         const float pc = p32[c];
-        const float qc = row_dot(mr, c, coef32, p32, diag32[c] * pc);
+        const float qc = layout_dot(L, c, coef32, p32, diag32[c] * pc);
         q32[c] = qc;
         acc[0] = static_cast<double>(qc) * static_cast<double>(pc);
     }
@@ -118,15 +119,16 @@ k_mx_correct(SolverParams sp, double *__restrict__ T, const float *__restrict__ 
 }
 
 // true residual r = b - A T in FP64; partial sums of |r|
+template <class Lay>
 __global__ void __launch_bounds__(kCellBlock)
-k_mx_residual(SolverParams sp, MeshRows mr, const double *__restrict__ diagB, const double *__restrict__ coef,
+k_mx_residual(SolverParams sp, Lay L, const double *__restrict__ diagB, const double *__restrict__ coef,
               const double *__restrict__ srcB, const double *__restrict__ T, double *__restrict__ r,
               double *__restrict__ part, const PcgState *__restrict__ st) {
     if (st->done) return;
     const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
     double acc[1] = {0.0};
     if (c < sp.n) {
-        const double ax = row_dot(mr, c, coef, T, diagB[c] * T[c]);
+        const double ax = layout_dot(L, c, coef, T, diagB[c] * T[c]);
         const double rc = srcB[c] - ax;
         r[c] = rc;
         acc[0] = fabs(rc);
@@ -222,8 +224,10 @@ static void launch_mx_fin(lf_problem *P, hipStream_t s) {
 static void launch_inner_iteration(lf_problem *P, hipStream_t s) {
     LF_LAUNCH(P, LF_K_INNER_DIRECTION, s, k_mx_direction, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->rD32,
               P->r32, P->p32, P->state);
-    LF_LAUNCH(P, LF_K_INNER_AMUL_DOT, s, k_mx_amul_dot, cell_grid(P), dim3(kCellBlock), 0, s, P->sp,
-              mesh_rows(P->mesh), P->diag32, P->coef32, P->p32, P->q32, P->part, P->state);
+    with_layout(P, [&](auto lay) {
+        LF_LAUNCH(P, LF_K_INNER_AMUL_DOT, s, k_mx_amul_dot<decltype(lay)>, cell_grid(P), dim3(kCellBlock), 0, s,
+                  P->sp, lay, P->diag32, P->coef32, P->p32, P->q32, P->part, P->state);
+    });
     launch_mx_fin<kMxAlpha>(P, s);
     LF_LAUNCH(P, LF_K_INNER_UPDATE, s, k_mx_update, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->p32, P->q32,
               P->rD32, P->r32, P->d32, P->part, P->state);
@@ -241,8 +245,10 @@ static void launch_pass_start(lf_problem *P, hipStream_t s) {
 static void launch_pass_end(lf_problem *P, hipStream_t s) {
     LF_LAUNCH(P, LF_K_MIXED_CORRECT, s, k_mx_correct, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->T, P->d32,
               P->state);
-    LF_LAUNCH(P, LF_K_MIXED_RESIDUAL, s, k_mx_residual, cell_grid(P), dim3(kCellBlock), 0, s, P->sp,
-              mesh_rows(P->mesh), P->diagB, P->coef, P->srcB, P->T, P->r, P->part, P->state);
+    with_layout(P, [&](auto lay) {
+        LF_LAUNCH(P, LF_K_MIXED_RESIDUAL, s, k_mx_residual<decltype(lay)>, cell_grid(P), dim3(kCellBlock), 0, s,
+                  P->sp, lay, P->diagB, P->coef, P->srcB, P->T, P->r, P->part, P->state);
+    });
     launch_mx_fin<kMxOuter>(P, s);
 }
 

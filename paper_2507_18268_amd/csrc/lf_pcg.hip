@@ -22,7 +22,7 @@ namespace lf {
 // face order, source = (T_old/dt) V; fixedValue faces add (DT|S_b|) delta_b to
 // the diagonal and (DT|S_b|)(delta_b T_b) to the source.
 // ---------------------------------------------------------------------------
-template <int W>
+template <int W, bool kUpper>
 __device__ __forceinline__ double assemble_row_w(int32_t c, int32_t base, int32_t len, const MeshRows &mr,
                                                  const double *__restrict__ delta,
                                                  const double *__restrict__ mag_sf, double DT,
@@ -46,12 +46,13 @@ __device__ __forceinline__ double assemble_row_w(int32_t c, int32_t base, int32_
             const double lap_upper = dl[j] * (DT * ms[j]);
             coef[base + kSlice * j] = -lap_upper;
             lap_diag -= lap_upper;
-            if (col[j] > c) upper[f[j]] = -lap_upper;   // owned face: also in face order
+            if (kUpper && col[j] > c) upper[f[j]] = -lap_upper;   // owned face: also in face order
         }
     }
     return lap_diag;
 }
 
+template <bool kUpper>
 __device__ __forceinline__ double assemble_row(int32_t c, const MeshRows &mr, const double *__restrict__ delta,
                                                const double *__restrict__ mag_sf, double DT,
                                                double *__restrict__ coef, double *__restrict__ upper) {
@@ -62,14 +63,14 @@ __device__ __forceinline__ double assemble_row(int32_t c, const MeshRows &mr, co
     const int32_t len = mr.rlen[c];
     switch (width) {
         case 0: return 0.0;
-        case 1: return assemble_row_w<1>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
-        case 2: return assemble_row_w<2>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
-        case 3: return assemble_row_w<3>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
-        case 4: return assemble_row_w<4>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
-        case 5: return assemble_row_w<5>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
-        case 6: return assemble_row_w<6>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
-        case 7: return assemble_row_w<7>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
-        case 8: return assemble_row_w<8>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
+        case 1: return assemble_row_w<1, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
+        case 2: return assemble_row_w<2, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
+        case 3: return assemble_row_w<3, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
+        case 4: return assemble_row_w<4, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
+        case 5: return assemble_row_w<5, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
+        case 6: return assemble_row_w<6, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
+        case 7: return assemble_row_w<7, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
+        case 8: return assemble_row_w<8, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
         default: {
             double lap_diag = 0.0;
             int32_t idx = base;
@@ -78,7 +79,7 @@ __device__ __forceinline__ double assemble_row(int32_t c, const MeshRows &mr, co
                 const double lap_upper = delta[f] * (DT * mag_sf[f]);
                 coef[idx] = -lap_upper;
                 lap_diag -= lap_upper;
-                if (mr.scol[idx] > c) upper[f] = -lap_upper;
+                if (kUpper && mr.scol[idx] > c) upper[f] = -lap_upper;
             }
             return lap_diag;
         }
@@ -136,16 +137,110 @@ __device__ __forceinline__ void row_amul_sum(const MeshRows &mr, int32_t c, cons
     }
 }
 
+// Layout-generic pieces of the assembly kernel.  RowCoefs keeps what the setup
+// part needs of the row just assembled: the sliced layout re-reads the row it
+// stored (only this thread writes it); the band layout keeps all 2K
+// coefficients of the row in registers, since its lower coefficients live in
+// other rows' slots, written by other threads of the same launch.
+template <class Lay>
+struct RowCoefs {};
+template <int K>
+struct RowCoefs<BandLayout<K>> {
+    double a[2 * K];
+};
+
+template <bool kUpper>
+__device__ __forceinline__ double assemble_coefs(const SellLayout &L, int32_t c, double DT,
+                                                 double *__restrict__ coef, double *__restrict__ upper,
+                                                 RowCoefs<SellLayout> &) {
+    return assemble_row<kUpper>(c, L.mr, L.delta, L.mag_sf, DT, coef, upper);
+}
+
+// Band layout: the row's coefficients from the slot geometry (a slot without a
+// face has zero factors, so its coefficient is zero and it leaves lapDiag
+// unchanged); the row stores its owned faces' coefficients.  The face-order
+// copy is written by a separate face kernel when asked for.
+template <bool kUpper, int K>
+__device__ __forceinline__ double assemble_coefs(const BandLayout<K> &L, int32_t c, double DT,
+                                                 double *__restrict__ coef, double *__restrict__,
+                                                 RowCoefs<BandLayout<K>> &rc) {
+    double dl[2 * K], ms[2 * K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int k = K - 1 - j;
+        const bool ok = c >= L.d[k];
+        const int64_t slot = static_cast<int64_t>(k) * L.n + (ok ? c - L.d[k] : c);
+        const double d0 = L.delta[slot], m0 = L.mag_sf[slot];
+        dl[j] = ok ? d0 : 0.0;
+        ms[j] = ok ? m0 : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t slot = static_cast<int64_t>(k) * L.n + c;
+        dl[K + k] = L.delta[slot];
+        ms[K + k] = L.mag_sf[slot];
+    }
+    double lap_diag = 0.0;
+#pragma unroll
+    for (int j = 0; j < 2 * K; ++j) {
+        const double lap_upper = dl[j] * (DT * ms[j]);
+        rc.a[j] = -lap_upper;
+        lap_diag -= lap_upper;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) coef[static_cast<int64_t>(k) * L.n + c] = rc.a[K + k];
+    return lap_diag;
+}
+
+__device__ __forceinline__ void row_amul_sum(const SellLayout &L, int32_t c, const double *__restrict__ coef,
+                                             const RowCoefs<SellLayout> &, const double *__restrict__ x,
+                                             double &ax, double &sa) {
+    row_amul_sum(L.mr, c, coef, x, ax, sa);
+}
+
+template <int K>
+__device__ __forceinline__ void row_amul_sum(const BandLayout<K> &L, int32_t c, const double *__restrict__,
+                                             const RowCoefs<BandLayout<K>> &rc, const double *__restrict__ x,
+                                             double &ax, double &sa) {
+    double xv[2 * K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int k = K - 1 - j;
+        xv[j] = x[c >= L.d[k] ? c - L.d[k] : c];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) xv[K + k] = x[c < L.n - L.d[k] ? c + L.d[k] : c];
+#pragma unroll
+    for (int j = 0; j < 2 * K; ++j) {
+        ax += rc.a[j] * xv[j];
+        sa += rc.a[j];
+    }
+}
+
+// FP32 copy of the row's stored coefficients (precision form)
+__device__ __forceinline__ void store_coef32(const SellLayout &L, int32_t c, const double *__restrict__ coef,
+                                             const RowCoefs<SellLayout> &, float *__restrict__ coef32) {
+    int32_t idx = row_base(L.mr, c);
+    const int32_t len = L.mr.rlen[c];
+    for (int32_t j = 0; j < len; ++j, idx += kSlice) coef32[idx] = static_cast<float>(coef[idx]);
+}
+
+template <int K>
+__device__ __forceinline__ void store_coef32(const BandLayout<K> &L, int32_t c, const double *__restrict__,
+                                             const RowCoefs<BandLayout<K>> &rc, float *__restrict__ coef32) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) coef32[static_cast<int64_t>(k) * L.n + c] = static_cast<float>(rc.a[K + k]);
+}
+
 // kFull also stores diag/source without the boundary part (test hook).
 // kSetup fuses the start of the PCG solve from x0 = T (the row's coefficients
 // are at hand): wA = A x0, r = b - wA, the row sum of A, the row's terms
 // |wA - pA| + |b - pA| of the normalisation factor (pA = row sum * mean(x0),
 // the mean taken beforehand), and with the diagonal preconditioner
 // rD = 1/diag and w.r; partial sums of |r|, those terms and w.r.
-template <bool kFull, bool kSetup, bool kMixed>
+template <class Lay, bool kFull, bool kSetup, bool kMixed>
 __global__ void __launch_bounds__(kCellBlock)
-k_assemble(SolverParams sp, double rdt, double DT, MeshRows mr, const double *__restrict__ mag_sf,
-           const double *__restrict__ delta, const int32_t *__restrict__ bface_start,
+k_assemble(SolverParams sp, double rdt, double DT, Lay L, const int32_t *__restrict__ bface_start,
            const int32_t *__restrict__ bface_list, const int32_t *__restrict__ bface_patch,
            const double *__restrict__ bmag_sf, const double *__restrict__ bdelta,
            const int32_t *__restrict__ patch_type, const double *__restrict__ patch_value,
@@ -159,7 +254,8 @@ k_assemble(SolverParams sp, double rdt, double DT, MeshRows mr, const double *__
     double acc[3] = {0.0, 0.0, 0.0};
     const double x_avg = kSetup ? st->x_avg : 0.0;
     if (c < sp.n) {
-        const double lap_diag = assemble_row(c, mr, delta, mag_sf, DT, coef, upper);
+        RowCoefs<Lay> rcf;
+        const double lap_diag = assemble_coefs<kFull>(L, c, DT, coef, upper, rcf);
         const double v = V[c];
         const double d = rdt * v - lap_diag;
         const double xc = T[c];
@@ -185,15 +281,13 @@ k_assemble(SolverParams sp, double rdt, double DT, MeshRows mr, const double *__
         srcB[c] = sb;
         if (kMixed) {
             // FP32 copy of the solve-time matrix for the inner solves
-            int32_t idx = row_base(mr, c);
-            const int32_t len = mr.rlen[c];
-            for (int32_t j = 0; j < len; ++j, idx += kSlice) coef32[idx] = static_cast<float>(coef[idx]);
+            store_coef32(L, c, coef, rcf, coef32);
             diag32[c] = static_cast<float>(db);
             rD32[c] = static_cast<float>(1.0 / db);
         }
         if (kSetup) {
             double ax = db * xc, sa = db;
-            row_amul_sum(mr, c, coef, T, ax, sa);
+            row_amul_sum(L, c, coef, rcf, T, ax, sa);
             const double rc = sb - ax;
             const double pa = sa * x_avg;
             r[c] = rc;
@@ -223,11 +317,24 @@ k_sum_x(SolverParams sp, const double *__restrict__ T, double *__restrict__ part
 }
 
 // y = A x (diag x first, then the row's entries in order)
+template <class Lay>
 __global__ void __launch_bounds__(kCellBlock)
-k_amul(SolverParams sp, MeshRows mr, const double *__restrict__ diagB, const double *__restrict__ coef,
+k_amul(SolverParams sp, Lay L, const double *__restrict__ diagB, const double *__restrict__ coef,
        const double *__restrict__ x, double *__restrict__ y) {
     const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
-    if (c < sp.n) y[c] = row_dot(mr, c, coef, x, diagB[c] * x[c]);
+    if (c < sp.n) y[c] = layout_dot(L, c, coef, x, diagB[c] * x[c]);
+}
+
+// band layout: face-order copy of the coefficients, upper_f at slot k*N + owner_f
+__global__ void __launch_bounds__(kCellBlock)
+k_band_upper(int32_t F, int32_t N, BandOffsets bo, const int32_t *__restrict__ owner,
+             const int32_t *__restrict__ neighbour, const double *__restrict__ coef, double *__restrict__ upper) {
+    const int64_t f = static_cast<int64_t>(blockIdx.x) * kCellBlock + threadIdx.x;
+    if (f >= F) return;
+    const int32_t o = owner[f];
+    const int32_t off = neighbour[f] - o;
+    for (int32_t k = 0; k < bo.k; ++k)
+        if (bo.d[k] == off) upper[f] = coef[static_cast<int64_t>(k) * N + o];
 }
 
 // Start of PCG iteration k: p = w (k = 0) or p = w + beta p, with w = rD r
@@ -256,8 +363,9 @@ k_direction(SolverParams sp, const double *__restrict__ rD, const double *__rest
 }
 
 // q = A p and the partial sums of q.p
+template <class Lay>
 __global__ void __launch_bounds__(kCellBlock)
-k_amul_dot(SolverParams sp, MeshRows mr, const double *__restrict__ diagB, const double *__restrict__ coef,
+k_amul_dot(SolverParams sp, Lay L, const double *__restrict__ diagB, const double *__restrict__ coef,
            const double *__restrict__ p, double *__restrict__ q, double *__restrict__ part,
            const PcgState *__restrict__ st) {
     if (st->done) return;
@@ -265,7 +373,7 @@ k_amul_dot(SolverParams sp, MeshRows mr, const double *__restrict__ diagB, const
     double acc[1] = {0.0};
     if (c < sp.n) {
         const double pc = p[c];
-        const double qc = row_dot(mr, c, coef, p, diagB[c] * pc);
+        const double qc = layout_dot(L, c, coef, p, diagB[c] * pc);
         q[c] = qc;
         acc[0] = qc * pc;
     }
@@ -499,7 +607,7 @@ void carve_problem(Carver &cv, const lf_mesh *m, const lf_solver_opts &o, lf_pro
     double *vec[11];
     for (auto &v : vec) v = cv.take<double>(N);
     auto *upper = cv.take<double>(F);
-    auto *coef = cv.take<double>(static_cast<size_t>(m->n_entries));
+    auto *coef = cv.take<double>(coef_slots(m, use_bands(m, o)));
     auto *ic = cv.take<double>(B);
     auto *bc = cv.take<double>(B);
     auto *part = cv.take<double>(static_cast<size_t>(kNumPart) * G);
@@ -511,7 +619,7 @@ void carve_problem(Carver &cv, const lf_mesh *m, const lf_solver_opts &o, lf_pro
         P->upper = upper; P->coef = coef; P->int_coeff = ic; P->bou_coeff = bc; P->part = part;
         P->state = state;
     }
-    if (o.precision == LF_PREC_MIXED) carve_mixed(cv, m, P);
+    if (o.precision == LF_PREC_MIXED) carve_mixed(cv, m, use_bands(m, o), P);
 }
 
 MeshRows mesh_rows(const lf_mesh *m) { return MeshRows{m->soff, m->scol, m->sface, m->rlen}; }
@@ -521,11 +629,21 @@ static void launch_assemble_t(lf_problem *P, hipStream_t s) {
     const lf_mesh *m = P->mesh;
     const double rdt = 1.0 / P->dt;
     const bool diag_pc = P->opts.precond == LF_PC_DIAGONAL;
-    LF_LAUNCH(P, LF_K_ASSEMBLE, s, (k_assemble<kFull, kSetup, kMixed>), cell_grid(P), dim3(kCellBlock), 0, s,
-              P->sp, rdt, P->DT, mesh_rows(m), m->mag_sf, m->delta, m->bface_start, m->bface_list,
-              m->bface_patch, m->bmag_sf, m->bdelta, P->patch_type, P->patch_value, m->V, P->T, P->coef,
-              P->upper, P->diag, P->source, P->diagB, P->srcB, P->int_coeff, P->bou_coeff, diag_pc ? 1 : 0,
-              P->r, P->rD, P->part, P->state, P->coef32, P->diag32, P->rD32);
+    with_layout(P, [&](auto lay) {
+        auto kern = k_assemble<decltype(lay), kFull, kSetup, kMixed>;
+        LF_LAUNCH(P, LF_K_ASSEMBLE, s, kern, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, rdt, P->DT, lay,
+                  m->bface_start, m->bface_list, m->bface_patch, m->bmag_sf, m->bdelta, P->patch_type,
+                  P->patch_value, m->V, P->T, P->coef, P->upper, P->diag, P->source, P->diagB, P->srcB,
+                  P->int_coeff, P->bou_coeff, diag_pc ? 1 : 0, P->r, P->rD, P->part, P->state, P->coef32,
+                  P->diag32, P->rD32);
+    });
+    if (kFull && P->banded && m->F > 0) {
+        BandOffsets bo{};
+        bo.k = m->n_bands;
+        for (int k = 0; k < m->n_bands; ++k) bo.d[k] = m->band_d[k];
+        hipLaunchKernelGGL(k_band_upper, dim3(static_cast<unsigned>((m->F + kCellBlock - 1) / kCellBlock)),
+                           dim3(kCellBlock), 0, s, m->F, m->N, bo, m->owner, m->neighbour, P->coef, P->upper);
+    }
 }
 
 lf_status launch_assemble(lf_problem *P, bool full, hipStream_t s) {
@@ -586,8 +704,10 @@ static lf_status launch_setup(lf_problem *P, hipStream_t s) {
 static lf_status launch_iteration(lf_problem *P, hipStream_t s) {
     const lf_mesh *m = P->mesh;
     const bool diag_pc = P->opts.precond == LF_PC_DIAGONAL;
-    LF_LAUNCH(P, LF_K_AMUL_DOT, s, k_amul_dot, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, mesh_rows(m),
-              P->diagB, P->coef, P->p, P->q, P->part, P->state);
+    with_layout(P, [&](auto lay) {
+        LF_LAUNCH(P, LF_K_AMUL_DOT, s, k_amul_dot<decltype(lay)>, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, lay,
+                  P->diagB, P->coef, P->p, P->q, P->part, P->state);
+    });
     launch_fin<kFinAlpha>(P, s);
     if (diag_pc) {
         LF_LAUNCH(P, LF_K_UPDATE, s, k_update<true>, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->q, P->r,
@@ -690,8 +810,10 @@ lf_status solve_fp64(lf_problem *P, lf_solve_stats *out) {
 }
 
 lf_status launch_amul_hook(lf_problem *P, const double *x, double *y) {
-    hipLaunchKernelGGL(k_amul, cell_grid(P), dim3(kCellBlock), 0, P->stream, P->sp, mesh_rows(P->mesh), P->diagB,
-                       P->coef, x, y);
+    with_layout(P, [&](auto lay) {
+        hipLaunchKernelGGL(k_amul<decltype(lay)>, cell_grid(P), dim3(kCellBlock), 0, P->stream, P->sp, lay,
+                           P->diagB, P->coef, x, y);
+    });
     LF_HIP(hipGetLastError());
     return LF_OK;
 }

@@ -69,7 +69,9 @@ struct lf_problem {
     double *T = nullptr;                       // [N] the field; PCG solves in place
     double *r = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr, *w = nullptr, *rD = nullptr;
     double *diag = nullptr, *source = nullptr, *diagB = nullptr, *srcB = nullptr;
-    double *upper = nullptr, *coef = nullptr;  // [F] face order, [n_entries] row layout
+    bool banded = false;                       // coefficients in the band layout
+    double *upper = nullptr;                   // [F] face order (test hook copy)
+    double *coef = nullptr;                    // [n_entries] row layout or [n_bands N] bands
     double *int_coeff = nullptr, *bou_coeff = nullptr;
     double *part = nullptr;                    // [kNumPart][grid]
     lf::PcgState *state = nullptr;

@@ -13,8 +13,50 @@ template <int Mode>
 void launch_fin(lf_problem *P, hipStream_t s);
 
 MeshRows mesh_rows(const lf_mesh *m);
+
+// Which coefficient layout a problem uses (LF_LAYOUT_BANDS needs the band
+// form and the diagonal preconditioner; lf_problem_create checks that).
+inline bool use_bands(const lf_mesh *m, const lf_solver_opts &o) {
+    if (o.layout == LF_LAYOUT_ROWS || m->n_bands == 0 || o.precond != LF_PC_DIAGONAL) return false;
+    return true;
+}
+// coefficient slots of a problem's layout
+inline size_t coef_slots(const lf_mesh *m, bool banded) {
+    return banded ? static_cast<size_t>(m->n_bands) * m->N : static_cast<size_t>(m->n_entries);
+}
+
+inline SellLayout sell_layout(const lf_mesh *m) {
+    return SellLayout{mesh_rows(m), m->mag_sf, m->delta};
+}
+
+template <int K>
+inline BandLayout<K> band_layout(const lf_mesh *m) {
+    BandLayout<K> L;
+    L.n = m->N;
+    for (int k = 0; k < K; ++k) L.d[k] = m->band_d[k];
+    L.mag_sf = m->band_mag_sf;
+    L.delta = m->band_delta;
+    return L;
+}
+
+// Calls fn(layout) with the problem's layout object (a kernel template
+// argument is then decltype(layout)).
+template <class Fn>
+inline void with_layout(const lf_problem *P, Fn &&fn) {
+    const lf_mesh *m = P->mesh;
+    if (!P->banded) {
+        fn(sell_layout(m));
+        return;
+    }
+    switch (m->n_bands) {
+        case 1: fn(band_layout<1>(m)); break;
+        case 2: fn(band_layout<2>(m)); break;
+        case 3: fn(band_layout<3>(m)); break;
+        default: fn(band_layout<4>(m)); break;
+    }
+}
 void carve_problem(Carver &cv, const lf_mesh *m, const lf_solver_opts &o, lf_problem *P);
-void carve_mixed(Carver &cv, const lf_mesh *m, lf_problem *P);
+void carve_mixed(Carver &cv, const lf_mesh *m, bool banded, lf_problem *P);
 lf_status launch_assemble(lf_problem *P, bool full, hipStream_t s);
 lf_status launch_assemble_setup(lf_problem *P, hipStream_t s);
 lf_status solve_fp64(lf_problem *P, lf_solve_stats *out);

@@ -27,6 +27,9 @@ LF_PC_DIAGONAL = 0
 LF_PC_DIC = 1
 LF_PREC_FP64 = 0
 LF_PREC_MIXED = 1
+LF_LAYOUT_AUTO = 0
+LF_LAYOUT_ROWS = 1
+LF_LAYOUT_BANDS = 2
 
 _STATUS = {0: "LF_OK", -1: "LF_EINVAL", -2: "LF_EMESH", -3: "LF_ENOMEM", -4: "LF_EBUDGET",
            -5: "LF_EDEVICE", -6: "LF_ESTATE", -7: "LF_ENONFINITE"}
@@ -55,7 +58,7 @@ class lf_solver_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("rel_tol", C.c_double), ("max_iter", C.c_int32),
                 ("min_iter", C.c_int32), ("precond", C.c_int32), ("precision", C.c_int32),
                 ("iters_per_check", C.c_int32), ("use_graph", C.c_int32),
-                ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("block_cells", C.c_int32)]
+                ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("layout", C.c_int32)]
 
 
 class lf_solve_stats(C.Structure):
@@ -83,6 +86,7 @@ _SIGS = {
                                       C.POINTER(lf_solver_opts), C.c_void_p, C.c_size_t,
                                       C.c_void_p, C.POINTER(C.c_void_p)]),
     "lf_problem_destroy": (C.c_int32, [C.c_void_p]),
+    "lf_problem_layout": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32)]),
     "lf_set_T": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
     "lf_get_T": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
     "lf_step": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
@@ -180,6 +184,12 @@ def lf_problem_create(mesh_h, bcs, DT, dt, opts, ws_ptr, ws_bytes, stream):
 
 def lf_problem_destroy(h):
     _check(lib().lf_problem_destroy(h), "lf_problem_destroy")
+
+
+def lf_problem_layout(h):
+    v = C.c_int32(0)
+    _check(lib().lf_problem_layout(h, C.byref(v)), "lf_problem_layout")
+    return v.value
 
 
 def lf_set_T(h, ptr, on_device):
@@ -347,11 +357,11 @@ class Mesh:
 
 def make_opts(tol=1e-9, rel_tol=0.0, max_iter=1000, min_iter=0, precond=LF_PC_DIAGONAL,
               precision=LF_PREC_FP64, iters_per_check=0, use_graph=1, inner_tol=0.0, max_outer=0,
-              block_cells=0):
+              layout=LF_LAYOUT_AUTO):
     o = lf_default_opts()
     o.tol, o.rel_tol, o.max_iter, o.min_iter = tol, rel_tol, max_iter, min_iter
     o.precond, o.precision, o.iters_per_check, o.use_graph = precond, precision, iters_per_check, use_graph
-    o.inner_tol, o.max_outer, o.block_cells = inner_tol, max_outer, block_cells
+    o.inner_tol, o.max_outer, o.layout = inner_tol, max_outer, layout
     return o
 
 
@@ -371,6 +381,10 @@ class Problem:
         self.stream = _stream_ptr(stream) if stream is not None else mesh.stream
         self.h = lf_problem_create(mesh.h, arr, DT, dt, self.opts, self.ws.data_ptr(),
                                    self.ws_bytes, self.stream)
+
+    def layout(self):
+        """LF_LAYOUT_ROWS or LF_LAYOUT_BANDS."""
+        return lf_problem_layout(self.h)
 
     def set_T(self, T):
         if hasattr(T, "data_ptr"):

@@ -95,7 +95,7 @@ class Server:
 
     # -------------------------------------------------------------- memory
     def _request_bytes(self, req, mesh):
-        opts = L.make_opts(precision=L.LF_PREC_MIXED)
+        opts = L.make_opts(precision=L.LF_PREC_MIXED, layout=L.LF_LAYOUT_ROWS)
         return L.lf_problem_workspace_bytes(mesh.h, opts) + 8 * req.steps * mesh.n_cells
 
     def preload_mesh(self, side):
@@ -161,7 +161,8 @@ class Server:
                     continue
                 return
             self.queue.popleft()
-            P = L.Problem(mesh, req.bcs, req.DT, req.dt, L.make_opts(precision=L.LF_PREC_MIXED))
+            P = L.Problem(mesh, req.bcs, req.DT, req.dt,
+                          L.make_opts(precision=L.LF_PREC_MIXED, layout=L.LF_LAYOUT_ROWS))
             P.set_T(req.T0)
             snap = self.torch.empty(req.steps * mesh.n_cells, dtype=self.torch.float64, device="cuda")
             self.used += need

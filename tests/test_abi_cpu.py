@@ -53,7 +53,7 @@ int main(void) {
   printf("lf_patch_bc %zu\\n", sizeof(lf_patch_bc));
   printf("lf_solver_opts %zu\\n", sizeof(lf_solver_opts));
   printf("lf_solve_stats %zu\\n", sizeof(lf_solve_stats));
-  P(lf_mesh_desc, bface_centre) P(lf_solver_opts, block_cells) P(lf_solver_opts, inner_tol)
+  P(lf_mesh_desc, bface_centre) P(lf_solver_opts, layout) P(lf_solver_opts, inner_tol)
   P(lf_solve_stats, solve_ms) P(lf_patch_bc, value)
   return 0;
 }
@@ -68,7 +68,7 @@ int main(void) {
     assert int(out["lf_solver_opts"]) == C.sizeof(L.lf_solver_opts)
     assert int(out["lf_solve_stats"]) == C.sizeof(L.lf_solve_stats)
     assert int(out["lf_mesh_desc.bface_centre"]) == L.lf_mesh_desc.bface_centre.offset
-    assert int(out["lf_solver_opts.block_cells"]) == L.lf_solver_opts.block_cells.offset
+    assert int(out["lf_solver_opts.layout"]) == L.lf_solver_opts.layout.offset
     assert int(out["lf_solver_opts.inner_tol"]) == L.lf_solver_opts.inner_tol.offset
     assert int(out["lf_solve_stats.solve_ms"]) == L.lf_solve_stats.solve_ms.offset
     assert int(out["lf_patch_bc.value"]) == L.lf_patch_bc.value.offset

@@ -48,7 +48,8 @@ def _run(L, reqs, steps, bs=512, n_wg=0, order=None):
     for i in order:
         mesh, bcs, DT, dt, T0 = reqs[i]
         m = L.Mesh(mesh)
-        P = L.Problem(m, bcs, DT, dt, L.make_opts(precision=L.LF_PREC_MIXED))
+        P = L.Problem(m, bcs, DT, dt,
+                      L.make_opts(precision=L.LF_PREC_MIXED, layout=L.LF_LAYOUT_ROWS))
         P.set_T(T0)
         meshes.append(m)
         probs.append(P)
@@ -129,13 +130,19 @@ def test_batch_refuses_bad_input(L):
     b = L.Batch(2, 2)
     with pytest.raises(L.LapfoamError):
         b.launch([P], 1)
-    Pm = L.Problem(m, synth.fixed_x_bcs(), 1e-3, 1e-3, L.make_opts(precision=L.LF_PREC_MIXED))
+    Pm = L.Problem(m, synth.fixed_x_bcs(), 1e-3, 1e-3,
+                   L.make_opts(precision=L.LF_PREC_MIXED, layout=L.LF_LAYOUT_ROWS))
     with pytest.raises(L.LapfoamError):
         b.launch([Pm, Pm, Pm], 1)                                # more than max_tasks
     with pytest.raises(L.LapfoamError):
         b.launch([Pm], 3)                                        # more than max_steps
     with pytest.raises(L.LapfoamError):
         b.launch([Pm], 1, block_threads=128)
+    Pb = L.Problem(m, synth.fixed_x_bcs(), 1e-3, 1e-3,
+                   L.make_opts(precision=L.LF_PREC_MIXED, layout=L.LF_LAYOUT_BANDS))
+    with pytest.raises(L.LapfoamError):
+        b.launch([Pb], 1)                                        # band layout
+    Pb.close()
     b.close()
     P.close()
     Pm.close()

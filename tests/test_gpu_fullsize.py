@@ -1,0 +1,96 @@
+"""Parity at the full sizes of the timed workloads, in the launch configuration
+the benchmark times (default options: iteration blocks captured as graphs,
+adaptive convergence checks, several time steps in one call).
+
+At these sizes the oracle still finishes a time step in seconds, so every
+output is compared, not a sample: the assembled coefficients and one LDU
+product bitwise, T after each step within 1e-8 (max relative) of the oracle's
+solve of the same system, iteration counts within one.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_common import lapfoam, max_rel
+
+pytestmark = pytest.mark.gpu
+
+T_TOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def L():
+    return lapfoam()
+
+
+def _problem(L, p, precision=None):
+    precond = L.LF_PC_DIC if p.precond == "dic" else L.LF_PC_DIAGONAL
+    if precision is None:
+        precision = L.LF_PREC_MIXED if p.precision == "mixed" else L.LF_PREC_FP64
+    opts = L.make_opts(tol=synth.TOL, rel_tol=synth.REL_TOL, max_iter=synth.MAX_ITER,
+                       precond=precond, precision=precision)
+    m = L.Mesh(p.mesh)
+    return m, L.Problem(m, p.bcs, p.DT, p.dt, opts), precond
+
+
+@pytest.mark.parametrize("cfg", ["graded_256", "permuted_192"])
+def test_full_size_matrix_and_amul_bitwise(L, oracle, cfg):
+    import torch
+    p = synth.build_config(cfg)
+    m, P, _ = _problem(L, p)
+    P.set_T(p.T0)
+    P.assemble()
+    g = P.matrix()
+    o = oracle.assemble(p.mesh, p.bcs, p.DT, p.dt, p.T0)
+    for k in ("diag", "upper", "source", "diag_b", "source_b", "int_coeff", "bou_coeff"):
+        assert np.array_equal(g[k], o[k]), k
+    x = np.random.default_rng(11).uniform(-1.0, 1.0, p.mesh.n_cells)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.empty_like(xd)
+    P.amul(xd, yd)
+    torch.cuda.synchronize()
+    assert np.array_equal(yd.cpu().numpy(), oracle.amul(p.mesh, o["diag_b"], o["upper"], x))
+    P.close()
+    m.close()
+
+
+@pytest.mark.parametrize("cfg,steps", [("graded_256", 2), ("permuted_192", 2), ("graded_256_dic", 1)])
+def test_full_size_steps_match_oracle(L, oracle, cfg, steps):
+    p = synth.build_config(cfg, steps=steps)
+    m, P, pc = _problem(L, p)
+    P.set_T(p.T0)
+    sg, _ = P.step(steps)                  # one call for all steps, as the benchmark does
+    Tg = P.get_T()
+    P.close()
+    m.close()
+    To, so, _ = oracle.run(p.mesh, p.bcs, p.DT, p.dt, steps, p.T0, pc=pc)
+    assert max_rel(Tg, To) <= T_TOL, max_rel(Tg, To)
+    for s in range(steps):
+        assert abs(sg[s]["n_iter"] - so[s]["n_iter"]) <= 1, (s, sg[s], so[s])
+        assert sg[s]["converged"] == 1 and so[s]["converged"] == 1
+        assert abs(sg[s]["initial_residual"] - so[s]["initial_residual"]) <= \
+            1e-10 * so[s]["initial_residual"]
+        assert sg[s]["final_residual"] < synth.TOL
+
+
+def test_full_size_mixed_matches_oracle_per_step(L, oracle):
+    """Precision form at 256^3, each step on the same system as the oracle (the
+    oracle steps once from the precision form's own T).  At this size the FP64
+    PCG stopped at tol 1e-9 is itself about 2.5e-8 (max relative) away from the
+    solution of the system, so the 1e-8 bar is taken against the oracle's
+    converged solve (tol 1e-13); the stopping residual is checked against tol."""
+    p = synth.build_config("mixed_256", steps=2)
+    m, P, _ = _problem(L, p)
+    P.set_T(p.T0)
+    T_prev = p.T0
+    for s in range(2):
+        sg, _ = P.step(1)
+        Tg = P.get_T()
+        exact, so, _ = oracle.run(p.mesh, p.bcs, p.DT, p.dt, 1, T_prev, tol=1e-13)
+        assert max_rel(Tg, exact) <= T_TOL, (s, max_rel(Tg, exact))
+        assert sg[0]["converged"] == 1 and sg[0]["final_residual"] < synth.TOL
+        assert abs(sg[0]["initial_residual"] - so[0]["initial_residual"]) <= \
+            1e-10 * so[0]["initial_residual"]
+        T_prev = Tg
+    P.close()
+    m.close()

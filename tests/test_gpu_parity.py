@@ -58,12 +58,24 @@ BCS_MIXED = [(FIXED_VALUE, 273.0), (FIXED_VALUE, 573.0), (ZERO_GRADIENT, 0.0),
              (FIXED_VALUE, 400.0), (ZERO_GRADIENT, 0.0), (FIXED_VALUE, 300.0)]
 
 
+def _expected_layout(mesh, layout):
+    """Band layout when asked for (or AUTO) and the faces take at most 4 offsets."""
+    offsets = np.unique(mesh.neighbour.astype(np.int64) - mesh.owner)
+    banded = mesh.n_faces > 0 and offsets.size <= 4
+    return 2 if (layout != 1 and banded) else 1
+
+
+LAYOUTS = [0, 1]   # AUTO (bands where the mesh allows), ROWS
+
+
+@pytest.mark.parametrize("layout", LAYOUTS, ids=["auto", "rows"])
 @pytest.mark.parametrize("name,mesh", list(_meshes()), ids=[n for n, _ in _meshes()])
-def test_matrix_matches_oracle(L, oracle, name, mesh):
+def test_matrix_matches_oracle(L, oracle, name, mesh, layout):
     T0 = synth.initial_field(mesh.n_cells, 5)
     DT, dt = 3e-3, 2e-3
     m = L.Mesh(mesh)
-    P = L.Problem(m, BCS_MIXED, DT, dt)
+    P = L.Problem(m, BCS_MIXED, DT, dt, L.make_opts(layout=layout))
+    assert P.layout() == _expected_layout(mesh, layout)
     P.set_T(T0)
     P.assemble()
     g = P.matrix()
@@ -78,12 +90,14 @@ def test_matrix_matches_oracle(L, oracle, name, mesh):
     m.close()
 
 
-def test_matrix_is_bitwise_equal_to_oracle(L, oracle):
+@pytest.mark.parametrize("layout", LAYOUTS, ids=["auto", "rows"])
+def test_matrix_is_bitwise_equal_to_oracle(L, oracle, layout):
     """Same operation order and no contraction: the coefficients agree bit for bit."""
     mesh = synth.box_mesh(24, 20, 18, z_ratio=10.0)
     T0 = synth.initial_field(mesh.n_cells, 6)
     m = L.Mesh(mesh)
-    P = L.Problem(m, BCS_MIXED, 1e-3, 1e-3)
+    P = L.Problem(m, BCS_MIXED, 1e-3, 1e-3, L.make_opts(layout=layout))
+    assert P.layout() == _expected_layout(mesh, layout)
     P.set_T(T0)
     P.assemble()
     g = P.matrix()
@@ -94,12 +108,14 @@ def test_matrix_is_bitwise_equal_to_oracle(L, oracle):
     m.close()
 
 
+@pytest.mark.parametrize("layout", LAYOUTS, ids=["auto", "rows"])
 @pytest.mark.parametrize("name,mesh", list(_meshes()), ids=[n for n, _ in _meshes()])
-def test_amul_bitwise(L, oracle, name, mesh):
+def test_amul_bitwise(L, oracle, name, mesh, layout):
     import torch
     T0 = synth.initial_field(mesh.n_cells, 7)
     m = L.Mesh(mesh)
-    P = L.Problem(m, BCS_MIXED, 1e-3, 1e-3)
+    P = L.Problem(m, BCS_MIXED, 1e-3, 1e-3, L.make_opts(layout=layout))
+    assert P.layout() == _expected_layout(mesh, layout)
     P.set_T(T0)
     P.assemble()
     g = P.matrix()
@@ -150,8 +166,10 @@ EDGE = [
     ("max_iter_1", lambda: synth.box_mesh(10, 10, 10), synth.fixed_x_bcs(), 1e-2, 1e-2, dict(max_iter=1)),
     ("min_iter_7", lambda: synth.box_mesh(10, 10, 10), synth.fixed_x_bcs(), 1e-3, 1e-3, dict(min_iter=7)),
     ("rel_tol", lambda: synth.box_mesh(10, 10, 10), synth.fixed_x_bcs(), 1e-2, 1e-2, dict(rel_tol=1e-3)),
-    ("tiny_chunks", lambda: synth.box_mesh(13, 11, 9, z_ratio=2.0), synth.fixed_x_bcs(), 1e-2, 1e-2,
-     dict(block_cells=7)),
+    ("rows_layout", lambda: synth.box_mesh(13, 11, 9, z_ratio=2.0), synth.fixed_x_bcs(), 1e-2, 1e-2,
+     dict(layout=1)),
+    ("bands_layout", lambda: synth.box_mesh(13, 11, 9, z_ratio=2.0), synth.fixed_x_bcs(), 1e-2, 1e-2,
+     dict(layout=2)),
     ("no_graph", lambda: synth.box_mesh(13, 11, 9), synth.fixed_x_bcs(), 1e-2, 1e-2, dict(use_graph=0)),
     ("check_every_iter", lambda: synth.box_mesh(13, 11, 9), synth.fixed_x_bcs(), 1e-2, 1e-2,
      dict(iters_per_check=1)),
