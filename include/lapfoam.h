@@ -180,6 +180,15 @@ lf_status lf_problem_create(const lf_mesh *mesh, const lf_patch_bc *bcs, double 
                             size_t workspace_bytes, void *stream, lf_problem **out);
 lf_status lf_problem_destroy(lf_problem *problem);  /* NULL-safe */
 
+/* Re-targets an existing problem to new boundary conditions, DT and dt (same
+ * mesh, options, workspace and stream; checks as in lf_problem_create).  T is
+ * kept: set it with lf_set_T.  Returns after the new values are on the device
+ * (synchronises the problem's stream only).  For callers that solve many
+ * problems of one mesh: destroying a problem frees pinned host memory, which
+ * waits for the whole device.  Must not be called while a batch launch uses
+ * the problem. */
+lf_status lf_problem_reset(lf_problem *problem, const lf_patch_bc *bcs, double DT, double dt);
+
 /* The coefficient layout the problem resolved to: LF_LAYOUT_ROWS or
  * LF_LAYOUT_BANDS (never AUTO). */
 lf_status lf_problem_layout(const lf_problem *problem, int32_t *layout);
@@ -246,7 +255,10 @@ lf_status lf_batch_stats(lf_batch *batch, lf_solve_stats *stats, double *elapsed
  * When enabled, lf_step records a HIP event pair around every kernel launch on
  * the handle's stream (plain launches instead of graphs, and a convergence
  * check after every iteration so that no launch is a no-op) and accumulates
- * the device time of each kernel class.  lf_profile_read copies, for class k in
+ * the device time of each kernel class.  Each group of launches is preceded by
+ * a 200 us GPU-side wait so the host has enqueued the group before the GPU
+ * reaches it (the events then time the kernels, not the host); with timing on,
+ * the stats' assemble_ms / solve_ms include those waits.  lf_profile_read copies, for class k in
  * [0, n_classes), the accumulated milliseconds to total_ms[k] and the launch
  * count to launches[k] (either may be NULL); lf_profile_enable(p, 1) also
  * clears the accumulators. */
@@ -265,7 +277,8 @@ lf_status lf_batch_stats(lf_batch *batch, lf_solve_stats *stats, double *elapsed
 #define LF_K_INNER_DIRECTION 11 /* mixed: FP32 direction update */
 #define LF_K_INNER_AMUL_DOT 12  /* mixed: FP32 q = A p, FP64 p.q partials */
 #define LF_K_INNER_UPDATE 13    /* mixed: FP32 update, FP64 partials */
-#define LF_K_MIXED_PREP 14      /* mixed: FP32 coefficients */
+#define LF_K_MIXED_PREP 14      /* mixed: no longer launched (the pass start is part
+                                   of the assembly and residual kernels) */
 #define LF_K_FINALIZE 15        /* one-workgroup reductions and scalar decisions */
 #define LF_NUM_KERNEL_CLASSES 16
 lf_status lf_profile_enable(lf_problem *problem, int32_t on);

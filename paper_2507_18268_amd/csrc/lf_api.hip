@@ -37,15 +37,31 @@ size_t lf_problem_workspace_bytes(const lf_mesh *m, const lf_solver_opts *o) {
     return cv.bytes();
 }
 
+// boundary conditions, DT and dt of a problem on mesh m
+static lf_status check_physics(const lf_mesh *m, const lf_patch_bc *bcs, double DT, double dt) {
+    if (m->P > 0 && !bcs) { set_error("bcs is NULL"); return LF_EINVAL; }
+    if (!(DT >= 0.0) || !std::isfinite(DT)) { set_error("DT must be finite and >= 0"); return LF_EINVAL; }
+    if (!(dt > 0.0) || !std::isfinite(dt)) { set_error("dt must be finite and > 0"); return LF_EINVAL; }
+    for (int32_t p = 0; p < m->P; ++p) {
+        if (bcs[p].type != LF_BC_ZERO_GRADIENT && bcs[p].type != LF_BC_FIXED_VALUE) {
+            set_error("patch %d: unknown boundary condition type %d", p, bcs[p].type);
+            return LF_EINVAL;
+        }
+        if (bcs[p].type == LF_BC_FIXED_VALUE && !std::isfinite(bcs[p].value)) {
+            set_error("patch %d: fixed value not finite", p);
+            return LF_EINVAL;
+        }
+    }
+    return LF_OK;
+}
+
 lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT, double dt,
                             const lf_solver_opts *o, void *ws, size_t ws_bytes, void *stream, lf_problem **out) {
     clear_error();
     if (!out) { set_error("out is NULL"); return LF_EINVAL; }
     *out = nullptr;
     if (!m) { set_error("mesh is NULL"); return LF_EINVAL; }
-    if (m->P > 0 && !bcs) { set_error("bcs is NULL"); return LF_EINVAL; }
-    if (!(DT >= 0.0) || !std::isfinite(DT)) { set_error("DT must be finite and >= 0"); return LF_EINVAL; }
-    if (!(dt > 0.0) || !std::isfinite(dt)) { set_error("dt must be finite and > 0"); return LF_EINVAL; }
+    LF_TRY(check_physics(m, bcs, DT, dt));
     lf_solver_opts opts;
     if (o) opts = *o; else lf_default_opts(&opts);
     if (opts.max_iter < 0 || opts.min_iter < 0 || !std::isfinite(opts.tol) || !std::isfinite(opts.rel_tol) ||
@@ -72,16 +88,6 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
         set_error("the mixed-precision form uses the diagonal preconditioner");
         return LF_EINVAL;
     }
-    for (int32_t p = 0; p < m->P; ++p) {
-        if (bcs[p].type != LF_BC_ZERO_GRADIENT && bcs[p].type != LF_BC_FIXED_VALUE) {
-            set_error("patch %d: unknown boundary condition type %d", p, bcs[p].type);
-            return LF_EINVAL;
-        }
-        if (bcs[p].type == LF_BC_FIXED_VALUE && !std::isfinite(bcs[p].value)) {
-            set_error("patch %d: fixed value not finite", p);
-            return LF_EINVAL;
-        }
-    }
     Carver dry(nullptr);
     carve_problem(dry, m, opts, nullptr);
     if (!ws || ws_bytes < dry.bytes() || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) {
@@ -105,6 +111,7 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
     P->sp.min_iter = opts.min_iter;
     P->sp.n = m->N;
     P->sp.grid = cell_blocks(m->N);
+    P->sp.grid_mx = mx_blocks(m->N);
     P->sp.n_red = m->two_colour ? m->n_red : m->N;
     P->sp.max_outer = opts.max_outer > 0 ? opts.max_outer : 50;
     P->sp.inner_tol = opts.inner_tol > 0.0 ? opts.inner_tol : 1e-5;
@@ -144,6 +151,24 @@ lf_status lf_problem_destroy(lf_problem *P) {
     for (auto &e : P->ev_pool) if (e) (void)hipEventDestroy(e);
     if (P->h_state) (void)hipHostFree(P->h_state);
     delete P;
+    return LF_OK;
+}
+
+lf_status lf_problem_reset(lf_problem *P, const lf_patch_bc *bcs, double DT, double dt) {
+    clear_error();
+    if (!P) { set_error("problem is NULL"); return LF_EINVAL; }
+    const lf_mesh *m = P->mesh;
+    LF_TRY(check_physics(m, bcs, DT, dt));
+    std::vector<int32_t> pt(std::max<int32_t>(m->P, 1), 0);
+    std::vector<double> pv(std::max<int32_t>(m->P, 1), 0.0);
+    for (int32_t p = 0; p < m->P; ++p) { pt[p] = bcs[p].type; pv[p] = bcs[p].value; }
+    LF_HIP(hipMemcpyAsync(P->patch_type, pt.data(), sizeof(int32_t) * pt.size(), hipMemcpyHostToDevice, P->stream));
+    LF_HIP(hipMemcpyAsync(P->patch_value, pv.data(), sizeof(double) * pv.size(), hipMemcpyHostToDevice, P->stream));
+    LF_HIP(hipStreamSynchronize(P->stream));
+    P->bcs.assign(bcs, bcs + m->P);
+    P->DT = DT;
+    P->dt = dt;
+    P->assembled = false;
     return LF_OK;
 }
 
@@ -243,6 +268,7 @@ lf_status lf_step(lf_problem *P, int32_t n_steps, lf_solve_stats *stats) {
     for (int32_t i = 0; i < n_steps; ++i) {
         lf_solve_stats st;
         std::memset(&st, 0, sizeof(st));
+        prof_lead(P, s);
         LF_HIP(hipEventRecord(P->ev[0], s));
         LF_TRY(launch_assemble_setup(P, s));
         LF_HIP(hipEventRecord(P->ev[1], s));

@@ -39,6 +39,15 @@ __device__ __forceinline__ void block_sum(double (&v)[NQ]) {
     __syncthreads();
 }
 
+// Rows of a launch with R rows per thread: workgroup b covers the R tiles of
+// kCellBlock consecutive rows starting at row b * R * kCellBlock, thread t takes
+// row t of each tile (each load of a wavefront stays one contiguous 64-row
+// access, and a thread has R independent rows in flight).
+template <int R>
+__device__ __forceinline__ int32_t cell_row(int j) {
+    return (static_cast<int32_t>(blockIdx.x) * R + j) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+}
+
 // first stage: the workgroup's partial sums go to part[slot * G + blockIdx.x]
 template <int NQ>
 __device__ __forceinline__ void write_partials(double *__restrict__ part, int32_t G, const int (&slot)[NQ],

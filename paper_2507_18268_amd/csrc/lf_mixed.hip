@@ -35,25 +35,6 @@ void carve_mixed(Carver &cv, const lf_mesh *m, bool banded, lf_problem *P) {
     }
 }
 
-// start of a pass: r32 = r (rounded), d = 0; partials of |r32| and w.r
-__global__ void __launch_bounds__(kCellBlock)
-k_mx_to32(SolverParams sp, const double *__restrict__ r, const float *__restrict__ rD32, float *__restrict__ r32,
-          float *__restrict__ d32, double *__restrict__ part, const PcgState *__restrict__ st) {
-    if (st->done) return;
-    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
-    double acc[2] = {0.0, 0.0};
-    if (c < sp.n) {
-        const float rc = static_cast<float>(r[c]);
-        r32[c] = rc;
-        d32[c] = 0.0f;
-        const float wc = rD32[c] * rc;
-        acc[0] = fabs(static_cast<double>(rc));
-        acc[1] = static_cast<double>(wc) * static_cast<double>(rc);
-    }
-    const int slots[2] = {kPartSumR, kPartWr};
-    write_partials<2>(part, sp.grid, slots, acc);
-}
-
 __device__ __forceinline__ bool inner_off(const PcgState *st) { return st->done || st->inner_done; }
 
 // p = w (first inner iteration) or w + beta p, w = rD r, all FP32
@@ -63,8 +44,10 @@ k_mx_direction(SolverParams sp, const float *__restrict__ rD32, const float *__r
     if (inner_off(st)) return;
     const bool first = st->inner_iter == 0;
     const float beta = static_cast<float>(st->beta);
-    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
-    if (c < sp.n) {
+#pragma unroll
+    for (int j = 0; j < kMxRows; ++j) {
+        const int32_t c = cell_row<kMxRows>(j);
+        if (c >= sp.n) continue;
         const float wc = rD32[c] * r32[c];
         p32[c] = first ? wc : wc + beta * p32[c];
     }
@@ -77,16 +60,18 @@ k_mx_amul_dot(SolverParams sp, Lay L, const float *__restrict__ diag32, const fl
               const float *__restrict__ p32, float *__restrict__ q32, double *__restrict__ part,
               const PcgState *__restrict__ st) {
     if (inner_off(st)) return;
-    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
     double acc[1] = {0.0};
-    if (c < sp.n) {
+#pragma unroll
+    for (int j = 0; j < kMxRows; ++j) {
+        const int32_t c = cell_row<kMxRows>(j);
+        if (c >= sp.n) continue;
         const float pc = p32[c];
         const float qc = layout_dot(L, c, coef32, p32, diag32[c] * pc);
         q32[c] = qc;
-        acc[0] = static_cast<double>(qc) * static_cast<double>(pc);
+        acc[0] += static_cast<double>(qc) * static_cast<double>(pc);
     }
     const int slots[1] = {kPartPq};
-    write_partials<1>(part, sp.grid, slots, acc);
+    write_partials<1>(part, sp.grid_mx, slots, acc);
 }
 
 // d += alpha p; r -= alpha q (FP32); FP64 partials of |r| and w.r
@@ -96,18 +81,20 @@ k_mx_update(SolverParams sp, const float *__restrict__ p32, const float *__restr
             double *__restrict__ part, const PcgState *__restrict__ st) {
     if (inner_off(st)) return;
     const float alpha = static_cast<float>(st->alpha);
-    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
     double acc[2] = {0.0, 0.0};
-    if (c < sp.n) {
+#pragma unroll
+    for (int j = 0; j < kMxRows; ++j) {
+        const int32_t c = cell_row<kMxRows>(j);
+        if (c >= sp.n) continue;
         d32[c] += alpha * p32[c];
         const float rc = r32[c] - alpha * q32[c];
         r32[c] = rc;
         const float wc = rD32[c] * rc;
-        acc[0] = fabs(static_cast<double>(rc));
-        acc[1] = static_cast<double>(wc) * static_cast<double>(rc);
+        acc[0] += fabs(static_cast<double>(rc));
+        acc[1] += static_cast<double>(wc) * static_cast<double>(rc);
     }
     const int slots[2] = {kPartSumR, kPartWr};
-    write_partials<2>(part, sp.grid, slots, acc);
+    write_partials<2>(part, sp.grid_mx, slots, acc);
 }
 
 // T += d (FP64)
@@ -118,23 +105,32 @@ k_mx_correct(SolverParams sp, double *__restrict__ T, const float *__restrict__ 
     if (c < sp.n) T[c] += static_cast<double>(d32[c]);
 }
 
-// true residual r = b - A T in FP64; partial sums of |r|
+// true residual r = b - A T in FP64 and its partial sums of |r|; also the
+// start of the next pass, which runs if the outer check does not stop the
+// solve: r32 = r rounded to FP32, d = 0, partial sums of |r32| and w32.r32
 template <class Lay>
 __global__ void __launch_bounds__(kCellBlock)
 k_mx_residual(SolverParams sp, Lay L, const double *__restrict__ diagB, const double *__restrict__ coef,
               const double *__restrict__ srcB, const double *__restrict__ T, double *__restrict__ r,
+              const float *__restrict__ rD32, float *__restrict__ r32, float *__restrict__ d32,
               double *__restrict__ part, const PcgState *__restrict__ st) {
     if (st->done) return;
     const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
-    double acc[1] = {0.0};
+    double acc[3] = {0.0, 0.0, 0.0};
     if (c < sp.n) {
         const double ax = layout_dot(L, c, coef, T, diagB[c] * T[c]);
         const double rc = srcB[c] - ax;
         r[c] = rc;
         acc[0] = fabs(rc);
+        const float r32c = static_cast<float>(rc);
+        r32[c] = r32c;
+        d32[c] = 0.0f;
+        const float w32 = rD32[c] * r32c;
+        acc[1] = fabs(static_cast<double>(r32c));
+        acc[2] = static_cast<double>(w32) * static_cast<double>(r32c);
     }
-    const int slots[1] = {kPartSumR};
-    write_partials<1>(part, sp.grid, slots, acc);
+    const int slots[3] = {kPartSumR, kPartSumR32, kPartWr32};
+    write_partials<3>(part, sp.grid, slots, acc);
 }
 
 // one-workgroup decisions of the refinement
@@ -143,11 +139,12 @@ enum MxFin : int { kMxInnerStart = 0, kMxAlpha = 1, kMxBeta = 2, kMxOuter = 3 };
 template <int Mode>
 __global__ void __launch_bounds__(kFinBlock) k_mx_finalize(SolverParams sp, const double *__restrict__ part,
                                                           PcgState *__restrict__ st) {
-    const int32_t G = sp.grid;
+    // partials per slot: the FP32 inner kernels use their own grid
+    const int32_t G = (Mode == kMxAlpha || Mode == kMxBeta) ? sp.grid_mx : sp.grid;
     if (Mode == kMxInnerStart) {
         if (st->done) return;
         double v[2];
-        const int slots[2] = {kPartSumR, kPartWr};
+        const int slots[2] = {kPartSumR32, kPartWr32};
         reduce_partials<2>(part, G, slots, v);
         if (threadIdx.x == 0) {
             const double target = fmax(sp.inner_tol * v[0], 0.5 * kTighten * sp.tol * st->nf);
@@ -222,24 +219,21 @@ static void launch_mx_fin(lf_problem *P, hipStream_t s) {
 }
 
 static void launch_inner_iteration(lf_problem *P, hipStream_t s) {
-    LF_LAUNCH(P, LF_K_INNER_DIRECTION, s, k_mx_direction, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->rD32,
+    LF_LAUNCH(P, LF_K_INNER_DIRECTION, s, k_mx_direction, mx_grid(P), dim3(kCellBlock), 0, s, P->sp, P->rD32,
               P->r32, P->p32, P->state);
     with_layout(P, [&](auto lay) {
-        LF_LAUNCH(P, LF_K_INNER_AMUL_DOT, s, k_mx_amul_dot<decltype(lay)>, cell_grid(P), dim3(kCellBlock), 0, s,
+        LF_LAUNCH(P, LF_K_INNER_AMUL_DOT, s, k_mx_amul_dot<decltype(lay)>, mx_grid(P), dim3(kCellBlock), 0, s,
                   P->sp, lay, P->diag32, P->coef32, P->p32, P->q32, P->part, P->state);
     });
     launch_mx_fin<kMxAlpha>(P, s);
-    LF_LAUNCH(P, LF_K_INNER_UPDATE, s, k_mx_update, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->p32, P->q32,
+    LF_LAUNCH(P, LF_K_INNER_UPDATE, s, k_mx_update, mx_grid(P), dim3(kCellBlock), 0, s, P->sp, P->p32, P->q32,
               P->rD32, P->r32, P->d32, P->part, P->state);
     launch_mx_fin<kMxBeta>(P, s);
 }
 
-// start of a refinement pass
-static void launch_pass_start(lf_problem *P, hipStream_t s) {
-    LF_LAUNCH(P, LF_K_MIXED_PREP, s, k_mx_to32, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->r, P->rD32, P->r32,
-              P->d32, P->part, P->state);
-    launch_mx_fin<kMxInnerStart>(P, s);
-}
+// start of a refinement pass (r32, d = 0 and their partial sums were written
+// by the kernel that formed the FP64 residual: the assembly or k_mx_residual)
+static void launch_pass_start(lf_problem *P, hipStream_t s) { launch_mx_fin<kMxInnerStart>(P, s); }
 
 // end of a pass: correction, true residual, outer decision
 static void launch_pass_end(lf_problem *P, hipStream_t s) {
@@ -247,7 +241,8 @@ static void launch_pass_end(lf_problem *P, hipStream_t s) {
               P->state);
     with_layout(P, [&](auto lay) {
         LF_LAUNCH(P, LF_K_MIXED_RESIDUAL, s, k_mx_residual<decltype(lay)>, cell_grid(P), dim3(kCellBlock), 0, s,
-                  P->sp, lay, P->diagB, P->coef, P->srcB, P->T, P->r, P->part, P->state);
+                  P->sp, lay, P->diagB, P->coef, P->srcB, P->T, P->r, P->rD32, P->r32, P->d32, P->part,
+                  P->state);
     });
     launch_mx_fin<kMxOuter>(P, s);
 }
@@ -286,6 +281,7 @@ static lf_status launch_inner(lf_problem *P, int32_t k) {
 
 lf_status solve_mixed(lf_problem *P, lf_solve_stats *out) {
     hipStream_t s = P->stream;
+    prof_lead(P, s);
     launch_fin<kFinStart>(P, s);      // normFactor, res0 and the initial decision (shared with FP64)
     launch_pass_start(P, s);
     LF_HIP(hipGetLastError());
@@ -293,6 +289,7 @@ lf_status solve_mixed(lf_problem *P, lf_solve_stats *out) {
     int32_t k = fixed_k > 0 ? fixed_k : std::max<int32_t>(2, P->last_inner > 0 ? P->last_inner : 8);
     int32_t launched = 0;
     for (;;) {
+        prof_lead(P, s);
         LF_TRY(launch_inner(P, k));
         launched += k;
         LF_HIP(hipMemcpyAsync(P->h_state, P->state, sizeof(PcgState), hipMemcpyDeviceToHost, s));
@@ -311,6 +308,7 @@ lf_status solve_mixed(lf_problem *P, lf_solve_stats *out) {
         }
         // pass finished: correct, check, start the next pass (no-ops once done)
         if (fixed_k <= 0) { k = std::max<int32_t>(2, h.inner_iter); P->last_inner = h.inner_iter; }
+        prof_lead(P, s);
         launch_pass_end(P, s);
         launch_pass_start(P, s);
         LF_HIP(hipGetLastError());

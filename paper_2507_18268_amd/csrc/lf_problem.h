@@ -14,7 +14,9 @@ enum PartialSlot : int {
     kPartNf = 2,     // sum |A x0 - pA| + |b - pA|
     kPartWr = 3,     // sum w.r
     kPartPq = 4,     // sum p.Ap
-    kNumPart = 5
+    kPartSumR32 = 5, // precision form, at a pass start: sum |r32| (r32 = r rounded to FP32)
+    kPartWr32 = 6,   //   and sum w32.r32, w32 = rD32 r32
+    kNumPart = 7
 };
 
 // Solver state on the device.  Written only by the one-workgroup reduction
@@ -49,6 +51,7 @@ struct SolverParams {
     int32_t max_iter, min_iter;
     int32_t n;            // cells
     int32_t grid;         // workgroups of a cell-parallel launch (= partials per slot)
+    int32_t grid_mx;      // workgroups of an FP32 inner-solve launch (kMxRows rows per thread)
     int32_t n_red;        // DIC: first black cell
     int32_t max_outer;    // mixed: refinement passes cap
     double inner_tol;     // mixed: relative reduction of each inner solve
@@ -90,6 +93,7 @@ struct lf_problem {
     size_t ws_bytes = 0;
     // per-kernel device timing (diagnostics)
     bool prof_on = false;
+    int64_t prof_ticks = 0;                    // lead time of the timing spin (wall-clock ticks)
     double prof_ms[LF_NUM_KERNEL_CLASSES] = {};
     int64_t prof_n[LF_NUM_KERNEL_CLASSES] = {};
     struct ProfRec { int cls; hipEvent_t a, b; };
@@ -130,6 +134,8 @@ struct ProfScope {
 };
 // accumulate the recorded pairs (call after the stream has been synchronised)
 void prof_flush(lf_problem *P);
+// when timing: a short GPU-side wait ahead of the launches that follow
+void prof_lead(lf_problem *P, hipStream_t s);
 }  // namespace lf
 
 #define LF_LAUNCH(P, cls, s, ...)                  \

@@ -7,6 +7,11 @@ namespace lf {
 
 inline int32_t cell_blocks(int32_t n) { return n > 0 ? (n + kCellBlock - 1) / kCellBlock : 1; }
 inline dim3 cell_grid(const lf_problem *P) { return dim3(static_cast<unsigned>(P->sp.grid)); }
+inline int32_t mx_blocks(int32_t n) {
+    constexpr int32_t kTile = kCellBlock * kMxRows;
+    return n > 0 ? (n + kTile - 1) / kTile : 1;
+}
+inline dim3 mx_grid(const lf_problem *P) { return dim3(static_cast<unsigned>(P->sp.grid_mx)); }
 
 enum FinMode : int { kFinMean = 0, kFinStart = 1, kFinAlpha = 2, kFinBeta = 3 };
 template <int Mode>

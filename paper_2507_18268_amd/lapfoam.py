@@ -87,6 +87,7 @@ _SIGS = {
                                       C.c_void_p, C.POINTER(C.c_void_p)]),
     "lf_problem_destroy": (C.c_int32, [C.c_void_p]),
     "lf_problem_layout": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "lf_problem_reset": (C.c_int32, [C.c_void_p, C.POINTER(lf_patch_bc), C.c_double, C.c_double]),
     "lf_set_T": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
     "lf_get_T": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
     "lf_step": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
@@ -184,6 +185,10 @@ def lf_problem_create(mesh_h, bcs, DT, dt, opts, ws_ptr, ws_bytes, stream):
 
 def lf_problem_destroy(h):
     _check(lib().lf_problem_destroy(h), "lf_problem_destroy")
+
+
+def lf_problem_reset(h, bcs_array, DT, dt):
+    _check(lib().lf_problem_reset(h, bcs_array, C.c_double(DT), C.c_double(dt)), "lf_problem_reset")
 
 
 def lf_problem_layout(h):
@@ -385,6 +390,13 @@ class Problem:
     def layout(self):
         """LF_LAYOUT_ROWS or LF_LAYOUT_BANDS."""
         return lf_problem_layout(self.h)
+
+    def reset(self, bcs, DT, dt):
+        """New boundary conditions, DT and dt for the same mesh and workspace."""
+        arr = (lf_patch_bc * max(len(bcs), 1))()
+        for i, (t, v) in enumerate(bcs):
+            arr[i].type, arr[i].value = int(t), float(v)
+        lf_problem_reset(self.h, arr, DT, dt)
 
     def set_T(self, T):
         if hasattr(T, "data_ptr"):

@@ -6,26 +6,44 @@ of that side) and every admitted request's fields resident on the device, and
 runs continuous batching over several launch slots, each a stream with its own
 batched-kernel task table:
 
-* admission: a queued request is admitted when its device bytes (problem
-  workspace + snapshot buffer, plus its mesh if that is not resident yet) fit
-  the HBM budget; resident meshes no admitted request uses are evicted first
+* admission: a queued request is admitted when its device bytes (snapshot
+  buffer, plus a problem workspace unless an idle one of its side can be
+  re-used, plus its mesh if that is not resident yet) fit the HBM budget; idle
+  problems, then resident meshes no admitted request uses, are evicted first
   when memory is short;
 * launch: whenever a slot is free, the admitted requests not yet running
   (largest first, up to a slot's capacity, one workgroup size per launch) go
   into that slot's persistent batched kernel, so requests that arrive while
   others run start on free slots and their work overlaps on the device;
-* completion: a finished slot's snapshots are copied to the host, its
-  requests' memory returns to the budget, and their latency (arrival to
+* completion: a finished slot's snapshots are copied to the host, the
+  requests' problems go back to a per-side pool (destroying a problem frees
+  pinned host memory, which waits for the whole device, so problems are
+  re-targeted with lf_problem_reset instead), and the latency (arrival to
   results on the host) is recorded.
+
+Large requests can instead take the direct lane: a few worker threads, each
+with its own stream and its own pool of problems, run a request's steps with
+the multi-kernel solver (the whole GPU's bandwidth for one problem,
+coefficients in the band layout where the mesh allows) and copy T after each
+step into the snapshot buffer.  One workgroup is far too little for a large
+mesh, so this cuts both their latency and the time the batched slots spend
+waiting for them.
+
+The server uses n_slots + direct_workers + 1 streams.  The process needs at
+least that many hardware queues (HIP's GPU_MAX_HW_QUEUES, 4 by default, set
+before the runtime starts): streams that share a queue run in order, so a
+direct-lane kernel would wait behind a whole persistent batched launch.
 
 Every request's result is independent of what it shares the GPU with: the
 batched kernel solves each problem inside one workgroup with fixed-order sums,
 and the workgroup size comes from the autotuner's table for the request's
-size.
+size; the direct lane's kernels use fixed-order reductions too, and which lane
+a request takes depends only on its size.
 """
 import collections
 import time
-from dataclasses import dataclass, field
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass
 from typing import Dict, List, Optional
 
 import numpy as np
@@ -62,12 +80,24 @@ class _Live:
     req: Request
     problem: object
     snap: object                   # device tensor [steps * N]
-    nbytes: int
+    snap_bytes: int
+    key: tuple                     # problem pool of the request: (side, lane)
+
+
+@dataclass
+class _Direct:
+    req: Request
+    mesh: object
+    problem: object                # pooled problem or None (created by the worker)
+    snap_bytes: int
+    key: tuple
+    worker: int
+    future: object = None
 
 
 class Server:
     def __init__(self, mesh_for_side, budget_bytes, n_slots=4, slot_capacity=64, max_steps=10,
-                 tuning=None):
+                 tuning=None, direct_min_side=None, direct_workers=4):
         import torch
         self.torch = torch
         self.mesh_for_side = mesh_for_side          # side -> mesh description (host arrays)
@@ -76,9 +106,18 @@ class Server:
         self.slot_capacity = slot_capacity
         self.max_steps = max_steps
         self.tuning = tuning if tuning is not None else autotune.load()
+        self.admit_stream = torch.cuda.Stream()     # set-up work of batched-lane problems
         self.streams = [torch.cuda.Stream() for _ in range(n_slots)]
         self.batches = [L.Batch(slot_capacity, max_steps, stream=s) for s in self.streams]
         self.slot_live: List[Optional[List[_Live]]] = [None] * n_slots
+        # requests with side >= direct_min_side take the direct lane (None: never)
+        self.direct_min_side = direct_min_side
+        nd = direct_workers if direct_min_side is not None else 0
+        self.direct_streams = [torch.cuda.Stream() for _ in range(nd)]
+        self.direct_exec = [ThreadPoolExecutor(1) for _ in range(nd)]
+        self.direct_load = [0] * nd
+        self.direct_live: List[_Direct] = []
+        self.idle: Dict[tuple, List[object]] = collections.defaultdict(list)   # key -> idle problems
         self.meshes: Dict[int, object] = {}          # side -> L.Mesh
         self.mesh_bytes: Dict[int, int] = {}
         self.mesh_users: Dict[int, int] = collections.defaultdict(int)
@@ -86,17 +125,25 @@ class Server:
         self.queue = collections.deque()              # arrived, not admitted
         self.ready: List[_Live] = []                  # admitted, not launched
         self.finished: List[Request] = []
-        self.t0 = time.perf_counter()
         self.rejected: List[Request] = []
+        self.t0 = time.perf_counter()
 
     # ------------------------------------------------------------------ clock
     def now(self):
         return time.perf_counter() - self.t0
 
     # -------------------------------------------------------------- memory
-    def _request_bytes(self, req, mesh):
-        opts = L.make_opts(precision=L.LF_PREC_MIXED, layout=L.LF_LAYOUT_ROWS)
-        return L.lf_problem_workspace_bytes(mesh.h, opts) + 8 * req.steps * mesh.n_cells
+    def _is_direct(self, req):
+        return self.direct_min_side is not None and req.n >= self.direct_min_side
+
+    def _opts(self, direct):
+        # the batched kernel needs the row layout; the direct lane takes the
+        # band layout where the mesh has one
+        layout = L.LF_LAYOUT_AUTO if direct else L.LF_LAYOUT_ROWS
+        return L.make_opts(precision=L.LF_PREC_MIXED, layout=layout)
+
+    def idle_bytes(self):
+        return sum(P.ws_bytes for ps in self.idle.values() for P in ps)
 
     def preload_mesh(self, side):
         """Make a side's mesh resident (counted in the budget)."""
@@ -109,15 +156,28 @@ class Server:
         self.mesh_last_use[side] = self.now()
         return m
 
-    def _evict_meshes(self, need):
-        idle = sorted((t, s) for s, t in self.mesh_last_use.items()
-                      if self.mesh_users[s] == 0 and s in self.meshes)
-        for _, s in idle:
+    def _close_idle(self, key):
+        for P in self.idle.pop(key, []):
+            self.used -= P.ws_bytes
+            P.close()
+
+    def _evict(self, need, keep_side):
+        """Free idle problems, then idle meshes (least recently used sides
+        first, the requesting side last) until `need` more bytes fit."""
+        order = sorted(self.meshes, key=lambda s: (s == keep_side, self.mesh_last_use.get(s, 0.0)))
+        for side in order:
             if self.used + need <= self.budget:
-                break
-            self.meshes.pop(s).close()
-            self.used -= self.mesh_bytes.pop(s)
-            self.mesh_last_use.pop(s, None)
+                return
+            for key in [k for k in self.idle if k[0] == side]:
+                self._close_idle(key)
+        for side in order:
+            if self.used + need <= self.budget:
+                return
+            if side != keep_side and self.mesh_users[side] == 0 and not any(
+                    k[0] == side and ps for k, ps in self.idle.items()):
+                self.meshes.pop(side).close()
+                self.used -= self.mesh_bytes.pop(side)
+                self.mesh_last_use.pop(side, None)
 
     # -------------------------------------------------------------- requests
     def submit(self, req: Request):
@@ -127,52 +187,67 @@ class Server:
             return
         self.queue.append(req)
 
+    def _reject(self, req, why):
+        self.queue.popleft()
+        req.error = why
+        self.rejected.append(req)
+
     def _admit(self):
         while self.queue:
             req = self.queue[0]
-            mesh_new = req.n not in self.meshes
-            if mesh_new:
+            direct = self._is_direct(req)
+            worker = int(np.argmin(self.direct_load)) if direct else -1
+            key = (req.n, worker)
+            if req.n not in self.meshes:
                 # size the mesh from its description before building it
-                desc = self.mesh_for_side(req.n)
-                d = _desc_of(desc)
-                mbytes = L.lf_mesh_workspace_bytes(d[0])
-            else:
-                mbytes = 0
-            if mesh_new:
-                self._evict_meshes(mbytes)
+                mbytes = L.lf_mesh_workspace_bytes(_desc_of(self.mesh_for_side(req.n))[0])
+                self._evict(mbytes, req.n)
                 if self.used + mbytes > self.budget:
                     if not self._anything_live():
-                        self.queue.popleft()
-                        req.error = "mesh larger than the device-memory budget"
-                        self.rejected.append(req)
+                        self._reject(req, "mesh larger than the device-memory budget")
                         continue
                     return
                 mesh = self.preload_mesh(req.n)
             else:
                 mesh = self.meshes[req.n]
-            need = self._request_bytes(req, mesh)
+            snap_bytes = 8 * req.steps * mesh.n_cells
+            new_bytes = L.lf_problem_workspace_bytes(mesh.h, self._opts(direct))
+            need = snap_bytes if self.idle.get(key) else snap_bytes + new_bytes
             if self.used + need > self.budget:
-                self._evict_meshes(need)
+                self._evict(need, req.n)
+                need = snap_bytes if self.idle.get(key) else snap_bytes + new_bytes
             if self.used + need > self.budget:
                 if not self._anything_live():
-                    self.queue.popleft()
-                    req.error = "request larger than the device-memory budget"
-                    self.rejected.append(req)
+                    self._reject(req, "request larger than the device-memory budget")
                     continue
                 return
             self.queue.popleft()
-            P = L.Problem(mesh, req.bcs, req.DT, req.dt,
-                          L.make_opts(precision=L.LF_PREC_MIXED, layout=L.LF_LAYOUT_ROWS))
-            P.set_T(req.T0)
-            snap = self.torch.empty(req.steps * mesh.n_cells, dtype=self.torch.float64, device="cuda")
             self.used += need
             self.mesh_users[req.n] += 1
             req.admitted = self.now()
-            self.ready.append(_Live(req, P, snap, need))
+            P = self.idle[key].pop() if self.idle.get(key) else None
+            if direct:
+                d = _Direct(req, mesh, P, snap_bytes, key, worker)
+                self.direct_load[worker] += 1
+                d.future = self.direct_exec[worker].submit(self._run_direct, d)
+                req.launched = self.now()
+                self.direct_live.append(d)
+                continue
+            with self.torch.cuda.stream(self.admit_stream):
+                if P is None:
+                    P = L.Problem(mesh, req.bcs, req.DT, req.dt, self._opts(False),
+                                  stream=self.admit_stream)
+                else:
+                    P.reset(req.bcs, req.DT, req.dt)
+                P.set_T(req.T0)                      # host copy: done when this returns
+                snap = self.torch.empty(req.steps * mesh.n_cells, dtype=self.torch.float64,
+                                        device="cuda")
+            self.ready.append(_Live(req, P, snap, snap_bytes, key))
 
     def _anything_live(self):
-        return bool(self.ready) or any(s is not None for s in self.slot_live)
+        return bool(self.ready) or bool(self.direct_live) or any(s is not None for s in self.slot_live)
 
+    # -------------------------------------------------------------- batched lane
     def _launch(self):
         for k, live in enumerate(self.slot_live):
             if live is not None or not self.ready:
@@ -186,14 +261,19 @@ class Server:
                      and x.req.steps == steps][: self.slot_capacity]
             for x in group:
                 self.ready.remove(x)
-            # the problems' set-up (workspace clearing, T) finished synchronously
-            # on their own stream when they were admitted
             self.batches[k].launch([x.problem for x in group], steps, block_threads=bs,
                                    snapshots=[x.snap for x in group])
             t = self.now()
             for x in group:
                 x.req.launched = t
             self.slot_live[k] = group
+
+    def _finish(self, req, snap_bytes):
+        req.done = self.now()
+        self.finished.append(req)
+        self.used -= snap_bytes
+        self.mesh_users[req.n] -= 1
+        self.mesh_last_use[req.n] = req.done
 
     def _collect(self):
         for k, live in enumerate(self.slot_live):
@@ -202,44 +282,98 @@ class Server:
             stats, _ = self.batches[k].stats()
             with self.torch.cuda.stream(self.streams[k]):
                 host = [x.snap.to("cpu", non_blocking=False) for x in live]
-            t = self.now()
             for x, st, h in zip(live, stats, host):
                 x.req.snapshots = h.numpy().reshape(x.req.steps, -1)
                 x.req.stats = st
-                x.req.done = t
-                self.finished.append(x.req)
-                x.problem.close()
-                self.used -= x.nbytes
-                self.mesh_users[x.req.n] -= 1
-                self.mesh_last_use[x.req.n] = t
+                self.idle[x.key].append(x.problem)
+                self._finish(x.req, x.snap_bytes)
             self.slot_live[k] = None
 
+    # -------------------------------------------------------------- direct lane
+    def _run_direct(self, d: _Direct):
+        """Worker thread: all steps of one request on this worker's stream."""
+        torch = self.torch
+        req = d.req
+        st = self.direct_streams[d.worker]
+        P = d.problem
+        with torch.cuda.stream(st):
+            try:
+                if P is None:
+                    P = L.Problem(d.mesh, req.bcs, req.DT, req.dt, self._opts(True), stream=st)
+                else:
+                    P.reset(req.bcs, req.DT, req.dt)
+                snap = torch.empty((req.steps, d.mesh.n_cells), dtype=torch.float64, device="cuda")
+                P.set_T(req.T0)
+                stats = []
+                for s in range(req.steps):
+                    st_s, _ = P.step(1)
+                    stats += st_s
+                    P.get_T(out=snap[s])
+                host = snap.to("cpu")          # synchronous on this stream
+                return host.numpy(), stats, P, None
+            except Exception as e:             # reported on the request, the server goes on
+                return None, None, P, f"direct lane: {e}"
+
+    def _collect_direct(self):
+        still = []
+        for d in self.direct_live:
+            if not d.future.done():
+                still.append(d)
+                continue
+            host, stats, P, err = d.future.result()
+            req = d.req
+            self.direct_load[d.worker] -= 1
+            if err is None:
+                req.snapshots, req.stats = host, stats
+                self.idle[d.key].append(P)
+            else:
+                req.error = err
+                if P is not None:
+                    self.used -= P.ws_bytes
+                    P.close()
+                else:
+                    self.used -= L.lf_problem_workspace_bytes(d.mesh.h, self._opts(True))
+            self._finish(req, d.snap_bytes)
+        self.direct_live = still
+
+    # -------------------------------------------------------------- loop
     def pump(self):
-        """One scheduling pass: collect finished slots, admit, launch."""
+        """One scheduling pass: collect finished work, admit, launch."""
+        self._collect_direct()
         self._collect()
         self._admit()
         self._launch()
 
-    def idle(self):
+    def idle_now(self):
         return not self.queue and not self._anything_live()
 
-    def run(self, requests: List[Request], poll_s=0.0002):
+    def run(self, requests: List[Request], poll_s=0.0002, progress=None, every=64):
         """Serve requests whose `arrival` times (seconds) are on this server's clock,
-        starting now.  Returns when every request has finished."""
+        starting now.  Returns the requests finished by this call.  progress(done,
+        total) is called each time another `every` requests have finished."""
         pending = sorted(requests, key=lambda r: r.arrival)
         self.t0 = time.perf_counter()
+        self.finished = []
         i = 0
-        while i < len(pending) or not self.idle():
+        reported = 0
+        while i < len(pending) or not self.idle_now():
             t = self.now()
             while i < len(pending) and pending[i].arrival <= t:
                 self.submit(pending[i])
                 i += 1
             self.pump()
-            if poll_s:
-                time.sleep(poll_s)
+            if progress is not None and len(self.finished) >= reported + every:
+                reported = len(self.finished) // every * every
+                progress(len(self.finished), len(pending))
+            time.sleep(poll_s)      # also lets the direct-lane workers take the interpreter lock
         return self.finished
 
     def close(self):
+        for ex in self.direct_exec:
+            ex.shutdown(wait=True)
+        self.direct_exec = []
+        for key in list(self.idle):
+            self._close_idle(key)
         for b in self.batches:
             b.close()
         for m in self.meshes.values():

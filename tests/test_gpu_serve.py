@@ -2,8 +2,10 @@
 
 Every request's snapshots are the same alone and in a mix (bitwise: each
 problem is solved inside one workgroup with fixed-order sums and the workgroup
-size depends only on the request's size), a deliberately small budget still
-serves everything, and the answers match the oracle's solve of each step.
+size depends only on the request's size; direct-lane requests run the
+multi-kernel solver, whose reductions have a fixed order too), a deliberately
+small budget still serves everything, and the answers match the oracle's solve
+of each step.
 """
 import numpy as np
 import pytest
@@ -47,11 +49,13 @@ def make_requests(k, seed=3, lo=6, hi=20, steps=4, rate=None):
 TUNING = {"block_threads": [256, 256, 512, 512, 1024, 1024]}
 
 
-def serve(L, reqs, budget=8 << 30, slots=3, cap=5):
+def serve(L, reqs, budget=8 << 30, slots=3, cap=5, **kw):
     from paper_2507_18268_amd.serve import Server
-    srv = Server(mesh_for_side, budget, n_slots=slots, slot_capacity=cap, max_steps=4, tuning=TUNING)
+    srv = Server(mesh_for_side, budget, n_slots=slots, slot_capacity=cap, max_steps=4, tuning=TUNING,
+                 **kw)
     done = srv.run(reqs, poll_s=0.0)
-    assert srv.used == sum(srv.mesh_bytes.values())      # every request's memory returned
+    # every request's memory returned: what is left are the meshes and the idle problems
+    assert srv.used == sum(srv.mesh_bytes.values()) + srv.idle_bytes()
     srv.close()
     return {r.rid: r for r in done}, srv
 
@@ -93,3 +97,25 @@ def test_request_larger_than_budget_is_rejected(L):
     assert not done and len(srv.rejected) == 3
     assert all("budget" in r.error for r in srv.rejected)
     srv.close()
+
+
+def test_direct_lane_alone_equals_in_mix_and_matches_oracle(L, oracle):
+    reqs = make_requests(12, seed=6, rate=400.0)
+    mix, srv = serve(L, reqs, direct_min_side=14, direct_workers=3)
+    assert len(mix) == 12 and all(r.error is None for r in mix.values())
+    big = sorted(r.rid for r in mix.values() if r.n >= 14)
+    small = sorted(r.rid for r in mix.values() if r.n < 14)
+    assert big and small
+    for rid in (big[0], big[-1], small[0]):
+        alone, _ = serve(L, [make_requests(12, seed=6, rate=400.0)[rid]], slots=1, cap=1,
+                         direct_min_side=14, direct_workers=1)
+        assert np.array_equal(alone[rid].snapshots, mix[rid].snapshots)
+    for rid in (big[0], small[0]):
+        r = mix[rid]
+        mesh = mesh_for_side(r.n)
+        T_prev = r.T0
+        for s in range(r.steps):
+            ref, _, _ = oracle.run(mesh, r.bcs, r.DT, r.dt, 1, T_prev)
+            assert max_rel(r.snapshots[s], ref) <= 1e-8
+            assert r.stats[s]["converged"] == 1
+            T_prev = r.snapshots[s]
