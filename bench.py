@@ -260,7 +260,7 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-capacity", type=int, default=64)
-    ap.add_argument("--serve-direct-min", type=int, default=40,
+    ap.add_argument("--serve-direct-min", type=int, default=0,
                     help="requests with at least this cube side run on the multi-kernel solver (0 = never)")
     ap.add_argument("--serve-direct-workers", type=int, default=4)
     ap.add_argument("--copy-calibration", action="store_true",

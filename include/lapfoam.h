@@ -197,6 +197,11 @@ lf_status lf_problem_layout(const lf_problem *problem, int32_t *layout);
  * 0 a host pointer (synchronous).  lf_set_T rejects non-finite values. */
 lf_status lf_set_T(lf_problem *problem, const double *T, int32_t on_device);
 lf_status lf_get_T(lf_problem *problem, double *T, int32_t on_device);
+/* Tb[B]: the field on the boundary faces, in boundary-face order (patch by
+ * patch): the patch's value on fixedValue patches, the value of the face's cell
+ * on zeroGradient patches (the boundary values that go with T; output only,
+ * the solve does not use them).  on_device as for lf_get_T. */
+lf_status lf_get_boundary_T(lf_problem *problem, double *Tb, int32_t on_device);
 
 /* Advance n_steps time steps.  stats[n_steps] (host, may be NULL).
  * Per step: assemble TEqn from the current T, solve from x0 = T, T = x.

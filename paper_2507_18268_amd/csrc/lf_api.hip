@@ -207,6 +207,34 @@ lf_status lf_get_T(lf_problem *P, double *T, int32_t on_device) {
     return LF_OK;
 }
 
+// field values on the boundary faces: the fixed value on fixedValue patches,
+// the face cell's value on zeroGradient patches
+__global__ void k_boundary_values(int32_t B, const int32_t *__restrict__ bface_cell,
+                                  const int32_t *__restrict__ bface_patch, const int32_t *__restrict__ patch_type,
+                                  const double *__restrict__ patch_value, const double *__restrict__ T,
+                                  double *__restrict__ Tb) {
+    const int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const int32_t pt = bface_patch[b];
+    Tb[b] = patch_type[pt] == LF_BC_FIXED_VALUE ? patch_value[pt] : T[bface_cell[b]];
+}
+
+lf_status lf_get_boundary_T(lf_problem *P, double *Tb, int32_t on_device) {
+    clear_error();
+    if (!P || (!Tb && P->mesh->B > 0)) { set_error("NULL argument"); return LF_EINVAL; }
+    const lf_mesh *m = P->mesh;
+    if (m->B == 0) return LF_OK;
+    double *dst = on_device ? Tb : P->Tb;
+    hipLaunchKernelGGL(k_boundary_values, dim3(static_cast<unsigned>((m->B + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       P->stream, m->B, m->bface_cell, m->bface_patch, P->patch_type, P->patch_value, P->T, dst);
+    LF_HIP(hipGetLastError());
+    if (!on_device) {
+        LF_HIP(hipMemcpyAsync(Tb, P->Tb, sizeof(double) * m->B, hipMemcpyDeviceToHost, P->stream));
+        LF_HIP(hipStreamSynchronize(P->stream));
+    }
+    return LF_OK;
+}
+
 lf_status lf_assemble(lf_problem *P) {
     clear_error();
     if (!P) { set_error("NULL problem"); return LF_EINVAL; }

@@ -54,17 +54,41 @@ __device__ __forceinline__ void bsum2(double &a0, double &a1) {
     a1 = a[1];
 }
 
+// The task's arrays are distinct allocations: taking them into __restrict__
+// locals lets the compiler overlap the loads of several rows of a loop.
 template <int BS>
 __device__ void solve_task(const BatchTask &tk, int32_t n_steps, lf_solve_stats *__restrict__ stats) {
     const MeshRows mr{tk.soff, tk.scol, tk.sface, tk.rlen};
     const int32_t n = tk.n;
+    const double *__restrict__ V = tk.V;
+    const double *__restrict__ mag_sf = tk.mag_sf;
+    const double *__restrict__ delta = tk.delta;
+    const int32_t *__restrict__ bface_start = tk.bface_start;
+    const int32_t *__restrict__ bface_list = tk.bface_list;
+    const int32_t *__restrict__ bface_patch = tk.bface_patch;
+    const double *__restrict__ bmag_sf = tk.bmag_sf;
+    const double *__restrict__ bdelta = tk.bdelta;
+    const int32_t *__restrict__ patch_type = tk.patch_type;
+    const double *__restrict__ patch_value = tk.patch_value;
+    double *__restrict__ T = tk.T;
+    double *__restrict__ coef = tk.coef;
+    double *__restrict__ diagB = tk.diagB;
+    double *__restrict__ srcB = tk.srcB;
+    double *__restrict__ r = tk.r;
+    float *__restrict__ coef32 = tk.coef32;
+    float *__restrict__ diag32 = tk.diag32;
+    float *__restrict__ rD32 = tk.rD32;
+    float *__restrict__ r32 = tk.r32;
+    float *__restrict__ p32 = tk.p32;
+    float *__restrict__ q32 = tk.q32;
+    float *__restrict__ d32 = tk.d32;
     const int32_t tid = static_cast<int32_t>(threadIdx.x);
     const double rdt = 1.0 / tk.dt;
     const double DT = tk.DT;
     for (int32_t step = 0; step < n_steps; ++step) {
         // ---- mean of x0 = T
         double sx = 0.0;
-        for (int32_t c = tid; c < n; c += BS) sx += tk.T[c];
+        for (int32_t c = tid; c < n; c += BS) sx += T[c];
         const double x_avg = bsum1<BS>(sx) / static_cast<double>(n);
         // ---- assembly (FP64 + FP32 copy), r0 = b - A x0, normalisation terms
         double a_r = 0.0, a_nf = 0.0;
@@ -74,37 +98,37 @@ __device__ void solve_task(const BatchTask &tk, int32_t n_steps, lf_solve_stats 
             double lap_diag = 0.0;
             for (int32_t j = 0; j < len; ++j, idx += kSlice) {
                 const int32_t f = mr.sface[idx];
-                const double lap_upper = tk.delta[f] * (DT * tk.mag_sf[f]);
-                tk.coef[idx] = -lap_upper;
-                tk.coef32[idx] = static_cast<float>(-lap_upper);
+                const double lap_upper = delta[f] * (DT * mag_sf[f]);
+                coef[idx] = -lap_upper;
+                coef32[idx] = static_cast<float>(-lap_upper);
                 lap_diag -= lap_upper;
             }
-            const double v = tk.V[c];
-            const double xc = tk.T[c];
+            const double v = V[c];
+            const double xc = T[c];
             double db = rdt * v - lap_diag;
             double sb = (rdt * xc) * v;
-            for (int32_t i = tk.bface_start[c]; i < tk.bface_start[c + 1]; ++i) {
-                const int32_t b = tk.bface_list[i];
-                const int32_t pt = tk.bface_patch[b];
-                if (tk.patch_type[pt] == LF_BC_FIXED_VALUE) {
-                    const double g = DT * tk.bmag_sf[b];
-                    db += g * tk.bdelta[b];
-                    sb += g * (tk.bdelta[b] * tk.patch_value[pt]);
+            for (int32_t i = bface_start[c]; i < bface_start[c + 1]; ++i) {
+                const int32_t b = bface_list[i];
+                const int32_t pt = bface_patch[b];
+                if (patch_type[pt] == LF_BC_FIXED_VALUE) {
+                    const double g = DT * bmag_sf[b];
+                    db += g * bdelta[b];
+                    sb += g * (bdelta[b] * patch_value[pt]);
                 }
             }
-            tk.diagB[c] = db;
-            tk.srcB[c] = sb;
-            tk.diag32[c] = static_cast<float>(db);
-            tk.rD32[c] = static_cast<float>(1.0 / db);
+            diagB[c] = db;
+            srcB[c] = sb;
+            diag32[c] = static_cast<float>(db);
+            rD32[c] = static_cast<float>(1.0 / db);
             double ax = db * xc, sa = db;
             idx = row_base(mr, c);
             for (int32_t j = 0; j < len; ++j, idx += kSlice) {
-                const double a = tk.coef[idx];
-                ax += a * tk.T[mr.scol[idx]];
+                const double a = coef[idx];
+                ax += a * T[mr.scol[idx]];
                 sa += a;
             }
             const double rc = sb - ax;
-            tk.r[c] = rc;
+            r[c] = rc;
             const double pa = sa * x_avg;
             a_r += fabs(rc);
             a_nf += fabs(ax - pa) + fabs(sb - pa);
@@ -120,11 +144,12 @@ __device__ void solve_task(const BatchTask &tk, int32_t n_steps, lf_solve_stats 
         // ---- refinement passes
         while (!nonfinite && !tight && n_outer < tk.max_outer && n_iter < tk.max_iter) {
             double s_r = 0.0, s_wr = 0.0;
+            #pragma unroll 2
             for (int32_t c = tid; c < n; c += BS) {
-                const float rc = static_cast<float>(tk.r[c]);
-                tk.r32[c] = rc;
-                tk.d32[c] = 0.0f;
-                const float wc = tk.rD32[c] * rc;
+                const float rc = static_cast<float>(r[c]);
+                r32[c] = rc;
+                d32[c] = 0.0f;
+                const float wc = rD32[c] * rc;
                 s_r += fabs(static_cast<double>(rc));
                 s_wr += static_cast<double>(wc) * static_cast<double>(rc);
             }
@@ -136,16 +161,17 @@ __device__ void solve_task(const BatchTask &tk, int32_t n_steps, lf_solve_stats 
             int32_t inner_iter = 0;
             while (!inner_done) {
                 const float fb = static_cast<float>(beta);
+                #pragma unroll 2
                 for (int32_t c = tid; c < n; c += BS) {
-                    const float wc = tk.rD32[c] * tk.r32[c];
-                    tk.p32[c] = inner_iter == 0 ? wc : wc + fb * tk.p32[c];
+                    const float wc = rD32[c] * r32[c];
+                    p32[c] = inner_iter == 0 ? wc : wc + fb * p32[c];
                 }
                 __syncthreads();
                 double s_pq = 0.0;
                 for (int32_t c = tid; c < n; c += BS) {
-                    const float pc = tk.p32[c];
-                    const float qc = row_dot(mr, c, tk.coef32, tk.p32, tk.diag32[c] * pc);
-                    tk.q32[c] = qc;
+                    const float pc = p32[c];
+                    const float qc = row_dot(mr, c, coef32, p32, diag32[c] * pc);
+                    q32[c] = qc;
                     s_pq += static_cast<double>(qc) * static_cast<double>(pc);
                 }
                 const double pq = bsum1<BS>(s_pq);
@@ -154,11 +180,12 @@ __device__ void solve_task(const BatchTask &tk, int32_t n_steps, lf_solve_stats 
                 const double alpha = wArA / pq;
                 const float fa = static_cast<float>(alpha);
                 double u_r = 0.0, u_wr = 0.0;
+                #pragma unroll 2
                 for (int32_t c = tid; c < n; c += BS) {
-                    tk.d32[c] += fa * tk.p32[c];
-                    const float rc = tk.r32[c] - fa * tk.q32[c];
-                    tk.r32[c] = rc;
-                    const float wc = tk.rD32[c] * rc;
+                    d32[c] += fa * p32[c];
+                    const float rc = r32[c] - fa * q32[c];
+                    r32[c] = rc;
+                    const float wc = rD32[c] * rc;
                     u_r += fabs(static_cast<double>(rc));
                     u_wr += static_cast<double>(wc) * static_cast<double>(rc);
                 }
@@ -175,13 +202,14 @@ __device__ void solve_task(const BatchTask &tk, int32_t n_steps, lf_solve_stats 
             }
             if (nonfinite) break;
             // T += d, then the FP64 true residual
-            for (int32_t c = tid; c < n; c += BS) tk.T[c] += static_cast<double>(tk.d32[c]);
+            #pragma unroll 2
+            for (int32_t c = tid; c < n; c += BS) T[c] += static_cast<double>(d32[c]);
             __syncthreads();
             double o_r = 0.0;
             for (int32_t c = tid; c < n; c += BS) {
-                const double ax = row_dot(mr, c, tk.coef, tk.T, tk.diagB[c] * tk.T[c]);
-                const double rc = tk.srcB[c] - ax;
-                tk.r[c] = rc;
+                const double ax = row_dot(mr, c, coef, T, diagB[c] * T[c]);
+                const double rc = srcB[c] - ax;
+                r[c] = rc;
                 o_r += fabs(rc);
             }
             o_r = bsum1<BS>(o_r);
@@ -193,7 +221,8 @@ __device__ void solve_task(const BatchTask &tk, int32_t n_steps, lf_solve_stats 
         }
         if (tk.snap) {
             double *__restrict__ out = tk.snap + static_cast<int64_t>(step) * n;
-            for (int32_t c = tid; c < n; c += BS) out[c] = tk.T[c];
+            #pragma unroll 2
+            for (int32_t c = tid; c < n; c += BS) out[c] = T[c];
         }
         if (tid == 0) {
             lf_solve_stats st;

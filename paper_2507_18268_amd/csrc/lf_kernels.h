@@ -60,28 +60,35 @@ __device__ __forceinline__ void write_partials(double *__restrict__ part, int32_
 }
 
 // second stage (one workgroup of kFinBlock threads): fixed-order sums.  Thread
-// t adds part[t], part[t + 1024], ... in that order; the loads are issued in
-// groups of 8 so the serial chain waits once per group, not once per load.
+// t adds part[t], part[t + 1024], ... of each slot in that order; the loads of
+// a group (kU per slot, every slot) are issued together, so the serial chain
+// waits once per group: one or two groups at the sizes used here.
 template <int NQ>
 __device__ __forceinline__ void reduce_partials(const double *__restrict__ part, int32_t G, const int (&slot)[NQ],
                                                 double (&out)[NQ]) {
-    constexpr int kU = 8;
+    constexpr int kU = NQ == 1 ? 32 : (NQ == 2 ? 16 : 8);
+    double s[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const double *__restrict__ src = part + static_cast<int64_t>(slot[q]) * G;
-        double s = 0.0;
-        for (int32_t i0 = threadIdx.x; i0 < G; i0 += kU * kFinBlock) {
-            double v[kU];
+    for (int q = 0; q < NQ; ++q) s[q] = 0.0;
+    for (int32_t i0 = threadIdx.x; i0 < G; i0 += kU * kFinBlock) {
+        double v[NQ][kU];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const double *__restrict__ src = part + static_cast<int64_t>(slot[q]) * G;
 #pragma unroll
             for (int j = 0; j < kU; ++j) {
                 const int32_t i = i0 + j * kFinBlock;
-                v[j] = i < G ? src[i] : 0.0;
+                v[q][j] = i < G ? src[i] : 0.0;
             }
-#pragma unroll
-            for (int j = 0; j < kU; ++j) s += v[j];
         }
-        out[q] = s;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+            for (int j = 0; j < kU; ++j) s[q] += v[q][j];
+        }
     }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) out[q] = s[q];
     block_sum<kFinBlock, NQ>(out);
 }
 

@@ -389,8 +389,10 @@ k_amul_dot(SolverParams sp, Lay L, const double *__restrict__ diagB, const doubl
     double acc[1] = {0.0};
     if (c < sp.n) {
         const double pc = p[c];
-        const double qc = layout_dot(L, c, coef, p, diagB[c] * pc);
-        q[c] = qc;
+        // diag and q are touched once per launch: stream them past the caches
+        // that keep p and the coefficients for the neighbouring rows
+        const double qc = layout_dot(L, c, coef, p, __builtin_nontemporal_load(&diagB[c]) * pc);
+        __builtin_nontemporal_store(qc, &q[c]);
         acc[0] = qc * pc;
     }
     const int slots[1] = {kPartPq};
@@ -635,13 +637,14 @@ void carve_problem(Carver &cv, const lf_mesh *m, const lf_solver_opts &o, lf_pro
     auto *coef = cv.take<double>(coef_slots(m, use_bands(m, o)));
     auto *ic = cv.take<double>(B);
     auto *bc = cv.take<double>(B);
+    auto *tb = cv.take<double>(B);
     auto *part = cv.take<double>(static_cast<size_t>(kNumPart) * G);
     auto *state = cv.take<PcgState>(1);
     if (P) {
         P->patch_type = pt; P->patch_value = pv;
         P->T = vec[0]; P->r = vec[1]; P->p = vec[2]; P->q = vec[3]; P->w = vec[4]; P->rD = vec[5];
         P->p2 = vec[6]; P->diag = vec[7]; P->source = vec[8]; P->diagB = vec[9]; P->srcB = vec[10];
-        P->upper = upper; P->coef = coef; P->int_coeff = ic; P->bou_coeff = bc; P->part = part;
+        P->upper = upper; P->coef = coef; P->int_coeff = ic; P->bou_coeff = bc; P->Tb = tb; P->part = part;
         P->state = state;
     }
     if (o.precision == LF_PREC_MIXED) carve_mixed(cv, m, use_bands(m, o), P);

@@ -76,6 +76,7 @@ struct lf_problem {
     double *upper = nullptr;                   // [F] face order (test hook copy)
     double *coef = nullptr;                    // [n_entries] row layout or [n_bands N] bands
     double *int_coeff = nullptr, *bou_coeff = nullptr;
+    double *Tb = nullptr;                      // [B] boundary-face values (output staging)
     double *part = nullptr;                    // [kNumPart][grid]
     lf::PcgState *state = nullptr;
     // mixed precision (FP32 inner solve)

@@ -90,6 +90,7 @@ _SIGS = {
     "lf_problem_reset": (C.c_int32, [C.c_void_p, C.POINTER(lf_patch_bc), C.c_double, C.c_double]),
     "lf_set_T": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
     "lf_get_T": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "lf_get_boundary_T": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
     "lf_step": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
     "lf_assemble": (C.c_int32, [C.c_void_p]),
     "lf_get_matrix": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 7),
@@ -203,6 +204,10 @@ def lf_set_T(h, ptr, on_device):
 
 def lf_get_T(h, ptr, on_device):
     _check(lib().lf_get_T(h, C.c_void_p(ptr), C.c_int32(on_device)), "lf_get_T")
+
+
+def lf_get_boundary_T(h, ptr, on_device):
+    _check(lib().lf_get_boundary_T(h, C.c_void_p(ptr), C.c_int32(on_device)), "lf_get_boundary_T")
 
 
 def lf_step(h, n_steps, stats_array=None):
@@ -412,6 +417,12 @@ class Problem:
         a = np.empty(self.mesh.n_cells, np.float64)
         lf_get_T(self.h, a.ctypes.data, 0)
         return a
+
+    def boundary_T(self):
+        """Field values on the boundary faces (host array, boundary-face order)."""
+        a = np.empty(max(self.mesh.n_bfaces, 1), np.float64)
+        lf_get_boundary_T(self.h, a.ctypes.data, 0)
+        return a[: self.mesh.n_bfaces]
 
     def step(self, n_steps=1, check=True):
         stats = (lf_solve_stats * max(n_steps, 1))()

@@ -29,6 +29,11 @@ step into the snapshot buffer.  One workgroup is far too little for a large
 mesh, so this cuts both their latency and the time the batched slots spend
 waiting for them.
 
+A batched workgroup occupies its compute unit for the whole of its problem,
+so with the direct lane on the server keeps at most batch_max_running batched
+problems in flight (3/4 of the CUs by default) and the direct lane's kernels
+always find free CUs.
+
 The server uses n_slots + direct_workers + 1 streams.  The process needs at
 least that many hardware queues (HIP's GPU_MAX_HW_QUEUES, 4 by default, set
 before the runtime starts): streams that share a queue run in order, so a
@@ -97,9 +102,16 @@ class _Direct:
 
 class Server:
     def __init__(self, mesh_for_side, budget_bytes, n_slots=4, slot_capacity=64, max_steps=10,
-                 tuning=None, direct_min_side=None, direct_workers=4):
+                 tuning=None, direct_min_side=None, direct_workers=4, batch_max_running=None):
         import torch
         self.torch = torch
+        # A batched workgroup holds its CU for a whole problem; with the direct
+        # lane on, at most this many batched problems run at once so that
+        # direct-lane kernels always find free CUs (default: 3/4 of the CUs).
+        n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+        if batch_max_running is None:
+            batch_max_running = (3 * n_cu) // 4 if direct_min_side is not None else n_slots * slot_capacity
+        self.batch_max_running = max(1, int(batch_max_running))
         self.mesh_for_side = mesh_for_side          # side -> mesh description (host arrays)
         self.budget = int(budget_bytes)
         self.used = 0
@@ -239,10 +251,28 @@ class Server:
                                   stream=self.admit_stream)
                 else:
                     P.reset(req.bcs, req.DT, req.dt)
-                P.set_T(req.T0)                      # host copy: done when this returns
+                self._upload_T(P, req.T0)
                 snap = self.torch.empty(req.steps * mesh.n_cells, dtype=self.torch.float64,
                                         device="cuda")
+                self.admit_stream.synchronize()      # T in place before any slot uses it
             self.ready.append(_Live(req, P, snap, snap_bytes, key))
+
+    # Host transfers go through pinned buffers on the lane's own stream: a copy
+    # from or to pageable host memory can wait for work on other streams, i.e.
+    # for whole persistent batched launches.
+    def _upload_T(self, P, T0):
+        torch = self.torch
+        h = torch.from_numpy(np.ascontiguousarray(T0, dtype=np.float64)).pin_memory()
+        d = torch.empty(h.shape, dtype=torch.float64, device="cuda")
+        d.copy_(h, non_blocking=True)
+        P.set_T(d)                                   # device copy on the problem's stream
+
+    def _download(self, dev):
+        torch = self.torch
+        h = torch.empty(dev.shape, dtype=dev.dtype, pin_memory=True)
+        h.copy_(dev, non_blocking=True)
+        torch.cuda.current_stream().synchronize()
+        return h.numpy()
 
     def _anything_live(self):
         return bool(self.ready) or bool(self.direct_live) or any(s is not None for s in self.slot_live)
@@ -252,13 +282,16 @@ class Server:
         for k, live in enumerate(self.slot_live):
             if live is not None or not self.ready:
                 continue
+            room = self.batch_max_running - sum(len(g) for g in self.slot_live if g is not None)
+            if room <= 0:
+                return
             # largest first; one workgroup size and one step count per launch
             self.ready.sort(key=lambda x: -x.problem.mesh.n_cells)
             bs = autotune.block_threads_for(self.ready[0].req.n, self.tuning)
             steps = self.ready[0].req.steps
             group = [x for x in self.ready
                      if autotune.block_threads_for(x.req.n, self.tuning) == bs
-                     and x.req.steps == steps][: self.slot_capacity]
+                     and x.req.steps == steps][: min(self.slot_capacity, room)]
             for x in group:
                 self.ready.remove(x)
             self.batches[k].launch([x.problem for x in group], steps, block_threads=bs,
@@ -281,9 +314,9 @@ class Server:
                 continue
             stats, _ = self.batches[k].stats()
             with self.torch.cuda.stream(self.streams[k]):
-                host = [x.snap.to("cpu", non_blocking=False) for x in live]
+                host = [self._download(x.snap) for x in live]
             for x, st, h in zip(live, stats, host):
-                x.req.snapshots = h.numpy().reshape(x.req.steps, -1)
+                x.req.snapshots = h.reshape(x.req.steps, -1)
                 x.req.stats = st
                 self.idle[x.key].append(x.problem)
                 self._finish(x.req, x.snap_bytes)
@@ -303,14 +336,13 @@ class Server:
                 else:
                     P.reset(req.bcs, req.DT, req.dt)
                 snap = torch.empty((req.steps, d.mesh.n_cells), dtype=torch.float64, device="cuda")
-                P.set_T(req.T0)
+                self._upload_T(P, req.T0)
                 stats = []
                 for s in range(req.steps):
                     st_s, _ = P.step(1)
                     stats += st_s
                     P.get_T(out=snap[s])
-                host = snap.to("cpu")          # synchronous on this stream
-                return host.numpy(), stats, P, None
+                return self._download(snap), stats, P, None
             except Exception as e:             # reported on the request, the server goes on
                 return None, None, P, f"direct lane: {e}"
 

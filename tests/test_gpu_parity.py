@@ -241,3 +241,52 @@ def test_dic_refused_without_two_colours(L):
         L.Problem(m, synth.fixed_x_bcs(), 1e-3, 1e-3, L.make_opts(precond=L.LF_PC_DIC))
     assert e.value.status == L.LF_EINVAL
     m.close()
+
+
+def test_problem_reset_equals_fresh_problem(L, oracle):
+    """lf_problem_reset re-targets a problem (BCs, DT, dt): its steps are bitwise
+    those of a problem created with the new values, in both precision forms."""
+    mesh = synth.box_mesh(12, 10, 9, z_ratio=3.0)
+    m = L.Mesh(mesh)
+    T0 = synth.initial_field(mesh.n_cells, 21)
+    bcs2 = [(FIXED_VALUE, 300.0), (ZERO_GRADIENT, 0.0), (FIXED_VALUE, 450.0), (ZERO_GRADIENT, 0.0),
+            (ZERO_GRADIENT, 0.0), (FIXED_VALUE, 350.0)]
+    for precision in (L.LF_PREC_FP64, L.LF_PREC_MIXED):
+        P = L.Problem(m, synth.fixed_x_bcs(), 1e-3, 1e-3, L.make_opts(precision=precision))
+        P.set_T(T0)
+        P.step(2)
+        P.reset(bcs2, 5e-3, 2e-3)
+        P.set_T(T0)
+        s1, _ = P.step(3)
+        Q = L.Problem(m, bcs2, 5e-3, 2e-3, L.make_opts(precision=precision))
+        Q.set_T(T0)
+        s2, _ = Q.step(3)
+        assert np.array_equal(P.get_T(), Q.get_T()), precision
+        assert [s["n_iter"] for s in s1] == [s["n_iter"] for s in s2]
+        ref, _, _ = oracle.run(mesh, bcs2, 5e-3, 2e-3, 3, T0)
+        assert max_rel(P.get_T(), ref) <= T_TOL * 3
+        with pytest.raises(L.LapfoamError):
+            P.reset(bcs2, -1.0, 2e-3)
+        P.close()
+        Q.close()
+    m.close()
+
+
+def test_boundary_face_values(L):
+    """Boundary-face field: the patch value on fixedValue patches, the cell's T on
+    zeroGradient patches (boundary-face order), before and after a step."""
+    mesh = synth.box_mesh(7, 5, 4, z_ratio=2.0)
+    m = L.Mesh(mesh)
+    P = L.Problem(m, BCS_MIXED, 1e-3, 1e-3)
+    T0 = synth.initial_field(mesh.n_cells, 9)
+    P.set_T(T0)
+    patch_of = np.repeat(np.arange(mesh.n_patches), np.diff(mesh.patch_start))
+    for T in (T0, None):
+        if T is None:
+            P.step(1)
+            T = P.get_T()
+        want = np.array([BCS_MIXED[p][1] if BCS_MIXED[p][0] == FIXED_VALUE else T[c]
+                         for p, c in zip(patch_of, mesh.bface_cell)])
+        assert np.array_equal(P.boundary_T(), want)
+    P.close()
+    m.close()
