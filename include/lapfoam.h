@@ -161,6 +161,11 @@ lf_status lf_mesh_create(const lf_mesh_desc *desc, void *dev_workspace, size_t w
                          void *stream, lf_mesh **out);
 lf_status lf_mesh_destroy(lf_mesh *mesh);   /* NULL-safe; does not free the workspace */
 
+/* The mesh's band form: *n_bands distinct offsets neighbour - owner (0 when the
+ * faces take more than 4), ascending in offsets[4] (may be NULL; unused
+ * entries 0).  Problems on a mesh with n_bands > 0 can use LF_LAYOUT_BANDS. */
+lf_status lf_mesh_bands(const lf_mesh *mesh, int32_t *n_bands, int32_t *offsets);
+
 /* Test hook: copies the device addressing to host arrays (any may be NULL):
  * owner_start[N+1] (faces owned by c are [owner_start[c], owner_start[c+1])),
  * losort[F], losort_start[N+1] (faces whose neighbour is c are

@@ -56,8 +56,10 @@ def measure(side, bs, copies=64, steps=3, seed=0):
     m = L.Mesh(mesh)
     probs = []
     for i in range(copies):
+        # the layout the server gives batched requests: bands on 3-band meshes
+        lay = L.LF_LAYOUT_AUTO if m.n_bands == 3 else L.LF_LAYOUT_ROWS
         P = L.Problem(m, synth.fixed_x_bcs(), 1e-3 * (1 + i % 7), 1e-3,
-                      L.make_opts(precision=L.LF_PREC_MIXED, layout=L.LF_LAYOUT_ROWS))
+                      L.make_opts(precision=L.LF_PREC_MIXED, layout=lay))
         P.set_T(synth.initial_field(mesh.n_cells, seed + i))
         probs.append(P)
     b = L.Batch(copies, steps)
@@ -77,7 +79,7 @@ def measure(side, bs, copies=64, steps=3, seed=0):
     return ms * 1e-3, mesh.n_cells * copies * steps
 
 
-def tune(path=CACHE, copies=64, steps=3, verbose=True):
+def tune(path=CACHE, copies=64, steps=3, verbose=True, out_path=None):
     table = {"block_threads": [], "throughput": [], "when": time.strftime("%Y-%m-%d %H:%M:%S")}
     for lo, hi, side in BUCKETS:
         best, best_rate, rates = None, -1.0, {}
@@ -98,10 +100,11 @@ def tune(path=CACHE, copies=64, steps=3, verbose=True):
         with open(path) as f:
             data = json.load(f)
     data[f"{arch_key()}/mixed"] = table
-    with open(path, "w") as f:
+    with open(out_path or path, "w") as f:
         json.dump(data, f, indent=1)
     return table
 
 
 if __name__ == "__main__":
-    tune()
+    import sys
+    tune(out_path=sys.argv[1] if len(sys.argv) > 1 else None)

@@ -32,6 +32,9 @@ struct BatchTask {
     double *T, *coef, *diagB, *srcB, *r;
     float *coef32, *diag32, *rD32, *r32, *p32, *q32, *d32;
     double *snap;          // [n_steps][n] copies of T after each step, or null
+    // band layout of the problem's coefficients (nb = 3; 0: sliced row layout)
+    const double *band_mag_sf, *band_delta;
+    int32_t nb, band_d[kMaxBands];
     double DT, dt, tol, rel_tol, inner_tol;
     int32_t n, max_iter, max_outer, pad;
 };
@@ -56,13 +59,10 @@ __device__ __forceinline__ void bsum2(double &a0, double &a1) {
 
 // The task's arrays are distinct allocations: taking them into __restrict__
 // locals lets the compiler overlap the loads of several rows of a loop.
-template <int BS>
-__device__ void solve_task(const BatchTask &tk, int32_t n_steps, lf_solve_stats *__restrict__ stats) {
-    const MeshRows mr{tk.soff, tk.scol, tk.sface, tk.rlen};
+template <int BS, class Lay>
+__device__ void solve_task(const BatchTask &tk, const Lay &L, int32_t n_steps, lf_solve_stats *__restrict__ stats) {
     const int32_t n = tk.n;
     const double *__restrict__ V = tk.V;
-    const double *__restrict__ mag_sf = tk.mag_sf;
-    const double *__restrict__ delta = tk.delta;
     const int32_t *__restrict__ bface_start = tk.bface_start;
     const int32_t *__restrict__ bface_list = tk.bface_list;
     const int32_t *__restrict__ bface_patch = tk.bface_patch;
@@ -93,16 +93,9 @@ __device__ void solve_task(const BatchTask &tk, int32_t n_steps, lf_solve_stats 
         // ---- assembly (FP64 + FP32 copy), r0 = b - A x0, normalisation terms
         double a_r = 0.0, a_nf = 0.0;
         for (int32_t c = tid; c < n; c += BS) {
-            int32_t idx = row_base(mr, c);
-            const int32_t len = mr.rlen[c];
-            double lap_diag = 0.0;
-            for (int32_t j = 0; j < len; ++j, idx += kSlice) {
-                const int32_t f = mr.sface[idx];
-                const double lap_upper = delta[f] * (DT * mag_sf[f]);
-                coef[idx] = -lap_upper;
-                coef32[idx] = static_cast<float>(-lap_upper);
-                lap_diag -= lap_upper;
-            }
+            RowCoefs<Lay> rcf;
+            const double lap_diag = assemble_coefs<false>(L, c, DT, coef, nullptr, rcf);
+            store_coef32(L, c, coef, rcf, coef32);
             const double v = V[c];
             const double xc = T[c];
             double db = rdt * v - lap_diag;
@@ -121,12 +114,7 @@ __device__ void solve_task(const BatchTask &tk, int32_t n_steps, lf_solve_stats 
             diag32[c] = static_cast<float>(db);
             rD32[c] = static_cast<float>(1.0 / db);
             double ax = db * xc, sa = db;
-            idx = row_base(mr, c);
-            for (int32_t j = 0; j < len; ++j, idx += kSlice) {
-                const double a = coef[idx];
-                ax += a * T[mr.scol[idx]];
-                sa += a;
-            }
+            row_amul_sum(L, c, coef, rcf, T, ax, sa);
             const double rc = sb - ax;
             r[c] = rc;
             const double pa = sa * x_avg;
@@ -170,7 +158,7 @@ __device__ void solve_task(const BatchTask &tk, int32_t n_steps, lf_solve_stats 
                 double s_pq = 0.0;
                 for (int32_t c = tid; c < n; c += BS) {
                     const float pc = p32[c];
-                    const float qc = row_dot(mr, c, coef32, p32, diag32[c] * pc);
+                    const float qc = layout_dot(L, c, coef32, p32, diag32[c] * pc);
                     q32[c] = qc;
                     s_pq += static_cast<double>(qc) * static_cast<double>(pc);
                 }
@@ -207,7 +195,7 @@ __device__ void solve_task(const BatchTask &tk, int32_t n_steps, lf_solve_stats 
             __syncthreads();
             double o_r = 0.0;
             for (int32_t c = tid; c < n; c += BS) {
-                const double ax = row_dot(mr, c, coef, T, diagB[c] * T[c]);
+                const double ax = layout_dot(L, c, coef, T, diagB[c] * T[c]);
                 const double rc = srcB[c] - ax;
                 r[c] = rc;
                 o_r += fabs(rc);
@@ -261,7 +249,20 @@ __global__ void __launch_bounds__(BS) k_batch(const BatchTask *__restrict__ task
         const int32_t t = s_task;
         __syncthreads();
         if (t >= n_tasks) return;
-        solve_task<BS>(tasks[t], n_steps, stats + static_cast<int64_t>(t) * n_steps);
+        const BatchTask &tk = tasks[t];
+        lf_solve_stats *st = stats + static_cast<int64_t>(t) * n_steps;
+        if (tk.nb == 3) {
+            BandLayout<3> L;
+            L.n = tk.n;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) L.d[k] = tk.band_d[k];
+            L.mag_sf = tk.band_mag_sf;
+            L.delta = tk.band_delta;
+            solve_task<BS>(tk, L, n_steps, st);
+        } else {
+            const SellLayout L{MeshRows{tk.soff, tk.scol, tk.sface, tk.rlen}, tk.mag_sf, tk.delta};
+            solve_task<BS>(tk, L, n_steps, st);
+        }
     }
 }
 
@@ -370,10 +371,6 @@ lf_status lf_batch_launch(lf_batch *b, int32_t n, lf_problem *const *problems, d
             set_error("problem %d: the batched form needs LF_PREC_MIXED with the diagonal preconditioner", i);
             return LF_EINVAL;
         }
-        if (P->banded) {
-            set_error("problem %d: the batched form uses the row layout (create it with LF_LAYOUT_ROWS)", i);
-            return LF_EINVAL;
-        }
         if (P->mesh->device != b->device) { set_error("problem %d lives on another device", i); return LF_EINVAL; }
         const lf_mesh *m = P->mesh;
         BatchTask &t = b->h_tasks[i];
@@ -386,6 +383,15 @@ lf_status lf_batch_launch(lf_batch *b, int32_t n, lf_problem *const *problems, d
         t.coef32 = P->coef32; t.diag32 = P->diag32; t.rD32 = P->rD32; t.r32 = P->r32;
         t.p32 = P->p32; t.q32 = P->q32; t.d32 = P->d32;
         t.snap = snapshots ? snapshots[i] : nullptr;
+        if (P->banded && m->n_bands != 3) {
+            set_error("problem %d: the batched form takes the band layout of 3-band (structured 3-D) meshes "
+                      "only; create it with LF_LAYOUT_ROWS", i);
+            return LF_EINVAL;
+        }
+        t.nb = P->banded ? 3 : 0;
+        for (int k = 0; k < kMaxBands; ++k) t.band_d[k] = k < m->n_bands ? m->band_d[k] : 0;
+        t.band_mag_sf = m->band_mag_sf;
+        t.band_delta = m->band_delta;
         t.DT = P->DT; t.dt = P->dt; t.tol = P->sp.tol; t.rel_tol = P->sp.rel_tol; t.inner_tol = P->sp.inner_tol;
         t.n = m->N; t.max_iter = P->sp.max_iter; t.max_outer = P->sp.max_outer; t.pad = 0;
     }

@@ -220,4 +220,221 @@ __device__ __forceinline__ A layout_dot(const BandLayout<K> &L, int32_t c, const
     return acc;
 }
 
+
+// ---------------------------------------------------------------------------
+// assembly (Listing 1): upper_f = -(delta_f (DT |S_f|)), diag = V/dt - lapDiag
+// with lapDiag the negated sum of the Laplacian face coefficients of the row in
+// face order, source = (T_old/dt) V; fixedValue faces add (DT|S_b|) delta_b to
+// the diagonal and (DT|S_b|)(delta_b T_b) to the source.
+// ---------------------------------------------------------------------------
+template <int W, bool kUpper>
+__device__ __forceinline__ double assemble_row_w(int32_t c, int32_t base, int32_t len, const MeshRows &mr,
+                                                 const double *__restrict__ delta,
+                                                 const double *__restrict__ mag_sf, double DT,
+                                                 double *__restrict__ coef, double *__restrict__ upper) {
+    int32_t f[W], col[W];
+    double dl[W], ms[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        f[j] = mr.sface[base + kSlice * j];
+        col[j] = mr.scol[base + kSlice * j];
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        dl[j] = delta[f[j]];
+        ms[j] = mag_sf[f[j]];
+    }
+    double lap_diag = 0.0;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        if (j < len) {
+            const double lap_upper = dl[j] * (DT * ms[j]);
+            coef[base + kSlice * j] = -lap_upper;
+            lap_diag -= lap_upper;
+            if (kUpper && col[j] > c) upper[f[j]] = -lap_upper;   // owned face: also in face order
+        }
+    }
+    return lap_diag;
+}
+
+template <bool kUpper>
+__device__ __forceinline__ double assemble_row(int32_t c, const MeshRows &mr, const double *__restrict__ delta,
+                                               const double *__restrict__ mag_sf, double DT,
+                                               double *__restrict__ coef, double *__restrict__ upper) {
+    const int32_t s = c >> 6;
+    const int32_t o0 = mr.soff[s];
+    const int32_t base = o0 + (c & (kSlice - 1));
+    const int32_t width = (mr.soff[s + 1] - o0) >> 6;
+    const int32_t len = mr.rlen[c];
+    switch (width) {
+        case 0: return 0.0;
+        case 1: return assemble_row_w<1, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
+        case 2: return assemble_row_w<2, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
+        case 3: return assemble_row_w<3, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
+        case 4: return assemble_row_w<4, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
+        case 5: return assemble_row_w<5, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
+        case 6: return assemble_row_w<6, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
+        case 7: return assemble_row_w<7, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
+        case 8: return assemble_row_w<8, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
+        default: {
+            double lap_diag = 0.0;
+            int32_t idx = base;
+            for (int32_t j = 0; j < len; ++j, idx += kSlice) {
+                const int32_t f = mr.sface[idx];
+                const double lap_upper = delta[f] * (DT * mag_sf[f]);
+                coef[idx] = -lap_upper;
+                lap_diag -= lap_upper;
+                if (kUpper && mr.scol[idx] > c) upper[f] = -lap_upper;
+            }
+            return lap_diag;
+        }
+    }
+}
+
+// row product and row sum in one pass over the row's entries:
+// ax = diag x_c + sum a_j x_j, sa = diag + sum a_j (both in entry order)
+template <int W>
+__device__ __forceinline__ void row_amul_sum_w(int32_t base, int32_t len, const int32_t *__restrict__ scol,
+                                               const double *__restrict__ coef, const double *__restrict__ x,
+                                               double &ax, double &sa) {
+    int32_t col[W];
+    double a[W], xv[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        col[j] = scol[base + kSlice * j];
+        a[j] = coef[base + kSlice * j];
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j) xv[j] = x[col[j]];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        if (j < len) {
+            ax += a[j] * xv[j];
+            sa += a[j];
+        }
+    }
+}
+
+__device__ __forceinline__ void row_amul_sum(const MeshRows &mr, int32_t c, const double *__restrict__ coef,
+                                             const double *__restrict__ x, double &ax, double &sa) {
+    const int32_t s = c >> 6;
+    const int32_t o0 = mr.soff[s];
+    const int32_t base = o0 + (c & (kSlice - 1));
+    const int32_t width = (mr.soff[s + 1] - o0) >> 6;
+    const int32_t len = mr.rlen[c];
+    switch (width) {
+        case 0: return;
+        case 1: row_amul_sum_w<1>(base, len, mr.scol, coef, x, ax, sa); return;
+        case 2: row_amul_sum_w<2>(base, len, mr.scol, coef, x, ax, sa); return;
+        case 3: row_amul_sum_w<3>(base, len, mr.scol, coef, x, ax, sa); return;
+        case 4: row_amul_sum_w<4>(base, len, mr.scol, coef, x, ax, sa); return;
+        case 5: row_amul_sum_w<5>(base, len, mr.scol, coef, x, ax, sa); return;
+        case 6: row_amul_sum_w<6>(base, len, mr.scol, coef, x, ax, sa); return;
+        case 7: row_amul_sum_w<7>(base, len, mr.scol, coef, x, ax, sa); return;
+        case 8: row_amul_sum_w<8>(base, len, mr.scol, coef, x, ax, sa); return;
+        default: {
+            int32_t idx = base;
+            for (int32_t j = 0; j < len; ++j, idx += kSlice) {
+                ax += coef[idx] * x[mr.scol[idx]];
+                sa += coef[idx];
+            }
+        }
+    }
+}
+
+// Layout-generic pieces of the assembly kernel.  RowCoefs keeps what the setup
+// part needs of the row just assembled: the sliced layout re-reads the row it
+// stored (only this thread writes it); the band layout keeps all 2K
+// coefficients of the row in registers, since its lower coefficients live in
+// other rows' slots, written by other threads of the same launch.
+template <class Lay>
+struct RowCoefs {};
+template <int K>
+struct RowCoefs<BandLayout<K>> {
+    double a[2 * K];
+};
+
+template <bool kUpper>
+__device__ __forceinline__ double assemble_coefs(const SellLayout &L, int32_t c, double DT,
+                                                 double *__restrict__ coef, double *__restrict__ upper,
+                                                 RowCoefs<SellLayout> &) {
+    return assemble_row<kUpper>(c, L.mr, L.delta, L.mag_sf, DT, coef, upper);
+}
+
+// Band layout: the row's coefficients from the slot geometry (a slot without a
+// face has zero factors, so its coefficient is zero and it leaves lapDiag
+// unchanged); the row stores its owned faces' coefficients.  The face-order
+// copy is written by a separate face kernel when asked for.
+template <bool kUpper, int K>
+__device__ __forceinline__ double assemble_coefs(const BandLayout<K> &L, int32_t c, double DT,
+                                                 double *__restrict__ coef, double *__restrict__,
+                                                 RowCoefs<BandLayout<K>> &rc) {
+    double dl[2 * K], ms[2 * K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int k = K - 1 - j;
+        const bool ok = c >= L.d[k];
+        const int64_t slot = static_cast<int64_t>(k) * L.n + (ok ? c - L.d[k] : c);
+        const double d0 = L.delta[slot], m0 = L.mag_sf[slot];
+        dl[j] = ok ? d0 : 0.0;
+        ms[j] = ok ? m0 : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t slot = static_cast<int64_t>(k) * L.n + c;
+        dl[K + k] = L.delta[slot];
+        ms[K + k] = L.mag_sf[slot];
+    }
+    double lap_diag = 0.0;
+#pragma unroll
+    for (int j = 0; j < 2 * K; ++j) {
+        const double lap_upper = dl[j] * (DT * ms[j]);
+        rc.a[j] = -lap_upper;
+        lap_diag -= lap_upper;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) coef[static_cast<int64_t>(k) * L.n + c] = rc.a[K + k];
+    return lap_diag;
+}
+
+__device__ __forceinline__ void row_amul_sum(const SellLayout &L, int32_t c, const double *__restrict__ coef,
+                                             const RowCoefs<SellLayout> &, const double *__restrict__ x,
+                                             double &ax, double &sa) {
+    row_amul_sum(L.mr, c, coef, x, ax, sa);
+}
+
+template <int K>
+__device__ __forceinline__ void row_amul_sum(const BandLayout<K> &L, int32_t c, const double *__restrict__,
+                                             const RowCoefs<BandLayout<K>> &rc, const double *__restrict__ x,
+                                             double &ax, double &sa) {
+    double xv[2 * K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int k = K - 1 - j;
+        xv[j] = x[c >= L.d[k] ? c - L.d[k] : c];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) xv[K + k] = x[c < L.n - L.d[k] ? c + L.d[k] : c];
+#pragma unroll
+    for (int j = 0; j < 2 * K; ++j) {
+        ax += rc.a[j] * xv[j];
+        sa += rc.a[j];
+    }
+}
+
+// FP32 copy of the row's stored coefficients (precision form)
+__device__ __forceinline__ void store_coef32(const SellLayout &L, int32_t c, const double *__restrict__ coef,
+                                             const RowCoefs<SellLayout> &, float *__restrict__ coef32) {
+    int32_t idx = row_base(L.mr, c);
+    const int32_t len = L.mr.rlen[c];
+    for (int32_t j = 0; j < len; ++j, idx += kSlice) coef32[idx] = static_cast<float>(coef[idx]);
+}
+
+template <int K>
+__device__ __forceinline__ void store_coef32(const BandLayout<K> &L, int32_t c, const double *__restrict__,
+                                             const RowCoefs<BandLayout<K>> &rc, float *__restrict__ coef32) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) coef32[static_cast<int64_t>(k) * L.n + c] = static_cast<float>(rc.a[K + k]);
+}
+
 }  // namespace lf

@@ -582,6 +582,15 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
     return LF_OK;
 }
 
+lf_status lf_mesh_bands(const lf_mesh *m, int32_t *n_bands, int32_t *offsets) {
+    clear_error();
+    if (!m || !n_bands) { set_error("NULL argument"); return LF_EINVAL; }
+    *n_bands = m->n_bands;
+    if (offsets)
+        for (int32_t k = 0; k < kMaxBands; ++k) offsets[k] = k < m->n_bands ? m->band_d[k] : 0;
+    return LF_OK;
+}
+
 lf_status lf_mesh_destroy(lf_mesh *m) {
     delete m;
     return LF_OK;

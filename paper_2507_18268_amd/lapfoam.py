@@ -80,6 +80,7 @@ _SIGS = {
     "lf_mesh_create": (C.c_int32, [C.POINTER(lf_mesh_desc), C.c_void_p, C.c_size_t, C.c_void_p,
                                    C.POINTER(C.c_void_p)]),
     "lf_mesh_destroy": (C.c_int32, [C.c_void_p]),
+    "lf_mesh_bands": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.c_void_p]),
     "lf_mesh_get_addressing": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 5),
     "lf_problem_workspace_bytes": (C.c_size_t, [C.c_void_p, C.POINTER(lf_solver_opts)]),
     "lf_problem_create": (C.c_int32, [C.c_void_p, C.POINTER(lf_patch_bc), C.c_double, C.c_double,
@@ -163,6 +164,14 @@ def lf_mesh_create(desc, ws_ptr, ws_bytes, stream):
 
 def lf_mesh_destroy(h):
     _check(lib().lf_mesh_destroy(h), "lf_mesh_destroy")
+
+
+def lf_mesh_bands(h):
+    """(n_bands, offsets[4]) of a device mesh."""
+    n = C.c_int32(0)
+    offs = (C.c_int32 * 4)()
+    _check(lib().lf_mesh_bands(h, C.byref(n), offs), "lf_mesh_bands")
+    return n.value, list(offs)
 
 
 def lf_mesh_get_addressing(h, owner_start=None, losort=None, losort_start=None,
@@ -341,6 +350,7 @@ class Mesh:
         assert self.ws.data_ptr() % 256 == 0
         self.stream = _stream_ptr(stream)
         self.h = lf_mesh_create(d, self.ws.data_ptr(), self.ws_bytes, self.stream)
+        self.n_bands, self.band_offsets = lf_mesh_bands(self.h)
         del self._keep   # host arrays were read during the call only
 
     def addressing(self):

@@ -21,13 +21,15 @@ batched-kernel task table:
   re-targeted with lf_problem_reset instead), and the latency (arrival to
   results on the host) is recorded.
 
-Large requests can instead take the direct lane: a few worker threads, each
-with its own stream and its own pool of problems, run a request's steps with
-the multi-kernel solver (the whole GPU's bandwidth for one problem,
-coefficients in the band layout where the mesh allows) and copy T after each
-step into the snapshot buffer.  One workgroup is far too little for a large
-mesh, so this cuts both their latency and the time the batched slots spend
-waiting for them.
+Large requests can instead take the direct lane: up to direct_workers of them
+at a time, each on a stream of its own and with its own pool of problems, are
+advanced one time step per scheduling pass with the multi-kernel solver (the
+whole GPU's bandwidth for one problem, coefficients in the band layout where
+the mesh allows), T being copied after each step into the snapshot buffer.
+One workgroup is far too little for a large mesh, so this cuts both their
+latency and the time the batched slots spend waiting for them.  The lane runs
+on the scheduling thread: a step returns in milliseconds, and no second host
+thread has to share the interpreter with the scheduler.
 
 A batched workgroup occupies its compute unit for the whole of its problem,
 so with the direct lane on the server keeps at most batch_max_running batched
@@ -47,7 +49,6 @@ a request takes depends only on its size.
 """
 import collections
 import time
-from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass
 from typing import Dict, List, Optional
 
@@ -92,17 +93,19 @@ class _Live:
 @dataclass
 class _Direct:
     req: Request
-    mesh: object
-    problem: object                # pooled problem or None (created by the worker)
+    problem: object
+    snap: object                   # device tensor [steps, N]
     snap_bytes: int
     key: tuple
-    worker: int
-    future: object = None
+    worker: int                    # direct-lane slot (its stream)
+    step: int = 0
+    stats: list = None
 
 
 class Server:
     def __init__(self, mesh_for_side, budget_bytes, n_slots=4, slot_capacity=64, max_steps=10,
-                 tuning=None, direct_min_side=None, direct_workers=4, batch_max_running=None):
+                 tuning=None, direct_min_side=None, direct_workers=4, batch_max_running=None,
+                 direct_use_graph=True):
         import torch
         self.torch = torch
         # A batched workgroup holds its CU for a whole problem; with the direct
@@ -124,11 +127,10 @@ class Server:
         self.slot_live: List[Optional[List[_Live]]] = [None] * n_slots
         # requests with side >= direct_min_side take the direct lane (None: never)
         self.direct_min_side = direct_min_side
+        self.direct_use_graph = direct_use_graph
         nd = direct_workers if direct_min_side is not None else 0
         self.direct_streams = [torch.cuda.Stream() for _ in range(nd)]
-        self.direct_exec = [ThreadPoolExecutor(1) for _ in range(nd)]
-        self.direct_load = [0] * nd
-        self.direct_live: List[_Direct] = []
+        self.direct_slot: List[Optional[_Direct]] = [None] * nd
         self.idle: Dict[tuple, List[object]] = collections.defaultdict(list)   # key -> idle problems
         self.meshes: Dict[int, object] = {}          # side -> L.Mesh
         self.mesh_bytes: Dict[int, int] = {}
@@ -148,11 +150,13 @@ class Server:
     def _is_direct(self, req):
         return self.direct_min_side is not None and req.n >= self.direct_min_side
 
-    def _opts(self, direct):
-        # the batched kernel needs the row layout; the direct lane takes the
-        # band layout where the mesh has one
-        layout = L.LF_LAYOUT_AUTO if direct else L.LF_LAYOUT_ROWS
-        return L.make_opts(precision=L.LF_PREC_MIXED, layout=layout)
+    def _opts(self, direct, mesh):
+        # band layout where the mesh has one; the batched kernel takes it for
+        # 3-band (structured 3-D) meshes only
+        banded = mesh.n_bands == 3 or (direct and mesh.n_bands > 0)
+        layout = L.LF_LAYOUT_AUTO if banded else L.LF_LAYOUT_ROWS
+        graph = 1 if (not direct or self.direct_use_graph) else 0
+        return L.make_opts(precision=L.LF_PREC_MIXED, layout=layout, use_graph=graph)
 
     def idle_bytes(self):
         return sum(P.ws_bytes for ps in self.idle.values() for P in ps)
@@ -208,7 +212,12 @@ class Server:
         while self.queue:
             req = self.queue[0]
             direct = self._is_direct(req)
-            worker = int(np.argmin(self.direct_load)) if direct else -1
+            worker = -1
+            if direct:
+                free = [k for k, d in enumerate(self.direct_slot) if d is None]
+                if not free:
+                    return                   # in arrival order: wait for a direct slot
+                worker = free[0]
             key = (req.n, worker)
             if req.n not in self.meshes:
                 # size the mesh from its description before building it
@@ -223,7 +232,7 @@ class Server:
             else:
                 mesh = self.meshes[req.n]
             snap_bytes = 8 * req.steps * mesh.n_cells
-            new_bytes = L.lf_problem_workspace_bytes(mesh.h, self._opts(direct))
+            new_bytes = L.lf_problem_workspace_bytes(mesh.h, self._opts(direct, mesh))
             need = snap_bytes if self.idle.get(key) else snap_bytes + new_bytes
             if self.used + need > self.budget:
                 self._evict(need, req.n)
@@ -239,15 +248,11 @@ class Server:
             req.admitted = self.now()
             P = self.idle[key].pop() if self.idle.get(key) else None
             if direct:
-                d = _Direct(req, mesh, P, snap_bytes, key, worker)
-                self.direct_load[worker] += 1
-                d.future = self.direct_exec[worker].submit(self._run_direct, d)
-                req.launched = self.now()
-                self.direct_live.append(d)
+                self._start_direct(req, mesh, P, snap_bytes, key, worker)
                 continue
             with self.torch.cuda.stream(self.admit_stream):
                 if P is None:
-                    P = L.Problem(mesh, req.bcs, req.DT, req.dt, self._opts(False),
+                    P = L.Problem(mesh, req.bcs, req.DT, req.dt, self._opts(False, mesh),
                                   stream=self.admit_stream)
                 else:
                     P.reset(req.bcs, req.DT, req.dt)
@@ -275,7 +280,8 @@ class Server:
         return h.numpy()
 
     def _anything_live(self):
-        return bool(self.ready) or bool(self.direct_live) or any(s is not None for s in self.slot_live)
+        return bool(self.ready) or any(d is not None for d in self.direct_slot) or \
+            any(s is not None for s in self.slot_live)
 
     # -------------------------------------------------------------- batched lane
     def _launch(self):
@@ -323,58 +329,51 @@ class Server:
             self.slot_live[k] = None
 
     # -------------------------------------------------------------- direct lane
-    def _run_direct(self, d: _Direct):
-        """Worker thread: all steps of one request on this worker's stream."""
+    def _start_direct(self, req, mesh, P, snap_bytes, key, k):
         torch = self.torch
-        req = d.req
-        st = self.direct_streams[d.worker]
-        P = d.problem
+        st = self.direct_streams[k]
         with torch.cuda.stream(st):
-            try:
-                if P is None:
-                    P = L.Problem(d.mesh, req.bcs, req.DT, req.dt, self._opts(True), stream=st)
-                else:
-                    P.reset(req.bcs, req.DT, req.dt)
-                snap = torch.empty((req.steps, d.mesh.n_cells), dtype=torch.float64, device="cuda")
-                self._upload_T(P, req.T0)
-                stats = []
-                for s in range(req.steps):
-                    st_s, _ = P.step(1)
-                    stats += st_s
-                    P.get_T(out=snap[s])
-                return self._download(snap), stats, P, None
-            except Exception as e:             # reported on the request, the server goes on
-                return None, None, P, f"direct lane: {e}"
-
-    def _collect_direct(self):
-        still = []
-        for d in self.direct_live:
-            if not d.future.done():
-                still.append(d)
-                continue
-            host, stats, P, err = d.future.result()
-            req = d.req
-            self.direct_load[d.worker] -= 1
-            if err is None:
-                req.snapshots, req.stats = host, stats
-                self.idle[d.key].append(P)
+            if P is None:
+                P = L.Problem(mesh, req.bcs, req.DT, req.dt, self._opts(True, mesh), stream=st)
             else:
-                req.error = err
-                if P is not None:
-                    self.used -= P.ws_bytes
-                    P.close()
-                else:
-                    self.used -= L.lf_problem_workspace_bytes(d.mesh.h, self._opts(True))
+                P.reset(req.bcs, req.DT, req.dt)
+            self._upload_T(P, req.T0)
+            snap = torch.empty((req.steps, mesh.n_cells), dtype=torch.float64, device="cuda")
+        req.launched = self.now()
+        self.direct_slot[k] = _Direct(req, P, snap, snap_bytes, key, k, 0, [])
+
+    def _step_direct(self):
+        """One time step of every running direct-lane request."""
+        torch = self.torch
+        for k, d in enumerate(self.direct_slot):
+            if d is None:
+                continue
+            req = d.req
+            with torch.cuda.stream(self.direct_streams[k]):
+                st, status = d.problem.step(1, check=False)
+                d.stats += st
+                d.problem.get_T(out=d.snap[d.step])
+                d.step += 1
+                failed = status != L.LF_OK
+                if d.step < req.steps and not failed:
+                    continue
+                host = self._download(d.snap)
+            if failed:
+                req.error = f"direct lane: status {status}"
+            else:
+                req.snapshots, req.stats = host, d.stats
+            self.idle[d.key].append(d.problem)
             self._finish(req, d.snap_bytes)
-        self.direct_live = still
+            self.direct_slot[k] = None
 
     # -------------------------------------------------------------- loop
     def pump(self):
-        """One scheduling pass: collect finished work, admit, launch."""
-        self._collect_direct()
+        """One scheduling pass: collect finished work, admit, launch, and one
+        step of each running direct-lane request."""
         self._collect()
         self._admit()
         self._launch()
+        self._step_direct()
 
     def idle_now(self):
         return not self.queue and not self._anything_live()
@@ -397,13 +396,11 @@ class Server:
             if progress is not None and len(self.finished) >= reported + every:
                 reported = len(self.finished) // every * every
                 progress(len(self.finished), len(pending))
-            time.sleep(poll_s)      # also lets the direct-lane workers take the interpreter lock
+            if poll_s:
+                time.sleep(poll_s)
         return self.finished
 
     def close(self):
-        for ex in self.direct_exec:
-            ex.shutdown(wait=True)
-        self.direct_exec = []
         for key in list(self.idle):
             self._close_idle(key)
         for b in self.batches:

@@ -41,15 +41,17 @@ def _requests(k, seed=0):
     return out
 
 
-def _run(L, reqs, steps, bs=512, n_wg=0, order=None):
+def _run(L, reqs, steps, bs=512, n_wg=0, order=None, layout=None):
     import torch
     order = list(range(len(reqs))) if order is None else order
     meshes, probs, snaps = [], [], []
     for i in order:
         mesh, bcs, DT, dt, T0 = reqs[i]
         m = L.Mesh(mesh)
-        P = L.Problem(m, bcs, DT, dt,
-                      L.make_opts(precision=L.LF_PREC_MIXED, layout=L.LF_LAYOUT_ROWS))
+        lay = L.LF_LAYOUT_ROWS if layout is None else layout
+        if lay == L.LF_LAYOUT_AUTO and m.n_bands not in (0, 3):
+            lay = L.LF_LAYOUT_ROWS                     # the batched band layout is for 3-band meshes
+        P = L.Problem(m, bcs, DT, dt, L.make_opts(precision=L.LF_PREC_MIXED, layout=lay))
         P.set_T(T0)
         meshes.append(m)
         probs.append(P)
@@ -70,10 +72,11 @@ def _run(L, reqs, steps, bs=512, n_wg=0, order=None):
     return res
 
 
-def test_batch_matches_oracle(L, oracle):
+@pytest.mark.parametrize("layout", ["rows", "auto"])
+def test_batch_matches_oracle(L, oracle, layout):
     reqs = _requests(12, seed=1)
     steps = 3
-    res = _run(L, reqs, steps)
+    res = _run(L, reqs, steps, layout=L.LF_LAYOUT_ROWS if layout == "rows" else L.LF_LAYOUT_AUTO)
     for i, (mesh, bcs, DT, dt, T0) in enumerate(reqs):
         snaps, stats, T_final = res[i]
         assert np.array_equal(snaps[-1], T_final)
@@ -94,14 +97,15 @@ def test_batch_matches_oracle(L, oracle):
             T_prev = snaps[s]
 
 
-@pytest.mark.parametrize("bs", [256, 1024])
-def test_alone_equals_in_mix(L, bs):
+@pytest.mark.parametrize("bs,layout", [(256, "rows"), (1024, "rows"), (512, "auto")])
+def test_alone_equals_in_mix(L, bs, layout):
+    lay = L.LF_LAYOUT_ROWS if layout == "rows" else L.LF_LAYOUT_AUTO
     reqs = _requests(10, seed=2)
     steps = 2
-    mix = _run(L, reqs, steps, bs=bs)
-    shuffled = _run(L, reqs, steps, bs=bs, order=[9, 3, 0, 7, 1, 8, 2, 6, 4, 5], n_wg=3)
+    mix = _run(L, reqs, steps, bs=bs, layout=lay)
+    shuffled = _run(L, reqs, steps, bs=bs, order=[9, 3, 0, 7, 1, 8, 2, 6, 4, 5], n_wg=3, layout=lay)
     for i in (0, 4, 9):
-        alone = _run(L, [reqs[i]], steps, bs=bs)[0]
+        alone = _run(L, [reqs[i]], steps, bs=bs, layout=lay)[0]
         assert np.array_equal(alone[0], mix[i][0])
         assert np.array_equal(alone[0], shuffled[i][0])
         assert alone[1] == mix[i][1]
@@ -138,11 +142,14 @@ def test_batch_refuses_bad_input(L):
         b.launch([Pm], 3)                                        # more than max_steps
     with pytest.raises(L.LapfoamError):
         b.launch([Pm], 1, block_threads=128)
-    Pb = L.Problem(m, synth.fixed_x_bcs(), 1e-3, 1e-3,
+    flat = L.Mesh(synth.box_mesh(6, 5, 1))                     # 2 bands: not batched in bands
+    assert flat.n_bands == 2
+    Pb = L.Problem(flat, synth.fixed_x_bcs(), 1e-3, 1e-3,
                    L.make_opts(precision=L.LF_PREC_MIXED, layout=L.LF_LAYOUT_BANDS))
     with pytest.raises(L.LapfoamError):
-        b.launch([Pb], 1)                                        # band layout
+        b.launch([Pb], 1)
     Pb.close()
+    flat.close()
     b.close()
     P.close()
     Pm.close()
