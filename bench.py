@@ -207,7 +207,8 @@ def run_serving(L, torch, args):
     srv = S.Server(mesh_for_side, int(args.serve_budget_gib * 2 ** 30), n_slots=args.serve_slots,
                    slot_capacity=args.serve_capacity, max_steps=10, tuning=tuning,
                    direct_min_side=args.serve_direct_min or None,
-                   direct_workers=args.serve_direct_workers)
+                   direct_workers=args.serve_direct_workers,
+                   direct_use_graph=not args.serve_direct_no_graph)
     for n in sides:
         srv.preload_mesh(n)
     torch.cuda.synchronize()
@@ -260,9 +261,10 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-capacity", type=int, default=64)
-    ap.add_argument("--serve-direct-min", type=int, default=0,
+    ap.add_argument("--serve-direct-min", type=int, default=32,
                     help="requests with at least this cube side run on the multi-kernel solver (0 = never)")
-    ap.add_argument("--serve-direct-workers", type=int, default=4)
+    ap.add_argument("--serve-direct-workers", type=int, default=8)
+    ap.add_argument("--serve-direct-no-graph", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()

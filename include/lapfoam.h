@@ -214,6 +214,16 @@ lf_status lf_get_boundary_T(lf_problem *problem, double *Tb, int32_t on_device);
  * residual stops the call with LF_ENONFINITE after that step's stats. */
 lf_status lf_step(lf_problem *problem, int32_t n_steps, lf_solve_stats *stats);
 
+/* lf_step for n distinct problems at once: each advances n_steps time steps
+ * exactly as lf_step would (same results), their device work interleaved so
+ * that problems on different streams run concurrently; the host waits only
+ * when every problem has work queued.  stats[n * n_steps] (host, problem-major,
+ * may be NULL).  A problem whose step ends with a non-finite residual stops
+ * there (its later stats are not written) while the others go on; the call
+ * then returns LF_ENONFINITE.  For many medium-size problems whose single
+ * solves cannot fill the GPU. */
+lf_status lf_step_many(lf_problem *const *problems, int32_t n, int32_t n_steps, lf_solve_stats *stats);
+
 /* ---- test hooks ------------------------------------------------------------ */
 /* Assemble TEqn from the current T (no solve).  Then lf_get_matrix copies, to
  * host arrays (any may be NULL): diag[N] and source[N] of TEqn, upper[F],

@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <thread>
+#include <vector>
 
 #include "lf_solver.h"
 
@@ -289,32 +291,109 @@ lf_status lf_profile_read(lf_problem *P, int32_t n, double *total_ms, int64_t *l
     return LF_OK;
 }
 
+// One problem's time steps as a sequence of enqueue / advance phases (see
+// SolveCtx); lf_step drives one, lf_step_many several at once.
+struct StepDriver {
+    lf_problem *P = nullptr;
+    lf_solve_stats *stats = nullptr;   // [n_steps] or null
+    int32_t n_steps = 0, step = 0;
+    SolveCtx c;
+    lf_solve_stats cur{};
+    bool active = false, nonfinite = false;
+};
+
+static lf_status begin_step(StepDriver &d) {
+    lf_problem *P = d.P;
+    hipStream_t s = P->stream;
+    std::memset(&d.cur, 0, sizeof(d.cur));
+    prof_lead(P, s);
+    LF_HIP(hipEventRecord(P->ev[0], s));
+    LF_TRY(launch_assemble_setup(P, s));
+    LF_HIP(hipEventRecord(P->ev[1], s));
+    P->assembled = true;
+    return P->opts.precision == LF_PREC_MIXED ? mixed_start(P, d.c) : fp64_start(P, d.c);
+}
+
+// called once P->ev[2] has completed
+static lf_status advance(StepDriver &d) {
+    lf_problem *P = d.P;
+    bool done = false;
+    LF_TRY(P->opts.precision == LF_PREC_MIXED ? mixed_advance(P, d.c, &done, &d.cur)
+                                              : fp64_advance(P, d.c, &done, &d.cur));
+    if (!done) return LF_OK;
+    float a_ms = 0.f, s_ms = 0.f;
+    LF_HIP(hipEventElapsedTime(&a_ms, P->ev[0], P->ev[1]));
+    LF_HIP(hipEventElapsedTime(&s_ms, P->ev[1], P->ev[2]));
+    d.cur.assemble_ms = a_ms;
+    d.cur.solve_ms = s_ms;
+    P->last_iters = d.cur.n_iter;
+    if (d.stats) d.stats[d.step] = d.cur;
+    ++d.step;
+    if (d.cur.nonfinite) {
+        d.nonfinite = true;
+        d.active = false;
+        return LF_OK;
+    }
+    if (d.step < d.n_steps) return begin_step(d);
+    d.active = false;
+    return LF_OK;
+}
+
 lf_status lf_step(lf_problem *P, int32_t n_steps, lf_solve_stats *stats) {
     clear_error();
     if (!P || n_steps < 0) { set_error("bad argument"); return LF_EINVAL; }
-    hipStream_t s = P->stream;
-    for (int32_t i = 0; i < n_steps; ++i) {
-        lf_solve_stats st;
-        std::memset(&st, 0, sizeof(st));
-        prof_lead(P, s);
-        LF_HIP(hipEventRecord(P->ev[0], s));
-        LF_TRY(launch_assemble_setup(P, s));
-        LF_HIP(hipEventRecord(P->ev[1], s));
-        P->assembled = true;
-        if (P->opts.precision == LF_PREC_MIXED) {
-            LF_TRY(solve_mixed(P, &st));
-        } else {
-            LF_TRY(solve_fp64(P, &st));
-        }
-        float a_ms = 0.f, s_ms = 0.f;
-        LF_HIP(hipEventElapsedTime(&a_ms, P->ev[0], P->ev[1]));
-        LF_HIP(hipEventElapsedTime(&s_ms, P->ev[1], P->ev[2]));
-        st.assemble_ms = a_ms;
-        st.solve_ms = s_ms;
-        P->last_iters = st.n_iter;
-        if (stats) stats[i] = st;
-        if (st.nonfinite) { set_error("non-finite residual in step %d", i); return LF_ENONFINITE; }
+    if (n_steps == 0) return LF_OK;
+    StepDriver d;
+    d.P = P;
+    d.stats = stats;
+    d.n_steps = n_steps;
+    d.active = true;
+    LF_TRY(begin_step(d));
+    while (d.active) {
+        LF_HIP(hipEventSynchronize(P->ev[2]));
+        LF_TRY(advance(d));
     }
+    if (d.nonfinite) { set_error("non-finite residual in step %d", d.step - 1); return LF_ENONFINITE; }
+    return LF_OK;
+}
+
+lf_status lf_step_many(lf_problem *const *problems, int32_t n, int32_t n_steps, lf_solve_stats *stats) {
+    clear_error();
+    if (!problems || n < 1 || n_steps < 0) { set_error("bad argument"); return LF_EINVAL; }
+    for (int32_t i = 0; i < n; ++i) {
+        if (!problems[i]) { set_error("problem %d is NULL", i); return LF_EINVAL; }
+        for (int32_t j = 0; j < i; ++j)
+            if (problems[j] == problems[i]) { set_error("problem %d given twice", i); return LF_EINVAL; }
+    }
+    if (n_steps == 0) return LF_OK;
+    std::vector<StepDriver> ds(static_cast<size_t>(n));
+    for (int32_t i = 0; i < n; ++i) {
+        ds[i].P = problems[i];
+        ds[i].stats = stats ? stats + static_cast<int64_t>(i) * n_steps : nullptr;
+        ds[i].n_steps = n_steps;
+        ds[i].active = true;
+        LF_TRY(begin_step(ds[i]));
+    }
+    // advance whichever problem's last enqueued block has finished; every
+    // active problem always has work queued on its stream
+    for (int32_t active = n; active > 0;) {
+        bool progressed = false;
+        for (auto &d : ds) {
+            if (!d.active) continue;
+            const hipError_t q = hipEventQuery(d.P->ev[2]);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) { set_error("hipEventQuery failed: %s", hipGetErrorString(q)); return LF_EDEVICE; }
+            LF_TRY(advance(d));
+            progressed = true;
+            if (!d.active) --active;
+        }
+        if (!progressed) std::this_thread::yield();
+    }
+    for (int32_t i = 0; i < n; ++i)
+        if (ds[i].nonfinite) {
+            set_error("problem %d: non-finite residual in step %d", i, ds[i].step - 1);
+            return LF_ENONFINITE;
+        }
     return LF_OK;
 }
 

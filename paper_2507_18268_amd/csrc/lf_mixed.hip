@@ -279,49 +279,63 @@ static lf_status launch_inner(lf_problem *P, int32_t k) {
     return LF_OK;
 }
 
-lf_status solve_mixed(lf_problem *P, lf_solve_stats *out) {
+// block of k inner iterations, then the state copy and ev[2]
+static lf_status mixed_block(lf_problem *P, SolveCtx &c) {
+    hipStream_t s = P->stream;
+    prof_lead(P, s);
+    LF_TRY(launch_inner(P, c.k));
+    c.launched += c.k;
+    LF_HIP(hipMemcpyAsync(P->h_state, P->state, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    LF_HIP(hipEventRecord(P->ev[2], s));
+    return LF_OK;
+}
+
+lf_status mixed_start(lf_problem *P, SolveCtx &c) {
     hipStream_t s = P->stream;
     prof_lead(P, s);
     launch_fin<kFinStart>(P, s);      // normFactor, res0 and the initial decision (shared with FP64)
     launch_pass_start(P, s);
     LF_HIP(hipGetLastError());
-    const int32_t fixed_k = P->prof_on ? 1 : P->opts.iters_per_check;
-    int32_t k = fixed_k > 0 ? fixed_k : std::max<int32_t>(2, P->last_inner > 0 ? P->last_inner : 8);
-    int32_t launched = 0;
-    for (;;) {
-        prof_lead(P, s);
-        LF_TRY(launch_inner(P, k));
-        launched += k;
-        LF_HIP(hipMemcpyAsync(P->h_state, P->state, sizeof(PcgState), hipMemcpyDeviceToHost, s));
-        LF_HIP(hipEventRecord(P->ev[2], s));
-        LF_HIP(hipEventSynchronize(P->ev[2]));
-        prof_flush(P);
-        const PcgState &h = *P->h_state;
-        if (h.done) break;
-        if (launched > 4 * (P->sp.max_iter + 8) + 64 * P->sp.max_outer) {
-            set_error("mixed solver never reached done after %d launched inner iterations", launched);
-            return LF_ESTATE;
-        }
-        if (!h.inner_done) {
-            if (fixed_k <= 0) k = std::max<int32_t>(2, k / 2);
-            continue;
-        }
+    c.fixed_k = P->prof_on ? 1 : P->opts.iters_per_check;
+    c.k = c.fixed_k > 0 ? c.fixed_k : std::max<int32_t>(2, P->last_inner > 0 ? P->last_inner : 8);
+    c.launched = 0;
+    return mixed_block(P, c);
+}
+
+lf_status mixed_advance(lf_problem *P, SolveCtx &c, bool *finished, lf_solve_stats *out) {
+    hipStream_t s = P->stream;
+    prof_flush(P);
+    *finished = false;
+    const PcgState &h = *P->h_state;
+    if (h.done) {
+        out->initial_residual = h.res0;
+        out->final_residual = h.res;
+        out->n_iter = h.n_iter;
+        out->converged = h.converged;
+        out->singular = 0;
+        out->nonfinite = h.nonfinite;
+        out->n_outer = h.n_outer;
+        *finished = true;
+        return LF_OK;
+    }
+    if (c.launched > 4 * (P->sp.max_iter + 8) + 64 * P->sp.max_outer) {
+        set_error("mixed solver never reached done after %d launched inner iterations", c.launched);
+        return LF_ESTATE;
+    }
+    if (!h.inner_done) {
+        if (c.fixed_k <= 0) c.k = std::max<int32_t>(2, c.k / 2);
+    } else {
         // pass finished: correct, check, start the next pass (no-ops once done)
-        if (fixed_k <= 0) { k = std::max<int32_t>(2, h.inner_iter); P->last_inner = h.inner_iter; }
+        if (c.fixed_k <= 0) {
+            c.k = std::max<int32_t>(2, h.inner_iter);
+            P->last_inner = h.inner_iter;
+        }
         prof_lead(P, s);
         launch_pass_end(P, s);
         launch_pass_start(P, s);
         LF_HIP(hipGetLastError());
     }
-    const PcgState &h = *P->h_state;
-    out->initial_residual = h.res0;
-    out->final_residual = h.res;
-    out->n_iter = h.n_iter;
-    out->converged = h.converged;
-    out->singular = 0;
-    out->nonfinite = h.nonfinite;
-    out->n_outer = h.n_outer;
-    return LF_OK;
+    return mixed_block(P, c);
 }
 
 }  // namespace lf

@@ -596,44 +596,59 @@ static lf_status launch_iterations(lf_problem *P, int32_t k) {
     return LF_OK;
 }
 
-lf_status solve_fp64(lf_problem *P, lf_solve_stats *out) {
+// block of k iterations, then the state copy and ev[2]
+static lf_status fp64_block(lf_problem *P, SolveCtx &c) {
+    hipStream_t s = P->stream;
+    c.k = std::min<int32_t>(c.k, std::max<int32_t>(1, P->sp.max_iter + 1 - c.launched));
+    prof_lead(P, s);
+    LF_TRY(launch_iterations(P, c.k));
+    c.launched += c.k;
+    LF_HIP(hipMemcpyAsync(P->h_state, P->state, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    LF_HIP(hipEventRecord(P->ev[2], s));
+    return LF_OK;
+}
+
+lf_status fp64_start(lf_problem *P, SolveCtx &c) {
     hipStream_t s = P->stream;
     prof_lead(P, s);
     LF_TRY(launch_setup(P, s));
-    const int32_t fixed_k = P->prof_on ? 1 : P->opts.iters_per_check;
-    int32_t k = fixed_k > 0 ? fixed_k : std::max<int32_t>(1, P->last_iters > 0 ? P->last_iters + 1 : 8);
-    int32_t launched = 0;
-    for (;;) {
-        k = std::min<int32_t>(k, std::max<int32_t>(1, P->sp.max_iter + 1 - launched));
-        prof_lead(P, s);
-        LF_TRY(launch_iterations(P, k));
-        launched += k;
-        LF_HIP(hipMemcpyAsync(P->h_state, P->state, sizeof(PcgState), hipMemcpyDeviceToHost, s));
-        LF_HIP(hipEventRecord(P->ev[2], s));
-        LF_HIP(hipEventSynchronize(P->ev[2]));
-        prof_flush(P);
-        if (P->h_state->done) break;
-        if (launched > P->sp.max_iter + P->sp.min_iter + 8) {
-            set_error("solver state never reached done after %d iterations", launched);
-            return LF_ESTATE;
-        }
-        if (fixed_k <= 0) k = std::max<int32_t>(2, k / 2);
-    }
-    prof_lead(P, s);
-    LF_LAUNCH(P, LF_K_COMMIT, s, k_commit, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->T, P->p, P->state);
-    LF_HIP(hipGetLastError());
-    LF_HIP(hipEventRecord(P->ev[2], s));
-    LF_HIP(hipEventSynchronize(P->ev[2]));
+    c.fixed_k = P->prof_on ? 1 : P->opts.iters_per_check;
+    c.k = c.fixed_k > 0 ? c.fixed_k : std::max<int32_t>(1, P->last_iters > 0 ? P->last_iters + 1 : 8);
+    c.launched = 0;
+    c.stage = 0;
+    return fp64_block(P, c);
+}
+
+lf_status fp64_advance(lf_problem *P, SolveCtx &c, bool *finished, lf_solve_stats *out) {
+    hipStream_t s = P->stream;
     prof_flush(P);
-    const PcgState &h = *P->h_state;
-    out->initial_residual = h.res0;
-    out->final_residual = h.res;
-    out->n_iter = h.n_iter;
-    out->converged = h.converged;
-    out->singular = h.singular;
-    out->nonfinite = h.nonfinite;
-    out->n_outer = 1;
-    return LF_OK;
+    *finished = false;
+    if (c.stage == 1) {
+        const PcgState &h = *P->h_state;
+        out->initial_residual = h.res0;
+        out->final_residual = h.res;
+        out->n_iter = h.n_iter;
+        out->converged = h.converged;
+        out->singular = h.singular;
+        out->nonfinite = h.nonfinite;
+        out->n_outer = 1;
+        *finished = true;
+        return LF_OK;
+    }
+    if (P->h_state->done) {
+        prof_lead(P, s);
+        LF_LAUNCH(P, LF_K_COMMIT, s, k_commit, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->T, P->p, P->state);
+        LF_HIP(hipGetLastError());
+        LF_HIP(hipEventRecord(P->ev[2], s));
+        c.stage = 1;
+        return LF_OK;
+    }
+    if (c.launched > P->sp.max_iter + P->sp.min_iter + 8) {
+        set_error("solver state never reached done after %d iterations", c.launched);
+        return LF_ESTATE;
+    }
+    if (c.fixed_k <= 0) c.k = std::max<int32_t>(2, c.k / 2);
+    return fp64_block(P, c);
 }
 
 lf_status launch_amul_hook(lf_problem *P, const double *x, double *y) {

@@ -64,8 +64,22 @@ void carve_problem(Carver &cv, const lf_mesh *m, const lf_solver_opts &o, lf_pro
 void carve_mixed(Carver &cv, const lf_mesh *m, bool banded, lf_problem *P);
 lf_status launch_assemble(lf_problem *P, bool full, hipStream_t s);
 lf_status launch_assemble_setup(lf_problem *P, hipStream_t s);
-lf_status solve_fp64(lf_problem *P, lf_solve_stats *out);
-lf_status solve_mixed(lf_problem *P, lf_solve_stats *out);
+// A solve is driven in two halves so that one host loop can drive several
+// problems on their own streams: *_start enqueues the set-up and the first
+// block of iterations, followed by an async copy of the solver state and
+// P->ev[2]; once that event has completed, *_advance reads the state and
+// either enqueues the next block (again ending with the copy and ev[2]) or
+// reports the solve finished, its stats in *out.
+struct SolveCtx {
+    int32_t fixed_k = 0;   // iterations per block when fixed (>0), else adaptive
+    int32_t k = 0;         // iterations of the next block
+    int32_t launched = 0;  // iterations enqueued so far
+    int32_t stage = 0;     // FP64: 0 iterating, 1 committing
+};
+lf_status fp64_start(lf_problem *P, SolveCtx &c);
+lf_status fp64_advance(lf_problem *P, SolveCtx &c, bool *finished, lf_solve_stats *out);
+lf_status mixed_start(lf_problem *P, SolveCtx &c);
+lf_status mixed_advance(lf_problem *P, SolveCtx &c, bool *finished, lf_solve_stats *out);
 lf_status launch_amul_hook(lf_problem *P, const double *x, double *y);
 lf_status check_finite_device(lf_problem *P, const double *T, bool *ok);
 

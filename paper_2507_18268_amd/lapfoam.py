@@ -93,6 +93,7 @@ _SIGS = {
     "lf_get_T": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
     "lf_get_boundary_T": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
     "lf_step": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "lf_step_many": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     "lf_assemble": (C.c_int32, [C.c_void_p]),
     "lf_get_matrix": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 7),
     "lf_amul": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -213,6 +214,22 @@ def lf_set_T(h, ptr, on_device):
 
 def lf_get_T(h, ptr, on_device):
     _check(lib().lf_get_T(h, C.c_void_p(ptr), C.c_int32(on_device)), "lf_get_T")
+
+
+def lf_step_many(handles, n_steps, stats_array=None):
+    arr = (C.c_void_p * len(handles))(*handles)
+    return lib().lf_step_many(arr, C.c_int32(len(handles)), C.c_int32(n_steps), stats_array)
+
+
+def step_many(problems, n_steps=1, check=True):
+    """Advance several problems together (lf_step_many); returns (per-problem
+    lists of per-step stats, status)."""
+    k = len(problems)
+    stats = (lf_solve_stats * max(k * n_steps, 1))()
+    status = lf_step_many([P.h for P in problems], n_steps, stats)
+    if check:
+        _check(status, "lf_step_many")
+    return [[stats[i * n_steps + s].as_dict() for s in range(n_steps)] for i in range(k)], status
 
 
 def lf_get_boundary_T(h, ptr, on_device):

@@ -25,7 +25,8 @@ Large requests can instead take the direct lane: up to direct_workers of them
 at a time, each on a stream of its own and with its own pool of problems, are
 advanced one time step per scheduling pass with the multi-kernel solver (the
 whole GPU's bandwidth for one problem, coefficients in the band layout where
-the mesh allows), T being copied after each step into the snapshot buffer.
+the mesh allows; lf_step_many interleaves their solves on their streams), T
+being copied after each step into the snapshot buffer.
 One workgroup is far too little for a large mesh, so this cuts both their
 latency and the time the batched slots spend waiting for them.  The lane runs
 on the scheduling thread: a step returns in milliseconds, and no second host
@@ -343,23 +344,27 @@ class Server:
         self.direct_slot[k] = _Direct(req, P, snap, snap_bytes, key, k, 0, [])
 
     def _step_direct(self):
-        """One time step of every running direct-lane request."""
+        """One time step of every running direct-lane request, advanced together
+        (lf_step_many: their solves interleave on their own streams)."""
         torch = self.torch
-        for k, d in enumerate(self.direct_slot):
-            if d is None:
-                continue
+        live = [(k, d) for k, d in enumerate(self.direct_slot) if d is not None]
+        if not live:
+            return
+        stats, status = L.step_many([d.problem for _, d in live], 1, check=False)
+        if status not in (L.LF_OK, L.LF_ENONFINITE):
+            raise L.LapfoamError(status, "lf_step_many", L.lib().lf_last_error().decode())
+        for (k, d), st in zip(live, stats):
             req = d.req
+            failed = st[0]["nonfinite"] != 0
             with torch.cuda.stream(self.direct_streams[k]):
-                st, status = d.problem.step(1, check=False)
-                d.stats += st
                 d.problem.get_T(out=d.snap[d.step])
+                d.stats += st
                 d.step += 1
-                failed = status != L.LF_OK
                 if d.step < req.steps and not failed:
                     continue
                 host = self._download(d.snap)
             if failed:
-                req.error = f"direct lane: status {status}"
+                req.error = "direct lane: non-finite residual"
             else:
                 req.snapshots, req.stats = host, d.stats
             self.idle[d.key].append(d.problem)

@@ -290,3 +290,43 @@ def test_boundary_face_values(L):
         assert np.array_equal(P.boundary_T(), want)
     P.close()
     m.close()
+
+
+def test_step_many_equals_single_steps(L):
+    """lf_step_many interleaves the solves of several problems (own streams,
+    different meshes, layouts and precision forms): each result is bitwise the
+    one lf_step gives for that problem alone."""
+    import torch
+    cases = [
+        (synth.box_mesh(20, 17, 13, z_ratio=4.0), dict()),
+        (synth.renumber(synth.box_mesh(11, 9, 8), synth.random_permutation(792, 3)), dict()),
+        (synth.box_mesh(24, 24, 24), dict(precision=L.LF_PREC_MIXED)),
+        (synth.box_mesh(16, 12, 10), dict(precision=L.LF_PREC_MIXED, layout=L.LF_LAYOUT_ROWS)),
+    ]
+    steps = 3
+
+    def make():
+        out = []
+        for i, (mesh, o) in enumerate(cases):
+            m = L.Mesh(mesh)
+            P = L.Problem(m, BCS_MIXED, 2e-3, 1e-3, L.make_opts(**o), stream=torch.cuda.Stream())
+            P.set_T(synth.initial_field(mesh.n_cells, 40 + i))
+            out.append((m, P))
+        return out
+
+    alone = make()
+    ref = []
+    for m, P in alone:
+        st, _ = P.step(steps)
+        ref.append((P.get_T(), [s["n_iter"] for s in st]))
+    together = make()
+    stats, status = L.step_many([P for _, P in together], steps)
+    assert status == L.LF_OK
+    for (m, P), (T_ref, it_ref), st in zip(together, ref, stats):
+        assert np.array_equal(P.get_T(), T_ref)
+        assert [s["n_iter"] for s in st] == it_ref
+    with pytest.raises(L.LapfoamError):
+        L.step_many([together[0][1], together[0][1]], 1)        # the same problem twice
+    for m, P in alone + together:
+        P.close()
+        m.close()
