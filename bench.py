@@ -170,6 +170,42 @@ def run_mixed(L, torch, p, mesh, prob64, T0, args):
             "speedup_vs_fp64_time_to_tol": None}
 
 
+def run_config_leg(L, torch, name, steps, warmup=1):
+    """Another config of the workload family, timed like the main line: `steps`
+    time steps from T0 after `warmup` steps, wall clock around the whole steps."""
+    import synth
+    t = time.perf_counter()
+    p = synth.build_config(name, steps=steps)
+    N = p.mesh.n_cells
+    log(f"[bench] {name}: {N} cells, mesh generated in {time.perf_counter() - t:.1f} s")
+    precond = L.LF_PC_DIC if p.precond == "dic" else L.LF_PC_DIAGONAL
+    precision = L.LF_PREC_MIXED if p.precision == "mixed" else L.LF_PREC_FP64
+    opts = L.make_opts(tol=synth.TOL, rel_tol=synth.REL_TOL, max_iter=synth.MAX_ITER,
+                       precond=precond, precision=precision)
+    mesh = L.Mesh(p.mesh)
+    prob = L.Problem(mesh, p.bcs, p.DT, p.dt, opts)
+    T0 = torch.from_numpy(p.T0).cuda()
+    prob.set_T(T0)
+    if warmup > 0:
+        prob.step(warmup)
+    prob.set_T(T0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats, _ = prob.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    iters = sum(s["n_iter"] for s in stats)
+    out = {"n_cells": N, "steps": steps, "precond": p.precond, "precision": p.precision,
+           "layout": "bands" if prob.layout() == L.LF_LAYOUT_BANDS else "rows",
+           "ms_per_step": wall * 1e3 / steps, "iters_per_step_mean": iters / steps,
+           "cell_iters_per_s": N * iters / wall, "us_per_iteration": wall * 1e6 / max(iters, 1),
+           "all_converged": all(s["converged"] == 1 for s in stats)}
+    prob.close()
+    mesh.close()
+    log(f"[bench] {name}: {out['ms_per_step']:.3f} ms/step, {out['iters_per_step_mean']:.1f} iterations")
+    return out
+
+
 def run_serving(L, torch, args):
     """512 parametric requests (side log-uniform in [16, 96], DT log-uniform in
     [1e-4, 1e-2], dt = 1e-3, 10 steps, snapshots of every step returned):
@@ -255,6 +291,7 @@ def main():
     ap.add_argument("--accuracy-steps", type=int, default=20)
     ap.add_argument("--inner-tol", type=float, default=0.0, help="mixed: inner reduction (0 = default)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-extra-configs", action="store_true")
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--serve-sweep", action="store_true", help="Poisson rates 0.25x..4x of saturated")
     ap.add_argument("--serve-requests", type=int, default=512)
@@ -386,6 +423,14 @@ def main():
     if not args.no_mixed and precision == L.LF_PREC_FP64 and precond == L.LF_PC_DIAGONAL:
         out["mixed"] = run_mixed(L, torch, p, mesh, prob, T0, args)
         out["mixed"]["speedup_vs_fp64_time_to_tol"] = out["ms_per_step"] / out["mixed"]["ms_per_step"]
+
+    if not args.no_extra_configs:
+        # the other configs of the workload family (parity cases elsewhere),
+        # timed the same way: 32^3 (launch-latency bound), 192^3 permuted (row
+        # layout, random-neighbour gathers), 256^3 red-black DIC
+        out["other_configs"] = {name: run_config_leg(L, torch, name, steps)
+                                for name, steps in (("plain_32", 20), ("permuted_192", 30),
+                                                    ("graded_256_dic", 50))}
 
     if not args.no_serve:
         out["serving"] = run_serving(L, torch, args)

@@ -21,7 +21,10 @@ namespace lf {
 // are at hand): wA = A x0, r = b - wA, the row sum of A, the row's terms
 // |wA - pA| + |b - pA| of the normalisation factor (pA = row sum * mean(x0),
 // the mean taken beforehand), and with the diagonal preconditioner
-// rD = 1/diag and w.r; partial sums of |r|, those terms and w.r.
+// rD = 1/diag, w.r and the first direction p = w; partial sums of |r|, those
+// terms and w.r.  kMixed (precision form) instead writes the FP32 copies of
+// the matrix and starts the first refinement pass: r32 = r rounded, d = 0 and
+// the partial sums of |r32| and w32.r32.
 template <class Lay, bool kFull, bool kSetup, bool kMixed>
 __global__ void __launch_bounds__(kCellBlock)
 k_assemble(SolverParams sp, double rdt, double DT, Lay L, const int32_t *__restrict__ bface_start,
@@ -34,7 +37,7 @@ k_assemble(SolverParams sp, double rdt, double DT, Lay L, const int32_t *__restr
            double *__restrict__ bou_coeff, int32_t diag_pc, double *__restrict__ r, double *__restrict__ rD,
            double *__restrict__ part, const PcgState *__restrict__ st, float *__restrict__ coef32,
            float *__restrict__ diag32, float *__restrict__ rD32, float *__restrict__ r32,
-           float *__restrict__ d32) {
+           float *__restrict__ d32, double *__restrict__ p) {
     const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const double x_avg = kSetup ? st->x_avg : 0.0;
@@ -85,6 +88,7 @@ k_assemble(SolverParams sp, double rdt, double DT, Lay L, const int32_t *__restr
                 rD[c] = rd;
                 const double wc = rd * rc;
                 acc[2] = wc * rc;
+                p[c] = wc;                  // first search direction p = w (used only if the solve iterates)
             }
             if (kMixed) {
                 // start of the first refinement pass: r32 = r rounded, d = 0
@@ -447,7 +451,7 @@ static void launch_assemble_t(lf_problem *P, hipStream_t s) {
                   m->bface_start, m->bface_list, m->bface_patch, m->bmag_sf, m->bdelta, P->patch_type,
                   P->patch_value, m->V, P->T, P->coef, P->upper, P->diag, P->source, P->diagB, P->srcB,
                   P->int_coeff, P->bou_coeff, diag_pc ? 1 : 0, P->r, P->rD, P->part, P->state, P->coef32,
-                  P->diag32, P->rD32, P->r32, P->d32);
+                  P->diag32, P->rD32, P->r32, P->d32, P->p);
     });
     if (kFull && P->banded && m->F > 0) {
         BandOffsets bo{};
@@ -505,7 +509,9 @@ static lf_status launch_setup(lf_problem *P, hipStream_t s) {
                   mesh_rows(m), P->coef, P->rD, P->r, P->w, P->part, P->state);
     }
     launch_fin<kFinStart>(P, s);
-    launch_direction(P, s);
+    // first direction p = w: with the diagonal preconditioner the assembly
+    // kernel has written it already
+    if (!diag_pc) launch_direction(P, s);
     LF_HIP(hipGetLastError());
     return LF_OK;
 }
