@@ -104,3 +104,72 @@ def test_host_only_entry_points_without_gpu():
         L.lf_mesh_create(d, 0, nbytes, 0)
     assert e.value.status == L.LF_EMESH
     assert "owner" in L.lf_last_error()
+
+
+def _desc(L, m, keep):
+    import numpy as np
+    d = L.lf_mesh_desc()
+    arrs = dict(owner=m["owner"], neighbour=m["neighbour"], cell_volume=m["cell_volume"],
+                cell_centre=m["cell_centre"], face_area=m["face_area"], patch_start=m["patch_start"],
+                bface_cell=m["bface_cell"], bface_area=m["bface_area"], bface_centre=m["bface_centre"])
+    for k, v in arrs.items():
+        v = np.ascontiguousarray(v)
+        keep.append(v)
+        setattr(d, k, v.ctypes.data)
+    d.n_cells, d.n_faces, d.n_patches = m["n_cells"], m["owner"].size, m["patch_start"].size - 1
+    return d
+
+
+def _box_dict(m):
+    return dict(owner=m.owner.astype("int32"), neighbour=m.neighbour.astype("int32"),
+                cell_volume=m.cell_volume, cell_centre=m.cell_centre, face_area=m.face_area,
+                patch_start=m.patch_start.astype("int32"), bface_cell=m.bface_cell.astype("int32"),
+                bface_area=m.bface_area, bface_centre=m.bface_centre, n_cells=m.n_cells)
+
+
+@pytest.mark.parametrize("defect", ["unsorted", "non_orthogonal", "inward_boundary", "bad_index",
+                                    "zero_volume"])
+def test_mesh_validation_rejects(defect):
+    """Host validation (no device call is made before it fails)."""
+    from paper_2507_18268_amd import lapfoam as L
+    import synth
+    m = _box_dict(synth.box_mesh(4, 3, 3))
+    m = {k: (v.copy() if hasattr(v, "copy") else v) for k, v in m.items()}
+    if defect == "unsorted":
+        m["owner"][[0, 1]] = m["owner"][[1, 0]]
+        m["neighbour"][[0, 1]] = m["neighbour"][[1, 0]]
+        m["face_area"][[0, 1]] = m["face_area"][[1, 0]]
+    elif defect == "non_orthogonal":
+        m["face_area"][5] = m["face_area"][5] + [0.0, 0.3 * abs(m["face_area"][5]).max(), 0.0]
+    elif defect == "inward_boundary":
+        m["bface_area"][2] = -m["bface_area"][2]
+    elif defect == "bad_index":
+        m["neighbour"][-1] = m["n_cells"]
+    elif defect == "zero_volume":
+        m["cell_volume"][7] = 0.0
+    keep = []
+    d = _desc(L, m, keep)
+    with pytest.raises(L.LapfoamError) as e:
+        L.lf_mesh_create(d, 0, 1 << 20, 0)
+    assert e.value.status == L.LF_EMESH, L.lf_last_error()
+
+
+def test_mesh_rows_longer_than_255_are_refused():
+    """A cell with 256 faces exceeds the row layout's uint8 row length: LF_EMESH
+    (and a zero workspace size), before any device call."""
+    from paper_2507_18268_amd import lapfoam as L
+    import numpy as np
+    k = 256
+    ang = np.linspace(0.0, np.pi, k + 2)[1:-1]
+    dirs = np.stack([np.cos(ang), np.sin(ang), np.zeros(k)], axis=1)     # all distinct, in one half-plane
+    centres = np.concatenate([np.zeros((1, 3)), dirs], axis=0)
+    m = dict(owner=np.zeros(k, np.int32), neighbour=np.arange(1, k + 1, dtype=np.int32),
+             cell_volume=np.full(k + 1, 1e-3), cell_centre=centres, face_area=0.01 * dirs,
+             patch_start=np.zeros(1, np.int32), bface_cell=np.zeros(0, np.int32),
+             bface_area=np.zeros((0, 3)), bface_centre=np.zeros((0, 3)), n_cells=k + 1)
+    keep = []
+    d = _desc(L, m, keep)
+    assert L.lf_mesh_workspace_bytes(d) == 0
+    with pytest.raises(L.LapfoamError) as e:
+        L.lf_mesh_create(d, 0, 1 << 20, 0)
+    assert e.value.status == L.LF_EMESH and "255" in L.lf_last_error()
