@@ -349,8 +349,9 @@ def main():
     T0 = torch.from_numpy(p.T0).cuda()
     torch.cuda.synchronize()
     layout_name = "bands" if prob.layout() == L.LF_LAYOUT_BANDS else "rows"
+    walk = prob.amul_walk()
     log(f"[bench] device mesh + problem ready in {time.perf_counter() - t:.1f} s "
-        f"(workspaces {mesh.ws_bytes / 2**30:.2f} + {prob.ws_bytes / 2**30:.2f} GiB, {layout_name} layout)")
+        f"(workspaces {mesh.ws_bytes / 2**30:.2f} + {prob.ws_bytes / 2**30:.2f} GiB, {layout_name} layout{', row-walk Amul' if walk else ''})")
 
     prob.set_T(T0)
     if args.warmup > 0:
@@ -379,7 +380,8 @@ def main():
         "config": {"workload": f"{args.config}: {round(N ** (1 / 3))}^3 box, z expansion ratio "
                                f"{synth.CONFIGS[args.config]['z_ratio']}, DT={p.DT}, dt={p.dt}, "
                                f"implicit Euler, PCG {p.precond}, tol {synth.TOL}",
-                   "n_cells": N, "n_faces": F, "precision": p.precision, "layout": layout_name},
+                   "n_cells": N, "n_faces": F, "precision": p.precision, "layout": layout_name,
+                   "amul": "row walk" if walk else "one row per thread"},
         "iters_per_step_mean": total_iters / len(stats),
         "solver_only_cell_iters_per_s": N * total_iters / solve_s if solve_s > 0 else None,
         "assemble_ms_mean": sum(s["assemble_ms"] for s in stats) / len(stats),
@@ -400,7 +402,8 @@ def main():
         ka = kernels["amul_dot"]
         per_launch = amul_bytes(N, F)
         achieved = per_launch / (ka["avg_us"] * 1e-6) / 1e9
-        roof = {"kernel": "k_amul_dot (q = A p with p.q partials)", "bound": "hbm",
+        kname = "k_amul_dot_walk" if walk else "k_amul_dot"
+        roof = {"kernel": f"{kname} (q = A p with p.q partials)", "bound": "hbm",
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                 "algorithmic_bytes_per_launch": per_launch,
@@ -413,7 +416,8 @@ def main():
         if os.path.exists(TRAFFIC_FILE):
             with open(TRAFFIC_FILE) as f:
                 tr = json.load(f)
-            if tr.get("source_sha256") == kernel_source_hash() and tr.get("n_cells") == N:
+            if (tr.get("source_sha256") == kernel_source_hash() and tr.get("n_cells") == N
+                    and tr.get("kernel") == kname):
                 roof["traffic"] = tr["hbm_bytes_per_launch"]
         out["roofline"] = roof
         # whole-iteration view: the three kernels of one PCG iteration

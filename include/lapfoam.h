@@ -71,6 +71,14 @@ typedef int32_t lf_status;
                               structured numbering); each coefficient stored
                               once, no column indices; diagonal PC only */
 
+#define LF_WALK_AUTO 0     /* FP64 matrix-vector product of a band layout with
+                              two or more bands by the row walk when the mesh
+                              fills the GPU with it (at least 2048 workgroups
+                              of 512 threads, 8 rows each), else one row per
+                              thread */
+#define LF_WALK_ON 1       /* the row walk whenever the layout allows it (tests) */
+#define LF_WALK_OFF 2      /* always one row per thread */
+
 #define LF_PREC_FP64 0     /* everything in binary64 */
 #define LF_PREC_MIXED 1    /* FP64 outer residual and update, FP32 inner PCG
                               (coefficients, vectors, SpMV) with FP64 dot
@@ -120,6 +128,10 @@ typedef struct lf_solver_opts {
                                    Results do not depend on it beyond the sign
                                    of exact zeros: both layouts sum a row's
                                    entries in the same order */
+    int32_t amul_walk;          /* LF_WALK_* (default AUTO).  Both forms give
+                                   bitwise the same product; only the order of
+                                   the partial sums of p.Ap differs */
+    int32_t reserved;           /* 0 */
 } lf_solver_opts;
 
 /* Per time step results. */
@@ -197,6 +209,9 @@ lf_status lf_problem_reset(lf_problem *problem, const lf_patch_bc *bcs, double D
 /* The coefficient layout the problem resolved to: LF_LAYOUT_ROWS or
  * LF_LAYOUT_BANDS (never AUTO). */
 lf_status lf_problem_layout(const lf_problem *problem, int32_t *layout);
+
+/* 1 if the problem's FP64 matrix-vector product uses the row walk, else 0. */
+lf_status lf_problem_amul_walk(const lf_problem *problem, int32_t *walk);
 
 /* T[N]: on_device = 1 means a device pointer (copied on the handle's stream),
  * 0 a host pointer (synchronous).  lf_set_T rejects non-finite values. */

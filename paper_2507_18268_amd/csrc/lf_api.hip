@@ -27,6 +27,8 @@ lf_status lf_default_opts(lf_solver_opts *o) {
     o->inner_tol = 0.0;
     o->max_outer = 0;
     o->layout = LF_LAYOUT_AUTO;
+    o->amul_walk = LF_WALK_AUTO;
+    o->reserved = 0;
     return LF_OK;
 }
 
@@ -81,6 +83,10 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
         set_error("unknown layout %d", opts.layout);
         return LF_EINVAL;
     }
+    if (opts.amul_walk != LF_WALK_AUTO && opts.amul_walk != LF_WALK_ON && opts.amul_walk != LF_WALK_OFF) {
+        set_error("unknown amul_walk %d", opts.amul_walk);
+        return LF_EINVAL;
+    }
     if (opts.layout == LF_LAYOUT_BANDS && (m->n_bands == 0 || opts.precond != LF_PC_DIAGONAL)) {
         set_error(m->n_bands == 0 ? "the band layout needs a mesh whose faces take at most %d offsets"
                                   : "the band layout is for the diagonal preconditioner (%d)", kMaxBands);
@@ -114,6 +120,14 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
     P->sp.n = m->N;
     P->sp.grid = cell_blocks(m->N);
     P->sp.grid_mx = mx_blocks(m->N);
+    P->sp.grid_amul = P->sp.grid;
+    if (P->banded && m->n_bands >= 2 && opts.amul_walk != LF_WALK_OFF) {
+        const int32_t wb = walk_blocks(m->N, m->band_d[1]);
+        if ((opts.amul_walk == LF_WALK_ON || wb >= kWalkMinBlocks) && wb <= P->sp.grid) {
+            P->walk = true;
+            P->sp.grid_amul = wb;
+        }
+    }
     P->sp.n_red = m->two_colour ? m->n_red : m->N;
     P->sp.max_outer = opts.max_outer > 0 ? opts.max_outer : 50;
     P->sp.inner_tol = opts.inner_tol > 0.0 ? opts.inner_tol : 1e-5;
@@ -178,6 +192,13 @@ lf_status lf_problem_layout(const lf_problem *P, int32_t *layout) {
     clear_error();
     if (!P || !layout) { set_error("NULL argument"); return LF_EINVAL; }
     *layout = P->banded ? LF_LAYOUT_BANDS : LF_LAYOUT_ROWS;
+    return LF_OK;
+}
+
+lf_status lf_problem_amul_walk(const lf_problem *P, int32_t *walk) {
+    clear_error();
+    if (!P || !walk) { set_error("NULL argument"); return LF_EINVAL; }
+    *walk = P->walk ? 1 : 0;
     return LF_OK;
 }
 

@@ -220,6 +220,112 @@ __device__ __forceinline__ A layout_dot(const BandLayout<K> &L, int32_t c, const
     return acc;
 }
 
+// ---------------------------------------------------------------------------
+// Row walk over a band layout with K >= 2 bands.  The rows are cut into runs of
+// kWalkRows * d1 consecutive rows (d1 = the second band's offset); thread t of
+// run g takes the rows c0 = g kWalkRows d1 + t, c0 + d1, c0 + 2 d1, ...  A row's
+// band-1 neighbours are then the thread's previous and next rows: their x
+// values and the band-1 coefficient of the previous row stay in registers
+// instead of being gathered again (on a box numbered x fastest these are the
+// rows at -+nx, which for many rows lie in another workgroup, often on another
+// XCD).  Each row's sum is layout_dot's, term for term in the same order, so
+// the result is bitwise the same.
+// ---------------------------------------------------------------------------
+constexpr int kWalkRows = 8;
+constexpr int kWalkMinBlocks = 2048;   // below this the flat one-row-per-thread launch is used
+
+// workgroups of a walk launch over n rows with band-1 offset d1
+inline int32_t walk_blocks(int32_t n, int32_t d1) {
+    const int64_t run = static_cast<int64_t>(kWalkRows) * d1;
+    const int64_t threads = (static_cast<int64_t>(n) + run - 1) / run * d1;
+    return static_cast<int32_t>((threads + kCellBlock - 1) / kCellBlock);
+}
+
+// K when a layout can be walked (a band layout with K >= 2), else 0
+template <class Lay>
+struct WalkBands { static constexpr int value = 0; };
+template <int K>
+struct WalkBands<BandLayout<K>> { static constexpr int value = K >= 2 ? K : 0; };
+
+// acc + the row's entries in layout_dot's order, with the band-1 lower entry
+// (a_lo, x_lo) and the band-1 upper x value x_up supplied; a_up returns the
+// row's own band-1 coefficient (the next row's lower one)
+template <int K, class T, class A>
+__device__ __forceinline__ A walk_row_dot(const BandLayout<K> &L, int64_t c, const T *__restrict__ coef,
+                                          const T *__restrict__ x, A acc, T a_lo, T x_lo, T x_up, T &a_up) {
+    static_assert(K >= 2, "the walk needs a second band");
+    const int64_t n = L.n;
+    T a[2 * K], xv[2 * K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int k = K - 1 - j;
+        if (k == 1) {
+            a[j] = a_lo;
+            xv[j] = x_lo;
+        } else {
+            const bool ok = c >= L.d[k];
+            const int64_t col = ok ? c - L.d[k] : c;
+            const T v = coef[k * n + col];
+            a[j] = ok ? v : T(0);
+            xv[j] = x[col];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        a[K + k] = coef[k * n + c];
+        if (k == 1) {
+            xv[K + k] = x_up;
+        } else {
+            const int64_t col = c < n - L.d[k] ? c + L.d[k] : c;
+            xv[K + k] = x[col];
+        }
+    }
+    a_up = a[K + 1];
+#pragma unroll
+    for (int j = 0; j < 2 * K; ++j) acc += a[j] * xv[j];
+    return acc;
+}
+
+// y = A x over the thread's run rows (diag x first, as layout_dot's callers do);
+// returns the sum over those rows, in row order, of y_c x_c
+template <int K, bool kStream>
+__device__ __forceinline__ double band_walk(const BandLayout<K> &L, const double *__restrict__ diagB,
+                                            const double *__restrict__ coef, const double *__restrict__ x,
+                                            double *__restrict__ y) {
+    const int64_t n = L.n, d1 = L.d[1];
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kCellBlock + threadIdx.x;
+    const int64_t g = i / d1;
+    int64_t c = g * kWalkRows * d1 + (i - g * d1);
+    double dot = 0.0;
+    if (c >= n) return dot;
+    double a_lo = 0.0, x_lo;
+    if (c >= d1) {
+        a_lo = coef[n + c - d1];
+        x_lo = x[c - d1];
+    } else {
+        x_lo = x[c];
+    }
+    double xc = x[c];
+#pragma unroll
+    for (int r = 0; r < kWalkRows; ++r) {
+        if (c >= n) break;
+        const double x_up = x[c < n - d1 ? c + d1 : c];
+        const double dc = kStream ? __builtin_nontemporal_load(&diagB[c]) : diagB[c];
+        double a_up;
+        const double yc = walk_row_dot(L, c, coef, x, dc * xc, a_lo, x_lo, x_up, a_up);
+        if (kStream)
+            __builtin_nontemporal_store(yc, &y[c]);
+        else
+            y[c] = yc;
+        dot += yc * xc;
+        a_lo = a_up;
+        x_lo = xc;
+        xc = x_up;
+        c += d1;
+    }
+    return dot;
+}
+
 
 // ---------------------------------------------------------------------------
 // assembly (Listing 1): upper_f = -(delta_f (DT |S_f|)), diag = V/dt - lapDiag

@@ -129,6 +129,14 @@ k_amul(SolverParams sp, Lay L, const double *__restrict__ diagB, const double *_
     if (c < sp.n) y[c] = layout_dot(L, c, coef, x, diagB[c] * x[c]);
 }
 
+// y = A x by the row walk (band layouts with two or more bands)
+template <int K>
+__global__ void __launch_bounds__(kCellBlock)
+k_amul_walk(BandLayout<K> L, const double *__restrict__ diagB, const double *__restrict__ coef,
+            const double *__restrict__ x, double *__restrict__ y) {
+    band_walk<K, false>(L, diagB, coef, x, y);
+}
+
 // band layout: face-order copy of the coefficients, upper_f at slot k*N + owner_f
 __global__ void __launch_bounds__(kCellBlock)
 k_band_upper(int32_t F, int32_t N, BandOffsets bo, const int32_t *__restrict__ owner,
@@ -185,6 +193,19 @@ k_amul_dot(SolverParams sp, Lay L, const double *__restrict__ diagB, const doubl
     }
     const int slots[1] = {kPartPq};
     write_partials<1>(part, sp.grid, slots, acc);
+}
+
+// k_amul_dot by the row walk: sp.grid_amul workgroups, whose partials of q.p
+// fill the first sp.grid_amul entries of the p.q slot
+template <int K>
+__global__ void __launch_bounds__(kCellBlock)
+k_amul_dot_walk(SolverParams sp, BandLayout<K> L, const double *__restrict__ diagB, const double *__restrict__ coef,
+                const double *__restrict__ p, double *__restrict__ q, double *__restrict__ part,
+                const PcgState *__restrict__ st) {
+    if (st->done) return;
+    double acc[1] = {band_walk<K, true>(L, diagB, coef, p, q)};
+    const int slots[1] = {0};
+    write_partials<1>(part + static_cast<int64_t>(kPartPq) * sp.grid, sp.grid_amul, slots, acc);
 }
 
 // r -= alpha q; partial sums of |r| and (diagonal) of w.r, w = rD r
@@ -352,9 +373,10 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(SolverParams sp, const d
         }
     } else if (Mode == kFinAlpha) {
         if (st->done) return;
+        // the Amul launch wrote sp.grid_amul partials from the slot's start
         double v[1];
-        const int slots[1] = {kPartPq};
-        reduce_partials<1>(part, G, slots, v);
+        const int slots[1] = {0};
+        reduce_partials<1>(part + static_cast<int64_t>(kPartPq) * G, sp.grid_amul, slots, v);
         if (threadIdx.x == 0) {
             const double pq = v[0];
             if (!isfinite(pq)) {
@@ -523,6 +545,14 @@ static lf_status launch_iteration(lf_problem *P, hipStream_t s) {
     const lf_mesh *m = P->mesh;
     const bool diag_pc = P->opts.precond == LF_PC_DIAGONAL;
     with_layout(P, [&](auto lay) {
+        constexpr int K = WalkBands<decltype(lay)>::value;
+        if constexpr (K > 0) {
+            if (P->walk) {
+                LF_LAUNCH(P, LF_K_AMUL_DOT, s, k_amul_dot_walk<K>, dim3(static_cast<unsigned>(P->sp.grid_amul)),
+                          dim3(kCellBlock), 0, s, P->sp, lay, P->diagB, P->coef, P->p, P->q, P->part, P->state);
+                return;
+            }
+        }
         LF_LAUNCH(P, LF_K_AMUL_DOT, s, k_amul_dot<decltype(lay)>, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, lay,
                   P->diagB, P->coef, P->p, P->q, P->part, P->state);
     });
@@ -659,6 +689,14 @@ lf_status fp64_advance(lf_problem *P, SolveCtx &c, bool *finished, lf_solve_stat
 
 lf_status launch_amul_hook(lf_problem *P, const double *x, double *y) {
     with_layout(P, [&](auto lay) {
+        constexpr int K = WalkBands<decltype(lay)>::value;
+        if constexpr (K > 0) {
+            if (P->walk) {
+                hipLaunchKernelGGL(k_amul_walk<K>, dim3(static_cast<unsigned>(P->sp.grid_amul)), dim3(kCellBlock), 0,
+                                   P->stream, lay, P->diagB, P->coef, x, y);
+                return;
+            }
+        }
         hipLaunchKernelGGL(k_amul<decltype(lay)>, cell_grid(P), dim3(kCellBlock), 0, P->stream, P->sp, lay,
                            P->diagB, P->coef, x, y);
     });

@@ -54,6 +54,7 @@ struct SolverParams {
     int32_t grid_mx;      // workgroups of an FP32 inner-solve launch (kMxRows rows per thread)
     int32_t n_red;        // DIC: first black cell
     int32_t max_outer;    // mixed: refinement passes cap
+    int32_t grid_amul;    // workgroups of the FP64 Amul launch (= its p.q partials)
     double inner_tol;     // mixed: relative reduction of each inner solve
 };
 
@@ -73,6 +74,7 @@ struct lf_problem {
     double *r = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr, *w = nullptr, *rD = nullptr;
     double *diag = nullptr, *source = nullptr, *diagB = nullptr, *srcB = nullptr;
     bool banded = false;                       // coefficients in the band layout
+    bool walk = false;                         // FP64 Amul by the row walk (bands >= 2, large meshes)
     double *upper = nullptr;                   // [F] face order (test hook copy)
     double *coef = nullptr;                    // [n_entries] row layout or [n_bands N] bands
     double *int_coeff = nullptr, *bou_coeff = nullptr;

@@ -30,6 +30,9 @@ LF_PREC_MIXED = 1
 LF_LAYOUT_AUTO = 0
 LF_LAYOUT_ROWS = 1
 LF_LAYOUT_BANDS = 2
+LF_WALK_AUTO = 0
+LF_WALK_ON = 1
+LF_WALK_OFF = 2
 
 _STATUS = {0: "LF_OK", -1: "LF_EINVAL", -2: "LF_EMESH", -3: "LF_ENOMEM", -4: "LF_EBUDGET",
            -5: "LF_EDEVICE", -6: "LF_ESTATE", -7: "LF_ENONFINITE"}
@@ -58,7 +61,8 @@ class lf_solver_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("rel_tol", C.c_double), ("max_iter", C.c_int32),
                 ("min_iter", C.c_int32), ("precond", C.c_int32), ("precision", C.c_int32),
                 ("iters_per_check", C.c_int32), ("use_graph", C.c_int32),
-                ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("layout", C.c_int32)]
+                ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("layout", C.c_int32),
+                ("amul_walk", C.c_int32), ("reserved", C.c_int32)]
 
 
 class lf_solve_stats(C.Structure):
@@ -88,6 +92,7 @@ _SIGS = {
                                       C.c_void_p, C.POINTER(C.c_void_p)]),
     "lf_problem_destroy": (C.c_int32, [C.c_void_p]),
     "lf_problem_layout": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "lf_problem_amul_walk": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32)]),
     "lf_problem_reset": (C.c_int32, [C.c_void_p, C.POINTER(lf_patch_bc), C.c_double, C.c_double]),
     "lf_set_T": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
     "lf_get_T": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
@@ -205,6 +210,12 @@ def lf_problem_reset(h, bcs_array, DT, dt):
 def lf_problem_layout(h):
     v = C.c_int32(0)
     _check(lib().lf_problem_layout(h, C.byref(v)), "lf_problem_layout")
+    return v.value
+
+
+def lf_problem_amul_walk(h):
+    v = C.c_int32(0)
+    _check(lib().lf_problem_amul_walk(h, C.byref(v)), "lf_problem_amul_walk")
     return v.value
 
 
@@ -394,11 +405,11 @@ class Mesh:
 
 def make_opts(tol=1e-9, rel_tol=0.0, max_iter=1000, min_iter=0, precond=LF_PC_DIAGONAL,
               precision=LF_PREC_FP64, iters_per_check=0, use_graph=1, inner_tol=0.0, max_outer=0,
-              layout=LF_LAYOUT_AUTO):
+              layout=LF_LAYOUT_AUTO, amul_walk=LF_WALK_AUTO):
     o = lf_default_opts()
     o.tol, o.rel_tol, o.max_iter, o.min_iter = tol, rel_tol, max_iter, min_iter
     o.precond, o.precision, o.iters_per_check, o.use_graph = precond, precision, iters_per_check, use_graph
-    o.inner_tol, o.max_outer, o.layout = inner_tol, max_outer, layout
+    o.inner_tol, o.max_outer, o.layout, o.amul_walk = inner_tol, max_outer, layout, amul_walk
     return o
 
 
@@ -422,6 +433,10 @@ class Problem:
     def layout(self):
         """LF_LAYOUT_ROWS or LF_LAYOUT_BANDS."""
         return lf_problem_layout(self.h)
+
+    def amul_walk(self):
+        """True if the FP64 matrix-vector product runs as the row walk."""
+        return bool(lf_problem_amul_walk(self.h))
 
     def reset(self, bcs, DT, dt):
         """New boundary conditions, DT and dt for the same mesh and workspace."""

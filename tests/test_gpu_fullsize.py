@@ -38,6 +38,9 @@ def test_full_size_matrix_and_amul_bitwise(L, oracle, cfg):
     import torch
     p = synth.build_config(cfg)
     m, P, _ = _problem(L, p)
+    # the 256^3 band layout takes the row-walk product by default (the
+    # configuration the benchmark times); the permuted mesh has no band form
+    assert P.amul_walk() == (cfg == "graded_256")
     P.set_T(p.T0)
     P.assemble()
     g = P.matrix()
@@ -58,6 +61,7 @@ def test_full_size_matrix_and_amul_bitwise(L, oracle, cfg):
 def test_full_size_steps_match_oracle(L, oracle, cfg, steps):
     p = synth.build_config(cfg, steps=steps)
     m, P, pc = _problem(L, p)
+    assert P.amul_walk() == (cfg == "graded_256")
     P.set_T(p.T0)
     sg, _ = P.step(steps)                  # one call for all steps, as the benchmark does
     Tg = P.get_T()

@@ -131,6 +131,61 @@ def test_amul_bitwise(L, oracle, name, mesh, layout):
     m.close()
 
 
+WALK_MESHES = [
+    # band-1 offset d1 = nx; runs of 8 d1 rows, the last one ragged
+    ("13x7x5", lambda: synth.box_mesh(13, 7, 5, z_ratio=3.0)),
+    ("130x9x4", lambda: synth.box_mesh(130, 9, 4)),
+    ("5x40x9", lambda: synth.box_mesh(5, 40, 9, z_ratio=2.0)),
+    ("two_bands_6x5x1", lambda: synth.box_mesh(6, 5, 1)),
+    ("one_plane_row_3x1x7", lambda: synth.box_mesh(3, 1, 7)),
+]
+
+
+@pytest.mark.parametrize("name,mk", WALK_MESHES, ids=[n for n, _ in WALK_MESHES])
+def test_amul_walk_bitwise(L, oracle, name, mk):
+    """The row-walk product equals the one-row-per-thread product and the
+    oracle's LDU product bitwise (same terms in the same order)."""
+    import torch
+    mesh = mk()
+    T0 = synth.initial_field(mesh.n_cells, 8)
+    x = np.random.default_rng(4).uniform(-1.0, 1.0, mesh.n_cells)
+    m = L.Mesh(mesh)
+    assert m.n_bands >= 2
+    ys = []
+    for walk in (L.LF_WALK_ON, L.LF_WALK_OFF):
+        P = L.Problem(m, BCS_MIXED, 2e-3, 1e-3, L.make_opts(amul_walk=walk))
+        assert P.layout() == L.LF_LAYOUT_BANDS
+        assert P.amul_walk() == (walk == L.LF_WALK_ON)
+        P.set_T(T0)
+        P.assemble()
+        g = P.matrix()
+        xd = torch.from_numpy(x).cuda()
+        yd = torch.empty_like(xd)
+        P.amul(xd, yd)
+        torch.cuda.synchronize()
+        ys.append(yd.cpu().numpy())
+        P.close()
+    assert np.array_equal(ys[0], ys[1])
+    assert np.array_equal(ys[0], oracle.amul(mesh, g["diag_b"], g["upper"], x))
+    m.close()
+
+
+def test_amul_walk_option_checked(L):
+    m = L.Mesh(synth.box_mesh(4, 4, 4))
+    with pytest.raises(L.LapfoamError):
+        L.Problem(m, synth.fixed_x_bcs(), 1e-3, 1e-3, L.make_opts(amul_walk=7))
+    # rows layout and one-band meshes keep the one-row-per-thread product
+    P = L.Problem(m, synth.fixed_x_bcs(), 1e-3, 1e-3, L.make_opts(layout=1, amul_walk=L.LF_WALK_ON))
+    assert not P.amul_walk()
+    P.close()
+    m.close()
+    m = L.Mesh(synth.box_mesh(9, 1, 1))
+    P = L.Problem(m, synth.fixed_x_bcs(), 1e-3, 1e-3, L.make_opts(amul_walk=L.LF_WALK_ON))
+    assert not P.amul_walk()
+    P.close()
+    m.close()
+
+
 CASES = [
     # name, config, n override, steps, precond
     ("plain_32", "plain_32", None, 20, 0),
@@ -170,6 +225,11 @@ EDGE = [
      dict(layout=1)),
     ("bands_layout", lambda: synth.box_mesh(13, 11, 9, z_ratio=2.0), synth.fixed_x_bcs(), 1e-2, 1e-2,
      dict(layout=2)),
+    ("walk_13x11x9", lambda: synth.box_mesh(13, 11, 9, z_ratio=2.0), synth.fixed_x_bcs(), 1e-2, 1e-2,
+     dict(amul_walk=1)),
+    ("walk_130x9x4", lambda: synth.box_mesh(130, 9, 4), synth.fixed_x_bcs(), 1e-2, 1e-2, dict(amul_walk=1)),
+    ("walk_min_iter_5", lambda: synth.box_mesh(13, 11, 9), synth.fixed_x_bcs(), 1e-3, 1e-3,
+     dict(amul_walk=1, min_iter=5)),
     ("no_graph", lambda: synth.box_mesh(13, 11, 9), synth.fixed_x_bcs(), 1e-2, 1e-2, dict(use_graph=0)),
     ("check_every_iter", lambda: synth.box_mesh(13, 11, 9), synth.fixed_x_bcs(), 1e-2, 1e-2,
      dict(iters_per_check=1)),
