@@ -71,18 +71,22 @@ typedef int32_t lf_status;
                               structured numbering); each coefficient stored
                               once, no column indices; diagonal PC only */
 
-#define LF_WALK_AUTO 0     /* FP64 matrix-vector product of a band layout with
-                              two or more bands by the row walk when the mesh
-                              fills the GPU with it (at least 2048 workgroups
-                              of 512 threads, 8 rows each), else one row per
-                              thread */
+#define LF_WALK_AUTO 0     /* matrix-vector products of a band layout with two
+                              or more bands (the FP64 solve's, and the inner
+                              FP32 solve's of LF_PREC_MIXED) by the row walk
+                              when the mesh fills the GPU with it (at least
+                              2048 workgroups of 512 threads, 8 rows each),
+                              else one row per thread */
 #define LF_WALK_ON 1       /* the row walk whenever the layout allows it (tests) */
 #define LF_WALK_OFF 2      /* always one row per thread */
 
 #define LF_PREC_FP64 0     /* everything in binary64 */
-#define LF_PREC_MIXED 1    /* FP64 outer residual and update, FP32 inner PCG
-                              (coefficients, vectors, SpMV) with FP64 dot
-                              products, alpha and beta (iterative refinement) */
+#define LF_PREC_MIXED 1    /* FP64 outer residual and update; inner solve in
+                              FP32 (coefficients, vectors, SpMV) with FP64 dot
+                              products, alpha and beta: CG on S A S, S =
+                              diag(1/sqrt(diag A)), which is the diagonally
+                              preconditioned CG of A d = r in exact arithmetic
+                              (iterative refinement) */
 
 /* Mesh in OpenFOAM face addressing (host pointers). */
 typedef struct lf_mesh_desc {
@@ -210,7 +214,7 @@ lf_status lf_problem_reset(lf_problem *problem, const lf_patch_bc *bcs, double D
  * LF_LAYOUT_BANDS (never AUTO). */
 lf_status lf_problem_layout(const lf_problem *problem, int32_t *layout);
 
-/* 1 if the problem's FP64 matrix-vector product uses the row walk, else 0. */
+/* 1 if the problem's matrix-vector products use the row walk, else 0. */
 lf_status lf_problem_amul_walk(const lf_problem *problem, int32_t *walk);
 
 /* T[N]: on_device = 1 means a device pointer (copied on the handle's stream),
@@ -312,8 +316,8 @@ lf_status lf_batch_stats(lf_batch *batch, lf_solve_stats *stats, double *elapsed
 #define LF_K_INNER_DIRECTION 11 /* mixed: FP32 direction update */
 #define LF_K_INNER_AMUL_DOT 12  /* mixed: FP32 q = A p, FP64 p.q partials */
 #define LF_K_INNER_UPDATE 13    /* mixed: FP32 update, FP64 partials */
-#define LF_K_MIXED_PREP 14      /* mixed: no longer launched (the pass start is part
-                                   of the assembly and residual kernels) */
+#define LF_K_MIXED_PREP 14      /* mixed: FP32 coefficients of the scaled matrix
+                                   (once per step) */
 #define LF_K_FINALIZE 15        /* one-workgroup reductions and scalar decisions */
 #define LF_NUM_KERNEL_CLASSES 16
 lf_status lf_profile_enable(lf_problem *problem, int32_t on);

@@ -121,11 +121,14 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
     P->sp.grid = cell_blocks(m->N);
     P->sp.grid_mx = mx_blocks(m->N);
     P->sp.grid_amul = P->sp.grid;
+    P->sp.grid_mx_amul = P->sp.grid_mx;
     if (P->banded && m->n_bands >= 2 && opts.amul_walk != LF_WALK_OFF) {
+        // the walk's partials must fit the p.q slot of both solvers' reductions
         const int32_t wb = walk_blocks(m->N, m->band_d[1]);
-        if ((opts.amul_walk == LF_WALK_ON || wb >= kWalkMinBlocks) && wb <= P->sp.grid) {
+        if ((opts.amul_walk == LF_WALK_ON || wb >= kWalkMinBlocks) && wb <= P->sp.grid_mx) {
             P->walk = true;
             P->sp.grid_amul = wb;
+            P->sp.grid_mx_amul = wb;
         }
     }
     P->sp.n_red = m->two_colour ? m->n_red : m->N;

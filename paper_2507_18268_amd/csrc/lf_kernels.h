@@ -59,13 +59,14 @@ __device__ __forceinline__ void write_partials(double *__restrict__ part, int32_
     }
 }
 
-// second stage (one workgroup of kFinBlock threads): fixed-order sums.  Thread
-// t adds part[t], part[t + 1024], ... of each slot in that order; the loads of
+// second stage (one workgroup of kFinBlock threads): fixed-order sums of the
+// first G partials of each slot (slots `stride` apart).  Thread t adds
+// part[t], part[t + 1024], ... of each slot in that order; the loads of
 // a group (kU per slot, every slot) are issued together, so the serial chain
 // waits once per group: one or two groups at the sizes used here.
 template <int NQ>
-__device__ __forceinline__ void reduce_partials(const double *__restrict__ part, int32_t G, const int (&slot)[NQ],
-                                                double (&out)[NQ]) {
+__device__ __forceinline__ void reduce_partials(const double *__restrict__ part, int32_t stride, int32_t G,
+                                                const int (&slot)[NQ], double (&out)[NQ]) {
     constexpr int kU = NQ == 1 ? 32 : (NQ == 2 ? 16 : 8);
     double s[NQ];
 #pragma unroll
@@ -74,7 +75,7 @@ __device__ __forceinline__ void reduce_partials(const double *__restrict__ part,
         double v[NQ][kU];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            const double *__restrict__ src = part + static_cast<int64_t>(slot[q]) * G;
+            const double *__restrict__ src = part + static_cast<int64_t>(slot[q]) * stride;
 #pragma unroll
             for (int j = 0; j < kU; ++j) {
                 const int32_t i = i0 + j * kFinBlock;
@@ -90,6 +91,13 @@ __device__ __forceinline__ void reduce_partials(const double *__restrict__ part,
 #pragma unroll
     for (int q = 0; q < NQ; ++q) out[q] = s[q];
     block_sum<kFinBlock, NQ>(out);
+}
+
+// the usual case: G partials per slot, slots G apart
+template <int NQ>
+__device__ __forceinline__ void reduce_partials(const double *__restrict__ part, int32_t G, const int (&slot)[NQ],
+                                                double (&out)[NQ]) {
+    reduce_partials<NQ>(part, G, G, slot, out);
 }
 
 __device__ __forceinline__ bool check_conv(double res, double res0, double tol, double rel_tol) {
@@ -286,43 +294,59 @@ __device__ __forceinline__ A walk_row_dot(const BandLayout<K> &L, int64_t c, con
     return acc;
 }
 
-// y = A x over the thread's run rows (diag x first, as layout_dot's callers do);
-// returns the sum over those rows, in row order, of y_c x_c
-template <int K, bool kStream>
-__device__ __forceinline__ double band_walk(const BandLayout<K> &L, const double *__restrict__ diagB,
-                                            const double *__restrict__ coef, const double *__restrict__ x,
-                                            double *__restrict__ y) {
+// The walk itself: calls fn(c, y_c, x_c, diag_c) for the thread's run rows in
+// order, y = A x (diag x first, as layout_dot's callers do; kUnitDiag: a matrix
+// with unit diagonal, x first, diag_c = 1).  kStream streams diag past the
+// caches (it is touched once per launch).
+template <int K, bool kStream, bool kUnitDiag, class T, class Fn>
+__device__ __forceinline__ void band_walk_rows(const BandLayout<K> &L, const T *__restrict__ diag,
+                                               const T *__restrict__ coef, const T *__restrict__ x, Fn &&fn) {
     const int64_t n = L.n, d1 = L.d[1];
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kCellBlock + threadIdx.x;
     const int64_t g = i / d1;
     int64_t c = g * kWalkRows * d1 + (i - g * d1);
-    double dot = 0.0;
-    if (c >= n) return dot;
-    double a_lo = 0.0, x_lo;
+    if (c >= n) return;
+    T a_lo = T(0), x_lo;
     if (c >= d1) {
         a_lo = coef[n + c - d1];
         x_lo = x[c - d1];
     } else {
         x_lo = x[c];
     }
-    double xc = x[c];
+    T xc = x[c];
 #pragma unroll
     for (int r = 0; r < kWalkRows; ++r) {
         if (c >= n) break;
-        const double x_up = x[c < n - d1 ? c + d1 : c];
-        const double dc = kStream ? __builtin_nontemporal_load(&diagB[c]) : diagB[c];
-        double a_up;
-        const double yc = walk_row_dot(L, c, coef, x, dc * xc, a_lo, x_lo, x_up, a_up);
-        if (kStream)
-            __builtin_nontemporal_store(yc, &y[c]);
-        else
-            y[c] = yc;
-        dot += yc * xc;
+        const T x_up = x[c < n - d1 ? c + d1 : c];
+        T dc = T(1), acc = xc;
+        if (!kUnitDiag) {
+            dc = kStream ? __builtin_nontemporal_load(&diag[c]) : diag[c];
+            acc = dc * xc;
+        }
+        T a_up;
+        const T yc = walk_row_dot(L, c, coef, x, acc, a_lo, x_lo, x_up, a_up);
+        fn(c, yc, xc, dc);
         a_lo = a_up;
         x_lo = xc;
         xc = x_up;
         c += d1;
     }
+}
+
+// y = A x by the walk; returns the FP64 sum over the thread's rows, in row
+// order, of y_c x_c.  kStream also streams y past the caches.
+template <int K, bool kStream, bool kUnitDiag, class T>
+__device__ __forceinline__ double band_walk(const BandLayout<K> &L, const T *__restrict__ diag,
+                                            const T *__restrict__ coef, const T *__restrict__ x,
+                                            T *__restrict__ y) {
+    double dot = 0.0;
+    band_walk_rows<K, kStream, kUnitDiag>(L, diag, coef, x, [&](int64_t c, T yc, T xc, T) {
+        if (kStream)
+            __builtin_nontemporal_store(yc, &y[c]);
+        else
+            y[c] = yc;
+        dot += static_cast<double>(yc) * static_cast<double>(xc);
+    });
     return dot;
 }
 

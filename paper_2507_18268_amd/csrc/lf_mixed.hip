@@ -1,19 +1,29 @@
 // Precision form: mixed-precision iterative refinement.
 //
-// The matrix is assembled in FP64 (with an FP32 copy of its coefficients).
-// Outer loop in FP64: r = b - A T (true residual, FP64 coefficients and T),
-// res = sum|r| / normFactor with the normalisation factor of x0 = T_old, stop
-// when res < tol.  Each pass solves A d = r approximately with a PCG whose
-// vectors, coefficients and products are FP32, while its dot products, alpha
-// and beta are FP64; then T += d in FP64.  The inner solve of a pass stops
-// when its L1 residual has fallen by inner_tol, or below half the outer
-// target, whichever is larger.
+// The matrix is assembled in FP64.  Outer loop in FP64: r = b - A T (true
+// residual, FP64 coefficients and T), res = sum|r| / normFactor with the
+// normalisation factor of x0 = T_old, stop when res < tol.  Each pass solves
+// A d = r approximately in FP32 vectors, coefficients and products, with FP64
+// dot products, alpha and beta; then T += d in FP64.
 //
-// The refinement runs until res < kTighten * tol (convergence is still
-// reported against tol).  Every FP64 PCG that stops just below tol leaves an
-// error of its own in T (up to ~6e-9 relative per step on these meshes); by
-// stopping an order of magnitude lower the precision form stays within 1e-8
-// of such a solve of the same system.
+// The inner system is the symmetrically scaled one: with s = sqrt(diag A),
+// As = S^-1 A S^-1 has a unit diagonal, rs = r / s, and plain CG on
+// As y = rs gives d = y / s.  In exact arithmetic its iterates are those of
+// the diagonally preconditioned CG on A d = r (the same alpha, beta and
+// w.r = rs.rs); in the loop it reads neither the diagonal nor its
+// reciprocal.  s is sqrt(diag A) rounded to FP32 (the scaled diagonal is 1 to
+// FP32 rounding); the FP32 coefficients a / (s_c s_n) are formed once per
+// step from the FP64 ones.  The update y += alpha p of an iteration is applied by
+// the next iteration's direction kernel (which reads p anyway), and the last
+// one by the correction T += (y + alpha p) / s.
+//
+// The inner solve of a pass stops when the L1 norm of the residual it sees,
+// sum s_c |rs_c|, has fallen by inner_tol, or below half the outer target,
+// whichever is larger.  The refinement runs until res < kTighten * tol
+// (convergence is still reported against tol).  Every FP64 PCG that stops
+// just below tol leaves an error of its own in T (up to ~6e-9 relative per
+// step on these meshes); by stopping an order of magnitude lower the
+// precision form stays within 1e-8 of such a solve of the same system.
 constexpr double kTighten = 0.1;
 #include <hip/hip_runtime.h>
 
@@ -27,38 +37,82 @@ namespace lf {
 void carve_mixed(Carver &cv, const lf_mesh *m, bool banded, lf_problem *P) {
     const size_t N = m->N;
     auto *coef32 = cv.take<float>(coef_slots(m, banded));
-    float *v32[6];
+    float *v32[7];
     for (auto &v : v32) v = cv.take<float>(N);
     if (P) {
         P->coef32 = coef32; P->diag32 = v32[0]; P->rD32 = v32[1]; P->r32 = v32[2];
-        P->p32 = v32[3]; P->q32 = v32[4]; P->d32 = v32[5];
+        P->p32 = v32[3]; P->q32 = v32[4]; P->d32 = v32[5]; P->sig32 = v32[6];
     }
 }
 
 __device__ __forceinline__ bool inner_off(const PcgState *st) { return st->done || st->inner_done; }
 
-// p = w (first inner iteration) or w + beta p, w = rD r, all FP32
+// FP32 coefficients of the scaled matrix: a_cn / (s_c s_n), with s the FP32
+// sqrt(diagB) that also scales the residual and the correction (the scaled
+// diagonal is then 1 to FP32 rounding, and taken as 1).  Band layout: the face
+// (c, c + d_k) at k n + c.
+template <int K>
+__device__ __forceinline__ void scale_row(const BandLayout<K> &L, int32_t c, double sc,
+                                          const float *__restrict__ sig32, const double *__restrict__ coef,
+                                          float *__restrict__ coef32) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t slot = static_cast<int64_t>(k) * L.n + c;
+        const bool ok = c < L.n - L.d[k];      // otherwise no face: the slot holds 0
+        const double sn = ok ? static_cast<double>(sig32[c + L.d[k]]) : 1.0;
+        coef32[slot] = static_cast<float>(coef[slot] / (sc * sn));
+    }
+}
+
+// Row layout: each coefficient is in both its rows; s_c s_n = s_n s_c, so the
+// two copies stay equal and the scaled matrix symmetric.
+__device__ __forceinline__ void scale_row(const SellLayout &L, int32_t c, double sc,
+                                          const float *__restrict__ sig32, const double *__restrict__ coef,
+                                          float *__restrict__ coef32) {
+    int32_t idx = row_base(L.mr, c);
+    const int32_t len = L.mr.rlen[c];
+    for (int32_t j = 0; j < len; ++j, idx += kSlice)
+        coef32[idx] = static_cast<float>(coef[idx] / (sc * static_cast<double>(sig32[L.mr.scol[idx]])));
+}
+
+template <class Lay>
 __global__ void __launch_bounds__(kCellBlock)
-k_mx_direction(SolverParams sp, const float *__restrict__ rD32, const float *__restrict__ r32,
-               float *__restrict__ p32, const PcgState *__restrict__ st) {
+k_mx_scale(SolverParams sp, Lay L, const float *__restrict__ sig32, const double *__restrict__ coef,
+           float *__restrict__ coef32) {
+    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+    if (c < sp.n) scale_row(L, c, static_cast<double>(sig32[c]), sig32, coef, coef32);
+}
+
+// first inner iteration: p = rs; later: y += alpha p (the previous
+// iteration's update), then p = rs + beta p; all FP32
+__global__ void __launch_bounds__(kCellBlock)
+k_mx_direction(SolverParams sp, const float *__restrict__ r32, float *__restrict__ p32, float *__restrict__ d32,
+               const PcgState *__restrict__ st) {
     if (inner_off(st)) return;
     const bool first = st->inner_iter == 0;
     const float beta = static_cast<float>(st->beta);
+    const float alpha = static_cast<float>(st->alpha);
 #pragma unroll
     for (int j = 0; j < kMxRows; ++j) {
         const int32_t c = cell_row<kMxRows>(j);
         if (c >= sp.n) continue;
-        const float wc = rD32[c] * r32[c];
-        p32[c] = first ? wc : wc + beta * p32[c];
+        const float rc = r32[c];
+        if (first) {
+            p32[c] = rc;
+        } else {
+            const float pc = p32[c];
+            d32[c] += alpha * pc;
+            p32[c] = rc + beta * pc;
+        }
     }
 }
 
-// q = A p in FP32; FP64 partial sums of p.q
+// q = As p in FP32 (unit diagonal: p_c first, then the row's entries in
+// order); FP64 partial sums of p.q
 template <class Lay>
 __global__ void __launch_bounds__(kCellBlock)
-k_mx_amul_dot(SolverParams sp, Lay L, const float *__restrict__ diag32, const float *__restrict__ coef32,
-              const float *__restrict__ p32, float *__restrict__ q32, double *__restrict__ part,
-              const PcgState *__restrict__ st) {
+k_mx_amul_dot(SolverParams sp, Lay L, const float *__restrict__ coef32, const float *__restrict__ p32,
+              float *__restrict__ q32, double *__restrict__ part, const PcgState *__restrict__ st) {
     if (inner_off(st)) return;
     double acc[1] = {0.0};
 #pragma unroll
@@ -66,19 +120,32 @@ k_mx_amul_dot(SolverParams sp, Lay L, const float *__restrict__ diag32, const fl
         const int32_t c = cell_row<kMxRows>(j);
         if (c >= sp.n) continue;
         const float pc = p32[c];
-        const float qc = layout_dot(L, c, coef32, p32, diag32[c] * pc);
-        q32[c] = qc;
+        const float qc = layout_dot(L, c, coef32, p32, pc);
+        __builtin_nontemporal_store(qc, &q32[c]);
         acc[0] += static_cast<double>(qc) * static_cast<double>(pc);
     }
     const int slots[1] = {kPartPq};
     write_partials<1>(part, sp.grid_mx, slots, acc);
 }
 
-// d += alpha p; r -= alpha q (FP32); FP64 partials of |r| and w.r
+// the same product by the row walk (band layouts with two or more bands):
+// sp.grid_mx_amul workgroups, whose partials fill the start of the p.q slot
+// (slots sp.grid_mx apart)
+template <int K>
 __global__ void __launch_bounds__(kCellBlock)
-k_mx_update(SolverParams sp, const float *__restrict__ p32, const float *__restrict__ q32,
-            const float *__restrict__ rD32, float *__restrict__ r32, float *__restrict__ d32,
-            double *__restrict__ part, const PcgState *__restrict__ st) {
+k_mx_amul_dot_walk(SolverParams sp, BandLayout<K> L, const float *__restrict__ coef32,
+                   const float *__restrict__ p32, float *__restrict__ q32, double *__restrict__ part,
+                   const PcgState *__restrict__ st) {
+    if (inner_off(st)) return;
+    double acc[1] = {band_walk<K, true, true, float>(L, nullptr, coef32, p32, q32)};
+    const int slots[1] = {kPartPq};
+    write_partials<1>(part, sp.grid_mx, slots, acc);
+}
+
+// rs -= alpha q (FP32); FP64 partials of the L1 norm s|rs| and of rs.rs
+__global__ void __launch_bounds__(kCellBlock)
+k_mx_update(SolverParams sp, const float *__restrict__ q32, const float *__restrict__ sig32,
+            float *__restrict__ r32, double *__restrict__ part, const PcgState *__restrict__ st) {
     if (inner_off(st)) return;
     const float alpha = static_cast<float>(st->alpha);
     double acc[2] = {0.0, 0.0};
@@ -86,49 +153,77 @@ k_mx_update(SolverParams sp, const float *__restrict__ p32, const float *__restr
     for (int j = 0; j < kMxRows; ++j) {
         const int32_t c = cell_row<kMxRows>(j);
         if (c >= sp.n) continue;
-        d32[c] += alpha * p32[c];
-        const float rc = r32[c] - alpha * q32[c];
+        const float rc = r32[c] - alpha * __builtin_nontemporal_load(&q32[c]);
         r32[c] = rc;
-        const float wc = rD32[c] * rc;
-        acc[0] += fabs(static_cast<double>(rc));
-        acc[1] += static_cast<double>(wc) * static_cast<double>(rc);
+        acc[0] += fabs(static_cast<double>(sig32[c]) * static_cast<double>(rc));
+        acc[1] += static_cast<double>(rc) * static_cast<double>(rc);
     }
     const int slots[2] = {kPartSumR, kPartWr};
     write_partials<2>(part, sp.grid_mx, slots, acc);
 }
 
-// T += d (FP64)
+// T += d = (y + alpha p) / s in FP64, alpha p being the last inner update
+// when it is still pending
 __global__ void __launch_bounds__(kCellBlock)
-k_mx_correct(SolverParams sp, double *__restrict__ T, const float *__restrict__ d32, const PcgState *__restrict__ st) {
+k_mx_correct(SolverParams sp, double *__restrict__ T, const float *__restrict__ d32, const float *__restrict__ p32,
+             const float *__restrict__ sig32, const PcgState *__restrict__ st) {
     if (st->done) return;
+    const bool pend = st->inner_pend != 0;
+    const float alpha = static_cast<float>(st->alpha);
     const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
-    if (c < sp.n) T[c] += static_cast<double>(d32[c]);
+    if (c < sp.n) {
+        float y = d32[c];
+        if (pend) y += alpha * p32[c];
+        T[c] += static_cast<double>(y) / static_cast<double>(sig32[c]);
+    }
 }
 
 // true residual r = b - A T in FP64 and its partial sums of |r|; also the
 // start of the next pass, which runs if the outer check does not stop the
-// solve: r32 = r rounded to FP32, d = 0, partial sums of |r32| and w32.r32
+// solve: rs = r / s rounded to FP32, y = 0, partial sums of s|rs| and rs.rs
 template <class Lay>
 __global__ void __launch_bounds__(kCellBlock)
 k_mx_residual(SolverParams sp, Lay L, const double *__restrict__ diagB, const double *__restrict__ coef,
-              const double *__restrict__ srcB, const double *__restrict__ T, double *__restrict__ r,
-              const float *__restrict__ rD32, float *__restrict__ r32, float *__restrict__ d32,
-              double *__restrict__ part, const PcgState *__restrict__ st) {
+              const double *__restrict__ srcB, const double *__restrict__ T, float *__restrict__ r32,
+              float *__restrict__ d32, double *__restrict__ part, const PcgState *__restrict__ st) {
     if (st->done) return;
     const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
     double acc[3] = {0.0, 0.0, 0.0};
     if (c < sp.n) {
-        const double ax = layout_dot(L, c, coef, T, diagB[c] * T[c]);
+        const double db = diagB[c];
+        const double ax = layout_dot(L, c, coef, T, db * T[c]);
         const double rc = srcB[c] - ax;
-        r[c] = rc;
         acc[0] = fabs(rc);
-        const float r32c = static_cast<float>(rc);
-        r32[c] = r32c;
+        const double sg = static_cast<float>(sqrt(db));     // the s of the scaled system
+        const float rs = static_cast<float>(rc / sg);
+        r32[c] = rs;
         d32[c] = 0.0f;
-        const float w32 = rD32[c] * r32c;
-        acc[1] = fabs(static_cast<double>(r32c));
-        acc[2] = static_cast<double>(w32) * static_cast<double>(r32c);
+        acc[1] = fabs(sg * static_cast<double>(rs));
+        acc[2] = static_cast<double>(rs) * static_cast<double>(rs);
     }
+    const int slots[3] = {kPartSumR, kPartSumR32, kPartWr32};
+    write_partials<3>(part, sp.grid, slots, acc);
+}
+
+// the same residual by the row walk (sp.grid_amul workgroups)
+template <int K>
+__global__ void __launch_bounds__(kCellBlock)
+k_mx_residual_walk(SolverParams sp, BandLayout<K> L, const double *__restrict__ diagB,
+                   const double *__restrict__ coef, const double *__restrict__ srcB, const double *__restrict__ T,
+                   float *__restrict__ r32, float *__restrict__ d32, double *__restrict__ part,
+                   const PcgState *__restrict__ st) {
+    if (st->done) return;
+    double acc[3] = {0.0, 0.0, 0.0};
+    band_walk_rows<K, true, false>(L, diagB, coef, T, [&](int64_t c, double ax, double, double db) {
+        const double rc = srcB[c] - ax;
+        acc[0] += fabs(rc);
+        const double sg = static_cast<float>(sqrt(db));
+        const float rs = static_cast<float>(rc / sg);
+        r32[c] = rs;
+        d32[c] = 0.0f;
+        acc[1] += fabs(sg * static_cast<double>(rs));
+        acc[2] += static_cast<double>(rs) * static_cast<double>(rs);
+    });
     const int slots[3] = {kPartSumR, kPartSumR32, kPartWr32};
     write_partials<3>(part, sp.grid, slots, acc);
 }
@@ -143,13 +238,17 @@ __global__ void __launch_bounds__(kFinBlock) k_mx_finalize(SolverParams sp, cons
     const int32_t G = (Mode == kMxAlpha || Mode == kMxBeta) ? sp.grid_mx : sp.grid;
     if (Mode == kMxInnerStart) {
         if (st->done) return;
+        // the first pass starts from the assembly's partials (sp.grid of them),
+        // later ones from the residual launch's (sp.grid_amul)
         double v[2];
         const int slots[2] = {kPartSumR32, kPartWr32};
-        reduce_partials<2>(part, G, slots, v);
+        reduce_partials<2>(part, G, st->n_outer == 0 ? sp.grid : sp.grid_amul, slots, v);
         if (threadIdx.x == 0) {
             const double target = fmax(sp.inner_tol * v[0], 0.5 * kTighten * sp.tol * st->nf);
             st->inner_target = target;
             st->inner_iter = 0;
+            st->inner_pend = 0;
+            st->alpha = 0.0;
             st->wArA = v[1];
             st->inner_done = (v[0] <= target || !(v[1] > 0.0)) ? 1 : 0;
             if (!isfinite(v[0]) || !isfinite(v[1])) {
@@ -159,11 +258,13 @@ __global__ void __launch_bounds__(kFinBlock) k_mx_finalize(SolverParams sp, cons
         }
     } else if (Mode == kMxAlpha) {
         if (inner_off(st)) return;
+        // the Amul launch wrote sp.grid_mx_amul partials
         double v[1];
         const int slots[1] = {kPartPq};
-        reduce_partials<1>(part, G, slots, v);
+        reduce_partials<1>(part, G, sp.grid_mx_amul, slots, v);
         if (threadIdx.x == 0) {
             const double pq = v[0];
+            st->inner_pend = 0;              // the direction kernel applied the previous update
             if (!isfinite(pq)) {
                 st->nonfinite = 1;
                 st->done = 1;
@@ -179,6 +280,7 @@ __global__ void __launch_bounds__(kFinBlock) k_mx_finalize(SolverParams sp, cons
         const int slots[2] = {kPartSumR, kPartWr};
         reduce_partials<2>(part, G, slots, v);
         if (threadIdx.x == 0) {
+            st->inner_pend = 1;              // y += alpha p of this iteration is pending
             st->inner_iter += 1;
             st->n_iter += 1;
             if (!isfinite(v[0]) || !isfinite(v[1])) {
@@ -195,7 +297,7 @@ __global__ void __launch_bounds__(kFinBlock) k_mx_finalize(SolverParams sp, cons
         if (st->done) return;
         double v[1];
         const int slots[1] = {kPartSumR};
-        reduce_partials<1>(part, G, slots, v);
+        reduce_partials<1>(part, G, sp.grid_amul, slots, v);     // the residual launch's partials
         if (threadIdx.x == 0) {
             const double res = v[0] / st->nf;
             st->res = res;
@@ -219,30 +321,54 @@ static void launch_mx_fin(lf_problem *P, hipStream_t s) {
 }
 
 static void launch_inner_iteration(lf_problem *P, hipStream_t s) {
-    LF_LAUNCH(P, LF_K_INNER_DIRECTION, s, k_mx_direction, mx_grid(P), dim3(kCellBlock), 0, s, P->sp, P->rD32,
-              P->r32, P->p32, P->state);
+    LF_LAUNCH(P, LF_K_INNER_DIRECTION, s, k_mx_direction, mx_grid(P), dim3(kCellBlock), 0, s, P->sp, P->r32,
+              P->p32, P->d32, P->state);
     with_layout(P, [&](auto lay) {
+        constexpr int K = WalkBands<decltype(lay)>::value;
+        if constexpr (K > 0) {
+            if (P->walk) {
+                LF_LAUNCH(P, LF_K_INNER_AMUL_DOT, s, k_mx_amul_dot_walk<K>,
+                          dim3(static_cast<unsigned>(P->sp.grid_mx_amul)), dim3(kCellBlock), 0, s, P->sp, lay,
+                          P->coef32, P->p32, P->q32, P->part, P->state);
+                return;
+            }
+        }
         LF_LAUNCH(P, LF_K_INNER_AMUL_DOT, s, k_mx_amul_dot<decltype(lay)>, mx_grid(P), dim3(kCellBlock), 0, s,
-                  P->sp, lay, P->diag32, P->coef32, P->p32, P->q32, P->part, P->state);
+                  P->sp, lay, P->coef32, P->p32, P->q32, P->part, P->state);
     });
     launch_mx_fin<kMxAlpha>(P, s);
-    LF_LAUNCH(P, LF_K_INNER_UPDATE, s, k_mx_update, mx_grid(P), dim3(kCellBlock), 0, s, P->sp, P->p32, P->q32,
-              P->rD32, P->r32, P->d32, P->part, P->state);
+    LF_LAUNCH(P, LF_K_INNER_UPDATE, s, k_mx_update, mx_grid(P), dim3(kCellBlock), 0, s, P->sp, P->q32, P->sig32,
+              P->r32, P->part, P->state);
     launch_mx_fin<kMxBeta>(P, s);
 }
 
-// start of a refinement pass (r32, d = 0 and their partial sums were written
+void launch_mx_scale(lf_problem *P, hipStream_t s) {
+    with_layout(P, [&](auto lay) {
+        LF_LAUNCH(P, LF_K_MIXED_PREP, s, k_mx_scale<decltype(lay)>, cell_grid(P), dim3(kCellBlock), 0, s, P->sp,
+                  lay, P->sig32, P->coef, P->coef32);
+    });
+}
+
+// start of a refinement pass (rs, y = 0 and their partial sums were written
 // by the kernel that formed the FP64 residual: the assembly or k_mx_residual)
 static void launch_pass_start(lf_problem *P, hipStream_t s) { launch_mx_fin<kMxInnerStart>(P, s); }
 
 // end of a pass: correction, true residual, outer decision
 static void launch_pass_end(lf_problem *P, hipStream_t s) {
     LF_LAUNCH(P, LF_K_MIXED_CORRECT, s, k_mx_correct, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->T, P->d32,
-              P->state);
+              P->p32, P->sig32, P->state);
     with_layout(P, [&](auto lay) {
+        constexpr int K = WalkBands<decltype(lay)>::value;
+        if constexpr (K > 0) {
+            if (P->walk) {
+                LF_LAUNCH(P, LF_K_MIXED_RESIDUAL, s, k_mx_residual_walk<K>,
+                          dim3(static_cast<unsigned>(P->sp.grid_amul)), dim3(kCellBlock), 0, s, P->sp, lay,
+                          P->diagB, P->coef, P->srcB, P->T, P->r32, P->d32, P->part, P->state);
+                return;
+            }
+        }
         LF_LAUNCH(P, LF_K_MIXED_RESIDUAL, s, k_mx_residual<decltype(lay)>, cell_grid(P), dim3(kCellBlock), 0, s,
-                  P->sp, lay, P->diagB, P->coef, P->srcB, P->T, P->r, P->rD32, P->r32, P->d32, P->part,
-                  P->state);
+                  P->sp, lay, P->diagB, P->coef, P->srcB, P->T, P->r32, P->d32, P->part, P->state);
     });
     launch_mx_fin<kMxOuter>(P, s);
 }
@@ -279,7 +405,7 @@ static lf_status launch_inner(lf_problem *P, int32_t k) {
     return LF_OK;
 }
 
-// block of k inner iterations, then the state copy and ev[2]
+// block of k inner iterations (k may be 0), then the state copy and ev[2]
 static lf_status mixed_block(lf_problem *P, SolveCtx &c) {
     hipStream_t s = P->stream;
     prof_lead(P, s);
@@ -290,6 +416,13 @@ static lf_status mixed_block(lf_problem *P, SolveCtx &c) {
     return LF_OK;
 }
 
+// first block of refinement pass `pass`: as many iterations as that pass took
+// in the last step (the counts repeat closely from step to step)
+static int32_t predicted_inner(const lf_problem *P, int32_t pass) {
+    const int32_t k = pass < lf_problem::kPassTrack ? P->last_inner[pass] : 0;
+    return k > 0 ? k : 8;
+}
+
 lf_status mixed_start(lf_problem *P, SolveCtx &c) {
     hipStream_t s = P->stream;
     prof_lead(P, s);
@@ -297,16 +430,22 @@ lf_status mixed_start(lf_problem *P, SolveCtx &c) {
     launch_pass_start(P, s);
     LF_HIP(hipGetLastError());
     c.fixed_k = P->prof_on ? 1 : P->opts.iters_per_check;
-    c.k = c.fixed_k > 0 ? c.fixed_k : std::max<int32_t>(2, P->last_inner > 0 ? P->last_inner : 8);
+    c.k = c.fixed_k > 0 ? c.fixed_k : predicted_inner(P, 0);
     c.launched = 0;
+    c.stage = 0;
     return mixed_block(P, c);
 }
 
+// Host side of the refinement.  Iterations past the end of a pass (or of the
+// solve) run as no-op launches, so the blocks are sized to what the pass is
+// expected to need; after the pass that ended the last step the outer check
+// is read back before another pass is enqueued (stage 1).
 lf_status mixed_advance(lf_problem *P, SolveCtx &c, bool *finished, lf_solve_stats *out) {
     hipStream_t s = P->stream;
     prof_flush(P);
     *finished = false;
     const PcgState &h = *P->h_state;
+    const bool adaptive = c.fixed_k <= 0;
     if (h.done) {
         out->initial_residual = h.res0;
         out->final_residual = h.res;
@@ -315,6 +454,7 @@ lf_status mixed_advance(lf_problem *P, SolveCtx &c, bool *finished, lf_solve_sta
         out->singular = 0;
         out->nonfinite = h.nonfinite;
         out->n_outer = h.n_outer;
+        P->last_outer = h.n_outer;
         *finished = true;
         return LF_OK;
     }
@@ -322,19 +462,35 @@ lf_status mixed_advance(lf_problem *P, SolveCtx &c, bool *finished, lf_solve_sta
         set_error("mixed solver never reached done after %d launched inner iterations", c.launched);
         return LF_ESTATE;
     }
-    if (!h.inner_done) {
-        if (c.fixed_k <= 0) c.k = std::max<int32_t>(2, c.k / 2);
-    } else {
-        // pass finished: correct, check, start the next pass (no-ops once done)
-        if (c.fixed_k <= 0) {
-            c.k = std::max<int32_t>(2, h.inner_iter);
-            P->last_inner = h.inner_iter;
-        }
+    if (c.stage == 1) {
+        // the outer check after a pass asked for another one
+        c.stage = 0;
         prof_lead(P, s);
-        launch_pass_end(P, s);
         launch_pass_start(P, s);
         LF_HIP(hipGetLastError());
+        c.k = predicted_inner(P, h.n_outer);
+        return mixed_block(P, c);
     }
+    if (!h.inner_done) {
+        // the pass needs more than predicted: small top-ups
+        if (adaptive) c.k = 2;
+        return mixed_block(P, c);
+    }
+    // pass finished: correct, check, and (unless it may have been the last one)
+    // start the next pass, all no-ops once the solve is done
+    const int32_t pass = h.n_outer;
+    if (pass < lf_problem::kPassTrack) P->last_inner[pass] = h.inner_iter;
+    prof_lead(P, s);
+    launch_pass_end(P, s);
+    LF_HIP(hipGetLastError());
+    if (adaptive && P->last_outer > 0 && pass + 1 >= P->last_outer) {
+        c.stage = 1;
+        c.k = 0;
+        return mixed_block(P, c);
+    }
+    launch_pass_start(P, s);
+    LF_HIP(hipGetLastError());
+    if (adaptive) c.k = predicted_inner(P, pass + 1);
     return mixed_block(P, c);
 }
 

@@ -22,9 +22,10 @@ namespace lf {
 // |wA - pA| + |b - pA| of the normalisation factor (pA = row sum * mean(x0),
 // the mean taken beforehand), and with the diagonal preconditioner
 // rD = 1/diag, w.r and the first direction p = w; partial sums of |r|, those
-// terms and w.r.  kMixed (precision form) instead writes the FP32 copies of
-// the matrix and starts the first refinement pass: r32 = r rounded, d = 0 and
-// the partial sums of |r32| and w32.r32.
+// terms and w.r.  kMixed (precision form) instead starts the first refinement
+// pass of the scaled inner system: s = sqrt(diag) rounded to FP32, the scaled
+// residual rs = r / s rounded to FP32, y = 0, and the partial sums of s|rs|
+// (the L1 norm of the residual the inner solve sees) and rs.rs.
 template <class Lay, bool kFull, bool kSetup, bool kMixed>
 __global__ void __launch_bounds__(kCellBlock)
 k_assemble(SolverParams sp, double rdt, double DT, Lay L, const int32_t *__restrict__ bface_start,
@@ -35,13 +36,11 @@ k_assemble(SolverParams sp, double rdt, double DT, Lay L, const int32_t *__restr
            double *__restrict__ upper, double *__restrict__ diag, double *__restrict__ source,
            double *__restrict__ diagB, double *__restrict__ srcB, double *__restrict__ int_coeff,
            double *__restrict__ bou_coeff, int32_t diag_pc, double *__restrict__ r, double *__restrict__ rD,
-           double *__restrict__ part, const PcgState *__restrict__ st, float *__restrict__ coef32,
-           float *__restrict__ diag32, float *__restrict__ rD32, float *__restrict__ r32,
-           float *__restrict__ d32, double *__restrict__ p) {
+           double *__restrict__ part, const PcgState *__restrict__ st, float *__restrict__ sig32,
+           float *__restrict__ r32, float *__restrict__ d32, double *__restrict__ p) {
     const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const double x_avg = kSetup ? st->x_avg : 0.0;
-    float rd32 = 0.0f;
     if (c < sp.n) {
         RowCoefs<Lay> rcf;
         const double lap_diag = assemble_coefs<kFull>(L, c, DT, coef, upper, rcf);
@@ -68,19 +67,12 @@ k_assemble(SolverParams sp, double rdt, double DT, Lay L, const int32_t *__restr
         if (kFull) { diag[c] = d; source[c] = s; }
         diagB[c] = db;
         srcB[c] = sb;
-        if (kMixed) {
-            // FP32 copy of the solve-time matrix for the inner solves
-            store_coef32(L, c, coef, rcf, coef32);
-            diag32[c] = static_cast<float>(db);
-            rd32 = static_cast<float>(1.0 / db);
-            rD32[c] = rd32;
-        }
         if (kSetup) {
             double ax = db * xc, sa = db;
             row_amul_sum(L, c, coef, rcf, T, ax, sa);
             const double rc = sb - ax;
             const double pa = sa * x_avg;
-            r[c] = rc;
+            if (!kMixed) r[c] = rc;
             acc[0] = fabs(rc);
             acc[1] = fabs(ax - pa) + fabs(sb - pa);
             if (diag_pc && !kMixed) {       // the precision form keeps only the FP32 rD
@@ -91,13 +83,15 @@ k_assemble(SolverParams sp, double rdt, double DT, Lay L, const int32_t *__restr
                 p[c] = wc;                  // first search direction p = w (used only if the solve iterates)
             }
             if (kMixed) {
-                // start of the first refinement pass: r32 = r rounded, d = 0
-                const float r32c = static_cast<float>(rc);
-                r32[c] = r32c;
+                // start of the first refinement pass: rs = r / s rounded, y = 0
+                const float sg32 = static_cast<float>(sqrt(db));
+                const double sg = sg32;
+                sig32[c] = sg32;
+                const float rs = static_cast<float>(rc / sg);
+                r32[c] = rs;
                 d32[c] = 0.0f;
-                const float w32 = rd32 * r32c;
-                acc[3] = fabs(static_cast<double>(r32c));
-                acc[4] = static_cast<double>(w32) * static_cast<double>(r32c);
+                acc[3] = fabs(sg * static_cast<double>(rs));
+                acc[4] = static_cast<double>(rs) * static_cast<double>(rs);
             }
         }
     }
@@ -134,7 +128,7 @@ template <int K>
 __global__ void __launch_bounds__(kCellBlock)
 k_amul_walk(BandLayout<K> L, const double *__restrict__ diagB, const double *__restrict__ coef,
             const double *__restrict__ x, double *__restrict__ y) {
-    band_walk<K, false>(L, diagB, coef, x, y);
+    band_walk<K, false, false>(L, diagB, coef, x, y);
 }
 
 // band layout: face-order copy of the coefficients, upper_f at slot k*N + owner_f
@@ -196,16 +190,16 @@ k_amul_dot(SolverParams sp, Lay L, const double *__restrict__ diagB, const doubl
 }
 
 // k_amul_dot by the row walk: sp.grid_amul workgroups, whose partials of q.p
-// fill the first sp.grid_amul entries of the p.q slot
+// fill the first sp.grid_amul entries of the p.q slot (slots sp.grid apart)
 template <int K>
 __global__ void __launch_bounds__(kCellBlock)
 k_amul_dot_walk(SolverParams sp, BandLayout<K> L, const double *__restrict__ diagB, const double *__restrict__ coef,
                 const double *__restrict__ p, double *__restrict__ q, double *__restrict__ part,
                 const PcgState *__restrict__ st) {
     if (st->done) return;
-    double acc[1] = {band_walk<K, true>(L, diagB, coef, p, q)};
-    const int slots[1] = {0};
-    write_partials<1>(part + static_cast<int64_t>(kPartPq) * sp.grid, sp.grid_amul, slots, acc);
+    double acc[1] = {band_walk<K, true, false>(L, diagB, coef, p, q)};
+    const int slots[1] = {kPartPq};
+    write_partials<1>(part, sp.grid, slots, acc);
 }
 
 // r -= alpha q; partial sums of |r| and (diagonal) of w.r, w = rD r
@@ -373,10 +367,10 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(SolverParams sp, const d
         }
     } else if (Mode == kFinAlpha) {
         if (st->done) return;
-        // the Amul launch wrote sp.grid_amul partials from the slot's start
+        // the Amul launch wrote sp.grid_amul partials
         double v[1];
-        const int slots[1] = {0};
-        reduce_partials<1>(part + static_cast<int64_t>(kPartPq) * G, sp.grid_amul, slots, v);
+        const int slots[1] = {kPartPq};
+        reduce_partials<1>(part, G, sp.grid_amul, slots, v);
         if (threadIdx.x == 0) {
             const double pq = v[0];
             if (!isfinite(pq)) {
@@ -472,8 +466,8 @@ static void launch_assemble_t(lf_problem *P, hipStream_t s) {
         LF_LAUNCH(P, LF_K_ASSEMBLE, s, kern, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, rdt, P->DT, lay,
                   m->bface_start, m->bface_list, m->bface_patch, m->bmag_sf, m->bdelta, P->patch_type,
                   P->patch_value, m->V, P->T, P->coef, P->upper, P->diag, P->source, P->diagB, P->srcB,
-                  P->int_coeff, P->bou_coeff, diag_pc ? 1 : 0, P->r, P->rD, P->part, P->state, P->coef32,
-                  P->diag32, P->rD32, P->r32, P->d32, P->p);
+                  P->int_coeff, P->bou_coeff, diag_pc ? 1 : 0, P->r, P->rD, P->part, P->state, P->sig32,
+                  P->r32, P->d32, P->p);
     });
     if (kFull && P->banded && m->F > 0) {
         BandOffsets bo{};
@@ -500,8 +494,12 @@ void launch_fin(lf_problem *P, hipStream_t s) {
 lf_status launch_assemble_setup(lf_problem *P, hipStream_t s) {
     LF_LAUNCH(P, LF_K_SETUP1, s, k_sum_x, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->T, P->part);
     launch_fin<kFinMean>(P, s);
-    if (P->opts.precision == LF_PREC_MIXED) launch_assemble_t<false, true, true>(P, s);
-    else launch_assemble_t<false, true, false>(P, s);
+    if (P->opts.precision == LF_PREC_MIXED) {
+        launch_assemble_t<false, true, true>(P, s);
+        launch_mx_scale(P, s);
+    } else {
+        launch_assemble_t<false, true, false>(P, s);
+    }
     LF_HIP(hipGetLastError());
     return LF_OK;
 }

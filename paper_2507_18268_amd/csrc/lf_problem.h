@@ -14,8 +14,8 @@ enum PartialSlot : int {
     kPartNf = 2,     // sum |A x0 - pA| + |b - pA|
     kPartWr = 3,     // sum w.r
     kPartPq = 4,     // sum p.Ap
-    kPartSumR32 = 5, // precision form, at a pass start: sum |r32| (r32 = r rounded to FP32)
-    kPartWr32 = 6,   //   and sum w32.r32, w32 = rD32 r32
+    kPartSumR32 = 5, // precision form, at a pass start: sum |r| of the inner solve's residual
+    kPartWr32 = 6,   //   (sum s_c |rs_c|, rs its scaled form) and sum rs.rs
     kNumPart = 7
 };
 
@@ -37,11 +37,11 @@ struct PcgState {
     int32_t nonfinite;
     int32_t flag;         // scratch flag (input checks)
     // mixed precision: inner FP32 solve of one refinement pass
-    double inner_target;  // stop when sum|r32| <= this
+    double inner_target;  // stop when the inner residual's L1 norm <= this
     int32_t inner_done;
     int32_t inner_iter;   // iterations of the current pass
     int32_t n_outer;      // refinement passes
-    int32_t pad2;
+    int32_t inner_pend;   // y += alpha p of the last inner update not applied yet
 };
 
 constexpr int kMaxGraphLog = 6;   // largest captured block: 64 iterations
@@ -55,6 +55,7 @@ struct SolverParams {
     int32_t n_red;        // DIC: first black cell
     int32_t max_outer;    // mixed: refinement passes cap
     int32_t grid_amul;    // workgroups of the FP64 Amul launch (= its p.q partials)
+    int32_t grid_mx_amul; // workgroups of the FP32 inner Amul launch (= its p.q partials)
     double inner_tol;     // mixed: relative reduction of each inner solve
 };
 
@@ -84,6 +85,7 @@ struct lf_problem {
     // mixed precision (FP32 inner solve)
     float *coef32 = nullptr, *diag32 = nullptr, *rD32 = nullptr;
     float *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
+    float *sig32 = nullptr;                    // multi-kernel precision form: sqrt(diagB) in FP32
     // host side
     lf::PcgState *h_state = nullptr;           // pinned
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
@@ -91,7 +93,11 @@ struct lf_problem {
     hipGraphExec_t g_iter[lf::kMaxGraphLog + 1] = {};   // 2^i PCG iterations
     hipGraphExec_t g_inner[lf::kMaxGraphLog + 1] = {};  // 2^i inner FP32 iterations
     int32_t last_iters = 0;
-    int32_t last_inner = 0;
+    // precision form, for sizing the iteration blocks: inner iterations of
+    // each refinement pass and the number of passes of the last step
+    static constexpr int kPassTrack = 8;
+    int32_t last_inner[kPassTrack] = {};
+    int32_t last_outer = 0;
     bool assembled = false;
     size_t ws_bytes = 0;
     // per-kernel device timing (diagnostics)

@@ -64,6 +64,8 @@ void carve_problem(Carver &cv, const lf_mesh *m, const lf_solver_opts &o, lf_pro
 void carve_mixed(Carver &cv, const lf_mesh *m, bool banded, lf_problem *P);
 lf_status launch_assemble(lf_problem *P, bool full, hipStream_t s);
 lf_status launch_assemble_setup(lf_problem *P, hipStream_t s);
+// precision form: FP32 coefficients of the scaled matrix, after the assembly
+void launch_mx_scale(lf_problem *P, hipStream_t s);
 // A solve is driven in two halves so that one host loop can drive several
 // problems on their own streams: *_start enqueues the set-up and the first
 // block of iterations, followed by an async copy of the solver state and
@@ -74,7 +76,8 @@ struct SolveCtx {
     int32_t fixed_k = 0;   // iterations per block when fixed (>0), else adaptive
     int32_t k = 0;         // iterations of the next block
     int32_t launched = 0;  // iterations enqueued so far
-    int32_t stage = 0;     // FP64: 0 iterating, 1 committing
+    int32_t stage = 0;     // FP64: 0 iterating, 1 committing; mixed: 1 awaiting the
+                           // outer check of a pass before starting another
 };
 lf_status fp64_start(lf_problem *P, SolveCtx &c);
 lf_status fp64_advance(lf_problem *P, SolveCtx &c, bool *finished, lf_solve_stats *out);

@@ -1,5 +1,6 @@
-"""Precision form (FP32 inner PCG with FP64 dots / alpha / beta, FP64 outer
-refinement on the true residual) against the FP64 oracle.
+"""Precision form (FP32 inner CG on the Jacobi-scaled system with FP64 dots /
+alpha / beta, FP64 outer refinement on the true residual) against the FP64
+oracle.
 
 Per step, both solve the same system: the oracle takes one step from the
 precision form's own T_n, and T_{n+1} must agree to a max relative error of
@@ -32,6 +33,9 @@ CASES = [
     ("graded_24_loose_inner", "graded_256", 24, 4, dict(inner_tol=1e-2)),
     ("graded_24_tight_inner", "graded_256", 24, 4, dict(inner_tol=1e-6)),
     ("graded_24_no_graph", "graded_256", 24, 3, dict(use_graph=0)),
+    ("graded_24_walk", "graded_256", 24, 4, dict(amul_walk=1)),
+    ("graded_13_walk_rows", "graded_256", 13, 4, dict(amul_walk=1, layout=1)),
+    ("plain_32_walk", "plain_32", None, 6, dict(amul_walk=1)),
 ]
 
 
