@@ -135,7 +135,10 @@ typedef struct lf_solver_opts {
     int32_t amul_walk;          /* LF_WALK_* (default AUTO).  Both forms give
                                    bitwise the same product; only the order of
                                    the partial sums of p.Ap differs */
-    int32_t reserved;           /* 0 */
+    int32_t inner_restart;      /* LF_PREC_MIXED: 0 (default) continues the inner CG
+                                   across refinement passes (the true residual
+                                   replaces the recurred one, the search direction
+                                   is kept); 1 restarts it at every pass */
 } lf_solver_opts;
 
 /* Per time step results. */

@@ -28,7 +28,7 @@ lf_status lf_default_opts(lf_solver_opts *o) {
     o->max_outer = 0;
     o->layout = LF_LAYOUT_AUTO;
     o->amul_walk = LF_WALK_AUTO;
-    o->reserved = 0;
+    o->inner_restart = 0;
     return LF_OK;
 }
 
@@ -83,6 +83,10 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
         set_error("unknown layout %d", opts.layout);
         return LF_EINVAL;
     }
+    if (opts.inner_restart != 0 && opts.inner_restart != 1) {
+        set_error("inner_restart must be 0 or 1");
+        return LF_EINVAL;
+    }
     if (opts.amul_walk != LF_WALK_AUTO && opts.amul_walk != LF_WALK_ON && opts.amul_walk != LF_WALK_OFF) {
         set_error("unknown amul_walk %d", opts.amul_walk);
         return LF_EINVAL;
@@ -120,6 +124,7 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
     P->sp.n = m->N;
     P->sp.grid = cell_blocks(m->N);
     P->sp.grid_mx = mx_blocks(m->N);
+    P->sp.grid_upd = opts.precond == LF_PC_DIAGONAL ? update_blocks(m->N) : P->sp.grid;
     P->sp.grid_amul = P->sp.grid;
     P->sp.grid_mx_amul = P->sp.grid_mx;
     if (P->banded && m->n_bands >= 2 && opts.amul_walk != LF_WALK_OFF) {
@@ -134,6 +139,7 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
     P->sp.n_red = m->two_colour ? m->n_red : m->N;
     P->sp.max_outer = opts.max_outer > 0 ? opts.max_outer : 50;
     P->sp.inner_tol = opts.inner_tol > 0.0 ? opts.inner_tol : 1e-5;
+    P->sp.inner_restart = opts.inner_restart ? 1 : 0;
     P->bcs.assign(bcs, bcs + m->P);
     P->ws_bytes = dry.bytes();
     Carver cv(ws);

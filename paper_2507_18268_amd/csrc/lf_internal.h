@@ -60,6 +60,7 @@ struct Carver {
 constexpr int kBlock = 256;        // threads per workgroup of the mesh-build kernels
 constexpr int kCellBlock = 512;    // threads per workgroup of the per-step kernels (one row each)
 constexpr int kMxRows = 2;         // rows per thread of the precision form's FP32 inner kernels
+constexpr int kUpdRows = 4;        // rows per thread of the FP64 update (diagonal preconditioner)
 constexpr int kFinBlock = 1024;    // threads of the one-workgroup reduction kernels
 constexpr int kNumXcd = 8;         // MI355X: 8 accelerator complex dies
 constexpr int kSlice = 64;         // rows per slice of the sliced row layout

@@ -17,6 +17,13 @@
 // the next iteration's direction kernel (which reads p anyway), and the last
 // one by the correction T += (y + alpha p) / s.
 //
+// A pass after the first continues the CG of the one before instead of
+// restarting it (a reliable update in the sense of Sleijpen and van der Vorst,
+// 1996, as used for mixed-precision CG by Clark et al., 2010): the FP64 true
+// residual replaces the recurred one and the last search direction is kept,
+// projected so that it is orthogonal to the new residual.  A restart would
+// discard the Krylov space built so far; the option inner_restart keeps it.
+//
 // The inner solve of a pass stops when the L1 norm of the residual it sees,
 // sum s_c |rs_c|, has fallen by inner_tol, or below half the outer target,
 // whichever is larger.  The refinement runs until res < kTighten * tol
@@ -83,22 +90,25 @@ k_mx_scale(SolverParams sp, Lay L, const float *__restrict__ sig32, const double
     if (c < sp.n) scale_row(L, c, static_cast<double>(sig32[c]), sig32, coef, coef32);
 }
 
-// first inner iteration: p = rs; later: y += alpha p (the previous
-// iteration's update), then p = rs + beta p; all FP32
+// first inner iteration of a pass: p = rs, or, continuing the previous pass's
+// CG, p = gamma rs + beta p; later: y += alpha p (the previous iteration's
+// update), then p = rs + beta p; all FP32
 __global__ void __launch_bounds__(kCellBlock)
 k_mx_direction(SolverParams sp, const float *__restrict__ r32, float *__restrict__ p32, float *__restrict__ d32,
                const PcgState *__restrict__ st) {
     if (inner_off(st)) return;
     const bool first = st->inner_iter == 0;
+    const bool cont = st->inner_cont != 0;
     const float beta = static_cast<float>(st->beta);
     const float alpha = static_cast<float>(st->alpha);
+    const float gamma = static_cast<float>(st->gamma);
 #pragma unroll
     for (int j = 0; j < kMxRows; ++j) {
         const int32_t c = cell_row<kMxRows>(j);
         if (c >= sp.n) continue;
         const float rc = r32[c];
         if (first) {
-            p32[c] = rc;
+            p32[c] = cont ? gamma * rc + beta * p32[c] : rc;
         } else {
             const float pc = p32[c];
             d32[c] += alpha * pc;
@@ -178,31 +188,41 @@ k_mx_correct(SolverParams sp, double *__restrict__ T, const float *__restrict__ 
     }
 }
 
-// true residual r = b - A T in FP64 and its partial sums of |r|; also the
-// start of the next pass, which runs if the outer check does not stop the
-// solve: rs = r / s rounded to FP32, y = 0, partial sums of s|rs| and rs.rs
+// one row of a pass end: from ax = (A T)_c, the FP64 residual r and the start
+// of the next pass, which runs if the outer check does not stop the solve:
+// rs = r / s rounded to FP32, y = 0; partial sums of |r|, s|rs|, rs.rs and,
+// when the pass that just ended has a direction p (it iterated), rs.p
+__device__ __forceinline__ void pass_end_row(int64_t c, double ax, double db, bool keep,
+                                             const double *__restrict__ srcB, const float *__restrict__ p32,
+                                             float *__restrict__ r32, float *__restrict__ d32, double (&acc)[4]) {
+    const double rc = srcB[c] - ax;
+    acc[0] += fabs(rc);
+    const double sg = static_cast<float>(sqrt(db));     // the s of the scaled system
+    const float rs = static_cast<float>(rc / sg);
+    r32[c] = rs;
+    d32[c] = 0.0f;
+    acc[1] += fabs(sg * static_cast<double>(rs));
+    acc[2] += static_cast<double>(rs) * static_cast<double>(rs);
+    if (keep) acc[3] += static_cast<double>(rs) * static_cast<double>(p32[c]);
+}
+
+// true residual r = b - A T in FP64 and the start of the next pass (above)
 template <class Lay>
 __global__ void __launch_bounds__(kCellBlock)
 k_mx_residual(SolverParams sp, Lay L, const double *__restrict__ diagB, const double *__restrict__ coef,
-              const double *__restrict__ srcB, const double *__restrict__ T, float *__restrict__ r32,
-              float *__restrict__ d32, double *__restrict__ part, const PcgState *__restrict__ st) {
+              const double *__restrict__ srcB, const double *__restrict__ T, const float *__restrict__ p32,
+              float *__restrict__ r32, float *__restrict__ d32, double *__restrict__ part,
+              const PcgState *__restrict__ st) {
     if (st->done) return;
+    const bool keep = st->inner_iter > 0;
     const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
-    double acc[3] = {0.0, 0.0, 0.0};
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (c < sp.n) {
         const double db = diagB[c];
-        const double ax = layout_dot(L, c, coef, T, db * T[c]);
-        const double rc = srcB[c] - ax;
-        acc[0] = fabs(rc);
-        const double sg = static_cast<float>(sqrt(db));     // the s of the scaled system
-        const float rs = static_cast<float>(rc / sg);
-        r32[c] = rs;
-        d32[c] = 0.0f;
-        acc[1] = fabs(sg * static_cast<double>(rs));
-        acc[2] = static_cast<double>(rs) * static_cast<double>(rs);
+        pass_end_row(c, layout_dot(L, c, coef, T, db * T[c]), db, keep, srcB, p32, r32, d32, acc);
     }
-    const int slots[3] = {kPartSumR, kPartSumR32, kPartWr32};
-    write_partials<3>(part, sp.grid, slots, acc);
+    const int slots[4] = {kPartSumR, kPartSumR32, kPartWr32, kPartRp32};
+    write_partials<4>(part, sp.grid, slots, acc);
 }
 
 // the same residual by the row walk (sp.grid_amul workgroups)
@@ -210,22 +230,16 @@ template <int K>
 __global__ void __launch_bounds__(kCellBlock)
 k_mx_residual_walk(SolverParams sp, BandLayout<K> L, const double *__restrict__ diagB,
                    const double *__restrict__ coef, const double *__restrict__ srcB, const double *__restrict__ T,
-                   float *__restrict__ r32, float *__restrict__ d32, double *__restrict__ part,
-                   const PcgState *__restrict__ st) {
+                   const float *__restrict__ p32, float *__restrict__ r32, float *__restrict__ d32,
+                   double *__restrict__ part, const PcgState *__restrict__ st) {
     if (st->done) return;
-    double acc[3] = {0.0, 0.0, 0.0};
+    const bool keep = st->inner_iter > 0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     band_walk_rows<K, true, false>(L, diagB, coef, T, [&](int64_t c, double ax, double, double db) {
-        const double rc = srcB[c] - ax;
-        acc[0] += fabs(rc);
-        const double sg = static_cast<float>(sqrt(db));
-        const float rs = static_cast<float>(rc / sg);
-        r32[c] = rs;
-        d32[c] = 0.0f;
-        acc[1] += fabs(sg * static_cast<double>(rs));
-        acc[2] += static_cast<double>(rs) * static_cast<double>(rs);
+        pass_end_row(c, ax, db, keep, srcB, p32, r32, d32, acc);
     });
-    const int slots[3] = {kPartSumR, kPartSumR32, kPartWr32};
-    write_partials<3>(part, sp.grid, slots, acc);
+    const int slots[4] = {kPartSumR, kPartSumR32, kPartWr32, kPartRp32};
+    write_partials<4>(part, sp.grid, slots, acc);
 }
 
 // one-workgroup decisions of the refinement
@@ -240,11 +254,25 @@ __global__ void __launch_bounds__(kFinBlock) k_mx_finalize(SolverParams sp, cons
         if (st->done) return;
         // the first pass starts from the assembly's partials (sp.grid of them),
         // later ones from the residual launch's (sp.grid_amul)
-        double v[2];
-        const int slots[2] = {kPartSumR32, kPartWr32};
-        reduce_partials<2>(part, G, st->n_outer == 0 ? sp.grid : sp.grid_amul, slots, v);
+        double v[3];
+        const int slots[3] = {kPartSumR32, kPartWr32, kPartRp32};
+        reduce_partials<3>(part, G, st->n_outer == 0 ? sp.grid : sp.grid_amul, slots, v);
         if (threadIdx.x == 0) {
             const double target = fmax(sp.inner_tol * v[0], 0.5 * kTighten * sp.tol * st->nf);
+            // a later pass continues the CG of the one before (which iterated):
+            // the true residual replaces the recurred one, and the last
+            // direction p is kept, made orthogonal to it (rs.p = 0, which CG's
+            // alpha = rs.rs / p.Ap assumes): p = gamma rs + beta p with
+            // beta = rs.rs / (rs.rs before the replacement) and
+            // gamma = 1 - beta rs.p / rs.rs
+            const bool cont = !sp.inner_restart && st->n_outer > 0 && st->inner_iter > 0 && st->wArA > 0.0 &&
+                              v[1] > 0.0 && isfinite(v[1]) && isfinite(v[2]);
+            st->inner_cont = cont ? 1 : 0;
+            if (cont) {
+                const double beta = v[1] / st->wArA;
+                st->beta = beta;
+                st->gamma = 1.0 - beta * (v[2] / v[1]);
+            }
             st->inner_target = target;
             st->inner_iter = 0;
             st->inner_pend = 0;
@@ -363,12 +391,12 @@ static void launch_pass_end(lf_problem *P, hipStream_t s) {
             if (P->walk) {
                 LF_LAUNCH(P, LF_K_MIXED_RESIDUAL, s, k_mx_residual_walk<K>,
                           dim3(static_cast<unsigned>(P->sp.grid_amul)), dim3(kCellBlock), 0, s, P->sp, lay,
-                          P->diagB, P->coef, P->srcB, P->T, P->r32, P->d32, P->part, P->state);
+                          P->diagB, P->coef, P->srcB, P->T, P->p32, P->r32, P->d32, P->part, P->state);
                 return;
             }
         }
         LF_LAUNCH(P, LF_K_MIXED_RESIDUAL, s, k_mx_residual<decltype(lay)>, cell_grid(P), dim3(kCellBlock), 0, s,
-                  P->sp, lay, P->diagB, P->coef, P->srcB, P->T, P->r32, P->d32, P->part, P->state);
+                  P->sp, lay, P->diagB, P->coef, P->srcB, P->T, P->p32, P->r32, P->d32, P->part, P->state);
     });
     launch_mx_fin<kMxOuter>(P, s);
 }

@@ -202,22 +202,29 @@ k_amul_dot_walk(SolverParams sp, BandLayout<K> L, const double *__restrict__ dia
     write_partials<1>(part, sp.grid, slots, acc);
 }
 
-// r -= alpha q; partial sums of |r| and (diagonal) of w.r, w = rD r
+// r -= alpha q; partial sums of |r| and (diagonal) of w.r, w = rD r.  With
+// the diagonal preconditioner each thread takes kUpdRows rows (fewer partials
+// for the reduction that follows: sp.grid_upd workgroups); with DIC one row,
+// since the DIC sweep that follows writes the w.r partials on the cell grid.
+
 template <bool kDiag>
 __global__ void __launch_bounds__(kCellBlock)
 k_update(SolverParams sp, const double *__restrict__ q, double *__restrict__ r, const double *__restrict__ rD,
          double *__restrict__ part, const PcgState *__restrict__ st) {
     if (st->done) return;
+    constexpr int R = kDiag ? kUpdRows : 1;
     const double alpha = st->alpha;
-    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
     double acc[2] = {0.0, 0.0};
-    if (c < sp.n) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int32_t c = cell_row<R>(j);
+        if (c >= sp.n) continue;
         const double rc = r[c] - alpha * q[c];
         r[c] = rc;
-        acc[0] = fabs(rc);
+        acc[0] += fabs(rc);
         if (kDiag) {
             const double wc = rD[c] * rc;
-            acc[1] = wc * rc;
+            acc[1] += wc * rc;
         }
     }
     const int slots[2] = {kPartSumR, kPartWr};
@@ -387,7 +394,7 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(SolverParams sp, const d
         if (st->done) return;
         double v[2];
         const int slots[2] = {kPartSumR, kPartWr};
-        reduce_partials<2>(part, G, slots, v);
+        reduce_partials<2>(part, G, sp.grid_upd, slots, v);       // the update's partials
         if (threadIdx.x == 0) {
             const double res = v[0] / st->nf;
             const int32_t k = st->n_iter + 1;
@@ -556,7 +563,8 @@ static lf_status launch_iteration(lf_problem *P, hipStream_t s) {
     });
     launch_fin<kFinAlpha>(P, s);
     if (diag_pc) {
-        LF_LAUNCH(P, LF_K_UPDATE, s, k_update<true>, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->q, P->r,
+        LF_LAUNCH(P, LF_K_UPDATE, s, k_update<true>, dim3(static_cast<unsigned>(P->sp.grid_upd)),
+                  dim3(kCellBlock), 0, s, P->sp, P->q, P->r,
                   P->rD, P->part, P->state);
     } else {
         LF_LAUNCH(P, LF_K_UPDATE, s, k_update<false>, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->q, P->r,

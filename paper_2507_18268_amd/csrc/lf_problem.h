@@ -15,8 +15,9 @@ enum PartialSlot : int {
     kPartWr = 3,     // sum w.r
     kPartPq = 4,     // sum p.Ap
     kPartSumR32 = 5, // precision form, at a pass start: sum |r| of the inner solve's residual
-    kPartWr32 = 6,   //   (sum s_c |rs_c|, rs its scaled form) and sum rs.rs
-    kNumPart = 7
+    kPartWr32 = 6,   //   (sum s_c |rs_c|, rs its scaled form) and sum rs.rs,
+    kPartRp32 = 7,   //   and sum rs.p with the previous pass's last direction p
+    kNumPart = 8
 };
 
 // Solver state on the device.  Written only by the one-workgroup reduction
@@ -29,7 +30,7 @@ struct PcgState {
     double alpha;         // step length of the current iteration
     double beta;          // direction coefficient of the next iteration
     double x_avg;         // mean of x0
-    double pad;
+    double gamma;         // mixed: weight of rs in the first direction of a continued pass
     int32_t n_iter;
     int32_t done;
     int32_t converged;
@@ -42,6 +43,8 @@ struct PcgState {
     int32_t inner_iter;   // iterations of the current pass
     int32_t n_outer;      // refinement passes
     int32_t inner_pend;   // y += alpha p of the last inner update not applied yet
+    int32_t inner_cont;   // this pass continues the previous one's CG (keeps its direction)
+    int32_t pad3;
 };
 
 constexpr int kMaxGraphLog = 6;   // largest captured block: 64 iterations
@@ -56,6 +59,8 @@ struct SolverParams {
     int32_t max_outer;    // mixed: refinement passes cap
     int32_t grid_amul;    // workgroups of the FP64 Amul launch (= its p.q partials)
     int32_t grid_mx_amul; // workgroups of the FP32 inner Amul launch (= its p.q partials)
+    int32_t inner_restart;// mixed: 1 restarts the inner CG at every refinement pass
+    int32_t grid_upd;     // workgroups of the FP64 update launch (= its |r| and w.r partials)
     double inner_tol;     // mixed: relative reduction of each inner solve
 };
 

@@ -12,6 +12,11 @@ inline int32_t mx_blocks(int32_t n) {
     return n > 0 ? (n + kTile - 1) / kTile : 1;
 }
 inline dim3 mx_grid(const lf_problem *P) { return dim3(static_cast<unsigned>(P->sp.grid_mx)); }
+// workgroups of the FP64 update with the diagonal preconditioner
+inline int32_t update_blocks(int32_t n) {
+    constexpr int32_t kTile = kCellBlock * kUpdRows;
+    return n > 0 ? (n + kTile - 1) / kTile : 1;
+}
 
 enum FinMode : int { kFinMean = 0, kFinStart = 1, kFinAlpha = 2, kFinBeta = 3 };
 template <int Mode>

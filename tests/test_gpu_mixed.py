@@ -36,6 +36,9 @@ CASES = [
     ("graded_24_walk", "graded_256", 24, 4, dict(amul_walk=1)),
     ("graded_13_walk_rows", "graded_256", 13, 4, dict(amul_walk=1, layout=1)),
     ("plain_32_walk", "plain_32", None, 6, dict(amul_walk=1)),
+    ("graded_24_restart", "graded_256", 24, 4, dict(inner_restart=1)),
+    ("permuted_20_restart", "permuted_192", 20, 4, dict(inner_restart=1)),
+    ("graded_24_tight_continued", "graded_256", 24, 4, dict(inner_tol=1e-3)),
 ]
 
 
