@@ -280,7 +280,9 @@ __device__ __forceinline__ A walk_row_dot(const BandLayout<K> &L, int64_t c, con
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        a[K + k] = coef[k * n + c];
+        // the band-1 coefficient is read by this thread only (the next row
+        // takes it from a register): stream it past the caches
+        a[K + k] = k == 1 ? __builtin_nontemporal_load(&coef[k * n + c]) : coef[k * n + c];
         if (k == 1) {
             xv[K + k] = x_up;
         } else {

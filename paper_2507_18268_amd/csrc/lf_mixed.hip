@@ -111,7 +111,8 @@ k_mx_direction(SolverParams sp, const float *__restrict__ r32, float *__restrict
             p32[c] = cont ? gamma * rc + beta * p32[c] : rc;
         } else {
             const float pc = p32[c];
-            d32[c] += alpha * pc;
+            // y is next needed an iteration later: stream it past the caches
+            __builtin_nontemporal_store(__builtin_nontemporal_load(&d32[c]) + alpha * pc, &d32[c]);
             p32[c] = rc + beta * pc;
         }
     }

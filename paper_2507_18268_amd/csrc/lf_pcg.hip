@@ -157,12 +157,14 @@ k_direction(SolverParams sp, const double *__restrict__ rD, const double *__rest
     const double beta = st->beta, alpha = st->alpha;
     const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
     if (c < sp.n) {
-        const double wc = kDiag ? rD[c] * r[c] : w[c];
+        const double wc = kDiag ? __builtin_nontemporal_load(&rD[c]) * r[c] : w[c];
         if (first) {
             p[c] = wc;
         } else {
             const double pc = p[c];
-            x[c] += alpha * pc;
+            // x is next needed an iteration later: stream it past the caches
+            // that p, read by the product that follows, can use
+            __builtin_nontemporal_store(__builtin_nontemporal_load(&x[c]) + alpha * pc, &x[c]);
             p[c] = wc + beta * pc;
         }
     }
@@ -219,7 +221,7 @@ k_update(SolverParams sp, const double *__restrict__ q, double *__restrict__ r, 
     for (int j = 0; j < R; ++j) {
         const int32_t c = cell_row<R>(j);
         if (c >= sp.n) continue;
-        const double rc = r[c] - alpha * q[c];
+        const double rc = r[c] - alpha * __builtin_nontemporal_load(&q[c]);
         r[c] = rc;
         acc[0] += fabs(rc);
         if (kDiag) {
