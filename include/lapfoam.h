@@ -185,6 +185,16 @@ lf_status lf_mesh_destroy(lf_mesh *mesh);   /* NULL-safe; does not free the work
  * entries 0).  Problems on a mesh with n_bands > 0 can use LF_LAYOUT_BANDS. */
 lf_status lf_mesh_bands(const lf_mesh *mesh, int32_t *n_bands, int32_t *offsets);
 
+/* Cell order of the solver's arrays.  A mesh without band form and without a
+ * two-colour numbering is stored with its cells sorted by the Morton (Z-order)
+ * key of their centres (21 bits per axis over the bounding box, ties by cell
+ * index), so that a row's neighbours lie near it in memory; every row keeps its
+ * entries in the mesh's face order, so each row sum is unchanged.  Fields still
+ * cross this interface in the mesh's order.  *reordered = 1 for such a mesh;
+ * order[N] (host, may be NULL) receives the mesh cell of each solver row
+ * (the identity when not reordered). */
+lf_status lf_mesh_cell_order(const lf_mesh *mesh, int32_t *reordered, int32_t *order);
+
 /* Test hook: copies the device addressing to host arrays (any may be NULL):
  * owner_start[N+1] (faces owned by c are [owner_start[c], owner_start[c+1])),
  * losort[F], losort_start[N+1] (faces whose neighbour is c are

@@ -211,6 +211,55 @@ lf_status lf_problem_amul_walk(const lf_problem *P, int32_t *walk) {
     return LF_OK;
 }
 
+// Cell fields cross the boundary in the mesh's cell order; the solver keeps
+// them in its own (lf_mesh::iperm).  y[r] = x[iperm[r]] and y[iperm[r]] = x[r].
+__global__ void k_to_solver_order(int32_t n, const int32_t *__restrict__ iperm, const double *__restrict__ x,
+                                  double *__restrict__ y) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r < n) y[r] = x[iperm[r]];
+}
+
+__global__ void k_to_mesh_order(int32_t n, const int32_t *__restrict__ iperm, const double *__restrict__ x,
+                                double *__restrict__ y) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r < n) y[iperm[r]] = x[r];
+}
+
+// dst (solver order) from src (mesh order, device), or a copy without a cell order
+static lf_status to_solver_order(lf_problem *P, const double *src, double *dst) {
+    const lf_mesh *m = P->mesh;
+    if (m->iperm)
+        hipLaunchKernelGGL(k_to_solver_order, dim3((m->N + kBlock - 1) / kBlock), dim3(kBlock), 0, P->stream, m->N,
+                           m->iperm, src, dst);
+    else
+        LF_HIP(hipMemcpyAsync(dst, src, sizeof(double) * m->N, hipMemcpyDeviceToDevice, P->stream));
+    LF_HIP(hipGetLastError());
+    return LF_OK;
+}
+
+static lf_status to_mesh_order(lf_problem *P, const double *src, double *dst) {
+    const lf_mesh *m = P->mesh;
+    if (m->iperm)
+        hipLaunchKernelGGL(k_to_mesh_order, dim3((m->N + kBlock - 1) / kBlock), dim3(kBlock), 0, P->stream, m->N,
+                           m->iperm, src, dst);
+    else
+        LF_HIP(hipMemcpyAsync(dst, src, sizeof(double) * m->N, hipMemcpyDeviceToDevice, P->stream));
+    LF_HIP(hipGetLastError());
+    return LF_OK;
+}
+
+// a solver-order field to host memory in mesh order (through the scratch p2)
+static lf_status download_mesh_order(lf_problem *P, const double *src, double *host) {
+    const size_t bytes = sizeof(double) * P->mesh->N;
+    if (P->mesh->iperm) {
+        LF_TRY(to_mesh_order(P, src, P->p2));
+        LF_HIP(hipMemcpyAsync(host, P->p2, bytes, hipMemcpyDeviceToHost, P->stream));
+    } else {
+        LF_HIP(hipMemcpyAsync(host, src, bytes, hipMemcpyDeviceToHost, P->stream));
+    }
+    return LF_OK;
+}
+
 lf_status lf_set_T(lf_problem *P, const double *T, int32_t on_device) {
     clear_error();
     if (!P || !T) { set_error("NULL argument"); return LF_EINVAL; }
@@ -218,24 +267,27 @@ lf_status lf_set_T(lf_problem *P, const double *T, int32_t on_device) {
     if (!on_device) {
         for (int32_t c = 0; c < N; ++c)
             if (!std::isfinite(T[c])) { set_error("T[%d] is not finite", c); return LF_EINVAL; }
-        LF_HIP(hipMemcpyAsync(P->T, T, sizeof(double) * N, hipMemcpyHostToDevice, P->stream));
+        if (P->mesh->iperm) {
+            LF_HIP(hipMemcpyAsync(P->p2, T, sizeof(double) * N, hipMemcpyHostToDevice, P->stream));
+            LF_TRY(to_solver_order(P, P->p2, P->T));
+        } else {
+            LF_HIP(hipMemcpyAsync(P->T, T, sizeof(double) * N, hipMemcpyHostToDevice, P->stream));
+        }
         LF_HIP(hipStreamSynchronize(P->stream));
         return LF_OK;
     }
     bool ok = false;
     LF_TRY(check_finite_device(P, T, &ok));
     if (!ok) { set_error("T holds a non-finite value"); return LF_EINVAL; }
-    LF_HIP(hipMemcpyAsync(P->T, T, sizeof(double) * N, hipMemcpyDeviceToDevice, P->stream));
-    return LF_OK;
+    return to_solver_order(P, T, P->T);
 }
 
 lf_status lf_get_T(lf_problem *P, double *T, int32_t on_device) {
     clear_error();
     if (!P || !T) { set_error("NULL argument"); return LF_EINVAL; }
-    const int32_t N = P->mesh->N;
-    LF_HIP(hipMemcpyAsync(T, P->T, sizeof(double) * N, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                          P->stream));
-    if (!on_device) LF_HIP(hipStreamSynchronize(P->stream));
+    if (on_device) return to_mesh_order(P, P->T, T);
+    LF_TRY(download_mesh_order(P, P->T, T));
+    LF_HIP(hipStreamSynchronize(P->stream));
     return LF_OK;
 }
 
@@ -258,7 +310,7 @@ lf_status lf_get_boundary_T(lf_problem *P, double *Tb, int32_t on_device) {
     if (m->B == 0) return LF_OK;
     double *dst = on_device ? Tb : P->Tb;
     hipLaunchKernelGGL(k_boundary_values, dim3(static_cast<unsigned>((m->B + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       P->stream, m->B, m->bface_cell, m->bface_patch, P->patch_type, P->patch_value, P->T, dst);
+                       P->stream, m->B, m->rbface_cell, m->bface_patch, P->patch_type, P->patch_value, P->T, dst);
     LF_HIP(hipGetLastError());
     if (!on_device) {
         LF_HIP(hipMemcpyAsync(Tb, P->Tb, sizeof(double) * m->B, hipMemcpyDeviceToHost, P->stream));
@@ -283,10 +335,11 @@ lf_status lf_get_matrix(lf_problem *P, double *diag, double *upper, double *sour
     const lf_mesh *m = P->mesh;
     hipStream_t s = P->stream;
     const size_t N = m->N, F = m->F, B = m->B;
-    if (diag) LF_HIP(hipMemcpyAsync(diag, P->diag, 8 * N, hipMemcpyDeviceToHost, s));
-    if (source) LF_HIP(hipMemcpyAsync(source, P->source, 8 * N, hipMemcpyDeviceToHost, s));
-    if (diag_b) LF_HIP(hipMemcpyAsync(diag_b, P->diagB, 8 * N, hipMemcpyDeviceToHost, s));
-    if (source_b) LF_HIP(hipMemcpyAsync(source_b, P->srcB, 8 * N, hipMemcpyDeviceToHost, s));
+    (void)N;
+    if (diag) LF_TRY(download_mesh_order(P, P->diag, diag));
+    if (source) LF_TRY(download_mesh_order(P, P->source, source));
+    if (diag_b) LF_TRY(download_mesh_order(P, P->diagB, diag_b));
+    if (source_b) LF_TRY(download_mesh_order(P, P->srcB, source_b));
     if (upper && F) LF_HIP(hipMemcpyAsync(upper, P->upper, 8 * F, hipMemcpyDeviceToHost, s));
     if (int_coeff && B) LF_HIP(hipMemcpyAsync(int_coeff, P->int_coeff, 8 * B, hipMemcpyDeviceToHost, s));
     if (bou_coeff && B) LF_HIP(hipMemcpyAsync(bou_coeff, P->bou_coeff, 8 * B, hipMemcpyDeviceToHost, s));
@@ -298,7 +351,10 @@ lf_status lf_amul(lf_problem *P, const double *x, double *y) {
     clear_error();
     if (!P || !x || !y) { set_error("NULL argument"); return LF_EINVAL; }
     if (!P->assembled) { set_error("call lf_assemble first"); return LF_ESTATE; }
-    return launch_amul_hook(P, x, y);
+    if (!P->mesh->iperm) return launch_amul_hook(P, x, y);
+    LF_TRY(to_solver_order(P, x, P->p2));
+    LF_TRY(launch_amul_hook(P, P->p2, P->q));
+    return to_mesh_order(P, P->q, y);
 }
 
 lf_status lf_profile_enable(lf_problem *P, int32_t on) {

@@ -31,7 +31,8 @@ struct BatchTask {
     // problem
     double *T, *coef, *diagB, *srcB, *r;
     float *coef32, *diag32, *rD32, *r32, *p32, *q32, *d32;
-    double *snap;          // [n_steps][n] copies of T after each step, or null
+    double *snap;          // [n_steps][n] copies of T after each step (mesh cell order), or null
+    const int32_t *iperm;  // mesh cell of each solver row, or null (same order)
     // band layout of the problem's coefficients (nb = 3; 0: sliced row layout)
     const double *band_mag_sf, *band_delta;
     int32_t nb, band_d[kMaxBands];
@@ -209,8 +210,9 @@ __device__ void solve_task(const BatchTask &tk, const Lay &L, int32_t n_steps, l
         }
         if (tk.snap) {
             double *__restrict__ out = tk.snap + static_cast<int64_t>(step) * n;
+            const int32_t *__restrict__ ip = tk.iperm;
             #pragma unroll 2
-            for (int32_t c = tid; c < n; c += BS) out[c] = T[c];
+            for (int32_t c = tid; c < n; c += BS) out[ip ? ip[c] : c] = T[c];
         }
         if (tid == 0) {
             lf_solve_stats st;
@@ -376,7 +378,8 @@ lf_status lf_batch_launch(lf_batch *b, int32_t n, lf_problem *const *problems, d
         BatchTask &t = b->h_tasks[i];
         t.soff = m->soff; t.scol = m->scol; t.sface = m->sface; t.rlen = m->rlen;
         t.V = m->V; t.mag_sf = m->mag_sf; t.delta = m->delta;
-        t.bface_start = m->bface_start; t.bface_list = m->bface_list; t.bface_patch = m->bface_patch;
+        t.bface_start = m->rbface_start; t.bface_list = m->rbface_list; t.bface_patch = m->bface_patch;
+        t.iperm = m->iperm;
         t.bmag_sf = m->bmag_sf; t.bdelta = m->bdelta;
         t.patch_type = P->patch_type; t.patch_value = P->patch_value;
         t.T = P->T; t.coef = P->coef; t.diagB = P->diagB; t.srcB = P->srcB; t.r = P->r;

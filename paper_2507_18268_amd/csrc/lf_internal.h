@@ -108,7 +108,17 @@ struct lf_mesh {
     int32_t n_bands = 0;
     int32_t band_d[lf::kMaxBands] = {0, 0, 0, 0};
     double *band_mag_sf = nullptr, *band_delta = nullptr; // [n_bands*N]
-    double *V = nullptr;                                  // [N]
+    // Cell order of the solver's arrays.  Meshes without a band form and
+    // without a two-colour numbering keep their cells in Morton order of the
+    // cell centres (so that a row's neighbours lie near it in memory): the
+    // solver's cell c is the mesh's cell iperm[c], and perm is the inverse.
+    // Both are null when the mesh's own order is kept.  The lists of lists
+    // above (owner_start, losort, bface_*) stay in the mesh's numbering; the
+    // row layout, V and the rbface_* lists below are in the solver's order.
+    int32_t *perm = nullptr, *iperm = nullptr;            // [N]
+    int32_t *rbface_start = nullptr, *rbface_list = nullptr;   // [N+1], [B] boundary faces per solver row
+    int32_t *rbface_cell = nullptr;                       // [B] solver row of each boundary face
+    double *V = nullptr;                                  // [N] (solver order)
     double *mag_sf = nullptr, *delta = nullptr;           // [F]
     double *bmag_sf = nullptr, *bdelta = nullptr;         // [B]
     size_t ws_bytes = 0;

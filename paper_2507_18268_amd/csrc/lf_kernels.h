@@ -125,10 +125,12 @@ __device__ __forceinline__ A row_dot_w(int32_t base, int32_t len, const int32_t 
                                        const T *__restrict__ coef, const T *__restrict__ x, A acc) {
     int32_t col[W];
     T a[W], xv[W];
+    // the row's column indices and coefficients are read once per product:
+    // streamed past the caches, which then keep x for the gathers
 #pragma unroll
     for (int j = 0; j < W; ++j) {
-        col[j] = scol[base + kSlice * j];
-        a[j] = coef[base + kSlice * j];
+        col[j] = __builtin_nontemporal_load(&scol[base + kSlice * j]);
+        a[j] = __builtin_nontemporal_load(&coef[base + kSlice * j]);
     }
 #pragma unroll
     for (int j = 0; j < W; ++j) xv[j] = x[col[j]];

@@ -153,29 +153,33 @@ __global__ void k_sort_segments(const int32_t *__restrict__ start, int32_t n, in
 // l = c%64) sits at soff[s] + 64 j + l; entries past the row's length are
 // padding (column = c, face = 0, coefficient 0): kernels may load them but
 // never use them.
+// With a cell order (perm/iperm, see lf_mesh), row r of the layout is the
+// mesh's cell iperm[r], in the same face order, and columns are solver rows.
 __global__ void k_sell_fill(int32_t n, const int32_t *__restrict__ owner, const int32_t *__restrict__ neighbour,
                             const int32_t *__restrict__ owner_start, const int32_t *__restrict__ losort,
                             const int32_t *__restrict__ losort_start, const int32_t *__restrict__ soff,
+                            const int32_t *__restrict__ perm, const int32_t *__restrict__ iperm,
                             int32_t *__restrict__ scol, int32_t *__restrict__ sface, uint8_t *__restrict__ rlen) {
-    int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (c >= n) return;
-    const int32_t s = static_cast<int32_t>(c / kSlice), lane = static_cast<int32_t>(c % kSlice);
+    int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int32_t c = iperm ? iperm[r] : static_cast<int32_t>(r);
+    const int32_t s = static_cast<int32_t>(r / kSlice), lane = static_cast<int32_t>(r % kSlice);
     const int32_t width = (soff[s + 1] - soff[s]) / kSlice;
     int32_t idx = soff[s] + lane, j = 0;
     // the host sized every slice from the same face counts; the j < width
     // guards only keep a disagreement from writing outside the slice
     for (int32_t i = losort_start[c]; i < losort_start[c + 1] && j < width; ++i, ++j, idx += kSlice) {
         const int32_t f = losort[i];
-        scol[idx] = owner[f];
+        scol[idx] = perm ? perm[owner[f]] : owner[f];
         sface[idx] = f;
     }
     for (int32_t f = owner_start[c]; f < owner_start[c + 1] && j < width; ++f, ++j, idx += kSlice) {
-        scol[idx] = neighbour[f];
+        scol[idx] = perm ? perm[neighbour[f]] : neighbour[f];
         sface[idx] = f;
     }
-    rlen[c] = static_cast<uint8_t>(j);
+    rlen[r] = static_cast<uint8_t>(j);
     for (; j < width; ++j, idx += kSlice) {
-        scol[idx] = static_cast<int32_t>(c);
+        scol[idx] = static_cast<int32_t>(r);
         sface[idx] = 0;
     }
 }
@@ -260,8 +264,8 @@ struct MeshScratch {
     double *bS, *bC;     // [3B]
 };
 
-static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, int32_t K, lf_mesh *m,
-                       MeshScratch *s) {
+static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, int32_t K, bool reorder,
+                       lf_mesh *m, MeshScratch *s) {
     size_t n1 = static_cast<size_t>(N) + 1;
     const int32_t ns = (N + kSlice - 1) / kSlice;
     auto *owner = cv.take<int32_t>(F);
@@ -282,6 +286,14 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, i
     auto *delta = cv.take<double>(F);
     auto *bmag = cv.take<double>(B);
     auto *bdelta = cv.take<double>(B);
+    int32_t *perm = nullptr, *iperm = nullptr, *rbstart = bface_start, *rblist = bface_list, *rbcell = bface_cell;
+    if (reorder) {
+        perm = cv.take<int32_t>(N);
+        iperm = cv.take<int32_t>(N);
+        rbstart = cv.take<int32_t>(n1);
+        rblist = cv.take<int32_t>(B);
+        rbcell = cv.take<int32_t>(B);
+    }
     double *band_mag = nullptr, *band_delta = nullptr;
     if (K > 0) {
         band_mag = cv.take<double>(static_cast<size_t>(K) * N);
@@ -302,6 +314,8 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, i
         m->n_slices = ns; m->n_entries = E; m->soff = soff; m->scol = scol; m->sface = sface; m->rlen = rlen;
         m->V = V; m->mag_sf = mag_sf; m->delta = delta; m->bmag_sf = bmag; m->bdelta = bdelta;
         m->band_mag_sf = band_mag; m->band_delta = band_delta;
+        m->perm = perm; m->iperm = iperm;
+        m->rbface_start = rbstart; m->rbface_list = rblist; m->rbface_cell = rbcell;
     }
     if (s) *s = sc;
 }
@@ -309,7 +323,11 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, i
 // Slice offsets of the row layout from the row lengths (faces per cell),
 // counted on the host from the owner/neighbour lists: this only sizes the
 // workspace; the entries themselves are filled on the GPU.
-static lf_status plan_slices(const lf_mesh_desc *d, std::vector<int32_t> *soff, int64_t *E) {
+// With a cell order (iperm, solver row -> mesh cell) the rows are taken in
+// that order; `bound` sizes every slice by the longest row instead (an upper
+// bound for any order, used to size the workspace without the order).
+static lf_status plan_slices(const lf_mesh_desc *d, const std::vector<int32_t> *iperm, bool bound,
+                             std::vector<int32_t> *soff, int64_t *E) {
     const int32_t N = d->n_cells, F = d->n_faces;
     std::vector<int32_t> len(static_cast<size_t>(N), 0);
     for (int32_t f = 0; f < F; ++f) {
@@ -317,12 +335,17 @@ static lf_status plan_slices(const lf_mesh_desc *d, std::vector<int32_t> *soff, 
         if (o >= 0 && o < N) ++len[o];
         if (n >= 0 && n < N) ++len[n];
     }
+    int32_t longest = 0;
+    for (int32_t c = 0; c < N; ++c) longest = std::max(longest, len[c]);
+    const bool order = iperm && !iperm->empty();
     const int32_t ns = (N + kSlice - 1) / kSlice;
     if (soff) soff->assign(static_cast<size_t>(ns) + 1, 0);
     int64_t total = 0;
     for (int32_t s = 0; s < ns; ++s) {
-        int32_t w = 0;
-        for (int32_t c = s * kSlice; c < std::min(N, (s + 1) * kSlice); ++c) w = std::max(w, len[c]);
+        int32_t w = bound ? longest : 0;
+        if (!bound)
+            for (int32_t r = s * kSlice; r < std::min(N, (s + 1) * kSlice); ++r)
+                w = std::max(w, len[order ? (*iperm)[r] : r]);
         if (w > kMaxRowLen) {
             set_error("cell with %d faces: rows longer than %d are not supported", w, kMaxRowLen);
             return LF_EMESH;
@@ -358,6 +381,50 @@ static BandOffsets plan_bands(const lf_mesh_desc *d) {
     bo.k = k;
     for (int32_t j = 0; j < k; ++j) bo.d[j] = v[j];
     return bo;
+}
+
+// Cell order of the solver's arrays (see lf_mesh): for a mesh without band
+// form and without a two-colour numbering, the cells sorted by the Morton
+// (Z-order) key of their centres, 21 bits per axis over the bounding box,
+// ties by cell index; empty (the mesh's own order) otherwise.
+static uint64_t spread21(uint64_t v) {
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+static bool wants_cell_order(const lf_mesh_desc *d, int32_t n_bands, bool two_colour) {
+    return n_bands == 0 && !two_colour && d->n_faces > 0 && d->n_cells > 1;
+}
+
+static std::vector<int32_t> plan_cell_order(const lf_mesh_desc *d) {
+    const int32_t N = d->n_cells;
+    const double *C = d->cell_centre;
+    double lo[3] = {C[0], C[1], C[2]}, hi[3] = {C[0], C[1], C[2]};
+    for (int32_t c = 1; c < N; ++c)
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], C[3 * static_cast<int64_t>(c) + k]);
+            hi[k] = std::max(hi[k], C[3 * static_cast<int64_t>(c) + k]);
+        }
+    std::vector<std::pair<uint64_t, int32_t>> key(static_cast<size_t>(N));
+    for (int32_t c = 0; c < N; ++c) {
+        uint64_t z = 0;
+        for (int k = 0; k < 3; ++k) {
+            const double span = hi[k] - lo[k];
+            double t = span > 0.0 ? (C[3 * static_cast<int64_t>(c) + k] - lo[k]) / span : 0.0;
+            t = std::min(std::max(t, 0.0), 1.0);
+            z |= spread21(static_cast<uint64_t>(t * 2097151.0)) << k;
+        }
+        key[c] = {z, c};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<int32_t> iperm(static_cast<size_t>(N));
+    for (int32_t r = 0; r < N; ++r) iperm[r] = key[r].second;
+    return iperm;
 }
 
 // ---------------------------------------------------------------------------
@@ -474,11 +541,20 @@ const char *lf_last_error(void) { return g_err; }
 size_t lf_mesh_workspace_bytes(const lf_mesh_desc *d) {
     if (!d || d->n_cells < 1 || d->n_faces < 0 || d->n_patches < 0 || !d->patch_start) return 0;
     if (d->n_faces > 0 && (!d->owner || !d->neighbour)) return 0;
-    int64_t E = 0;
-    if (plan_slices(d, nullptr, &E) != LF_OK) return 0;
     const BandOffsets bo = plan_bands(d);
+    // whether the cells are reordered depends on the two-colour test, which
+    // needs the face lists only: the largest face owner against the smallest
+    // neighbour
+    int32_t max_owner = -1, min_nei = d->n_cells;
+    for (int32_t f = 0; f < d->n_faces; ++f) {
+        max_owner = std::max(max_owner, d->owner[f]);
+        min_nei = std::min(min_nei, d->neighbour[f]);
+    }
+    const bool reorder = wants_cell_order(d, bo.k, d->n_faces > 0 && max_owner < min_nei);
+    int64_t E = 0;
+    if (plan_slices(d, nullptr, reorder, nullptr, &E) != LF_OK) return 0;
     Carver cv(nullptr);
-    carve_mesh(cv, d->n_cells, d->n_faces, d->patch_start[d->n_patches], E, bo.k, nullptr, nullptr);
+    carve_mesh(cv, d->n_cells, d->n_faces, d->patch_start[d->n_patches], E, bo.k, reorder, nullptr, nullptr);
     return cv.bytes();
 }
 
@@ -490,12 +566,15 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
     bool two_colour = false;
     LF_TRY(validate(d, &B, &two_colour, &n_red));
     const int32_t N = d->n_cells, F = d->n_faces, P = d->n_patches;
+    const BandOffsets bo = plan_bands(d);
+    const bool reorder = wants_cell_order(d, bo.k, two_colour);
+    std::vector<int32_t> iperm_h;
+    if (reorder) iperm_h = plan_cell_order(d);
     std::vector<int32_t> soff_h;
     int64_t E = 0;
-    LF_TRY(plan_slices(d, &soff_h, &E));
-    const BandOffsets bo = plan_bands(d);
+    LF_TRY(plan_slices(d, &iperm_h, false, &soff_h, &E));
     Carver dry(nullptr);
-    carve_mesh(dry, N, F, B, E, bo.k, nullptr, nullptr);
+    carve_mesh(dry, N, F, B, E, bo.k, reorder, nullptr, nullptr);
     if (!ws || ws_bytes < dry.bytes() || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) {
         set_error("mesh workspace too small or misaligned: need %zu bytes, 256-aligned", dry.bytes());
         return LF_ENOMEM;
@@ -513,7 +592,7 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
     if (hipGetDevice(&m->device) != hipSuccess) { delete m; set_error("hipGetDevice failed"); return LF_EDEVICE; }
     Carver cv(ws);
     MeshScratch sc;
-    carve_mesh(cv, N, F, B, E, bo.k, m, &sc);
+    carve_mesh(cv, N, F, B, E, bo.k, reorder, m, &sc);
     hipStream_t s = m->stream;
 
     auto fail = [&](lf_status st) { delete m; return st; };
@@ -535,7 +614,23 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
         LF_HIPM(hipMemcpyAsync(m->neighbour, d->neighbour, sizeof(int32_t) * F, hipMemcpyHostToDevice, s));
     }
     LF_HIPM(hipMemcpyAsync(m->soff, soff_h.data(), sizeof(int32_t) * soff_h.size(), hipMemcpyHostToDevice, s));
-    LF_HIPM(hipMemcpyAsync(m->V, d->cell_volume, sizeof(double) * N, hipMemcpyHostToDevice, s));
+    std::vector<int32_t> perm_h, rbcell_h;
+    std::vector<double> V_h;
+    if (reorder) {
+        perm_h.resize(static_cast<size_t>(N));
+        for (int32_t r = 0; r < N; ++r) perm_h[iperm_h[r]] = r;
+        V_h.resize(static_cast<size_t>(N));
+        for (int32_t r = 0; r < N; ++r) V_h[r] = d->cell_volume[iperm_h[r]];
+        rbcell_h.resize(static_cast<size_t>(B));
+        for (int32_t b = 0; b < B; ++b) rbcell_h[b] = perm_h[d->bface_cell[b]];
+        LF_HIPM(hipMemcpyAsync(m->perm, perm_h.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, s));
+        LF_HIPM(hipMemcpyAsync(m->iperm, iperm_h.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, s));
+        LF_HIPM(hipMemcpyAsync(m->V, V_h.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+        if (B > 0)
+            LF_HIPM(hipMemcpyAsync(m->rbface_cell, rbcell_h.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice, s));
+    } else {
+        LF_HIPM(hipMemcpyAsync(m->V, d->cell_volume, sizeof(double) * N, hipMemcpyHostToDevice, s));
+    }
     LF_HIPM(hipMemcpyAsync(sc.C, d->cell_centre, sizeof(double) * 3 * static_cast<size_t>(N),
                            hipMemcpyHostToDevice, s));
     if (B > 0) {
@@ -554,8 +649,14 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
     if (st != LF_OK) return fail(st);
     st = group_by_key(m->bface_cell, B, N, m->bface_start, m->bface_list, sc.cnt, sc.tile, s);
     if (st != LF_OK) return fail(st);
+    if (reorder) {
+        // the same boundary lists, per solver row
+        st = group_by_key(m->rbface_cell, B, N, m->rbface_start, m->rbface_list, sc.cnt, sc.tile, s);
+        if (st != LF_OK) return fail(st);
+    }
     hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, m->owner, m->neighbour,
-                       m->owner_start, m->losort, m->losort_start, m->soff, m->scol, m->sface, m->rlen);
+                       m->owner_start, m->losort, m->losort_start, m->soff, m->perm, m->iperm, m->scol, m->sface,
+                       m->rlen);
 
     // geometry factors, faces staged in chunks
     for (int64_t f0 = 0; f0 < F; f0 += kGeomChunk) {
@@ -588,6 +689,21 @@ lf_status lf_mesh_bands(const lf_mesh *m, int32_t *n_bands, int32_t *offsets) {
     *n_bands = m->n_bands;
     if (offsets)
         for (int32_t k = 0; k < kMaxBands; ++k) offsets[k] = k < m->n_bands ? m->band_d[k] : 0;
+    return LF_OK;
+}
+
+lf_status lf_mesh_cell_order(const lf_mesh *m, int32_t *reordered, int32_t *order) {
+    clear_error();
+    if (!m || !reordered) { set_error("NULL argument"); return LF_EINVAL; }
+    *reordered = m->iperm ? 1 : 0;
+    if (order) {
+        if (m->iperm) {
+            LF_HIP(hipMemcpyAsync(order, m->iperm, sizeof(int32_t) * m->N, hipMemcpyDeviceToHost, m->stream));
+            LF_HIP(hipStreamSynchronize(m->stream));
+        } else {
+            for (int32_t c = 0; c < m->N; ++c) order[c] = c;
+        }
+    }
     return LF_OK;
 }
 

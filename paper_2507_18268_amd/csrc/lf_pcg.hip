@@ -473,7 +473,7 @@ static void launch_assemble_t(lf_problem *P, hipStream_t s) {
     with_layout(P, [&](auto lay) {
         auto kern = k_assemble<decltype(lay), kFull, kSetup, kMixed>;
         LF_LAUNCH(P, LF_K_ASSEMBLE, s, kern, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, rdt, P->DT, lay,
-                  m->bface_start, m->bface_list, m->bface_patch, m->bmag_sf, m->bdelta, P->patch_type,
+                  m->rbface_start, m->rbface_list, m->bface_patch, m->bmag_sf, m->bdelta, P->patch_type,
                   P->patch_value, m->V, P->T, P->coef, P->upper, P->diag, P->source, P->diagB, P->srcB,
                   P->int_coeff, P->bou_coeff, diag_pc ? 1 : 0, P->r, P->rD, P->part, P->state, P->sig32,
                   P->r32, P->d32, P->p);

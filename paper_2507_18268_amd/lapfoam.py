@@ -93,6 +93,7 @@ _SIGS = {
     "lf_problem_destroy": (C.c_int32, [C.c_void_p]),
     "lf_problem_layout": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32)]),
     "lf_problem_amul_walk": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "lf_mesh_cell_order": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.c_void_p]),
     "lf_problem_reset": (C.c_int32, [C.c_void_p, C.POINTER(lf_patch_bc), C.c_double, C.c_double]),
     "lf_set_T": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
     "lf_get_T": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
@@ -211,6 +212,14 @@ def lf_problem_layout(h):
     v = C.c_int32(0)
     _check(lib().lf_problem_layout(h, C.byref(v)), "lf_problem_layout")
     return v.value
+
+
+def lf_mesh_cell_order(h, n_cells):
+    """(reordered, order) of a device mesh: order[r] = mesh cell of solver row r."""
+    v = C.c_int32(0)
+    order = np.empty(n_cells, dtype=np.int32)
+    _check(lib().lf_mesh_cell_order(h, C.byref(v), order.ctypes.data), "lf_mesh_cell_order")
+    return bool(v.value), order
 
 
 def lf_problem_amul_walk(h):
@@ -380,6 +389,11 @@ class Mesh:
         self.h = lf_mesh_create(d, self.ws.data_ptr(), self.ws_bytes, self.stream)
         self.n_bands, self.band_offsets = lf_mesh_bands(self.h)
         del self._keep   # host arrays were read during the call only
+
+    def cell_order(self):
+        """(reordered, order): whether the solver keeps the cells in Morton order
+        of their centres, and the mesh cell of each solver row."""
+        return lf_mesh_cell_order(self.h, self.n_cells)
 
     def addressing(self):
         N, F, B = self.n_cells, self.n_faces, self.n_bfaces

@@ -170,6 +170,40 @@ def test_amul_walk_bitwise(L, oracle, name, mk):
     m.close()
 
 
+def _morton(C):
+    """Z-order keys of points, 21 bits per axis over their bounding box."""
+    lo, hi = C.min(axis=0), C.max(axis=0)
+    span = np.where(hi > lo, hi - lo, 1.0)
+    q = np.floor(np.clip((C - lo) / span, 0.0, 1.0) * 2097151.0).astype(np.uint64)
+    key = np.zeros(len(C), dtype=np.uint64)
+    for bit in range(21):
+        for k in range(3):
+            key |= ((q[:, k] >> np.uint64(bit)) & np.uint64(1)) << np.uint64(3 * bit + k)
+    return key
+
+
+def test_cell_order():
+    """Meshes without band form and without two colours are kept in Morton
+    order of their cell centres (a permutation, keys nondecreasing, ties by
+    index); structured and red-black numberings keep their own order."""
+    L = lapfoam()
+    base = synth.box_mesh(9, 7, 5, z_ratio=3.0)
+    rnd = synth.renumber(base, synth.random_permutation(base.n_cells, 8))
+    m = L.Mesh(rnd)
+    reordered, order = m.cell_order()
+    assert reordered
+    assert np.array_equal(np.sort(order), np.arange(rnd.n_cells))
+    key = _morton(rnd.cell_centre.reshape(-1, 3))[order]
+    assert np.all((key[1:] > key[:-1]) | ((key[1:] == key[:-1]) & (order[1:] > order[:-1])))
+    m.close()
+    for mesh in (base, synth.renumber(synth.box_mesh(6, 6, 4),
+                                      synth.red_black_numbering(synth.box_mesh(6, 6, 4))[0])):
+        m = L.Mesh(mesh)
+        reordered, order = m.cell_order()
+        assert not reordered and np.array_equal(order, np.arange(mesh.n_cells))
+        m.close()
+
+
 def test_amul_walk_option_checked(L):
     m = L.Mesh(synth.box_mesh(4, 4, 4))
     with pytest.raises(L.LapfoamError):
