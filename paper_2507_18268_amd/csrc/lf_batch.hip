@@ -24,6 +24,7 @@ struct BatchTask {
     const int32_t *soff, *scol, *sface;
     const uint8_t *rlen;
     const double *V, *mag_sf, *delta;
+    const double *emag_sf, *edelta;   // per entry of the row layout, or null
     const int32_t *bface_start, *bface_list, *bface_patch;
     const double *bmag_sf, *bdelta;
     const int32_t *patch_type;
@@ -262,7 +263,8 @@ __global__ void __launch_bounds__(BS) k_batch(const BatchTask *__restrict__ task
             L.delta = tk.band_delta;
             solve_task<BS>(tk, L, n_steps, st);
         } else {
-            const SellLayout L{MeshRows{tk.soff, tk.scol, tk.sface, tk.rlen}, tk.mag_sf, tk.delta};
+            const SellLayout L{MeshRows{tk.soff, tk.scol, tk.sface, tk.rlen}, tk.mag_sf, tk.delta, tk.emag_sf,
+                               tk.edelta};
             solve_task<BS>(tk, L, n_steps, st);
         }
     }
@@ -378,6 +380,7 @@ lf_status lf_batch_launch(lf_batch *b, int32_t n, lf_problem *const *problems, d
         BatchTask &t = b->h_tasks[i];
         t.soff = m->soff; t.scol = m->scol; t.sface = m->sface; t.rlen = m->rlen;
         t.V = m->V; t.mag_sf = m->mag_sf; t.delta = m->delta;
+        t.emag_sf = m->emag_sf; t.edelta = m->edelta;
         t.bface_start = m->rbface_start; t.bface_list = m->rbface_list; t.bface_patch = m->bface_patch;
         t.iperm = m->iperm;
         t.bmag_sf = m->bmag_sf; t.bdelta = m->bdelta;

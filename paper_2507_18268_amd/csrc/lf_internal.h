@@ -118,6 +118,9 @@ struct lf_mesh {
     int32_t *perm = nullptr, *iperm = nullptr;            // [N]
     int32_t *rbface_start = nullptr, *rbface_list = nullptr;   // [N+1], [B] boundary faces per solver row
     int32_t *rbface_cell = nullptr;                       // [B] solver row of each boundary face
+    // |S_f| and delta_f per entry of the row layout (meshes without band form,
+    // whose problems use that layout): the assembly reads them in row order
+    double *emag_sf = nullptr, *edelta = nullptr;         // [n_entries], or null
     double *V = nullptr;                                  // [N] (solver order)
     double *mag_sf = nullptr, *delta = nullptr;           // [F]
     double *bmag_sf = nullptr, *bdelta = nullptr;         // [B]

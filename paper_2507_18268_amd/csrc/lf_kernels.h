@@ -189,6 +189,9 @@ struct SellLayout {
     MeshRows mr;
     const double *__restrict__ mag_sf;   // [F]
     const double *__restrict__ delta;    // [F]
+    // the same factors per row entry, in the layout's order (null: gather by face)
+    const double *__restrict__ emag_sf;  // [n_entries]
+    const double *__restrict__ edelta;   // [n_entries]
 };
 
 template <int K>
@@ -361,10 +364,14 @@ __device__ __forceinline__ double band_walk(const BandLayout<K> &L, const T *__r
 // face order, source = (T_old/dt) V; fixedValue faces add (DT|S_b|) delta_b to
 // the diagonal and (DT|S_b|)(delta_b T_b) to the source.
 // ---------------------------------------------------------------------------
+// (edelta, emag_sf: the factors per entry, read contiguously; else gathered
+// by face index)
 template <int W, bool kUpper>
 __device__ __forceinline__ double assemble_row_w(int32_t c, int32_t base, int32_t len, const MeshRows &mr,
                                                  const double *__restrict__ delta,
-                                                 const double *__restrict__ mag_sf, double DT,
+                                                 const double *__restrict__ mag_sf,
+                                                 const double *__restrict__ edelta,
+                                                 const double *__restrict__ emag_sf, double DT,
                                                  double *__restrict__ coef, double *__restrict__ upper) {
     int32_t f[W], col[W];
     double dl[W], ms[W];
@@ -373,10 +380,18 @@ __device__ __forceinline__ double assemble_row_w(int32_t c, int32_t base, int32_
         f[j] = mr.sface[base + kSlice * j];
         col[j] = mr.scol[base + kSlice * j];
     }
+    if (edelta) {
 #pragma unroll
-    for (int j = 0; j < W; ++j) {
-        dl[j] = delta[f[j]];
-        ms[j] = mag_sf[f[j]];
+        for (int j = 0; j < W; ++j) {
+            dl[j] = edelta[base + kSlice * j];
+            ms[j] = emag_sf[base + kSlice * j];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            dl[j] = delta[f[j]];
+            ms[j] = mag_sf[f[j]];
+        }
     }
     double lap_diag = 0.0;
 #pragma unroll
@@ -393,7 +408,9 @@ __device__ __forceinline__ double assemble_row_w(int32_t c, int32_t base, int32_
 
 template <bool kUpper>
 __device__ __forceinline__ double assemble_row(int32_t c, const MeshRows &mr, const double *__restrict__ delta,
-                                               const double *__restrict__ mag_sf, double DT,
+                                               const double *__restrict__ mag_sf,
+                                               const double *__restrict__ edelta,
+                                               const double *__restrict__ emag_sf, double DT,
                                                double *__restrict__ coef, double *__restrict__ upper) {
     const int32_t s = c >> 6;
     const int32_t o0 = mr.soff[s];
@@ -402,20 +419,20 @@ __device__ __forceinline__ double assemble_row(int32_t c, const MeshRows &mr, co
     const int32_t len = mr.rlen[c];
     switch (width) {
         case 0: return 0.0;
-        case 1: return assemble_row_w<1, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
-        case 2: return assemble_row_w<2, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
-        case 3: return assemble_row_w<3, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
-        case 4: return assemble_row_w<4, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
-        case 5: return assemble_row_w<5, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
-        case 6: return assemble_row_w<6, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
-        case 7: return assemble_row_w<7, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
-        case 8: return assemble_row_w<8, kUpper>(c, base, len, mr, delta, mag_sf, DT, coef, upper);
+        case 1: return assemble_row_w<1, kUpper>(c, base, len, mr, delta, mag_sf, edelta, emag_sf, DT, coef, upper);
+        case 2: return assemble_row_w<2, kUpper>(c, base, len, mr, delta, mag_sf, edelta, emag_sf, DT, coef, upper);
+        case 3: return assemble_row_w<3, kUpper>(c, base, len, mr, delta, mag_sf, edelta, emag_sf, DT, coef, upper);
+        case 4: return assemble_row_w<4, kUpper>(c, base, len, mr, delta, mag_sf, edelta, emag_sf, DT, coef, upper);
+        case 5: return assemble_row_w<5, kUpper>(c, base, len, mr, delta, mag_sf, edelta, emag_sf, DT, coef, upper);
+        case 6: return assemble_row_w<6, kUpper>(c, base, len, mr, delta, mag_sf, edelta, emag_sf, DT, coef, upper);
+        case 7: return assemble_row_w<7, kUpper>(c, base, len, mr, delta, mag_sf, edelta, emag_sf, DT, coef, upper);
+        case 8: return assemble_row_w<8, kUpper>(c, base, len, mr, delta, mag_sf, edelta, emag_sf, DT, coef, upper);
         default: {
             double lap_diag = 0.0;
             int32_t idx = base;
             for (int32_t j = 0; j < len; ++j, idx += kSlice) {
                 const int32_t f = mr.sface[idx];
-                const double lap_upper = delta[f] * (DT * mag_sf[f]);
+                const double lap_upper = edelta ? edelta[idx] * (DT * emag_sf[idx]) : delta[f] * (DT * mag_sf[f]);
                 coef[idx] = -lap_upper;
                 lap_diag -= lap_upper;
                 if (kUpper && mr.scol[idx] > c) upper[f] = -lap_upper;
@@ -492,7 +509,7 @@ template <bool kUpper>
 __device__ __forceinline__ double assemble_coefs(const SellLayout &L, int32_t c, double DT,
                                                  double *__restrict__ coef, double *__restrict__ upper,
                                                  RowCoefs<SellLayout> &) {
-    return assemble_row<kUpper>(c, L.mr, L.delta, L.mag_sf, DT, coef, upper);
+    return assemble_row<kUpper>(c, L.mr, L.delta, L.mag_sf, L.edelta, L.emag_sf, DT, coef, upper);
 }
 
 // Band layout: the row's coefficients from the slot geometry (a slot without a

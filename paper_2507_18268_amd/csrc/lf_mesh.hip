@@ -206,6 +206,24 @@ __global__ void k_face_geometry(int32_t f0, int32_t m, const int32_t *__restrict
     delta[f] = 1.0 / (nd > lim ? nd : lim);
 }
 
+// the face factors copied to each entry of the row layout, row by row over
+// exactly the entries k_sell_fill wrote (padding entries copy face 0: loaded,
+// never used; the lanes of a last, partial slice past the rows hold nothing)
+__global__ void k_entry_geometry(int32_t n, const int32_t *__restrict__ soff, const int32_t *__restrict__ sface,
+                                 const double *__restrict__ mag_sf, const double *__restrict__ delta,
+                                 double *__restrict__ emag_sf, double *__restrict__ edelta) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int32_t s = static_cast<int32_t>(r / kSlice), lane = static_cast<int32_t>(r % kSlice);
+    const int32_t width = (soff[s + 1] - soff[s]) / kSlice;
+    int32_t idx = soff[s] + lane;
+    for (int32_t j = 0; j < width; ++j, idx += kSlice) {
+        const int32_t f = sface[idx];
+        emag_sf[idx] = mag_sf[f];
+        edelta[idx] = delta[f];
+    }
+}
+
 // boundary: |S_b| and delta_b = 1/(n_b.(C_b - C_P))
 __global__ void k_bface_geometry(int32_t nb, const int32_t *__restrict__ bcell, const double *__restrict__ C,
                                  const double *__restrict__ S, const double *__restrict__ Cb,
@@ -294,6 +312,11 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, i
         rblist = cv.take<int32_t>(B);
         rbcell = cv.take<int32_t>(B);
     }
+    double *emag = nullptr, *edelta = nullptr;
+    if (K == 0 && E > 0) {
+        emag = cv.take<double>(static_cast<size_t>(E));
+        edelta = cv.take<double>(static_cast<size_t>(E));
+    }
     double *band_mag = nullptr, *band_delta = nullptr;
     if (K > 0) {
         band_mag = cv.take<double>(static_cast<size_t>(K) * N);
@@ -315,6 +338,7 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, i
         m->V = V; m->mag_sf = mag_sf; m->delta = delta; m->bmag_sf = bmag; m->bdelta = bdelta;
         m->band_mag_sf = band_mag; m->band_delta = band_delta;
         m->perm = perm; m->iperm = iperm;
+        m->emag_sf = emag; m->edelta = edelta;
         m->rbface_start = rbstart; m->rbface_list = rblist; m->rbface_cell = rbcell;
     }
     if (s) *s = sc;
@@ -673,6 +697,9 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
         hipLaunchKernelGGL(k_band_fill, dim3(blocks_for(F)), dim3(kBlock), 0, s, F, N, bo, m->owner, m->neighbour,
                            m->mag_sf, m->delta, m->band_mag_sf, m->band_delta);
     }
+    if (m->emag_sf)
+        hipLaunchKernelGGL(k_entry_geometry, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, m->soff, m->sface,
+                           m->mag_sf, m->delta, m->emag_sf, m->edelta);
     if (B > 0)
         hipLaunchKernelGGL(k_bface_geometry, dim3(blocks_for(B)), dim3(kBlock), 0, s, B, m->bface_cell, sc.C,
                            sc.bS, sc.bC, m->bmag_sf, m->bdelta);

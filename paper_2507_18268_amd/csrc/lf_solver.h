@@ -36,7 +36,7 @@ inline size_t coef_slots(const lf_mesh *m, bool banded) {
 }
 
 inline SellLayout sell_layout(const lf_mesh *m) {
-    return SellLayout{mesh_rows(m), m->mag_sf, m->delta};
+    return SellLayout{mesh_rows(m), m->mag_sf, m->delta, m->emag_sf, m->edelta};
 }
 
 template <int K>
