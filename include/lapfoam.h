@@ -256,6 +256,22 @@ lf_status lf_step(lf_problem *problem, int32_t n_steps, lf_solve_stats *stats);
  * solves cannot fill the GPU. */
 lf_status lf_step_many(lf_problem *const *problems, int32_t n, int32_t n_steps, lf_solve_stats *stats);
 
+/* lf_step without waiting: lf_step_begin enqueues the first of n_steps time
+ * steps on the problem's stream and returns; lf_step_poll then advances the run
+ * as far as its finished device work allows, without waiting for the device
+ * (event queries only): it enqueues each next block of iterations or next step
+ * and reports *steps_done and *finished (1 once all steps, or a step with a
+ * non-finite residual, have finished; then LF_ENONFINITE is returned for the
+ * latter).  Same results as lf_step.  snapshots (device, [n_steps][N] in the
+ * mesh's cell order, may be NULL) receive T after each step, copied on the
+ * problem's stream; stats[n_steps] (host, may be NULL) receives the stats of
+ * the finished steps.  While a run is in flight the problem must not be
+ * stepped, reset or read (those calls return LF_ESTATE); destroying it waits for
+ * the run's device work.  For a scheduler that keeps several problems of
+ * different sizes going without one waiting for another. */
+lf_status lf_step_begin(lf_problem *problem, int32_t n_steps, double *snapshots);
+lf_status lf_step_poll(lf_problem *problem, int32_t *steps_done, int32_t *finished, lf_solve_stats *stats);
+
 /* ---- test hooks ------------------------------------------------------------ */
 /* Assemble TEqn from the current T (no solve).  Then lf_get_matrix copies, to
  * host arrays (any may be NULL): diag[N] and source[N] of TEqn, upper[F],

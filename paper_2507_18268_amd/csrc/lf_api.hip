@@ -11,6 +11,23 @@
 
 using namespace lf;
 
+// One problem's stepping: lf_step and lf_step_many run it to the end;
+// lf_step_begin keeps one in the problem and lf_step_poll advances it.
+namespace lf {
+struct StepDriver {
+    lf_problem *P = nullptr;
+    lf_solve_stats *stats = nullptr;   // [n_steps] or null
+    double *snap = nullptr;            // device [n_steps][N], mesh order, or null
+    int32_t n_steps = 0, step = 0;
+    SolveCtx c;
+    lf_solve_stats cur{};
+    bool active = false, nonfinite = false;
+    std::vector<lf_solve_stats> own_stats;   // lf_step_begin's stats
+};
+}  // namespace lf
+
+static bool async_running(const lf_problem *P) { return P->async && P->async->active; }
+
 extern "C" {
 
 lf_status lf_default_opts(lf_solver_opts *o) {
@@ -169,6 +186,10 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
 
 lf_status lf_problem_destroy(lf_problem *P) {
     if (!P) return LF_OK;
+    if (P->async) {
+        if (P->async->active) (void)hipStreamSynchronize(P->stream);   // a run still in flight
+        delete P->async;
+    }
     for (auto &g : P->g_iter) if (g) (void)hipGraphExecDestroy(g);
     for (auto &g : P->g_inner) if (g) (void)hipGraphExecDestroy(g);
     if (P->capture_stream) (void)hipStreamDestroy(P->capture_stream);
@@ -182,6 +203,7 @@ lf_status lf_problem_destroy(lf_problem *P) {
 lf_status lf_problem_reset(lf_problem *P, const lf_patch_bc *bcs, double DT, double dt) {
     clear_error();
     if (!P) { set_error("problem is NULL"); return LF_EINVAL; }
+    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
     const lf_mesh *m = P->mesh;
     LF_TRY(check_physics(m, bcs, DT, dt));
     std::vector<int32_t> pt(std::max<int32_t>(m->P, 1), 0);
@@ -263,6 +285,7 @@ static lf_status download_mesh_order(lf_problem *P, const double *src, double *h
 lf_status lf_set_T(lf_problem *P, const double *T, int32_t on_device) {
     clear_error();
     if (!P || !T) { set_error("NULL argument"); return LF_EINVAL; }
+    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
     const int32_t N = P->mesh->N;
     if (!on_device) {
         for (int32_t c = 0; c < N; ++c)
@@ -285,6 +308,7 @@ lf_status lf_set_T(lf_problem *P, const double *T, int32_t on_device) {
 lf_status lf_get_T(lf_problem *P, double *T, int32_t on_device) {
     clear_error();
     if (!P || !T) { set_error("NULL argument"); return LF_EINVAL; }
+    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
     if (on_device) return to_mesh_order(P, P->T, T);
     LF_TRY(download_mesh_order(P, P->T, T));
     LF_HIP(hipStreamSynchronize(P->stream));
@@ -379,14 +403,7 @@ lf_status lf_profile_read(lf_problem *P, int32_t n, double *total_ms, int64_t *l
 
 // One problem's time steps as a sequence of enqueue / advance phases (see
 // SolveCtx); lf_step drives one, lf_step_many several at once.
-struct StepDriver {
-    lf_problem *P = nullptr;
-    lf_solve_stats *stats = nullptr;   // [n_steps] or null
-    int32_t n_steps = 0, step = 0;
-    SolveCtx c;
-    lf_solve_stats cur{};
-    bool active = false, nonfinite = false;
-};
+
 
 static lf_status begin_step(StepDriver &d) {
     lf_problem *P = d.P;
@@ -414,6 +431,8 @@ static lf_status advance(StepDriver &d) {
     d.cur.solve_ms = s_ms;
     P->last_iters = d.cur.n_iter;
     if (d.stats) d.stats[d.step] = d.cur;
+    // T of this step into its snapshot, on the stream before the next step's work
+    if (d.snap) LF_TRY(to_mesh_order(P, P->T, d.snap + static_cast<int64_t>(d.step) * P->mesh->N));
     ++d.step;
     if (d.cur.nonfinite) {
         d.nonfinite = true;
@@ -428,6 +447,7 @@ static lf_status advance(StepDriver &d) {
 lf_status lf_step(lf_problem *P, int32_t n_steps, lf_solve_stats *stats) {
     clear_error();
     if (!P || n_steps < 0) { set_error("bad argument"); return LF_EINVAL; }
+    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
     if (n_steps == 0) return LF_OK;
     StepDriver d;
     d.P = P;
@@ -448,6 +468,7 @@ lf_status lf_step_many(lf_problem *const *problems, int32_t n, int32_t n_steps, 
     if (!problems || n < 1 || n_steps < 0) { set_error("bad argument"); return LF_EINVAL; }
     for (int32_t i = 0; i < n; ++i) {
         if (!problems[i]) { set_error("problem %d is NULL", i); return LF_EINVAL; }
+        if (async_running(problems[i])) { set_error("problem %d: an lf_step_begin run is in flight", i); return LF_ESTATE; }
         for (int32_t j = 0; j < i; ++j)
             if (problems[j] == problems[i]) { set_error("problem %d given twice", i); return LF_EINVAL; }
     }
@@ -480,6 +501,54 @@ lf_status lf_step_many(lf_problem *const *problems, int32_t n, int32_t n_steps, 
             set_error("problem %d: non-finite residual in step %d", i, ds[i].step - 1);
             return LF_ENONFINITE;
         }
+    return LF_OK;
+}
+
+lf_status lf_step_begin(lf_problem *P, int32_t n_steps, double *snapshots) {
+    clear_error();
+    if (!P || n_steps < 1) { set_error("bad argument"); return LF_EINVAL; }
+    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
+    if (!P->async) {
+        P->async = new (std::nothrow) StepDriver();
+        if (!P->async) { set_error("host allocation failed"); return LF_ENOMEM; }
+    }
+    StepDriver &d = *P->async;
+    d.own_stats.assign(static_cast<size_t>(n_steps), lf_solve_stats{});
+    d.P = P;
+    d.stats = d.own_stats.data();
+    d.snap = snapshots;
+    d.n_steps = n_steps;
+    d.step = 0;
+    d.nonfinite = false;
+    d.active = true;
+    const lf_status st = begin_step(d);
+    if (st != LF_OK) d.active = false;
+    return st;
+}
+
+lf_status lf_step_poll(lf_problem *P, int32_t *steps_done, int32_t *finished, lf_solve_stats *stats) {
+    clear_error();
+    if (!P || !steps_done || !finished) { set_error("NULL argument"); return LF_EINVAL; }
+    if (!P->async) { set_error("no lf_step_begin run"); return LF_ESTATE; }
+    StepDriver &d = *P->async;
+    while (d.active) {
+        const hipError_t q = hipEventQuery(P->ev[2]);
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess) {
+            d.active = false;
+            set_error("hipEventQuery failed: %s", hipGetErrorString(q));
+            return LF_EDEVICE;
+        }
+        const lf_status st = advance(d);
+        if (st != LF_OK) { d.active = false; return st; }
+    }
+    *steps_done = d.step;
+    *finished = d.active ? 0 : 1;
+    if (stats && d.step > 0) std::memcpy(stats, d.own_stats.data(), sizeof(lf_solve_stats) * d.step);
+    if (!d.active && d.nonfinite) {
+        set_error("non-finite residual in step %d", d.step - 1);
+        return LF_ENONFINITE;
+    }
     return LF_OK;
 }
 

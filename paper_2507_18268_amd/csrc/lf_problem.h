@@ -66,8 +66,11 @@ struct SolverParams {
 
 }  // namespace lf
 
+namespace lf { struct StepDriver; }
+
 struct lf_problem {
     const lf_mesh *mesh = nullptr;
+    lf::StepDriver *async = nullptr;           // lf_step_begin's run (null when none has started)
     lf_solver_opts opts{};
     double DT = 0, dt = 0;
     hipStream_t stream = nullptr;

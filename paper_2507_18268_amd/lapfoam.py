@@ -94,6 +94,8 @@ _SIGS = {
     "lf_problem_layout": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32)]),
     "lf_problem_amul_walk": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32)]),
     "lf_mesh_cell_order": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.c_void_p]),
+    "lf_step_begin": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "lf_step_poll": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_void_p]),
     "lf_problem_reset": (C.c_int32, [C.c_void_p, C.POINTER(lf_patch_bc), C.c_double, C.c_double]),
     "lf_set_T": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
     "lf_get_T": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
@@ -220,6 +222,21 @@ def lf_mesh_cell_order(h, n_cells):
     order = np.empty(n_cells, dtype=np.int32)
     _check(lib().lf_mesh_cell_order(h, C.byref(v), order.ctypes.data), "lf_mesh_cell_order")
     return bool(v.value), order
+
+
+def lf_step_begin(h, n_steps, snapshots_ptr=None):
+    _check(lib().lf_step_begin(h, int(n_steps), snapshots_ptr), "lf_step_begin")
+
+
+def lf_step_poll(h, n_steps):
+    """(steps_done, finished, stats of the finished steps, status); status is
+    LF_OK or LF_ENONFINITE (other errors raise)."""
+    done, fin = C.c_int32(0), C.c_int32(0)
+    st = (lf_solve_stats * max(int(n_steps), 1))()
+    status = lib().lf_step_poll(h, C.byref(done), C.byref(fin), st)
+    if status not in (LF_OK, LF_ENONFINITE):
+        _check(status, "lf_step_poll")
+    return done.value, bool(fin.value), [st[i].as_dict() for i in range(done.value)], status
 
 
 def lf_problem_amul_walk(h):
@@ -487,6 +504,25 @@ class Problem:
         if check:
             _check(status, "lf_step")
         return [s.as_dict() for s in stats[:n_steps]], status
+
+    def step_begin(self, n_steps, snapshots=None):
+        """Start n_steps time steps without waiting; snapshots: a device float64
+        tensor of n_steps * n_cells values (mesh cell order) that receives T
+        after each step, or None."""
+        if snapshots is not None:
+            assert snapshots.dtype.is_floating_point and snapshots.element_size() == 8
+            assert snapshots.is_cuda and snapshots.is_contiguous()
+            assert snapshots.numel() >= n_steps * self.mesh.n_cells
+        self._async_steps = int(n_steps)
+        self._async_snap = snapshots     # kept alive while the run may write it
+        lf_step_begin(self.h, n_steps, snapshots.data_ptr() if snapshots is not None else None)
+
+    def step_poll(self):
+        """(steps_done, finished, stats of the finished steps, status), without waiting."""
+        out = lf_step_poll(self.h, self._async_steps)
+        if out[1]:
+            self._async_snap = None
+        return out
 
     def assemble(self):
         lf_assemble(self.h)

@@ -22,15 +22,17 @@ batched-kernel task table:
   results on the host) is recorded.
 
 Large requests can instead take the direct lane: up to direct_workers of them
-at a time, each on a stream of its own and with its own pool of problems, are
-advanced one time step per scheduling pass with the multi-kernel solver (the
-whole GPU's bandwidth for one problem, coefficients in the band layout where
-the mesh allows; lf_step_many interleaves their solves on their streams), T
-being copied after each step into the snapshot buffer.
+at a time, each on a stream of its own and with its own pool of problems, run
+all their steps with the multi-kernel solver (the whole GPU's bandwidth for one
+problem, coefficients in the band layout where the mesh allows), T being copied
+after each step into the snapshot buffer.  A request's run starts when it is
+admitted (lf_step_begin) and every scheduling pass advances each running one as
+far as its finished device work allows (lf_step_poll, which never waits), so a
+small request does not wait for a large one's steps.
 One workgroup is far too little for a large mesh, so this cuts both their
 latency and the time the batched slots spend waiting for them.  The lane runs
-on the scheduling thread: a step returns in milliseconds, and no second host
-thread has to share the interpreter with the scheduler.
+on the scheduling thread: polling returns at once, and no second host thread
+has to share the interpreter with the scheduler.
 
 A batched workgroup occupies its compute unit for the whole of its problem,
 so with the direct lane on the server keeps at most batch_max_running batched
@@ -340,41 +342,36 @@ class Server:
                 P.reset(req.bcs, req.DT, req.dt)
             self._upload_T(P, req.T0)
             snap = torch.empty((req.steps, mesh.n_cells), dtype=torch.float64, device="cuda")
+            P.step_begin(req.steps, snap)        # the whole run; _step_direct advances it
         req.launched = self.now()
         self.direct_slot[k] = _Direct(req, P, snap, snap_bytes, key, k, 0, [])
 
     def _step_direct(self):
-        """One time step of every running direct-lane request, advanced together
-        (lf_step_many: their solves interleave on their own streams)."""
+        """Advance every running direct-lane request as far as its finished device
+        work allows (lf_step_poll: no waiting) and finish those whose last step
+        is done."""
         torch = self.torch
-        live = [(k, d) for k, d in enumerate(self.direct_slot) if d is not None]
-        if not live:
-            return
-        stats, status = L.step_many([d.problem for _, d in live], 1, check=False)
-        if status not in (L.LF_OK, L.LF_ENONFINITE):
-            raise L.LapfoamError(status, "lf_step_many", L.lib().lf_last_error().decode())
-        for (k, d), st in zip(live, stats):
+        for k, d in enumerate(self.direct_slot):
+            if d is None:
+                continue
+            _, finished, stats, status = d.problem.step_poll()
+            if not finished:
+                continue
             req = d.req
-            failed = st[0]["nonfinite"] != 0
-            with torch.cuda.stream(self.direct_streams[k]):
-                d.problem.get_T(out=d.snap[d.step])
-                d.stats += st
-                d.step += 1
-                if d.step < req.steps and not failed:
-                    continue
-                host = self._download(d.snap)
+            failed = status == L.LF_ENONFINITE
             if failed:
                 req.error = "direct lane: non-finite residual"
             else:
-                req.snapshots, req.stats = host, d.stats
+                with torch.cuda.stream(self.direct_streams[k]):
+                    req.snapshots, req.stats = self._download(d.snap), stats
             self.idle[d.key].append(d.problem)
             self._finish(req, d.snap_bytes)
             self.direct_slot[k] = None
 
     # -------------------------------------------------------------- loop
     def pump(self):
-        """One scheduling pass: collect finished work, admit, launch, and one
-        step of each running direct-lane request."""
+        """One scheduling pass: collect finished work, admit, launch, and advance
+        the running direct-lane requests."""
         self._collect()
         self._admit()
         self._launch()

@@ -204,6 +204,54 @@ def test_cell_order():
         m.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_step_begin_poll_equals_step(L, precision):
+    """lf_step_begin / lf_step_poll: bitwise the snapshots and stats of stepping
+    one step at a time, snapshots in the mesh's cell order (also on a mesh the
+    solver keeps in Morton order); the problem refuses other calls while the
+    run is in flight."""
+    import torch
+    base = synth.box_mesh(12, 10, 9, z_ratio=3.0)
+    meshes = [base, synth.renumber(base, synth.random_permutation(base.n_cells, 3))]
+    steps = 4
+    for mesh in meshes:
+        N = mesh.n_cells
+        T0 = synth.initial_field(N, 31)
+        m = L.Mesh(mesh)
+        opts = L.make_opts(precision=precision)
+        A = L.Problem(m, BCS_MIXED, 5e-3, 2e-3, opts)
+        A.set_T(T0)
+        ref, sref = [], []
+        for _ in range(steps):
+            st, _ = A.step(1)
+            sref += st
+            ref.append(A.get_T())
+        B = L.Problem(m, BCS_MIXED, 5e-3, 2e-3, opts)
+        B.set_T(T0)
+        with pytest.raises(L.LapfoamError):
+            L.lf_step_poll(B.h, steps)                   # nothing started
+        snap = torch.empty(steps * N, dtype=torch.float64, device="cuda")
+        B.step_begin(steps, snap)
+        with pytest.raises(L.LapfoamError):
+            B.step(1)                                    # a run is in flight
+        with pytest.raises(L.LapfoamError):
+            B.get_T()
+        while True:
+            done, finished, stats, status = B.step_poll()
+            if finished:
+                break
+        assert status == L.LF_OK and done == steps
+        got = snap.view(steps, N).cpu().numpy()
+        for s in range(steps):
+            assert np.array_equal(got[s], ref[s]), s
+            assert stats[s]["n_iter"] == sref[s]["n_iter"]
+            assert stats[s]["final_residual"] == sref[s]["final_residual"]
+        assert np.array_equal(B.get_T(), ref[-1])
+        A.close()
+        B.close()
+        m.close()
+
+
 def test_amul_walk_option_checked(L):
     m = L.Mesh(synth.box_mesh(4, 4, 4))
     with pytest.raises(L.LapfoamError):
