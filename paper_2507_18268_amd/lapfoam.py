@@ -461,6 +461,7 @@ class Problem:
         self.stream = _stream_ptr(stream) if stream is not None else mesh.stream
         self.h = lf_problem_create(mesh.h, arr, DT, dt, self.opts, self.ws.data_ptr(),
                                    self.ws_bytes, self.stream)
+        self._async_steps, self._async_snap = 0, None     # lf_step_begin's run
 
     def layout(self):
         """LF_LAYOUT_ROWS or LF_LAYOUT_BANDS."""

@@ -229,7 +229,7 @@ def test_step_begin_poll_equals_step(L, precision):
         B = L.Problem(m, BCS_MIXED, 5e-3, 2e-3, opts)
         B.set_T(T0)
         with pytest.raises(L.LapfoamError):
-            L.lf_step_poll(B.h, steps)                   # nothing started
+            B.step_poll()                                # nothing started
         snap = torch.empty(steps * N, dtype=torch.float64, device="cuda")
         B.step_begin(steps, snap)
         with pytest.raises(L.LapfoamError):
