@@ -29,6 +29,8 @@ def _meshes():
     yield "random_7x5x3", synth.renumber(base, synth.random_permutation(base.n_cells, 2))
     yield "redblack_6x6x4", synth.renumber(synth.box_mesh(6, 6, 4),
                                            synth.red_black_numbering(synth.box_mesh(6, 6, 4))[0])
+    tiny = synth.box_mesh(3, 3, 2)                                # 18 cells: one partial slice
+    yield "random_3x3x2", synth.renumber(tiny, synth.random_permutation(tiny.n_cells, 4))
     yield "line_9", synth.box_mesh(9, 1, 1)
     yield "one_cell", synth.box_mesh(1, 1, 1)
     g = synth.box_mesh(24, 20, 18, z_ratio=10.0)                 # several workgroups
