@@ -255,6 +255,27 @@ k_commit(SolverParams sp, double *__restrict__ x, const double *__restrict__ p, 
 //             with w_o = rD_o r_o for the red owners
 //   backward: w_r = rD_r r_r - sum over owned faces (descending) (rD_r upper) w_n
 // ---------------------------------------------------------------------------
+// a black row's DIC diagonal with slice width W: loads first, then the terms in
+// ascending entry order (padding entries loaded, never used)
+template <int W>
+__device__ __forceinline__ double dic_rd_row(int32_t base, int32_t len, const MeshRows &mr,
+                                             const double *__restrict__ coef, const double *__restrict__ diagB,
+                                             double d) {
+    int32_t col[W];
+    double a[W], dg[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        col[j] = mr.scol[base + kSlice * j];
+        a[j] = coef[base + kSlice * j];
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j) dg[j] = diagB[col[j]];
+#pragma unroll
+    for (int j = 0; j < W; ++j)
+        if (j < len) d -= a[j] * a[j] / dg[j];
+    return d;
+}
+
 __global__ void __launch_bounds__(kCellBlock)
 k_dic_rd(SolverParams sp, MeshRows mr, const double *__restrict__ diagB, const double *__restrict__ coef,
          double *__restrict__ rD) {
@@ -262,14 +283,74 @@ k_dic_rd(SolverParams sp, MeshRows mr, const double *__restrict__ diagB, const d
     if (c >= sp.n) return;
     double d = diagB[c];
     if (c >= sp.n_red) {
-        int32_t idx = row_base(mr, c);
+        const int32_t s = c >> 6;
+        const int32_t base = mr.soff[s] + (c & (kSlice - 1));
+        const int32_t width = (mr.soff[s + 1] - mr.soff[s]) >> 6;
         const int32_t len = mr.rlen[c];
-        for (int32_t j = 0; j < len; ++j, idx += kSlice) {
-            const double u = coef[idx];
-            d -= u * u / diagB[mr.scol[idx]];
+        switch (width) {
+            case 0: break;
+            case 1: d = dic_rd_row<1>(base, len, mr, coef, diagB, d); break;
+            case 2: d = dic_rd_row<2>(base, len, mr, coef, diagB, d); break;
+            case 3: d = dic_rd_row<3>(base, len, mr, coef, diagB, d); break;
+            case 4: d = dic_rd_row<4>(base, len, mr, coef, diagB, d); break;
+            case 5: d = dic_rd_row<5>(base, len, mr, coef, diagB, d); break;
+            case 6: d = dic_rd_row<6>(base, len, mr, coef, diagB, d); break;
+            default: {
+                int32_t idx = base;
+                for (int32_t j = 0; j < len; ++j, idx += kSlice) {
+                    const double u = coef[idx];
+                    d -= u * u / diagB[mr.scol[idx]];
+                }
+            }
         }
     }
     rD[c] = 1.0 / d;
+}
+
+// A sweep row with slice width W: every entry's column and coefficient (read
+// once per sweep: streamed past the caches) and its gathered operands are
+// loaded first, then the terms are taken in the recurrence's order (forward:
+// ascending entries; backward: descending).  Padding entries (j >= len) point
+// at the row itself; they are loaded, never used.
+template <int W>
+__device__ __forceinline__ double dic_forward_row(int32_t base, int32_t len, const MeshRows &mr,
+                                                  const double *__restrict__ coef, const double *__restrict__ rD,
+                                                  const double *__restrict__ r, double rd, double wc) {
+    int32_t col[W];
+    double a[W], ro[W], rdo[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        col[j] = __builtin_nontemporal_load(&mr.scol[base + kSlice * j]);
+        a[j] = __builtin_nontemporal_load(&coef[base + kSlice * j]);
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        rdo[j] = rD[col[j]];
+        ro[j] = r[col[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j)
+        if (j < len) wc -= rd * a[j] * (rdo[j] * ro[j]);
+    return wc;
+}
+
+template <int W>
+__device__ __forceinline__ double dic_backward_row(int32_t base, int32_t len, const MeshRows &mr,
+                                                   const double *__restrict__ coef, const double *__restrict__ w,
+                                                   double rd, double wc) {
+    int32_t col[W];
+    double a[W], wo[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        col[j] = __builtin_nontemporal_load(&mr.scol[base + kSlice * j]);
+        a[j] = __builtin_nontemporal_load(&coef[base + kSlice * j]);
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j) wo[j] = w[col[j]];
+#pragma unroll
+    for (int j = W - 1; j >= 0; --j)
+        if (j < len) wc -= rd * a[j] * wo[j];
+    return wc;
 }
 
 __global__ void __launch_bounds__(kCellBlock)
@@ -280,11 +361,25 @@ k_dic_forward(SolverParams sp, MeshRows mr, const double *__restrict__ coef, con
     if (c >= sp.n || c < sp.n_red) return;
     const double rd = rD[c];
     double wc = rd * r[c];
-    int32_t idx = row_base(mr, c);
+    const int32_t s = c >> 6;
+    const int32_t base = mr.soff[s] + (c & (kSlice - 1));
+    const int32_t width = (mr.soff[s + 1] - mr.soff[s]) >> 6;
     const int32_t len = mr.rlen[c];
-    for (int32_t j = 0; j < len; ++j, idx += kSlice) {
-        const int32_t o = mr.scol[idx];
-        wc -= rd * coef[idx] * (rD[o] * r[o]);
+    switch (width) {
+        case 0: break;
+        case 1: wc = dic_forward_row<1>(base, len, mr, coef, rD, r, rd, wc); break;
+        case 2: wc = dic_forward_row<2>(base, len, mr, coef, rD, r, rd, wc); break;
+        case 3: wc = dic_forward_row<3>(base, len, mr, coef, rD, r, rd, wc); break;
+        case 4: wc = dic_forward_row<4>(base, len, mr, coef, rD, r, rd, wc); break;
+        case 5: wc = dic_forward_row<5>(base, len, mr, coef, rD, r, rd, wc); break;
+        case 6: wc = dic_forward_row<6>(base, len, mr, coef, rD, r, rd, wc); break;
+        default: {
+            int32_t idx = base;
+            for (int32_t j = 0; j < len; ++j, idx += kSlice) {
+                const int32_t o = mr.scol[idx];
+                wc -= rd * coef[idx] * (rD[o] * r[o]);
+            }
+        }
     }
     w[c] = wc;
 }
@@ -303,9 +398,23 @@ k_dic_backward(SolverParams sp, MeshRows mr, const double *__restrict__ coef, co
         if (c < sp.n_red) {
             const double rd = rD[c];
             wc = rd * rc;
+            const int32_t s = c >> 6;
+            const int32_t base = mr.soff[s] + (c & (kSlice - 1));
+            const int32_t width = (mr.soff[s + 1] - mr.soff[s]) >> 6;
             const int32_t len = mr.rlen[c];
-            int32_t idx = row_base(mr, c) + (len - 1) * kSlice;
-            for (int32_t j = len - 1; j >= 0; --j, idx -= kSlice) wc -= rd * coef[idx] * w[mr.scol[idx]];
+            switch (width) {
+                case 0: break;
+                case 1: wc = dic_backward_row<1>(base, len, mr, coef, w, rd, wc); break;
+                case 2: wc = dic_backward_row<2>(base, len, mr, coef, w, rd, wc); break;
+                case 3: wc = dic_backward_row<3>(base, len, mr, coef, w, rd, wc); break;
+                case 4: wc = dic_backward_row<4>(base, len, mr, coef, w, rd, wc); break;
+                case 5: wc = dic_backward_row<5>(base, len, mr, coef, w, rd, wc); break;
+                case 6: wc = dic_backward_row<6>(base, len, mr, coef, w, rd, wc); break;
+                default: {
+                    int32_t idx = base + (len - 1) * kSlice;
+                    for (int32_t j = len - 1; j >= 0; --j, idx -= kSlice) wc -= rd * coef[idx] * w[mr.scol[idx]];
+                }
+            }
             w[c] = wc;
         } else {
             wc = w[c];
