@@ -199,3 +199,61 @@ def run(mesh, bcs, DT, dt, n_steps, T0, pc=PC_DIAGONAL, tol=1e-9, rel_tol=0.0, m
             snaps.append(T.copy())
         done += k
     return T, stats_all, snaps
+
+
+def interp_weights(mesh):
+    """Linear interpolation weights w_f of the internal faces (needs face centres)."""
+    F = mesh.n_faces
+    w = np.empty(F)
+    own, nei = _i32(mesh.owner), _i32(mesh.neighbour)
+    cc, sf, fc = _f64(mesh.cell_centre), _f64(mesh.face_area), _f64(mesh.face_centre)
+    lib().lfo_interp_weights(C.c_int32(F), _p(own, np.int32), _p(nei, np.int32),
+                             _p(cc, np.float64), _p(sf, np.float64), _p(fc, np.float64),
+                             _p(w, np.float64))
+    return w
+
+
+def interpolate(mesh, w, v):
+    """Face values s_f = w_f (v_P - v_N) + v_N."""
+    F = mesh.n_faces
+    s = np.empty(F)
+    own, nei = _i32(mesh.owner), _i32(mesh.neighbour)
+    w, v = _f64(w), _f64(v)
+    lib().lfo_interpolate(C.c_int32(F), _p(own, np.int32), _p(nei, np.int32),
+                          _p(w, np.float64), _p(v, np.float64), _p(s, np.float64))
+    return s
+
+
+def boundary_values(mesh, bcs, T):
+    """(T_b, snGrad_b) on the boundary faces for the patches' conditions."""
+    B = mesh.n_bfaces
+    _, bdlt = bface_geometry(mesh)
+    ps, pt, pv = _patch_arrays(mesh, bcs)
+    Tb, snb = np.empty(B), np.empty(B)
+    bcell, T = _i32(mesh.bface_cell), _f64(T)
+    rc = lib().lfo_boundary_values(C.c_int32(mesh.n_patches), _p(ps, np.int32), _p(pt, np.int32),
+                                   _p(pv, np.float64), _p(bcell, np.int32), _p(bdlt, np.float64),
+                                   _p(T, np.float64), _p(Tb, np.float64), _p(snb, np.float64))
+    if rc != 0:
+        raise ValueError(f"oracle boundary_values failed: {rc}")
+    return Tb, snb
+
+
+def gauss_grad(mesh, T, Tb, snb, w=None):
+    """Gauss gradient of the cell field T with boundary values Tb and boundary
+    normal gradients snb: returns (grad [N,3], bgrad [B,3])."""
+    N, F, B = mesh.n_cells, mesh.n_faces, mesh.n_bfaces
+    if w is None:
+        w = interp_weights(mesh)
+    s = interpolate(mesh, w, T)
+    grad = np.empty((N, 3))
+    bgrad = np.empty((B, 3))
+    own, nei = _i32(mesh.owner), _i32(mesh.neighbour)
+    vol, sf = _f64(mesh.cell_volume), _f64(mesh.face_area)
+    bcell, ba = _i32(mesh.bface_cell), _f64(mesh.bface_area)
+    Tb, snb = _f64(Tb), _f64(snb)
+    lib().lfo_gauss_grad(C.c_int32(N), C.c_int32(F), _p(own, np.int32), _p(nei, np.int32),
+                         _p(vol, np.float64), _p(sf, np.float64), _p(s, np.float64), C.c_int32(B),
+                         _p(bcell, np.int32), _p(ba, np.float64), _p(Tb, np.float64),
+                         _p(snb, np.float64), _p(grad, np.float64), _p(bgrad, np.float64))
+    return grad, bgrad

@@ -202,6 +202,29 @@ def renumber(mesh: BoxMesh, new_of_old: np.ndarray) -> BoxMesh:
         nodes=mesh.nodes)
 
 
+def affine(mesh: BoxMesh, A) -> BoxMesh:
+    """The mesh mapped by the linear map x -> A x (det A > 0): a box becomes a
+    skewed box of parallelepiped cells whose faces are not orthogonal to the
+    lines joining cell centres.  Centres map by A, area vectors by
+    det(A) A^-T, volumes by det(A); numbering and patches are unchanged."""
+    A = np.asarray(A, dtype=np.float64)
+    det = float(np.linalg.det(A))
+    if A.shape != (3, 3) or not det > 0.0:
+        raise ValueError("A must be a 3x3 matrix with positive determinant")
+    cof = det * np.linalg.inv(A)             # rows: S' = S @ cof
+    return BoxMesh(
+        n_cells=mesh.n_cells, n_faces=mesh.n_faces, owner=mesh.owner.copy(),
+        neighbour=mesh.neighbour.copy(), cell_volume=det * mesh.cell_volume,
+        cell_centre=mesh.cell_centre @ A.T, face_area=mesh.face_area @ cof,
+        face_centre=mesh.face_centre @ A.T, patch_names=mesh.patch_names,
+        patch_start=mesh.patch_start.copy(), bface_cell=mesh.bface_cell.copy(),
+        bface_area=mesh.bface_area @ cof, bface_centre=mesh.bface_centre @ A.T,
+        shape=mesh.shape, ijk=mesh.ijk, nodes=None)
+
+
+SKEW = ((1.0, 0.30, 0.10), (0.20, 1.0, 0.25), (-0.10, 0.15, 1.0))
+
+
 def random_permutation(n: int, seed: int) -> np.ndarray:
     """new_of_old for a seeded random relabelling: cells ranked by SplitMix64 keys."""
     keys = splitmix64(seed, n)

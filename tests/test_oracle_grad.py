@@ -1,0 +1,148 @@
+"""Pins of the oracle's Gauss gradient against facts of the mathematics (no GPU).
+
+A slip anywhere in the oracle's gradient fails one of these: swapped
+interpolation weights (linear exactness on graded cells), a wrong sign or a
+transposed owner/neighbour in the face loop (central differences), a dropped
+boundary term or volume division (boundary cells, linear exactness), a wrong
+sign or normalisation in the boundary correction (its normal component).
+"""
+import numpy as np
+import pytest
+
+import synth
+from synth import FIXED_VALUE, ZERO_GRADIENT
+
+
+def _skewed(shape, ratio, numbering="natural", seed=5):
+    mesh = synth.affine(synth.box_mesh(*shape, z_ratio=ratio), synth.SKEW)
+    if numbering == "random":
+        mesh = synth.renumber(mesh, synth.random_permutation(mesh.n_cells, seed))
+    return mesh
+
+
+def _unit_normals(mesh):
+    S = mesh.bface_area
+    return S / np.sqrt((S * S).sum(axis=1))[:, None]
+
+
+def test_weights_are_width_ratios_on_graded_skewed_box(oracle):
+    """On a box graded in z and then skewed, the owner weight of the face
+    between cells of widths h_P and h_N (along the face's axis) is
+    h_N / (h_P + h_N): the map keeps ratios of lengths along a line."""
+    nx, ny, nz = 3, 4, 6
+    base = synth.box_mesh(nx, ny, nz, z_ratio=5.0)
+    mesh = synth.affine(base, synth.SKEW)
+    w = oracle.interp_weights(mesh)
+    widths = [np.diff(x) for x in base.nodes]
+    ijk = base.ijk
+    want = np.empty(mesh.n_faces)
+    for f in range(mesh.n_faces):
+        P, N = mesh.owner[f], mesh.neighbour[f]
+        axis = int(np.flatnonzero(ijk[N] != ijk[P])[0])
+        hP, hN = widths[axis][ijk[P, axis]], widths[axis][ijk[N, axis]]
+        want[f] = hN / (hP + hN)
+    assert np.max(np.abs(w - want)) < 1e-13
+    assert np.any(np.abs(want - 0.5) > 0.05)      # the grading makes them differ
+
+
+@pytest.mark.parametrize("shape,ratio,numbering", [
+    ((4, 3, 5), 1.0, "natural"), ((3, 4, 6), 6.0, "natural"), ((5, 4, 3), 3.0, "random"),
+    ((1, 1, 1), 1.0, "natural"), ((6, 1, 1), 2.0, "random")])
+def test_linear_field_gradient_exact_on_skewed_box(oracle, shape, ratio, numbering):
+    """T = a + g.x on parallelepiped cells: linear interpolation is exact at
+    each face centre and the face sum is the exact surface integral, so the
+    Gauss gradient is g in every cell (boundary values given exactly).  The
+    boundary gradient is g + n e when snGrad_b = g.n + e."""
+    mesh = _skewed(shape, ratio, numbering)
+    g = np.array([1.7, -2.3, 0.9])
+    a = 3.25
+    T = a + mesh.cell_centre @ g
+    Tb = a + mesh.bface_centre @ g
+    n = _unit_normals(mesh)
+    e = synth.uniform01(21, mesh.n_bfaces) - 0.5
+    snb = n @ g + e
+    grad, bgrad = oracle.gauss_grad(mesh, T, Tb, snb)
+    assert np.max(np.abs(grad - g)) < 1e-11
+    assert np.max(np.abs(bgrad - (g + n * e[:, None]))) < 1e-11
+
+
+@pytest.mark.parametrize("numbering", ["natural", "random"])
+def test_central_differences_on_uniform_box(oracle, numbering):
+    """On a uniform box the Gauss gradient of any field is the central
+    difference (T_{i+1} - T_{i-1}) / (2h) inside; a boundary cell uses its face
+    value: ((T_i + T_{i+1})/2 - T_b) / h at a low boundary."""
+    nx, ny, nz = 5, 4, 3
+    L = (1.0, 0.8, 0.45)
+    mesh = synth.box_mesh(nx, ny, nz, lengths=L)
+    if numbering == "random":
+        mesh = synth.renumber(mesh, synth.random_permutation(mesh.n_cells, 9))
+    T = synth.initial_field(mesh.n_cells, 4)
+    Tb = 250.0 + 100.0 * synth.uniform01(8, mesh.n_bfaces)
+    snb = np.zeros(mesh.n_bfaces)
+    grad, _ = oracle.gauss_grad(mesh, T, Tb, snb)
+    h = np.array([L[0] / nx, L[1] / ny, L[2] / nz])
+    dims = (nx, ny, nz)
+    cell_at = {tuple(ijk): c for c, ijk in enumerate(mesh.ijk)}
+    bval = {}
+    for p in range(6):
+        axis, hi = p // 2, p % 2
+        for b in range(mesh.patch_start[p], mesh.patch_start[p + 1]):
+            bval[(int(mesh.bface_cell[b]), axis, hi)] = Tb[b]
+    for c, ijk in enumerate(mesh.ijk):
+        for axis in range(3):
+            lo_ijk, hi_ijk = list(ijk), list(ijk)
+            lo_ijk[axis] -= 1
+            hi_ijk[axis] += 1
+            lo = (T[cell_at[tuple(lo_ijk)]] + T[c]) / 2 if ijk[axis] > 0 else bval[(c, axis, 0)]
+            up = (T[cell_at[tuple(hi_ijk)]] + T[c]) / 2 if ijk[axis] < dims[axis] - 1 \
+                else bval[(c, axis, 1)]
+            want = (up - lo) / h[axis]
+            assert abs(grad[c, axis] - want) <= 1e-9 * max(1.0, abs(want)), (c, axis)
+
+
+def test_divergence_identity(oracle):
+    """Internal faces cancel in pairs: sum_c V_c g_c = sum_b S_b T_b for any
+    cell field and boundary values (skewed, graded, randomly numbered)."""
+    mesh = _skewed((5, 4, 6), 4.0, "random", seed=17)
+    T = synth.initial_field(mesh.n_cells, 6)
+    Tb = synth.initial_field(mesh.n_bfaces, 7)
+    grad, _ = oracle.gauss_grad(mesh, T, Tb, np.zeros(mesh.n_bfaces))
+    lhs = (mesh.cell_volume[:, None] * grad).sum(axis=0)
+    rhs = (mesh.bface_area * Tb[:, None]).sum(axis=0)
+    scale = np.abs(mesh.bface_area * Tb[:, None]).sum(axis=0)
+    assert np.all(np.abs(lhs - rhs) <= 1e-12 * scale)
+
+
+def test_boundary_correction_sets_normal_component(oracle):
+    """n.g_b = snGrad_b and the tangential part is the face cell's gradient."""
+    mesh = _skewed((4, 3, 3), 2.0)
+    T = synth.initial_field(mesh.n_cells, 12)
+    Tb = synth.initial_field(mesh.n_bfaces, 13)
+    snb = 50.0 * (synth.uniform01(14, mesh.n_bfaces) - 0.5)
+    grad, bgrad = oracle.gauss_grad(mesh, T, Tb, snb)
+    n = _unit_normals(mesh)
+    gP = grad[mesh.bface_cell]
+    assert np.max(np.abs((n * bgrad).sum(axis=1) - snb)) < 1e-9
+    tang_b = bgrad - n * (n * bgrad).sum(axis=1)[:, None]
+    tang_P = gP - n * (n * gP).sum(axis=1)[:, None]
+    assert np.max(np.abs(tang_b - tang_P)) < 1e-9
+
+
+def test_boundary_values_of_the_conditions(oracle):
+    """fixedValue: T_b = value, snGrad = (value - T_P) / (h/2) on a uniform
+    box; zeroGradient: T_b = T_P, snGrad = 0."""
+    nx, ny, nz = 4, 3, 2
+    mesh = synth.box_mesh(nx, ny, nz)
+    bcs = [(FIXED_VALUE, 300.0), (FIXED_VALUE, 500.0), (ZERO_GRADIENT, 0.0),
+           (FIXED_VALUE, 410.0), (ZERO_GRADIENT, 0.0), (ZERO_GRADIENT, 0.0)]
+    T = synth.initial_field(mesh.n_cells, 2)
+    Tb, snb = oracle.boundary_values(mesh, bcs, T)
+    half = (0.5 / nx, 0.5 / ny, 0.5 / nz)
+    for p, (kind, val) in enumerate(bcs):
+        for b in range(mesh.patch_start[p], mesh.patch_start[p + 1]):
+            Tc = T[mesh.bface_cell[b]]
+            if kind == FIXED_VALUE:
+                assert Tb[b] == val
+                assert abs(snb[b] - (val - Tc) / half[p // 2]) < 1e-9 * abs(val)
+            else:
+                assert Tb[b] == Tc and snb[b] == 0.0
