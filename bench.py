@@ -206,6 +206,49 @@ def run_config_leg(L, torch, name, steps, warmup=1):
     return out
 
 
+def grad_bytes(n_cells, n_faces, n_bfaces):
+    """Algorithmic bytes of one Gauss-gradient launch: per cell T, V, the
+    gradient (3 doubles) and three list starts; per internal face its 32-byte
+    record, its lower-list entry, and the other cell's label on each side; per
+    boundary face its list entry, T_b, snGrad_b, its record and the boundary
+    gradient."""
+    return 52 * n_cells + 44 * n_faces + 76 * n_bfaces
+
+
+def run_grad(L, torch, p, launches=20):
+    """The Gauss gradient on the config's box, skewed (non-orthogonal faces)."""
+    import numpy as np
+    import synth
+    host = synth.affine(p.mesh, synth.SKEW)
+    m = L.Mesh(host, gradient=True, non_orthogonal=True)
+    N, F, B = host.n_cells, host.n_faces, host.n_bfaces
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    T = dev(synth.initial_field(N, 61))
+    Tb = dev(synth.initial_field(B, 62))
+    snb = dev(400.0 * (synth.uniform01(63, B) - 0.5))
+    del host
+    g = torch.empty((N, 3), dtype=torch.float64, device="cuda")
+    bg = torch.empty((B, 3), dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        L.lf_grad(m.h, T.data_ptr(), Tb.data_ptr(), snb.data_ptr(), g.data_ptr(), bg.data_ptr())
+    torch.cuda.synchronize()
+    # the mesh's stream is torch's current stream, so these events bracket the launches
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(launches):
+        L.lf_grad(m.h, T.data_ptr(), Tb.data_ptr(), snb.data_ptr(), g.data_ptr(), bg.data_ptr())
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / launches
+    m.close()
+    nbytes = grad_bytes(N, F, B)
+    gbps = nbytes / (us * 1e-6) / 1e9
+    return {"workload": f"Gauss gradient, {round(N ** (1 / 3))}^3 box graded in z and skewed",
+            "kernel": "k_grad", "launches": launches, "avg_us": us,
+            "algorithmic_bytes": nbytes, "achieved_GBps": gbps, "peak_GBps": HBM_PEAK_GBS,
+            "frac": gbps / HBM_PEAK_GBS}
+
+
 def run_serving(L, torch, args):
     """512 parametric requests (side log-uniform in [16, 96], DT log-uniform in
     [1e-4, 1e-2], dt = 1e-3, 10 steps, snapshots of every step returned):
@@ -291,6 +334,7 @@ def main():
     ap.add_argument("--accuracy-steps", type=int, default=20)
     ap.add_argument("--inner-tol", type=float, default=0.0, help="mixed: inner reduction (0 = default)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-extra-configs", action="store_true")
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--serve-sweep", action="store_true", help="Poisson rates 0.25x..4x of saturated")
@@ -435,6 +479,10 @@ def main():
         out["other_configs"] = {name: run_config_leg(L, torch, name, steps)
                                 for name, steps in (("plain_32", 20), ("permuted_192", 30),
                                                     ("graded_256_dic", 50))}
+
+    if not args.no_grad and args.n is None:
+        log("[bench] Gauss gradient ...")
+        out["grad"] = run_grad(L, torch, p)
 
     if not args.no_serve:
         out["serving"] = run_serving(L, torch, args)

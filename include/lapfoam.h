@@ -88,19 +88,27 @@ typedef int32_t lf_status;
                               preconditioned CG of A d = r in exact arithmetic
                               (iterative refinement) */
 
+#define LF_MESH_NON_ORTHOGONAL 1   /* lf_mesh_desc.flags: accept faces that are not
+                                      orthogonal to the line joining their cell
+                                      centres (skewed cells).  Such a mesh serves
+                                      lf_grad; problems reject it (the Laplacian's
+                                      explicit non-orthogonal correction is not
+                                      implemented) */
+
 /* Mesh in OpenFOAM face addressing (host pointers). */
 typedef struct lf_mesh_desc {
     int32_t n_cells;            /* N >= 1 */
     int32_t n_faces;            /* F >= 0 internal faces */
     int32_t n_patches;          /* P >= 0 */
-    int32_t reserved;
+    int32_t flags;              /* 0 or LF_MESH_NON_ORTHOGONAL */
     const int32_t *owner;       /* [F] owner cell of each internal face */
     const int32_t *neighbour;   /* [F] neighbour cell; owner < neighbour and faces
                                    sorted by (owner, neighbour): upper-triangular order */
     const double *cell_volume;  /* [N] V_c > 0 */
     const double *cell_centre;  /* [3N] C_c, xyz interleaved */
     const double *face_area;    /* [3F] S_f, |S_f| = face area, owner -> neighbour */
-    const double *face_centre;  /* [3F] C_f; may be NULL (not used by this path) */
+    const double *face_centre;  /* [3F] C_f; may be NULL: then the mesh holds no
+                                   gradient geometry and lf_grad returns LF_EINVAL */
     const int32_t *patch_start; /* [P+1] boundary faces of patch p are
                                    [patch_start[p], patch_start[p+1]); patch_start[0] = 0 */
     const int32_t *bface_cell;  /* [B] cell of each boundary face, B = patch_start[P] */
@@ -167,10 +175,14 @@ lf_status lf_default_opts(lf_solver_opts *opts);
 
 /* ---- mesh (once per mesh) ------------------------------------------------
  * Validation (LF_EMESH): every owner/neighbour/face cell index in [0, N);
- * owner < neighbour; faces strictly increasing in (owner, neighbour); every
- * face orthogonal (|S x d| <= 1e-9 |S||d|, d = C_N - C_P, S.d > 0: no
+ * owner < neighbour; faces strictly increasing in (owner, neighbour);
+ * S.d > 0 for every face (d = C_N - C_P), and unless flags has
+ * LF_MESH_NON_ORTHOGONAL every face orthogonal (|S x d| <= 1e-9 |S||d|: no
  * non-orthogonal correction is implemented); boundary faces outward
- * (S_b.(C_b - C_P) > 0); V > 0.
+ * (S_b.(C_b - C_P) > 0); V > 0; unknown flags give LF_EINVAL.
+ * With face_centre given, the device copy also holds the gradient's face
+ * records (S_f and the interpolation weight w_f, 32 bytes per face) and
+ * boundary-face records (S_b and |S_b|), which lf_grad reads.
  * The device copy holds the addressing (Section 5.2 lists of lists: per cell
  * its owned faces, its lower faces in ascending face order, its boundary
  * faces in ascending boundary-face order) and the geometry factors
@@ -204,10 +216,34 @@ lf_status lf_mesh_get_addressing(const lf_mesh *mesh, int32_t *owner_start, int3
                                  int32_t *losort_start, int32_t *bface_start,
                                  int32_t *bface_list);
 
+/* Gauss gradient of a cell field (Section 5.2: calcGrad = linear
+ * interpolation to the faces, gradf, then correctBoundaryConditions), for the
+ * explicit non-orthogonal correction of the Laplacian:
+ *   w_f = |S_f.(C_N - C_f)| / (|S_f.(C_f - C_P)| + |S_f.(C_N - C_f)|) (owner weight)
+ *   s_f = w_f (T_P - T_N) + T_N
+ *   grad_c = (sum over the faces owned by c of S_f s_f - sum over the faces
+ *            whose neighbour is c of S_f s_f + sum over its boundary faces of
+ *            S_b Tb_b) / V_c
+ *   bgrad_b = grad_P + n (snGrad_b - n.grad_P), n = S_b/|S_b|, P the face cell.
+ * One thread gathers each cell's faces through the lists of lists (lower faces
+ * ascending, then owned faces ascending, then boundary faces ascending: the
+ * order in which the sequential face loop reaches the cell), so each result
+ * equals, bit for bit, the sequential loop over faces then boundary faces.
+ * T[N], Tb[B] (the field's boundary values) and snGrad_b[B] (its normal
+ * gradient on the boundary faces) are device inputs in the mesh's cell and
+ * boundary-face order; grad[3N] and bgrad[3B] (xyz interleaved, same orders)
+ * are device outputs.  bgrad may be NULL (then snGrad_b is not read).  The
+ * work is ordered on the mesh's stream and the call returns without waiting.
+ * LF_EINVAL: NULL mesh, T, grad, or Tb (B > 0), or snGrad_b with bgrad given;
+ * a mesh created without face centres. */
+lf_status lf_grad(const lf_mesh *mesh, const double *T, const double *Tb, const double *snGrad_b,
+                  double *grad, double *bgrad);
+
 /* ---- problem: mesh + boundary conditions + DT + dt + solver ------------- */
 size_t lf_problem_workspace_bytes(const lf_mesh *mesh, const lf_solver_opts *opts);
 /* bcs[n_patches]; DT >= 0 finite; dt > 0 finite.  LF_PC_DIC on a mesh without
- * the two-colour property returns LF_EINVAL.  T starts at 0: set it with
+ * the two-colour property returns LF_EINVAL, and so does a mesh created with
+ * non-orthogonal faces (LF_MESH_NON_ORTHOGONAL).  T starts at 0: set it with
  * lf_set_T before stepping. */
 lf_status lf_problem_create(const lf_mesh *mesh, const lf_patch_bc *bcs, double DT, double dt,
                             const lf_solver_opts *opts, void *dev_workspace,

@@ -82,6 +82,11 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
     if (!out) { set_error("out is NULL"); return LF_EINVAL; }
     *out = nullptr;
     if (!m) { set_error("mesh is NULL"); return LF_EINVAL; }
+    if (!m->orthogonal) {
+        set_error("the mesh was created with non-orthogonal faces: the Laplacian's non-orthogonal correction "
+                  "is not implemented");
+        return LF_EINVAL;
+    }
     LF_TRY(check_physics(m, bcs, DT, dt));
     lf_solver_opts opts;
     if (o) opts = *o; else lf_default_opts(&opts);

@@ -280,10 +280,11 @@ struct MeshScratch {
     double *C;           // [3N]
     double *S;           // [3*chunk]
     double *bS, *bC;     // [3B]
+    double *Cf;          // [3*chunk] face centres (gradient geometry only)
 };
 
 static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, int32_t K, bool reorder,
-                       lf_mesh *m, MeshScratch *s) {
+                       bool grad, lf_mesh *m, MeshScratch *s) {
     size_t n1 = static_cast<size_t>(N) + 1;
     const int32_t ns = (N + kSlice - 1) / kSlice;
     auto *owner = cv.take<int32_t>(F);
@@ -322,6 +323,11 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, i
         band_mag = cv.take<double>(static_cast<size_t>(K) * N);
         band_delta = cv.take<double>(static_cast<size_t>(K) * N);
     }
+    double *gface = nullptr, *gbface = nullptr;
+    if (grad) {
+        gface = cv.take<double>(4 * static_cast<size_t>(F));
+        gbface = cv.take<double>(4 * static_cast<size_t>(B));
+    }
     size_t tiles = (n1 + kScanTile - 1) / kScanTile + 1;
     MeshScratch sc;
     sc.cnt = cv.take<int32_t>(n1);
@@ -330,7 +336,10 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, i
     sc.S = cv.take<double>(3 * static_cast<size_t>(std::min<int64_t>(std::max(F, 1), kGeomChunk)));
     sc.bS = cv.take<double>(3 * static_cast<size_t>(B));
     sc.bC = cv.take<double>(3 * static_cast<size_t>(B));
+    sc.Cf = grad ? cv.take<double>(3 * static_cast<size_t>(std::min<int64_t>(std::max(F, 1), kGeomChunk)))
+                 : nullptr;
     if (m) {
+        m->gface = gface; m->gbface = gbface;
         m->owner = owner; m->neighbour = neighbour; m->owner_start = owner_start;
         m->losort = losort; m->losort_start = losort_start; m->bface_start = bface_start;
         m->bface_list = bface_list; m->bface_cell = bface_cell; m->bface_patch = bface_patch;
@@ -463,6 +472,8 @@ static lf_status validate(const lf_mesh_desc *d, int32_t *B_out, bool *two_colou
         set_error("NULL mesh array");
         return LF_EINVAL;
     }
+    if ((d->flags & ~LF_MESH_NON_ORTHOGONAL) != 0) { set_error("unknown mesh flags 0x%x", d->flags); return LF_EINVAL; }
+    const bool skew_ok = (d->flags & LF_MESH_NON_ORTHOGONAL) != 0;
     if (d->patch_start[0] != 0) { set_error("patch_start[0] must be 0"); return LF_EMESH; }
     for (int32_t p = 0; p < P; ++p)
         if (d->patch_start[p + 1] < d->patch_start[p]) { set_error("patch_start not monotone"); return LF_EMESH; }
@@ -501,9 +512,16 @@ static lf_status validate(const lf_mesh_desc *d, int32_t *B_out, bool *two_colou
         double d2 = dx * dx + dy * dy + dz * dz;
         double sd = S[0] * dx + S[1] * dy + S[2] * dz;
         if (!(s2 > 0.0) || !(d2 > 0.0) || !std::isfinite(s2) || !(sd > 0.0) ||
-            cx * cx + cy * cy + cz * cz > 1e-18 * s2 * d2) {
+            (!skew_ok && cx * cx + cy * cy + cz * cz > 1e-18 * s2 * d2)) {
             set_error("face %d: degenerate, inward or non-orthogonal face", f);
             return LF_EMESH;
+        }
+        if (d->face_centre) {
+            const double *Cf = d->face_centre + 3 * static_cast<int64_t>(f);
+            if (!std::isfinite(Cf[0]) || !std::isfinite(Cf[1]) || !std::isfinite(Cf[2])) {
+                set_error("face %d: non-finite face centre", f);
+                return LF_EMESH;
+            }
         }
     }
     for (int32_t b = 0; b < B; ++b) {
@@ -578,7 +596,8 @@ size_t lf_mesh_workspace_bytes(const lf_mesh_desc *d) {
     int64_t E = 0;
     if (plan_slices(d, nullptr, reorder, nullptr, &E) != LF_OK) return 0;
     Carver cv(nullptr);
-    carve_mesh(cv, d->n_cells, d->n_faces, d->patch_start[d->n_patches], E, bo.k, reorder, nullptr, nullptr);
+    carve_mesh(cv, d->n_cells, d->n_faces, d->patch_start[d->n_patches], E, bo.k, reorder,
+               d->face_centre != nullptr, nullptr, nullptr);
     return cv.bytes();
 }
 
@@ -597,8 +616,9 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
     std::vector<int32_t> soff_h;
     int64_t E = 0;
     LF_TRY(plan_slices(d, &iperm_h, false, &soff_h, &E));
+    const bool grad = d->face_centre != nullptr;
     Carver dry(nullptr);
-    carve_mesh(dry, N, F, B, E, bo.k, reorder, nullptr, nullptr);
+    carve_mesh(dry, N, F, B, E, bo.k, reorder, grad, nullptr, nullptr);
     if (!ws || ws_bytes < dry.bytes() || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) {
         set_error("mesh workspace too small or misaligned: need %zu bytes, 256-aligned", dry.bytes());
         return LF_ENOMEM;
@@ -616,7 +636,8 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
     if (hipGetDevice(&m->device) != hipSuccess) { delete m; set_error("hipGetDevice failed"); return LF_EDEVICE; }
     Carver cv(ws);
     MeshScratch sc;
-    carve_mesh(cv, N, F, B, E, bo.k, reorder, m, &sc);
+    carve_mesh(cv, N, F, B, E, bo.k, reorder, grad, m, &sc);
+    m->orthogonal = (d->flags & LF_MESH_NON_ORTHOGONAL) == 0;
     hipStream_t s = m->stream;
 
     auto fail = [&](lf_status st) { delete m; return st; };
@@ -689,6 +710,12 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
                                hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_face_geometry, dim3(blocks_for(cnt)), dim3(kBlock), 0, s, static_cast<int32_t>(f0),
                            cnt, m->owner, m->neighbour, sc.C, sc.S, m->mag_sf, m->delta);
+        if (grad) {
+            LF_HIPM(hipMemcpyAsync(sc.Cf, d->face_centre + 3 * f0, sizeof(double) * 3 * static_cast<size_t>(cnt),
+                                   hipMemcpyHostToDevice, s));
+            launch_grad_face_geometry(static_cast<int32_t>(f0), cnt, m->owner, m->neighbour, sc.C, sc.S, sc.Cf,
+                                      m->gface, s);
+        }
     }
     if (bo.k > 0) {
         const int64_t slots = static_cast<int64_t>(bo.k) * N;
@@ -703,6 +730,7 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
     if (B > 0)
         hipLaunchKernelGGL(k_bface_geometry, dim3(blocks_for(B)), dim3(kBlock), 0, s, B, m->bface_cell, sc.C,
                            sc.bS, sc.bC, m->bmag_sf, m->bdelta);
+    if (grad && B > 0) launch_grad_bface_geometry(B, sc.bS, m->gbface, s);
     LF_HIPM(hipGetLastError());
     LF_HIPM(hipStreamSynchronize(s));
 #undef LF_HIPM

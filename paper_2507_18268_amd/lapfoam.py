@@ -33,6 +33,7 @@ LF_LAYOUT_BANDS = 2
 LF_WALK_AUTO = 0
 LF_WALK_ON = 1
 LF_WALK_OFF = 2
+LF_MESH_NON_ORTHOGONAL = 1
 
 _STATUS = {0: "LF_OK", -1: "LF_EINVAL", -2: "LF_EMESH", -3: "LF_ENOMEM", -4: "LF_EBUDGET",
            -5: "LF_EDEVICE", -6: "LF_ESTATE", -7: "LF_ENONFINITE"}
@@ -46,7 +47,7 @@ class LapfoamError(RuntimeError):
 
 class lf_mesh_desc(C.Structure):
     _fields_ = [("n_cells", C.c_int32), ("n_faces", C.c_int32), ("n_patches", C.c_int32),
-                ("reserved", C.c_int32), ("owner", C.c_void_p), ("neighbour", C.c_void_p),
+                ("flags", C.c_int32), ("owner", C.c_void_p), ("neighbour", C.c_void_p),
                 ("cell_volume", C.c_void_p), ("cell_centre", C.c_void_p),
                 ("face_area", C.c_void_p), ("face_centre", C.c_void_p),
                 ("patch_start", C.c_void_p), ("bface_cell", C.c_void_p),
@@ -105,6 +106,7 @@ _SIGS = {
     "lf_assemble": (C.c_int32, [C.c_void_p]),
     "lf_get_matrix": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 7),
     "lf_amul": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lf_grad": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 5),
     "lf_batch_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
     "lf_batch_create": (C.c_int32, [C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
                                     C.POINTER(C.c_void_p)]),
@@ -290,6 +292,11 @@ def lf_get_matrix(h, diag=None, upper=None, source=None, diag_b=None, source_b=N
            "lf_get_matrix")
 
 
+def lf_grad(h, T_ptr, Tb_ptr, snb_ptr, grad_ptr, bgrad_ptr):
+    _check(lib().lf_grad(h, C.c_void_p(T_ptr), C.c_void_p(Tb_ptr), C.c_void_p(snb_ptr),
+                         C.c_void_p(grad_ptr), C.c_void_p(bgrad_ptr)), "lf_grad")
+
+
 def lf_amul(h, x_ptr, y_ptr):
     _check(lib().lf_amul(h, C.c_void_p(x_ptr), C.c_void_p(y_ptr)), "lf_amul")
 
@@ -371,11 +378,13 @@ class Mesh:
 
     `m` has the fields of lf_mesh_desc as numpy arrays: n_cells, n_faces,
     owner, neighbour, cell_volume, cell_centre [N,3], face_area [F,3],
-    patch_start, bface_cell, bface_area [B,3], bface_centre [B,3]
-    (face_centre optional).
+    patch_start, bface_cell, bface_area [B,3], bface_centre [B,3], and
+    face_centre [F,3] when `gradient` (the mesh then serves `grad`).
+    `non_orthogonal` accepts skewed faces (gradient only: problems refuse
+    such a mesh).
     """
 
-    def __init__(self, m, stream=None):
+    def __init__(self, m, stream=None, gradient=False, non_orthogonal=False):
         torch = _torch()
         self._keep = dict(
             owner=np.ascontiguousarray(m.owner, dtype=np.int32),
@@ -387,6 +396,8 @@ class Mesh:
             bface_cell=np.ascontiguousarray(m.bface_cell, dtype=np.int32),
             bface_area=np.ascontiguousarray(m.bface_area, dtype=np.float64),
             bface_centre=np.ascontiguousarray(m.bface_centre, dtype=np.float64))
+        if gradient:
+            self._keep["face_centre"] = np.ascontiguousarray(m.face_centre, dtype=np.float64)
         k = self._keep
         self.n_cells = int(m.n_cells)
         self.n_faces = int(m.n_faces)
@@ -397,7 +408,9 @@ class Mesh:
         for name in ("owner", "neighbour", "cell_volume", "cell_centre", "face_area",
                      "patch_start", "bface_cell", "bface_area", "bface_centre"):
             setattr(d, name, k[name].ctypes.data)
-        d.face_centre = None
+        d.face_centre = k["face_centre"].ctypes.data if gradient else None
+        d.flags = LF_MESH_NON_ORTHOGONAL if non_orthogonal else 0
+        self.has_gradient = bool(gradient)
         self.desc = d
         self.ws_bytes = lf_mesh_workspace_bytes(d)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device="cuda")
@@ -411,6 +424,24 @@ class Mesh:
         """(reordered, order): whether the solver keeps the cells in Morton order
         of their centres, and the mesh cell of each solver row."""
         return lf_mesh_cell_order(self.h, self.n_cells)
+
+    def grad(self, T, Tb, snb=None, with_boundary=True):
+        """Gauss gradient of the cell field T (device float64 tensor [N], mesh
+        order) with boundary values Tb [B] and, for the boundary gradient,
+        their normal gradients snb [B].  Returns (grad [N,3], bgrad [B,3] or
+        None) as new device tensors, ordered on the mesh's stream."""
+        torch = _torch()
+        N, B = self.n_cells, self.n_bfaces
+        for name, t, n in (("T", T, N), ("Tb", Tb, B)) + ((("snb", snb, B),) if with_boundary else ()):
+            if t is None or t.dtype != torch.float64 or not t.is_cuda or t.numel() != n \
+                    or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous CUDA float64 tensor of {n} values")
+        g = torch.empty((N, 3), dtype=torch.float64, device=T.device)
+        bg = torch.empty((max(B, 1), 3), dtype=torch.float64, device=T.device) if with_boundary else None
+        lf_grad(self.h, T.data_ptr(), Tb.data_ptr() if B else 0,
+                snb.data_ptr() if (with_boundary and B) else 0, g.data_ptr(),
+                bg.data_ptr() if with_boundary else 0)
+        return g, (bg[:B] if with_boundary else None)
 
     def addressing(self):
         N, F, B = self.n_cells, self.n_faces, self.n_bfaces

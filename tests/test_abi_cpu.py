@@ -173,3 +173,32 @@ def test_mesh_rows_longer_than_255_are_refused():
     with pytest.raises(L.LapfoamError) as e:
         L.lf_mesh_create(d, 0, 1 << 20, 0)
     assert e.value.status == L.LF_EMESH and "255" in L.lf_last_error()
+
+
+def test_mesh_flags_on_host():
+    """LF_MESH_NON_ORTHOGONAL lets a skewed box past validation (the call then
+    stops at the missing workspace, before any device call); unknown flags are
+    refused; face centres add the gradient's records to the workspace."""
+    from paper_2507_18268_amd import lapfoam as L
+    import numpy as np
+    import synth
+    mesh = synth.affine(synth.box_mesh(4, 3, 3), synth.SKEW)
+    keep = []
+    d = _desc(L, _box_dict(mesh), keep)
+    with pytest.raises(L.LapfoamError) as e:
+        L.lf_mesh_create(d, 0, 1 << 20, 0)
+    assert e.value.status == L.LF_EMESH
+    d.flags = L.LF_MESH_NON_ORTHOGONAL
+    with pytest.raises(L.LapfoamError) as e:
+        L.lf_mesh_create(d, 0, 1 << 20, 0)
+    assert e.value.status == L.LF_ENOMEM, L.lf_last_error()
+    d.flags = 4
+    with pytest.raises(L.LapfoamError) as e:
+        L.lf_mesh_create(d, 0, 1 << 20, 0)
+    assert e.value.status == L.LF_EINVAL
+    d.flags = L.LF_MESH_NON_ORTHOGONAL
+    plain = L.lf_mesh_workspace_bytes(d)
+    fc = np.ascontiguousarray(mesh.face_centre)
+    d.face_centre = fc.ctypes.data
+    with_grad = L.lf_mesh_workspace_bytes(d)
+    assert with_grad >= plain + 32 * (mesh.n_faces + mesh.n_bfaces)
