@@ -42,9 +42,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
+GRAD_SOURCES = ["paper_2507_18268_amd/csrc/lf_grad.hip"]
+GRAD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_grad_band_skewed256.json")
+
+
+def kernel_source_hash(sources=None):
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in (sources or KERNEL_SOURCES):
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -206,12 +210,15 @@ def run_config_leg(L, torch, name, steps, warmup=1):
     return out
 
 
-def grad_bytes(n_cells, n_faces, n_bfaces):
-    """Algorithmic bytes of one Gauss-gradient launch: per cell T, V, the
-    gradient (3 doubles) and three list starts; per internal face its 32-byte
-    record, its lower-list entry, and the other cell's label on each side; per
-    boundary face its list entry, T_b, snGrad_b, its record and the boundary
-    gradient."""
+def grad_bytes(n_cells, n_faces, n_bfaces, n_bands=0):
+    """Algorithmic bytes of one Gauss-gradient launch.  Both paths: per cell
+    T, V and the gradient (3 doubles); per boundary face its list entry, T_b,
+    snGrad_b, its 32-byte record and the boundary gradient.  Band path: the
+    boundary-list start per cell and one 32-byte record per band slot (n_bands
+    per cell).  List path: three list starts per cell; per internal face its
+    record, its lower-list entry and the other cell's label on each side."""
+    if n_bands:
+        return 44 * n_cells + 32 * n_bands * n_cells + 76 * n_bfaces
     return 52 * n_cells + 44 * n_faces + 76 * n_bfaces
 
 
@@ -240,13 +247,23 @@ def run_grad(L, torch, p, launches=20):
     e1.record()
     torch.cuda.synchronize()
     us = e0.elapsed_time(e1) * 1e3 / launches
+    K = m.n_bands
     m.close()
-    nbytes = grad_bytes(N, F, B)
+    nbytes = grad_bytes(N, F, B, K)
     gbps = nbytes / (us * 1e-6) / 1e9
+    kname = f"k_grad_band<{K}>" if K else "k_grad"
+    traffic = None
+    if os.path.exists(GRAD_TRAFFIC_FILE):
+        with open(GRAD_TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        # counters taken on this kernel source and size only
+        if (tr.get("source_sha256") == kernel_source_hash(GRAD_SOURCES) and tr.get("n_cells") == N
+                and tr.get("kernel") == kname):
+            traffic = tr["hbm_bytes_per_launch"]
     return {"workload": f"Gauss gradient, {round(N ** (1 / 3))}^3 box graded in z and skewed",
-            "kernel": "k_grad", "launches": launches, "avg_us": us,
+            "kernel": kname, "launches": launches, "avg_us": us,
             "algorithmic_bytes": nbytes, "achieved_GBps": gbps, "peak_GBps": HBM_PEAK_GBS,
-            "frac": gbps / HBM_PEAK_GBS}
+            "frac": gbps / HBM_PEAK_GBS, "traffic": traffic}
 
 
 def run_serving(L, torch, args):
@@ -335,6 +352,8 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=0.0, help="mixed: inner reduction (0 = default)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--grad-only", action="store_true",
+                    help="only the Gauss-gradient leg (for profiling it alone)")
     ap.add_argument("--no-extra-configs", action="store_true")
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--serve-sweep", action="store_true", help="Poisson rates 0.25x..4x of saturated")
@@ -383,6 +402,9 @@ def main():
     p = synth.build_config(args.config, n=args.n)
     N, F = p.mesh.n_cells, p.mesh.n_faces
     log(f"[bench] {args.config}: {N} cells, {F} faces, mesh generated in {time.perf_counter() - t:.1f} s")
+    if args.grad_only:
+        print(json.dumps({"grad": run_grad(L, torch, p)}), flush=True)
+        return
     precond = L.LF_PC_DIC if p.precond == "dic" else L.LF_PC_DIAGONAL
     precision = L.LF_PREC_MIXED if p.precision == "mixed" else L.LF_PREC_FP64
     opts = L.make_opts(tol=synth.TOL, rel_tol=synth.REL_TOL, max_iter=synth.MAX_ITER,

@@ -225,10 +225,11 @@ lf_status lf_mesh_get_addressing(const lf_mesh *mesh, int32_t *owner_start, int3
  *            whose neighbour is c of S_f s_f + sum over its boundary faces of
  *            S_b Tb_b) / V_c
  *   bgrad_b = grad_P + n (snGrad_b - n.grad_P), n = S_b/|S_b|, P the face cell.
- * One thread gathers each cell's faces through the lists of lists (lower faces
- * ascending, then owned faces ascending, then boundary faces ascending: the
- * order in which the sequential face loop reaches the cell), so each result
- * equals, bit for bit, the sequential loop over faces then boundary faces.
+ * One thread takes each cell's faces (lower faces ascending, then owned faces
+ * ascending, then boundary faces ascending: the order in which the sequential
+ * face loop reaches the cell), from band slots on a mesh with band form, else
+ * through the lists of lists, so each result equals, bit for bit, the
+ * sequential loop over faces then boundary faces.
  * T[N], Tb[B] (the field's boundary values) and snGrad_b[B] (its normal
  * gradient on the boundary faces) are device inputs in the mesh's cell and
  * boundary-face order; grad[3N] and bgrad[3B] (xyz interleaved, same orders)

@@ -127,7 +127,11 @@ struct lf_mesh {
     // Gauss gradient geometry (meshes created with face centres), in the
     // mesh's face order: per internal face {S_x, S_y, S_z, w_f} and per
     // boundary face {S_x, S_y, S_z, |S_b|}, 32 bytes each (two 16-byte loads)
+    // On a mesh with band form the face records are kept by band slot
+    // instead (gband, slot k*N + c for the face (c, c + band_d[k]), zero where
+    // there is no such face) and gface is null.
     double *gface = nullptr;                              // [4F], or null
+    double *gband = nullptr;                              // [4*n_bands*N], or null
     double *gbface = nullptr;                             // [4B], or null
     bool orthogonal = true;     // created without LF_MESH_NON_ORTHOGONAL
     size_t ws_bytes = 0;
@@ -138,9 +142,11 @@ struct lf_problem;   // defined in lf_problem.h
 namespace lf {
 // Gauss gradient geometry, built once per mesh (lf_grad.hip): the face records
 // of faces [f0, f0 + cnt) from that chunk's area vectors S[3cnt] and centres
-// Cf[3cnt] (cell centres C[3N]); the boundary-face records from S_b[3B]
-void launch_grad_face_geometry(int32_t f0, int32_t cnt, const int32_t *owner, const int32_t *neighbour,
-                               const double *C, const double *S, const double *Cf, double *gface,
-                               hipStream_t s);
+// Cf[3cnt] (cell centres C[3N]), stored at face f of gface, or, when bo.k > 0,
+// at the face's band slot of gband (zeroed beforehand); the boundary-face
+// records from S_b[3B]
+void launch_grad_face_geometry(int32_t f0, int32_t cnt, int32_t N, BandOffsets bo, const int32_t *owner,
+                               const int32_t *neighbour, const double *C, const double *S, const double *Cf,
+                               double *gface, double *gband, hipStream_t s);
 void launch_grad_bface_geometry(int32_t nb, const double *bS, double *gbface, hipStream_t s);
 }  // namespace lf

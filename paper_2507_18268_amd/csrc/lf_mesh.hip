@@ -323,9 +323,12 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, i
         band_mag = cv.take<double>(static_cast<size_t>(K) * N);
         band_delta = cv.take<double>(static_cast<size_t>(K) * N);
     }
-    double *gface = nullptr, *gbface = nullptr;
+    double *gface = nullptr, *gband = nullptr, *gbface = nullptr;
     if (grad) {
-        gface = cv.take<double>(4 * static_cast<size_t>(F));
+        if (K > 0)
+            gband = cv.take<double>(4 * static_cast<size_t>(K) * N);
+        else
+            gface = cv.take<double>(4 * static_cast<size_t>(F));
         gbface = cv.take<double>(4 * static_cast<size_t>(B));
     }
     size_t tiles = (n1 + kScanTile - 1) / kScanTile + 1;
@@ -339,7 +342,7 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, i
     sc.Cf = grad ? cv.take<double>(3 * static_cast<size_t>(std::min<int64_t>(std::max(F, 1), kGeomChunk)))
                  : nullptr;
     if (m) {
-        m->gface = gface; m->gbface = gbface;
+        m->gface = gface; m->gband = gband; m->gbface = gbface;
         m->owner = owner; m->neighbour = neighbour; m->owner_start = owner_start;
         m->losort = losort; m->losort_start = losort_start; m->bface_start = bface_start;
         m->bface_list = bface_list; m->bface_cell = bface_cell; m->bface_patch = bface_patch;
@@ -704,6 +707,10 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
                        m->rlen);
 
     // geometry factors, faces staged in chunks
+    if (m->gband) {
+        const int64_t slots = 4 * static_cast<int64_t>(bo.k) * N;
+        hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(slots)), dim3(kBlock), 0, s, m->gband, slots, 0.0);
+    }
     for (int64_t f0 = 0; f0 < F; f0 += kGeomChunk) {
         int32_t cnt = static_cast<int32_t>(std::min<int64_t>(kGeomChunk, F - f0));
         LF_HIPM(hipMemcpyAsync(sc.S, d->face_area + 3 * f0, sizeof(double) * 3 * static_cast<size_t>(cnt),
@@ -713,8 +720,8 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
         if (grad) {
             LF_HIPM(hipMemcpyAsync(sc.Cf, d->face_centre + 3 * f0, sizeof(double) * 3 * static_cast<size_t>(cnt),
                                    hipMemcpyHostToDevice, s));
-            launch_grad_face_geometry(static_cast<int32_t>(f0), cnt, m->owner, m->neighbour, sc.C, sc.S, sc.Cf,
-                                      m->gface, s);
+            launch_grad_face_geometry(static_cast<int32_t>(f0), cnt, N, bo, m->owner, m->neighbour, sc.C, sc.S,
+                                      sc.Cf, m->gface, m->gband, s);
         }
     }
     if (bo.k > 0) {

@@ -42,6 +42,7 @@ def _meshes():
     tiny = synth.box_mesh(3, 3, 2)
     yield "skew_random_3x3x2", skew(synth.renumber(tiny, synth.random_permutation(tiny.n_cells, 4))), True
     yield "line_9", synth.renumber(synth.box_mesh(9, 1, 1), synth.random_permutation(9, 6)), False
+    yield "line_9_natural", synth.box_mesh(9, 1, 1, z_ratio=1.0), False
     yield "one_cell", skew(synth.box_mesh(1, 1, 1)), True
     yield "no_patches_5x4x3", _strip_boundary(skew(synth.box_mesh(5, 4, 3, z_ratio=2.0))), True
 
@@ -127,6 +128,20 @@ def test_grad_errors(L):
     with pytest.raises(L.LapfoamError, match="LF_EINVAL"):
         plain.grad(T, Tb, Tb)
     plain.close()
+
+
+def test_grad_skewed_128(L, oracle):
+    """128^3 skewed box (two cells per thread along z, 8192 workgroups):
+    every output bit for bit."""
+    mesh = synth.affine(synth.box_mesh(128, 128, 128, z_ratio=10.0), synth.SKEW)
+    m = L.Mesh(mesh, gradient=True, non_orthogonal=True)
+    assert m.n_bands == 3
+    T, Tb, snb = _inputs(mesh, 71)
+    g, bg = _gpu_grad(L, m, T, Tb, snb)
+    m.close()
+    og, obg = oracle.gauss_grad(mesh, T, Tb, snb)
+    assert np.array_equal(g, og), float(np.max(np.abs(g - og)))
+    assert np.array_equal(bg, obg), float(np.max(np.abs(bg - obg)))
 
 
 def test_grad_full_size_skewed_256(L, oracle):
