@@ -43,6 +43,7 @@ def log(*a):
 
 
 GRAD_SOURCES = ["paper_2507_18268_amd/csrc/lf_grad.hip"]
+GRAD_LABEL = "256^3 box graded in z (ratio 10) and skewed"
 GRAD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_grad_band_skewed256.json")
 
 
@@ -210,24 +211,27 @@ def run_config_leg(L, torch, name, steps, warmup=1):
     return out
 
 
-def grad_bytes(n_cells, n_faces, n_bfaces, n_bands=0):
-    """Algorithmic bytes of one Gauss-gradient launch.  Both paths: per cell
-    T, V and the gradient (3 doubles); per boundary face its list entry, T_b,
-    snGrad_b, its 32-byte record and the boundary gradient.  Band path: the
-    boundary-list start per cell and one 32-byte record per band slot (n_bands
-    per cell).  List path: three list starts per cell; per internal face its
-    record, its lower-list entry and the other cell's label on each side."""
+def grad_bytes(n_cells, n_faces, n_bfaces, n_bands=0, reordered=False):
+    """Algorithmic bytes of one Gauss-gradient call.  Both paths: per cell T,
+    V, the gradient (3 doubles) and the boundary-list start; per boundary face
+    its list entry, T_b, snGrad_b, its 32-byte record and the boundary
+    gradient.  Band path: one 32-byte record per band slot (n_bands per cell).
+    Row path: the row length per cell and, per internal face, on each of its
+    two rows a 32-byte record and a column index; a mesh kept in Morton order
+    adds the field's copy into that order (label, read, write) and the
+    label of each row's mesh cell."""
     if n_bands:
         return 44 * n_cells + 32 * n_bands * n_cells + 76 * n_bfaces
-    return 52 * n_cells + 44 * n_faces + 76 * n_bfaces
+    return 45 * n_cells + 72 * n_faces + 76 * n_bfaces + (24 * n_cells if reordered else 0)
 
 
-def run_grad(L, torch, p, launches=20):
+def run_grad(L, torch, p, label, launches=20):
     """The Gauss gradient on the config's box, skewed (non-orthogonal faces)."""
     import numpy as np
     import synth
     host = synth.affine(p.mesh, synth.SKEW)
     m = L.Mesh(host, gradient=True, non_orthogonal=True)
+    reordered = bool(m.cell_order()[0])
     N, F, B = host.n_cells, host.n_faces, host.n_bfaces
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
     T = dev(synth.initial_field(N, 61))
@@ -249,9 +253,9 @@ def run_grad(L, torch, p, launches=20):
     us = e0.elapsed_time(e1) * 1e3 / launches
     K = m.n_bands
     m.close()
-    nbytes = grad_bytes(N, F, B, K)
+    nbytes = grad_bytes(N, F, B, K, reordered)
     gbps = nbytes / (us * 1e-6) / 1e9
-    kname = f"k_grad_band<{K}>" if K else "k_grad"
+    kname = f"k_grad_band<{K}>" if K else "k_grad_rows"
     traffic = None
     if os.path.exists(GRAD_TRAFFIC_FILE):
         with open(GRAD_TRAFFIC_FILE) as f:
@@ -260,7 +264,7 @@ def run_grad(L, torch, p, launches=20):
         if (tr.get("source_sha256") == kernel_source_hash(GRAD_SOURCES) and tr.get("n_cells") == N
                 and tr.get("kernel") == kname):
             traffic = tr["hbm_bytes_per_launch"]
-    return {"workload": f"Gauss gradient, {round(N ** (1 / 3))}^3 box graded in z and skewed",
+    return {"workload": f"Gauss gradient, {label}",
             "kernel": kname, "launches": launches, "avg_us": us,
             "algorithmic_bytes": nbytes, "achieved_GBps": gbps, "peak_GBps": HBM_PEAK_GBS,
             "frac": gbps / HBM_PEAK_GBS, "traffic": traffic}
@@ -403,7 +407,7 @@ def main():
     N, F = p.mesh.n_cells, p.mesh.n_faces
     log(f"[bench] {args.config}: {N} cells, {F} faces, mesh generated in {time.perf_counter() - t:.1f} s")
     if args.grad_only:
-        print(json.dumps({"grad": run_grad(L, torch, p)}), flush=True)
+        print(json.dumps({"grad": run_grad(L, torch, p, GRAD_LABEL)}), flush=True)
         return
     precond = L.LF_PC_DIC if p.precond == "dic" else L.LF_PC_DIAGONAL
     precision = L.LF_PREC_MIXED if p.precision == "mixed" else L.LF_PREC_FP64
@@ -504,7 +508,11 @@ def main():
 
     if not args.no_grad and args.n is None:
         log("[bench] Gauss gradient ...")
-        out["grad"] = run_grad(L, torch, p)
+        out["grad"] = run_grad(L, torch, p, GRAD_LABEL)
+        if not args.no_extra_configs:
+            # the row path: the randomly numbered 192^3 box, skewed (kept in Morton order)
+            out["grad_rows"] = run_grad(L, torch, synth.build_config("permuted_192"),
+                                        "192^3 box graded in z, randomly numbered and skewed")
 
     if not args.no_serve:
         out["serving"] = run_serving(L, torch, args)

@@ -1,6 +1,6 @@
 // Gauss gradient of a cell field (Section 5.2: calcGrad = interpolate, gradf,
-// correctBoundaryConditions), gathered per cell: through the lists of lists,
-// or, on meshes with band form, from band slots (k_grad_band below).
+// correctBoundaryConditions), gathered per cell: over the row layout built
+// from the lists of lists, or, on meshes with band form, from band slots.
 //
 // The paper parallelises the face loop of gradf, which scatters S_f s_f to the
 // owner (+) and the neighbour (-) of each face, by turning it into a gather:
@@ -91,63 +91,94 @@ void launch_grad_bface_geometry(int32_t nb, const double *bS, double *gbface, hi
 
 constexpr int kGradBlock = 256;
 
-// One cell per thread, mesh order.  V is in the solver's order: V[vperm[c]]
-// when the mesh keeps its cells reordered (vperm = perm), else V[c].
+// Per-entry records of the row layout, one thread per solver row over exactly
+// the entries of the row: the face's record, negated (area vector and weight)
+// when the row's cell is the face's neighbour.  The weight is >= 0, so its sign
+// bit tells the two kinds apart (-0.0 for a zero weight).
+__global__ void k_grad_entry_geometry(int32_t n, const int32_t *__restrict__ soff, const int32_t *__restrict__ sface,
+                                      const uint8_t *__restrict__ rlen, const int32_t *__restrict__ iperm,
+                                      const int32_t *__restrict__ neighbour, const double *__restrict__ gface,
+                                      double *__restrict__ gerec) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int32_t mc = iperm ? iperm[r] : static_cast<int32_t>(r);
+    int64_t idx = soff[r / kSlice] + r % kSlice;
+    for (int32_t j = 0; j < rlen[r]; ++j, idx += kSlice) {
+        const int32_t f = sface[idx];
+        const Rec q = load_rec(gface, f);
+        if (neighbour[f] == mc)
+            store_rec(gerec, idx, -q.x, -q.y, -q.z, -q.w);
+        else
+            store_rec(gerec, idx, q.x, q.y, q.z, q.w);
+    }
+}
+
+void launch_grad_entry_geometry(const lf_mesh *m, hipStream_t s) {
+    hipLaunchKernelGGL(k_grad_entry_geometry, dim3((m->N + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m->N, m->soff,
+                       m->sface, m->rlen, m->iperm, m->neighbour, m->gface, m->gerec);
+}
+
+// the field in the solver's row order: Ts[r] = T[iperm[r]]
+__global__ void k_grad_to_rows(int32_t n, const int32_t *__restrict__ iperm, const double *__restrict__ T,
+                               double *__restrict__ Ts) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r < n) Ts[r] = T[iperm[r]];
+}
+
+// Meshes without band form: one solver row per thread over the row layout,
+// whose entries are the row's lower faces then its owned faces, each in
+// ascending face order (the face loop's order); then the row's boundary faces
+// ascending.  The field is read in the solver's order (Ts: T itself when the
+// mesh keeps its order, else its copy in Morton order), so neighbours' values
+// lie near the row; the gradient goes to the row's mesh cell.
 __global__ void __launch_bounds__(kGradBlock)
-k_grad(int32_t n, const double *__restrict__ T, const double *__restrict__ Tb, const double *__restrict__ snb,
-       const int32_t *__restrict__ owner, const int32_t *__restrict__ neighbour,
-       const int32_t *__restrict__ owner_start, const int32_t *__restrict__ losort,
-       const int32_t *__restrict__ losort_start, const int32_t *__restrict__ bface_start,
-       const int32_t *__restrict__ bface_list, const double *__restrict__ gface,
-       const double *__restrict__ gbface, const double *__restrict__ V, const int32_t *__restrict__ vperm,
-       double *__restrict__ grad, double *__restrict__ bgrad) {
-    const int64_t c = static_cast<int64_t>(blockIdx.x) * kGradBlock + threadIdx.x;
-    if (c >= n) return;
-    const double Tc = T[c];
-    const double v = V[vperm ? vperm[c] : c];
-    const int32_t l0 = losort_start[c], l1 = losort_start[c + 1];
-    const int32_t o0 = owner_start[c], o1 = owner_start[c + 1];
-    const int32_t b0 = bface_start[c], b1 = bface_start[c + 1];
+k_grad_rows(int32_t n, const double *__restrict__ Ts, const double *__restrict__ Tb, const double *__restrict__ snb,
+            const int32_t *__restrict__ soff, const int32_t *__restrict__ scol, const uint8_t *__restrict__ rlen,
+            const double *__restrict__ gerec, const int32_t *__restrict__ rbface_start,
+            const int32_t *__restrict__ rbface_list, const double *__restrict__ gbface,
+            const double *__restrict__ V, const int32_t *__restrict__ iperm, double *__restrict__ grad,
+            double *__restrict__ bgrad) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * kGradBlock + threadIdx.x;
+    if (r >= n) return;
+    const int64_t idx0 = soff[r / kSlice] + r % kSlice;
+    const int32_t len = rlen[r];
+    const double Tr = Ts[r];
+    const double v = V[r];
+    const int32_t b0 = rbface_start[r], b1 = rbface_start[r + 1];
     double gx = 0.0, gy = 0.0, gz = 0.0;
-    // faces whose neighbour is c: s_f = w (T_P - T_c) + T_c, subtracted
-    for (int32_t k = l0; k < l1; ++k) {
-        const int32_t f = losort[k];
-        const Rec r = load_rec(gface, f);
-        const double s = r.w * (T[owner[f]] - Tc) + Tc;
-        gx -= r.x * s;
-        gy -= r.y * s;
-        gz -= r.z * s;
+    for (int32_t j = 0; j < len; ++j) {
+        const int64_t idx = idx0 + static_cast<int64_t>(kSlice) * j;
+        const Rec q = load_rec(gerec, idx);
+        const double To = Ts[scol[idx]];
+        // lower face (negated record): s = w (T_P - T_r) + T_r, g -= S s;
+        // owned face: s = w (T_r - T_N) + T_N, g += S s
+        const double w = fabs(q.w);
+        const double s = signbit(q.w) ? w * (To - Tr) + Tr : w * (Tr - To) + To;
+        gx += q.x * s;
+        gy += q.y * s;
+        gz += q.z * s;
     }
-    // faces c owns: s_f = w (T_c - T_N) + T_N, added
-    for (int32_t f = o0; f < o1; ++f) {
-        const Rec r = load_rec(gface, f);
-        const double TN = T[neighbour[f]];
-        const double s = r.w * (Tc - TN) + TN;
-        gx += r.x * s;
-        gy += r.y * s;
-        gz += r.z * s;
-    }
-    // boundary faces: S_b T_b, added
     for (int32_t k = b0; k < b1; ++k) {
-        const int32_t b = bface_list[k];
-        const Rec r = load_rec(gbface, b);
+        const int32_t b = rbface_list[k];
+        const Rec q = load_rec(gbface, b);
         const double tb = Tb[b];
-        gx += r.x * tb;
-        gy += r.y * tb;
-        gz += r.z * tb;
+        gx += q.x * tb;
+        gy += q.y * tb;
+        gz += q.z * tb;
     }
     gx /= v;
     gy /= v;
     gz /= v;
+    const int64_t c = iperm ? iperm[r] : r;
     grad[3 * c] = gx;
     grad[3 * c + 1] = gy;
     grad[3 * c + 2] = gz;
     if (!bgrad) return;
     // boundary value: g_b = g_c + n (snGrad_b - n.g_c), n = S_b / |S_b|
     for (int32_t k = b0; k < b1; ++k) {
-        const int32_t b = bface_list[k];
-        const Rec r = load_rec(gbface, b);
-        const double nx = r.x / r.w, ny = r.y / r.w, nz = r.z / r.w;
+        const int32_t b = rbface_list[k];
+        const Rec q = load_rec(gbface, b);
+        const double nx = q.x / q.w, ny = q.y / q.w, nz = q.z / q.w;
         const double d = snb[b] - (nx * gx + ny * gy + nz * gz);
         bgrad[3 * static_cast<int64_t>(b)] = gx + nx * d;
         bgrad[3 * static_cast<int64_t>(b) + 1] = gy + ny * d;
@@ -296,9 +327,14 @@ extern "C" lf_status lf_grad(const lf_mesh *m, const double *T, const double *Tb
     if (m->B == 0) bgrad = nullptr;
     const dim3 block(kGradBlock);
     if (!m->gband) {
-        hipLaunchKernelGGL(k_grad, dim3((m->N + kGradBlock - 1) / kGradBlock), block, 0, m->stream, m->N, T, Tb,
-                           snb, m->owner, m->neighbour, m->owner_start, m->losort, m->losort_start,
-                           m->bface_start, m->bface_list, m->gface, m->gbface, m->V, m->perm, grad, bgrad);
+        const dim3 grid((m->N + kGradBlock - 1) / kGradBlock);
+        const double *Ts = T;
+        if (m->iperm) {
+            hipLaunchKernelGGL(k_grad_to_rows, grid, block, 0, m->stream, m->N, m->iperm, T, m->gT);
+            Ts = m->gT;
+        }
+        hipLaunchKernelGGL(k_grad_rows, grid, block, 0, m->stream, m->N, Ts, Tb, snb, m->soff, m->scol, m->rlen,
+                           m->gerec, m->rbface_start, m->rbface_list, m->gbface, m->V, m->iperm, grad, bgrad);
         LF_HIP(hipGetLastError());
         return LF_OK;
     }

@@ -130,7 +130,13 @@ struct lf_mesh {
     // On a mesh with band form the face records are kept by band slot
     // instead (gband, slot k*N + c for the face (c, c + band_d[k]), zero where
     // there is no such face) and gface is null.
+    // Without band form the records are also kept per entry of the row layout
+    // (gerec, in the solver's row order; an entry whose face has the row's cell
+    // as neighbour stores -S_f and -w_f, the sign bit of w marking it), and
+    // a reordered mesh keeps a scratch copy of the field in the solver's order.
     double *gface = nullptr;                              // [4F], or null
+    double *gerec = nullptr;                              // [4*n_entries], or null
+    double *gT = nullptr;                                 // [N], or null
     double *gband = nullptr;                              // [4*n_bands*N], or null
     double *gbface = nullptr;                             // [4B], or null
     bool orthogonal = true;     // created without LF_MESH_NON_ORTHOGONAL
@@ -149,4 +155,6 @@ void launch_grad_face_geometry(int32_t f0, int32_t cnt, int32_t N, BandOffsets b
                                const int32_t *neighbour, const double *C, const double *S, const double *Cf,
                                double *gface, double *gband, hipStream_t s);
 void launch_grad_bface_geometry(int32_t nb, const double *bS, double *gbface, hipStream_t s);
+// the per-entry records gerec from the face records (after every chunk of them)
+void launch_grad_entry_geometry(const lf_mesh *m, hipStream_t s);
 }  // namespace lf

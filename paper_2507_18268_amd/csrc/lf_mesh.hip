@@ -323,12 +323,15 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, i
         band_mag = cv.take<double>(static_cast<size_t>(K) * N);
         band_delta = cv.take<double>(static_cast<size_t>(K) * N);
     }
-    double *gface = nullptr, *gband = nullptr, *gbface = nullptr;
+    double *gface = nullptr, *gband = nullptr, *gbface = nullptr, *gerec = nullptr, *gT = nullptr;
     if (grad) {
-        if (K > 0)
+        if (K > 0) {
             gband = cv.take<double>(4 * static_cast<size_t>(K) * N);
-        else
+        } else {
             gface = cv.take<double>(4 * static_cast<size_t>(F));
+            gerec = cv.take<double>(4 * static_cast<size_t>(E));
+            if (reorder) gT = cv.take<double>(N);
+        }
         gbface = cv.take<double>(4 * static_cast<size_t>(B));
     }
     size_t tiles = (n1 + kScanTile - 1) / kScanTile + 1;
@@ -342,7 +345,7 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, i
     sc.Cf = grad ? cv.take<double>(3 * static_cast<size_t>(std::min<int64_t>(std::max(F, 1), kGeomChunk)))
                  : nullptr;
     if (m) {
-        m->gface = gface; m->gband = gband; m->gbface = gbface;
+        m->gface = gface; m->gband = gband; m->gbface = gbface; m->gerec = gerec; m->gT = gT;
         m->owner = owner; m->neighbour = neighbour; m->owner_start = owner_start;
         m->losort = losort; m->losort_start = losort_start; m->bface_start = bface_start;
         m->bface_list = bface_list; m->bface_cell = bface_cell; m->bface_patch = bface_patch;
@@ -738,6 +741,7 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
         hipLaunchKernelGGL(k_bface_geometry, dim3(blocks_for(B)), dim3(kBlock), 0, s, B, m->bface_cell, sc.C,
                            sc.bS, sc.bC, m->bmag_sf, m->bdelta);
     if (grad && B > 0) launch_grad_bface_geometry(B, sc.bS, m->gbface, s);
+    if (m->gerec) launch_grad_entry_geometry(m, s);
     LF_HIPM(hipGetLastError());
     LF_HIPM(hipStreamSynchronize(s));
 #undef LF_HIPM

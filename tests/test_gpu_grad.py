@@ -157,3 +157,17 @@ def test_grad_full_size_skewed_256(L, oracle):
     og, obg = oracle.gauss_grad(mesh, T, Tb, snb)
     assert np.array_equal(g, og), float(np.max(np.abs(g - og)))
     assert np.array_equal(bg, obg), float(np.max(np.abs(bg - obg)))
+
+
+def test_grad_full_size_permuted_192_skewed(L, oracle):
+    """The row path at full size: the randomly numbered 192^3 box (kept by the
+    library in Morton cell order), skewed; every output bit for bit."""
+    mesh = synth.affine(synth.build_config("permuted_192").mesh, synth.SKEW)
+    m = L.Mesh(mesh, gradient=True, non_orthogonal=True)
+    assert m.n_bands == 0 and m.cell_order()[0] == 1
+    T, Tb, snb = _inputs(mesh, 81)
+    g, bg = _gpu_grad(L, m, T, Tb, snb)
+    m.close()
+    og, obg = oracle.gauss_grad(mesh, T, Tb, snb)
+    assert np.array_equal(g, og), float(np.max(np.abs(g - og)))
+    assert np.array_equal(bg, obg), float(np.max(np.abs(bg - obg)))
