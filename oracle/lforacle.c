@@ -117,6 +117,8 @@ int lfo_bface_geometry(int32_t n_bfaces, const int32_t *bface_cell, const double
 /*   b: internalCoeff = -(DT|S_b|) delta_b, boundaryCoeff = -(DT|S_b|)       */
 /*   (delta_b T_b); zeroGradient contributes nothing.                        */
 /*  ddt (READING: implicit Euler): diag (1/dt) V, source ((1/dt) T_old) V.  */
+/*  On a mesh with non-orthogonal faces the laplacian also has an explicit   */
+/*  source lap_src (lfo_nonorth_source), which TEqn subtracts; NULL = none. */
 /*  TEqn = ddt - laplacian, then the solve adds the boundary internal        */
 /*  coefficients to diag and the boundary coefficients to source.            */
 /* ------------------------------------------------------------------------ */
@@ -125,7 +127,7 @@ int lfo_assemble(int32_t n_cells, int32_t n_faces, const int32_t *owner,
                  const double *delta, int32_t n_patches, const int32_t *patch_start,
                  const int32_t *patch_type, const double *patch_value,
                  const int32_t *bface_cell, const double *bmag_sf, const double *bdelta,
-                 double DT, double dt, const double *T_old,
+                 double DT, double dt, const double *T_old, const double *lap_src,
                  double *diag, double *upper, double *source,
                  double *diag_b, double *source_b, double *int_coeff, double *bou_coeff)
 {
@@ -152,6 +154,8 @@ int lfo_assemble(int32_t n_cells, int32_t n_faces, const int32_t *owner,
         double ddt_diag = rdt * cell_volume[c];
         diag[c] = ddt_diag - lap_diag[c];
         source[c] = (rdt * T_old[c]) * cell_volume[c];
+        if (lap_src) /* the laplacian's explicit non-orthogonal source, subtracted */
+            source[c] = source[c] - lap_src[c];
     }
     free(lap_diag);
 
@@ -406,7 +410,7 @@ int lfo_run(int32_t n_cells, int32_t n_faces, const int32_t *owner, const int32_
         double t0 = now_s();
         rc = lfo_assemble(n_cells, n_faces, owner, neighbour, cell_volume, mag_sf, delta,
                           n_patches, patch_start, patch_type, patch_value, bface_cell, bmag_sf,
-                          bdelta, DT, dt, T, diag, upper, source, diag_b, source_b, ic, bc);
+                          bdelta, DT, dt, T, NULL, diag, upper, source, diag_b, source_b, ic, bc);
         if (rc != LFO_OK)
             goto done;
         double t1 = now_s();
@@ -531,5 +535,54 @@ int lfo_gauss_grad(int32_t n_cells, int32_t n_faces, const int32_t *owner,
         for (int k = 0; k < 3; ++k)
             bgrad[3 * (size_t)b + k] = g[k] + n[k] * d;
     }
+    return LFO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Explicit non-orthogonal correction of the Gauss linear corrected         */
+/* Laplacian (Section 5.1: the loop of non-orthogonal correctors around     */
+/* TEqn, whose explicit part is what the gradient of Section 5.2 feeds).     */
+/* READING (the scheme's standard form; the paper names it without          */
+/* stating it): the face's correction vector k_f = n_f - delta_f d_f        */
+/* (n_f = S_f/|S_f|, d_f = C_N - C_P, delta_f as for the implicit part),     */
+/* the face gradient interpolated linearly g_f = w_f (g_P - g_N) + g_N per   */
+/* component, the face flux (DT |S_f|) (k_f . g_f), its divergence          */
+/* div_c = (sum over owned faces - sum over neighbour faces) / V_c (no       */
+/* boundary face contributes: k_b = 0 on non-coupled patches), and the      */
+/* laplacian's source lap_src_c = 0 - V_c div_c.  With one pass of the      */
+/* corrector loop (no extra correctors) g is the gradient of T at assembly. */
+/* ------------------------------------------------------------------------ */
+int lfo_nonorth_source(int32_t n_cells, int32_t n_faces, const int32_t *owner,
+                       const int32_t *neighbour, const double *cell_volume,
+                       const double *cell_centre, const double *face_area, const double *mag_sf,
+                       const double *delta, const double *w, const double *grad, double DT,
+                       double *lap_src)
+{
+    double *div = (double *)malloc(sizeof(double) * (size_t)(n_cells > 0 ? n_cells : 1));
+    if (!div)
+        return LFO_ENOMEM;
+    for (int32_t c = 0; c < n_cells; ++c)
+        div[c] = 0.0;
+    for (int32_t f = 0; f < n_faces; ++f) {
+        const double *S = face_area + 3 * (size_t)f;
+        const double *P = cell_centre + 3 * (size_t)owner[f];
+        const double *N = cell_centre + 3 * (size_t)neighbour[f];
+        const double *gP = grad + 3 * (size_t)owner[f];
+        const double *gN = grad + 3 * (size_t)neighbour[f];
+        double k[3], gf[3];
+        for (int i = 0; i < 3; ++i) {
+            k[i] = S[i] / mag_sf[f] - delta[f] * (N[i] - P[i]);
+            gf[i] = w[f] * (gP[i] - gN[i]) + gN[i];
+        }
+        double corr = k[0] * gf[0] + k[1] * gf[1] + k[2] * gf[2];
+        double flux = (DT * mag_sf[f]) * corr;
+        div[owner[f]] += flux;
+        div[neighbour[f]] -= flux;
+    }
+    for (int32_t c = 0; c < n_cells; ++c) {
+        div[c] /= cell_volume[c];
+        lap_src[c] = 0.0 - cell_volume[c] * div[c];
+    }
+    free(div);
     return LFO_OK;
 }

@@ -84,8 +84,9 @@ def _patch_arrays(mesh, bcs):
     return _i32(mesh.patch_start), types, vals
 
 
-def assemble(mesh, bcs, DT, dt, T_old):
-    """Return dict with diag, upper, source, diag_b, source_b, int_coeff, bou_coeff."""
+def assemble(mesh, bcs, DT, dt, T_old, lap_src=None):
+    """Return dict with diag, upper, source, diag_b, source_b, int_coeff, bou_coeff.
+    lap_src: the laplacian's explicit non-orthogonal source (None = none)."""
     N, F, B = mesh.n_cells, mesh.n_faces, mesh.n_bfaces
     mag, dlt = face_geometry(mesh)
     bmag, bdlt = bface_geometry(mesh)
@@ -97,12 +98,13 @@ def assemble(mesh, bcs, DT, dt, T_old):
     own, nei, vol = _i32(mesh.owner), _i32(mesh.neighbour), _f64(mesh.cell_volume)
     bcell = _i32(mesh.bface_cell)
     T_old = _f64(T_old)
+    ls = None if lap_src is None else _f64(lap_src)
     rc = lib().lfo_assemble(
         C.c_int32(N), C.c_int32(F), _p(own, np.int32), _p(nei, np.int32), _p(vol, np.float64),
         _p(mag, np.float64), _p(dlt, np.float64), C.c_int32(mesh.n_patches), _p(ps, np.int32),
         _p(pt, np.int32), _p(pv, np.float64), _p(bcell, np.int32), _p(bmag, np.float64),
         _p(bdlt, np.float64), C.c_double(DT), C.c_double(dt), _p(T_old, np.float64),
-        _p(out["diag"], np.float64), _p(out["upper"], np.float64), _p(out["source"], np.float64),
+        None if ls is None else _p(ls, np.float64), _p(out["diag"], np.float64), _p(out["upper"], np.float64), _p(out["source"], np.float64),
         _p(out["diag_b"], np.float64), _p(out["source_b"], np.float64),
         _p(out["int_coeff"], np.float64), _p(out["bou_coeff"], np.float64))
     if rc != 0:
@@ -257,3 +259,46 @@ def gauss_grad(mesh, T, Tb, snb, w=None):
                          _p(bcell, np.int32), _p(ba, np.float64), _p(Tb, np.float64),
                          _p(snb, np.float64), _p(grad, np.float64), _p(bgrad, np.float64))
     return grad, bgrad
+
+
+def nonorth_source(mesh, DT, grad, w=None):
+    """The laplacian's explicit non-orthogonal source lap_src [N] from the cell
+    gradient grad [N,3] (TEqn subtracts it from its source)."""
+    N, F = mesh.n_cells, mesh.n_faces
+    if w is None:
+        w = interp_weights(mesh)
+    mag, dlt = face_geometry(mesh)
+    out = np.empty(N)
+    own, nei = _i32(mesh.owner), _i32(mesh.neighbour)
+    vol, cc, sf = _f64(mesh.cell_volume), _f64(mesh.cell_centre), _f64(mesh.face_area)
+    w, g = _f64(w), _f64(grad)
+    rc = lib().lfo_nonorth_source(C.c_int32(N), C.c_int32(F), _p(own, np.int32), _p(nei, np.int32),
+                                  _p(vol, np.float64), _p(cc, np.float64), _p(sf, np.float64),
+                                  _p(mag, np.float64), _p(dlt, np.float64), _p(w, np.float64),
+                                  _p(g, np.float64), C.c_double(DT), _p(out, np.float64))
+    if rc != 0:
+        raise ValueError(f"oracle nonorth_source failed: {rc}")
+    return out
+
+
+def step_source(mesh, bcs, DT, T):
+    """lap_src of a time step on a mesh with non-orthogonal faces: the
+    gradient of T with its boundary values, then the correction."""
+    Tb, snb = boundary_values(mesh, bcs, T)
+    g, _ = gauss_grad(mesh, T, Tb, snb)
+    return nonorth_source(mesh, DT, g)
+
+
+def run_nonorth(mesh, bcs, DT, dt, n_steps, T0, pc=PC_DIAGONAL, tol=1e-9, rel_tol=0.0,
+                max_iter=1000, min_iter=0):
+    """Time steps with the explicit non-orthogonal correction (one pass of the
+    corrector loop per step).  Returns (T_final, [stats], [T per step])."""
+    T = np.array(T0, dtype=np.float64, copy=True)
+    stats, snaps = [], []
+    for _ in range(n_steps):
+        A = assemble(mesh, bcs, DT, dt, T, lap_src=step_source(mesh, bcs, DT, T))
+        T, st = pcg(mesh, A["diag_b"], A["upper"], A["source_b"], T, pc=pc, tol=tol,
+                    rel_tol=rel_tol, max_iter=max_iter, min_iter=min_iter)
+        stats.append(st)
+        snaps.append(T.copy())
+    return T, stats, snaps

@@ -5,6 +5,8 @@ interpolation weights (linear exactness on graded cells), a wrong sign or a
 transposed owner/neighbour in the face loop (central differences), a dropped
 boundary term or volume division (boundary cells, linear exactness), a wrong
 sign or normalisation in the boundary correction (its normal component).
+For the Laplacian's non-orthogonal correction: a wrong correction vector,
+factor or sign fails the exact face flux of a linear field.
 """
 import numpy as np
 import pytest
@@ -146,3 +148,92 @@ def test_boundary_values_of_the_conditions(oracle):
                 assert abs(snb[b] - (val - Tc) / half[p // 2]) < 1e-9 * abs(val)
             else:
                 assert Tb[b] == Tc and snb[b] == 0.0
+
+
+# --------------------------------------------------------------------------
+# the Laplacian's explicit non-orthogonal correction
+# --------------------------------------------------------------------------
+def _laplacian_of(mesh, A, lap_src, T):
+    """Per cell: sum over its internal faces of lapU_f (T_other - T_c) minus
+    the explicit source (the discrete laplacian the corrected scheme applies;
+    lapU_f = -upper_f)."""
+    lapU = -A["upper"]
+    out = np.zeros(mesh.n_cells)
+    np.add.at(out, mesh.owner, lapU * (T[mesh.neighbour] - T[mesh.owner]))
+    np.add.at(out, mesh.neighbour, lapU * (T[mesh.owner] - T[mesh.neighbour]))
+    scale = np.zeros(mesh.n_cells)
+    np.add.at(scale, mesh.owner, np.abs(lapU * (T[mesh.neighbour] - T[mesh.owner])))
+    np.add.at(scale, mesh.neighbour, np.abs(lapU * (T[mesh.owner] - T[mesh.neighbour])))
+    return out - lap_src, scale
+
+
+@pytest.mark.parametrize("shape", [(2, 1, 1), (1, 2, 1), (1, 1, 2)])
+def test_corrected_face_flux_is_exact_for_linear_field(oracle, shape):
+    """Two skewed cells, one face: the implicit flux DT|S| delta (T_N - T_P)
+    plus the correction DT|S| k.g (n = delta d + k) is the exact flux DT S.g
+    of a linear field, which the implicit part alone misses on a skewed face.
+    With one face, lap_src of the owner is minus that face's correction."""
+    mesh = synth.affine(synth.box_mesh(*shape, lengths=(0.5, 0.7, 0.9)), synth.SKEW)
+    assert mesh.n_faces == 1
+    g = np.array([1.7, -2.3, 0.9])
+    T = 3.25 + mesh.cell_centre @ g
+    grad, _ = oracle.gauss_grad(mesh, T, 3.25 + mesh.bface_centre @ g, np.zeros(mesh.n_bfaces))
+    DT = 0.7
+    lap_src = oracle.nonorth_source(mesh, DT, grad)
+    A = oracle.assemble(mesh, synth.all_zero_gradient(), DT, 0.1, T, lap_src=lap_src)
+    implicit = -A["upper"][0] * (T[1] - T[0])
+    exact = DT * (mesh.face_area[0] @ g)
+    assert abs(implicit - lap_src[0] - exact) < 1e-12 * abs(exact)
+    assert abs(lap_src[0] + lap_src[1]) < 1e-15 * abs(exact)
+    assert abs(implicit - exact) > 1e-2 * abs(exact)
+
+
+@pytest.mark.parametrize("numbering", ["natural", "random"])
+def test_corrected_laplacian_of_linear_field_vanishes(oracle, numbering):
+    """With the correction the face flux is DT S_f.g for a linear field, so
+    every cell without boundary faces has zero net flux."""
+    mesh = _skewed((6, 5, 7), 3.0, numbering)
+    g = np.array([1.7, -2.3, 0.9])
+    T = 3.25 + mesh.cell_centre @ g
+    grad, _ = oracle.gauss_grad(mesh, T, 3.25 + mesh.bface_centre @ g, np.zeros(mesh.n_bfaces))
+    DT = 0.7
+    lap_src = oracle.nonorth_source(mesh, DT, grad)
+    A = oracle.assemble(mesh, synth.all_zero_gradient(), DT, 0.1, T, lap_src=lap_src)
+    inner = np.ones(mesh.n_cells, bool)
+    inner[mesh.bface_cell] = False
+    assert inner.sum() > 20
+    L, scale = _laplacian_of(mesh, A, lap_src, T)
+    assert np.max(np.abs(L[inner]) / scale[inner]) < 1e-12
+
+
+def test_correction_vanishes_on_orthogonal_box(oracle):
+    """k_f = n_f - delta_f d_f is exactly zero on an axis-aligned box."""
+    mesh = synth.box_mesh(5, 4, 6, z_ratio=4.0)
+    T = synth.initial_field(mesh.n_cells, 3)
+    lap_src = oracle.step_source(mesh, synth.fixed_x_bcs(), 0.5, T)
+    assert np.all(lap_src == 0.0)
+
+
+def test_correction_enters_the_source(oracle):
+    """TEqn's source is the ddt source minus the laplacian's explicit source."""
+    mesh = _skewed((4, 3, 5), 2.0)
+    T = synth.initial_field(mesh.n_cells, 4)
+    bcs = synth.fixed_x_bcs()
+    lap_src = oracle.step_source(mesh, bcs, 0.4, T)
+    A0 = oracle.assemble(mesh, bcs, 0.4, 0.05, T)
+    A1 = oracle.assemble(mesh, bcs, 0.4, 0.05, T, lap_src=lap_src)
+    assert np.array_equal(A1["source"], A0["source"] - lap_src)
+    assert np.array_equal(A1["diag"], A0["diag"]) and np.array_equal(A1["upper"], A0["upper"])
+    assert np.max(np.abs(lap_src)) > 0.0
+
+
+def test_corrected_steps_conserve_heat(oracle):
+    """All walls zeroGradient: internal faces cancel in the sum of the
+    explicit source, so sum V T is kept to the solver tolerance."""
+    mesh = _skewed((5, 4, 4), 2.0, "random")
+    T0 = synth.initial_field(mesh.n_cells, 8)
+    T, stats, _ = oracle.run_nonorth(mesh, synth.all_zero_gradient(), 0.05, 0.01, 3, T0,
+                                     tol=1e-13)
+    h0, h1 = (mesh.cell_volume * T0).sum(), (mesh.cell_volume * T).sum()
+    assert abs(h1 - h0) <= 1e-10 * h0
+    assert all(s["converged"] for s in stats)
