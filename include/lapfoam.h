@@ -90,10 +90,12 @@ typedef int32_t lf_status;
 
 #define LF_MESH_NON_ORTHOGONAL 1   /* lf_mesh_desc.flags: accept faces that are not
                                       orthogonal to the line joining their cell
-                                      centres (skewed cells).  Such a mesh serves
-                                      lf_grad; problems reject it (the Laplacian's
-                                      explicit non-orthogonal correction is not
-                                      implemented) */
+                                      centres (skewed cells).  Created with face
+                                      centres, such a mesh also holds the
+                                      Laplacian's correction vectors, and its
+                                      problems apply the explicit non-orthogonal
+                                      correction every step (see
+                                      lf_problem_create) */
 
 /* Mesh in OpenFOAM face addressing (host pointers). */
 typedef struct lf_mesh_desc {
@@ -243,8 +245,16 @@ lf_status lf_grad(const lf_mesh *mesh, const double *T, const double *Tb, const 
 /* ---- problem: mesh + boundary conditions + DT + dt + solver ------------- */
 size_t lf_problem_workspace_bytes(const lf_mesh *mesh, const lf_solver_opts *opts);
 /* bcs[n_patches]; DT >= 0 finite; dt > 0 finite.  LF_PC_DIC on a mesh without
- * the two-colour property returns LF_EINVAL, and so does a mesh created with
- * non-orthogonal faces (LF_MESH_NON_ORTHOGONAL).  T starts at 0: set it with
+ * the two-colour property returns LF_EINVAL.
+ * On a mesh created with LF_MESH_NON_ORTHOGONAL (which then needs face centres,
+ * else LF_EINVAL) the Laplacian is the Gauss linear corrected scheme in full
+ * (Section 5.1, one pass of the non-orthogonal corrector loop per step): before
+ * each assembly the gradient of T (as lf_grad, with T's boundary values) is
+ * interpolated to the faces, each face's correction flux
+ * (DT |S_f|) (k_f . g_f), k_f = S_f/|S_f| - delta_f (C_N - C_P), is summed per
+ * cell in the face loop's order (owned faces +, lower faces -), divided by V_c,
+ * and lap_src_c = 0 - V_c div_c is subtracted from TEqn's source.  Such problems
+ * are refused by lf_batch_launch. */  T starts at 0: set it with
  * lf_set_T before stepping. */
 lf_status lf_problem_create(const lf_mesh *mesh, const lf_patch_bc *bcs, double DT, double dt,
                             const lf_solver_opts *opts, void *dev_workspace,

@@ -82,9 +82,8 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
     if (!out) { set_error("out is NULL"); return LF_EINVAL; }
     *out = nullptr;
     if (!m) { set_error("mesh is NULL"); return LF_EINVAL; }
-    if (!m->orthogonal) {
-        set_error("the mesh was created with non-orthogonal faces: the Laplacian's non-orthogonal correction "
-                  "is not implemented");
+    if (!m->orthogonal && !m->gkband && !m->gkerec) {
+        set_error("a mesh with non-orthogonal faces needs face centres (the correction's gradient)");
         return LF_EINVAL;
     }
     LF_TRY(check_physics(m, bcs, DT, dt));
@@ -139,6 +138,7 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
     P->dt = dt;
     P->stream = static_cast<hipStream_t>(stream);
     P->banded = use_bands(m, opts);
+    P->nonorth = !m->orthogonal;
     P->sp.tol = opts.tol;
     P->sp.rel_tol = opts.rel_tol;
     P->sp.max_iter = opts.max_iter;

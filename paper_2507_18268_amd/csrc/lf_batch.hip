@@ -376,6 +376,10 @@ lf_status lf_batch_launch(lf_batch *b, int32_t n, lf_problem *const *problems, d
             return LF_EINVAL;
         }
         if (P->mesh->device != b->device) { set_error("problem %d lives on another device", i); return LF_EINVAL; }
+        if (P->nonorth) {
+            set_error("problem %d: the batched kernel has no non-orthogonal correction", i);
+            return LF_EINVAL;
+        }
         const lf_mesh *m = P->mesh;
         BatchTask &t = b->h_tasks[i];
         t.soff = m->soff; t.scol = m->scol; t.sface = m->sface; t.rlen = m->rlen;

@@ -22,7 +22,7 @@
 //
 // Face records: {S_x, S_y, S_z, w_f} per internal face and {S_x, S_y, S_z,
 // |S_b|} per boundary face, 32 bytes each, read as two 16-byte loads.
-#include "lf_internal.h"
+#include "lf_solver.h"
 
 namespace lf {
 
@@ -46,11 +46,17 @@ __device__ __forceinline__ void store_rec(double *__restrict__ r, int64_t i, dou
 // Interpolation weights (Section 5.2, the weights loop): with the projected
 // distances SfdOwn = |S_f.(C_f - C_P)| and SfdNei = |S_f.(C_N - C_f)|, the
 // owner's weight is w_f = SfdNei / (SfdOwn + SfdNei).
+//
+// On a non-orthogonal mesh (gkface or gkband given) also the record of the
+// Laplacian's correction: k_f = S_f/|S_f| - delta_f (C_N - C_P), with |S_f| and
+// delta_f as the implicit part uses them, and the same weight.
 __global__ void k_grad_face_geometry(int32_t f0, int32_t m, int32_t n, BandOffsets bo,
                                      const int32_t *__restrict__ owner, const int32_t *__restrict__ neighbour,
                                      const double *__restrict__ C, const double *__restrict__ S,
-                                     const double *__restrict__ Cf, double *__restrict__ gface,
-                                     double *__restrict__ gband) {
+                                     const double *__restrict__ Cf, const double *__restrict__ mag_sf,
+                                     const double *__restrict__ delta, double *__restrict__ gface,
+                                     double *__restrict__ gband, double *__restrict__ gkface,
+                                     double *__restrict__ gkband) {
     const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (j >= m) return;
     const int64_t f = f0 + j;
@@ -61,13 +67,25 @@ __global__ void k_grad_face_geometry(int32_t f0, int32_t m, int32_t n, BandOffse
     const double sfd_own = fabs(sx * (fx - P[0]) + sy * (fy - P[1]) + sz * (fz - P[2]));
     const double sfd_nei = fabs(sx * (Q[0] - fx) + sy * (Q[1] - fy) + sz * (Q[2] - fz));
     const double w = sfd_nei / (sfd_own + sfd_nei);
+    double kx = 0.0, ky = 0.0, kz = 0.0;
+    if (gkface || gkband) {
+        const double mg = mag_sf[f], dl = delta[f];
+        kx = sx / mg - dl * (Q[0] - P[0]);
+        ky = sy / mg - dl * (Q[1] - P[1]);
+        kz = sz / mg - dl * (Q[2] - P[2]);
+    }
     if (bo.k == 0) {
         store_rec(gface, f, sx, sy, sz, w);
+        if (gkface) store_rec(gkface, f, kx, ky, kz, w);
         return;
     }
     const int32_t o = owner[f], off = neighbour[f] - o;
-    for (int32_t k = 0; k < bo.k; ++k)
-        if (bo.d[k] == off) store_rec(gband, static_cast<int64_t>(k) * n + o, sx, sy, sz, w);
+    for (int32_t k = 0; k < bo.k; ++k) {
+        if (bo.d[k] == off) {
+            store_rec(gband, static_cast<int64_t>(k) * n + o, sx, sy, sz, w);
+            if (gkband) store_rec(gkband, static_cast<int64_t>(k) * n + o, kx, ky, kz, w);
+        }
+    }
 }
 
 __global__ void k_grad_bface_geometry(int32_t nb, const double *__restrict__ S, double *__restrict__ gbface) {
@@ -79,9 +97,10 @@ __global__ void k_grad_bface_geometry(int32_t nb, const double *__restrict__ S, 
 
 void launch_grad_face_geometry(int32_t f0, int32_t cnt, int32_t N, BandOffsets bo, const int32_t *owner,
                                const int32_t *neighbour, const double *C, const double *S, const double *Cf,
-                               double *gface, double *gband, hipStream_t s) {
+                               const double *mag_sf, const double *delta, double *gface, double *gband,
+                               double *gkface, double *gkband, hipStream_t s) {
     hipLaunchKernelGGL(k_grad_face_geometry, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, s, f0, cnt, N,
-                       bo, owner, neighbour, C, S, Cf, gface, gband);
+                       bo, owner, neighbour, C, S, Cf, mag_sf, delta, gface, gband, gkface, gkband);
 }
 
 void launch_grad_bface_geometry(int32_t nb, const double *bS, double *gbface, hipStream_t s) {
@@ -114,8 +133,12 @@ __global__ void k_grad_entry_geometry(int32_t n, const int32_t *__restrict__ sof
 }
 
 void launch_grad_entry_geometry(const lf_mesh *m, hipStream_t s) {
-    hipLaunchKernelGGL(k_grad_entry_geometry, dim3((m->N + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m->N, m->soff,
-                       m->sface, m->rlen, m->iperm, m->neighbour, m->gface, m->gerec);
+    const dim3 grid((m->N + kBlock - 1) / kBlock), block(kBlock);
+    hipLaunchKernelGGL(k_grad_entry_geometry, grid, block, 0, s, m->N, m->soff, m->sface, m->rlen, m->iperm,
+                       m->neighbour, m->gface, m->gerec);
+    if (m->gkerec)
+        hipLaunchKernelGGL(k_grad_entry_geometry, grid, block, 0, s, m->N, m->soff, m->sface, m->rlen, m->iperm,
+                           m->neighbour, m->gkface, m->gkerec);
 }
 
 // the field in the solver's row order: Ts[r] = T[iperm[r]]
@@ -138,6 +161,7 @@ k_grad_rows(int32_t n, const double *__restrict__ Ts, const double *__restrict__
             const int32_t *__restrict__ rbface_list, const double *__restrict__ gbface,
             const double *__restrict__ V, const int32_t *__restrict__ iperm, double *__restrict__ grad,
             double *__restrict__ bgrad) {
+    // iperm null: the gradient stays in the solver's order (or the orders agree)
     const int64_t r = static_cast<int64_t>(blockIdx.x) * kGradBlock + threadIdx.x;
     if (r >= n) return;
     const int64_t idx0 = soff[r / kSlice] + r % kSlice;
@@ -310,6 +334,161 @@ static int64_t grad_walk_groups(int64_t n, int64_t D, int R) {
     return (threads + kGradBlock - 1) / kGradBlock;
 }
 
+static BandOffsets mesh_bands(const lf_mesh *m) {
+    return BandOffsets{m->n_bands, {m->band_d[0], m->band_d[1], m->band_d[2], m->band_d[3]}};
+}
+
+// the band path's launch (1 <= n_bands <= 4, checked by the callers)
+static void launch_grad_band(const lf_mesh *m, const double *T, const double *Tb, const double *snb, double *grad,
+                             double *bgrad, hipStream_t s) {
+    const BandOffsets bo = mesh_bands(m);
+    const int K = bo.k;
+    const int64_t D = bo.d[K - 1];
+    const int R = grad_walk_rows(m->N, D);
+    const dim3 grid(static_cast<unsigned>(grad_walk_groups(m->N, D, R))), block(kGradBlock);
+#define LF_GRAD_BAND(KK, RR)                                                                         \
+    if (K == KK && R == RR)                                                                          \
+        hipLaunchKernelGGL((k_grad_band<KK, RR>), grid, block, 0, s, m->N, bo, T, Tb, snb, m->gband,  \
+                           m->bface_start, m->bface_list, m->gbface, m->V, grad, bgrad);
+#define LF_GRAD_BAND_R(KK) LF_GRAD_BAND(KK, 1) LF_GRAD_BAND(KK, 2)
+    LF_GRAD_BAND_R(1)
+    LF_GRAD_BAND_R(2)
+    LF_GRAD_BAND_R(3)
+    LF_GRAD_BAND_R(4)
+#undef LF_GRAD_BAND_R
+#undef LF_GRAD_BAND
+}
+
+// ---------------------------------------------------------------------------
+// The Laplacian's explicit non-orthogonal correction (Gauss linear corrected
+// scheme; the corrector loop around TEqn of Section 5.1 runs it once per step):
+// face flux (DT |S_f|) (k_f . g_f) with g_f = w_f (g_P - g_N) + g_N, its
+// divergence div_c = (owned faces' fluxes - lower faces' fluxes) / V_c summed
+// in the face loop's order, and the laplacian's source 0 - V_c div_c, which the
+// assembly subtracts from TEqn's source.  No boundary face contributes
+// (k_b = 0 on non-coupled patches).
+// ---------------------------------------------------------------------------
+
+// T on the boundary faces: the fixed value, or the face cell's value
+__global__ void k_nonorth_bvalues(int32_t nb, const int32_t *__restrict__ rbface_cell,
+                                  const int32_t *__restrict__ bface_patch, const int32_t *__restrict__ patch_type,
+                                  const double *__restrict__ patch_value, const double *__restrict__ T,
+                                  double *__restrict__ Tb) {
+    const int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const int32_t pt = bface_patch[b];
+    Tb[b] = patch_type[pt] == LF_BC_FIXED_VALUE ? patch_value[pt] : T[rbface_cell[b]];
+}
+
+// band-form meshes: a slot holds a face when its |S_f| > 0
+template <int K>
+__global__ void __launch_bounds__(kGradBlock)
+k_nonorth_band(int32_t n, BandOffsets bo, double DT, const double *__restrict__ g, const double *__restrict__ gkband,
+               const double *__restrict__ band_mag_sf, const double *__restrict__ V, double *__restrict__ lap_src) {
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * kGradBlock + threadIdx.x;
+    if (c >= n) return;
+    const double gx = g[3 * c], gy = g[3 * c + 1], gz = g[3 * c + 2];
+    const double v = V[c];
+    double div = 0.0;
+#pragma unroll
+    for (int k = K - 1; k >= 0; --k) {          // lower faces (owner c - d_k): flux subtracted
+        const int64_t cl = c - bo.d[k];
+        if (cl < 0) continue;
+        const int64_t slot = static_cast<int64_t>(k) * n + cl;
+        const double mg = band_mag_sf[slot];
+        if (mg > 0.0) {
+            const Rec q = load_rec(gkband, slot);
+            const double fx = q.w * (g[3 * cl] - gx) + gx;
+            const double fy = q.w * (g[3 * cl + 1] - gy) + gy;
+            const double fz = q.w * (g[3 * cl + 2] - gz) + gz;
+            const double corr = q.x * fx + q.y * fy + q.z * fz;
+            div -= (DT * mg) * corr;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {               // owned faces (neighbour c + d_k): flux added
+        const int64_t cu = c + bo.d[k];
+        if (cu >= n) continue;
+        const int64_t slot = static_cast<int64_t>(k) * n + c;
+        const double mg = band_mag_sf[slot];
+        if (mg > 0.0) {
+            const Rec q = load_rec(gkband, slot);
+            const double nx = g[3 * cu], ny = g[3 * cu + 1], nz = g[3 * cu + 2];
+            const double fx = q.w * (gx - nx) + nx;
+            const double fy = q.w * (gy - ny) + ny;
+            const double fz = q.w * (gz - nz) + nz;
+            const double corr = q.x * fx + q.y * fy + q.z * fz;
+            div += (DT * mg) * corr;
+        }
+    }
+    div /= v;
+    lap_src[c] = 0.0 - v * div;
+}
+
+// row layout (solver order): lower entries hold -k_f and -w_f, so their
+// (negated) flux is added; the weight's sign bit picks the interpolation side
+__global__ void __launch_bounds__(kGradBlock)
+k_nonorth_rows(int32_t n, double DT, const double *__restrict__ g, const int32_t *__restrict__ soff,
+               const int32_t *__restrict__ scol, const uint8_t *__restrict__ rlen, const double *__restrict__ gkerec,
+               const double *__restrict__ emag_sf, const double *__restrict__ V, double *__restrict__ lap_src) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * kGradBlock + threadIdx.x;
+    if (r >= n) return;
+    const int64_t idx0 = soff[r / kSlice] + r % kSlice;
+    const int32_t len = rlen[r];
+    const double gx = g[3 * r], gy = g[3 * r + 1], gz = g[3 * r + 2];
+    const double v = V[r];
+    double div = 0.0;
+    for (int32_t j = 0; j < len; ++j) {
+        const int64_t idx = idx0 + static_cast<int64_t>(kSlice) * j;
+        const Rec q = load_rec(gkerec, idx);
+        const int64_t o = scol[idx];
+        const double mg = emag_sf[idx];
+        const double ox = g[3 * o], oy = g[3 * o + 1], oz = g[3 * o + 2];
+        const double w = fabs(q.w);
+        double fx, fy, fz;
+        if (signbit(q.w)) {                     // lower face: g_f = w (g_o - g_r) + g_r
+            fx = w * (ox - gx) + gx;
+            fy = w * (oy - gy) + gy;
+            fz = w * (oz - gz) + gz;
+        } else {                                // owned face: g_f = w (g_r - g_o) + g_o
+            fx = w * (gx - ox) + ox;
+            fy = w * (gy - oy) + oy;
+            fz = w * (gz - oz) + oz;
+        }
+        const double corr = q.x * fx + q.y * fy + q.z * fz;
+        div += (DT * mg) * corr;
+    }
+    div /= v;
+    lap_src[r] = 0.0 - v * div;
+}
+
+void launch_nonorth_source(lf_problem *P, hipStream_t s) {
+    const lf_mesh *m = P->mesh;
+    const dim3 block(kGradBlock), grid((m->N + kGradBlock - 1) / kGradBlock);
+    if (m->B > 0)
+        hipLaunchKernelGGL(k_nonorth_bvalues, dim3((m->B + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m->B,
+                           m->rbface_cell, m->bface_patch, P->patch_type, P->patch_value, P->T, P->Tb);
+    if (m->gkband) {
+        launch_grad_band(m, P->T, P->Tb, nullptr, P->grad3, nullptr, s);
+        const BandOffsets bo = mesh_bands(m);
+#define LF_NONORTH_BAND(KK)                                                                                \
+        if (bo.k == KK)                                                                                    \
+            hipLaunchKernelGGL(k_nonorth_band<KK>, grid, block, 0, s, m->N, bo, P->DT, P->grad3, m->gkband, \
+                               m->band_mag_sf, m->V, P->lap_src);
+        LF_NONORTH_BAND(1)
+        LF_NONORTH_BAND(2)
+        LF_NONORTH_BAND(3)
+        LF_NONORTH_BAND(4)
+#undef LF_NONORTH_BAND
+    } else {
+        // the gradient in the solver's order (T is kept in it): no copy, no scatter
+        hipLaunchKernelGGL(k_grad_rows, grid, block, 0, s, m->N, P->T, P->Tb, nullptr, m->soff, m->scol, m->rlen,
+                           m->gerec, m->rbface_start, m->rbface_list, m->gbface, m->V, nullptr, P->grad3, nullptr);
+        hipLaunchKernelGGL(k_nonorth_rows, grid, block, 0, s, m->N, P->DT, P->grad3, m->soff, m->scol, m->rlen,
+                           m->gkerec, m->emag_sf, m->V, P->lap_src);
+    }
+}
+
 }  // namespace lf
 
 using namespace lf;
@@ -338,23 +517,8 @@ extern "C" lf_status lf_grad(const lf_mesh *m, const double *T, const double *Tb
         LF_HIP(hipGetLastError());
         return LF_OK;
     }
-    const int K = m->n_bands;
-    if (K < 1 || K > kMaxBands) { set_error("bad band count %d", K); return LF_EINVAL; }
-    BandOffsets bo{K, {m->band_d[0], m->band_d[1], m->band_d[2], m->band_d[3]}};
-    const int64_t D = bo.d[K - 1];
-    const int R = grad_walk_rows(m->N, D);
-    const dim3 grid(static_cast<unsigned>(grad_walk_groups(m->N, D, R)));
-#define LF_GRAD_BAND(KK, RR)                                                                               \
-    if (K == KK && R == RR)                                                                                \
-        hipLaunchKernelGGL((k_grad_band<KK, RR>), grid, block, 0, m->stream, m->N, bo, T, Tb, snb, m->gband, \
-                           m->bface_start, m->bface_list, m->gbface, m->V, grad, bgrad);
-#define LF_GRAD_BAND_R(KK) LF_GRAD_BAND(KK, 1) LF_GRAD_BAND(KK, 2)
-    LF_GRAD_BAND_R(1)
-    LF_GRAD_BAND_R(2)
-    LF_GRAD_BAND_R(3)
-    LF_GRAD_BAND_R(4)
-#undef LF_GRAD_BAND_R
-#undef LF_GRAD_BAND
+    if (m->n_bands < 1 || m->n_bands > kMaxBands) { set_error("bad band count %d", m->n_bands); return LF_EINVAL; }
+    launch_grad_band(m, T, Tb, snb, grad, bgrad, m->stream);
     LF_HIP(hipGetLastError());
     return LF_OK;
 }

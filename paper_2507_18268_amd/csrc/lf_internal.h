@@ -139,6 +139,12 @@ struct lf_mesh {
     double *gT = nullptr;                                 // [N], or null
     double *gband = nullptr;                              // [4*n_bands*N], or null
     double *gbface = nullptr;                             // [4B], or null
+    // Non-orthogonal meshes (LF_MESH_NON_ORTHOGONAL with face centres): the
+    // Laplacian's correction records {k_x, k_y, k_z, w_f}, k_f = S_f/|S_f| -
+    // delta_f (C_N - C_P), laid out like the gradient's (by band slot, or by
+    // face and per row entry, negated for an entry whose row is the face's
+    // neighbour)
+    double *gkface = nullptr, *gkerec = nullptr, *gkband = nullptr;
     bool orthogonal = true;     // created without LF_MESH_NON_ORTHOGONAL
     size_t ws_bytes = 0;
 };
@@ -153,7 +159,8 @@ namespace lf {
 // records from S_b[3B]
 void launch_grad_face_geometry(int32_t f0, int32_t cnt, int32_t N, BandOffsets bo, const int32_t *owner,
                                const int32_t *neighbour, const double *C, const double *S, const double *Cf,
-                               double *gface, double *gband, hipStream_t s);
+                               const double *mag_sf, const double *delta, double *gface, double *gband,
+                               double *gkface, double *gkband, hipStream_t s);
 void launch_grad_bface_geometry(int32_t nb, const double *bS, double *gbface, hipStream_t s);
 // the per-entry records gerec from the face records (after every chunk of them)
 void launch_grad_entry_geometry(const lf_mesh *m, hipStream_t s);

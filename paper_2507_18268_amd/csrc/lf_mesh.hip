@@ -284,7 +284,7 @@ struct MeshScratch {
 };
 
 static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, int32_t K, bool reorder,
-                       bool grad, lf_mesh *m, MeshScratch *s) {
+                       bool grad, bool skew, lf_mesh *m, MeshScratch *s) {
     size_t n1 = static_cast<size_t>(N) + 1;
     const int32_t ns = (N + kSlice - 1) / kSlice;
     auto *owner = cv.take<int32_t>(F);
@@ -324,13 +324,19 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, i
         band_delta = cv.take<double>(static_cast<size_t>(K) * N);
     }
     double *gface = nullptr, *gband = nullptr, *gbface = nullptr, *gerec = nullptr, *gT = nullptr;
+    double *gkface = nullptr, *gkerec = nullptr, *gkband = nullptr;
     if (grad) {
         if (K > 0) {
             gband = cv.take<double>(4 * static_cast<size_t>(K) * N);
+            if (skew) gkband = cv.take<double>(4 * static_cast<size_t>(K) * N);
         } else {
             gface = cv.take<double>(4 * static_cast<size_t>(F));
             gerec = cv.take<double>(4 * static_cast<size_t>(E));
             if (reorder) gT = cv.take<double>(N);
+            if (skew) {
+                gkface = cv.take<double>(4 * static_cast<size_t>(F));
+                gkerec = cv.take<double>(4 * static_cast<size_t>(E));
+            }
         }
         gbface = cv.take<double>(4 * static_cast<size_t>(B));
     }
@@ -346,6 +352,7 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, i
                  : nullptr;
     if (m) {
         m->gface = gface; m->gband = gband; m->gbface = gbface; m->gerec = gerec; m->gT = gT;
+        m->gkface = gkface; m->gkerec = gkerec; m->gkband = gkband;
         m->owner = owner; m->neighbour = neighbour; m->owner_start = owner_start;
         m->losort = losort; m->losort_start = losort_start; m->bface_start = bface_start;
         m->bface_list = bface_list; m->bface_cell = bface_cell; m->bface_patch = bface_patch;
@@ -603,7 +610,7 @@ size_t lf_mesh_workspace_bytes(const lf_mesh_desc *d) {
     if (plan_slices(d, nullptr, reorder, nullptr, &E) != LF_OK) return 0;
     Carver cv(nullptr);
     carve_mesh(cv, d->n_cells, d->n_faces, d->patch_start[d->n_patches], E, bo.k, reorder,
-               d->face_centre != nullptr, nullptr, nullptr);
+               d->face_centre != nullptr, (d->flags & LF_MESH_NON_ORTHOGONAL) != 0, nullptr, nullptr);
     return cv.bytes();
 }
 
@@ -623,8 +630,9 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
     int64_t E = 0;
     LF_TRY(plan_slices(d, &iperm_h, false, &soff_h, &E));
     const bool grad = d->face_centre != nullptr;
+    const bool skew = (d->flags & LF_MESH_NON_ORTHOGONAL) != 0;
     Carver dry(nullptr);
-    carve_mesh(dry, N, F, B, E, bo.k, reorder, grad, nullptr, nullptr);
+    carve_mesh(dry, N, F, B, E, bo.k, reorder, grad, skew, nullptr, nullptr);
     if (!ws || ws_bytes < dry.bytes() || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) {
         set_error("mesh workspace too small or misaligned: need %zu bytes, 256-aligned", dry.bytes());
         return LF_ENOMEM;
@@ -642,7 +650,7 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
     if (hipGetDevice(&m->device) != hipSuccess) { delete m; set_error("hipGetDevice failed"); return LF_EDEVICE; }
     Carver cv(ws);
     MeshScratch sc;
-    carve_mesh(cv, N, F, B, E, bo.k, reorder, grad, m, &sc);
+    carve_mesh(cv, N, F, B, E, bo.k, reorder, grad, skew, m, &sc);
     m->orthogonal = (d->flags & LF_MESH_NON_ORTHOGONAL) == 0;
     hipStream_t s = m->stream;
 
@@ -713,6 +721,8 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
     if (m->gband) {
         const int64_t slots = 4 * static_cast<int64_t>(bo.k) * N;
         hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(slots)), dim3(kBlock), 0, s, m->gband, slots, 0.0);
+        if (m->gkband)
+            hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(slots)), dim3(kBlock), 0, s, m->gkband, slots, 0.0);
     }
     for (int64_t f0 = 0; f0 < F; f0 += kGeomChunk) {
         int32_t cnt = static_cast<int32_t>(std::min<int64_t>(kGeomChunk, F - f0));
@@ -724,7 +734,7 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
             LF_HIPM(hipMemcpyAsync(sc.Cf, d->face_centre + 3 * f0, sizeof(double) * 3 * static_cast<size_t>(cnt),
                                    hipMemcpyHostToDevice, s));
             launch_grad_face_geometry(static_cast<int32_t>(f0), cnt, N, bo, m->owner, m->neighbour, sc.C, sc.S,
-                                      sc.Cf, m->gface, m->gband, s);
+                                      sc.Cf, m->mag_sf, m->delta, m->gface, m->gband, m->gkface, m->gkband, s);
         }
     }
     if (bo.k > 0) {

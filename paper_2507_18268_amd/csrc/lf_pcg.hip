@@ -37,7 +37,8 @@ k_assemble(SolverParams sp, double rdt, double DT, Lay L, const int32_t *__restr
            double *__restrict__ diagB, double *__restrict__ srcB, double *__restrict__ int_coeff,
            double *__restrict__ bou_coeff, int32_t diag_pc, double *__restrict__ r, double *__restrict__ rD,
            double *__restrict__ part, const PcgState *__restrict__ st, float *__restrict__ sig32,
-           float *__restrict__ r32, float *__restrict__ d32, double *__restrict__ p) {
+           float *__restrict__ r32, float *__restrict__ d32, double *__restrict__ p,
+           const double *__restrict__ lap_src) {
     const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const double x_avg = kSetup ? st->x_avg : 0.0;
@@ -47,7 +48,9 @@ k_assemble(SolverParams sp, double rdt, double DT, Lay L, const int32_t *__restr
         const double v = V[c];
         const double d = rdt * v - lap_diag;
         const double xc = T[c];
-        const double s = (rdt * xc) * v;
+        // TEqn = ddt - laplacian: the laplacian's explicit non-orthogonal
+        // source (null on orthogonal meshes) is subtracted from the ddt source
+        const double s = lap_src ? (rdt * xc) * v - lap_src[c] : (rdt * xc) * v;
         double db = d, sb = s;
         for (int32_t i = bface_start[c]; i < bface_start[c + 1]; ++i) {
             const int32_t b = bface_list[i];
@@ -562,7 +565,13 @@ void carve_problem(Carver &cv, const lf_mesh *m, const lf_solver_opts &o, lf_pro
     auto *tb = cv.take<double>(B);
     auto *part = cv.take<double>(static_cast<size_t>(kNumPart) * G);
     auto *state = cv.take<PcgState>(1);
+    double *grad3 = nullptr, *lap_src = nullptr;
+    if (!m->orthogonal) {
+        grad3 = cv.take<double>(3 * N);
+        lap_src = cv.take<double>(N);
+    }
     if (P) {
+        P->grad3 = grad3; P->lap_src = lap_src;
         P->patch_type = pt; P->patch_value = pv;
         P->T = vec[0]; P->r = vec[1]; P->p = vec[2]; P->q = vec[3]; P->w = vec[4]; P->rD = vec[5];
         P->p2 = vec[6]; P->diag = vec[7]; P->source = vec[8]; P->diagB = vec[9]; P->srcB = vec[10];
@@ -579,13 +588,14 @@ static void launch_assemble_t(lf_problem *P, hipStream_t s) {
     const lf_mesh *m = P->mesh;
     const double rdt = 1.0 / P->dt;
     const bool diag_pc = P->opts.precond == LF_PC_DIAGONAL;
+    if (P->nonorth) launch_nonorth_source(P, s);
     with_layout(P, [&](auto lay) {
         auto kern = k_assemble<decltype(lay), kFull, kSetup, kMixed>;
         LF_LAUNCH(P, LF_K_ASSEMBLE, s, kern, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, rdt, P->DT, lay,
                   m->rbface_start, m->rbface_list, m->bface_patch, m->bmag_sf, m->bdelta, P->patch_type,
                   P->patch_value, m->V, P->T, P->coef, P->upper, P->diag, P->source, P->diagB, P->srcB,
                   P->int_coeff, P->bou_coeff, diag_pc ? 1 : 0, P->r, P->rD, P->part, P->state, P->sig32,
-                  P->r32, P->d32, P->p);
+                  P->r32, P->d32, P->p, P->nonorth ? P->lap_src : nullptr);
     });
     if (kFull && P->banded && m->F > 0) {
         BandOffsets bo{};

@@ -88,6 +88,11 @@ struct lf_problem {
     double *coef = nullptr;                    // [n_entries] row layout or [n_bands N] bands
     double *int_coeff = nullptr, *bou_coeff = nullptr;
     double *Tb = nullptr;                      // [B] boundary-face values (output staging)
+    // non-orthogonal meshes: the gradient of T at assembly (solver order) and
+    // the Laplacian's explicit source built from it
+    bool nonorth = false;
+    double *grad3 = nullptr;                   // [3N]
+    double *lap_src = nullptr;                 // [N]
     double *part = nullptr;                    // [kNumPart][grid]
     lf::PcgState *state = nullptr;
     // mixed precision (FP32 inner solve)

@@ -71,6 +71,9 @@ lf_status launch_assemble(lf_problem *P, bool full, hipStream_t s);
 lf_status launch_assemble_setup(lf_problem *P, hipStream_t s);
 // precision form: FP32 coefficients of the scaled matrix, after the assembly
 void launch_mx_scale(lf_problem *P, hipStream_t s);
+// non-orthogonal meshes: boundary values and gradient of T, then P->lap_src
+// (lf_grad.hip); runs before the assembly of each step
+void launch_nonorth_source(lf_problem *P, hipStream_t s);
 // A solve is driven in two halves so that one host loop can drive several
 // problems on their own streams: *_start enqueues the set-up and the first
 // block of iterations, followed by an async copy of the solver state and
