@@ -254,8 +254,8 @@ size_t lf_problem_workspace_bytes(const lf_mesh *mesh, const lf_solver_opts *opt
  * (DT |S_f|) (k_f . g_f), k_f = S_f/|S_f| - delta_f (C_N - C_P), is summed per
  * cell in the face loop's order (owned faces +, lower faces -), divided by V_c,
  * and lap_src_c = 0 - V_c div_c is subtracted from TEqn's source.  Such problems
- * are refused by lf_batch_launch. */  T starts at 0: set it with
- * lf_set_T before stepping. */
+ * are refused by lf_batch_launch.  T starts at 0: set it with lf_set_T before
+ * stepping. */
 lf_status lf_problem_create(const lf_mesh *mesh, const lf_patch_bc *bcs, double DT, double dt,
                             const lf_solver_opts *opts, void *dev_workspace,
                             size_t workspace_bytes, void *stream, lf_problem **out);
