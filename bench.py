@@ -175,19 +175,23 @@ def run_mixed(L, torch, p, mesh, prob64, T0, args):
             "speedup_vs_fp64_time_to_tol": None}
 
 
-def run_config_leg(L, torch, name, steps, warmup=1):
+def run_config_leg(L, torch, name, steps, warmup=1, skew=False):
     """Another config of the workload family, timed like the main line: `steps`
-    time steps from T0 after `warmup` steps, wall clock around the whole steps."""
+    time steps from T0 after `warmup` steps, wall clock around the whole steps.
+    skew: the config's box mapped by synth.SKEW (non-orthogonal faces), so every
+    step also runs the Laplacian's explicit non-orthogonal correction."""
     import synth
     t = time.perf_counter()
     p = synth.build_config(name, steps=steps)
+    if skew:
+        p.mesh = synth.affine(p.mesh, synth.SKEW)
     N = p.mesh.n_cells
-    log(f"[bench] {name}: {N} cells, mesh generated in {time.perf_counter() - t:.1f} s")
+    log(f"[bench] {name}{' skewed' if skew else ''}: {N} cells, mesh generated in {time.perf_counter() - t:.1f} s")
     precond = L.LF_PC_DIC if p.precond == "dic" else L.LF_PC_DIAGONAL
     precision = L.LF_PREC_MIXED if p.precision == "mixed" else L.LF_PREC_FP64
     opts = L.make_opts(tol=synth.TOL, rel_tol=synth.REL_TOL, max_iter=synth.MAX_ITER,
                        precond=precond, precision=precision)
-    mesh = L.Mesh(p.mesh)
+    mesh = L.Mesh(p.mesh, gradient=skew, non_orthogonal=skew)
     prob = L.Problem(mesh, p.bcs, p.DT, p.dt, opts)
     T0 = torch.from_numpy(p.T0).cuda()
     prob.set_T(T0)
@@ -205,6 +209,8 @@ def run_config_leg(L, torch, name, steps, warmup=1):
            "ms_per_step": wall * 1e3 / steps, "iters_per_step_mean": iters / steps,
            "cell_iters_per_s": N * iters / wall, "us_per_iteration": wall * 1e6 / max(iters, 1),
            "all_converged": all(s["converged"] == 1 for s in stats)}
+    if skew:
+        out["mesh"] = "skewed (non-orthogonal correction every step)"
     prob.close()
     mesh.close()
     log(f"[bench] {name}: {out['ms_per_step']:.3f} ms/step, {out['iters_per_step_mean']:.1f} iterations")
@@ -358,6 +364,8 @@ def main():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--grad-only", action="store_true",
                     help="only the Gauss-gradient leg (for profiling it alone)")
+    ap.add_argument("--skewed-only", action="store_true",
+                    help="only the config's box skewed, --steps corrected time steps (for profiling)")
     ap.add_argument("--no-extra-configs", action="store_true")
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--serve-sweep", action="store_true", help="Poisson rates 0.25x..4x of saturated")
@@ -408,6 +416,9 @@ def main():
     log(f"[bench] {args.config}: {N} cells, {F} faces, mesh generated in {time.perf_counter() - t:.1f} s")
     if args.grad_only:
         print(json.dumps({"grad": run_grad(L, torch, p, GRAD_LABEL)}), flush=True)
+        return
+    if args.skewed_only:
+        print(json.dumps({"skewed": run_config_leg(L, torch, args.config, args.steps, skew=True)}), flush=True)
         return
     precond = L.LF_PC_DIC if p.precond == "dic" else L.LF_PC_DIAGONAL
     precision = L.LF_PREC_MIXED if p.precision == "mixed" else L.LF_PREC_FP64
@@ -505,6 +516,9 @@ def main():
         out["other_configs"] = {name: run_config_leg(L, torch, name, steps)
                                 for name, steps in (("plain_32", 20), ("permuted_192", 30),
                                                     ("graded_256_dic", 50))}
+        # the same 256^3 box skewed: the corrected Laplacian (gradient, correction
+        # fluxes and their divergence before each assembly)
+        out["other_configs"]["graded_256_skewed"] = run_config_leg(L, torch, "graded_256", 50, skew=True)
 
     if not args.no_grad and args.n is None:
         log("[bench] Gauss gradient ...")
