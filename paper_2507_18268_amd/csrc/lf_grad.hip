@@ -380,49 +380,82 @@ __global__ void k_nonorth_bvalues(int32_t nb, const int32_t *__restrict__ rbface
     Tb[b] = patch_type[pt] == LF_BC_FIXED_VALUE ? patch_value[pt] : T[rbface_cell[b]];
 }
 
-// band-form meshes: a slot holds a face when its |S_f| > 0
-template <int K>
+// band-form meshes: a slot holds a face when its |S_f| > 0.  Launched like
+// the gradient's band kernel: R cells per thread along the widest band, the
+// shared face's record, |S_f| and the lower cell's gradient carried in
+// registers, workgroups in die order.
+template <int K, int R>
 __global__ void __launch_bounds__(kGradBlock)
 k_nonorth_band(int32_t n, BandOffsets bo, double DT, const double *__restrict__ g, const double *__restrict__ gkband,
                const double *__restrict__ band_mag_sf, const double *__restrict__ V, double *__restrict__ lap_src) {
-    const int64_t c = static_cast<int64_t>(blockIdx.x) * kGradBlock + threadIdx.x;
+    const int64_t D = bo.d[K - 1];
+    const int64_t t = die_block(blockIdx.x, gridDim.x) * kGradBlock + threadIdx.x;
+    const int64_t chunk = t / D;
+    int64_t c = chunk * R * D + (t - chunk * D);
     if (c >= n) return;
-    const double gx = g[3 * c], gy = g[3 * c + 1], gz = g[3 * c + 2];
-    const double v = V[c];
-    double div = 0.0;
+    const int64_t top = static_cast<int64_t>(K - 1) * n;     // slots of the widest band
+    const Rec none{0.0, 0.0, 0.0, 0.0};
+    Rec carry = none;
+    double carry_mg = 0.0, carry_g[3] = {0.0, 0.0, 0.0};
+    if (c - D >= 0) {
+        carry = load_rec(gkband, top + c - D);
+        carry_mg = band_mag_sf[top + c - D];
+        for (int i = 0; i < 3; ++i) carry_g[i] = g[3 * (c - D) + i];
+    }
+    double gc[3] = {g[3 * c], g[3 * c + 1], g[3 * c + 2]};
 #pragma unroll
-    for (int k = K - 1; k >= 0; --k) {          // lower faces (owner c - d_k): flux subtracted
-        const int64_t cl = c - bo.d[k];
-        if (cl < 0) continue;
-        const int64_t slot = static_cast<int64_t>(k) * n + cl;
-        const double mg = band_mag_sf[slot];
-        if (mg > 0.0) {
-            const Rec q = load_rec(gkband, slot);
-            const double fx = q.w * (g[3 * cl] - gx) + gx;
-            const double fy = q.w * (g[3 * cl + 1] - gy) + gy;
-            const double fz = q.w * (g[3 * cl + 2] - gz) + gz;
-            const double corr = q.x * fx + q.y * fy + q.z * fz;
-            div -= (DT * mg) * corr;
+    for (int r = 0; r < R; ++r, c += D) {
+        if (c >= n) break;
+        const double v = V[c];
+        Rec lo[K], up[K];
+        double lmg[K], umg[K], glo[K][3], gup[K][3];
+        lo[K - 1] = carry;
+        lmg[K - 1] = carry_mg;
+        for (int i = 0; i < 3; ++i) glo[K - 1][i] = carry_g[i];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int64_t cl = c - bo.d[k], cu = c + bo.d[k];
+            if (k < K - 1) {
+                const bool in = cl >= 0;
+                lo[k] = in ? load_rec(gkband, static_cast<int64_t>(k) * n + cl) : none;
+                lmg[k] = in ? band_mag_sf[static_cast<int64_t>(k) * n + cl] : 0.0;
+                for (int i = 0; i < 3; ++i) glo[k][i] = in ? g[3 * cl + i] : 0.0;
+            }
+            const bool in = cu < n;
+            up[k] = in ? load_rec(gkband, static_cast<int64_t>(k) * n + c) : none;
+            umg[k] = in ? band_mag_sf[static_cast<int64_t>(k) * n + c] : 0.0;
+            for (int i = 0; i < 3; ++i) gup[k][i] = in ? g[3 * cu + i] : 0.0;
+        }
+        double div = 0.0;
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {      // lower faces (owner c - d_k): flux subtracted
+            if (lmg[k] > 0.0) {
+                const double fx = lo[k].w * (glo[k][0] - gc[0]) + gc[0];
+                const double fy = lo[k].w * (glo[k][1] - gc[1]) + gc[1];
+                const double fz = lo[k].w * (glo[k][2] - gc[2]) + gc[2];
+                const double corr = lo[k].x * fx + lo[k].y * fy + lo[k].z * fz;
+                div -= (DT * lmg[k]) * corr;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {           // owned faces (neighbour c + d_k): flux added
+            if (umg[k] > 0.0) {
+                const double fx = up[k].w * (gc[0] - gup[k][0]) + gup[k][0];
+                const double fy = up[k].w * (gc[1] - gup[k][1]) + gup[k][1];
+                const double fz = up[k].w * (gc[2] - gup[k][2]) + gup[k][2];
+                const double corr = up[k].x * fx + up[k].y * fy + up[k].z * fz;
+                div += (DT * umg[k]) * corr;
+            }
+        }
+        div /= v;
+        lap_src[c] = 0.0 - v * div;
+        carry = up[K - 1];
+        carry_mg = umg[K - 1];
+        for (int i = 0; i < 3; ++i) {
+            carry_g[i] = gc[i];
+            gc[i] = gup[K - 1][i];
         }
     }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {               // owned faces (neighbour c + d_k): flux added
-        const int64_t cu = c + bo.d[k];
-        if (cu >= n) continue;
-        const int64_t slot = static_cast<int64_t>(k) * n + c;
-        const double mg = band_mag_sf[slot];
-        if (mg > 0.0) {
-            const Rec q = load_rec(gkband, slot);
-            const double nx = g[3 * cu], ny = g[3 * cu + 1], nz = g[3 * cu + 2];
-            const double fx = q.w * (gx - nx) + nx;
-            const double fy = q.w * (gy - ny) + ny;
-            const double fz = q.w * (gz - nz) + nz;
-            const double corr = q.x * fx + q.y * fy + q.z * fz;
-            div += (DT * mg) * corr;
-        }
-    }
-    div /= v;
-    lap_src[c] = 0.0 - v * div;
 }
 
 // row layout (solver order): lower entries hold -k_f and -w_f, so their
@@ -471,14 +504,19 @@ void launch_nonorth_source(lf_problem *P, hipStream_t s) {
     if (m->gkband) {
         launch_grad_band(m, P->T, P->Tb, nullptr, P->grad3, nullptr, s);
         const BandOffsets bo = mesh_bands(m);
-#define LF_NONORTH_BAND(KK)                                                                                \
-        if (bo.k == KK)                                                                                    \
-            hipLaunchKernelGGL(k_nonorth_band<KK>, grid, block, 0, s, m->N, bo, P->DT, P->grad3, m->gkband, \
-                               m->band_mag_sf, m->V, P->lap_src);
-        LF_NONORTH_BAND(1)
-        LF_NONORTH_BAND(2)
-        LF_NONORTH_BAND(3)
-        LF_NONORTH_BAND(4)
+        const int64_t D = bo.d[bo.k - 1];
+        const int R = grad_walk_rows(m->N, D);
+        const dim3 wgrid(static_cast<unsigned>(grad_walk_groups(m->N, D, R)));
+#define LF_NONORTH_BAND(KK, RR)                                                                              \
+        if (bo.k == KK && R == RR)                                                                           \
+            hipLaunchKernelGGL((k_nonorth_band<KK, RR>), wgrid, block, 0, s, m->N, bo, P->DT, P->grad3,      \
+                               m->gkband, m->band_mag_sf, m->V, P->lap_src);
+#define LF_NONORTH_BAND_R(KK) LF_NONORTH_BAND(KK, 1) LF_NONORTH_BAND(KK, 2)
+        LF_NONORTH_BAND_R(1)
+        LF_NONORTH_BAND_R(2)
+        LF_NONORTH_BAND_R(3)
+        LF_NONORTH_BAND_R(4)
+#undef LF_NONORTH_BAND_R
 #undef LF_NONORTH_BAND
     } else {
         // the gradient in the solver's order (T is kept in it): no copy, no scatter
