@@ -217,6 +217,51 @@ def run_config_leg(L, torch, name, steps, warmup=1, skew=False):
     return out
 
 
+PAPER_SIDES = (100, 200, 300, 400)     # the four box meshes of the paper's evaluation
+PAPER_DT, PAPER_STEPS, PAPER_DIFFUSIVITY = 0.2, 500, 1e-4
+
+
+def run_paper_sweep(L, torch, sides=PAPER_SIDES, steps=PAPER_STEPS):
+    """The paper's evaluation shapes: uniform unit boxes of n^3 cells, 500 time
+    steps of 0.2 s (100 s simulated), PCG with the diagonal preconditioner, FP64.
+    The diffusivity is not given there: 1e-4 m^2/s.  Boundary conditions and
+    T0 as the other configs.  Assembly and solver time are the library's own
+    per-step event timings, summed; total is the wall clock of the steps."""
+    import synth
+    out = []
+    for n in sides:
+        t = time.perf_counter()
+        mesh_h = synth.box_mesh(n, n, n)
+        T0 = synth.initial_field(mesh_h.n_cells, 20250724)
+        gen = time.perf_counter() - t
+        opts = L.make_opts(tol=synth.TOL, rel_tol=synth.REL_TOL, max_iter=synth.MAX_ITER)
+        mesh = L.Mesh(mesh_h)
+        N, F = mesh_h.n_cells, mesh_h.n_faces
+        del mesh_h
+        prob = L.Problem(mesh, synth.fixed_x_bcs(), PAPER_DIFFUSIVITY, PAPER_DT, opts)
+        T0d = torch.from_numpy(T0).cuda()
+        prob.set_T(T0d)
+        prob.step(2)                      # warm-up (graph capture, first launches)
+        prob.set_T(T0d)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats, _ = prob.step(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        rec = {"side": n, "n_cells": N, "n_faces": F, "steps": steps, "dt": PAPER_DT,
+               "DT": PAPER_DIFFUSIVITY, "assembly_s": sum(x["assemble_ms"] for x in stats) / 1e3,
+               "solver_s": sum(x["solve_ms"] for x in stats) / 1e3, "total_s": wall,
+               "iters_per_step_mean": sum(x["n_iter"] for x in stats) / steps,
+               "all_converged": all(x["converged"] == 1 for x in stats), "mesh_generation_s": gen}
+        log(f"[bench] paper shape {n}^3: {wall:.2f} s for {steps} steps")
+        out.append(rec)
+        prob.close()
+        mesh.close()
+        del T0d
+        torch.cuda.empty_cache()
+    return out
+
+
 def grad_bytes(n_cells, n_faces, n_bfaces, n_bands=0, reordered=False):
     """Algorithmic bytes of one Gauss-gradient call.  Both paths: per cell T,
     V, the gradient (3 doubles) and the boundary-list start; per boundary face
@@ -364,6 +409,8 @@ def main():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--grad-only", action="store_true",
                     help="only the Gauss-gradient leg (for profiling it alone)")
+    ap.add_argument("--paper-sweep", action="store_true",
+                    help="the paper's four box sizes, 500 steps of 0.2 s each (about a minute)")
     ap.add_argument("--skewed-only", action="store_true",
                     help="only the config's box skewed, --steps corrected time steps (for profiling)")
     ap.add_argument("--no-extra-configs", action="store_true")
@@ -408,6 +455,9 @@ def main():
 
     if args.serve_only:
         print(json.dumps({"serving": run_serving(L, torch, args)}), flush=True)
+        return
+    if args.paper_sweep:
+        print(json.dumps({"paper_sweep": run_paper_sweep(L, torch)}), flush=True)
         return
 
     t = time.perf_counter()
