@@ -237,6 +237,9 @@ lf_status lf_mesh_get_addressing(const lf_mesh *mesh, int32_t *owner_start, int3
  * boundary-face order; grad[3N] and bgrad[3B] (xyz interleaved, same orders)
  * are device outputs.  bgrad may be NULL (then snGrad_b is not read).  The
  * work is ordered on the mesh's stream and the call returns without waiting.
+ * On a mesh kept in Morton order (lf_mesh_cell_order) T is first copied into
+ * that order in a scratch array of the mesh: calls on one mesh must stay on
+ * its stream (not concurrent from several threads).
  * LF_EINVAL: NULL mesh, T, grad, or Tb (B > 0), or snGrad_b with bgrad given;
  * a mesh created without face centres. */
 lf_status lf_grad(const lf_mesh *mesh, const double *T, const double *Tb, const double *snGrad_b,
