@@ -179,8 +179,8 @@ lf_status lf_default_opts(lf_solver_opts *opts);
  * Validation (LF_EMESH): every owner/neighbour/face cell index in [0, N);
  * owner < neighbour; faces strictly increasing in (owner, neighbour);
  * S.d > 0 for every face (d = C_N - C_P), and unless flags has
- * LF_MESH_NON_ORTHOGONAL every face orthogonal (|S x d| <= 1e-9 |S||d|: no
- * non-orthogonal correction is implemented); boundary faces outward
+ * LF_MESH_NON_ORTHOGONAL every face orthogonal (|S x d| <= 1e-9 |S||d|: such a
+ * mesh's problems skip the non-orthogonal correction); boundary faces outward
  * (S_b.(C_b - C_P) > 0); V > 0; unknown flags give LF_EINVAL.
  * With face_centre given, the device copy also holds the gradient's face
  * records (S_f and the interpolation weight w_f, 32 bytes per face) and
