@@ -149,6 +149,13 @@ typedef struct lf_solver_opts {
                                    across refinement passes (the true residual
                                    replaces the recurred one, the search direction
                                    is kept); 1 restarts it at every pass */
+    int32_t n_nonorth_corr;     /* extra passes of the non-orthogonal corrector loop
+                                   per time step, 0..100 (default 0): each pass
+                                   assembles TEqn again, its ddt source from T at
+                                   the start of the step and its correction from
+                                   the latest T, and solves from the latest T.
+                                   Used on meshes with non-orthogonal faces only
+                                   (elsewhere the correction is zero) */
 } lf_solver_opts;
 
 /* Per time step results. */

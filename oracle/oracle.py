@@ -290,15 +290,27 @@ def step_source(mesh, bcs, DT, T):
 
 
 def run_nonorth(mesh, bcs, DT, dt, n_steps, T0, pc=PC_DIAGONAL, tol=1e-9, rel_tol=0.0,
-                max_iter=1000, min_iter=0):
-    """Time steps with the explicit non-orthogonal correction (one pass of the
-    corrector loop per step).  Returns (T_final, [stats], [T per step])."""
+                max_iter=1000, min_iter=0, n_corr=0):
+    """Time steps with the explicit non-orthogonal correction: per step,
+    1 + n_corr passes of the corrector loop (Section 5.1), each assembling
+    TEqn with its ddt source from T at the start of the step and its
+    correction from the latest T, then solving from the latest T.  Returns
+    (T_final, [stats per step: iterations summed over the passes, the first
+    pass's initial and the last pass's final residual], [T per step])."""
     T = np.array(T0, dtype=np.float64, copy=True)
     stats, snaps = [], []
     for _ in range(n_steps):
-        A = assemble(mesh, bcs, DT, dt, T, lap_src=step_source(mesh, bcs, DT, T))
-        T, st = pcg(mesh, A["diag_b"], A["upper"], A["source_b"], T, pc=pc, tol=tol,
-                    rel_tol=rel_tol, max_iter=max_iter, min_iter=min_iter)
-        stats.append(st)
+        T_old = T.copy()
+        total = None
+        for _ in range(1 + n_corr):
+            A = assemble(mesh, bcs, DT, dt, T_old, lap_src=step_source(mesh, bcs, DT, T))
+            T, st = pcg(mesh, A["diag_b"], A["upper"], A["source_b"], T, pc=pc, tol=tol,
+                        rel_tol=rel_tol, max_iter=max_iter, min_iter=min_iter)
+            if total is None:
+                total = dict(st)
+            else:
+                total.update(final_residual=st["final_residual"], converged=st["converged"],
+                             singular=st["singular"], n_iter=total["n_iter"] + st["n_iter"])
+        stats.append(total)
         snaps.append(T.copy())
     return T, stats, snaps

@@ -21,6 +21,8 @@ struct StepDriver {
     int32_t n_steps = 0, step = 0;
     SolveCtx c;
     lf_solve_stats cur{};
+    int32_t pass = 0;                  // pass of the non-orthogonal corrector loop
+    lf_solve_stats acc{};              // the step's earlier passes
     bool active = false, nonfinite = false;
     std::vector<lf_solve_stats> own_stats;   // lf_step_begin's stats
 };
@@ -46,6 +48,7 @@ lf_status lf_default_opts(lf_solver_opts *o) {
     o->layout = LF_LAYOUT_AUTO;
     o->amul_walk = LF_WALK_AUTO;
     o->inner_restart = 0;
+    o->n_nonorth_corr = 0;
     return LF_OK;
 }
 
@@ -90,7 +93,8 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
     lf_solver_opts opts;
     if (o) opts = *o; else lf_default_opts(&opts);
     if (opts.max_iter < 0 || opts.min_iter < 0 || !std::isfinite(opts.tol) || !std::isfinite(opts.rel_tol) ||
-        !std::isfinite(opts.inner_tol) || opts.inner_tol < 0.0 || opts.inner_tol >= 1.0 || opts.max_outer < 0) {
+        !std::isfinite(opts.inner_tol) || opts.inner_tol < 0.0 || opts.inner_tol >= 1.0 || opts.max_outer < 0 ||
+        opts.n_nonorth_corr < 0 || opts.n_nonorth_corr > 100) {
         set_error("bad solver options");
         return LF_EINVAL;
     }
@@ -410,7 +414,11 @@ lf_status lf_profile_read(lf_problem *P, int32_t n, double *total_ms, int64_t *l
 // SolveCtx); lf_step drives one, lf_step_many several at once.
 
 
-static lf_status begin_step(StepDriver &d) {
+static int32_t corrector_passes(const lf_problem *P) { return P->nonorth ? P->opts.n_nonorth_corr : 0; }
+
+// one assembly + solve: the step's only pass, or one pass of its
+// non-orthogonal corrector loop
+static lf_status begin_pass(StepDriver &d) {
     lf_problem *P = d.P;
     hipStream_t s = P->stream;
     std::memset(&d.cur, 0, sizeof(d.cur));
@@ -420,6 +428,16 @@ static lf_status begin_step(StepDriver &d) {
     LF_HIP(hipEventRecord(P->ev[1], s));
     P->assembled = true;
     return P->opts.precision == LF_PREC_MIXED ? mixed_start(P, d.c) : fp64_start(P, d.c);
+}
+
+static lf_status begin_step(StepDriver &d) {
+    lf_problem *P = d.P;
+    d.pass = 0;
+    std::memset(&d.acc, 0, sizeof(d.acc));
+    // the corrector passes take their ddt source from T at the start of the step
+    if (corrector_passes(P) > 0)
+        LF_HIP(hipMemcpyAsync(P->T_old, P->T, sizeof(double) * P->mesh->N, hipMemcpyDeviceToDevice, P->stream));
+    return begin_pass(d);
 }
 
 // called once P->ev[2] has completed
@@ -435,6 +453,25 @@ static lf_status advance(StepDriver &d) {
     d.cur.assemble_ms = a_ms;
     d.cur.solve_ms = s_ms;
     P->last_iters = d.cur.n_iter;
+    if (!d.cur.nonfinite && d.pass < corrector_passes(P)) {
+        // the next pass of the corrector loop from the T just solved for
+        if (d.pass == 0) d.acc.initial_residual = d.cur.initial_residual;
+        d.acc.n_iter += d.cur.n_iter;
+        d.acc.n_outer += d.cur.n_outer;
+        d.acc.assemble_ms += d.cur.assemble_ms;
+        d.acc.solve_ms += d.cur.solve_ms;
+        ++d.pass;
+        return begin_pass(d);
+    }
+    if (d.pass > 0) {
+        // the step's stats: the first pass's initial residual, the last pass's
+        // final residual and flags, iterations and times summed over the passes
+        d.cur.initial_residual = d.acc.initial_residual;
+        d.cur.n_iter += d.acc.n_iter;
+        d.cur.n_outer += d.acc.n_outer;
+        d.cur.assemble_ms += d.acc.assemble_ms;
+        d.cur.solve_ms += d.acc.solve_ms;
+    }
     if (d.stats) d.stats[d.step] = d.cur;
     // T of this step into its snapshot, on the stream before the next step's work
     if (d.snap) LF_TRY(to_mesh_order(P, P->T, d.snap + static_cast<int64_t>(d.step) * P->mesh->N));

@@ -38,7 +38,7 @@ k_assemble(SolverParams sp, double rdt, double DT, Lay L, const int32_t *__restr
            double *__restrict__ bou_coeff, int32_t diag_pc, double *__restrict__ r, double *__restrict__ rD,
            double *__restrict__ part, const PcgState *__restrict__ st, float *__restrict__ sig32,
            float *__restrict__ r32, float *__restrict__ d32, double *__restrict__ p,
-           const double *__restrict__ lap_src) {
+           const double *__restrict__ lap_src, const double *__restrict__ T_old) {
     const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const double x_avg = kSetup ? st->x_avg : 0.0;
@@ -49,8 +49,10 @@ k_assemble(SolverParams sp, double rdt, double DT, Lay L, const int32_t *__restr
         const double d = rdt * v - lap_diag;
         const double xc = T[c];
         // TEqn = ddt - laplacian: the laplacian's explicit non-orthogonal
-        // source (null on orthogonal meshes) is subtracted from the ddt source
-        const double s = lap_src ? (rdt * xc) * v - lap_src[c] : (rdt * xc) * v;
+        // source (null on orthogonal meshes) is subtracted from the ddt source,
+        // which uses T at the start of the step (T_old; null: T itself)
+        const double xo = T_old ? T_old[c] : xc;
+        const double s = lap_src ? (rdt * xo) * v - lap_src[c] : (rdt * xo) * v;
         double db = d, sb = s;
         for (int32_t i = bface_start[c]; i < bface_start[c + 1]; ++i) {
             const int32_t b = bface_list[i];
@@ -565,13 +567,14 @@ void carve_problem(Carver &cv, const lf_mesh *m, const lf_solver_opts &o, lf_pro
     auto *tb = cv.take<double>(B);
     auto *part = cv.take<double>(static_cast<size_t>(kNumPart) * G);
     auto *state = cv.take<PcgState>(1);
-    double *grad3 = nullptr, *lap_src = nullptr;
+    double *grad3 = nullptr, *lap_src = nullptr, *T_old = nullptr;
     if (!m->orthogonal) {
         grad3 = cv.take<double>(3 * N);
         lap_src = cv.take<double>(N);
+        T_old = cv.take<double>(N);
     }
     if (P) {
-        P->grad3 = grad3; P->lap_src = lap_src;
+        P->grad3 = grad3; P->lap_src = lap_src; P->T_old = T_old;
         P->patch_type = pt; P->patch_value = pv;
         P->T = vec[0]; P->r = vec[1]; P->p = vec[2]; P->q = vec[3]; P->w = vec[4]; P->rD = vec[5];
         P->p2 = vec[6]; P->diag = vec[7]; P->source = vec[8]; P->diagB = vec[9]; P->srcB = vec[10];
@@ -595,7 +598,8 @@ static void launch_assemble_t(lf_problem *P, hipStream_t s) {
                   m->rbface_start, m->rbface_list, m->bface_patch, m->bmag_sf, m->bdelta, P->patch_type,
                   P->patch_value, m->V, P->T, P->coef, P->upper, P->diag, P->source, P->diagB, P->srcB,
                   P->int_coeff, P->bou_coeff, diag_pc ? 1 : 0, P->r, P->rD, P->part, P->state, P->sig32,
-                  P->r32, P->d32, P->p, P->nonorth ? P->lap_src : nullptr);
+                  P->r32, P->d32, P->p, P->nonorth ? P->lap_src : nullptr,
+                  kSetup && P->nonorth && P->opts.n_nonorth_corr > 0 ? P->T_old : nullptr);
     });
     if (kFull && P->banded && m->F > 0) {
         BandOffsets bo{};

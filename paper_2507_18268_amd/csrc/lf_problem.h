@@ -93,6 +93,7 @@ struct lf_problem {
     bool nonorth = false;
     double *grad3 = nullptr;                   // [3N]
     double *lap_src = nullptr;                 // [N]
+    double *T_old = nullptr;                   // [N] T at the start of the step (corrector passes)
     double *part = nullptr;                    // [kNumPart][grid]
     lf::PcgState *state = nullptr;
     // mixed precision (FP32 inner solve)

@@ -63,7 +63,8 @@ class lf_solver_opts(C.Structure):
                 ("min_iter", C.c_int32), ("precond", C.c_int32), ("precision", C.c_int32),
                 ("iters_per_check", C.c_int32), ("use_graph", C.c_int32),
                 ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("layout", C.c_int32),
-                ("amul_walk", C.c_int32), ("inner_restart", C.c_int32)]
+                ("amul_walk", C.c_int32), ("inner_restart", C.c_int32),
+                ("n_nonorth_corr", C.c_int32)]
 
 
 class lf_solve_stats(C.Structure):
@@ -467,12 +468,13 @@ class Mesh:
 
 def make_opts(tol=1e-9, rel_tol=0.0, max_iter=1000, min_iter=0, precond=LF_PC_DIAGONAL,
               precision=LF_PREC_FP64, iters_per_check=0, use_graph=1, inner_tol=0.0, max_outer=0,
-              layout=LF_LAYOUT_AUTO, amul_walk=LF_WALK_AUTO, inner_restart=0):
+              layout=LF_LAYOUT_AUTO, amul_walk=LF_WALK_AUTO, inner_restart=0, n_nonorth_corr=0):
     o = lf_default_opts()
     o.tol, o.rel_tol, o.max_iter, o.min_iter = tol, rel_tol, max_iter, min_iter
     o.precond, o.precision, o.iters_per_check, o.use_graph = precond, precision, iters_per_check, use_graph
     o.inner_tol, o.max_outer, o.layout, o.amul_walk = inner_tol, max_outer, layout, amul_walk
     o.inner_restart = inner_restart
+    o.n_nonorth_corr = n_nonorth_corr
     return o
 
 

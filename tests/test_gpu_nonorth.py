@@ -135,3 +135,48 @@ def test_nonorth_full_size_skewed_256(L, oracle):
                          rel_tol=synth.REL_TOL, max_iter=synth.MAX_ITER)
     assert max_rel(T, Tn) <= 1e-8
     assert abs(st[0]["n_iter"] - ost["n_iter"]) <= 1
+
+
+@pytest.mark.parametrize("name,mesh,pc", [MESHES[0], MESHES[1], MESHES[2]], ids=IDS[:3])
+def test_nonorth_corrector_passes(L, oracle, name, mesh, pc):
+    """Two extra passes of the corrector loop per step: the same passes as the
+    oracle's (ddt from T at the step's start, correction from the latest T)."""
+    m, P = _problem(L, mesh, pc, n_nonorth_corr=2)
+    T0 = synth.initial_field(mesh.n_cells, 12)
+    P.set_T(T0)
+    steps = 3
+    _, ostats, osnaps = oracle.run_nonorth(mesh, BCS, DT, dt, steps, T0, n_corr=2,
+                                           pc=oracle.PC_DIC if pc == "dic" else oracle.PC_DIAGONAL)
+    for s in range(steps):
+        st, _ = P.step(1)
+        T = P.get_T()
+        assert max_rel(T, osnaps[s]) <= 1e-8, (name, s, max_rel(T, osnaps[s]))
+        assert abs(st[0]["n_iter"] - ostats[s]["n_iter"]) <= 3, (name, s)
+    # the test hook still assembles from the current T (no stale start-of-step copy)
+    P.assemble()
+    g = P.matrix()
+    Tn = P.get_T()
+    o = oracle.assemble(mesh, BCS, DT, dt, Tn, lap_src=oracle.step_source(mesh, BCS, DT, Tn))
+    assert np.array_equal(g["source"], o["source"])
+    P.close()
+    m.close()
+
+
+def test_nonorth_corrector_passes_mixed(L, oracle):
+    mesh = synth.affine(synth.box_mesh(12, 10, 8, z_ratio=3.0), synth.SKEW)
+    m, P = _problem(L, mesh, "diagonal", precision=L.LF_PREC_MIXED, n_nonorth_corr=1)
+    T = synth.initial_field(mesh.n_cells, 13)
+    P.set_T(T)
+    for s in range(2):
+        P.step(1)
+        Tg = P.get_T()
+        To, _, _ = oracle.run_nonorth(mesh, BCS, DT, dt, 1, T, n_corr=1)
+        assert max_rel(Tg, To) <= 1e-8, (s, max_rel(Tg, To))
+        T = Tg
+    P.close()
+    m.close()
+
+
+def test_corrector_option_checked(L):
+    with pytest.raises(L.LapfoamError, match="LF_EINVAL"):
+        _problem(L, MESHES[0][1], "diagonal", n_nonorth_corr=-1)

@@ -237,3 +237,19 @@ def test_corrected_steps_conserve_heat(oracle):
     h0, h1 = (mesh.cell_volume * T0).sum(), (mesh.cell_volume * T).sum()
     assert abs(h1 - h0) <= 1e-10 * h0
     assert all(s["converged"] for s in stats)
+
+
+def test_corrector_passes_converge_to_the_corrected_fixed_point(oracle):
+    """More passes of the corrector loop solve the step's implicit-in-the-
+    correction system ever more closely: the change from pass n to n+1 shrinks,
+    and with no correction (an orthogonal box) extra passes change nothing."""
+    mesh = _skewed((6, 5, 4), 3.0)
+    T0 = synth.initial_field(mesh.n_cells, 9)
+    bcs, DT, dt = synth.fixed_x_bcs(), 0.05, 0.02
+    Ts = [oracle.run_nonorth(mesh, bcs, DT, dt, 1, T0, tol=1e-14, n_corr=k)[0] for k in range(4)]
+    d = [np.max(np.abs(Ts[k + 1] - Ts[k])) for k in range(3)]
+    assert d[0] > 0.0 and d[1] < 0.5 * d[0] and d[2] < 0.5 * d[1], d
+    box = synth.box_mesh(5, 4, 3)
+    T1 = oracle.run_nonorth(box, bcs, DT, dt, 1, T0[:box.n_cells], tol=1e-14)[0]
+    T3 = oracle.run_nonorth(box, bcs, DT, dt, 1, T0[:box.n_cells], tol=1e-14, n_corr=2)[0]
+    assert np.max(np.abs(T3 - T1)) <= 1e-9 * np.max(np.abs(T1))
