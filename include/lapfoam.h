@@ -297,6 +297,16 @@ lf_status lf_get_T(lf_problem *problem, double *T, int32_t on_device);
  * the solve does not use them).  on_device as for lf_get_T. */
 lf_status lf_get_boundary_T(lf_problem *problem, double *Tb, int32_t on_device);
 
+/* Gauss gradient of the problem's current T with its own boundary conditions
+ * (Section 5.2, calcGrad of the solution field): lf_grad with T_b the values
+ * of lf_get_boundary_T and snGrad_b = delta_b (T_b - T_P) on fixedValue patches,
+ * 0 on zeroGradient ones.  grad[3N] and bgrad[3B] (may be NULL) are device
+ * outputs, xyz interleaved, in the mesh's cell and boundary-face order, written
+ * on the problem's stream (the call does not wait).  LF_EINVAL: NULL problem or
+ * grad, or a mesh created without face centres; LF_ESTATE while an
+ * lf_step_begin run is in flight. */
+lf_status lf_problem_grad(lf_problem *problem, double *grad, double *bgrad);
+
 /* Advance n_steps time steps.  stats[n_steps] (host, may be NULL).
  * Per step: assemble TEqn from the current T, solve from x0 = T, T = x.
  * Non-convergence is reported in stats, not as an error.  A non-finite

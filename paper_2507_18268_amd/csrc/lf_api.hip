@@ -352,6 +352,13 @@ lf_status lf_get_boundary_T(lf_problem *P, double *Tb, int32_t on_device) {
     return LF_OK;
 }
 
+lf_status lf_problem_grad(lf_problem *P, double *grad, double *bgrad) {
+    clear_error();
+    if (!P || !grad) { set_error("NULL argument"); return LF_EINVAL; }
+    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
+    return launch_problem_grad(P, grad, bgrad);
+}
+
 lf_status lf_assemble(lf_problem *P) {
     clear_error();
     if (!P) { set_error("NULL problem"); return LF_EINVAL; }

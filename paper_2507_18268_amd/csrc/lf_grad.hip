@@ -527,6 +527,48 @@ void launch_nonorth_source(lf_problem *P, hipStream_t s) {
     }
 }
 
+// normal gradient of T on the boundary faces for the problem's conditions:
+// fixedValue delta_b (T_b - T_P), zeroGradient 0
+__global__ void k_bsngrad(int32_t nb, const int32_t *__restrict__ rbface_cell, const int32_t *__restrict__ bface_patch,
+                          const int32_t *__restrict__ patch_type, const double *__restrict__ patch_value,
+                          const double *__restrict__ bdelta, const double *__restrict__ T, double *__restrict__ snb) {
+    const int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const int32_t pt = bface_patch[b];
+    snb[b] = patch_type[pt] == LF_BC_FIXED_VALUE ? bdelta[b] * (patch_value[pt] - T[rbface_cell[b]]) : 0.0;
+}
+
+// the gradient of the problem's T with its conditions (lf_problem_grad, whose
+// argument and state checks come first)
+lf_status launch_problem_grad(lf_problem *P, double *grad, double *bgrad) {
+    const lf_mesh *m = P->mesh;
+    if (!m->gface && !m->gband) {
+        set_error("the mesh holds no gradient geometry (created without face centres)");
+        return LF_EINVAL;
+    }
+    hipStream_t s = P->stream;
+    if (m->B == 0) bgrad = nullptr;
+    if (m->B > 0) {
+        const dim3 bgrid((m->B + kBlock - 1) / kBlock), bblock(kBlock);
+        hipLaunchKernelGGL(k_nonorth_bvalues, bgrid, bblock, 0, s, m->B, m->rbface_cell, m->bface_patch,
+                           P->patch_type, P->patch_value, P->T, P->Tb);
+        if (bgrad)
+            hipLaunchKernelGGL(k_bsngrad, bgrid, bblock, 0, s, m->B, m->rbface_cell, m->bface_patch, P->patch_type,
+                               P->patch_value, m->bdelta, P->T, P->snb);
+    }
+    if (m->gband) {
+        if (m->n_bands < 1 || m->n_bands > kMaxBands) { set_error("bad band count %d", m->n_bands); return LF_EINVAL; }
+        launch_grad_band(m, P->T, P->Tb, P->snb, grad, bgrad, s);
+    } else {
+        // T is kept in the solver's order: no copy; rows write to their mesh cells
+        hipLaunchKernelGGL(k_grad_rows, dim3((m->N + kGradBlock - 1) / kGradBlock), dim3(kGradBlock), 0, s, m->N,
+                           P->T, P->Tb, P->snb, m->soff, m->scol, m->rlen, m->gerec, m->rbface_start,
+                           m->rbface_list, m->gbface, m->V, m->iperm, grad, bgrad);
+    }
+    LF_HIP(hipGetLastError());
+    return LF_OK;
+}
+
 }  // namespace lf
 
 using namespace lf;

@@ -567,14 +567,15 @@ void carve_problem(Carver &cv, const lf_mesh *m, const lf_solver_opts &o, lf_pro
     auto *tb = cv.take<double>(B);
     auto *part = cv.take<double>(static_cast<size_t>(kNumPart) * G);
     auto *state = cv.take<PcgState>(1);
-    double *grad3 = nullptr, *lap_src = nullptr, *T_old = nullptr;
+    double *grad3 = nullptr, *lap_src = nullptr, *T_old = nullptr, *snb = nullptr;
     if (!m->orthogonal) {
         grad3 = cv.take<double>(3 * N);
         lap_src = cv.take<double>(N);
         T_old = cv.take<double>(N);
     }
+    if (m->gface || m->gband) snb = cv.take<double>(B);
     if (P) {
-        P->grad3 = grad3; P->lap_src = lap_src; P->T_old = T_old;
+        P->grad3 = grad3; P->lap_src = lap_src; P->T_old = T_old; P->snb = snb;
         P->patch_type = pt; P->patch_value = pv;
         P->T = vec[0]; P->r = vec[1]; P->p = vec[2]; P->q = vec[3]; P->w = vec[4]; P->rD = vec[5];
         P->p2 = vec[6]; P->diag = vec[7]; P->source = vec[8]; P->diagB = vec[9]; P->srcB = vec[10];

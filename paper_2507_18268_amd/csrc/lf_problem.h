@@ -94,6 +94,8 @@ struct lf_problem {
     double *grad3 = nullptr;                   // [3N]
     double *lap_src = nullptr;                 // [N]
     double *T_old = nullptr;                   // [N] T at the start of the step (corrector passes)
+    double *snb = nullptr;                     // [B] normal gradient of T on the boundary faces
+                                               // (lf_problem_grad; meshes with gradient geometry)
     double *part = nullptr;                    // [kNumPart][grid]
     lf::PcgState *state = nullptr;
     // mixed precision (FP32 inner solve)

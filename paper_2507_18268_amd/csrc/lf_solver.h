@@ -74,6 +74,7 @@ void launch_mx_scale(lf_problem *P, hipStream_t s);
 // non-orthogonal meshes: boundary values and gradient of T, then P->lap_src
 // (lf_grad.hip); runs before the assembly of each step
 void launch_nonorth_source(lf_problem *P, hipStream_t s);
+lf_status launch_problem_grad(lf_problem *P, double *grad, double *bgrad);
 // A solve is driven in two halves so that one host loop can drive several
 // problems on their own streams: *_start enqueues the set-up and the first
 // block of iterations, followed by an async copy of the solver state and

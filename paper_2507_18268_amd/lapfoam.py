@@ -108,6 +108,7 @@ _SIGS = {
     "lf_get_matrix": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 7),
     "lf_amul": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lf_grad": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 5),
+    "lf_problem_grad": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lf_batch_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
     "lf_batch_create": (C.c_int32, [C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
                                     C.POINTER(C.c_void_p)]),
@@ -296,6 +297,10 @@ def lf_get_matrix(h, diag=None, upper=None, source=None, diag_b=None, source_b=N
 def lf_grad(h, T_ptr, Tb_ptr, snb_ptr, grad_ptr, bgrad_ptr):
     _check(lib().lf_grad(h, C.c_void_p(T_ptr), C.c_void_p(Tb_ptr), C.c_void_p(snb_ptr),
                          C.c_void_p(grad_ptr), C.c_void_p(bgrad_ptr)), "lf_grad")
+
+
+def lf_problem_grad(h, grad_ptr, bgrad_ptr):
+    _check(lib().lf_problem_grad(h, C.c_void_p(grad_ptr), C.c_void_p(bgrad_ptr)), "lf_problem_grad")
 
 
 def lf_amul(h, x_ptr, y_ptr):
@@ -495,6 +500,17 @@ class Problem:
         self.h = lf_problem_create(mesh.h, arr, DT, dt, self.opts, self.ws.data_ptr(),
                                    self.ws_bytes, self.stream)
         self._async_steps, self._async_snap = 0, None     # lf_step_begin's run
+
+    def grad(self, with_boundary=True):
+        """Gauss gradient of the current T with the problem's boundary
+        conditions: (grad [N,3], bgrad [B,3] or None), new device tensors in
+        the mesh's order, ordered on the problem's stream."""
+        torch = _torch()
+        N, B = self.mesh.n_cells, self.mesh.n_bfaces
+        g = torch.empty((N, 3), dtype=torch.float64, device="cuda")
+        bg = torch.empty((max(B, 1), 3), dtype=torch.float64, device="cuda") if with_boundary else None
+        lf_problem_grad(self.h, g.data_ptr(), bg.data_ptr() if with_boundary else 0)
+        return g, (bg[:B] if with_boundary else None)
 
     def layout(self):
         """LF_LAYOUT_ROWS or LF_LAYOUT_BANDS."""

@@ -173,3 +173,43 @@ def test_grad_full_size_permuted_192_skewed(L, oracle):
     og, obg = oracle.gauss_grad(mesh, T, Tb, snb)
     assert np.array_equal(g, og), float(np.max(np.abs(g - og)))
     assert np.array_equal(bg, obg), float(np.max(np.abs(bg - obg)))
+
+
+PROBLEM_MESHES = [
+    ("graded_9x8x7", synth.box_mesh(9, 8, 7, z_ratio=4.0), False),
+    ("random_9x8x7", synth.renumber(synth.box_mesh(9, 8, 7, z_ratio=4.0),
+                                    synth.random_permutation(504, 3)), False),
+    ("skew_random_9x8x7", synth.affine(synth.renumber(synth.box_mesh(9, 8, 7, z_ratio=4.0),
+                                                      synth.random_permutation(504, 3)), synth.SKEW), True),
+    ("skew_graded_9x8x7", synth.affine(synth.box_mesh(9, 8, 7, z_ratio=4.0), synth.SKEW), True),
+]
+
+
+@pytest.mark.parametrize("name,mesh,skewed", PROBLEM_MESHES, ids=[n for n, _, _ in PROBLEM_MESHES])
+def test_problem_grad_with_its_conditions(L, oracle, name, mesh, skewed):
+    """The gradient of a problem's T with its own boundary conditions, bit for
+    bit against the oracle's boundary values and gradient (mixed conditions)."""
+    bcs = [(synth.FIXED_VALUE, 300.0), (synth.FIXED_VALUE, 500.0), (synth.ZERO_GRADIENT, 0.0),
+           (synth.FIXED_VALUE, 410.0), (synth.ZERO_GRADIENT, 0.0), (synth.ZERO_GRADIENT, 0.0)]
+    import torch
+    m = L.Mesh(mesh, gradient=True, non_orthogonal=skewed)
+    P = L.Problem(m, bcs, 1e-3, 5e-3)
+    T = synth.initial_field(mesh.n_cells, 91)
+    P.set_T(T)
+    g, bg = P.grad()
+    torch.cuda.synchronize()
+    Tb, snb = oracle.boundary_values(mesh, bcs, T)
+    og, obg = oracle.gauss_grad(mesh, T, Tb, snb)
+    assert np.array_equal(g.cpu().numpy(), og), name
+    assert np.array_equal(bg.cpu().numpy(), obg), name
+    P.close()
+    m.close()
+
+
+def test_problem_grad_needs_face_centres(L):
+    m = L.Mesh(synth.box_mesh(3, 3, 3))
+    P = L.Problem(m, synth.fixed_x_bcs(), 1e-3, 5e-3)
+    with pytest.raises(L.LapfoamError, match="LF_EINVAL"):
+        P.grad()
+    P.close()
+    m.close()
