@@ -180,3 +180,23 @@ def test_nonorth_corrector_passes_mixed(L, oracle):
 def test_corrector_option_checked(L):
     with pytest.raises(L.LapfoamError, match="LF_EINVAL"):
         _problem(L, MESHES[0][1], "diagonal", n_nonorth_corr=-1)
+
+
+def test_nonorth_rows_layout_on_band_mesh(L, oracle):
+    """A band-form mesh solved in the row layout: the correction (taken from
+    the mesh's band records) and the assembly (rows) together, bit for bit."""
+    mesh = MESHES[0][1]
+    m, P = _problem(L, mesh, "diagonal", layout=L.LF_LAYOUT_ROWS)
+    assert P.layout() == L.LF_LAYOUT_ROWS
+    T0 = synth.initial_field(mesh.n_cells, 14)
+    P.set_T(T0)
+    P.assemble()
+    g = P.matrix()
+    o = oracle.assemble(mesh, BCS, DT, dt, T0, lap_src=oracle.step_source(mesh, BCS, DT, T0))
+    for k in ("diag", "upper", "source", "diag_b", "source_b"):
+        assert np.array_equal(g[k], o[k]), k
+    st, _ = P.step(2)
+    _, ostats, osnaps = oracle.run_nonorth(mesh, BCS, DT, dt, 2, T0)
+    assert max_rel(P.get_T(), osnaps[-1]) <= 1e-8
+    P.close()
+    m.close()
