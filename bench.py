@@ -318,7 +318,9 @@ def run_grad(L, torch, p, label, launches=20):
     return {"workload": f"Gauss gradient, {label}",
             "kernel": kname, "launches": launches, "avg_us": us,
             "algorithmic_bytes": nbytes, "achieved_GBps": gbps, "peak_GBps": HBM_PEAK_GBS,
-            "frac": gbps / HBM_PEAK_GBS, "traffic": traffic}
+            "frac": gbps / HBM_PEAK_GBS, "traffic": traffic,
+            "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbps / HBM_PEAK_GBS, "traffic": traffic}}
 
 
 def run_serving(L, torch, args):

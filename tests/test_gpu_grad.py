@@ -213,3 +213,30 @@ def test_problem_grad_needs_face_centres(L):
         P.grad()
     P.close()
     m.close()
+
+
+def test_problem_grad_refused_while_stepping(L):
+    """lf_problem_grad reads T: refused (LF_ESTATE) while an lf_step_begin run
+    is in flight, allowed once it has finished."""
+    import time
+    mesh = synth.box_mesh(12, 10, 8)
+    m = L.Mesh(mesh, gradient=True)
+    P = L.Problem(m, synth.fixed_x_bcs(), 1e-3, 5e-3)
+    P.set_T(synth.initial_field(mesh.n_cells, 3))
+    P.step_begin(3)
+    finished = False
+    try:
+        P.grad()
+        refused = False
+    except L.LapfoamError as e:
+        refused = "LF_ESTATE" in str(e)
+    t0 = time.time()
+    while not finished and time.time() - t0 < 60:
+        _, finished, _, _ = P.step_poll()
+    assert finished
+    # the run advances only through step_poll, so it was still in flight at the call
+    assert refused
+    g, _ = P.grad()
+    assert g.shape == (mesh.n_cells, 3)
+    P.close()
+    m.close()
