@@ -228,7 +228,8 @@ lf_status lf_mesh_get_addressing(const lf_mesh *mesh, int32_t *owner_start, int3
 /* Gauss gradient of a cell field (Section 5.2: calcGrad = linear
  * interpolation to the faces, gradf, then correctBoundaryConditions), for the
  * explicit non-orthogonal correction of the Laplacian:
- *   w_f = |S_f.(C_N - C_f)| / (|S_f.(C_f - C_P)| + |S_f.(C_N - C_f)|) (owner weight)
+ *   w_f = |S_f.(C_N - C_f)| / (|S_f.(C_f - C_P)| + |S_f.(C_N - C_f)|) (owner weight),
+ *         or 1/2 where that denominator is not above ROOTVSMALL = 1e-150
  *   s_f = w_f (T_P - T_N) + T_N
  *   grad_c = (sum over the faces owned by c of S_f s_f - sum over the faces
  *            whose neighbour is c of S_f s_f + sum over its boundary faces of

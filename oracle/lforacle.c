@@ -434,11 +434,14 @@ done:
 /* on orthogonal meshes: it feeds the explicit non-orthogonal correction.   */
 /* ------------------------------------------------------------------------ */
 
-/* Linear interpolation weights (Section 5.2, the weights loop).  The paper
- * prints the two projected distances SfdOwn = |S_f.(C_f - C_P)| and
- * SfdNei = |S_f.(C_N - C_f)| but not the weight itself.  READING: the owner's
- * weight is the neighbour-side share, w_f = SfdNei / (SfdOwn + SfdNei), so
- * that a field linear along the line P-N is reproduced at the face. */
+/* Linear interpolation weights (Section 5.2, the weights loop): with the two
+ * projected distances SfdOwn = |S_f.(C_f - C_P)| and SfdNei = |S_f.(C_N - C_f)|
+ * the owner's weight is w_f = SfdNei / (SfdOwn + SfdNei), the neighbour-side
+ * share, so that a field linear along the line P-N is reproduced at the face;
+ * when |SfdOwn + SfdNei| is not above ROOTVSMALL the weight is 1/2.
+ * READING: the paper names ROOTVSMALL without its value; OpenFOAM's
+ * double-precision value is the square root of VSMALL = 1e-300, i.e. 1e-150. */
+#define LFO_ROOTVSMALL 1.0e-150
 int lfo_interp_weights(int32_t n_faces, const int32_t *owner, const int32_t *neighbour,
                        const double *cell_centre, const double *face_area,
                        const double *face_centre, double *w)
@@ -450,7 +453,8 @@ int lfo_interp_weights(int32_t n_faces, const int32_t *owner, const int32_t *nei
         const double *N = cell_centre + 3 * (size_t)neighbour[f];
         double sfd_own = fabs(S[0] * (Cf[0] - P[0]) + S[1] * (Cf[1] - P[1]) + S[2] * (Cf[2] - P[2]));
         double sfd_nei = fabs(S[0] * (N[0] - Cf[0]) + S[1] * (N[1] - Cf[1]) + S[2] * (N[2] - Cf[2]));
-        w[f] = sfd_nei / (sfd_own + sfd_nei);
+        double den = sfd_own + sfd_nei;
+        w[f] = fabs(den) > LFO_ROOTVSMALL ? sfd_nei / den : 0.5;
     }
     return LFO_OK;
 }

@@ -45,11 +45,15 @@ __device__ __forceinline__ void store_rec(double *__restrict__ r, int64_t i, dou
 
 // Interpolation weights (Section 5.2, the weights loop): with the projected
 // distances SfdOwn = |S_f.(C_f - C_P)| and SfdNei = |S_f.(C_N - C_f)|, the
-// owner's weight is w_f = SfdNei / (SfdOwn + SfdNei).
+// owner's weight is w_f = SfdNei / (SfdOwn + SfdNei), or 1/2 when
+// |SfdOwn + SfdNei| does not exceed ROOTVSMALL (OpenFOAM's double-precision
+// value, the square root of 1e-300).
 //
 // On a non-orthogonal mesh (gkface or gkband given) also the record of the
 // Laplacian's correction: k_f = S_f/|S_f| - delta_f (C_N - C_P), with |S_f| and
 // delta_f as the implicit part uses them, and the same weight.
+constexpr double kRootVSmall = 1.0e-150;
+
 __global__ void k_grad_face_geometry(int32_t f0, int32_t m, int32_t n, BandOffsets bo,
                                      const int32_t *__restrict__ owner, const int32_t *__restrict__ neighbour,
                                      const double *__restrict__ C, const double *__restrict__ S,
@@ -66,7 +70,8 @@ __global__ void k_grad_face_geometry(int32_t f0, int32_t m, int32_t n, BandOffse
     const double *Q = C + 3 * static_cast<int64_t>(neighbour[f]);
     const double sfd_own = fabs(sx * (fx - P[0]) + sy * (fy - P[1]) + sz * (fz - P[2]));
     const double sfd_nei = fabs(sx * (Q[0] - fx) + sy * (Q[1] - fy) + sz * (Q[2] - fz));
-    const double w = sfd_nei / (sfd_own + sfd_nei);
+    const double den = sfd_own + sfd_nei;
+    const double w = fabs(den) > kRootVSmall ? sfd_nei / den : 0.5;
     double kx = 0.0, ky = 0.0, kz = 0.0;
     if (gkface || gkband) {
         const double mg = mag_sf[f], dl = delta[f];

@@ -386,8 +386,9 @@ class Mesh:
     owner, neighbour, cell_volume, cell_centre [N,3], face_area [F,3],
     patch_start, bface_cell, bface_area [B,3], bface_centre [B,3], and
     face_centre [F,3] when `gradient` (the mesh then serves `grad`).
-    `non_orthogonal` accepts skewed faces (gradient only: problems refuse
-    such a mesh).
+    `non_orthogonal` accepts skewed faces; problems on such a mesh (created
+    with `gradient`) apply the Laplacian's explicit non-orthogonal
+    correction every step.
     """
 
     def __init__(self, m, stream=None, gradient=False, non_orthogonal=False):

@@ -224,6 +224,32 @@ def affine(mesh: BoxMesh, A) -> BoxMesh:
 
 SKEW = ((1.0, 0.30, 0.10), (0.20, 1.0, 0.25), (-0.10, 0.15, 1.0))
 
+# x sheared by 25 y: the x and y faces of a box make an angle of about 87.7
+# degrees with the lines joining their cell centres (cosine 1/sqrt(626), below
+# 1/20), the z faces stay orthogonal to them
+STEEP = ((1.0, 25.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0))
+
+
+def from_arrays(cell_centre, cell_volume, faces, patches) -> BoxMesh:
+    """A mesh given face by face (small hand-made cases).
+
+    faces: [(owner, neighbour, S_f, C_f)] in upper-triangular order;
+    patches: [[(cell, S_b, C_b), ...], ...] one list of boundary faces per patch.
+    """
+    cc = np.asarray(cell_centre, dtype=np.float64).reshape(-1, 3)
+    bf = [b for p in patches for b in p]
+    starts = np.concatenate(([0], np.cumsum([len(p) for p in patches]))).astype(np.int32)
+    f3 = lambda rows: np.asarray(rows, dtype=np.float64).reshape(-1, 3)
+    return BoxMesh(
+        n_cells=cc.shape[0], n_faces=len(faces),
+        owner=np.asarray([f[0] for f in faces], dtype=np.int32),
+        neighbour=np.asarray([f[1] for f in faces], dtype=np.int32),
+        cell_volume=np.asarray(cell_volume, dtype=np.float64), cell_centre=cc,
+        face_area=f3([f[2] for f in faces]), face_centre=f3([f[3] for f in faces]),
+        patch_names=tuple(f"patch{i}" for i in range(len(patches))), patch_start=starts,
+        bface_cell=np.asarray([b[0] for b in bf], dtype=np.int32),
+        bface_area=f3([b[1] for b in bf]), bface_centre=f3([b[2] for b in bf]))
+
 
 def random_permutation(n: int, seed: int) -> np.ndarray:
     """new_of_old for a seeded random relabelling: cells ranked by SplitMix64 keys."""

@@ -76,3 +76,23 @@ def norm_factor(A, b, x0):
 def line_mesh(n, z_ratio=1.0):
     import synth
     return synth.box_mesh(n, 1, 1, z_ratio=z_ratio)
+
+
+def tiny_face_cells():
+    """Two cells whose shared face reaches the interpolation weight's fallback.
+
+    Cells at (0, 0, 0) and (1e-11, 1, 0) with volumes 1e-140; the internal face
+    has S = (1e-140, 0, 0) and centre (2e-12, 0.5, 0), so its projected
+    distances sum to 1e-151 (the weight is 1/2, against 0.8 from their ratio)
+    and n.d = 1e-11 is far below 0.05|d| (the limiter binds).  Every area and
+    volume is of order 1e-140, so the face's value weighs as much in the
+    cells' gradients as on an ordinary mesh.  Six patches in the order of a
+    box's (x walls first), the last four empty.
+    """
+    import synth
+    s = 1e-140
+    return synth.from_arrays(
+        [[0.0, 0.0, 0.0], [1e-11, 1.0, 0.0]], [s, s],
+        [(0, 1, (s, 0.0, 0.0), (2e-12, 0.5, 0.0))],
+        [[(0, (-s, 0.0, 0.0), (-0.5, 0.0, 0.0))], [(1, (s, 0.0, 0.0), (0.5 + 1e-11, 1.0, 0.0))],
+         [(0, (0.0, -s, 0.0), (0.0, -0.5, 0.0))], [(1, (0.0, s, 0.0), (1e-11, 1.5, 0.0))], [], []])

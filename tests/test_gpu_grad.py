@@ -10,6 +10,7 @@ import pytest
 
 import synth
 from tests.gpu_common import lapfoam
+from tests.helpers import tiny_face_cells
 
 pytestmark = pytest.mark.gpu
 
@@ -45,6 +46,12 @@ def _meshes():
     yield "line_9_natural", synth.box_mesh(9, 1, 1, z_ratio=1.0), False
     yield "one_cell", skew(synth.box_mesh(1, 1, 1)), True
     yield "no_patches_5x4x3", _strip_boundary(skew(synth.box_mesh(5, 4, 3, z_ratio=2.0))), True
+    # x and y faces past the limiter's angle (delta_f = 1/(0.05|d|)), band form and rows
+    yield "steep_graded_9x8x7", synth.affine(g, synth.STEEP), True
+    yield "steep_random_9x8x7", synth.affine(synth.renumber(g, synth.random_permutation(g.n_cells, 5)),
+                                             synth.STEEP), True
+    # a face whose interpolation weight takes the ROOTVSMALL fallback of 1/2
+    yield "tiny_face_two_cells", tiny_face_cells(), True
 
 
 MESHES = list(_meshes())

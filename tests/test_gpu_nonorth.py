@@ -12,6 +12,7 @@ import pytest
 
 import synth
 from tests.gpu_common import lapfoam, max_rel
+from tests.helpers import tiny_face_cells
 
 pytestmark = pytest.mark.gpu
 
@@ -34,6 +35,11 @@ def _meshes():
     yield "skew_one_cell", skew(synth.box_mesh(1, 1, 1)), "diagonal"
     big = synth.box_mesh(20, 17, 13, z_ratio=10.0)
     yield "skew_random_20x17x13", skew(synth.renumber(big, synth.random_permutation(big.n_cells, 8))), "diagonal"
+    # x and y faces past the limiter's angle: delta_f = 1/(0.05|d|) (band form, rows, red-black)
+    steep = lambda m: synth.affine(m, synth.STEEP)
+    yield "steep_graded_9x8x7", steep(g), "diagonal"
+    yield "steep_random_9x8x7", steep(synth.renumber(g, synth.random_permutation(g.n_cells, 5))), "diagonal"
+    yield "steep_redblack_6x5x4_dic", steep(synth.renumber(rb, synth.red_black_numbering(rb)[0])), "dic"
 
 
 MESHES = list(_meshes())
@@ -61,6 +67,24 @@ def test_nonorth_matrix_bitwise(L, oracle, name, mesh, pc):
         assert np.array_equal(g[k], o[k]), (name, k, float(np.max(np.abs(g[k] - o[k]))))
     if mesh.n_faces:
         assert np.max(np.abs(lap_src)) > 0.0
+    P.close()
+    m.close()
+
+
+def test_nonorth_matrix_tiny_face_bitwise(L, oracle):
+    """Two cells whose face takes the interpolation weight's fallback (1/2) and
+    the limiter: the correction (weights, k_f, delta_f) bit for bit."""
+    mesh = tiny_face_cells()
+    m, P = _problem(L, mesh, "diagonal")
+    T0 = np.array([300.0, 500.0])
+    P.set_T(T0)
+    P.assemble()
+    g = P.matrix()
+    lap_src = oracle.step_source(mesh, BCS, DT, T0)
+    o = oracle.assemble(mesh, BCS, DT, dt, T0, lap_src=lap_src)
+    for k in ("diag", "upper", "source", "diag_b", "source_b", "int_coeff", "bou_coeff"):
+        assert np.array_equal(g[k], o[k]), (k, g[k], o[k])
+    assert np.max(np.abs(lap_src)) > 0.0
     P.close()
     m.close()
 
