@@ -42,6 +42,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+MIXED_SOURCES = ["paper_2507_18268_amd/csrc/lf_mixed.hip", "paper_2507_18268_amd/csrc/lf_kernels.h"]
+MIXED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mx_amul_graded256.json")
 GRAD_SOURCES = ["paper_2507_18268_amd/csrc/lf_grad.hip"]
 GRAD_LABEL = "256^3 box graded in z (ratio 10) and skewed"
 GRAD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_grad_band_skewed256.json")
@@ -55,10 +57,13 @@ def kernel_source_hash(sources=None):
     return h.hexdigest()
 
 
-def amul_bytes(n_cells, n_faces, value_bytes=8):
+def amul_bytes(n_cells, n_faces, value_bytes=8, addressed=True):
     """Algorithmic bytes of one LDU product: x, diag and Ax once per cell, the
-    coefficient and the two face addresses (int32) once per face."""
-    return 3 * value_bytes * n_cells + (value_bytes + 8) * n_faces
+    coefficient once per face and, when the faces are addressed (owner and
+    neighbour lists), their two int32 addresses.  A structured numbering (the
+    band layout) needs no addresses: the neighbour of row c across band k is
+    c + d_k."""
+    return 3 * value_bytes * n_cells + (value_bytes + (8 if addressed else 0)) * n_faces
 
 
 def layout_bytes(mesh, layout_name, value_bytes=8):
@@ -87,23 +92,42 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(p, budget_s):
-    """The oracle (single thread, FP64) on the first step(s) of the same workload."""
+    """The oracle (single thread, FP64) on the first step(s) of the same
+    workload, the calling thread pinned to one host core."""
     from oracle import oracle
-    steps, solve_s, iters = 0, 0.0, 0
-    T = p.T0.copy()
-    t_start = time.perf_counter()
-    while steps < p.steps:
-        T, st, _ = oracle.run(p.mesh, p.bcs, p.DT, p.dt, 1, T)
-        steps += 1
-        solve_s += st[0]["solve_s"]
-        iters += st[0]["n_iter"]
-        if time.perf_counter() - t_start > budget_s:
-            break
+    allowed = sorted(os.sched_getaffinity(0))
+    core = allowed[0]
+    os.sched_setaffinity(0, {core})
+    try:
+        steps, solve_s, iters = 0, 0.0, 0
+        T = p.T0.copy()
+        t_start = time.perf_counter()
+        while steps < p.steps:
+            T, st, _ = oracle.run(p.mesh, p.bcs, p.DT, p.dt, 1, T)
+            steps += 1
+            solve_s += st[0]["solve_s"]
+            iters += st[0]["n_iter"]
+            if time.perf_counter() - t_start > budget_s:
+                break
+    finally:
+        os.sched_setaffinity(0, set(allowed))
     return {"value": p.mesh.n_cells * iters / solve_s, "unit": "cell-PCG-iters/s", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "host_cpu": host_cpu_model(), "pinned_core": core,
+            "host_cores_visible": len(allowed),
             "sample": f"first {steps} time step(s) of the same workload, PCG solve time only, "
-                      f"{iters} iterations, {solve_s:.2f} s, one host thread"}
+                      f"{iters} iterations, {solve_s:.2f} s, one host thread pinned to core {core}"}
 
 
 def run_mixed(L, torch, p, mesh, prob64, T0, args):
@@ -156,11 +180,20 @@ def run_mixed(L, torch, p, mesh, prob64, T0, args):
         e_mf.append(float(((a - b).abs() / b.abs()).max()))
         e_mt.append(float(((a - t).abs() / t.abs()).max()))
         e_ft.append(float(((b - t).abs() / t.abs()).max()))
+    banded = pm.layout() == L.LF_LAYOUT_BANDS
+    walk = pm.amul_walk()
     pref.close()
     pm.close()
+    kernels = {k: {"avg_us": 1e3 * ms / n, "launches": n} for k, (ms, n) in prof.items()}
     return {"value_cell_steps_per_s": N * args.steps / wall, "inner_tol": opts.inner_tol,
-            "kernel_avg_us": {k: {"avg_us": 1e3 * ms / n, "launches": n} for k, (ms, n) in prof.items()},
+            "kernel_avg_us": kernels,
+            "roofline": mixed_roofline(kernels, N, p.mesh.n_faces, banded, walk),
             "accuracy_steps": n_acc,
+            "accuracy_reading": "per step on the same system: each step of the precision form, of "
+                                "the FP64 path at tol 1e-9 (itself within 1e-8 of the oracle in the "
+                                "parity tests) and of an FP64 solve converged to tol 1e-13 starts "
+                                "from the precision form's own T_n; the precision form refines to "
+                                "0.1 tol",
             "max_rel_T_err_vs_converged_fp64_max": max(e_mt),
             "fp64_at_tol_max_rel_T_err_vs_converged_fp64_max": max(e_ft),
             "max_rel_T_err_vs_converged_fp64_first_steps": e_mt[:5],
@@ -173,6 +206,58 @@ def run_mixed(L, torch, p, mesh, prob64, T0, args):
             "max_rel_T_err_vs_fp64_at_tol_max": max(e_mf),
             "max_rel_T_err_vs_fp64_at_tol_first_steps": e_mf[:5],
             "speedup_vs_fp64_time_to_tol": None}
+
+
+# Bytes each kernel of the precision form must move per launch, band layout
+# (FP32 inner vectors and coefficients, FP64 outer fields); per cell and per
+# internal face.  The inner product reads the FP32 scaled coefficient of each
+# face once (unit diagonal, not read).
+MIXED_KERNEL_BYTES = {
+    "inner_amul_dot": ("p, q (FP32) per cell + FP32 coefficient per face", 8, 4),
+    "inner_update": ("q, s, r read and r written (FP32) per cell", 16, 0),
+    "inner_direction": ("r, p, y read and p, y written (FP32) per cell", 20, 0),
+    "mixed_residual": ("diag, source, T (FP64), p (FP32) read, r, y (FP32) written per cell "
+                       "+ FP64 coefficient per face", 36, 8),
+    "mixed_prep": ("s (FP32) per cell + FP64 coefficient read and FP32 written per face", 4, 12),
+    "mixed_correct": ("T read and written (FP64), y, p, s read (FP32) per cell", 28, 0),
+}
+
+
+def mixed_roofline(kernels, n_cells, n_faces, banded, walk):
+    """Roofline of the precision form's kernels: algorithmic bytes (above) over
+    the average launch time; the dominant one (largest total time) in the
+    roofline object, every one in its table.  Counter traffic for the inner
+    product when the record matches the sources."""
+    table = {}
+    for k, (what, per_cell, per_face) in MIXED_KERNEL_BYTES.items():
+        if k not in kernels:
+            continue
+        b = per_cell * n_cells + per_face * n_faces
+        us = kernels[k]["avg_us"]
+        gbps = b / (us * 1e-6) / 1e9
+        table[k] = {"bytes_per_launch": b, "bytes": what, "avg_us": us, "GBps": gbps,
+                    "frac": gbps / HBM_PEAK_GBS, "launches": kernels[k]["launches"]}
+    if not table or not banded:
+        return {"kernels": table}
+    dom = max(table, key=lambda k: table[k]["avg_us"] * table[k]["launches"])
+    d = table[dom]
+    kname = {"inner_amul_dot": "k_mx_amul_dot_walk" if walk else "k_mx_amul_dot",
+             "inner_update": "k_mx_update", "inner_direction": "k_mx_direction",
+             "mixed_residual": "k_mx_residual_walk" if walk else "k_mx_residual",
+             "mixed_prep": "k_mx_scale", "mixed_correct": "k_mx_correct"}[dom]
+    roof = {"kernel": kname, "bound": "hbm", "achieved": d["GBps"], "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": d["frac"], "traffic": None,
+            "algorithmic_bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_us"],
+            "kernels": table}
+    if os.path.exists(MIXED_TRAFFIC_FILE):
+        with open(MIXED_TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if (tr.get("source_sha256") == kernel_source_hash(MIXED_SOURCES) and tr.get("n_cells") == n_cells
+                and tr.get("kernel") == kname):
+            roof["traffic"] = tr["hbm_bytes_per_launch"]
+            roof["traffic_GBps"] = roof["traffic"] / (d["avg_us"] * 1e-6) / 1e9
+            roof["traffic_frac"] = roof["traffic_GBps"] / HBM_PEAK_GBS
+    return roof
 
 
 def run_config_leg(L, torch, name, steps, warmup=1, skew=False):
@@ -221,15 +306,23 @@ PAPER_SIDES = (100, 200, 300, 400)     # the four box meshes of the paper's eval
 PAPER_DT, PAPER_STEPS, PAPER_DIFFUSIVITY = 0.2, 500, 1e-4
 
 
+# steps per side in the default run: the two small boxes in full, the two
+# large ones bounded (their per-step figures scale to the 500 steps)
+PAPER_BOUNDED_STEPS = {100: 500, 200: 500, 300: 100, 400: 40}
+
+
 def run_paper_sweep(L, torch, sides=PAPER_SIDES, steps=PAPER_STEPS):
     """The paper's evaluation shapes: uniform unit boxes of n^3 cells, 500 time
     steps of 0.2 s (100 s simulated), PCG with the diagonal preconditioner, FP64.
     The diffusivity is not given there: 1e-4 m^2/s.  Boundary conditions and
     T0 as the other configs.  Assembly and solver time are the library's own
-    per-step event timings, summed; total is the wall clock of the steps."""
+    per-step event timings, summed; total is the wall clock of the steps.
+    steps: an int for every side, or a dict side -> steps; a run shorter than
+    500 steps also reports the per-step times scaled to 500."""
     import synth
     out = []
     for n in sides:
+        n_steps = steps[n] if isinstance(steps, dict) else steps
         t = time.perf_counter()
         mesh_h = synth.box_mesh(n, n, n)
         T0 = synth.initial_field(mesh_h.n_cells, 20250724)
@@ -245,15 +338,20 @@ def run_paper_sweep(L, torch, sides=PAPER_SIDES, steps=PAPER_STEPS):
         prob.set_T(T0d)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        stats, _ = prob.step(steps)
+        stats, _ = prob.step(n_steps)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        rec = {"side": n, "n_cells": N, "n_faces": F, "steps": steps, "dt": PAPER_DT,
+        rec = {"side": n, "n_cells": N, "n_faces": F, "steps": n_steps, "dt": PAPER_DT,
                "DT": PAPER_DIFFUSIVITY, "assembly_s": sum(x["assemble_ms"] for x in stats) / 1e3,
                "solver_s": sum(x["solve_ms"] for x in stats) / 1e3, "total_s": wall,
-               "iters_per_step_mean": sum(x["n_iter"] for x in stats) / steps,
+               "iters_per_step_mean": sum(x["n_iter"] for x in stats) / n_steps,
+               "cell_iters_per_s": N * sum(x["n_iter"] for x in stats) / wall,
                "all_converged": all(x["converged"] == 1 for x in stats), "mesh_generation_s": gen}
-        log(f"[bench] paper shape {n}^3: {wall:.2f} s for {steps} steps")
+        if n_steps != PAPER_STEPS:
+            k = PAPER_STEPS / n_steps
+            rec["scaled_to_500_steps"] = {"assembly_s": rec["assembly_s"] * k,
+                                          "solver_s": rec["solver_s"] * k, "total_s": wall * k}
+        log(f"[bench] paper shape {n}^3: {wall:.2f} s for {n_steps} steps")
         out.append(rec)
         prob.close()
         mesh.close()
@@ -383,7 +481,7 @@ def run_serving(L, torch, args):
     sat["cell_steps_per_s"] = cells * 10 * sat["solves_per_s"] / len(base)
     out["saturated"] = sat
     rate_sat = sat["solves_per_s"]
-    fracs = [0.25, 0.5, 1.0, 2.0, 4.0] if args.serve_sweep else [0.5]
+    fracs = [0.5] if args.serve_quick else [0.25, 0.5, 1.0, 2.0, 4.0]
     out["poisson"] = []
     for f in fracs:
         summ = one(f * rate_sat, f"poisson {f}x")
@@ -391,6 +489,21 @@ def run_serving(L, torch, args):
         summ["fraction_of_saturated"] = f
         out["poisson"].append(summ)
     srv.close()
+    if args.serve_small_budget_gib > 0:
+        # a deliberately small HBM budget: meshes no longer all fit, so the
+        # server evicts idle problems and meshes and rebuilds them on demand
+        small = S.Server(mesh_for_side, int(args.serve_small_budget_gib * 2 ** 30),
+                         n_slots=args.serve_slots, slot_capacity=args.serve_capacity, max_steps=10,
+                         tuning=tuning, direct_min_side=args.serve_direct_min or None,
+                         direct_workers=args.serve_direct_workers,
+                         direct_use_graph=not args.serve_direct_no_graph)
+        srv = small
+        summ = one(None, f"saturated, budget {args.serve_small_budget_gib} GiB")
+        summ["budget_GiB"] = args.serve_small_budget_gib
+        summ["mesh_builds"] = small.mesh_builds
+        summ["evictions"] = small.evictions
+        out["small_budget"] = summ
+        small.close()
     return out
 
 
@@ -416,8 +529,13 @@ def main():
     ap.add_argument("--skewed-only", action="store_true",
                     help="only the config's box skewed, --steps corrected time steps (for profiling)")
     ap.add_argument("--no-extra-configs", action="store_true")
+    ap.add_argument("--no-paper-shapes", action="store_true",
+                    help="skip the bounded run of the paper's four box sizes")
     ap.add_argument("--serve-only", action="store_true")
-    ap.add_argument("--serve-sweep", action="store_true", help="Poisson rates 0.25x..4x of saturated")
+    ap.add_argument("--serve-quick", action="store_true",
+                    help="one Poisson rate (0.5x of saturated) instead of 0.25x..4x")
+    ap.add_argument("--serve-small-budget-gib", type=float, default=1.0,
+                    help="also serve the stream under this HBM budget (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -533,18 +651,26 @@ def main():
         out["kernel_avg_us"] = kernels
         dom = max(prof, key=lambda k: prof[k][0])
         ka = kernels["amul_dot"]
-        per_launch = amul_bytes(N, F)
-        achieved = per_launch / (ka["avg_us"] * 1e-6) / 1e9
+        us = ka["avg_us"]
+        # algorithmic bytes of the product as it runs: the band layout's
+        # neighbours are implicit (c + d_k), so no face addresses
+        per_launch = amul_bytes(N, F, addressed=(layout_name != "bands"))
+        achieved = per_launch / (us * 1e-6) / 1e9
         kname = "k_amul_dot_walk" if walk else "k_amul_dot"
         roof = {"kernel": f"{kname} (q = A p with p.q partials)", "bound": "hbm",
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                 "algorithmic_bytes_per_launch": per_launch,
-                "avg_launch_us": ka["avg_us"], "largest_total_time_kernel": dom}
+                "algorithmic_bytes": "24 B/cell (p, diag, q) + 8 B/face (coefficient)"
+                                     + ("" if layout_name == "bands" else " + 8 B/face (two int32 addresses)"),
+                "avg_launch_us": us, "largest_total_time_kernel": dom}
+        face_addr = amul_bytes(N, F, addressed=True)
+        roof["face_addressed_bytes_per_launch"] = face_addr
+        roof["face_addressed_frac"] = face_addr / (us * 1e-6) / 1e9 / HBM_PEAK_GBS
         lb = layout_bytes(p.mesh, layout_name)
         roof["layout"] = layout_name
         roof["layout_bytes_per_launch"] = lb
-        roof["layout_GBps"] = lb / (ka["avg_us"] * 1e-6) / 1e9
+        roof["layout_GBps"] = lb / (us * 1e-6) / 1e9
         roof["layout_frac"] = roof["layout_GBps"] / HBM_PEAK_GBS
         if os.path.exists(TRAFFIC_FILE):
             with open(TRAFFIC_FILE) as f:
@@ -552,6 +678,8 @@ def main():
             if (tr.get("source_sha256") == kernel_source_hash() and tr.get("n_cells") == N
                     and tr.get("kernel") == kname):
                 roof["traffic"] = tr["hbm_bytes_per_launch"]
+                roof["traffic_GBps"] = roof["traffic"] / (us * 1e-6) / 1e9
+                roof["traffic_frac"] = roof["traffic_GBps"] / HBM_PEAK_GBS
         out["roofline"] = roof
         # whole-iteration view: the three kernels of one PCG iteration
         it_us = sum(kernels[k]["avg_us"] for k in ("amul_dot", "update", "direction") if k in kernels)
@@ -582,6 +710,14 @@ def main():
 
     if not args.no_serve:
         out["serving"] = run_serving(L, torch, args)
+
+    if not args.no_paper_shapes and args.n is None:
+        # the paper's evaluation boxes (100^3 .. 400^3, dt 0.2 s), bounded steps
+        out["paper_shapes"] = {
+            "workload": "uniform unit boxes 100^3, 200^3, 300^3, 400^3 (the paper's Mesh-S..XL), "
+                        f"DT={PAPER_DIFFUSIVITY}, dt={PAPER_DT}, implicit Euler, PCG diagonal, "
+                        f"tol {synth.TOL}, FP64; steps per side {PAPER_BOUNDED_STEPS}",
+            "runs": run_paper_sweep(L, torch, steps=PAPER_BOUNDED_STEPS)}
 
     if not args.no_cpu_baseline:
         log("[bench] oracle on the host ...")

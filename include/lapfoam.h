@@ -334,7 +334,9 @@ lf_status lf_step_many(lf_problem *const *problems, int32_t n, int32_t n_steps, 
  * mesh's cell order, may be NULL) receive T after each step, copied on the
  * problem's stream; stats[n_steps] (host, may be NULL) receives the stats of
  * the finished steps.  While a run is in flight the problem must not be
- * stepped, reset or read (those calls return LF_ESTATE); destroying it waits for
+ * stepped, reset, assembled or read (lf_step, lf_step_many, lf_problem_reset,
+ * lf_set_T, lf_get_T, lf_get_boundary_T, lf_problem_grad, lf_assemble,
+ * lf_get_matrix, lf_amul and lf_batch_launch return LF_ESTATE); destroying it waits for
  * the run's device work.  For a scheduler that keeps several problems of
  * different sizes going without one waiting for another. */
 lf_status lf_step_begin(lf_problem *problem, int32_t n_steps, double *snapshots);
@@ -377,7 +379,8 @@ lf_status lf_batch_destroy(lf_batch *batch);     /* NULL-safe; waits for a launc
  * each step, step-major.  The problems' T must be set (and any work on their
  * own streams finished) before the call; they must not be used until the
  * launch has finished (lf_batch_poll / lf_batch_wait).  LF_ESTATE if the
- * previous launch has not finished. */
+ * previous launch has not finished or a problem has an lf_step_begin run in
+ * flight; LF_EINVAL if a problem is listed twice. */
 lf_status lf_batch_launch(lf_batch *batch, int32_t n, lf_problem *const *problems,
                           double *const *snapshots, int32_t n_steps, int32_t block_threads,
                           int32_t n_workgroups);

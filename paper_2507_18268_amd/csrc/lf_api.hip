@@ -28,7 +28,11 @@ struct StepDriver {
 };
 }  // namespace lf
 
-static bool async_running(const lf_problem *P) { return P->async && P->async->active; }
+namespace lf {
+bool problem_in_flight(const lf_problem *P) { return P->async && P->async->active; }
+}  // namespace lf
+
+static bool async_running(const lf_problem *P) { return problem_in_flight(P); }
 
 extern "C" {
 
@@ -339,6 +343,7 @@ __global__ void k_boundary_values(int32_t B, const int32_t *__restrict__ bface_c
 lf_status lf_get_boundary_T(lf_problem *P, double *Tb, int32_t on_device) {
     clear_error();
     if (!P || (!Tb && P->mesh->B > 0)) { set_error("NULL argument"); return LF_EINVAL; }
+    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
     const lf_mesh *m = P->mesh;
     if (m->B == 0) return LF_OK;
     double *dst = on_device ? Tb : P->Tb;
@@ -362,6 +367,7 @@ lf_status lf_problem_grad(lf_problem *P, double *grad, double *bgrad) {
 lf_status lf_assemble(lf_problem *P) {
     clear_error();
     if (!P) { set_error("NULL problem"); return LF_EINVAL; }
+    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
     LF_TRY(launch_assemble(P, true, P->stream));
     P->assembled = true;
     return LF_OK;
@@ -371,6 +377,7 @@ lf_status lf_get_matrix(lf_problem *P, double *diag, double *upper, double *sour
                         double *source_b, double *int_coeff, double *bou_coeff) {
     clear_error();
     if (!P) { set_error("NULL problem"); return LF_EINVAL; }
+    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
     if (!P->assembled) { set_error("call lf_assemble first"); return LF_ESTATE; }
     const lf_mesh *m = P->mesh;
     hipStream_t s = P->stream;
@@ -390,6 +397,7 @@ lf_status lf_get_matrix(lf_problem *P, double *diag, double *upper, double *sour
 lf_status lf_amul(lf_problem *P, const double *x, double *y) {
     clear_error();
     if (!P || !x || !y) { set_error("NULL argument"); return LF_EINVAL; }
+    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
     if (!P->assembled) { set_error("call lf_assemble first"); return LF_ESTATE; }
     if (!P->mesh->iperm) return launch_amul_hook(P, x, y);
     LF_TRY(to_solver_order(P, x, P->p2));

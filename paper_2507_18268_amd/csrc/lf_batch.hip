@@ -368,9 +368,18 @@ lf_status lf_batch_launch(lf_batch *b, int32_t n, lf_problem *const *problems, d
         set_error("block_threads must be 256, 512 or 1024");
         return LF_EINVAL;
     }
+    {
+        std::vector<const lf_problem *> seen(problems, problems + n);
+        std::sort(seen.begin(), seen.end());
+        if (std::adjacent_find(seen.begin(), seen.end()) != seen.end()) {
+            set_error("a problem is listed twice (each task writes its problem's T and vectors)");
+            return LF_EINVAL;
+        }
+    }
     for (int32_t i = 0; i < n; ++i) {
         const lf_problem *P = problems[i];
         if (!P) { set_error("problem %d is NULL", i); return LF_EINVAL; }
+        if (problem_in_flight(P)) { set_error("problem %d: an lf_step_begin run is in flight", i); return LF_ESTATE; }
         if (P->opts.precision != LF_PREC_MIXED || P->opts.precond != LF_PC_DIAGONAL) {
             set_error("problem %d: the batched form needs LF_PREC_MIXED with the diagonal preconditioner", i);
             return LF_EINVAL;

@@ -18,6 +18,9 @@ namespace lf {
 void set_error(const char *fmt, ...);
 void clear_error();
 
+// true while an lf_step_begin run of the problem has not finished
+bool problem_in_flight(const lf_problem *P);
+
 #define LF_HIP(call)                                                               \
     do {                                                                           \
         hipError_t e_ = (call);                                                    \

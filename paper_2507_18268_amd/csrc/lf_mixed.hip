@@ -28,9 +28,13 @@
 // sum s_c |rs_c|, has fallen by inner_tol, or below half the outer target,
 // whichever is larger.  The refinement runs until res < kTighten * tol
 // (convergence is still reported against tol).  Every FP64 PCG that stops
-// just below tol leaves an error of its own in T (up to ~6e-9 relative per
-// step on these meshes); by stopping an order of magnitude lower the
-// precision form stays within 1e-8 of such a solve of the same system.
+// just below tol leaves an error of its own in T, against the exactly solved
+// step (on the 256^3 graded box up to 2.6e-8 relative in the first step from
+// a random field, a few 1e-9 on small meshes); stopping an order of magnitude
+// lower keeps the precision form's own error a tenth of that (1.4e-9 there).
+// Its distance to one particular FP64 solve stopped at tol is then that
+// solve's error plus its own, and is not bounded by 1e-8 where the former
+// exceeds it.
 constexpr double kTighten = 0.1;
 #include <hip/hip_runtime.h>
 

@@ -143,6 +143,8 @@ class Server:
         self.ready: List[_Live] = []                  # admitted, not launched
         self.finished: List[Request] = []
         self.rejected: List[Request] = []
+        self.mesh_builds = 0                          # device meshes created
+        self.evictions = 0                            # idle problems and meshes freed for room
         self.t0 = time.perf_counter()
 
     # ------------------------------------------------------------------ clock
@@ -169,6 +171,7 @@ class Server:
         if side in self.meshes:
             return self.meshes[side]
         m = L.Mesh(self.mesh_for_side(side))
+        self.mesh_builds += 1
         self.meshes[side] = m
         self.mesh_bytes[side] = m.ws_bytes
         self.used += m.ws_bytes
@@ -178,6 +181,7 @@ class Server:
     def _close_idle(self, key):
         for P in self.idle.pop(key, []):
             self.used -= P.ws_bytes
+            self.evictions += 1
             P.close()
 
     def _evict(self, need, keep_side):
@@ -195,6 +199,7 @@ class Server:
             if side != keep_side and self.mesh_users[side] == 0 and not any(
                     k[0] == side and ps for k, ps in self.idle.items()):
                 self.meshes.pop(side).close()
+                self.evictions += 1
                 self.used -= self.mesh_bytes.pop(side)
                 self.mesh_last_use.pop(side, None)
 

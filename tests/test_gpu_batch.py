@@ -154,3 +154,32 @@ def test_batch_refuses_bad_input(L):
     P.close()
     Pm.close()
     m.close()
+
+
+def test_batch_at_served_sizes(L, oracle):
+    """The cube sides the serving stream puts on the batched kernel (24..31,
+    up to 29,791 cells; band layout, the tuned workgroup size of the bucket):
+    each step against the oracle's step from the same T, and each problem
+    bitwise the same alone and in the mix."""
+    from paper_2507_18268_amd import autotune
+    rng = np.random.default_rng(12)
+    reqs = []
+    for i, n in enumerate((24, 26, 29, 31)):
+        DT = float(np.exp(rng.uniform(np.log(1e-4), np.log(1e-2))))
+        reqs.append((synth.box_mesh(n, n, n), synth.fixed_x_bcs(), DT, 1e-3,
+                     synth.initial_field(n ** 3, 7000 + i)))
+    bs = autotune.block_threads_for(24)
+    assert all(autotune.block_threads_for(r[0].shape[0]) == bs for r in reqs)
+    steps = 3
+    mix = _run(L, reqs, steps, bs=bs, layout=L.LF_LAYOUT_AUTO)
+    for i, (mesh, bcs, DT, dt, T0) in enumerate(reqs):
+        snaps, stats, _ = mix[i]
+        T_prev = T0
+        for s in range(steps):
+            ref, _, _ = oracle.run(mesh, bcs, DT, dt, 1, T_prev)
+            assert max_rel(snaps[s], ref) <= T_TOL, (mesh.shape, s, max_rel(snaps[s], ref))
+            assert stats[s]["converged"] == 1
+            T_prev = snaps[s]
+    for i in (0, 3):
+        alone = _run(L, [reqs[i]], steps, bs=bs, layout=L.LF_LAYOUT_AUTO)[0]
+        assert np.array_equal(alone[0], mix[i][0])

@@ -77,24 +77,87 @@ def test_full_size_steps_match_oracle(L, oracle, cfg, steps):
         assert sg[s]["final_residual"] < synth.TOL
 
 
-def test_full_size_mixed_matches_oracle_per_step(L, oracle):
-    """Precision form at 256^3, each step on the same system as the oracle (the
-    oracle steps once from the precision form's own T).  At this size the FP64
-    PCG stopped at tol 1e-9 is itself about 2.5e-8 (max relative) away from the
-    solution of the system, so the 1e-8 bar is taken against the oracle's
-    converged solve (tol 1e-13); the stopping residual is checked against tol."""
-    p = synth.build_config("mixed_256", steps=2)
-    m, P, _ = _problem(L, p)
-    P.set_T(p.T0)
-    T_prev = p.T0
-    for s in range(2):
+def _paper_box(n):
+    """One of the paper's evaluation boxes: uniform n^3 cells on the unit cube,
+    DT = 1e-4 (unstated in the paper), dt = 0.2, the configs' boundary
+    conditions and T0 recipe."""
+    return synth.box_mesh(n, n, n), synth.fixed_x_bcs(), 1e-4, 0.2, \
+        synth.initial_field(n ** 3, 20250724)
+
+
+def test_paper_shape_100_steps_match_oracle(L, oracle):
+    """Mesh-S (100^3) at the paper's time step: five steps in the benchmark's
+    launch configuration, each against the oracle's step from the same T."""
+    mesh, bcs, DT, dt, T0 = _paper_box(100)
+    m = L.Mesh(mesh)
+    P = L.Problem(m, bcs, DT, dt, L.make_opts(tol=synth.TOL))
+    P.set_T(T0)
+    T_prev = T0
+    for s in range(5):
         sg, _ = P.step(1)
         Tg = P.get_T()
-        exact, so, _ = oracle.run(p.mesh, p.bcs, p.DT, p.dt, 1, T_prev, tol=1e-13)
-        assert max_rel(Tg, exact) <= T_TOL, (s, max_rel(Tg, exact))
-        assert sg[0]["converged"] == 1 and sg[0]["final_residual"] < synth.TOL
-        assert abs(sg[0]["initial_residual"] - so[0]["initial_residual"]) <= \
-            1e-10 * so[0]["initial_residual"]
+        To, so, _ = oracle.run(mesh, bcs, DT, dt, 1, T_prev)
+        assert max_rel(Tg, To) <= T_TOL, (s, max_rel(Tg, To))
+        assert abs(sg[0]["n_iter"] - so[0]["n_iter"]) <= 1, (s, sg[0], so[0])
+        assert sg[0]["converged"] == 1 and so[0]["converged"] == 1
         T_prev = Tg
+    P.close()
+    m.close()
+
+
+def test_paper_shape_300_one_step(L, oracle):
+    """Mesh-L (300^3, 27 M cells, 80.7 M internal faces), the largest size
+    compared with the oracle: the matrix bitwise, one time step within 1e-8."""
+    mesh, bcs, DT, dt, T0 = _paper_box(300)
+    m = L.Mesh(mesh)
+    P = L.Problem(m, bcs, DT, dt, L.make_opts(tol=synth.TOL))
+    assert P.layout() == L.LF_LAYOUT_BANDS and P.amul_walk()
+    P.set_T(T0)
+    P.assemble()
+    g = P.matrix()
+    o = oracle.assemble(mesh, bcs, DT, dt, T0)
+    for k in ("diag", "upper", "source", "diag_b", "source_b"):
+        assert np.array_equal(g[k], o[k]), k
+    del g, o
+    sg, _ = P.step(1)
+    Tg = P.get_T()
+    P.close()
+    m.close()
+    To, so, _ = oracle.run(mesh, bcs, DT, dt, 1, T0)
+    assert max_rel(Tg, To) <= T_TOL, max_rel(Tg, To)
+    assert abs(sg[0]["n_iter"] - so[0]["n_iter"]) <= 1, (sg[0], so[0])
+
+
+def test_full_size_mixed_twenty_steps(L, oracle):
+    """The precision form over the benchmark's 20 steps of the 256^3 box, each
+    step on the same system (from the precision form's own T_n): within 1e-8 of
+    an FP64 solve of that system converged to tol 1e-13 on the GPU at every
+    step, and of the oracle's converged solve at steps 1, 2 and 20 (which also
+    pins the GPU's converged solve); the stopping residual below tol."""
+    import torch
+    p = synth.build_config("mixed_256", steps=20)
+    m, P, _ = _problem(L, p)
+    R = L.Problem(m, p.bcs, p.DT, p.dt, L.make_opts(tol=1e-13, rel_tol=0.0, max_iter=synth.MAX_ITER))
+    N = p.mesh.n_cells
+    a = torch.from_numpy(p.T0).cuda()
+    t = torch.empty_like(a)
+    P.set_T(a)
+    for s in range(20):
+        T_prev = a.clone()
+        R.set_T(T_prev)
+        sg, _ = P.step(1)
+        R.step(1)
+        P.get_T(a)
+        R.get_T(t)
+        err = float(((a - t).abs() / t.abs()).max())
+        assert err <= T_TOL, (s, err)
+        assert sg[0]["converged"] == 1 and sg[0]["final_residual"] < synth.TOL
+        if s in (0, 1, 19):
+            exact, _, _ = oracle.run(p.mesh, p.bcs, p.DT, p.dt, 1, T_prev.cpu().numpy(), tol=1e-13)
+            Tg = a.cpu().numpy()
+            assert max_rel(Tg, exact) <= T_TOL, (s, max_rel(Tg, exact))
+            assert max_rel(t.cpu().numpy(), exact) <= 1e-10, s
+    assert a.numel() == N
+    R.close()
     P.close()
     m.close()

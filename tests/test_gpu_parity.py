@@ -401,14 +401,19 @@ def test_problem_reset_equals_fresh_problem(L, oracle):
         P.step(2)
         P.reset(bcs2, 5e-3, 2e-3)
         P.set_T(T0)
-        s1, _ = P.step(3)
+        s1 = []
+        for _ in range(3):
+            # each step against the oracle's step from the same T (the per-step bar)
+            T_prev = P.get_T()
+            st, _ = P.step(1)
+            s1 += st
+            ref, _, _ = oracle.run(mesh, bcs2, 5e-3, 2e-3, 1, T_prev)
+            assert max_rel(P.get_T(), ref) <= T_TOL, (precision, max_rel(P.get_T(), ref))
         Q = L.Problem(m, bcs2, 5e-3, 2e-3, L.make_opts(precision=precision))
         Q.set_T(T0)
         s2, _ = Q.step(3)
         assert np.array_equal(P.get_T(), Q.get_T()), precision
         assert [s["n_iter"] for s in s1] == [s["n_iter"] for s in s2]
-        ref, _, _ = oracle.run(mesh, bcs2, 5e-3, 2e-3, 3, T0)
-        assert max_rel(P.get_T(), ref) <= T_TOL * 3
         with pytest.raises(L.LapfoamError):
             P.reset(bcs2, -1.0, 2e-3)
         P.close()
@@ -474,3 +479,54 @@ def test_step_many_equals_single_steps(L):
     for m, P in alone + together:
         P.close()
         m.close()
+
+
+def test_calls_refused_while_in_flight_and_duplicate_batch_tasks(L):
+    """While an lf_step_begin run is in flight the problem is neither assembled
+    nor read through the test hooks or the boundary values, and no batch
+    launch takes it (LF_ESTATE); a batch launch listing one problem twice is
+    refused (LF_EINVAL).  Everything works again once the run has finished."""
+    import time
+    import torch
+    mesh = synth.box_mesh(10, 9, 8)
+    m = L.Mesh(mesh)
+    P = L.Problem(m, BCS_MIXED, 5e-3, 2e-3, L.make_opts(precision=L.LF_PREC_MIXED,
+                                                        layout=L.LF_LAYOUT_ROWS))
+    Q = L.Problem(m, BCS_MIXED, 5e-3, 2e-3, L.make_opts(precision=L.LF_PREC_MIXED,
+                                                        layout=L.LF_LAYOUT_ROWS))
+    T0 = synth.initial_field(mesh.n_cells, 41)
+    P.set_T(T0)
+    Q.set_T(T0)
+    P.assemble()
+    x = torch.ones(mesh.n_cells, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    B = L.Batch(4, 2)
+    with pytest.raises(L.LapfoamError, match="LF_EINVAL"):
+        B.launch([Q, Q], 1)
+    P.step_begin(3)
+    refused = []
+    for name, call in (("assemble", P.assemble), ("matrix", P.matrix),
+                       ("amul", lambda: P.amul(x, y)), ("boundary_T", P.boundary_T),
+                       ("batch", lambda: B.launch([Q, P], 1))):
+        try:
+            call()
+        except L.LapfoamError as e:
+            refused.append((name, "LF_ESTATE" in str(e)))
+        else:
+            refused.append((name, False))
+    t0 = time.time()
+    finished = False
+    while not finished and time.time() - t0 < 60:
+        _, finished, _, _ = P.step_poll()
+    assert finished
+    # the run advances only through step_poll, so it was in flight at each call
+    assert all(ok for _, ok in refused), refused
+    P.assemble()
+    P.matrix()
+    P.boundary_T()
+    B.launch([Q, P], 1)
+    B.wait()
+    B.close()
+    P.close()
+    Q.close()
+    m.close()

@@ -119,3 +119,35 @@ def test_direct_lane_alone_equals_in_mix_and_matches_oracle(L, oracle):
             assert max_rel(r.snapshots[s], ref) <= 1e-8
             assert r.stats[s]["converged"] == 1
             T_prev = r.snapshots[s]
+
+
+def test_direct_lane_at_served_sizes(L, oracle):
+    """Sides 32..48 on the direct lane (the serving stream sends sides >= 32
+    there), next to small batched requests: every step of the large requests
+    against the oracle's step from the same T, and alone = in the mix bitwise."""
+    from paper_2507_18268_amd.serve import Request
+    sides = (32, 40, 48, 12, 9, 36)
+    def reqs():
+        rng = np.random.default_rng(21)
+        out = []
+        for i, n in enumerate(sides):
+            DT = float(np.exp(rng.uniform(np.log(1e-4), np.log(1e-2))))
+            out.append(Request(rid=i, n=n, DT=DT, dt=1e-3, steps=3,
+                               T0=synth.initial_field(n ** 3, 8000 + i), bcs=synth.fixed_x_bcs(),
+                               arrival=0.0005 * i))
+        return out
+    mix, _ = serve(L, reqs(), budget=16 << 30, direct_min_side=32, direct_workers=3)
+    assert len(mix) == len(sides) and all(r.error is None for r in mix.values())
+    for rid in (0, 1, 2, 5):
+        r = mix[rid]
+        mesh = mesh_for_side(r.n)
+        T_prev = r.T0
+        for s in range(r.steps):
+            ref, _, _ = oracle.run(mesh, r.bcs, r.DT, r.dt, 1, T_prev)
+            assert max_rel(r.snapshots[s], ref) <= 1e-8, (r.n, s)
+            assert r.stats[s]["converged"] == 1
+            T_prev = r.snapshots[s]
+    for rid in (0, 2):
+        alone, _ = serve(L, [reqs()[rid]], slots=1, cap=1, budget=16 << 30, direct_min_side=32,
+                         direct_workers=1)
+        assert np.array_equal(alone[rid].snapshots, mix[rid].snapshots)
