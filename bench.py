@@ -260,7 +260,7 @@ def mixed_roofline(kernels, n_cells, n_faces, banded, walk):
     return roof
 
 
-def run_config_leg(L, torch, name, steps, warmup=1, skew=False):
+def run_config_leg(L, torch, name, steps, warmup=1, skew=False, precond=None):
     """Another config of the workload family, timed like the main line: `steps`
     time steps from T0 after `warmup` steps, wall clock around the whole steps.
     skew: the config's box mapped by synth.SKEW (non-orthogonal faces), so every
@@ -272,7 +272,8 @@ def run_config_leg(L, torch, name, steps, warmup=1, skew=False):
         p.mesh = synth.affine(p.mesh, synth.SKEW)
     N = p.mesh.n_cells
     log(f"[bench] {name}{' skewed' if skew else ''}: {N} cells, mesh generated in {time.perf_counter() - t:.1f} s")
-    precond = L.LF_PC_DIC if p.precond == "dic" else L.LF_PC_DIAGONAL
+    pc_name = precond or p.precond
+    precond = {"dic": L.LF_PC_DIC, "amg": L.LF_PC_AMG}.get(pc_name, L.LF_PC_DIAGONAL)
     precision = L.LF_PREC_MIXED if p.precision == "mixed" else L.LF_PREC_FP64
     opts = L.make_opts(tol=synth.TOL, rel_tol=synth.REL_TOL, max_iter=synth.MAX_ITER,
                        precond=precond, precision=precision)
@@ -289,7 +290,7 @@ def run_config_leg(L, torch, name, steps, warmup=1, skew=False):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     iters = sum(s["n_iter"] for s in stats)
-    out = {"n_cells": N, "steps": steps, "precond": p.precond, "precision": p.precision,
+    out = {"n_cells": N, "steps": steps, "precond": pc_name, "precision": p.precision,
            "layout": "bands" if prob.layout() == L.LF_LAYOUT_BANDS else "rows",
            "ms_per_step": wall * 1e3 / steps, "iters_per_step_mean": iters / steps,
            "cell_iters_per_s": N * iters / wall, "us_per_iteration": wall * 1e6 / max(iters, 1),
@@ -311,14 +312,16 @@ PAPER_DT, PAPER_STEPS, PAPER_DIFFUSIVITY = 0.2, 500, 1e-4
 PAPER_BOUNDED_STEPS = {100: 500, 200: 500, 300: 100, 400: 40}
 
 
-def run_paper_sweep(L, torch, sides=PAPER_SIDES, steps=PAPER_STEPS):
+def run_paper_sweep(L, torch, sides=PAPER_SIDES, steps=PAPER_STEPS, preconds=("diagonal",)):
     """The paper's evaluation shapes: uniform unit boxes of n^3 cells, 500 time
     steps of 0.2 s (100 s simulated), PCG with the diagonal preconditioner, FP64.
     The diffusivity is not given there: 1e-4 m^2/s.  Boundary conditions and
     T0 as the other configs.  Assembly and solver time are the library's own
     per-step event timings, summed; total is the wall clock of the steps.
     steps: an int for every side, or a dict side -> steps; a run shorter than
-    500 steps also reports the per-step times scaled to 500."""
+    500 steps also reports the per-step times scaled to 500.  Each side runs
+    once per preconditioner in `preconds` ("diagonal", "amg") on the same
+    device mesh."""
     import synth
     out = []
     for n in sides:
@@ -327,33 +330,37 @@ def run_paper_sweep(L, torch, sides=PAPER_SIDES, steps=PAPER_STEPS):
         mesh_h = synth.box_mesh(n, n, n)
         T0 = synth.initial_field(mesh_h.n_cells, 20250724)
         gen = time.perf_counter() - t
-        opts = L.make_opts(tol=synth.TOL, rel_tol=synth.REL_TOL, max_iter=synth.MAX_ITER)
         mesh = L.Mesh(mesh_h)
         N, F = mesh_h.n_cells, mesh_h.n_faces
         del mesh_h
-        prob = L.Problem(mesh, synth.fixed_x_bcs(), PAPER_DIFFUSIVITY, PAPER_DT, opts)
         T0d = torch.from_numpy(T0).cuda()
-        prob.set_T(T0d)
-        prob.step(2)                      # warm-up (graph capture, first launches)
-        prob.set_T(T0d)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        stats, _ = prob.step(n_steps)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        rec = {"side": n, "n_cells": N, "n_faces": F, "steps": n_steps, "dt": PAPER_DT,
-               "DT": PAPER_DIFFUSIVITY, "assembly_s": sum(x["assemble_ms"] for x in stats) / 1e3,
-               "solver_s": sum(x["solve_ms"] for x in stats) / 1e3, "total_s": wall,
-               "iters_per_step_mean": sum(x["n_iter"] for x in stats) / n_steps,
-               "cell_iters_per_s": N * sum(x["n_iter"] for x in stats) / wall,
-               "all_converged": all(x["converged"] == 1 for x in stats), "mesh_generation_s": gen}
-        if n_steps != PAPER_STEPS:
-            k = PAPER_STEPS / n_steps
-            rec["scaled_to_500_steps"] = {"assembly_s": rec["assembly_s"] * k,
-                                          "solver_s": rec["solver_s"] * k, "total_s": wall * k}
-        log(f"[bench] paper shape {n}^3: {wall:.2f} s for {n_steps} steps")
-        out.append(rec)
-        prob.close()
+        for pc in preconds:
+            opts = L.make_opts(tol=synth.TOL, rel_tol=synth.REL_TOL, max_iter=synth.MAX_ITER,
+                               precond=L.LF_PC_AMG if pc == "amg" else L.LF_PC_DIAGONAL)
+            prob = L.Problem(mesh, synth.fixed_x_bcs(), PAPER_DIFFUSIVITY, PAPER_DT, opts)
+            prob.set_T(T0d)
+            prob.step(2)                      # warm-up (graph capture, first launches)
+            prob.set_T(T0d)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            stats, _ = prob.step(n_steps)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            rec = {"side": n, "precond": pc, "n_cells": N, "n_faces": F, "steps": n_steps, "dt": PAPER_DT,
+                   "DT": PAPER_DIFFUSIVITY, "assembly_s": sum(x["assemble_ms"] for x in stats) / 1e3,
+                   "solver_s": sum(x["solve_ms"] for x in stats) / 1e3, "total_s": wall,
+                   "ms_per_step": wall * 1e3 / n_steps,
+                   "iters_per_step_mean": sum(x["n_iter"] for x in stats) / n_steps,
+                   "cell_iters_per_s": N * sum(x["n_iter"] for x in stats) / wall,
+                   "all_converged": all(x["converged"] == 1 for x in stats), "mesh_generation_s": gen}
+            if n_steps != PAPER_STEPS:
+                k = PAPER_STEPS / n_steps
+                rec["scaled_to_500_steps"] = {"assembly_s": rec["assembly_s"] * k,
+                                              "solver_s": rec["solver_s"] * k, "total_s": wall * k}
+            log(f"[bench] paper shape {n}^3, {pc}: {wall:.2f} s for {n_steps} steps, "
+                f"{rec['iters_per_step_mean']:.1f} iterations per step")
+            out.append(rec)
+            prob.close()
         mesh.close()
         del T0d
         torch.cuda.empty_cache()
@@ -577,7 +584,7 @@ def main():
         print(json.dumps({"serving": run_serving(L, torch, args)}), flush=True)
         return
     if args.paper_sweep:
-        print(json.dumps({"paper_sweep": run_paper_sweep(L, torch)}), flush=True)
+        print(json.dumps({"paper_sweep": run_paper_sweep(L, torch, preconds=("diagonal", "amg"))}), flush=True)
         return
 
     t = time.perf_counter()
@@ -699,6 +706,8 @@ def main():
         # the same 256^3 box skewed: the corrected Laplacian (gradient, correction
         # fluxes and their divergence before each assembly)
         out["other_configs"]["graded_256_skewed"] = run_config_leg(L, torch, "graded_256", 50, skew=True)
+        # the same box with the aggregation multigrid preconditioner
+        out["other_configs"]["graded_256_amg"] = run_config_leg(L, torch, "graded_256", 50, precond="amg")
 
     if not args.no_grad and args.n is None:
         log("[bench] Gauss gradient ...")
@@ -717,7 +726,7 @@ def main():
             "workload": "uniform unit boxes 100^3, 200^3, 300^3, 400^3 (the paper's Mesh-S..XL), "
                         f"DT={PAPER_DIFFUSIVITY}, dt={PAPER_DT}, implicit Euler, PCG diagonal, "
                         f"tol {synth.TOL}, FP64; steps per side {PAPER_BOUNDED_STEPS}",
-            "runs": run_paper_sweep(L, torch, steps=PAPER_BOUNDED_STEPS)}
+            "runs": run_paper_sweep(L, torch, steps=PAPER_BOUNDED_STEPS, preconds=("diagonal", "amg"))}
 
     if not args.no_cpu_baseline:
         log("[bench] oracle on the host ...")

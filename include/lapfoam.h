@@ -61,15 +61,23 @@ typedef int32_t lf_status;
 #define LF_PC_DIC 1        /* diagonal incomplete Cholesky; needs a two-colour
                               numbering: every face's owner < every face's
                               neighbour (all "red" cells before all "black") */
+#define LF_PC_AMG 2        /* aggregation multigrid V-cycle (FP64, meshes with
+                              the box form: see lf_problem_create) */
 
-#define LF_LAYOUT_AUTO 0   /* bands when the mesh has the band form and the
-                              preconditioner is diagonal, else rows */
+#define LF_LAYOUT_AUTO 0   /* bands when the mesh has a band form for the
+                              preconditioner (diagonal or multigrid: the band
+                              form; DIC: the two-colour band form), else rows */
 #define LF_LAYOUT_ROWS 1   /* sliced row layout from the lists of lists: any
                               mesh; each coefficient stored in both its rows */
 #define LF_LAYOUT_BANDS 2  /* band layout: meshes whose internal faces take at
                               most 4 distinct offsets neighbour - owner (a
-                              structured numbering); each coefficient stored
-                              once, no column indices; diagonal PC only */
+                              structured numbering), with the diagonal or
+                              multigrid preconditioner; with DIC, the two-colour
+                              band form (a box numbered red cells first, then
+                              black, each colour in natural order, x-lines of
+                              even length): each face's coefficient stored once
+                              at its red cell's direction slot.  Each
+                              coefficient stored once, no column indices */
 
 #define LF_WALK_AUTO 0     /* matrix-vector products of a band layout with two
                               or more bands (the FP64 solve's, and the inner
@@ -257,6 +265,19 @@ lf_status lf_grad(const lf_mesh *mesh, const double *T, const double *Tb, const 
 size_t lf_problem_workspace_bytes(const lf_mesh *mesh, const lf_solver_opts *opts);
 /* bcs[n_patches]; DT >= 0 finite; dt > 0 finite.  LF_PC_DIC on a mesh without
  * the two-colour property returns LF_EINVAL.
+ * LF_PC_AMG (Section 7 names an algebraic multigrid library as the better
+ * alternative to the diagonal PCG): PCG preconditioned by one V-cycle of
+ * aggregation multigrid per iteration.  The mesh must have the box form (band
+ * offsets 1, nx, nx*ny of an nx x ny x nz box numbered i + nx (j + ny k),
+ * sides >= 2, no face wrapping between lines or planes), FP64, the band
+ * layout; else LF_EINVAL.  Level l + 1 aggregates the 2 x 2 x 2 blocks of
+ * level l (a side of odd length ends with a one-cell block) while a level has
+ * more than 512 cells and every side is 3 or longer; coarse matrices are the
+ * Galerkin products P^T A P of the piecewise-constant prolongation, formed
+ * after each assembly; the cycle on a level: x = 0, two weighted-Jacobi sweeps
+ * x += 0.8 (b - A x) / diag, the residual summed over each block as the next
+ * level's right side, its cycle's result added to each cell of the block, two
+ * more sweeps; four sweeps from x = 0 on the coarsest level.
  * On a mesh created with LF_MESH_NON_ORTHOGONAL (which then needs face centres,
  * else LF_EINVAL) the Laplacian is the Gauss linear corrected scheme in full
  * (Section 5.1, one pass of the non-orthogonal corrector loop per step): before
@@ -354,6 +375,14 @@ lf_status lf_get_matrix(lf_problem *problem, double *diag, double *upper, double
  * problem's layout and order of the solver's products; x, y device
  * pointers of N doubles, ordered on the handle's stream. */
 lf_status lf_amul(lf_problem *problem, const double *x, double *y);
+/* w = M r: the FP64 solver's preconditioner (diagonal: w = (1/diag) r; DIC:
+ * its diagonal from the last assembled matrix, then the forward and backward
+ * sweeps; multigrid: the coarse matrices of the last assembled matrix, then
+ * one cycle), as the solve applies it.  r, w device pointers of N doubles in
+ * the mesh's cell order, ordered on the handle's stream; the problem's solver
+ * vectors are overwritten (set T again before stepping).  LF_EINVAL for the
+ * mixed-precision form; LF_ESTATE before lf_assemble or during a run. */
+lf_status lf_precondition(lf_problem *problem, const double *r, double *w);
 
 /* ---- batched form -------------------------------------------------------
  * Many independent problems (each its own mesh, boundary conditions, DT, dt
@@ -419,7 +448,11 @@ lf_status lf_batch_stats(lf_batch *batch, lf_solve_stats *stats, double *elapsed
 #define LF_K_MIXED_PREP 14      /* mixed: FP32 coefficients of the scaled matrix
                                    (once per step) */
 #define LF_K_FINALIZE 15        /* one-workgroup reductions and scalar decisions */
-#define LF_NUM_KERNEL_CLASSES 16
+#define LF_K_AMG_SMOOTH 16      /* multigrid: Jacobi sweeps (all levels) */
+#define LF_K_AMG_RESTRICT 17    /* multigrid: residual summed over the aggregates */
+#define LF_K_AMG_PROLONG 18     /* multigrid: coarse correction added back */
+#define LF_K_AMG_GALERKIN 19    /* multigrid: coarse matrices (once per step) */
+#define LF_NUM_KERNEL_CLASSES 20
 lf_status lf_profile_enable(lf_problem *problem, int32_t on);
 lf_status lf_profile_read(lf_problem *problem, int32_t n_classes, double *total_ms, int64_t *launches);
 

@@ -263,6 +263,227 @@ int lfo_precondition(int pc, int32_t n_cells, int32_t n_faces, const int32_t *ow
 }
 
 /* ------------------------------------------------------------------------ */
+/* Aggregation multigrid preconditioner (Section 7 names an algebraic       */
+/* multigrid library as the better alternative to the diagonal PCG).        */
+/* READING (the paper gives no cycle): a V-cycle over Galerkin coarse       */
+/* matrices A_{l+1} = P^T A_l P, with P the piecewise-constant prolongation */
+/* of an aggregation of the cells (agg_l[c] = the coarse cell holding c):   */
+/*   coarse diag_I = sum over the cells of I (ascending) of diag_c, then    */
+/*     plus 2 upper_f for each face inside I (ascending face order);        */
+/*   coarse upper of the pair (I, J), I < J = the sum over the faces        */
+/*     joining I and J (ascending face order), pairs in upper-triangular    */
+/*     order.                                                               */
+/* Smoother: weighted Jacobi, x_c = x_c + omega ((b_c - (A x)_c) / diag_c). */
+/* Cycle on level l for b: x = 0; nu sweeps; r = b - A x; the coarse right  */
+/* side sums r over each aggregate (ascending cells); cycle on level l + 1; */
+/* x_c += coarse x of c's aggregate; nu sweeps.  On the coarsest level:     */
+/* nu_c sweeps from x = 0.  With the same sweeps before and after, the      */
+/* cycle is a symmetric operator, as PCG needs.                             */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n, nf;
+    const int32_t *owner, *neighbour;
+    const double *diag, *upper;
+    const int32_t *agg;      /* [n] coarse cell of each cell; NULL on the coarsest level */
+} amg_level;
+
+typedef struct {
+    int32_t n_levels, nu, nu_c;
+    double omega;
+    amg_level *lv;           /* levels 1.. own their arrays */
+} amg_hier;
+
+typedef struct {
+    int32_t I, J, f;
+} amg_pair;
+
+static int cmp_amg_pair(const void *a, const void *b)
+{
+    const amg_pair *p = (const amg_pair *)a, *q = (const amg_pair *)b;
+    if (p->I != q->I)
+        return p->I < q->I ? -1 : 1;
+    if (p->J != q->J)
+        return p->J < q->J ? -1 : 1;
+    return p->f < q->f ? -1 : (p->f > q->f);
+}
+
+/* Galerkin coarse matrix of (fine matrix, aggregation into nc cells).  The
+ * coarse face arrays must hold up to nf entries; *nfc receives their count. */
+int lfo_galerkin(int32_t n, int32_t nf, const int32_t *owner, const int32_t *neighbour,
+                 const double *diag, const double *upper, const int32_t *agg, int32_t nc,
+                 int32_t *nfc, int32_t *cowner, int32_t *cneighbour, double *cdiag, double *cupper)
+{
+    if (n < 1 || nf < 0 || nc < 1)
+        return LFO_EINVAL;
+    for (int32_t c = 0; c < n; ++c)
+        if (agg[c] < 0 || agg[c] >= nc)
+            return LFO_EINVAL;
+    amg_pair *pairs = (amg_pair *)malloc(sizeof(amg_pair) * (size_t)(nf > 0 ? nf : 1));
+    if (!pairs)
+        return LFO_ENOMEM;
+    for (int32_t I = 0; I < nc; ++I)
+        cdiag[I] = 0.0;
+    for (int32_t c = 0; c < n; ++c)
+        cdiag[agg[c]] += diag[c];
+    int32_t m = 0;
+    for (int32_t f = 0; f < nf; ++f) {
+        int32_t I = agg[owner[f]], J = agg[neighbour[f]];
+        if (I == J) {
+            cdiag[I] += 2.0 * upper[f];
+        } else {
+            pairs[m].I = I < J ? I : J;
+            pairs[m].J = I < J ? J : I;
+            pairs[m].f = f;
+            ++m;
+        }
+    }
+    qsort(pairs, (size_t)m, sizeof(amg_pair), cmp_amg_pair);
+    int32_t k = -1;
+    for (int32_t i = 0; i < m; ++i) {
+        if (i == 0 || pairs[i].I != pairs[i - 1].I || pairs[i].J != pairs[i - 1].J) {
+            ++k;
+            cowner[k] = pairs[i].I;
+            cneighbour[k] = pairs[i].J;
+            cupper[k] = 0.0;
+        }
+        cupper[k] += upper[pairs[i].f];
+    }
+    *nfc = k + 1;
+    free(pairs);
+    return LFO_OK;
+}
+
+static void amg_free(amg_hier *h)
+{
+    if (!h->lv)
+        return;
+    for (int32_t l = 1; l < h->n_levels; ++l) {
+        free((void *)h->lv[l].owner);
+        free((void *)h->lv[l].neighbour);
+        free((void *)h->lv[l].diag);
+        free((void *)h->lv[l].upper);
+    }
+    free(h->lv);
+    h->lv = NULL;
+}
+
+/* level_cells[n_levels]: cells per level (level_cells[0] = n); aggs: the
+ * aggregation of each level but the last, concatenated. */
+static int amg_build(int32_t n, int32_t nf, const int32_t *owner, const int32_t *neighbour,
+                     const double *diag, const double *upper, int32_t n_levels,
+                     const int32_t *level_cells, const int32_t *aggs, int32_t nu, int32_t nu_c,
+                     double omega, amg_hier *h)
+{
+    h->lv = NULL;
+    if (n_levels < 1 || level_cells[0] != n || nu < 0 || nu_c < 0)
+        return LFO_EINVAL;
+    h->n_levels = n_levels;
+    h->nu = nu;
+    h->nu_c = nu_c;
+    h->omega = omega;
+    h->lv = (amg_level *)calloc((size_t)n_levels, sizeof(amg_level));
+    if (!h->lv)
+        return LFO_ENOMEM;
+    h->lv[0].n = n;
+    h->lv[0].nf = nf;
+    h->lv[0].owner = owner;
+    h->lv[0].neighbour = neighbour;
+    h->lv[0].diag = diag;
+    h->lv[0].upper = upper;
+    const int32_t *a = aggs;
+    for (int32_t l = 0; l + 1 < n_levels; ++l) {
+        amg_level *F = &h->lv[l], *C = &h->lv[l + 1];
+        F->agg = a;
+        a += F->n;
+        int32_t nc = level_cells[l + 1];
+        size_t cap = (size_t)(F->nf > 0 ? F->nf : 1);
+        int32_t *co = (int32_t *)malloc(sizeof(int32_t) * cap);
+        int32_t *cn = (int32_t *)malloc(sizeof(int32_t) * cap);
+        double *cd = (double *)malloc(sizeof(double) * (size_t)nc);
+        double *cu = (double *)malloc(sizeof(double) * cap);
+        C->owner = co;
+        C->neighbour = cn;
+        C->diag = cd;
+        C->upper = cu;
+        C->n = nc;
+        if (!co || !cn || !cd || !cu) {
+            h->n_levels = l + 2;
+            amg_free(h);
+            return LFO_ENOMEM;
+        }
+        int rc = lfo_galerkin(F->n, F->nf, F->owner, F->neighbour, F->diag, F->upper, F->agg, nc,
+                              &C->nf, co, cn, cd, cu);
+        if (rc != LFO_OK) {
+            h->n_levels = l + 2;
+            amg_free(h);
+            return rc;
+        }
+    }
+    return LFO_OK;
+}
+
+static void amg_jacobi(const amg_level *L, double omega, const double *b, double *x, double *y)
+{
+    lfo_amul(L->n, L->nf, L->owner, L->neighbour, L->diag, L->upper, x, y);
+    for (int32_t c = 0; c < L->n; ++c)
+        x[c] = x[c] + omega * ((b[c] - y[c]) / L->diag[c]);
+}
+
+static int amg_vcycle(const amg_hier *h, int32_t l, const double *b, double *x)
+{
+    const amg_level *L = &h->lv[l];
+    double *y = (double *)malloc(sizeof(double) * (size_t)L->n);
+    if (!y)
+        return LFO_ENOMEM;
+    for (int32_t c = 0; c < L->n; ++c)
+        x[c] = 0.0;
+    if (l == h->n_levels - 1) {
+        for (int32_t s = 0; s < h->nu_c; ++s)
+            amg_jacobi(L, h->omega, b, x, y);
+        free(y);
+        return LFO_OK;
+    }
+    for (int32_t s = 0; s < h->nu; ++s)
+        amg_jacobi(L, h->omega, b, x, y);
+    lfo_amul(L->n, L->nf, L->owner, L->neighbour, L->diag, L->upper, x, y);
+    for (int32_t c = 0; c < L->n; ++c)
+        y[c] = b[c] - y[c];
+    const amg_level *C = &h->lv[l + 1];
+    double *bc = (double *)calloc((size_t)C->n, sizeof(double));
+    double *xc = (double *)malloc(sizeof(double) * (size_t)C->n);
+    if (!bc || !xc) {
+        free(y); free(bc); free(xc);
+        return LFO_ENOMEM;
+    }
+    for (int32_t c = 0; c < L->n; ++c)
+        bc[L->agg[c]] += y[c];
+    int rc = amg_vcycle(h, l + 1, bc, xc);
+    if (rc == LFO_OK) {
+        for (int32_t c = 0; c < L->n; ++c)
+            x[c] += xc[L->agg[c]];
+        for (int32_t s = 0; s < h->nu; ++s)
+            amg_jacobi(L, h->omega, b, x, y);
+    }
+    free(y); free(bc); free(xc);
+    return rc;
+}
+
+/* One application of the cycle: w = M r. */
+int lfo_amg_apply(int32_t n, int32_t nf, const int32_t *owner, const int32_t *neighbour,
+                  const double *diag, const double *upper, int32_t n_levels,
+                  const int32_t *level_cells, const int32_t *aggs, int32_t nu, int32_t nu_c,
+                  double omega, const double *r, double *w)
+{
+    amg_hier h;
+    int rc = amg_build(n, nf, owner, neighbour, diag, upper, n_levels, level_cells, aggs, nu, nu_c,
+                       omega, &h);
+    if (rc == LFO_OK)
+        rc = amg_vcycle(&h, 0, r, w);
+    amg_free(&h);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* PCG (READING: OpenFOAM's PCG semantics).                                  */
 /*  r = b - A x0;  normFactor = sum_c(|Ax0_c - pA_c| + |b_c - pA_c|) + 1e-20 */
 /*  with pA = (row sums of A) * mean(x0);  res = sum|r| / normFactor.        */
@@ -277,10 +498,12 @@ static int check_conv(double res, double res0, double tol, double rel_tol)
     return (res < tol) || (rel_tol > 1e-20 && res < rel_tol * res0);
 }
 
-int lfo_pcg(int32_t n_cells, int32_t n_faces, const int32_t *owner, const int32_t *neighbour,
-            const double *diag, const double *upper, const double *b, double *x,
-            int pc, double tol, double rel_tol, int32_t max_iter, int32_t min_iter,
-            lfo_stats *st)
+/* The loop below with the preconditioner pc, or with the cycle of amg when
+ * amg is not NULL. */
+static int pcg_core(int32_t n_cells, int32_t n_faces, const int32_t *owner,
+                    const int32_t *neighbour, const double *diag, const double *upper,
+                    const double *b, double *x, int pc, const amg_hier *amg, double tol,
+                    double rel_tol, int32_t max_iter, int32_t min_iter, lfo_stats *st)
 {
     size_t n = (size_t)(n_cells > 0 ? n_cells : 1);
     double *wA = (double *)malloc(sizeof(double) * n);
@@ -329,7 +552,15 @@ int lfo_pcg(int32_t n_cells, int32_t n_faces, const int32_t *owner, const int32_
         double wArA = 1e20, wArA_old;
         for (;;) {
             wArA_old = wArA;
-            precondition(pc, n_cells, n_faces, owner, neighbour, upper, rD, rA, wA);
+            if (amg) {
+                int rc = amg_vcycle(amg, 0, rA, wA);
+                if (rc != LFO_OK) {
+                    free(wA); free(rA); free(pA); free(rD);
+                    return rc;
+                }
+            } else {
+                precondition(pc, n_cells, n_faces, owner, neighbour, upper, rD, rA, wA);
+            }
             wArA = 0.0;
             for (int32_t c = 0; c < n_cells; ++c)
                 wArA += wA[c] * rA[c];
@@ -368,6 +599,32 @@ int lfo_pcg(int32_t n_cells, int32_t n_faces, const int32_t *owner, const int32_
     }
     free(wA); free(rA); free(pA); free(rD);
     return LFO_OK;
+}
+
+int lfo_pcg(int32_t n_cells, int32_t n_faces, const int32_t *owner, const int32_t *neighbour,
+            const double *diag, const double *upper, const double *b, double *x,
+            int pc, double tol, double rel_tol, int32_t max_iter, int32_t min_iter,
+            lfo_stats *st)
+{
+    return pcg_core(n_cells, n_faces, owner, neighbour, diag, upper, b, x, pc, NULL, tol, rel_tol,
+                    max_iter, min_iter, st);
+}
+
+/* PCG preconditioned by the aggregation multigrid cycle above. */
+int lfo_pcg_amg(int32_t n_cells, int32_t n_faces, const int32_t *owner, const int32_t *neighbour,
+                const double *diag, const double *upper, const double *b, double *x,
+                int32_t n_levels, const int32_t *level_cells, const int32_t *aggs, int32_t nu,
+                int32_t nu_c, double omega, double tol, double rel_tol, int32_t max_iter,
+                int32_t min_iter, lfo_stats *st)
+{
+    amg_hier h;
+    int rc = amg_build(n_cells, n_faces, owner, neighbour, diag, upper, n_levels, level_cells, aggs,
+                       nu, nu_c, omega, &h);
+    if (rc == LFO_OK)
+        rc = pcg_core(n_cells, n_faces, owner, neighbour, diag, upper, b, x, PC_DIAGONAL, &h, tol,
+                      rel_tol, max_iter, min_iter, st);
+    amg_free(&h);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -314,3 +314,83 @@ def run_nonorth(mesh, bcs, DT, dt, n_steps, T0, pc=PC_DIAGONAL, tol=1e-9, rel_to
         stats.append(total)
         snaps.append(T.copy())
     return T, stats, snaps
+
+
+# aggregation multigrid (READING of the oracle's header): sweeps and weight
+AMG_NU, AMG_NU_C, AMG_OMEGA = 2, 4, 0.8
+
+
+def galerkin(n, owner, neighbour, diag, upper, agg, nc):
+    """Galerkin coarse matrix P^T A P of an LDU matrix for an aggregation
+    agg[n] into nc cells: (coarse owner, neighbour, diag, upper)."""
+    nf = len(owner)
+    own, nei = _i32(owner), _i32(neighbour)
+    diag, upper, agg = _f64(diag), _f64(upper), _i32(agg)
+    cap = max(nf, 1)
+    co, cn = np.empty(cap, np.int32), np.empty(cap, np.int32)
+    cd, cu = np.empty(nc), np.empty(cap)
+    nfc = C.c_int32(0)
+    rc = lib().lfo_galerkin(C.c_int32(n), C.c_int32(nf), _p(own, np.int32), _p(nei, np.int32),
+                            _p(diag, np.float64), _p(upper, np.float64), _p(agg, np.int32),
+                            C.c_int32(nc), C.byref(nfc), _p(co, np.int32), _p(cn, np.int32),
+                            _p(cd, np.float64), _p(cu, np.float64))
+    if rc != 0:
+        raise ValueError(f"oracle galerkin failed: {rc}")
+    k = nfc.value
+    return co[:k].copy(), cn[:k].copy(), cd, cu[:k].copy()
+
+
+def _levels(level_cells, aggs):
+    lc = np.ascontiguousarray(level_cells, dtype=np.int32)
+    ag = np.ascontiguousarray(np.concatenate(aggs) if aggs else np.zeros(1), dtype=np.int32)
+    return lc, ag
+
+
+def amg_apply(mesh, diag, upper, r, level_cells, aggs, nu=AMG_NU, nu_c=AMG_NU_C, omega=AMG_OMEGA):
+    """One cycle of the aggregation multigrid preconditioner: w = M r."""
+    N, F = mesh.n_cells, mesh.n_faces
+    own, nei = _i32(mesh.owner), _i32(mesh.neighbour)
+    diag, upper, r = _f64(diag), _f64(upper), _f64(r)
+    lc, ag = _levels(level_cells, aggs)
+    w = np.empty(N)
+    rc = lib().lfo_amg_apply(C.c_int32(N), C.c_int32(F), _p(own, np.int32), _p(nei, np.int32),
+                             _p(diag, np.float64), _p(upper, np.float64), C.c_int32(len(lc)),
+                             _p(lc, np.int32), _p(ag, np.int32), C.c_int32(nu), C.c_int32(nu_c),
+                             C.c_double(omega), _p(r, np.float64), _p(w, np.float64))
+    if rc != 0:
+        raise ValueError(f"oracle amg_apply failed: {rc}")
+    return w
+
+
+def pcg_amg(mesh, diag, upper, b, x0, level_cells, aggs, tol=1e-9, rel_tol=0.0, max_iter=1000,
+            min_iter=0, nu=AMG_NU, nu_c=AMG_NU_C, omega=AMG_OMEGA):
+    """PCG preconditioned by the aggregation multigrid cycle; returns (x, stats)."""
+    N, F = mesh.n_cells, mesh.n_faces
+    x = np.array(x0, dtype=np.float64, copy=True)
+    st = Stats()
+    own, nei = _i32(mesh.owner), _i32(mesh.neighbour)
+    diag, upper, b = _f64(diag), _f64(upper), _f64(b)
+    lc, ag = _levels(level_cells, aggs)
+    rc = lib().lfo_pcg_amg(C.c_int32(N), C.c_int32(F), _p(own, np.int32), _p(nei, np.int32),
+                           _p(diag, np.float64), _p(upper, np.float64), _p(b, np.float64),
+                           _p(x, np.float64), C.c_int32(len(lc)), _p(lc, np.int32), _p(ag, np.int32),
+                           C.c_int32(nu), C.c_int32(nu_c), C.c_double(omega), C.c_double(tol),
+                           C.c_double(rel_tol), C.c_int32(max_iter), C.c_int32(min_iter), C.byref(st))
+    if rc != 0:
+        raise ValueError(f"oracle pcg_amg failed: {rc}")
+    return x, st.as_dict()
+
+
+def run_amg(mesh, bcs, DT, dt, n_steps, T0, level_cells, aggs, tol=1e-9, rel_tol=0.0,
+            max_iter=1000, min_iter=0, keep_all=False, **kw):
+    """Time steps solved by PCG with the multigrid cycle: (T_final, [stats], [T per step])."""
+    T = np.array(T0, dtype=np.float64, copy=True)
+    stats, snaps = [], ([] if keep_all else None)
+    for _ in range(n_steps):
+        A = assemble(mesh, bcs, DT, dt, T)
+        T, st = pcg_amg(mesh, A["diag_b"], A["upper"], A["source_b"], T, level_cells, aggs, tol=tol,
+                        rel_tol=rel_tol, max_iter=max_iter, min_iter=min_iter, **kw)
+        stats.append(st)
+        if keep_all:
+            snaps.append(T.copy())
+    return T, stats, snaps

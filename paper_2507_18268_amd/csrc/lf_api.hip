@@ -102,7 +102,19 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
         set_error("bad solver options");
         return LF_EINVAL;
     }
-    if (opts.precond != LF_PC_DIAGONAL && opts.precond != LF_PC_DIC) { set_error("unknown preconditioner"); return LF_EINVAL; }
+    if (opts.precond != LF_PC_DIAGONAL && opts.precond != LF_PC_DIC && opts.precond != LF_PC_AMG) {
+        set_error("unknown preconditioner");
+        return LF_EINVAL;
+    }
+    if (opts.precond == LF_PC_AMG && (m->box_nx == 0 || opts.layout == LF_LAYOUT_ROWS)) {
+        set_error("the multigrid preconditioner needs a box mesh numbered i + nx (j + ny k) (band offsets 1, nx, "
+                  "nx ny, sides >= 2) and the band layout");
+        return LF_EINVAL;
+    }
+    if (opts.precond == LF_PC_AMG && opts.precision == LF_PREC_MIXED) {
+        set_error("the mixed-precision form uses the diagonal preconditioner");
+        return LF_EINVAL;
+    }
     if (opts.precision != LF_PREC_FP64 && opts.precision != LF_PREC_MIXED) { set_error("unknown precision"); return LF_EINVAL; }
     if (opts.precond == LF_PC_DIC && m->F > 0 && !m->two_colour) {
         set_error("DIC needs a two-colour numbering (every owner < every neighbour)");
@@ -120,9 +132,13 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
         set_error("unknown amul_walk %d", opts.amul_walk);
         return LF_EINVAL;
     }
-    if (opts.layout == LF_LAYOUT_BANDS && (m->n_bands == 0 || opts.precond != LF_PC_DIAGONAL)) {
-        set_error(m->n_bands == 0 ? "the band layout needs a mesh whose faces take at most %d offsets"
-                                  : "the band layout is for the diagonal preconditioner (%d)", kMaxBands);
+    if (opts.layout == LF_LAYOUT_BANDS && opts.precond == LF_PC_DIAGONAL && m->n_bands == 0) {
+        set_error("the band layout needs a mesh whose faces take at most %d offsets", kMaxBands);
+        return LF_EINVAL;
+    }
+    if (opts.layout == LF_LAYOUT_BANDS && opts.precond == LF_PC_DIC && m->rb_h == 0) {
+        set_error("the band layout with DIC needs a two-colour numbered box whose x-lines hold an even "
+                  "number of cells");
         return LF_EINVAL;
     }
     if (opts.precond == LF_PC_DIC && opts.precision == LF_PREC_MIXED) {
@@ -146,6 +162,7 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
     P->dt = dt;
     P->stream = static_cast<hipStream_t>(stream);
     P->banded = use_bands(m, opts);
+    P->rb = use_rb(m, opts);
     P->nonorth = !m->orthogonal;
     P->sp.tol = opts.tol;
     P->sp.rel_tol = opts.rel_tol;
@@ -167,6 +184,7 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
         }
     }
     P->sp.n_red = m->two_colour ? m->n_red : m->N;
+    if (P->rb) P->sp.grid_amul = cell_blocks(m->n_red);   // the pair product: one thread per red-black pair
     P->sp.max_outer = opts.max_outer > 0 ? opts.max_outer : 50;
     P->sp.inner_tol = opts.inner_tol > 0.0 ? opts.inner_tol : 1e-5;
     P->sp.inner_restart = opts.inner_restart ? 1 : 0;
@@ -188,7 +206,7 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
     if (e == hipSuccess) e = hipMemsetAsync(P->part, 0, sizeof(double) * kNumPart * P->sp.grid, P->stream);
     // padding entries of the row layout keep coefficient 0 for good; band
     // slots without a face are written as 0 by every assembly
-    const size_t slots = coef_slots(m, P->banded);
+    const size_t slots = coef_slots(m, P->banded, P->rb);
     if (e == hipSuccess) e = hipMemsetAsync(P->coef, 0, sizeof(double) * slots, P->stream);
     if (e == hipSuccess && P->coef32) e = hipMemsetAsync(P->coef32, 0, sizeof(float) * slots, P->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
@@ -235,7 +253,7 @@ lf_status lf_problem_reset(lf_problem *P, const lf_patch_bc *bcs, double DT, dou
 lf_status lf_problem_layout(const lf_problem *P, int32_t *layout) {
     clear_error();
     if (!P || !layout) { set_error("NULL argument"); return LF_EINVAL; }
-    *layout = P->banded ? LF_LAYOUT_BANDS : LF_LAYOUT_ROWS;
+    *layout = (P->banded || P->rb) ? LF_LAYOUT_BANDS : LF_LAYOUT_ROWS;
     return LF_OK;
 }
 
@@ -403,6 +421,17 @@ lf_status lf_amul(lf_problem *P, const double *x, double *y) {
     LF_TRY(to_solver_order(P, x, P->p2));
     LF_TRY(launch_amul_hook(P, P->p2, P->q));
     return to_mesh_order(P, P->q, y);
+}
+
+lf_status lf_precondition(lf_problem *P, const double *r, double *w) {
+    clear_error();
+    if (!P || !r || !w) { set_error("NULL argument"); return LF_EINVAL; }
+    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
+    if (!P->assembled) { set_error("call lf_assemble first"); return LF_ESTATE; }
+    if (P->opts.precision != LF_PREC_FP64) { set_error("the FP64 solver's preconditioner only"); return LF_EINVAL; }
+    LF_TRY(to_solver_order(P, r, P->r));
+    LF_TRY(launch_precondition_hook(P));
+    return to_mesh_order(P, P->w, w);
 }
 
 lf_status lf_profile_enable(lf_problem *P, int32_t on) {

@@ -76,6 +76,32 @@ struct BandOffsets {
     int32_t d[kMaxBands];
 };
 
+// Two-colour band form of a mesh (see lf_mesh): nr cells of each colour, h per
+// x-line, H per xy-plane (0: no third direction), ny lines per plane.
+struct RBForm {
+    int32_t nr, h, H, ny;
+};
+
+// parity of the line holding cell u of either colour
+__host__ __device__ inline int32_t rb_par(const RBForm &f, int32_t u) {
+    const int32_t line = u / f.h;
+    return ((line % f.ny) + line / f.ny) & 1;
+}
+
+// direction 0..5 (-z, -y, -x, +x, +y, +z) of a face from red cell u to black
+// cell nr + b, or -1 when no face of the form joins them
+__host__ __device__ inline int32_t rb_direction(const RBForm &f, int32_t u, int32_t b) {
+    const int32_t off = b - u;
+    if (f.H > 0 && off == -f.H) return 0;
+    if (off == -f.h) return 1;
+    if (off == f.h) return 4;
+    if (f.H > 0 && off == f.H) return 5;
+    const int32_t par = rb_par(f, u), pos = u % f.h;
+    if (off == par - 1 && pos + par - 1 >= 0) return 2;
+    if (off == par && pos + par <= f.h - 1) return 3;
+    return -1;
+}
+
 // ---------------------------------------------------------------------------
 // handles
 // ---------------------------------------------------------------------------
@@ -111,6 +137,22 @@ struct lf_mesh {
     int32_t n_bands = 0;
     int32_t band_d[lf::kMaxBands] = {0, 0, 0, 0};
     double *band_mag_sf = nullptr, *band_delta = nullptr; // [n_bands*N]
+    // Two-colour band form: a box whose x-lines hold an even number of cells,
+    // numbered red ((i+j+k) even) first, then black, each colour in natural
+    // order.  A red cell u (and black cell n_red + u) then lies in line
+    // u / rb_h of its colour, and its six neighbours of the other colour are
+    // at u - rb_H, u - rb_h, u + par - 1, u + par, u + rb_h, u + rb_H with par
+    // the line's parity ((line % rb_ny + line / rb_ny) & 1).  The face of red
+    // cell u in direction d (0..5 in that order: -z, -y, -x, +x, +y, +z) has
+    // slot d * n_red + u, whose geometry factors are stored there (0 where
+    // the face does not exist).  rb_h = 0 when the mesh has no such form.
+    int32_t rb_h = 0, rb_H = 0, rb_ny = 1;
+    double *rb_mag_sf = nullptr, *rb_delta = nullptr;     // [6*n_red]
+    // Box form: a band form with offsets 1, nx, nx*ny whose faces are those of
+    // an nx x ny x nz box of hexahedra numbered i + nx (j + ny k) (none wraps
+    // from one x-line or xy-plane into the next); 0 when not such a box.  The
+    // multigrid preconditioner aggregates its 2 x 2 x 2 blocks.
+    int32_t box_nx = 0, box_ny = 0, box_nz = 0;
     // Cell order of the solver's arrays.  Meshes without a band form and
     // without a two-colour numbering keep their cells in Morton order of the
     // cell centres (so that a row's neighbours lie near it in memory): the

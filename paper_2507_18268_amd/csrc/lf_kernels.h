@@ -202,10 +202,95 @@ struct BandLayout {
     const double *__restrict__ delta;    // [K n]
 };
 
+// RBLayout: meshes with the two-colour band form (lf_mesh): the coefficient of
+// the face of red cell u in direction d (-z, -y, -x, +x, +y, +z) is stored
+// once, at d * nr + u.  A red row's entries are its six slots in that order
+// (ascending black column); a black row's entries are the slots of its six
+// red neighbours, mirrored (-z: red u - H, slot +z, ...), in ascending red
+// column.  Both are the orders of the sliced layout, with absent faces as
+// zero terms (a red row's own absent slot holds 0; a black row does not read
+// a neighbour slot that belongs to another cell's face).
+struct RBLayout {
+    RBForm f;
+    const double *__restrict__ mag_sf;   // [6 nr], 0 where the face does not exist
+    const double *__restrict__ delta;    // [6 nr]
+};
+
+// Row c's entries: coefficient slot, column and whether the entry may hold a
+// face (else its term is zero; slot and column are then clamped in range)
+__device__ __forceinline__ void rb_row(const RBForm &f, int32_t c, int64_t (&slot)[6], int32_t (&col)[6],
+                                       bool (&ok)[6]) {
+    const int32_t nr = f.nr;
+    const bool red = c < nr;
+    const int32_t u = red ? c : c - nr;
+    const int32_t par = rb_par(f, u), pos = u % f.h;
+    // the other colour's cell of each entry, in the row's order
+    const int32_t o[6] = {u - f.H, u - f.h, red ? u + par - 1 : u - par, red ? u + par : u + 1 - par, u + f.h,
+                          u + f.H};
+    const bool xlo = red ? pos + par - 1 >= 0 : pos >= par;
+    const bool xhi = red ? pos + par <= f.h - 1 : pos + 1 - par <= f.h - 1;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        bool v = o[j] >= 0 && o[j] < nr;
+        if (j == 0 || j == 5) v = v && f.H > 0;
+        if (j == 2) v = v && xlo;
+        if (j == 3) v = v && xhi;
+        ok[j] = v;
+        const int32_t oc = v ? o[j] : u;
+        // red: own slot of direction j; black: the red neighbour's mirrored slot
+        slot[j] = static_cast<int64_t>(red ? j : 5 - j) * nr + (red ? u : oc);
+        col[j] = red ? nr + oc : oc;
+    }
+}
+
+// Both rows of half-index u (red cell u and black cell nr + u, neighbours in
+// x on the box): entries as rb_row gives them, the line's parity computed once.
+__device__ __forceinline__ void rb_pair(const RBForm &f, int32_t u, int64_t (&rslot)[6], int32_t (&rcol)[6],
+                                        bool (&rok)[6], int64_t (&bslot)[6], int32_t (&bcol)[6],
+                                        bool (&bok)[6]) {
+    const int32_t nr = f.nr;
+    const int32_t par = rb_par(f, u), pos = u % f.h;
+    const int32_t ro[6] = {u - f.H, u - f.h, u + par - 1, u + par, u + f.h, u + f.H};
+    const int32_t bo[6] = {u - f.H, u - f.h, u - par, u + 1 - par, u + f.h, u + f.H};
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        bool vr = ro[j] >= 0 && ro[j] < nr, vb = bo[j] >= 0 && bo[j] < nr;
+        if (j == 0 || j == 5) { vr = vr && f.H > 0; vb = vb && f.H > 0; }
+        if (j == 2) { vr = vr && pos + par - 1 >= 0; vb = vb && pos >= par; }
+        if (j == 3) { vr = vr && pos + par <= f.h - 1; vb = vb && pos + 1 - par <= f.h - 1; }
+        rok[j] = vr;
+        bok[j] = vb;
+        rslot[j] = static_cast<int64_t>(j) * nr + u;
+        rcol[j] = nr + (vr ? ro[j] : u);
+        const int32_t ob = vb ? bo[j] : u;
+        bslot[j] = static_cast<int64_t>(5 - j) * nr + ob;
+        bcol[j] = ob;
+    }
+}
+
 template <class T, class A>
 __device__ __forceinline__ A layout_dot(const SellLayout &L, int32_t c, const T *__restrict__ coef,
                                         const T *__restrict__ x, A acc) {
     return row_dot(L.mr, c, coef, x, acc);
+}
+
+template <class T, class A>
+__device__ __forceinline__ A layout_dot(const RBLayout &L, int32_t c, const T *__restrict__ coef,
+                                        const T *__restrict__ x, A acc) {
+    int64_t slot[6];
+    int32_t col[6];
+    bool ok[6];
+    rb_row(L.f, c, slot, col, ok);
+    T a[6], xv[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const T v = coef[slot[j]];
+        a[j] = ok[j] ? v : T(0);
+        xv[j] = x[col[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j) acc += a[j] * xv[j];
+    return acc;
 }
 
 // acc + sum over the row's entries (order above) of a_j x[col_j]
@@ -504,6 +589,11 @@ template <int K>
 struct RowCoefs<BandLayout<K>> {
     double a[2 * K];
 };
+template <>
+struct RowCoefs<RBLayout> {
+    double a[6];
+    int32_t col[6];
+};
 
 template <bool kUpper>
 __device__ __forceinline__ double assemble_coefs(const SellLayout &L, int32_t c, double DT,
@@ -546,6 +636,57 @@ __device__ __forceinline__ double assemble_coefs(const BandLayout<K> &L, int32_t
 #pragma unroll
     for (int k = 0; k < K; ++k) coef[static_cast<int64_t>(k) * L.n + c] = rc.a[K + k];
     return lap_diag;
+}
+
+// Two-colour band form: a red row computes and stores its six slots; a black
+// row computes its entries from the red neighbours' slot geometry (the same
+// factors, so the same values) and stores nothing.
+template <bool kUpper>
+__device__ __forceinline__ double assemble_coefs(const RBLayout &L, int32_t c, double DT,
+                                                 double *__restrict__ coef, double *__restrict__,
+                                                 RowCoefs<RBLayout> &rc) {
+    int64_t slot[6];
+    bool ok[6];
+    rb_row(L.f, c, slot, rc.col, ok);
+    double dl[6], ms[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const double d0 = L.delta[slot[j]], m0 = L.mag_sf[slot[j]];
+        dl[j] = ok[j] ? d0 : 0.0;
+        ms[j] = ok[j] ? m0 : 0.0;
+    }
+    double lap_diag = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const double lap_upper = dl[j] * (DT * ms[j]);
+        rc.a[j] = -lap_upper;
+        lap_diag -= lap_upper;
+    }
+    if (c < L.f.nr) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) coef[slot[j]] = rc.a[j];
+    }
+    return lap_diag;
+}
+
+__device__ __forceinline__ void row_amul_sum(const RBLayout &, int32_t, const double *__restrict__,
+                                             const RowCoefs<RBLayout> &rc, const double *__restrict__ x,
+                                             double &ax, double &sa) {
+    double xv[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) xv[j] = x[rc.col[j]];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        ax += rc.a[j] * xv[j];
+        sa += rc.a[j];
+    }
+}
+
+__device__ __forceinline__ void store_coef32(const RBLayout &L, int32_t c, const double *__restrict__,
+                                             const RowCoefs<RBLayout> &rc, float *__restrict__ coef32) {
+    if (c >= L.f.nr) return;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) coef32[static_cast<int64_t>(j) * L.f.nr + c] = static_cast<float>(rc.a[j]);
 }
 
 __device__ __forceinline__ void row_amul_sum(const SellLayout &L, int32_t c, const double *__restrict__ coef,

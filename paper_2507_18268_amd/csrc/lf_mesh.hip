@@ -265,6 +265,22 @@ __global__ void k_band_fill(int32_t F, int32_t N, BandOffsets bo, const int32_t 
     }
 }
 
+// two-colour band form: the geometry factors of face (u, nr + b) at slot
+// d * nr + u, d its direction (every face has one: checked on the host)
+__global__ void k_rb_fill(int32_t F, RBForm rf, const int32_t *__restrict__ owner,
+                          const int32_t *__restrict__ neighbour, const double *__restrict__ mag_sf,
+                          const double *__restrict__ delta, double *__restrict__ rb_mag_sf,
+                          double *__restrict__ rb_delta) {
+    int64_t f = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    const int32_t u = owner[f];
+    const int32_t d = rb_direction(rf, u, neighbour[f] - rf.nr);
+    if (d < 0) return;
+    const int64_t slot = static_cast<int64_t>(d) * rf.nr + u;
+    rb_mag_sf[slot] = mag_sf[f];
+    rb_delta[slot] = delta[f];
+}
+
 static inline unsigned blocks_for(int64_t n) {
     return static_cast<unsigned>((std::max<int64_t>(n, 1) + kBlock - 1) / kBlock);
 }
@@ -284,7 +300,7 @@ struct MeshScratch {
 };
 
 static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, int32_t K, bool reorder,
-                       bool grad, bool skew, lf_mesh *m, MeshScratch *s) {
+                       bool grad, bool skew, int32_t rb_nr, lf_mesh *m, MeshScratch *s) {
     size_t n1 = static_cast<size_t>(N) + 1;
     const int32_t ns = (N + kSlice - 1) / kSlice;
     auto *owner = cv.take<int32_t>(F);
@@ -323,6 +339,11 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, i
         band_mag = cv.take<double>(static_cast<size_t>(K) * N);
         band_delta = cv.take<double>(static_cast<size_t>(K) * N);
     }
+    double *rb_mag = nullptr, *rb_delta = nullptr;
+    if (rb_nr > 0) {
+        rb_mag = cv.take<double>(6 * static_cast<size_t>(rb_nr));
+        rb_delta = cv.take<double>(6 * static_cast<size_t>(rb_nr));
+    }
     double *gface = nullptr, *gband = nullptr, *gbface = nullptr, *gerec = nullptr, *gT = nullptr;
     double *gkface = nullptr, *gkerec = nullptr, *gkband = nullptr;
     if (grad) {
@@ -359,6 +380,7 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, i
         m->n_slices = ns; m->n_entries = E; m->soff = soff; m->scol = scol; m->sface = sface; m->rlen = rlen;
         m->V = V; m->mag_sf = mag_sf; m->delta = delta; m->bmag_sf = bmag; m->bdelta = bdelta;
         m->band_mag_sf = band_mag; m->band_delta = band_delta;
+        m->rb_mag_sf = rb_mag; m->rb_delta = rb_delta;
         m->perm = perm; m->iperm = iperm;
         m->emag_sf = emag; m->edelta = edelta;
         m->rbface_start = rbstart; m->rbface_list = rblist; m->rbface_cell = rbcell;
@@ -427,6 +449,57 @@ static BandOffsets plan_bands(const lf_mesh_desc *d) {
     bo.k = k;
     for (int32_t j = 0; j < k; ++j) bo.d[j] = v[j];
     return bo;
+}
+
+// Box form (see lf_mesh): the band offsets 1, nx, nx*ny with N = nx ny nz
+// (sides >= 2) and no face joining the end of an x-line or of an xy-plane to
+// the start of the next one.
+static void plan_box(const lf_mesh_desc *d, const BandOffsets &bo, int32_t dims[3]) {
+    dims[0] = dims[1] = dims[2] = 0;
+    const int32_t N = d->n_cells, F = d->n_faces;
+    if (bo.k != 3 || bo.d[0] != 1 || bo.d[1] < 2 || bo.d[2] % bo.d[1] != 0 || N % bo.d[2] != 0) return;
+    const int32_t nx = bo.d[1], ny = bo.d[2] / bo.d[1], nz = N / bo.d[2];
+    if (ny < 2 || nz < 2) return;
+    for (int32_t f = 0; f < F; ++f) {
+        const int32_t c = d->owner[f], off = d->neighbour[f] - c;
+        if (off == 1 && c % nx == nx - 1) return;
+        if (off == nx && (c / nx) % ny == ny - 1) return;
+    }
+    dims[0] = nx; dims[1] = ny; dims[2] = nz;
+}
+
+// Two-colour band form (see lf_mesh): a two-colour numbering with as many red
+// as black cells whose every face joins red cell u to black cell nr + b in
+// one of the six directions of the form.  The per-line count h and per-plane
+// count H are read off the offsets b - u of magnitude 2 or more (one
+// magnitude: h, no third direction; none: a single line); every face is then
+// checked against the form.  nr = 0 when the mesh does not have it.
+static RBForm plan_rb(const lf_mesh_desc *d, bool two_colour, int32_t n_red) {
+    RBForm none{0, 0, 0, 1};
+    const int32_t N = d->n_cells, F = d->n_faces;
+    if (!two_colour || F <= 0 || N % 2 != 0 || n_red != N / 2) return none;
+    const int32_t nr = n_red;
+    int64_t mags[2] = {0, 0};
+    int nm = 0;
+    for (int32_t f = 0; f < F; ++f) {
+        const int64_t off = static_cast<int64_t>(d->neighbour[f]) - nr - d->owner[f];
+        const int64_t a = off < 0 ? -off : off;
+        if (a < 2) continue;
+        if (nm > 0 && mags[0] == a) continue;
+        if (nm > 1 && mags[1] == a) continue;
+        if (nm == 2) return none;
+        mags[nm++] = a;
+    }
+    if (nm == 2 && mags[0] > mags[1]) std::swap(mags[0], mags[1]);
+    RBForm rf{nr, nm == 0 ? nr : static_cast<int32_t>(mags[0]), nm == 2 ? static_cast<int32_t>(mags[1]) : 0, 1};
+    if (rf.h < 2 || nr % rf.h != 0) return none;
+    if (rf.H > 0) {
+        if (rf.H % rf.h != 0 || nr % rf.H != 0) return none;
+        rf.ny = rf.H / rf.h;
+    }
+    for (int32_t f = 0; f < F; ++f)
+        if (rb_direction(rf, d->owner[f], d->neighbour[f] - nr) < 0) return none;
+    return rf;
 }
 
 // Cell order of the solver's arrays (see lf_mesh): for a mesh without band
@@ -605,12 +678,14 @@ size_t lf_mesh_workspace_bytes(const lf_mesh_desc *d) {
         max_owner = std::max(max_owner, d->owner[f]);
         min_nei = std::min(min_nei, d->neighbour[f]);
     }
-    const bool reorder = wants_cell_order(d, bo.k, d->n_faces > 0 && max_owner < min_nei);
+    const bool two_colour = d->n_faces > 0 && max_owner < min_nei;
+    const bool reorder = wants_cell_order(d, bo.k, two_colour);
+    const RBForm rf = plan_rb(d, two_colour, d->n_faces > 0 ? min_nei : d->n_cells);
     int64_t E = 0;
     if (plan_slices(d, nullptr, reorder, nullptr, &E) != LF_OK) return 0;
     Carver cv(nullptr);
     carve_mesh(cv, d->n_cells, d->n_faces, d->patch_start[d->n_patches], E, bo.k, reorder,
-               d->face_centre != nullptr, (d->flags & LF_MESH_NON_ORTHOGONAL) != 0, nullptr, nullptr);
+               d->face_centre != nullptr, (d->flags & LF_MESH_NON_ORTHOGONAL) != 0, rf.nr, nullptr, nullptr);
     return cv.bytes();
 }
 
@@ -624,6 +699,7 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
     const int32_t N = d->n_cells, F = d->n_faces, P = d->n_patches;
     const BandOffsets bo = plan_bands(d);
     const bool reorder = wants_cell_order(d, bo.k, two_colour);
+    const RBForm rf = plan_rb(d, two_colour, n_red);
     std::vector<int32_t> iperm_h;
     if (reorder) iperm_h = plan_cell_order(d);
     std::vector<int32_t> soff_h;
@@ -632,7 +708,7 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
     const bool grad = d->face_centre != nullptr;
     const bool skew = (d->flags & LF_MESH_NON_ORTHOGONAL) != 0;
     Carver dry(nullptr);
-    carve_mesh(dry, N, F, B, E, bo.k, reorder, grad, skew, nullptr, nullptr);
+    carve_mesh(dry, N, F, B, E, bo.k, reorder, grad, skew, rf.nr, nullptr, nullptr);
     if (!ws || ws_bytes < dry.bytes() || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) {
         set_error("mesh workspace too small or misaligned: need %zu bytes, 256-aligned", dry.bytes());
         return LF_ENOMEM;
@@ -650,7 +726,13 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
     if (hipGetDevice(&m->device) != hipSuccess) { delete m; set_error("hipGetDevice failed"); return LF_EDEVICE; }
     Carver cv(ws);
     MeshScratch sc;
-    carve_mesh(cv, N, F, B, E, bo.k, reorder, grad, skew, m, &sc);
+    carve_mesh(cv, N, F, B, E, bo.k, reorder, grad, skew, rf.nr, m, &sc);
+    if (rf.nr > 0) { m->rb_h = rf.h; m->rb_H = rf.H; m->rb_ny = rf.ny; }
+    {
+        int32_t dims[3];
+        plan_box(d, bo, dims);
+        m->box_nx = dims[0]; m->box_ny = dims[1]; m->box_nz = dims[2];
+    }
     m->orthogonal = (d->flags & LF_MESH_NON_ORTHOGONAL) == 0;
     hipStream_t s = m->stream;
 
@@ -743,6 +825,13 @@ lf_status lf_mesh_create(const lf_mesh_desc *d, void *ws, size_t ws_bytes, void 
         hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(slots)), dim3(kBlock), 0, s, m->band_delta, slots, 0.0);
         hipLaunchKernelGGL(k_band_fill, dim3(blocks_for(F)), dim3(kBlock), 0, s, F, N, bo, m->owner, m->neighbour,
                            m->mag_sf, m->delta, m->band_mag_sf, m->band_delta);
+    }
+    if (rf.nr > 0) {
+        const int64_t slots = 6 * static_cast<int64_t>(rf.nr);
+        hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(slots)), dim3(kBlock), 0, s, m->rb_mag_sf, slots, 0.0);
+        hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(slots)), dim3(kBlock), 0, s, m->rb_delta, slots, 0.0);
+        hipLaunchKernelGGL(k_rb_fill, dim3(blocks_for(F)), dim3(kBlock), 0, s, F, rf, m->owner, m->neighbour,
+                           m->mag_sf, m->delta, m->rb_mag_sf, m->rb_delta);
     }
     if (m->emag_sf)
         hipLaunchKernelGGL(k_entry_geometry, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, m->soff, m->sface,

@@ -86,6 +86,23 @@ __device__ __forceinline__ void scale_row(const SellLayout &L, int32_t c, double
         coef32[idx] = static_cast<float>(coef[idx] / (sc * static_cast<double>(sig32[L.mr.scol[idx]])));
 }
 
+// Two-colour band layout: a red row scales its six slots (the precision form
+// does not take DIC, so this serves only to complete the layout set)
+__device__ __forceinline__ void scale_row(const RBLayout &L, int32_t c, double sc,
+                                          const float *__restrict__ sig32, const double *__restrict__ coef,
+                                          float *__restrict__ coef32) {
+    if (c >= L.f.nr) return;
+    int64_t slot[6];
+    int32_t col[6];
+    bool ok[6];
+    rb_row(L.f, c, slot, col, ok);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const double sn = ok[j] ? static_cast<double>(sig32[col[j]]) : 1.0;
+        coef32[slot[j]] = static_cast<float>(coef[slot[j]] / (sc * sn));
+    }
+}
+
 template <class Lay>
 __global__ void __launch_bounds__(kCellBlock)
 k_mx_scale(SolverParams sp, Lay L, const float *__restrict__ sig32, const double *__restrict__ coef,

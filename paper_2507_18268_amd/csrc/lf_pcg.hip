@@ -8,6 +8,8 @@
 // convergence, singularity), so the cell-parallel kernels only read the state.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -431,6 +433,185 @@ k_dic_backward(SolverParams sp, MeshRows mr, const double *__restrict__ coef, co
 }
 
 // ---------------------------------------------------------------------------
+// The same DIC on the two-colour band layout: the same recurrences and term
+// order, entries from rb_row (absent faces skipped).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kCellBlock)
+k_dic_rd_rb(SolverParams sp, RBLayout L, const double *__restrict__ diagB, const double *__restrict__ coef,
+            double *__restrict__ rD) {
+    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+    if (c >= sp.n) return;
+    double d = diagB[c];
+    if (c >= sp.n_red) {
+        int64_t slot[6];
+        int32_t col[6];
+        bool ok[6];
+        rb_row(L.f, c, slot, col, ok);
+        double a[6], dg[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            a[j] = coef[slot[j]];
+            dg[j] = diagB[col[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            if (ok[j]) d -= a[j] * a[j] / dg[j];
+    }
+    rD[c] = 1.0 / d;
+}
+
+__global__ void __launch_bounds__(kCellBlock)
+k_dic_forward_rb(SolverParams sp, RBLayout L, const double *__restrict__ coef, const double *__restrict__ rD,
+                 const double *__restrict__ r, double *__restrict__ w, const PcgState *__restrict__ st) {
+    if (st->done) return;
+    const int32_t c = sp.n_red + static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+    if (c >= sp.n) return;
+    const double rd = rD[c];
+    double wc = rd * r[c];
+    int64_t slot[6];
+    int32_t col[6];
+    bool ok[6];
+    rb_row(L.f, c, slot, col, ok);
+    double a[6], ro[6], rdo[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        a[j] = coef[slot[j]];
+        rdo[j] = rD[col[j]];
+        ro[j] = r[col[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+        if (ok[j]) wc -= rd * a[j] * (rdo[j] * ro[j]);
+    w[c] = wc;
+}
+
+// backward sweep on red rows; every row contributes its w.r partial
+__global__ void __launch_bounds__(kCellBlock)
+k_dic_backward_rb(SolverParams sp, RBLayout L, const double *__restrict__ coef, const double *__restrict__ rD,
+                  const double *__restrict__ r, double *__restrict__ w, double *__restrict__ part,
+                  const PcgState *__restrict__ st) {
+    if (st->done) return;
+    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+    double acc[1] = {0.0};
+    if (c < sp.n) {
+        const double rc = r[c];
+        double wc;
+        if (c < sp.n_red) {
+            const double rd = rD[c];
+            wc = rd * rc;
+            int64_t slot[6];
+            int32_t col[6];
+            bool ok[6];
+            rb_row(L.f, c, slot, col, ok);
+            double a[6], wo[6];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                a[j] = coef[slot[j]];
+                wo[j] = w[col[j]];
+            }
+#pragma unroll
+            for (int j = 5; j >= 0; --j)
+                if (ok[j]) wc -= rd * a[j] * wo[j];
+            w[c] = wc;
+        } else {
+            wc = w[c];
+        }
+        acc[0] = wc * rc;
+    }
+    const int slots[1] = {kPartWr};
+    write_partials<1>(part, sp.grid, slots, acc);
+}
+
+// q = A p on the two-colour band layout, one thread per half-index u taking
+// the red row u and the black row nr + u (x-neighbours on the box, so the
+// coefficients a black row gathers from its red neighbours' slots are read
+// near the time the red rows read them); partial sums of p.q over the pairs
+// (sp.grid_amul workgroups)
+__global__ void __launch_bounds__(kCellBlock)
+k_amul_dot_rb(SolverParams sp, RBLayout L, const double *__restrict__ diagB, const double *__restrict__ coef,
+              const double *__restrict__ p, double *__restrict__ q, double *__restrict__ part,
+              const PcgState *__restrict__ st) {
+    if (st->done) return;
+    const int32_t nr = L.f.nr;
+    const int32_t u = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+    double acc[1] = {0.0};
+    if (u < nr) {
+        int64_t rs[6], bs[6];
+        int32_t rc[6], bc[6];
+        bool rok[6], bok[6];
+        rb_pair(L.f, u, rs, rc, rok, bs, bc, bok);
+        double ra[6], rx[6], ba[6], bx[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const double v = coef[rs[j]], w = coef[bs[j]];
+            ra[j] = rok[j] ? v : 0.0;
+            ba[j] = bok[j] ? w : 0.0;
+            rx[j] = p[rc[j]];
+            bx[j] = p[bc[j]];
+        }
+        const double pr = p[u], pb = p[nr + u];
+        double qr = __builtin_nontemporal_load(&diagB[u]) * pr;
+        double qb = __builtin_nontemporal_load(&diagB[nr + u]) * pb;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            qr += ra[j] * rx[j];
+            qb += ba[j] * bx[j];
+        }
+        __builtin_nontemporal_store(qr, &q[u]);
+        __builtin_nontemporal_store(qb, &q[nr + u]);
+        acc[0] = qr * pr + qb * pb;
+    }
+    const int slots[1] = {kPartPq};
+    write_partials<1>(part, sp.grid, slots, acc);
+}
+
+// backward sweep on the red rows, one thread per half-index u (red row u),
+// with the w.r partial sums of the red row and of the black row nr + u (its
+// w from the forward sweep); sp.grid_amul workgroups (the slot's further
+// partials hold the zeros the update wrote)
+__global__ void __launch_bounds__(kCellBlock)
+k_dic_backward_rb_pair(SolverParams sp, RBLayout L, const double *__restrict__ coef,
+                       const double *__restrict__ rD, const double *__restrict__ r, double *__restrict__ w,
+                       double *__restrict__ part, const PcgState *__restrict__ st) {
+    if (st->done) return;
+    const int32_t nr = L.f.nr;
+    const int32_t u = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+    double acc[1] = {0.0};
+    if (u < nr) {
+        int64_t slot[6];
+        int32_t col[6];
+        bool ok[6];
+        rb_row(L.f, u, slot, col, ok);
+        double a[6], wo[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            a[j] = coef[slot[j]];
+            wo[j] = w[col[j]];
+        }
+        const double rd = rD[u], rc = r[u];
+        double wc = rd * rc;
+#pragma unroll
+        for (int j = 5; j >= 0; --j)
+            if (ok[j]) wc -= rd * a[j] * wo[j];
+        w[u] = wc;
+        acc[0] = wc * rc + w[nr + u] * r[nr + u];
+    }
+    const int slots[1] = {kPartWr};
+    write_partials<1>(part, sp.grid, slots, acc);
+}
+
+// face-order copy of the two-colour band coefficients: upper_f at its slot
+__global__ void __launch_bounds__(kCellBlock)
+k_rb_upper(int32_t F, RBForm rf, const int32_t *__restrict__ owner, const int32_t *__restrict__ neighbour,
+           const double *__restrict__ coef, double *__restrict__ upper) {
+    const int64_t f = static_cast<int64_t>(blockIdx.x) * kCellBlock + threadIdx.x;
+    if (f >= F) return;
+    const int32_t u = owner[f];
+    const int32_t d = rb_direction(rf, u, neighbour[f] - rf.nr);
+    if (d >= 0) upper[f] = coef[static_cast<int64_t>(d) * rf.nr + u];
+}
+
+// ---------------------------------------------------------------------------
 // One-workgroup reductions and the solver's scalar decisions (READING:
 // OpenFOAM's PCG semantics):
 //  kFinMean:  mean of x0; resets the state.
@@ -506,6 +687,44 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(SolverParams sp, const d
                 st->alpha = st->wArA / pq;
             }
         }
+    } else if (Mode == kFinConv) {
+        // the iteration's convergence decision from the update's |r| partials
+        // alone (the multigrid cycle, which forms w, runs only if the solve
+        // goes on)
+        if (st->done) return;
+        double v[1];
+        const int slots[1] = {kPartSumR};
+        reduce_partials<1>(part, G, sp.grid_upd, slots, v);
+        if (threadIdx.x == 0) {
+            const double res = v[0] / st->nf;
+            const int32_t k = st->n_iter + 1;
+            st->n_iter = k;
+            const bool conv = (k < sp.max_iter) ? check_conv(res, st->res0, sp.tol, sp.rel_tol)
+                                                : (st->converged != 0);
+            const bool cont = (k < sp.max_iter && !conv) || k < sp.min_iter;
+            st->res = res;
+            st->converged = conv ? 1 : 0;
+            if (!isfinite(res)) {
+                st->nonfinite = 1;
+                st->done = 1;
+            } else if (!cont) {
+                st->done = 1;
+            }
+        }
+    } else if (Mode == kFinBetaOnly) {
+        if (st->done) return;
+        double v[1];
+        const int slots[1] = {kPartWr};
+        reduce_partials<1>(part, G, sp.grid, slots, v);
+        if (threadIdx.x == 0) {
+            if (!isfinite(v[0])) {
+                st->nonfinite = 1;
+                st->done = 1;
+            } else {
+                st->beta = v[0] / st->wArA;
+                st->wArA = v[0];
+            }
+        }
     } else {
         if (st->done) return;
         double v[2];
@@ -550,6 +769,19 @@ __global__ void k_any_nonfinite(const double *__restrict__ a, int32_t n, PcgStat
 
 __global__ void k_clear_flag(PcgState *st) { st->flag = 0; }
 
+// test hook: the solver state "not done", so that the preconditioner's kernels run
+__global__ void k_clear_done(PcgState *st) { st->done = 0; }
+
+// diagonal preconditioner as the solve applies it: w = (1/diag) r
+__global__ void __launch_bounds__(kCellBlock)
+k_diag_apply(int32_t n, const double *__restrict__ diagB, const double *__restrict__ r, double *__restrict__ w) {
+    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+    if (c < n) {
+        const double rd = 1.0 / diagB[c];
+        w[c] = rd * r[c];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -561,7 +793,7 @@ void carve_problem(Carver &cv, const lf_mesh *m, const lf_solver_opts &o, lf_pro
     double *vec[11];
     for (auto &v : vec) v = cv.take<double>(N);
     auto *upper = cv.take<double>(F);
-    auto *coef = cv.take<double>(coef_slots(m, use_bands(m, o)));
+    auto *coef = cv.take<double>(coef_slots(m, use_bands(m, o), use_rb(m, o)));
     auto *ic = cv.take<double>(B);
     auto *bc = cv.take<double>(B);
     auto *tb = cv.take<double>(B);
@@ -583,6 +815,7 @@ void carve_problem(Carver &cv, const lf_mesh *m, const lf_solver_opts &o, lf_pro
         P->state = state;
     }
     if (o.precision == LF_PREC_MIXED) carve_mixed(cv, m, use_bands(m, o), P);
+    if (o.precond == LF_PC_AMG) carve_amg(cv, m, P);
 }
 
 MeshRows mesh_rows(const lf_mesh *m) { return MeshRows{m->soff, m->scol, m->sface, m->rlen}; }
@@ -602,6 +835,9 @@ static void launch_assemble_t(lf_problem *P, hipStream_t s) {
                   P->r32, P->d32, P->p, P->nonorth ? P->lap_src : nullptr,
                   kSetup && P->nonorth && P->opts.n_nonorth_corr > 0 ? P->T_old : nullptr);
     });
+    if (kFull && P->rb && m->F > 0)
+        hipLaunchKernelGGL(k_rb_upper, dim3(static_cast<unsigned>((m->F + kCellBlock - 1) / kCellBlock)),
+                           dim3(kCellBlock), 0, s, m->F, rb_form(m), m->owner, m->neighbour, P->coef, P->upper);
     if (kFull && P->banded && m->F > 0) {
         BandOffsets bo{};
         bo.k = m->n_bands;
@@ -648,18 +884,41 @@ static void launch_direction(lf_problem *P, hipStream_t s) {
 
 template void launch_fin<kFinStart>(lf_problem *P, hipStream_t s);
 
+// DIC sweeps w = M^-1 r (forward on the black rows, then backward on the red
+// rows with the w.r partials of all rows)
+static void launch_dic_sweeps(lf_problem *P, hipStream_t s) {
+    const lf_mesh *m = P->mesh;
+    if (P->rb) {
+        const int32_t nb = m->N - m->n_red;
+        const dim3 gb(static_cast<unsigned>(std::max<int32_t>(1, (nb + kCellBlock - 1) / kCellBlock)));
+        LF_LAUNCH(P, LF_K_DIC_FORWARD, s, k_dic_forward_rb, gb, dim3(kCellBlock), 0, s, P->sp, rb_layout(m),
+                  P->coef, P->rD, P->r, P->w, P->state);
+        LF_LAUNCH(P, LF_K_DIC_BACKWARD, s, k_dic_backward_rb_pair, gb, dim3(kCellBlock), 0, s, P->sp,
+                  rb_layout(m), P->coef, P->rD, P->r, P->w, P->part, P->state);
+        return;
+    }
+    LF_LAUNCH(P, LF_K_DIC_FORWARD, s, k_dic_forward, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, mesh_rows(m),
+              P->coef, P->rD, P->r, P->w, P->state);
+    LF_LAUNCH(P, LF_K_DIC_BACKWARD, s, k_dic_backward, cell_grid(P), dim3(kCellBlock), 0, s, P->sp,
+              mesh_rows(m), P->coef, P->rD, P->r, P->w, P->part, P->state);
+}
+
 // after the fused assembly/setup kernel: preconditioner set-up (DIC), initial
 // residual and convergence decision, first direction
 static lf_status launch_setup(lf_problem *P, hipStream_t s) {
     const lf_mesh *m = P->mesh;
     const bool diag_pc = P->opts.precond == LF_PC_DIAGONAL;
-    if (!diag_pc) {
-        LF_LAUNCH(P, LF_K_DIC_RD, s, k_dic_rd, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, mesh_rows(m), P->diagB,
-                  P->coef, P->rD);
-        LF_LAUNCH(P, LF_K_DIC_FORWARD, s, k_dic_forward, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, mesh_rows(m),
-                  P->coef, P->rD, P->r, P->w, P->state);
-        LF_LAUNCH(P, LF_K_DIC_BACKWARD, s, k_dic_backward, cell_grid(P), dim3(kCellBlock), 0, s, P->sp,
-                  mesh_rows(m), P->coef, P->rD, P->r, P->w, P->part, P->state);
+    if (P->opts.precond == LF_PC_AMG) {
+        launch_amg_galerkin(P, s);
+        launch_amg_cycle(P, s);
+    } else if (!diag_pc) {
+        if (P->rb)
+            LF_LAUNCH(P, LF_K_DIC_RD, s, k_dic_rd_rb, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, rb_layout(m),
+                      P->diagB, P->coef, P->rD);
+        else
+            LF_LAUNCH(P, LF_K_DIC_RD, s, k_dic_rd, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, mesh_rows(m),
+                      P->diagB, P->coef, P->rD);
+        launch_dic_sweeps(P, s);
     }
     launch_fin<kFinStart>(P, s);
     // first direction p = w: with the diagonal preconditioner the assembly
@@ -673,7 +932,6 @@ static lf_status launch_setup(lf_problem *P, hipStream_t s) {
 // (DIC sweeps), convergence decision and beta, next direction (with the
 // deferred x update)
 static lf_status launch_iteration(lf_problem *P, hipStream_t s) {
-    const lf_mesh *m = P->mesh;
     const bool diag_pc = P->opts.precond == LF_PC_DIAGONAL;
     with_layout(P, [&](auto lay) {
         constexpr int K = WalkBands<decltype(lay)>::value;
@@ -683,6 +941,11 @@ static lf_status launch_iteration(lf_problem *P, hipStream_t s) {
                           dim3(kCellBlock), 0, s, P->sp, lay, P->diagB, P->coef, P->p, P->q, P->part, P->state);
                 return;
             }
+        }
+        if constexpr (std::is_same_v<decltype(lay), RBLayout>) {
+            LF_LAUNCH(P, LF_K_AMUL_DOT, s, k_amul_dot_rb, dim3(static_cast<unsigned>(P->sp.grid_amul)),
+                      dim3(kCellBlock), 0, s, P->sp, lay, P->diagB, P->coef, P->p, P->q, P->part, P->state);
+            return;
         }
         LF_LAUNCH(P, LF_K_AMUL_DOT, s, k_amul_dot<decltype(lay)>, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, lay,
                   P->diagB, P->coef, P->p, P->q, P->part, P->state);
@@ -695,10 +958,15 @@ static lf_status launch_iteration(lf_problem *P, hipStream_t s) {
     } else {
         LF_LAUNCH(P, LF_K_UPDATE, s, k_update<false>, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->q, P->r,
                   P->rD, P->part, P->state);
-        LF_LAUNCH(P, LF_K_DIC_FORWARD, s, k_dic_forward, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, mesh_rows(m),
-                  P->coef, P->rD, P->r, P->w, P->state);
-        LF_LAUNCH(P, LF_K_DIC_BACKWARD, s, k_dic_backward, cell_grid(P), dim3(kCellBlock), 0, s, P->sp,
-                  mesh_rows(m), P->coef, P->rD, P->r, P->w, P->part, P->state);
+        if (P->opts.precond == LF_PC_AMG) {
+            launch_fin<kFinConv>(P, s);
+            launch_amg_cycle(P, s);
+            launch_fin<kFinBetaOnly>(P, s);
+            launch_direction(P, s);
+            LF_HIP(hipGetLastError());
+            return LF_OK;
+        }
+        launch_dic_sweeps(P, s);
     }
     launch_fin<kFinBeta>(P, s);
     launch_direction(P, s);
@@ -817,6 +1085,31 @@ lf_status fp64_advance(lf_problem *P, SolveCtx &c, bool *finished, lf_solve_stat
     }
     if (c.fixed_k <= 0) c.k = std::max<int32_t>(2, c.k / 2);
     return fp64_block(P, c);
+}
+
+// w = M r with the last assembled matrix (P->r to P->w, solver order): the
+// preconditioner's set-up (DIC diagonal, multigrid coarse matrices) and one
+// application
+lf_status launch_precondition_hook(lf_problem *P) {
+    const lf_mesh *m = P->mesh;
+    hipStream_t s = P->stream;
+    hipLaunchKernelGGL(k_clear_done, dim3(1), dim3(1), 0, s, P->state);
+    if (P->opts.precond == LF_PC_DIAGONAL) {
+        hipLaunchKernelGGL(k_diag_apply, cell_grid(P), dim3(kCellBlock), 0, s, m->N, P->diagB, P->r, P->w);
+    } else if (P->opts.precond == LF_PC_AMG) {
+        launch_amg_galerkin(P, s);
+        launch_amg_cycle(P, s);
+    } else {
+        if (P->rb)
+            hipLaunchKernelGGL(k_dic_rd_rb, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, rb_layout(m), P->diagB,
+                               P->coef, P->rD);
+        else
+            hipLaunchKernelGGL(k_dic_rd, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, mesh_rows(m), P->diagB,
+                               P->coef, P->rD);
+        launch_dic_sweeps(P, s);
+    }
+    LF_HIP(hipGetLastError());
+    return LF_OK;
 }
 
 lf_status launch_amul_hook(lf_problem *P, const double *x, double *y) {

@@ -66,7 +66,20 @@ struct SolverParams {
 
 }  // namespace lf
 
-namespace lf { struct StepDriver; }
+namespace lf {
+struct StepDriver;
+
+// One coarse level of the multigrid preconditioner: a box of nx x ny x nz
+// cells numbered i + nx (j + ny k) whose matrix is kept in the band layout
+// (offsets 1, nx, nx*ny; slot k*n + c holds the face (c, c + d_k), 0 where
+// there is none); b its right side, xa and xb its iterates.
+struct AmgLevel {
+    int32_t n = 0, nx = 0, ny = 0, nz = 0;
+    double *coef = nullptr;      // [3n]
+    double *diag = nullptr;      // [n]
+    double *b = nullptr, *xa = nullptr, *xb = nullptr;   // [n]
+};
+}  // namespace lf
 
 struct lf_problem {
     const lf_mesh *mesh = nullptr;
@@ -83,7 +96,12 @@ struct lf_problem {
     double *r = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr, *w = nullptr, *rD = nullptr;
     double *diag = nullptr, *source = nullptr, *diagB = nullptr, *srcB = nullptr;
     bool banded = false;                       // coefficients in the band layout
+    bool rb = false;                           // coefficients in the two-colour band layout (DIC)
     bool walk = false;                         // FP64 Amul by the row walk (bands >= 2, large meshes)
+    // multigrid preconditioner: coarse levels 1.. (level 0 is the problem's own
+    // band matrix) and two work vectors of level 0
+    std::vector<lf::AmgLevel> amg;
+    double *amg_t1 = nullptr, *amg_t2 = nullptr;   // [N]
     double *upper = nullptr;                   // [F] face order (test hook copy)
     double *coef = nullptr;                    // [n_entries] row layout or [n_bands N] bands
     double *int_coeff = nullptr, *bou_coeff = nullptr;

@@ -18,22 +18,31 @@ inline int32_t update_blocks(int32_t n) {
     return n > 0 ? (n + kTile - 1) / kTile : 1;
 }
 
-enum FinMode : int { kFinMean = 0, kFinStart = 1, kFinAlpha = 2, kFinBeta = 3 };
+enum FinMode : int { kFinMean = 0, kFinStart = 1, kFinAlpha = 2, kFinBeta = 3, kFinConv = 4, kFinBetaOnly = 5 };
 template <int Mode>
 void launch_fin(lf_problem *P, hipStream_t s);
 
 MeshRows mesh_rows(const lf_mesh *m);
 
-// Which coefficient layout a problem uses (LF_LAYOUT_BANDS needs the band
-// form and the diagonal preconditioner; lf_problem_create checks that).
+// Which coefficient layout a problem uses: the band layout for the diagonal
+// preconditioner on a mesh with band form, the two-colour band layout for DIC
+// on a mesh with that form (LF_LAYOUT_BANDS asks for one of them;
+// lf_problem_create checks that it applies), else the sliced rows.
 inline bool use_bands(const lf_mesh *m, const lf_solver_opts &o) {
-    if (o.layout == LF_LAYOUT_ROWS || m->n_bands == 0 || o.precond != LF_PC_DIAGONAL) return false;
+    if (o.layout == LF_LAYOUT_ROWS || m->n_bands == 0 || o.precond == LF_PC_DIC) return false;
     return true;
 }
+inline bool use_rb(const lf_mesh *m, const lf_solver_opts &o) {
+    return o.layout != LF_LAYOUT_ROWS && m->rb_h > 0 && o.precond == LF_PC_DIC;
+}
 // coefficient slots of a problem's layout
-inline size_t coef_slots(const lf_mesh *m, bool banded) {
+inline size_t coef_slots(const lf_mesh *m, bool banded, bool rb = false) {
+    if (rb) return 6 * static_cast<size_t>(m->n_red);
     return banded ? static_cast<size_t>(m->n_bands) * m->N : static_cast<size_t>(m->n_entries);
 }
+
+inline RBForm rb_form(const lf_mesh *m) { return RBForm{m->n_red, m->rb_h, m->rb_H, m->rb_ny}; }
+inline RBLayout rb_layout(const lf_mesh *m) { return RBLayout{rb_form(m), m->rb_mag_sf, m->rb_delta}; }
 
 inline SellLayout sell_layout(const lf_mesh *m) {
     return SellLayout{mesh_rows(m), m->mag_sf, m->delta, m->emag_sf, m->edelta};
@@ -54,6 +63,10 @@ inline BandLayout<K> band_layout(const lf_mesh *m) {
 template <class Fn>
 inline void with_layout(const lf_problem *P, Fn &&fn) {
     const lf_mesh *m = P->mesh;
+    if (P->rb) {
+        fn(rb_layout(m));
+        return;
+    }
     if (!P->banded) {
         fn(sell_layout(m));
         return;
@@ -66,6 +79,11 @@ inline void with_layout(const lf_problem *P, Fn &&fn) {
     }
 }
 void carve_problem(Carver &cv, const lf_mesh *m, const lf_solver_opts &o, lf_problem *P);
+// multigrid preconditioner (lf_amg.hip): work space, coarse matrices (after
+// each assembly), one cycle w = M r with the w.r partials
+void carve_amg(Carver &cv, const lf_mesh *m, lf_problem *P);
+void launch_amg_galerkin(lf_problem *P, hipStream_t s);
+void launch_amg_cycle(lf_problem *P, hipStream_t s);
 void carve_mixed(Carver &cv, const lf_mesh *m, bool banded, lf_problem *P);
 lf_status launch_assemble(lf_problem *P, bool full, hipStream_t s);
 lf_status launch_assemble_setup(lf_problem *P, hipStream_t s);
@@ -93,6 +111,7 @@ lf_status fp64_advance(lf_problem *P, SolveCtx &c, bool *finished, lf_solve_stat
 lf_status mixed_start(lf_problem *P, SolveCtx &c);
 lf_status mixed_advance(lf_problem *P, SolveCtx &c, bool *finished, lf_solve_stats *out);
 lf_status launch_amul_hook(lf_problem *P, const double *x, double *y);
+lf_status launch_precondition_hook(lf_problem *P);
 lf_status check_finite_device(lf_problem *P, const double *T, bool *ok);
 
 }  // namespace lf

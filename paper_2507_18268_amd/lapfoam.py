@@ -25,6 +25,7 @@ LF_BC_ZERO_GRADIENT = 0
 LF_BC_FIXED_VALUE = 1
 LF_PC_DIAGONAL = 0
 LF_PC_DIC = 1
+LF_PC_AMG = 2
 LF_PREC_FP64 = 0
 LF_PREC_MIXED = 1
 LF_LAYOUT_AUTO = 0
@@ -118,13 +119,15 @@ _SIGS = {
     "lf_batch_poll": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32)]),
     "lf_batch_wait": (C.c_int32, [C.c_void_p]),
     "lf_batch_stats": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "lf_precondition": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lf_profile_enable": (C.c_int32, [C.c_void_p, C.c_int32]),
     "lf_profile_read": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
 }
 
 KERNEL_CLASSES = ["assemble", "sum_x", "commit", "direction", "amul_dot", "update", "dic_rd",
                   "dic_forward", "dic_backward", "mixed_residual", "mixed_correct",
-                  "inner_direction", "inner_amul_dot", "inner_update", "mixed_prep", "finalize"]
+                  "inner_direction", "inner_amul_dot", "inner_update", "mixed_prep", "finalize",
+                  "amg_smooth", "amg_restrict", "amg_prolong", "amg_galerkin"]
 
 
 def lib():
@@ -305,6 +308,10 @@ def lf_problem_grad(h, grad_ptr, bgrad_ptr):
 
 def lf_amul(h, x_ptr, y_ptr):
     _check(lib().lf_amul(h, C.c_void_p(x_ptr), C.c_void_p(y_ptr)), "lf_amul")
+
+
+def lf_precondition(h, r_ptr, w_ptr):
+    _check(lib().lf_precondition(h, C.c_void_p(r_ptr), C.c_void_p(w_ptr)), "lf_precondition")
 
 
 def lf_profile_enable(h, on):
@@ -592,6 +599,10 @@ class Problem:
     def amul(self, x, y):
         lf_amul(self.h, x.data_ptr(), y.data_ptr())
 
+    def precondition(self, r, w):
+        """w = M r with the problem's preconditioner (device float64 tensors)."""
+        lf_precondition(self.h, r.data_ptr(), w.data_ptr())
+
     def profile(self, on=True):
         lf_profile_enable(self.h, on)
 
@@ -650,3 +661,4 @@ class Batch:
             self.close()
         except Exception:
             pass
+

@@ -251,6 +251,30 @@ def from_arrays(cell_centre, cell_volume, faces, patches) -> BoxMesh:
         bface_area=f3([b[1] for b in bf]), bface_centre=f3([b[2] for b in bf]))
 
 
+def box_aggregation(shape, coarsest: int = 512, min_side: int = 3):
+    """Aggregation hierarchy of a box numbered c = i + nx (j + ny k): each level's
+    cells grouped in 2 x 2 x 2 blocks (a direction of odd length ends with a
+    block of one cell in it), coarse cells numbered the same way on the halved
+    box.  Levels are added while the current one has more than `coarsest`
+    cells and every side is at least `min_side` long (so that with the default
+    3 every level stays a box of sides 2 or more).  Returns (level_cells,
+    aggs): cells per level, and per level but the last the coarse cell of each
+    of its cells."""
+    nx, ny, nz = (int(v) for v in shape)
+    cells = [nx * ny * nz]
+    aggs = []
+    while cells[-1] > coarsest and min(nx, ny, nz) >= min_side and max(nx, ny, nz) > 1:
+        cx, cy, cz = (nx + 1) // 2, (ny + 1) // 2, (nz + 1) // 2
+        i = np.arange(nx) // 2
+        j = np.arange(ny) // 2
+        k = np.arange(nz) // 2
+        agg = (i[None, None, :] + cx * (j[None, :, None] + cy * k[:, None, None])).ravel()
+        aggs.append(agg.astype(np.int32))
+        nx, ny, nz = cx, cy, cz
+        cells.append(nx * ny * nz)
+    return cells, aggs
+
+
 def random_permutation(n: int, seed: int) -> np.ndarray:
     """new_of_old for a seeded random relabelling: cells ranked by SplitMix64 keys."""
     keys = splitmix64(seed, n)

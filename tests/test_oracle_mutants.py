@@ -9,14 +9,17 @@ import ctypes
 import os
 import subprocess
 
+import numpy as np
 import pytest
 
 from oracle import build as obuild
 from oracle import oracle as O
+from tests import test_oracle_amg as M
 from tests import test_oracle_geometry as G
 
 SRC = os.path.join(os.path.dirname(obuild.__file__), "lforacle.c")
 
+# (name, text in the oracle's source, its replacement); the face-factor pins
 MUTANTS = [
     ("delta_f over |d|", "delta[f] = 1.0 / (nd > lim ? nd : lim);", "delta[f] = 1.0 / dmag;"),
     ("delta_f without limiter", "delta[f] = 1.0 / (nd > lim ? nd : lim);", "delta[f] = 1.0 / nd;"),
@@ -32,6 +35,20 @@ MUTANTS = [
      "double lap_bc = -(gamma_b * patch_value[p]);"),
 ]
 
+# the same for the multigrid pins
+AMG_MUTANTS = [
+    ("restriction averages", "bc[L->agg[c]] += y[c];", "bc[L->agg[c]] += 0.125 * y[c];"),
+    ("prolongation dropped", "x[c] += xc[L->agg[c]];", "x[c] += 0.0 * xc[L->agg[c]];"),
+    ("internal face counted once", "cdiag[I] += 2.0 * upper[f];", "cdiag[I] += upper[f];"),
+    ("coarse face keeps one fine face", "cupper[k] += upper[pairs[i].f];", "cupper[k] = upper[pairs[i].f];"),
+    ("Jacobi without the diagonal", "x[c] = x[c] + omega * ((b[c] - y[c]) / L->diag[c]);",
+     "x[c] = x[c] + omega * (b[c] - y[c]);"),
+    ("no smoothing after the correction",
+     "x[c] += xc[L->agg[c]];\n        for (int32_t s = 0; s < h->nu; ++s)",
+     "x[c] += xc[L->agg[c]];\n        for (int32_t s = 0; s < 0; ++s)"),
+    ("coarse right side from b, not the residual", "bc[L->agg[c]] += y[c];", "bc[L->agg[c]] += b[c];"),
+]
+
 
 def _build(tmp_path, old, new):
     src = open(SRC).read()
@@ -43,19 +60,28 @@ def _build(tmp_path, old, new):
     return ctypes.CDLL(str(lib))
 
 
-@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_planted_slip_fails_a_pin(tmp_path, name, old, new):
+def _failing_pins(tmp_path, old, new, pins):
     O.lib()
     mutant = _build(tmp_path, old, new)
     saved = O._lib
     failed = []
     try:
         O._lib = mutant
-        for pin in G.PINS:
+        for pin in pins:
             try:
                 pin(O)
-            except AssertionError:
+            except (AssertionError, np.linalg.LinAlgError):
                 failed.append(pin.__name__)
     finally:
         O._lib = saved
-    assert failed, f"no pin caught the planted slip '{name}'"
+    return failed
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_slip_fails_a_pin(tmp_path, name, old, new):
+    assert _failing_pins(tmp_path, old, new, G.PINS), f"no pin caught the planted slip '{name}'"
+
+
+@pytest.mark.parametrize("name,old,new", AMG_MUTANTS, ids=[m[0] for m in AMG_MUTANTS])
+def test_planted_multigrid_slip_fails_a_pin(tmp_path, name, old, new):
+    assert _failing_pins(tmp_path, old, new, M.PINS), f"no pin caught the planted slip '{name}'"
