@@ -181,7 +181,7 @@ def run_mixed(L, torch, p, mesh, prob64, T0, args):
         e_mt.append(float(((a - t).abs() / t.abs()).max()))
         e_ft.append(float(((b - t).abs() / t.abs()).max()))
     banded = pm.layout() == L.LF_LAYOUT_BANDS
-    walk = pm.amul_walk()
+    walk = pm.amul_form()
     pref.close()
     pm.close()
     kernels = {k: {"avg_us": 1e3 * ms / n, "launches": n} for k, (ms, n) in prof.items()}
@@ -243,7 +243,7 @@ def mixed_roofline(kernels, n_cells, n_faces, banded, walk):
     d = table[dom]
     kname = {"inner_amul_dot": "k_mx_amul_dot_walk" if walk else "k_mx_amul_dot",
              "inner_update": "k_mx_update", "inner_direction": "k_mx_direction",
-             "mixed_residual": "k_mx_residual_walk" if walk else "k_mx_residual",
+             "mixed_residual": {0: "k_mx_residual", 1: "k_mx_residual_walk", 2: "k_mx_residual_box"}[walk],
              "mixed_prep": "k_mx_scale", "mixed_correct": "k_mx_correct"}[dom]
     roof = {"kernel": kname, "bound": "hbm", "achieved": d["GBps"], "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": d["frac"], "traffic": None,
@@ -607,9 +607,10 @@ def main():
     T0 = torch.from_numpy(p.T0).cuda()
     torch.cuda.synchronize()
     layout_name = "bands" if prob.layout() == L.LF_LAYOUT_BANDS else "rows"
-    walk = prob.amul_walk()
+    walk = prob.amul_form()
+    amul_form = {0: "one row per thread", 1: "row walk", 2: "block walk of the box"}[walk]
     log(f"[bench] device mesh + problem ready in {time.perf_counter() - t:.1f} s "
-        f"(workspaces {mesh.ws_bytes / 2**30:.2f} + {prob.ws_bytes / 2**30:.2f} GiB, {layout_name} layout{', row-walk Amul' if walk else ''})")
+        f"(workspaces {mesh.ws_bytes / 2**30:.2f} + {prob.ws_bytes / 2**30:.2f} GiB, {layout_name} layout{', Amul by the ' + amul_form if walk else ''})")
 
     prob.set_T(T0)
     if args.warmup > 0:
@@ -639,7 +640,7 @@ def main():
                                f"{synth.CONFIGS[args.config]['z_ratio']}, DT={p.DT}, dt={p.dt}, "
                                f"implicit Euler, PCG {p.precond}, tol {synth.TOL}",
                    "n_cells": N, "n_faces": F, "precision": p.precision, "layout": layout_name,
-                   "amul": "row walk" if walk else "one row per thread"},
+                   "amul": amul_form},
         "iters_per_step_mean": total_iters / len(stats),
         "solver_only_cell_iters_per_s": N * total_iters / solve_s if solve_s > 0 else None,
         "assemble_ms_mean": sum(s["assemble_ms"] for s in stats) / len(stats),
@@ -663,7 +664,7 @@ def main():
         # neighbours are implicit (c + d_k), so no face addresses
         per_launch = amul_bytes(N, F, addressed=(layout_name != "bands"))
         achieved = per_launch / (us * 1e-6) / 1e9
-        kname = "k_amul_dot_walk" if walk else "k_amul_dot"
+        kname = {0: "k_amul_dot", 1: "k_amul_dot_walk", 2: "k_amul_dot_box"}[walk]
         roof = {"kernel": f"{kname} (q = A p with p.q partials)", "bound": "hbm",
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,

@@ -84,7 +84,9 @@ typedef int32_t lf_status;
                               FP32 solve's of LF_PREC_MIXED) by the row walk
                               when the mesh fills the GPU with it (at least
                               2048 workgroups of 512 threads, 8 rows each),
-                              else one row per thread */
+                              else one row per thread; the FP64 products of a
+                              box then take the block walk
+                              (lf_problem_amul_walk) */
 #define LF_WALK_ON 1       /* the row walk whenever the layout allows it (tests) */
 #define LF_WALK_OFF 2      /* always one row per thread */
 
@@ -306,7 +308,12 @@ lf_status lf_problem_reset(lf_problem *problem, const lf_patch_bc *bcs, double D
  * LF_LAYOUT_BANDS (never AUTO). */
 lf_status lf_problem_layout(const lf_problem *problem, int32_t *layout);
 
-/* 1 if the problem's matrix-vector products use the row walk, else 0. */
+/* How the problem's FP64 matrix-vector products run: 0 one row per thread,
+ * 1 the row walk, 2 the block walk of a box (a band layout with offsets 1, nx,
+ * nx ny, nx even and N even, whenever the row walk is chosen for it: two
+ * x-adjacent rows per lane, two lines by two planes per thread).  With 1 or 2
+ * the inner FP32 products of LF_PREC_MIXED take the row walk.  All forms
+ * give bitwise the same product. */
 lf_status lf_problem_amul_walk(const lf_problem *problem, int32_t *walk);
 
 /* T[N]: on_device = 1 means a device pointer (copied on the handle's stream),

@@ -182,6 +182,15 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
             P->sp.grid_amul = wb;
             P->sp.grid_mx_amul = wb;
         }
+        // the FP64 products of a box take the block walk (its partials must
+        // fit the same slots)
+        BoxWalk bw;
+        if (P->walk && box_walk_plan(m->N, m->n_bands, m->band_d, &bw) && bw.blocks <= P->sp.grid_mx &&
+            bw.blocks <= P->sp.grid) {
+            P->box = true;
+            P->bw = bw;
+            P->sp.grid_amul = bw.blocks;
+        }
     }
     P->sp.n_red = m->two_colour ? m->n_red : m->N;
     if (P->rb) P->sp.grid_amul = cell_blocks(m->n_red);   // the pair product: one thread per red-black pair
@@ -260,7 +269,7 @@ lf_status lf_problem_layout(const lf_problem *P, int32_t *layout) {
 lf_status lf_problem_amul_walk(const lf_problem *P, int32_t *walk) {
     clear_error();
     if (!P || !walk) { set_error("NULL argument"); return LF_EINVAL; }
-    *walk = P->walk ? 1 : 0;
+    *walk = P->box ? 2 : (P->walk ? 1 : 0);
     return LF_OK;
 }
 

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
 #include "lf_problem.h"
 
 namespace lf {
@@ -49,10 +51,11 @@ __device__ __forceinline__ int32_t cell_row(int j) {
 }
 
 // first stage: the workgroup's partial sums go to part[slot * G + blockIdx.x]
-template <int NQ>
+// (BS: threads of the workgroup)
+template <int NQ, int BS = kCellBlock>
 __device__ __forceinline__ void write_partials(double *__restrict__ part, int32_t G, const int (&slot)[NQ],
                                                double (&v)[NQ]) {
-    block_sum<kCellBlock, NQ>(v);
+    block_sum<BS, NQ>(v);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) part[slot[q] * G + blockIdx.x] = v[q];
@@ -442,6 +445,163 @@ __device__ __forceinline__ double band_walk(const BandLayout<K> &L, const T *__r
     return dot;
 }
 
+
+// ---------------------------------------------------------------------------
+// Block walk over a box's band layout: three bands with offsets 1, nx, nx ny
+// (nx even, N even), i.e. row c = ix + nx iy + nx ny iz.  The rows are cut into
+// tiles of kBwY x-lines by kBwZ planes; thread t of tile g takes the two
+// x-adjacent rows c, c + 1 (ix = 2t) of each of the tile's lines, so every
+// array is read 16 bytes per lane.  A row's y- and z-neighbours inside the
+// thread's rows come from registers (the walk goes up the tile's lines: the
+// upper line's values become the next row's own), its x-neighbours from the
+// thread's other row or from the adjacent lane when that lane holds the
+// adjacent pair (same tile, which the lanes check once), else from memory.
+// Each row's sum is layout_dot's, term for term in the same order, so the
+// product is bitwise the same; fewer, wider loads reach more of the HBM
+// bandwidth than the one-row walk, whose neighbour gathers cost extra vector
+// memory instructions.
+// ---------------------------------------------------------------------------
+// lane i takes v from lane i - 1 (lane 0: fill) / lane i + 1 (lane 63: fill)
+// by the wavefront-wide DPP shifts; every lane of the wave must execute them
+__device__ __forceinline__ int lane_from_below(int v, int fill) {
+    return __builtin_amdgcn_update_dpp(fill, v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int lane_from_above(int v, int fill) {
+    return __builtin_amdgcn_update_dpp(fill, v, 0x130, 0xf, 0xf, false);
+}
+__device__ __forceinline__ double lane_from_below(double v) {
+    return __hiloint2double(lane_from_below(__double2hiint(v), 0), lane_from_below(__double2loint(v), 0));
+}
+__device__ __forceinline__ double lane_from_above(double v) {
+    return __hiloint2double(lane_from_above(__double2hiint(v), 0), lane_from_above(__double2loint(v), 0));
+}
+
+typedef double lf_v2d __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ double2 load2(const double *__restrict__ a, int64_t i) {
+    return *reinterpret_cast<const double2 *>(a + i);
+}
+__device__ __forceinline__ double2 load2_stream(const double *__restrict__ a, int64_t i) {
+    const lf_v2d v = __builtin_nontemporal_load(reinterpret_cast<const lf_v2d *>(a + i));
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void store2_stream(double *__restrict__ a, int64_t i, double2 v) {
+    lf_v2d w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, reinterpret_cast<lf_v2d *>(a + i));
+}
+
+// The walk: calls fn(c, y, x, diag) with the pair (rows c, c + 1) as double2,
+// y = A x, for the thread's pairs (lines in order, within a line the planes in
+// order).  kStream streams diag past the caches.  All lanes of a wave run the
+// lane exchanges, so the caller must not branch around the call.
+template <bool kStream, class Fn>
+__device__ __forceinline__ void box_walk(const BandLayout<3> &L, const BoxWalk &bw, const double *__restrict__ diag,
+                                         const double *__restrict__ coef, const double *__restrict__ x, Fn &&fn) {
+    const int64_t n = L.n, d1 = L.d[1], d2 = L.d[2];
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBwBlock + threadIdx.x;
+    const int64_t g = i / bw.hx, t = i - g * bw.hx;
+    const bool tv = g < bw.ntiles;
+    const int64_t yb = g % bw.nyb, zb = g / bw.nyb;
+    const int64_t iy0 = yb * kBwY;
+    const int64_t base = 2 * t + d1 * iy0 + d2 * (zb * kBwZ);
+    // the adjacent lanes hold the adjacent pairs of every row iff their first
+    // pair is base -+ 2 (then they are threads t -+ 1 of the same tile)
+    const int key = tv ? static_cast<int>(base) : -8;
+    const bool below_ok = lane_from_below(key, -1000) == key - 2;
+    const bool above_ok = lane_from_above(key, -1000) == key + 2;
+    const double2 z2 = make_double2(0.0, 0.0);
+    double2 xc[kBwZ], alo[kBwZ], xlo[kBwZ];
+#pragma unroll
+    for (int k = 0; k < kBwZ; ++k) {
+        const int64_t c = base + k * d2;
+        xc[k] = alo[k] = xlo[k] = z2;
+        if (tv && c < n) {
+            xc[k] = load2(x, c);
+            if (c >= d1) {
+                alo[k] = load2(coef, n + c - d1);
+                xlo[k] = load2(x, c - d1);
+            } else {
+                xlo[k] = xc[k];
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kBwY; ++j) {
+        const bool line = tv && iy0 + j < bw.ny;
+        const int64_t c0 = base + j * d1;
+        double2 xup[kBwZ], dg[kBwZ], a0[kBwZ], a1[kBwZ], a2[kBwZ];
+        bool ok[kBwZ];
+#pragma unroll
+        for (int k = 0; k < kBwZ; ++k) {
+            const int64_t c = c0 + k * d2;
+            ok[k] = line && c < n;
+            xup[k] = dg[k] = a0[k] = a1[k] = a2[k] = z2;
+            if (ok[k]) {
+                xup[k] = load2(x, c < n - d1 ? c + d1 : c);
+                dg[k] = kStream ? load2_stream(diag, c) : load2(diag, c);
+                a0[k] = load2(coef, c);
+                // the band-1 coefficient is read by this thread only (the next
+                // line's row takes it from a register): stream it
+                a1[k] = load2_stream(coef, n + c);
+                a2[k] = load2(coef, 2 * n + c);
+            }
+        }
+        // z neighbours outside the tile: below its first plane, above its last
+        double2 a2lo0 = z2, xzlo0 = xc[0], xzhi_top = xc[kBwZ - 1];
+        if (ok[0] && c0 >= d2) {
+            a2lo0 = load2(coef, 2 * n + c0 - d2);
+            xzlo0 = load2(x, c0 - d2);
+        }
+        {
+            const int64_t ct = c0 + (kBwZ - 1) * d2;
+            if (ok[kBwZ - 1] && ct < n - d2) xzhi_top = load2(x, ct + d2);
+        }
+#pragma unroll
+        for (int k = 0; k < kBwZ; ++k) {
+            const int64_t c = c0 + k * d2;
+            // x neighbours: row c's lower pair (coefficient and x of c - 1) and
+            // row c + 1's upper x (c + 2), from the adjacent lanes when they hold them
+            double a0lo = lane_from_below(a0[k].y), xm1 = lane_from_below(xc[k].y);
+            double xp2 = lane_from_above(xc[k].x);
+            if (ok[k] && !below_ok) {
+                if (c >= 1) {
+                    a0lo = coef[c - 1];
+                    xm1 = x[c - 1];
+                } else {
+                    a0lo = 0.0;
+                    xm1 = xc[k].x;
+                }
+            }
+            if (ok[k] && !above_ok) xp2 = c < n - 2 ? x[c + 2] : xc[k].y;
+            const double2 a2lo = k == 0 ? a2lo0 : a2[k - 1];
+            const double2 xzlo = k == 0 ? xzlo0 : xc[k - 1];
+            const double2 xzhi = c < n - d2 ? (k + 1 < kBwZ ? xc[k + 1] : xzhi_top) : xc[k];
+            double y0 = dg[k].x * xc[k].x;
+            y0 += a2lo.x * xzlo.x;
+            y0 += alo[k].x * xlo[k].x;
+            y0 += a0lo * xm1;
+            y0 += a0[k].x * xc[k].y;
+            y0 += a1[k].x * xup[k].x;
+            y0 += a2[k].x * xzhi.x;
+            double y1 = dg[k].y * xc[k].y;
+            y1 += a2lo.y * xzlo.y;
+            y1 += alo[k].y * xlo[k].y;
+            y1 += a0[k].x * xc[k].x;
+            y1 += a0[k].y * xp2;
+            y1 += a1[k].y * xup[k].y;
+            y1 += a2[k].y * xzhi.y;
+            if (ok[k]) fn(c, make_double2(y0, y1), xc[k], dg[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < kBwZ; ++k) {
+            alo[k] = a1[k];
+            xlo[k] = xc[k];
+            xc[k] = xup[k];
+        }
+    }
+}
 
 // ---------------------------------------------------------------------------
 // assembly (Listing 1): upper_f = -(delta_f (DT |S_f|)), diag = V/dt - lapDiag

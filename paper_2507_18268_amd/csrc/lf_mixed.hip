@@ -38,6 +38,8 @@
 constexpr double kTighten = 0.1;
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cmath>
 
@@ -264,6 +266,23 @@ k_mx_residual_walk(SolverParams sp, BandLayout<K> L, const double *__restrict__ 
     write_partials<4>(part, sp.grid, slots, acc);
 }
 
+// the same residual by the block walk of a box (bw.blocks workgroups)
+__global__ void __launch_bounds__(kBwBlock)
+k_mx_residual_box(SolverParams sp, BandLayout<3> L, BoxWalk bw, const double *__restrict__ diagB,
+                  const double *__restrict__ coef, const double *__restrict__ srcB, const double *__restrict__ T,
+                  const float *__restrict__ p32, float *__restrict__ r32, float *__restrict__ d32,
+                  double *__restrict__ part, const PcgState *__restrict__ st) {
+    if (st->done) return;
+    const bool keep = st->inner_iter > 0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    box_walk<true>(L, bw, diagB, coef, T, [&](int64_t c, double2 ax, double2, double2 db) {
+        pass_end_row(c, ax.x, db.x, keep, srcB, p32, r32, d32, acc);
+        pass_end_row(c + 1, ax.y, db.y, keep, srcB, p32, r32, d32, acc);
+    });
+    const int slots[4] = {kPartSumR, kPartSumR32, kPartWr32, kPartRp32};
+    write_partials<4, kBwBlock>(part, sp.grid, slots, acc);
+}
+
 // one-workgroup decisions of the refinement
 enum MxFin : int { kMxInnerStart = 0, kMxAlpha = 1, kMxBeta = 2, kMxOuter = 3 };
 
@@ -408,6 +427,14 @@ static void launch_pass_end(lf_problem *P, hipStream_t s) {
     LF_LAUNCH(P, LF_K_MIXED_CORRECT, s, k_mx_correct, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->T, P->d32,
               P->p32, P->sig32, P->state);
     with_layout(P, [&](auto lay) {
+        if constexpr (std::is_same_v<decltype(lay), BandLayout<3>>) {
+            if (P->box) {
+                LF_LAUNCH(P, LF_K_MIXED_RESIDUAL, s, k_mx_residual_box, dim3(static_cast<unsigned>(P->bw.blocks)),
+                          dim3(kBwBlock), 0, s, P->sp, lay, P->bw, P->diagB, P->coef, P->srcB, P->T, P->p32, P->r32,
+                          P->d32, P->part, P->state);
+                return;
+            }
+        }
         constexpr int K = WalkBands<decltype(lay)>::value;
         if constexpr (K > 0) {
             if (P->walk) {

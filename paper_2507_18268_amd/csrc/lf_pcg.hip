@@ -138,6 +138,16 @@ k_amul_walk(BandLayout<K> L, const double *__restrict__ diagB, const double *__r
     band_walk<K, false, false>(L, diagB, coef, x, y);
 }
 
+// y = A x by the block walk of a box
+__global__ void __launch_bounds__(kBwBlock)
+k_amul_box(BandLayout<3> L, BoxWalk bw, const double *__restrict__ diagB, const double *__restrict__ coef,
+           const double *__restrict__ x, double *__restrict__ y) {
+    box_walk<false>(L, bw, diagB, coef, x, [&](int64_t c, double2 yc, double2, double2) {
+        y[c] = yc.x;
+        y[c + 1] = yc.y;
+    });
+}
+
 // band layout: face-order copy of the coefficients, upper_f at slot k*N + owner_f
 __global__ void __launch_bounds__(kCellBlock)
 k_band_upper(int32_t F, int32_t N, BandOffsets bo, const int32_t *__restrict__ owner,
@@ -209,6 +219,23 @@ k_amul_dot_walk(SolverParams sp, BandLayout<K> L, const double *__restrict__ dia
     double acc[1] = {band_walk<K, true, false>(L, diagB, coef, p, q)};
     const int slots[1] = {kPartPq};
     write_partials<1>(part, sp.grid, slots, acc);
+}
+
+// k_amul_dot by the block walk of a box: bw.blocks workgroups of kBwBlock
+// threads, whose partials of q.p fill the first bw.blocks entries of the p.q slot
+__global__ void __launch_bounds__(kBwBlock)
+k_amul_dot_box(SolverParams sp, BandLayout<3> L, BoxWalk bw, const double *__restrict__ diagB,
+               const double *__restrict__ coef, const double *__restrict__ p, double *__restrict__ q,
+               double *__restrict__ part, const PcgState *__restrict__ st) {
+    if (st->done) return;
+    double acc[1] = {0.0};
+    box_walk<true>(L, bw, diagB, coef, p, [&](int64_t c, double2 qc, double2 pc, double2) {
+        store2_stream(q, c, qc);
+        acc[0] += qc.x * pc.x;
+        acc[0] += qc.y * pc.y;
+    });
+    const int slots[1] = {kPartPq};
+    write_partials<1, kBwBlock>(part, sp.grid, slots, acc);
 }
 
 // r -= alpha q; partial sums of |r| and (diagonal) of w.r, w = rD r.  With
@@ -934,6 +961,13 @@ static lf_status launch_setup(lf_problem *P, hipStream_t s) {
 static lf_status launch_iteration(lf_problem *P, hipStream_t s) {
     const bool diag_pc = P->opts.precond == LF_PC_DIAGONAL;
     with_layout(P, [&](auto lay) {
+        if constexpr (std::is_same_v<decltype(lay), BandLayout<3>>) {
+            if (P->box) {
+                LF_LAUNCH(P, LF_K_AMUL_DOT, s, k_amul_dot_box, dim3(static_cast<unsigned>(P->bw.blocks)),
+                          dim3(kBwBlock), 0, s, P->sp, lay, P->bw, P->diagB, P->coef, P->p, P->q, P->part, P->state);
+                return;
+            }
+        }
         constexpr int K = WalkBands<decltype(lay)>::value;
         if constexpr (K > 0) {
             if (P->walk) {
@@ -1114,6 +1148,13 @@ lf_status launch_precondition_hook(lf_problem *P) {
 
 lf_status launch_amul_hook(lf_problem *P, const double *x, double *y) {
     with_layout(P, [&](auto lay) {
+        if constexpr (std::is_same_v<decltype(lay), BandLayout<3>>) {
+            if (P->box) {
+                hipLaunchKernelGGL(k_amul_box, dim3(static_cast<unsigned>(P->bw.blocks)), dim3(kBwBlock), 0,
+                                   P->stream, lay, P->bw, P->diagB, P->coef, x, y);
+                return;
+            }
+        }
         constexpr int K = WalkBands<decltype(lay)>::value;
         if constexpr (K > 0) {
             if (P->walk) {

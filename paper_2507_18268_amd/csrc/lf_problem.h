@@ -47,6 +47,31 @@ struct PcgState {
     int32_t pad3;
 };
 
+// Block walk of a box's band layout (the tiles, lanes and rows are described
+// with the walk itself in lf_kernels.h)
+constexpr int kBwY = 2, kBwZ = 2;   // lines and planes of a tile
+constexpr int kBwBlock = 256;       // threads of a block-walk workgroup
+
+// host-side plan of a block walk
+struct BoxWalk {
+    int32_t hx;        // threads per tile (nx / 2)
+    int32_t ny;        // lines per plane
+    int32_t nyb;       // tiles per plane column (ceil(ny / kBwY))
+    int32_t ntiles;    // nyb ceil(nz / kBwZ)
+    int32_t blocks;    // workgroups of kBwBlock threads
+};
+
+inline bool box_walk_plan(int32_t n, int32_t K, const int32_t *d, BoxWalk *bw) {
+    if (K != 3 || n <= 0 || n % 2 != 0 || d[0] != 1 || d[1] < 2 || d[1] % 2 != 0 || d[2] % d[1] != 0) return false;
+    const int64_t hx = d[1] / 2, ny = d[2] / d[1], nz = (static_cast<int64_t>(n) + d[2] - 1) / d[2];
+    const int64_t nyb = (ny + kBwY - 1) / kBwY, ntiles = nyb * ((nz + kBwZ - 1) / kBwZ);
+    const int64_t blocks = (ntiles * hx + kBwBlock - 1) / kBwBlock;
+    if (ntiles > INT32_MAX || blocks > INT32_MAX) return false;
+    *bw = BoxWalk{static_cast<int32_t>(hx), static_cast<int32_t>(ny), static_cast<int32_t>(nyb),
+                  static_cast<int32_t>(ntiles), static_cast<int32_t>(blocks)};
+    return true;
+}
+
 constexpr int kMaxGraphLog = 6;   // largest captured block: 64 iterations
 
 struct SolverParams {
@@ -98,6 +123,8 @@ struct lf_problem {
     bool banded = false;                       // coefficients in the band layout
     bool rb = false;                           // coefficients in the two-colour band layout (DIC)
     bool walk = false;                         // FP64 Amul by the row walk (bands >= 2, large meshes)
+    bool box = false;                          // FP64 products by the block walk (box band layouts, with walk)
+    lf::BoxWalk bw{};                          // its plan
     // multigrid preconditioner: coarse levels 1.. (level 0 is the problem's own
     // band matrix) and two work vectors of level 0
     std::vector<lf::AmgLevel> amg;

@@ -525,8 +525,12 @@ class Problem:
         return lf_problem_layout(self.h)
 
     def amul_walk(self):
-        """True if the FP64 matrix-vector product runs as the row walk."""
+        """True if the FP64 matrix-vector product runs as a walk (row or block)."""
         return bool(lf_problem_amul_walk(self.h))
+
+    def amul_form(self):
+        """0 one row per thread, 1 the row walk, 2 the block walk of a box."""
+        return lf_problem_amul_walk(self.h)
 
     def reset(self, bcs, DT, dt):
         """New boundary conditions, DT and dt for the same mesh and workspace."""

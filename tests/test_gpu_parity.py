@@ -136,11 +136,21 @@ def test_amul_bitwise(L, oracle, name, mesh, layout):
 WALK_MESHES = [
     # band-1 offset d1 = nx; runs of 8 d1 rows, the last one ragged
     ("13x7x5", lambda: synth.box_mesh(13, 7, 5, z_ratio=3.0)),
-    ("130x9x4", lambda: synth.box_mesh(130, 9, 4)),
     ("5x40x9", lambda: synth.box_mesh(5, 40, 9, z_ratio=2.0)),
     ("two_bands_6x5x1", lambda: synth.box_mesh(6, 5, 1)),
     ("one_plane_row_3x1x7", lambda: synth.box_mesh(3, 1, 7)),
+    # block walk (nx even): tiles of 2 lines x 2 planes, nx / 2 threads each
+    ("block_130x9x4", lambda: synth.box_mesh(130, 9, 4)),          # tiles cross waves, odd line count
+    ("block_2x7x5", lambda: synth.box_mesh(2, 7, 5, z_ratio=2.0)),  # one thread per tile, odd lines and planes
+    ("block_128x6x3", lambda: synth.box_mesh(128, 6, 3)),           # one wave per tile line, odd planes
+    ("block_256x3x2", lambda: synth.box_mesh(256, 3, 2, z_ratio=4.0)),  # two waves per line
+    ("block_66x5x7", lambda: synth.box_mesh(66, 5, 7, z_ratio=3.0)),
 ]
+
+
+def _block_form(name):
+    """The meshes above on which LF_WALK_ON takes the block walk."""
+    return name.startswith("block_")
 
 
 @pytest.mark.parametrize("name,mk", WALK_MESHES, ids=[n for n, _ in WALK_MESHES])
@@ -158,6 +168,8 @@ def test_amul_walk_bitwise(L, oracle, name, mk):
         P = L.Problem(m, BCS_MIXED, 2e-3, 1e-3, L.make_opts(amul_walk=walk))
         assert P.layout() == L.LF_LAYOUT_BANDS
         assert P.amul_walk() == (walk == L.LF_WALK_ON)
+        if walk == L.LF_WALK_ON:
+            assert P.amul_form() == (2 if _block_form(name) else 1), P.amul_form()
         P.set_T(T0)
         P.assemble()
         g = P.matrix()
@@ -312,6 +324,9 @@ EDGE = [
     ("walk_13x11x9", lambda: synth.box_mesh(13, 11, 9, z_ratio=2.0), synth.fixed_x_bcs(), 1e-2, 1e-2,
      dict(amul_walk=1)),
     ("walk_130x9x4", lambda: synth.box_mesh(130, 9, 4), synth.fixed_x_bcs(), 1e-2, 1e-2, dict(amul_walk=1)),
+    ("block_walk_66x5x7", lambda: synth.box_mesh(66, 5, 7, z_ratio=3.0), synth.fixed_x_bcs(), 1e-2, 1e-2,
+     dict(amul_walk=1)),
+    ("block_walk_2x7x5", lambda: synth.box_mesh(2, 7, 5), synth.fixed_x_bcs(), 1e-2, 1e-2, dict(amul_walk=1)),
     ("walk_min_iter_5", lambda: synth.box_mesh(13, 11, 9), synth.fixed_x_bcs(), 1e-3, 1e-3,
      dict(amul_walk=1, min_iter=5)),
     ("no_graph", lambda: synth.box_mesh(13, 11, 9), synth.fixed_x_bcs(), 1e-2, 1e-2, dict(use_graph=0)),
