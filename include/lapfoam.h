@@ -263,6 +263,22 @@ lf_status lf_mesh_get_addressing(const lf_mesh *mesh, int32_t *owner_start, int3
 lf_status lf_grad(const lf_mesh *mesh, const double *T, const double *Tb, const double *snGrad_b,
                   double *grad, double *bgrad);
 
+/* lf_grad for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, layouts, ordering and results as lf_grad (bitwise); it calls no
+ * hipMalloc, hipFree or allocating library routine.  On a mesh kept in Morton
+ * order T is copied into a scratch array that the library holds in static
+ * device memory, one per GPU (64 MiB, kept until the process ends), instead of
+ * the mesh's workspace; its address on a GPU is looked up on the first call
+ * there.  Every call on one GPU shares that array: calls that overlap on one
+ * GPU (other streams, other threads, other meshes) race and must be ordered
+ * by the caller.  Meshes with band form use no scratch.
+ * LF_EINVAL: as lf_grad; a mesh in Morton order with more than 8,388,608
+ * cells (the scratch's size); the current device is not the mesh's.
+ * LF_EDEVICE: the scratch's address could not be looked up. */
+lf_status lf_grad_noalloc(const lf_mesh *mesh, const double *T, const double *Tb, const double *snGrad_b,
+                          double *grad, double *bgrad);
+
 /* ---- problem: mesh + boundary conditions + DT + dt + solver ------------- */
 size_t lf_problem_workspace_bytes(const lf_mesh *mesh, const lf_solver_opts *opts);
 /* bcs[n_patches]; DT >= 0 finite; dt > 0 finite.  LF_PC_DIC on a mesh without

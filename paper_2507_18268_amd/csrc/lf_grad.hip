@@ -22,9 +22,17 @@
 //
 // Face records: {S_x, S_y, S_z, w_f} per internal face and {S_x, S_y, S_z,
 // |S_b|} per boundary face, 32 bytes each, read as two 16-byte loads.
+#include <mutex>
+
 #include "lf_solver.h"
 
 namespace lf {
+
+// scratch of lf_grad_noalloc: at most this many cells of a mesh in Morton
+// order (8 Mi doubles, 64 MiB per GPU), on devices 0 .. kGradScratchDevices - 1
+constexpr int64_t kGradScratchCells = int64_t(1) << 23;
+constexpr int kGradScratchDevices = 64;
+
 
 struct Rec {
     double x, y, z, w;
@@ -615,6 +623,85 @@ extern "C" lf_status lf_grad(const lf_mesh *m, const double *T, const double *Tb
     }
     if (m->n_bands < 1 || m->n_bands > kMaxBands) { set_error("bad band count %d", m->n_bands); return LF_EINVAL; }
     launch_grad_band(m, T, Tb, snb, grad, bgrad, true, m->stream);
+    LF_HIP(hipGetLastError());
+    return LF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// lf_grad_noalloc: lf_grad for callers that cannot allocate device memory.
+// Its one scratch buffer (T copied into the solver's order on a mesh kept in
+// Morton order) is this file-scope array, one copy per GPU, held from the
+// module's load until the process ends.  Host code reaches it only through
+// the address hipGetSymbolAddress returns for that GPU (the array's name in
+// host code is not a device address).
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[kGradScratchCells];
+
+namespace {
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kGradScratchDevices] = {};
+
+// the array's address on the current device (= dev), resolved once per device
+lf_status grad_scratch(int dev, double **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (dev < 0 || dev >= kGradScratchDevices) {
+        set_error("device %d is beyond the %d devices the scratch table covers", dev, kGradScratchDevices);
+        return LF_EDEVICE;
+    }
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_error("hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+            return LF_EDEVICE;
+        }
+        g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return LF_OK;
+}
+}  // namespace
+
+extern "C" lf_status lf_grad_noalloc(const lf_mesh *m, const double *T, const double *Tb, const double *snb,
+                                     double *grad, double *bgrad) {
+    clear_error();
+    if (!m || !T || !grad) { set_error("NULL argument"); return LF_EINVAL; }
+    if (!m->gface && !m->gband) {
+        set_error("the mesh holds no gradient geometry (created without face centres)");
+        return LF_EINVAL;
+    }
+    if (m->B > 0 && !Tb) { set_error("Tb is NULL"); return LF_EINVAL; }
+    if (m->B > 0 && bgrad && !snb) { set_error("snGrad_b is NULL while bgrad is given"); return LF_EINVAL; }
+    if (m->B == 0) bgrad = nullptr;
+    if (m->gband) {
+        // the band form reads T in place: no scratch
+        if (m->n_bands < 1 || m->n_bands > kMaxBands) { set_error("bad band count %d", m->n_bands); return LF_EINVAL; }
+        launch_grad_band(m, T, Tb, snb, grad, bgrad, true, m->stream);
+        LF_HIP(hipGetLastError());
+        return LF_OK;
+    }
+    const double *Ts = T;
+    if (m->iperm) {
+        if (static_cast<int64_t>(m->N) > kGradScratchCells) {
+            set_error("lf_grad_noalloc: the mesh has %d cells in Morton order; its scratch holds at most %lld",
+                      m->N, static_cast<long long>(kGradScratchCells));
+            return LF_EINVAL;
+        }
+        int dev = -1;
+        LF_HIP(hipGetDevice(&dev));
+        if (dev != m->device) {
+            set_error("lf_grad_noalloc: device %d is current, the mesh lives on %d", dev, m->device);
+            return LF_EINVAL;
+        }
+        double *scr = nullptr;
+        LF_TRY(grad_scratch(dev, &scr));
+        const dim3 grid((m->N + kGradBlock - 1) / kGradBlock), block(kGradBlock);
+        hipLaunchKernelGGL(k_grad_to_rows, grid, block, 0, m->stream, m->N, m->iperm, T, scr);
+        Ts = scr;
+    }
+    hipLaunchKernelGGL(k_grad_rows, dim3((m->N + kGradBlock - 1) / kGradBlock), dim3(kGradBlock), 0, m->stream,
+                       m->N, Ts, Tb, snb, m->soff, m->scol, m->rlen, m->gerec, m->rbface_start, m->rbface_list,
+                       m->gbface, m->V, m->iperm, grad, bgrad);
     LF_HIP(hipGetLastError());
     return LF_OK;
 }

@@ -109,6 +109,7 @@ _SIGS = {
     "lf_get_matrix": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 7),
     "lf_amul": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lf_grad": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 5),
+    "lf_grad_noalloc": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 5),
     "lf_problem_grad": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lf_batch_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
     "lf_batch_create": (C.c_int32, [C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
@@ -300,6 +301,11 @@ def lf_get_matrix(h, diag=None, upper=None, source=None, diag_b=None, source_b=N
 def lf_grad(h, T_ptr, Tb_ptr, snb_ptr, grad_ptr, bgrad_ptr):
     _check(lib().lf_grad(h, C.c_void_p(T_ptr), C.c_void_p(Tb_ptr), C.c_void_p(snb_ptr),
                          C.c_void_p(grad_ptr), C.c_void_p(bgrad_ptr)), "lf_grad")
+
+
+def lf_grad_noalloc(h, T_ptr, Tb_ptr, snb_ptr, grad_ptr, bgrad_ptr):
+    _check(lib().lf_grad_noalloc(h, C.c_void_p(T_ptr), C.c_void_p(Tb_ptr), C.c_void_p(snb_ptr),
+                                 C.c_void_p(grad_ptr), C.c_void_p(bgrad_ptr)), "lf_grad_noalloc")
 
 
 def lf_problem_grad(h, grad_ptr, bgrad_ptr):
