@@ -327,9 +327,10 @@ lf_status lf_problem_layout(const lf_problem *problem, int32_t *layout);
 /* How the problem's FP64 matrix-vector products run: 0 one row per thread,
  * 1 the row walk, 2 the block walk of a box (a band layout with offsets 1, nx,
  * nx ny, nx even and N even, whenever the row walk is chosen for it: two
- * x-adjacent rows per lane, two lines by two planes per thread).  With 1 or 2
- * the inner FP32 products of LF_PREC_MIXED take the row walk.  All forms
- * give bitwise the same product. */
+ * x-adjacent rows per lane, two lines by two planes per thread).  With 2 the
+ * inner FP32 products of LF_PREC_MIXED take the block walk too when nx is a
+ * multiple of 4 (four rows per lane), else the row walk; with 1 the row walk.
+ * All forms give bitwise the same product. */
 lf_status lf_problem_amul_walk(const lf_problem *problem, int32_t *walk);
 
 /* T[N]: on_device = 1 means a device pointer (copied on the handle's stream),
@@ -398,6 +399,15 @@ lf_status lf_get_matrix(lf_problem *problem, double *diag, double *upper, double
  * problem's layout and order of the solver's products; x, y device
  * pointers of N doubles, ordered on the handle's stream. */
 lf_status lf_amul(lf_problem *problem, const double *x, double *y);
+/* y = A32 x: the inner FP32 product of LF_PREC_MIXED with the FP32
+ * coefficients the last step formed (the Jacobi-scaled matrix S A S, unit
+ * diagonal), in the form the inner solve runs it (one row per thread, row
+ * walk or block walk: bitwise the same).  x, y device pointers of N floats in
+ * the solver's row order (the mesh's cell order unless lf_mesh_cell_order
+ * reports a reordering), ordered on the handle's stream.  LF_EINVAL unless
+ * LF_PREC_MIXED; LF_ESTATE before the first step (or after lf_problem_reset)
+ * and during a run. */
+lf_status lf_amul_inner(lf_problem *problem, const float *x, float *y);
 /* w = M r: the FP64 solver's preconditioner (diagonal: w = (1/diag) r; DIC:
  * its diagonal from the last assembled matrix, then the forward and backward
  * sweeps; multigrid: the coarse matrices of the last assembled matrix, then

@@ -182,14 +182,19 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
             P->sp.grid_amul = wb;
             P->sp.grid_mx_amul = wb;
         }
-        // the FP64 products of a box take the block walk (its partials must
-        // fit the same slots)
-        BoxWalk bw;
-        if (P->walk && box_walk_plan(m->N, m->n_bands, m->band_d, &bw) && bw.blocks <= P->sp.grid_mx &&
+        // the products of a box take the block walk: two FP64 rows or four
+        // FP32 rows per lane (its partials must fit the same slots)
+        BoxWalk bw, bw32;
+        if (P->walk && box_walk_plan(m->N, m->n_bands, m->band_d, 2, &bw) && bw.blocks <= P->sp.grid_mx &&
             bw.blocks <= P->sp.grid) {
             P->box = true;
             P->bw = bw;
             P->sp.grid_amul = bw.blocks;
+            if (box_walk_plan(m->N, m->n_bands, m->band_d, 4, &bw32) && bw32.blocks <= P->sp.grid_mx) {
+                P->box32 = true;
+                P->bw32 = bw32;
+                P->sp.grid_mx_amul = bw32.blocks;
+            }
         }
     }
     P->sp.n_red = m->two_colour ? m->n_red : m->N;
@@ -256,6 +261,7 @@ lf_status lf_problem_reset(lf_problem *P, const lf_patch_bc *bcs, double DT, dou
     P->DT = DT;
     P->dt = dt;
     P->assembled = false;
+    P->scaled32 = false;
     return LF_OK;
 }
 
@@ -430,6 +436,15 @@ lf_status lf_amul(lf_problem *P, const double *x, double *y) {
     LF_TRY(to_solver_order(P, x, P->p2));
     LF_TRY(launch_amul_hook(P, P->p2, P->q));
     return to_mesh_order(P, P->q, y);
+}
+
+lf_status lf_amul_inner(lf_problem *P, const float *x, float *y) {
+    clear_error();
+    if (!P || !x || !y) { set_error("NULL argument"); return LF_EINVAL; }
+    if (P->opts.precision != LF_PREC_MIXED) { set_error("the mixed-precision form's inner product only"); return LF_EINVAL; }
+    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
+    if (!P->scaled32) { set_error("no step has formed the FP32 coefficients yet"); return LF_ESTATE; }
+    return launch_amul_inner_hook(P, x, y);
 }
 
 lf_status lf_precondition(lf_problem *P, const double *r, double *w) {

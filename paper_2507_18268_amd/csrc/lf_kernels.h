@@ -447,20 +447,21 @@ __device__ __forceinline__ double band_walk(const BandLayout<K> &L, const T *__r
 
 
 // ---------------------------------------------------------------------------
-// Block walk over a box's band layout: three bands with offsets 1, nx, nx ny
-// (nx even, N even), i.e. row c = ix + nx iy + nx ny iz.  The rows are cut into
-// tiles of kBwY x-lines by kBwZ planes; thread t of tile g takes the two
-// x-adjacent rows c, c + 1 (ix = 2t) of each of the tile's lines, so every
-// array is read 16 bytes per lane.  A row's y- and z-neighbours inside the
-// thread's rows come from registers (the walk goes up the tile's lines: the
-// upper line's values become the next row's own), its x-neighbours from the
-// thread's other row or from the adjacent lane when that lane holds the
-// adjacent pair (same tile, which the lanes check once), else from memory.
-// Each row's sum is layout_dot's, term for term in the same order, so the
-// product is bitwise the same; fewer, wider loads reach more of the HBM
-// bandwidth than the one-row walk, whose neighbour gathers cost extra vector
-// memory instructions.
+// Block walk over a box's band layout: three bands with offsets 1, nx, nx ny,
+// i.e. row c = ix + nx iy + nx ny iz, with nx and N multiples of W.  The rows
+// are cut into tiles of kBwY x-lines by kBwZ planes; thread t of tile g takes
+// the W x-adjacent rows c .. c + W - 1 (ix = W t) of each of the tile's
+// lines, so every array is read 16 bytes per lane (W = 2 doubles, W = 4
+// floats).  A row's y- and z-neighbours inside the thread's rows come from
+// registers (the walk goes up the tile's lines: the upper line's values
+// become the next row's own), its x-neighbours from the thread's other rows or
+// from the adjacent lane when that lane holds the adjacent rows (same tile,
+// which the lanes check once), else from memory.  Each row's sum is
+// layout_dot's, term for term in the same order, so the product is bitwise
+// the same; fewer, wider loads reach more of the HBM bandwidth than the
+// one-row walk, whose neighbour gathers cost extra vector memory instructions.
 // ---------------------------------------------------------------------------
+
 // lane i takes v from lane i - 1 (lane 0: fill) / lane i + 1 (lane 63: fill)
 // by the wavefront-wide DPP shifts; every lane of the wave must execute them
 __device__ __forceinline__ int lane_from_below(int v, int fill) {
@@ -469,6 +470,12 @@ __device__ __forceinline__ int lane_from_below(int v, int fill) {
 __device__ __forceinline__ int lane_from_above(int v, int fill) {
     return __builtin_amdgcn_update_dpp(fill, v, 0x130, 0xf, 0xf, false);
 }
+__device__ __forceinline__ float lane_from_below(float v) {
+    return __int_as_float(lane_from_below(__float_as_int(v), 0));
+}
+__device__ __forceinline__ float lane_from_above(float v) {
+    return __int_as_float(lane_from_above(__float_as_int(v), 0));
+}
 __device__ __forceinline__ double lane_from_below(double v) {
     return __hiloint2double(lane_from_below(__double2hiint(v), 0), lane_from_below(__double2loint(v), 0));
 }
@@ -476,52 +483,75 @@ __device__ __forceinline__ double lane_from_above(double v) {
     return __hiloint2double(lane_from_above(__double2hiint(v), 0), lane_from_above(__double2loint(v), 0));
 }
 
-typedef double lf_v2d __attribute__((ext_vector_type(2)));
+// W consecutive values, moved as one 16-byte access
+template <class T, int W>
+struct Lanes {
+    static_assert(sizeof(T) * W == 16, "a lane moves 16 bytes");
+    typedef T vec __attribute__((ext_vector_type(W)));
+    T v[W];
+};
 
-__device__ __forceinline__ double2 load2(const double *__restrict__ a, int64_t i) {
-    return *reinterpret_cast<const double2 *>(a + i);
-}
-__device__ __forceinline__ double2 load2_stream(const double *__restrict__ a, int64_t i) {
-    const lf_v2d v = __builtin_nontemporal_load(reinterpret_cast<const lf_v2d *>(a + i));
-    return make_double2(v.x, v.y);
-}
-__device__ __forceinline__ void store2_stream(double *__restrict__ a, int64_t i, double2 v) {
-    lf_v2d w;
-    w.x = v.x;
-    w.y = v.y;
-    __builtin_nontemporal_store(w, reinterpret_cast<lf_v2d *>(a + i));
+template <class T, int W>
+__device__ __forceinline__ Lanes<T, W> lanes_zero() {
+    Lanes<T, W> r;
+#pragma unroll
+    for (int w = 0; w < W; ++w) r.v[w] = T(0);
+    return r;
 }
 
-// The walk: calls fn(c, y, x, diag) with the pair (rows c, c + 1) as double2,
-// y = A x, for the thread's pairs (lines in order, within a line the planes in
-// order).  kStream streams diag past the caches.  All lanes of a wave run the
-// lane exchanges, so the caller must not branch around the call.
-template <bool kStream, class Fn>
-__device__ __forceinline__ void box_walk(const BandLayout<3> &L, const BoxWalk &bw, const double *__restrict__ diag,
-                                         const double *__restrict__ coef, const double *__restrict__ x, Fn &&fn) {
+template <class T, int W, bool kStream = false>
+__device__ __forceinline__ Lanes<T, W> lanes_load(const T *__restrict__ a, int64_t i) {
+    typedef typename Lanes<T, W>::vec V;
+    const V *p = reinterpret_cast<const V *>(a + i);
+    const V x = kStream ? __builtin_nontemporal_load(p) : *p;
+    Lanes<T, W> r;
+#pragma unroll
+    for (int w = 0; w < W; ++w) r.v[w] = x[w];
+    return r;
+}
+
+template <class T, int W>
+__device__ __forceinline__ void lanes_store_stream(T *__restrict__ a, int64_t i, const Lanes<T, W> &r) {
+    typedef typename Lanes<T, W>::vec V;
+    V x;
+#pragma unroll
+    for (int w = 0; w < W; ++w) x[w] = r.v[w];
+    __builtin_nontemporal_store(x, reinterpret_cast<V *>(a + i));
+}
+
+// The walk: calls fn(c, y, x, diag) for the thread's groups of W rows
+// (c .. c + W - 1; lines in order, within a line the planes in order), y = A x
+// with the diagonal term first (kUnitDiag: a matrix with unit diagonal, x
+// first, diag = 1, `diag` not read).  kStream streams diag past the caches.
+// All lanes of a wave run the lane exchanges, so the caller must not branch
+// around the call.
+template <class T, int W, bool kStream, bool kUnitDiag, class Fn>
+__device__ __forceinline__ void box_walk(const BandLayout<3> &L, const BoxWalk &bw, const T *__restrict__ diag,
+                                         const T *__restrict__ coef, const T *__restrict__ x, Fn &&fn) {
+    typedef Lanes<T, W> R;
     const int64_t n = L.n, d1 = L.d[1], d2 = L.d[2];
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBwBlock + threadIdx.x;
     const int64_t g = i / bw.hx, t = i - g * bw.hx;
     const bool tv = g < bw.ntiles;
     const int64_t yb = g % bw.nyb, zb = g / bw.nyb;
     const int64_t iy0 = yb * kBwY;
-    const int64_t base = 2 * t + d1 * iy0 + d2 * (zb * kBwZ);
-    // the adjacent lanes hold the adjacent pairs of every row iff their first
-    // pair is base -+ 2 (then they are threads t -+ 1 of the same tile)
+    const int64_t base = W * t + d1 * iy0 + d2 * (zb * kBwZ);
+    // the adjacent lanes hold the adjacent rows of every line iff their first
+    // row is base -+ W (then they are threads t -+ 1 of the same tile)
     const int key = tv ? static_cast<int>(base) : -8;
-    const bool below_ok = lane_from_below(key, -1000) == key - 2;
-    const bool above_ok = lane_from_above(key, -1000) == key + 2;
-    const double2 z2 = make_double2(0.0, 0.0);
-    double2 xc[kBwZ], alo[kBwZ], xlo[kBwZ];
+    const bool below_ok = lane_from_below(key, -1000) == key - W;
+    const bool above_ok = lane_from_above(key, -1000) == key + W;
+    const R z = lanes_zero<T, W>();
+    R xc[kBwZ], alo[kBwZ], xlo[kBwZ];
 #pragma unroll
     for (int k = 0; k < kBwZ; ++k) {
         const int64_t c = base + k * d2;
-        xc[k] = alo[k] = xlo[k] = z2;
+        xc[k] = alo[k] = xlo[k] = z;
         if (tv && c < n) {
-            xc[k] = load2(x, c);
+            xc[k] = lanes_load<T, W>(x, c);
             if (c >= d1) {
-                alo[k] = load2(coef, n + c - d1);
-                xlo[k] = load2(x, c - d1);
+                alo[k] = lanes_load<T, W>(coef, n + c - d1);
+                xlo[k] = lanes_load<T, W>(x, c - d1);
             } else {
                 xlo[k] = xc[k];
             }
@@ -531,68 +561,67 @@ __device__ __forceinline__ void box_walk(const BandLayout<3> &L, const BoxWalk &
     for (int j = 0; j < kBwY; ++j) {
         const bool line = tv && iy0 + j < bw.ny;
         const int64_t c0 = base + j * d1;
-        double2 xup[kBwZ], dg[kBwZ], a0[kBwZ], a1[kBwZ], a2[kBwZ];
+        R xup[kBwZ], dg[kBwZ], a0[kBwZ], a1[kBwZ], a2[kBwZ];
         bool ok[kBwZ];
 #pragma unroll
         for (int k = 0; k < kBwZ; ++k) {
             const int64_t c = c0 + k * d2;
             ok[k] = line && c < n;
-            xup[k] = dg[k] = a0[k] = a1[k] = a2[k] = z2;
+            xup[k] = dg[k] = a0[k] = a1[k] = a2[k] = z;
             if (ok[k]) {
-                xup[k] = load2(x, c < n - d1 ? c + d1 : c);
-                dg[k] = kStream ? load2_stream(diag, c) : load2(diag, c);
-                a0[k] = load2(coef, c);
+                xup[k] = lanes_load<T, W>(x, c < n - d1 ? c + d1 : c);
+                if (!kUnitDiag) dg[k] = lanes_load<T, W, kStream>(diag, c);
+                a0[k] = lanes_load<T, W>(coef, c);
                 // the band-1 coefficient is read by this thread only (the next
                 // line's row takes it from a register): stream it
-                a1[k] = load2_stream(coef, n + c);
-                a2[k] = load2(coef, 2 * n + c);
+                a1[k] = lanes_load<T, W, true>(coef, n + c);
+                a2[k] = lanes_load<T, W>(coef, 2 * n + c);
             }
         }
         // z neighbours outside the tile: below its first plane, above its last
-        double2 a2lo0 = z2, xzlo0 = xc[0], xzhi_top = xc[kBwZ - 1];
+        R a2lo0 = z, xzlo0 = xc[0], xzhi_top = xc[kBwZ - 1];
         if (ok[0] && c0 >= d2) {
-            a2lo0 = load2(coef, 2 * n + c0 - d2);
-            xzlo0 = load2(x, c0 - d2);
+            a2lo0 = lanes_load<T, W>(coef, 2 * n + c0 - d2);
+            xzlo0 = lanes_load<T, W>(x, c0 - d2);
         }
         {
             const int64_t ct = c0 + (kBwZ - 1) * d2;
-            if (ok[kBwZ - 1] && ct < n - d2) xzhi_top = load2(x, ct + d2);
+            if (ok[kBwZ - 1] && ct < n - d2) xzhi_top = lanes_load<T, W>(x, ct + d2);
         }
 #pragma unroll
         for (int k = 0; k < kBwZ; ++k) {
             const int64_t c = c0 + k * d2;
-            // x neighbours: row c's lower pair (coefficient and x of c - 1) and
-            // row c + 1's upper x (c + 2), from the adjacent lanes when they hold them
-            double a0lo = lane_from_below(a0[k].y), xm1 = lane_from_below(xc[k].y);
-            double xp2 = lane_from_above(xc[k].x);
+            // x neighbours across the lane's edges: row c's lower entry
+            // (coefficient and x of c - 1) and row c + W - 1's upper x (c + W),
+            // from the adjacent lanes when they hold them
+            T a0lo = lane_from_below(a0[k].v[W - 1]), xm1 = lane_from_below(xc[k].v[W - 1]);
+            T xpw = lane_from_above(xc[k].v[0]);
             if (ok[k] && !below_ok) {
                 if (c >= 1) {
                     a0lo = coef[c - 1];
                     xm1 = x[c - 1];
                 } else {
-                    a0lo = 0.0;
-                    xm1 = xc[k].x;
+                    a0lo = T(0);
+                    xm1 = xc[k].v[0];
                 }
             }
-            if (ok[k] && !above_ok) xp2 = c < n - 2 ? x[c + 2] : xc[k].y;
-            const double2 a2lo = k == 0 ? a2lo0 : a2[k - 1];
-            const double2 xzlo = k == 0 ? xzlo0 : xc[k - 1];
-            const double2 xzhi = c < n - d2 ? (k + 1 < kBwZ ? xc[k + 1] : xzhi_top) : xc[k];
-            double y0 = dg[k].x * xc[k].x;
-            y0 += a2lo.x * xzlo.x;
-            y0 += alo[k].x * xlo[k].x;
-            y0 += a0lo * xm1;
-            y0 += a0[k].x * xc[k].y;
-            y0 += a1[k].x * xup[k].x;
-            y0 += a2[k].x * xzhi.x;
-            double y1 = dg[k].y * xc[k].y;
-            y1 += a2lo.y * xzlo.y;
-            y1 += alo[k].y * xlo[k].y;
-            y1 += a0[k].x * xc[k].x;
-            y1 += a0[k].y * xp2;
-            y1 += a1[k].y * xup[k].y;
-            y1 += a2[k].y * xzhi.y;
-            if (ok[k]) fn(c, make_double2(y0, y1), xc[k], dg[k]);
+            if (ok[k] && !above_ok) xpw = c < n - W ? x[c + W] : xc[k].v[W - 1];
+            const R &a2lo = k == 0 ? a2lo0 : a2[k - 1];
+            const R &xzlo = k == 0 ? xzlo0 : xc[k - 1];
+            const R &xzhi = c < n - d2 ? (k + 1 < kBwZ ? xc[k + 1] : xzhi_top) : xc[k];
+            R y;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                T acc = kUnitDiag ? xc[k].v[w] : dg[k].v[w] * xc[k].v[w];
+                acc += a2lo.v[w] * xzlo.v[w];
+                acc += alo[k].v[w] * xlo[k].v[w];
+                acc += (w == 0 ? a0lo : a0[k].v[w - 1]) * (w == 0 ? xm1 : xc[k].v[w - 1]);
+                acc += a0[k].v[w] * (w == W - 1 ? xpw : xc[k].v[w + 1]);
+                acc += a1[k].v[w] * xup[k].v[w];
+                acc += a2[k].v[w] * xzhi.v[w];
+                y.v[w] = acc;
+            }
+            if (ok[k]) fn(c, y, xc[k], dg[k]);
         }
 #pragma unroll
         for (int k = 0; k < kBwZ; ++k) {

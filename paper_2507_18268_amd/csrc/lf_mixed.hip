@@ -176,6 +176,24 @@ k_mx_amul_dot_walk(SolverParams sp, BandLayout<K> L, const float *__restrict__ c
     write_partials<1>(part, sp.grid_mx, slots, acc);
 }
 
+// the same product by the block walk of a box, four rows per lane (bw.blocks
+// workgroups of kBwBlock threads, whose partials fill the start of the p.q slot)
+__global__ void __launch_bounds__(kBwBlock)
+k_mx_amul_dot_box(SolverParams sp, BandLayout<3> L, BoxWalk bw, const float *__restrict__ coef32,
+                  const float *__restrict__ p32, float *__restrict__ q32, double *__restrict__ part,
+                  const PcgState *__restrict__ st) {
+    if (inner_off(st)) return;
+    typedef Lanes<float, 4> R;
+    double acc[1] = {0.0};
+    box_walk<float, 4, false, true>(L, bw, nullptr, coef32, p32, [&](int64_t c, const R &qc, const R &pc, const R &) {
+        lanes_store_stream(q32, c, qc);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) acc[0] += static_cast<double>(qc.v[w]) * static_cast<double>(pc.v[w]);
+    });
+    const int slots[1] = {kPartPq};
+    write_partials<1, kBwBlock>(part, sp.grid_mx, slots, acc);
+}
+
 // rs -= alpha q (FP32); FP64 partials of the L1 norm s|rs| and of rs.rs
 __global__ void __launch_bounds__(kCellBlock)
 k_mx_update(SolverParams sp, const float *__restrict__ q32, const float *__restrict__ sig32,
@@ -275,9 +293,10 @@ k_mx_residual_box(SolverParams sp, BandLayout<3> L, BoxWalk bw, const double *__
     if (st->done) return;
     const bool keep = st->inner_iter > 0;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    box_walk<true>(L, bw, diagB, coef, T, [&](int64_t c, double2 ax, double2, double2 db) {
-        pass_end_row(c, ax.x, db.x, keep, srcB, p32, r32, d32, acc);
-        pass_end_row(c + 1, ax.y, db.y, keep, srcB, p32, r32, d32, acc);
+    typedef Lanes<double, 2> R;
+    box_walk<double, 2, true, false>(L, bw, diagB, coef, T, [&](int64_t c, const R &ax, const R &, const R &db) {
+        pass_end_row(c, ax.v[0], db.v[0], keep, srcB, p32, r32, d32, acc);
+        pass_end_row(c + 1, ax.v[1], db.v[1], keep, srcB, p32, r32, d32, acc);
     });
     const int slots[4] = {kPartSumR, kPartSumR32, kPartWr32, kPartRp32};
     write_partials<4, kBwBlock>(part, sp.grid, slots, acc);
@@ -393,6 +412,13 @@ static void launch_inner_iteration(lf_problem *P, hipStream_t s) {
     LF_LAUNCH(P, LF_K_INNER_DIRECTION, s, k_mx_direction, mx_grid(P), dim3(kCellBlock), 0, s, P->sp, P->r32,
               P->p32, P->d32, P->state);
     with_layout(P, [&](auto lay) {
+        if constexpr (std::is_same_v<decltype(lay), BandLayout<3>>) {
+            if (P->box32) {
+                LF_LAUNCH(P, LF_K_INNER_AMUL_DOT, s, k_mx_amul_dot_box, dim3(static_cast<unsigned>(P->bw32.blocks)),
+                          dim3(kBwBlock), 0, s, P->sp, lay, P->bw32, P->coef32, P->p32, P->q32, P->part, P->state);
+                return;
+            }
+        }
         constexpr int K = WalkBands<decltype(lay)>::value;
         if constexpr (K > 0) {
             if (P->walk) {
@@ -409,6 +435,57 @@ static void launch_inner_iteration(lf_problem *P, hipStream_t s) {
     LF_LAUNCH(P, LF_K_INNER_UPDATE, s, k_mx_update, mx_grid(P), dim3(kCellBlock), 0, s, P->sp, P->q32, P->sig32,
               P->r32, P->part, P->state);
     launch_mx_fin<kMxBeta>(P, s);
+}
+
+// y = A32 x with the inner solve's FP32 coefficients (unit diagonal), in the
+// form the inner solve uses (test hook)
+template <class Lay>
+__global__ void __launch_bounds__(kCellBlock)
+k_mx_amul_hook(SolverParams sp, Lay L, const float *__restrict__ coef32, const float *__restrict__ x,
+               float *__restrict__ y) {
+    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+    if (c < sp.n) y[c] = layout_dot(L, c, coef32, x, x[c]);
+}
+
+template <int K>
+__global__ void __launch_bounds__(kCellBlock)
+k_mx_amul_walk_hook(BandLayout<K> L, const float *__restrict__ coef32, const float *__restrict__ x,
+                    float *__restrict__ y) {
+    band_walk<K, false, true, float>(L, nullptr, coef32, x, y);
+}
+
+__global__ void __launch_bounds__(kBwBlock)
+k_mx_amul_box_hook(BandLayout<3> L, BoxWalk bw, const float *__restrict__ coef32, const float *__restrict__ x,
+                   float *__restrict__ y) {
+    typedef Lanes<float, 4> R;
+    box_walk<float, 4, false, true>(L, bw, nullptr, coef32, x, [&](int64_t c, const R &yc, const R &, const R &) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) y[c + w] = yc.v[w];
+    });
+}
+
+lf_status launch_amul_inner_hook(lf_problem *P, const float *x, float *y) {
+    with_layout(P, [&](auto lay) {
+        if constexpr (std::is_same_v<decltype(lay), BandLayout<3>>) {
+            if (P->box32) {
+                hipLaunchKernelGGL(k_mx_amul_box_hook, dim3(static_cast<unsigned>(P->bw32.blocks)), dim3(kBwBlock), 0,
+                                   P->stream, lay, P->bw32, P->coef32, x, y);
+                return;
+            }
+        }
+        constexpr int K = WalkBands<decltype(lay)>::value;
+        if constexpr (K > 0) {
+            if (P->walk) {
+                hipLaunchKernelGGL(k_mx_amul_walk_hook<K>, dim3(static_cast<unsigned>(P->sp.grid_mx_amul)),
+                                   dim3(kCellBlock), 0, P->stream, lay, P->coef32, x, y);
+                return;
+            }
+        }
+        hipLaunchKernelGGL(k_mx_amul_hook<decltype(lay)>, cell_grid(P), dim3(kCellBlock), 0, P->stream, P->sp, lay,
+                           P->coef32, x, y);
+    });
+    LF_HIP(hipGetLastError());
+    return LF_OK;
 }
 
 void launch_mx_scale(lf_problem *P, hipStream_t s) {

@@ -142,9 +142,10 @@ k_amul_walk(BandLayout<K> L, const double *__restrict__ diagB, const double *__r
 __global__ void __launch_bounds__(kBwBlock)
 k_amul_box(BandLayout<3> L, BoxWalk bw, const double *__restrict__ diagB, const double *__restrict__ coef,
            const double *__restrict__ x, double *__restrict__ y) {
-    box_walk<false>(L, bw, diagB, coef, x, [&](int64_t c, double2 yc, double2, double2) {
-        y[c] = yc.x;
-        y[c + 1] = yc.y;
+    typedef Lanes<double, 2> R;
+    box_walk<double, 2, false, false>(L, bw, diagB, coef, x, [&](int64_t c, const R &yc, const R &, const R &) {
+        y[c] = yc.v[0];
+        y[c + 1] = yc.v[1];
     });
 }
 
@@ -229,10 +230,11 @@ k_amul_dot_box(SolverParams sp, BandLayout<3> L, BoxWalk bw, const double *__res
                double *__restrict__ part, const PcgState *__restrict__ st) {
     if (st->done) return;
     double acc[1] = {0.0};
-    box_walk<true>(L, bw, diagB, coef, p, [&](int64_t c, double2 qc, double2 pc, double2) {
-        store2_stream(q, c, qc);
-        acc[0] += qc.x * pc.x;
-        acc[0] += qc.y * pc.y;
+    typedef Lanes<double, 2> R;
+    box_walk<double, 2, true, false>(L, bw, diagB, coef, p, [&](int64_t c, const R &qc, const R &pc, const R &) {
+        lanes_store_stream(q, c, qc);
+        acc[0] += qc.v[0] * pc.v[0];
+        acc[0] += qc.v[1] * pc.v[1];
     });
     const int slots[1] = {kPartPq};
     write_partials<1, kBwBlock>(part, sp.grid, slots, acc);
@@ -893,6 +895,7 @@ lf_status launch_assemble_setup(lf_problem *P, hipStream_t s) {
     if (P->opts.precision == LF_PREC_MIXED) {
         launch_assemble_t<false, true, true>(P, s);
         launch_mx_scale(P, s);
+        P->scaled32 = true;
     } else {
         launch_assemble_t<false, true, false>(P, s);
     }

@@ -52,18 +52,19 @@ struct PcgState {
 constexpr int kBwY = 2, kBwZ = 2;   // lines and planes of a tile
 constexpr int kBwBlock = 256;       // threads of a block-walk workgroup
 
-// host-side plan of a block walk
+// host-side plan of a block walk with W x-adjacent rows per lane
 struct BoxWalk {
-    int32_t hx;        // threads per tile (nx / 2)
+    int32_t hx;        // threads per tile (nx / W)
     int32_t ny;        // lines per plane
     int32_t nyb;       // tiles per plane column (ceil(ny / kBwY))
     int32_t ntiles;    // nyb ceil(nz / kBwZ)
     int32_t blocks;    // workgroups of kBwBlock threads
 };
 
-inline bool box_walk_plan(int32_t n, int32_t K, const int32_t *d, BoxWalk *bw) {
-    if (K != 3 || n <= 0 || n % 2 != 0 || d[0] != 1 || d[1] < 2 || d[1] % 2 != 0 || d[2] % d[1] != 0) return false;
-    const int64_t hx = d[1] / 2, ny = d[2] / d[1], nz = (static_cast<int64_t>(n) + d[2] - 1) / d[2];
+inline bool box_walk_plan(int32_t n, int32_t K, const int32_t *d, int32_t W, BoxWalk *bw) {
+    if (K != 3 || W < 1 || n <= 0 || n % W != 0 || d[0] != 1 || d[1] < W || d[1] % W != 0 || d[2] % d[1] != 0)
+        return false;
+    const int64_t hx = d[1] / W, ny = d[2] / d[1], nz = (static_cast<int64_t>(n) + d[2] - 1) / d[2];
     const int64_t nyb = (ny + kBwY - 1) / kBwY, ntiles = nyb * ((nz + kBwZ - 1) / kBwZ);
     const int64_t blocks = (ntiles * hx + kBwBlock - 1) / kBwBlock;
     if (ntiles > INT32_MAX || blocks > INT32_MAX) return false;
@@ -124,7 +125,9 @@ struct lf_problem {
     bool rb = false;                           // coefficients in the two-colour band layout (DIC)
     bool walk = false;                         // FP64 Amul by the row walk (bands >= 2, large meshes)
     bool box = false;                          // FP64 products by the block walk (box band layouts, with walk)
-    lf::BoxWalk bw{};                          // its plan
+    lf::BoxWalk bw{};                          // its plan (2 rows per lane)
+    bool box32 = false;                        // the FP32 inner product too (mixed; 4 rows per lane)
+    lf::BoxWalk bw32{};
     // multigrid preconditioner: coarse levels 1.. (level 0 is the problem's own
     // band matrix) and two work vectors of level 0
     std::vector<lf::AmgLevel> amg;
@@ -160,6 +163,7 @@ struct lf_problem {
     int32_t last_inner[kPassTrack] = {};
     int32_t last_outer = 0;
     bool assembled = false;
+    bool scaled32 = false;                     // mixed: the inner solve's FP32 coefficients are formed
     size_t ws_bytes = 0;
     // per-kernel device timing (diagnostics)
     bool prof_on = false;

@@ -89,6 +89,7 @@ lf_status launch_assemble(lf_problem *P, bool full, hipStream_t s);
 lf_status launch_assemble_setup(lf_problem *P, hipStream_t s);
 // precision form: FP32 coefficients of the scaled matrix, after the assembly
 void launch_mx_scale(lf_problem *P, hipStream_t s);
+lf_status launch_amul_inner_hook(lf_problem *P, const float *x, float *y);
 // non-orthogonal meshes: boundary values and gradient of T, then P->lap_src
 // (lf_grad.hip); runs before the assembly of each step
 void launch_nonorth_source(lf_problem *P, hipStream_t s);

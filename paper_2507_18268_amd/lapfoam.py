@@ -110,6 +110,7 @@ _SIGS = {
     "lf_amul": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lf_grad": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 5),
     "lf_grad_noalloc": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 5),
+    "lf_amul_inner": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lf_problem_grad": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lf_batch_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
     "lf_batch_create": (C.c_int32, [C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
@@ -314,6 +315,10 @@ def lf_problem_grad(h, grad_ptr, bgrad_ptr):
 
 def lf_amul(h, x_ptr, y_ptr):
     _check(lib().lf_amul(h, C.c_void_p(x_ptr), C.c_void_p(y_ptr)), "lf_amul")
+
+
+def lf_amul_inner(h, x_ptr, y_ptr):
+    _check(lib().lf_amul_inner(h, C.c_void_p(x_ptr), C.c_void_p(y_ptr)), "lf_amul_inner")
 
 
 def lf_precondition(h, r_ptr, w_ptr):
@@ -608,6 +613,11 @@ class Problem:
 
     def amul(self, x, y):
         lf_amul(self.h, x.data_ptr(), y.data_ptr())
+
+    def amul_inner(self, x, y):
+        """y = A32 x, the mixed form's inner FP32 product (device float32 tensors,
+        solver row order)."""
+        lf_amul_inner(self.h, x.data_ptr(), y.data_ptr())
 
     def precondition(self, r, w):
         """w = M r with the problem's preconditioner (device float64 tensors)."""

@@ -36,6 +36,9 @@ CASES = [
     ("graded_24_walk", "graded_256", 24, 4, dict(amul_walk=1)),
     ("graded_13_walk_rows", "graded_256", 13, 4, dict(amul_walk=1, layout=1)),
     ("plain_32_walk", "plain_32", None, 6, dict(amul_walk=1)),
+    # nx = 18: the FP64 products by the block walk, the FP32 ones by the row walk
+    ("graded_18_walk", "graded_256", 18, 4, dict(amul_walk=1)),
+    ("graded_20_walk", "graded_256", 20, 4, dict(amul_walk=1)),
     ("graded_24_restart", "graded_256", 24, 4, dict(inner_restart=1)),
     ("permuted_20_restart", "permuted_192", 20, 4, dict(inner_restart=1)),
     ("graded_24_tight_continued", "graded_256", 24, 4, dict(inner_tol=1e-3)),
@@ -108,4 +111,43 @@ def test_mixed_refuses_dic(L):
     with pytest.raises(L.LapfoamError):
         L.Problem(m, synth.fixed_x_bcs(), 1e-3, 1e-3,
                   L.make_opts(precond=L.LF_PC_DIC, precision=L.LF_PREC_MIXED))
+    m.close()
+
+
+INNER_MESHES = [
+    # (name, mesh, expected product form under LF_WALK_ON; FP32 block walk when nx % 4 == 0)
+    ("box_132x7x5", lambda: synth.box_mesh(132, 7, 5, z_ratio=3.0), 2),     # tiles cross waves, odd lines/planes
+    ("box_4x9x3", lambda: synth.box_mesh(4, 9, 3), 2),                      # one thread per tile line
+    ("box_256x2x3", lambda: synth.box_mesh(256, 2, 3, z_ratio=2.0), 2),     # one wave per tile line
+    ("box_18x5x4", lambda: synth.box_mesh(18, 5, 4), 2),                    # FP64 block walk, FP32 row walk
+    ("box_13x6x5", lambda: synth.box_mesh(13, 6, 5), 1),                    # row walk
+]
+
+
+@pytest.mark.parametrize("name,mk,form", INNER_MESHES, ids=[c[0] for c in INNER_MESHES])
+def test_inner_product_forms_bitwise(L, name, mk, form):
+    """The inner FP32 product in the walk forms equals the one-row-per-thread
+    product bitwise (the FP32 coefficients do not depend on T, so one step of
+    each problem forms the same ones)."""
+    import torch
+    mesh = mk()
+    T0 = synth.initial_field(mesh.n_cells, 17)
+    x = torch.from_numpy(np.random.default_rng(5).uniform(-1.0, 1.0, mesh.n_cells).astype(np.float32)).cuda()
+    m = L.Mesh(mesh)
+    ys = []
+    for walk in (L.LF_WALK_ON, L.LF_WALK_OFF):
+        P = L.Problem(m, synth.fixed_x_bcs(), 2e-3, 1e-3,
+                      L.make_opts(amul_walk=walk, precision=L.LF_PREC_MIXED))
+        assert P.amul_form() == (form if walk == L.LF_WALK_ON else 0)
+        with pytest.raises(L.LapfoamError, match="LF_ESTATE"):
+            P.amul_inner(x, torch.empty_like(x))
+        P.set_T(T0)
+        P.step(1)
+        y = torch.full_like(x, float("nan"))
+        P.amul_inner(x, y)
+        torch.cuda.synchronize()
+        ys.append(y.cpu().numpy())
+        P.close()
+    assert np.array_equal(ys[0], ys[1]), name
+    assert np.all(np.isfinite(ys[0]))
     m.close()
