@@ -456,7 +456,8 @@ def run_serving(L, torch, args):
                        f"batched kernel, large sides on the multi-kernel solver",
            "tuning": tuning["block_threads"] if tuning else None,
            "budget_GiB": args.serve_budget_gib, "slots": args.serve_slots,
-           "direct_min_side": args.serve_direct_min or None, "direct_workers": args.serve_direct_workers}
+           "direct_min_side": args.serve_direct_min or None, "direct_workers": args.serve_direct_workers,
+           "direct_lane": "alone (lf_step_begin)" if args.serve_direct_alone else "group (lf_group)"}
     sides = sorted({r.n for r in base})
     cells = sum(r.n ** 3 for r in base)
 
@@ -466,7 +467,9 @@ def run_serving(L, torch, args):
                    slot_capacity=args.serve_capacity, max_steps=10, tuning=tuning,
                    direct_min_side=args.serve_direct_min or None,
                    direct_workers=args.serve_direct_workers,
-                   direct_use_graph=not args.serve_direct_no_graph)
+                   direct_use_graph=not args.serve_direct_no_graph,
+                   direct_group=not args.serve_direct_alone, group_iters=args.serve_group_iters,
+                   direct_streams=args.serve_direct_streams)
     for n in sides:
         srv.preload_mesh(n)
     torch.cuda.synchronize()
@@ -503,7 +506,9 @@ def run_serving(L, torch, args):
                          n_slots=args.serve_slots, slot_capacity=args.serve_capacity, max_steps=10,
                          tuning=tuning, direct_min_side=args.serve_direct_min or None,
                          direct_workers=args.serve_direct_workers,
-                         direct_use_graph=not args.serve_direct_no_graph)
+                         direct_use_graph=not args.serve_direct_no_graph,
+                         direct_group=not args.serve_direct_alone, group_iters=args.serve_group_iters,
+                   direct_streams=args.serve_direct_streams)
         srv = small
         summ = one(None, f"saturated, budget {args.serve_small_budget_gib} GiB")
         summ["budget_GiB"] = args.serve_small_budget_gib
@@ -547,10 +552,16 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-capacity", type=int, default=64)
-    ap.add_argument("--serve-direct-min", type=int, default=32,
+    ap.add_argument("--serve-direct-min", type=int, default=24,
                     help="requests with at least this cube side run on the multi-kernel solver (0 = never)")
-    ap.add_argument("--serve-direct-workers", type=int, default=8)
+    ap.add_argument("--serve-direct-workers", type=int, default=32)
     ap.add_argument("--serve-direct-no-graph", action="store_true")
+    ap.add_argument("--serve-direct-alone", action="store_true",
+                    help="direct lane without the group: each request alone (lf_step_begin/poll)")
+    ap.add_argument("--serve-direct-streams", type=int, default=4,
+                    help="streams of the grouped direct lane's own work (assembly, pass turns)")
+    ap.add_argument("--serve-group-iters", type=int, default=0,
+                    help="inner iterations per group block (0: the library default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()

@@ -313,8 +313,9 @@ lf_status lf_problem_destroy(lf_problem *problem);  /* NULL-safe */
 
 /* Re-targets an existing problem to new boundary conditions, DT and dt (same
  * mesh, options, workspace and stream; checks as in lf_problem_create).  T is
- * kept: set it with lf_set_T.  Returns after the new values are on the device
- * (synchronises the problem's stream only).  For callers that solve many
+ * kept: set it with lf_set_T.  Returns after the new values are on the device:
+ * when the patch conditions change it synchronises the problem's stream (only
+ * that one); DT and dt alone change without waiting.  For callers that solve many
  * problems of one mesh: destroying a problem frees pinned host memory, which
  * waits for the whole device.  Must not be called while a batch launch uses
  * the problem. */
@@ -451,6 +452,53 @@ lf_status lf_batch_wait(lf_batch *batch);
 /* After the launch finished: stats[n * n_steps] (problem-major) and the device
  * time of the launch in milliseconds (either may be NULL). */
 lf_status lf_batch_stats(lf_batch *batch, lf_solve_stats *stats, double *elapsed_ms);
+
+/* ---- grouped form --------------------------------------------------------
+ * Several LF_PREC_MIXED problems (diagonal preconditioner, orthogonal meshes,
+ * FP64 products one row per thread: lf_problem_amul_walk reports 0) stepped
+ * together, for many mid-size problems at once, each too small to fill the
+ * GPU (the serving stream's large requests): the inner FP32 iterations of
+ * every member that is iterating run as one launch per kernel (each member
+ * keeps its own workgroups, rows and partial sums), the assembly and the
+ * refinement's outer work run on each member's own stream.  Members join and
+ * leave at any time: lf_group_add starts a member's run of n_steps steps,
+ * lf_group_poll advances every member as far as finished device work allows
+ * (event queries only; it never waits) and hands back the members whose runs
+ * have finished.  A member's results (T after each step, stats) are bitwise
+ * those of lf_step on the same problem, alone or with any other members.
+ * Stats of a member report no times (assemble_ms = solve_ms = 0).  While a
+ * member runs it must not be stepped, reset, read, set or destroyed (those
+ * calls return LF_ESTATE).  The group workspace holds the members' descriptors
+ * and their gathered solver states; the group's own launches go to `stream`. */
+typedef struct lf_group lf_group;
+size_t lf_group_workspace_bytes(int32_t max_members);   /* max_members <= 32 */
+/* iters_per_block: inner iterations launched between two looks at the
+ * members' states (0: 2; members whose pass ends inside a block idle through
+ * the rest of it, so short blocks measured faster than long ones). */
+lf_status lf_group_create(int32_t max_members, int32_t iters_per_block, void *dev_workspace,
+                          size_t workspace_bytes, void *stream, lf_group **out);
+/* LF_ESTATE if members are still running (the group is kept). */
+lf_status lf_group_destroy(lf_group *group);    /* NULL-safe */
+/* Start n_steps >= 1 steps of problem p from T0 (device, N doubles in the
+ * mesh's cell order, copied on the problem's stream; NULL: from its current
+ * T).  T0 is not checked (a non-finite value ends the first step with a
+ * non-finite residual) and must stay valid until the problem's stream has
+ * copied it.  snapshots (device, [n_steps][N] in the mesh's cell order, may
+ * be NULL) receive T after each step; stats (host, [n_steps], may be NULL)
+ * receive each step's stats; both must stay valid until the member is handed
+ * back by lf_group_poll.
+ * LF_EINVAL: a problem the group cannot run (see above) or on another device;
+ * LF_ESTATE: the problem runs already (here, in another group or an
+ * lf_step_begin run); LF_EBUDGET: the group is full. */
+lf_status lf_group_add(lf_group *group, lf_problem *p, int32_t n_steps, const double *T0,
+                       double *snapshots, lf_solve_stats *stats);
+/* Advance; finished[0 .. *n_finished) receive the members whose runs finished
+ * since the last call (at most max_finished; the rest on the next call) and
+ * whose snapshots are complete; *n_active counts the members not yet handed
+ * back.  A member whose step ended with a non-finite residual finishes there
+ * (its stats say nonfinite).  LF_EDEVICE on a device error. */
+lf_status lf_group_poll(lf_group *group, lf_problem **finished, int32_t max_finished, int32_t *n_finished,
+                        int32_t *n_active);
 
 /* ---- per-kernel device timing (diagnostics) ------------------------------
  * When enabled, lf_step records a HIP event pair around every kernel launch on

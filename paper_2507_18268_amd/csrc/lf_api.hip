@@ -29,7 +29,7 @@ struct StepDriver {
 }  // namespace lf
 
 namespace lf {
-bool problem_in_flight(const lf_problem *P) { return P->async && P->async->active; }
+bool problem_in_flight(const lf_problem *P) { return (P->async && P->async->active) || P->group; }
 }  // namespace lf
 
 static bool async_running(const lf_problem *P) { return problem_in_flight(P); }
@@ -231,6 +231,7 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
 
 lf_status lf_problem_destroy(lf_problem *P) {
     if (!P) return LF_OK;
+    if (P->group) { set_error("the problem is a member of a group until its run finishes"); return LF_ESTATE; }
     if (P->async) {
         if (P->async->active) (void)hipStreamSynchronize(P->stream);   // a run still in flight
         delete P->async;
@@ -248,15 +249,24 @@ lf_status lf_problem_destroy(lf_problem *P) {
 lf_status lf_problem_reset(lf_problem *P, const lf_patch_bc *bcs, double DT, double dt) {
     clear_error();
     if (!P) { set_error("problem is NULL"); return LF_EINVAL; }
-    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
+    if (async_running(P)) { set_error("a run is in flight (lf_step_begin or a group)"); return LF_ESTATE; }
     const lf_mesh *m = P->mesh;
     LF_TRY(check_physics(m, bcs, DT, dt));
-    std::vector<int32_t> pt(std::max<int32_t>(m->P, 1), 0);
-    std::vector<double> pv(std::max<int32_t>(m->P, 1), 0.0);
-    for (int32_t p = 0; p < m->P; ++p) { pt[p] = bcs[p].type; pv[p] = bcs[p].value; }
-    LF_HIP(hipMemcpyAsync(P->patch_type, pt.data(), sizeof(int32_t) * pt.size(), hipMemcpyHostToDevice, P->stream));
-    LF_HIP(hipMemcpyAsync(P->patch_value, pv.data(), sizeof(double) * pv.size(), hipMemcpyHostToDevice, P->stream));
-    LF_HIP(hipStreamSynchronize(P->stream));
+    // DT and dt are kernel arguments; the patch conditions live on the device
+    // and are only rewritten (and waited for) when they change
+    bool same = static_cast<int32_t>(P->bcs.size()) == m->P;
+    for (int32_t p = 0; same && p < m->P; ++p)
+        same = P->bcs[p].type == bcs[p].type && std::memcmp(&P->bcs[p].value, &bcs[p].value, sizeof(double)) == 0;
+    if (!same) {
+        std::vector<int32_t> pt(std::max<int32_t>(m->P, 1), 0);
+        std::vector<double> pv(std::max<int32_t>(m->P, 1), 0.0);
+        for (int32_t p = 0; p < m->P; ++p) { pt[p] = bcs[p].type; pv[p] = bcs[p].value; }
+        LF_HIP(hipMemcpyAsync(P->patch_type, pt.data(), sizeof(int32_t) * pt.size(), hipMemcpyHostToDevice,
+                              P->stream));
+        LF_HIP(hipMemcpyAsync(P->patch_value, pv.data(), sizeof(double) * pv.size(), hipMemcpyHostToDevice,
+                              P->stream));
+        LF_HIP(hipStreamSynchronize(P->stream));
+    }
     P->bcs.assign(bcs, bcs + m->P);
     P->DT = DT;
     P->dt = dt;
@@ -331,7 +341,7 @@ static lf_status download_mesh_order(lf_problem *P, const double *src, double *h
 lf_status lf_set_T(lf_problem *P, const double *T, int32_t on_device) {
     clear_error();
     if (!P || !T) { set_error("NULL argument"); return LF_EINVAL; }
-    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
+    if (async_running(P)) { set_error("a run is in flight (lf_step_begin or a group)"); return LF_ESTATE; }
     const int32_t N = P->mesh->N;
     if (!on_device) {
         for (int32_t c = 0; c < N; ++c)
@@ -354,7 +364,7 @@ lf_status lf_set_T(lf_problem *P, const double *T, int32_t on_device) {
 lf_status lf_get_T(lf_problem *P, double *T, int32_t on_device) {
     clear_error();
     if (!P || !T) { set_error("NULL argument"); return LF_EINVAL; }
-    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
+    if (async_running(P)) { set_error("a run is in flight (lf_step_begin or a group)"); return LF_ESTATE; }
     if (on_device) return to_mesh_order(P, P->T, T);
     LF_TRY(download_mesh_order(P, P->T, T));
     LF_HIP(hipStreamSynchronize(P->stream));
@@ -376,7 +386,7 @@ __global__ void k_boundary_values(int32_t B, const int32_t *__restrict__ bface_c
 lf_status lf_get_boundary_T(lf_problem *P, double *Tb, int32_t on_device) {
     clear_error();
     if (!P || (!Tb && P->mesh->B > 0)) { set_error("NULL argument"); return LF_EINVAL; }
-    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
+    if (async_running(P)) { set_error("a run is in flight (lf_step_begin or a group)"); return LF_ESTATE; }
     const lf_mesh *m = P->mesh;
     if (m->B == 0) return LF_OK;
     double *dst = on_device ? Tb : P->Tb;
@@ -393,14 +403,14 @@ lf_status lf_get_boundary_T(lf_problem *P, double *Tb, int32_t on_device) {
 lf_status lf_problem_grad(lf_problem *P, double *grad, double *bgrad) {
     clear_error();
     if (!P || !grad) { set_error("NULL argument"); return LF_EINVAL; }
-    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
+    if (async_running(P)) { set_error("a run is in flight (lf_step_begin or a group)"); return LF_ESTATE; }
     return launch_problem_grad(P, grad, bgrad);
 }
 
 lf_status lf_assemble(lf_problem *P) {
     clear_error();
     if (!P) { set_error("NULL problem"); return LF_EINVAL; }
-    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
+    if (async_running(P)) { set_error("a run is in flight (lf_step_begin or a group)"); return LF_ESTATE; }
     LF_TRY(launch_assemble(P, true, P->stream));
     P->assembled = true;
     return LF_OK;
@@ -410,7 +420,7 @@ lf_status lf_get_matrix(lf_problem *P, double *diag, double *upper, double *sour
                         double *source_b, double *int_coeff, double *bou_coeff) {
     clear_error();
     if (!P) { set_error("NULL problem"); return LF_EINVAL; }
-    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
+    if (async_running(P)) { set_error("a run is in flight (lf_step_begin or a group)"); return LF_ESTATE; }
     if (!P->assembled) { set_error("call lf_assemble first"); return LF_ESTATE; }
     const lf_mesh *m = P->mesh;
     hipStream_t s = P->stream;
@@ -430,7 +440,7 @@ lf_status lf_get_matrix(lf_problem *P, double *diag, double *upper, double *sour
 lf_status lf_amul(lf_problem *P, const double *x, double *y) {
     clear_error();
     if (!P || !x || !y) { set_error("NULL argument"); return LF_EINVAL; }
-    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
+    if (async_running(P)) { set_error("a run is in flight (lf_step_begin or a group)"); return LF_ESTATE; }
     if (!P->assembled) { set_error("call lf_assemble first"); return LF_ESTATE; }
     if (!P->mesh->iperm) return launch_amul_hook(P, x, y);
     LF_TRY(to_solver_order(P, x, P->p2));
@@ -442,7 +452,7 @@ lf_status lf_amul_inner(lf_problem *P, const float *x, float *y) {
     clear_error();
     if (!P || !x || !y) { set_error("NULL argument"); return LF_EINVAL; }
     if (P->opts.precision != LF_PREC_MIXED) { set_error("the mixed-precision form's inner product only"); return LF_EINVAL; }
-    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
+    if (async_running(P)) { set_error("a run is in flight (lf_step_begin or a group)"); return LF_ESTATE; }
     if (!P->scaled32) { set_error("no step has formed the FP32 coefficients yet"); return LF_ESTATE; }
     return launch_amul_inner_hook(P, x, y);
 }
@@ -450,7 +460,7 @@ lf_status lf_amul_inner(lf_problem *P, const float *x, float *y) {
 lf_status lf_precondition(lf_problem *P, const double *r, double *w) {
     clear_error();
     if (!P || !r || !w) { set_error("NULL argument"); return LF_EINVAL; }
-    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
+    if (async_running(P)) { set_error("a run is in flight (lf_step_begin or a group)"); return LF_ESTATE; }
     if (!P->assembled) { set_error("call lf_assemble first"); return LF_ESTATE; }
     if (P->opts.precision != LF_PREC_FP64) { set_error("the FP64 solver's preconditioner only"); return LF_EINVAL; }
     LF_TRY(to_solver_order(P, r, P->r));
@@ -557,7 +567,7 @@ static lf_status advance(StepDriver &d) {
 lf_status lf_step(lf_problem *P, int32_t n_steps, lf_solve_stats *stats) {
     clear_error();
     if (!P || n_steps < 0) { set_error("bad argument"); return LF_EINVAL; }
-    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
+    if (async_running(P)) { set_error("a run is in flight (lf_step_begin or a group)"); return LF_ESTATE; }
     if (n_steps == 0) return LF_OK;
     StepDriver d;
     d.P = P;
@@ -617,7 +627,7 @@ lf_status lf_step_many(lf_problem *const *problems, int32_t n, int32_t n_steps, 
 lf_status lf_step_begin(lf_problem *P, int32_t n_steps, double *snapshots) {
     clear_error();
     if (!P || n_steps < 1) { set_error("bad argument"); return LF_EINVAL; }
-    if (async_running(P)) { set_error("an lf_step_begin run is in flight"); return LF_ESTATE; }
+    if (async_running(P)) { set_error("a run is in flight (lf_step_begin or a group)"); return LF_ESTATE; }
     if (!P->async) {
         P->async = new (std::nothrow) StepDriver();
         if (!P->async) { set_error("host allocation failed"); return LF_ENOMEM; }

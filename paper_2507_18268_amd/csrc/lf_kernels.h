@@ -46,20 +46,30 @@ __device__ __forceinline__ void block_sum(double (&v)[NQ]) {
 // row t of each tile (each load of a wavefront stays one contiguous 64-row
 // access, and a thread has R independent rows in flight).
 template <int R>
+__device__ __forceinline__ int32_t cell_row_at(int32_t blk, int j) {
+    return (blk * R + j) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+}
+template <int R>
 __device__ __forceinline__ int32_t cell_row(int j) {
-    return (static_cast<int32_t>(blockIdx.x) * R + j) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+    return cell_row_at<R>(static_cast<int32_t>(blockIdx.x), j);
 }
 
 // first stage: the workgroup's partial sums go to part[slot * G + blockIdx.x]
-// (BS: threads of the workgroup)
+// (BS: threads of the workgroup; _at: the workgroup's index blk within its
+// problem's launch, for launches that serve several problems)
 template <int NQ, int BS = kCellBlock>
-__device__ __forceinline__ void write_partials(double *__restrict__ part, int32_t G, const int (&slot)[NQ],
-                                               double (&v)[NQ]) {
+__device__ __forceinline__ void write_partials_at(double *__restrict__ part, int32_t G, int32_t blk,
+                                                  const int (&slot)[NQ], double (&v)[NQ]) {
     block_sum<BS, NQ>(v);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) part[slot[q] * G + blockIdx.x] = v[q];
+        for (int q = 0; q < NQ; ++q) part[slot[q] * G + blk] = v[q];
     }
+}
+template <int NQ, int BS = kCellBlock>
+__device__ __forceinline__ void write_partials(double *__restrict__ part, int32_t G, const int (&slot)[NQ],
+                                               double (&v)[NQ]) {
+    write_partials_at<NQ, BS>(part, G, static_cast<int32_t>(blockIdx.x), slot, v);
 }
 
 // second stage (one workgroup of kFinBlock threads): fixed-order sums of the
@@ -217,6 +227,31 @@ struct RBLayout {
     RBForm f;
     const double *__restrict__ mag_sf;   // [6 nr], 0 where the face does not exist
     const double *__restrict__ delta;    // [6 nr]
+};
+
+// One problem of a group launch (several problems' inner FP32 iterations in
+// one launch per kernel): its parameters, layout (kind 0: the sliced rows mr;
+// K > 0: K bands with offsets d) and vectors.
+struct InnerMember {
+    SolverParams sp;
+    int32_t kind;
+    int32_t n;
+    int32_t d[4];
+    MeshRows mr;
+    const float *coef32, *sig32;
+    float *r32, *p32, *d32, *q32;
+    double *part;
+    PcgState *st;
+};
+
+constexpr int kGroupMax = 32;   // problems of one group
+
+// the members of one group launch: table slots and their first workgroups
+// (begin[n] = the launch's workgroups)
+struct GroupLaunch {
+    int32_t n;
+    int32_t slot[kGroupMax];
+    int32_t begin[kGroupMax + 1];
 };
 
 // Row c's entries: coefficient slot, column and whether the entry may hold a

@@ -116,9 +116,10 @@ k_mx_scale(SolverParams sp, Lay L, const float *__restrict__ sig32, const double
 // first inner iteration of a pass: p = rs, or, continuing the previous pass's
 // CG, p = gamma rs + beta p; later: y += alpha p (the previous iteration's
 // update), then p = rs + beta p; all FP32
-__global__ void __launch_bounds__(kCellBlock)
-k_mx_direction(SolverParams sp, const float *__restrict__ r32, float *__restrict__ p32, float *__restrict__ d32,
-               const PcgState *__restrict__ st) {
+// (workgroup blk of the problem's launch)
+__device__ __forceinline__ void mx_direction(int32_t blk, const SolverParams &sp, const float *__restrict__ r32,
+                                             float *__restrict__ p32, float *__restrict__ d32,
+                                             const PcgState *__restrict__ st) {
     if (inner_off(st)) return;
     const bool first = st->inner_iter == 0;
     const bool cont = st->inner_cont != 0;
@@ -127,7 +128,7 @@ k_mx_direction(SolverParams sp, const float *__restrict__ r32, float *__restrict
     const float gamma = static_cast<float>(st->gamma);
 #pragma unroll
     for (int j = 0; j < kMxRows; ++j) {
-        const int32_t c = cell_row<kMxRows>(j);
+        const int32_t c = cell_row_at<kMxRows>(blk, j);
         if (c >= sp.n) continue;
         const float rc = r32[c];
         if (first) {
@@ -141,17 +142,24 @@ k_mx_direction(SolverParams sp, const float *__restrict__ r32, float *__restrict
     }
 }
 
+__global__ void __launch_bounds__(kCellBlock)
+k_mx_direction(SolverParams sp, const float *__restrict__ r32, float *__restrict__ p32, float *__restrict__ d32,
+               const PcgState *__restrict__ st) {
+    mx_direction(static_cast<int32_t>(blockIdx.x), sp, r32, p32, d32, st);
+}
+
 // q = As p in FP32 (unit diagonal: p_c first, then the row's entries in
 // order); FP64 partial sums of p.q
 template <class Lay>
-__global__ void __launch_bounds__(kCellBlock)
-k_mx_amul_dot(SolverParams sp, Lay L, const float *__restrict__ coef32, const float *__restrict__ p32,
-              float *__restrict__ q32, double *__restrict__ part, const PcgState *__restrict__ st) {
+__device__ __forceinline__ void mx_amul_dot(int32_t blk, const SolverParams &sp, const Lay &L,
+                                            const float *__restrict__ coef32, const float *__restrict__ p32,
+                                            float *__restrict__ q32, double *__restrict__ part,
+                                            const PcgState *__restrict__ st) {
     if (inner_off(st)) return;
     double acc[1] = {0.0};
 #pragma unroll
     for (int j = 0; j < kMxRows; ++j) {
-        const int32_t c = cell_row<kMxRows>(j);
+        const int32_t c = cell_row_at<kMxRows>(blk, j);
         if (c >= sp.n) continue;
         const float pc = p32[c];
         const float qc = layout_dot(L, c, coef32, p32, pc);
@@ -159,7 +167,14 @@ k_mx_amul_dot(SolverParams sp, Lay L, const float *__restrict__ coef32, const fl
         acc[0] += static_cast<double>(qc) * static_cast<double>(pc);
     }
     const int slots[1] = {kPartPq};
-    write_partials<1>(part, sp.grid_mx, slots, acc);
+    write_partials_at<1>(part, sp.grid_mx, blk, slots, acc);
+}
+
+template <class Lay>
+__global__ void __launch_bounds__(kCellBlock)
+k_mx_amul_dot(SolverParams sp, Lay L, const float *__restrict__ coef32, const float *__restrict__ p32,
+              float *__restrict__ q32, double *__restrict__ part, const PcgState *__restrict__ st) {
+    mx_amul_dot(static_cast<int32_t>(blockIdx.x), sp, L, coef32, p32, q32, part, st);
 }
 
 // the same product by the row walk (band layouts with two or more bands):
@@ -195,15 +210,15 @@ k_mx_amul_dot_box(SolverParams sp, BandLayout<3> L, BoxWalk bw, const float *__r
 }
 
 // rs -= alpha q (FP32); FP64 partials of the L1 norm s|rs| and of rs.rs
-__global__ void __launch_bounds__(kCellBlock)
-k_mx_update(SolverParams sp, const float *__restrict__ q32, const float *__restrict__ sig32,
-            float *__restrict__ r32, double *__restrict__ part, const PcgState *__restrict__ st) {
+__device__ __forceinline__ void mx_update(int32_t blk, const SolverParams &sp, const float *__restrict__ q32,
+                                          const float *__restrict__ sig32, float *__restrict__ r32,
+                                          double *__restrict__ part, const PcgState *__restrict__ st) {
     if (inner_off(st)) return;
     const float alpha = static_cast<float>(st->alpha);
     double acc[2] = {0.0, 0.0};
 #pragma unroll
     for (int j = 0; j < kMxRows; ++j) {
-        const int32_t c = cell_row<kMxRows>(j);
+        const int32_t c = cell_row_at<kMxRows>(blk, j);
         if (c >= sp.n) continue;
         const float rc = r32[c] - alpha * __builtin_nontemporal_load(&q32[c]);
         r32[c] = rc;
@@ -211,7 +226,13 @@ k_mx_update(SolverParams sp, const float *__restrict__ q32, const float *__restr
         acc[1] += static_cast<double>(rc) * static_cast<double>(rc);
     }
     const int slots[2] = {kPartSumR, kPartWr};
-    write_partials<2>(part, sp.grid_mx, slots, acc);
+    write_partials_at<2>(part, sp.grid_mx, blk, slots, acc);
+}
+
+__global__ void __launch_bounds__(kCellBlock)
+k_mx_update(SolverParams sp, const float *__restrict__ q32, const float *__restrict__ sig32,
+            float *__restrict__ r32, double *__restrict__ part, const PcgState *__restrict__ st) {
+    mx_update(static_cast<int32_t>(blockIdx.x), sp, q32, sig32, r32, part, st);
 }
 
 // T += d = (y + alpha p) / s in FP64, alpha p being the last inner update
@@ -306,8 +327,8 @@ k_mx_residual_box(SolverParams sp, BandLayout<3> L, BoxWalk bw, const double *__
 enum MxFin : int { kMxInnerStart = 0, kMxAlpha = 1, kMxBeta = 2, kMxOuter = 3 };
 
 template <int Mode>
-__global__ void __launch_bounds__(kFinBlock) k_mx_finalize(SolverParams sp, const double *__restrict__ part,
-                                                          PcgState *__restrict__ st) {
+__device__ __forceinline__ void mx_finalize(const SolverParams &sp, const double *__restrict__ part,
+                                            PcgState *__restrict__ st) {
     // partials per slot: the FP32 inner kernels use their own grid
     const int32_t G = (Mode == kMxAlpha || Mode == kMxBeta) ? sp.grid_mx : sp.grid;
     if (Mode == kMxInnerStart) {
@@ -401,6 +422,108 @@ __global__ void __launch_bounds__(kFinBlock) k_mx_finalize(SolverParams sp, cons
             }
         }
     }
+}
+
+template <int Mode>
+__global__ void __launch_bounds__(kFinBlock) k_mx_finalize(SolverParams sp, const double *__restrict__ part,
+                                                          PcgState *__restrict__ st) {
+    mx_finalize<Mode>(sp, part, st);
+}
+
+// ---------------------------------------------------------------------------
+// The inner iteration of several problems in one launch per kernel (a group:
+// lf_group_*).  Member i of a launch takes its workgroups gl.begin[i] ..
+// gl.begin[i+1] - 1, which run the same rows and write the same partials as
+// workgroups 0 .. of its own launch; the finalize launches take one workgroup
+// per member.  Each problem's arithmetic and sums are therefore those of its
+// own launches, whatever else shares the launch.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t group_member(const GroupLaunch &gl, int32_t b) {
+    int32_t i = 0;
+    while (i + 1 < gl.n && b >= gl.begin[i + 1]) ++i;
+    return i;
+}
+
+__global__ void __launch_bounds__(kCellBlock)
+k_grp_direction(const InnerMember *__restrict__ tab, GroupLaunch gl) {
+    const int32_t b = static_cast<int32_t>(blockIdx.x), i = group_member(gl, b);
+    const InnerMember &m = tab[gl.slot[i]];
+    mx_direction(b - gl.begin[i], m.sp, m.r32, m.p32, m.d32, m.st);
+}
+
+__global__ void __launch_bounds__(kCellBlock)
+k_grp_amul_dot(const InnerMember *__restrict__ tab, GroupLaunch gl) {
+    const int32_t b = static_cast<int32_t>(blockIdx.x), i = group_member(gl, b);
+    const InnerMember &m = tab[gl.slot[i]];
+    const int32_t blk = b - gl.begin[i];
+    switch (m.kind) {
+        case 0: {
+            SellLayout L{m.mr, nullptr, nullptr, nullptr, nullptr};
+            mx_amul_dot(blk, m.sp, L, m.coef32, m.p32, m.q32, m.part, m.st);
+            break;
+        }
+        case 1: mx_amul_dot(blk, m.sp, BandLayout<1>{m.n, {m.d[0]}, nullptr, nullptr}, m.coef32, m.p32, m.q32, m.part, m.st); break;
+        case 2: mx_amul_dot(blk, m.sp, BandLayout<2>{m.n, {m.d[0], m.d[1]}, nullptr, nullptr}, m.coef32, m.p32, m.q32, m.part, m.st); break;
+        case 3: mx_amul_dot(blk, m.sp, BandLayout<3>{m.n, {m.d[0], m.d[1], m.d[2]}, nullptr, nullptr}, m.coef32, m.p32, m.q32, m.part, m.st); break;
+        default: mx_amul_dot(blk, m.sp, BandLayout<4>{m.n, {m.d[0], m.d[1], m.d[2], m.d[3]}, nullptr, nullptr}, m.coef32, m.p32, m.q32, m.part, m.st); break;
+    }
+}
+
+__global__ void __launch_bounds__(kCellBlock)
+k_grp_update(const InnerMember *__restrict__ tab, GroupLaunch gl) {
+    const int32_t b = static_cast<int32_t>(blockIdx.x), i = group_member(gl, b);
+    const InnerMember &m = tab[gl.slot[i]];
+    mx_update(b - gl.begin[i], m.sp, m.q32, m.sig32, m.r32, m.part, m.st);
+}
+
+template <int Mode>
+__global__ void __launch_bounds__(kFinBlock) k_grp_finalize(const InnerMember *__restrict__ tab, GroupLaunch gl) {
+    const InnerMember &m = tab[gl.slot[blockIdx.x]];
+    mx_finalize<Mode>(m.sp, m.part, m.st);
+}
+
+// every member's solver state into out[slot]
+__global__ void k_grp_gather(const InnerMember *__restrict__ tab, GroupLaunch gl, PcgState *__restrict__ out) {
+    const int32_t i = static_cast<int32_t>(blockIdx.x);
+    const int32_t n = static_cast<int32_t>(sizeof(PcgState) / sizeof(int32_t));
+    const int32_t *src = reinterpret_cast<const int32_t *>(tab[gl.slot[i]].st);
+    int32_t *dst = reinterpret_cast<int32_t *>(out + gl.slot[i]);
+    for (int32_t t = threadIdx.x; t < n; t += blockDim.x) dst[t] = src[t];
+}
+
+// one inner iteration of the launch's members (grid sizes from gl)
+void launch_group_iteration(const InnerMember *tab, const GroupLaunch &gl, hipStream_t s) {
+    const dim3 blk(kCellBlock), fin(kFinBlock), cells(static_cast<unsigned>(gl.begin[gl.n])),
+        each(static_cast<unsigned>(gl.n));
+    hipLaunchKernelGGL(k_grp_direction, cells, blk, 0, s, tab, gl);
+    hipLaunchKernelGGL(k_grp_amul_dot, cells, blk, 0, s, tab, gl);
+    hipLaunchKernelGGL(k_grp_finalize<kMxAlpha>, each, fin, 0, s, tab, gl);
+    hipLaunchKernelGGL(k_grp_update, cells, blk, 0, s, tab, gl);
+    hipLaunchKernelGGL(k_grp_finalize<kMxBeta>, each, fin, 0, s, tab, gl);
+}
+
+void launch_group_gather(const InnerMember *tab, const GroupLaunch &gl, PcgState *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_grp_gather, dim3(static_cast<unsigned>(gl.n)), dim3(64), 0, s, tab, gl, out);
+}
+
+// the descriptor of a problem's inner solve
+InnerMember inner_member(const lf_problem *P) {
+    InnerMember m{};
+    const lf_mesh *msh = P->mesh;
+    m.sp = P->sp;
+    m.kind = P->banded ? msh->n_bands : 0;
+    m.n = msh->N;
+    for (int k = 0; k < 4; ++k) m.d[k] = k < msh->n_bands ? msh->band_d[k] : 0;
+    m.mr = mesh_rows(msh);
+    m.coef32 = P->coef32;
+    m.sig32 = P->sig32;
+    m.r32 = P->r32;
+    m.p32 = P->p32;
+    m.d32 = P->d32;
+    m.q32 = P->q32;
+    m.part = P->part;
+    m.st = P->state;
+    return m;
 }
 
 template <int Mode>
@@ -646,6 +769,25 @@ lf_status mixed_advance(lf_problem *P, SolveCtx &c, bool *finished, lf_solve_sta
     LF_HIP(hipGetLastError());
     if (adaptive) c.k = predicted_inner(P, pass + 1);
     return mixed_block(P, c);
+}
+
+// the enqueued work of a problem's step in a group (on its own stream): the
+// assembly, the start of the solve and of its first refinement pass; and
+// between passes, the end of one pass and the start of the next (no-ops once
+// the solve is done)
+lf_status mixed_enqueue_step_start(lf_problem *P, hipStream_t s) {
+    LF_TRY(launch_assemble_setup(P, s));
+    launch_fin<kFinStart>(P, s);
+    launch_pass_start(P, s);
+    LF_HIP(hipGetLastError());
+    return LF_OK;
+}
+
+lf_status mixed_enqueue_pass_turn(lf_problem *P, hipStream_t s) {
+    launch_pass_end(P, s);
+    launch_pass_start(P, s);
+    LF_HIP(hipGetLastError());
+    return LF_OK;
 }
 
 }  // namespace lf

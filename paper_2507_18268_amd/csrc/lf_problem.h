@@ -110,6 +110,7 @@ struct AmgLevel {
 struct lf_problem {
     const lf_mesh *mesh = nullptr;
     lf::StepDriver *async = nullptr;           // lf_step_begin's run (null when none has started)
+    lf_group *group = nullptr;                 // the group running it (lf_group_add .. finished)
     lf_solver_opts opts{};
     double DT = 0, dt = 0;
     hipStream_t stream = nullptr;

@@ -90,6 +90,12 @@ lf_status launch_assemble_setup(lf_problem *P, hipStream_t s);
 // precision form: FP32 coefficients of the scaled matrix, after the assembly
 void launch_mx_scale(lf_problem *P, hipStream_t s);
 lf_status launch_amul_inner_hook(lf_problem *P, const float *x, float *y);
+// groups (lf_group.hip): inner iterations of several problems per launch
+InnerMember inner_member(const lf_problem *P);
+void launch_group_iteration(const InnerMember *tab, const GroupLaunch &gl, hipStream_t s);
+void launch_group_gather(const InnerMember *tab, const GroupLaunch &gl, PcgState *out, hipStream_t s);
+lf_status mixed_enqueue_step_start(lf_problem *P, hipStream_t s);
+lf_status mixed_enqueue_pass_turn(lf_problem *P, hipStream_t s);
 // non-orthogonal meshes: boundary values and gradient of T, then P->lap_src
 // (lf_grad.hip); runs before the assembly of each step
 void launch_nonorth_source(lf_problem *P, hipStream_t s);

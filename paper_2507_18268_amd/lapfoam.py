@@ -112,6 +112,13 @@ _SIGS = {
     "lf_grad_noalloc": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 5),
     "lf_amul_inner": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lf_problem_grad": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lf_group_workspace_bytes": (C.c_size_t, [C.c_int32]),
+    "lf_group_create": (C.c_int32, [C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                                    C.POINTER(C.c_void_p)]),
+    "lf_group_destroy": (C.c_int32, [C.c_void_p]),
+    "lf_group_add": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lf_group_poll": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_int32)]),
     "lf_batch_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
     "lf_batch_create": (C.c_int32, [C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
                                     C.POINTER(C.c_void_p)]),
@@ -335,6 +342,35 @@ def lf_profile_read(h, n=16):
     _check(lib().lf_profile_read(h, C.c_int32(n), C.c_void_p(ms.ctypes.data),
                                  C.c_void_p(cnt.ctypes.data)), "lf_profile_read")
     return ms, cnt
+
+
+def lf_group_workspace_bytes(max_members):
+    return int(lib().lf_group_workspace_bytes(C.c_int32(max_members)))
+
+
+def lf_group_create(max_members, iters_per_block, ws_ptr, ws_bytes, stream):
+    h = C.c_void_p()
+    _check(lib().lf_group_create(C.c_int32(max_members), C.c_int32(iters_per_block), C.c_void_p(ws_ptr),
+                                 C.c_size_t(ws_bytes), C.c_void_p(stream), C.byref(h)), "lf_group_create")
+    return h
+
+
+def lf_group_destroy(h):
+    _check(lib().lf_group_destroy(h), "lf_group_destroy")
+
+
+def lf_group_add(h, problem_h, n_steps, T0_ptr, snapshots_ptr, stats_array):
+    _check(lib().lf_group_add(h, problem_h, C.c_int32(n_steps), C.c_void_p(T0_ptr or None),
+                              C.c_void_p(snapshots_ptr or None),
+                              C.cast(stats_array, C.c_void_p) if stats_array is not None else None),
+           "lf_group_add")
+
+
+def lf_group_poll(h, max_finished=64):
+    out = (C.c_void_p * max(max_finished, 1))()
+    nf, na = C.c_int32(0), C.c_int32(0)
+    _check(lib().lf_group_poll(h, out, C.c_int32(max_finished), C.byref(nf), C.byref(na)), "lf_group_poll")
+    return [out[i] for i in range(nf.value)], na.value
 
 
 def lf_batch_workspace_bytes(max_tasks, max_steps):
@@ -634,6 +670,50 @@ class Problem:
     def close(self):
         if getattr(self, "h", None):
             lf_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Group:
+    """Problems stepped together: their inner FP32 iterations share launches
+    (lf_group_*).  add() starts a member's run; poll() advances every member
+    without waiting and returns [(problem, stats list)] of the finished runs."""
+
+    def __init__(self, max_members, iters_per_block=0, stream=None):
+        torch = _torch()
+        self.max_members = max_members
+        self.ws_bytes = lf_group_workspace_bytes(max_members)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device="cuda")
+        self.stream_obj = stream
+        self.stream = _stream_ptr(stream)
+        self.h = lf_group_create(max_members, iters_per_block, self.ws.data_ptr(), self.ws_bytes, self.stream)
+        self._runs = {}            # problem handle value -> (problem, stats array, snapshots)
+
+    def add(self, problem, n_steps, snapshots=None, T0=None):
+        """Start problem's run of n_steps steps from T0 (device float64 tensor
+        in mesh order, kept alive here until the run finishes) or its current T."""
+        stats = (lf_solve_stats * n_steps)()
+        lf_group_add(self.h, problem.h, n_steps, T0.data_ptr() if T0 is not None else 0,
+                     snapshots.data_ptr() if snapshots is not None else 0, stats)
+        self._runs[problem.h.value] = (problem, stats, snapshots, T0)
+
+    def poll(self):
+        handles, active = lf_group_poll(self.h, self.max_members)
+        done = []
+        for hv in handles:
+            problem, stats, _, _ = self._runs.pop(hv)
+            done.append((problem, [s.as_dict() for s in stats]))
+        self.active = active
+        return done
+
+    def close(self):
+        if getattr(self, "h", None):
+            lf_group_destroy(self.h)
             self.h = None
 
     def __del__(self):

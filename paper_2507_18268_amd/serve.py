@@ -22,13 +22,18 @@ batched-kernel task table:
   results on the host) is recorded.
 
 Large requests can instead take the direct lane: up to direct_workers of them
-at a time, each on a stream of its own and with its own pool of problems, run
-all their steps with the multi-kernel solver (the whole GPU's bandwidth for one
-problem, coefficients in the band layout where the mesh allows), T being copied
-after each step into the snapshot buffer.  A request's run starts when it is
-admitted (lf_step_begin) and every scheduling pass advances each running one as
-far as its finished device work allows (lf_step_poll, which never waits), so a
-small request does not wait for a large one's steps.
+at a time, each with its own pool of problems, run all their steps with the
+multi-kernel solver (many workgroups per problem, coefficients in the band
+layout where the mesh allows), T being copied after each step into the
+snapshot buffer.  By default the lane is a group (lf_group): the inner FP32
+iterations of every running direct request go out as one launch per kernel,
+so a mid-size request no longer pays a dependent launch per kernel of its own;
+its assembly and pass turns run on one of a few lane streams.  A request's run
+starts when it is admitted (lf_group_add) and every scheduling pass advances
+the group as far as its finished device work allows (lf_group_poll, which
+never waits), so a small request does not wait for a large one's steps.
+(direct_group=False runs each request alone with lf_step_begin/lf_step_poll
+on a stream of its own.)
 One workgroup is far too little for a large mesh, so this cuts both their
 latency and the time the batched slots spend waiting for them.  The lane runs
 on the scheduling thread: polling returns at once, and no second host thread
@@ -108,7 +113,7 @@ class _Direct:
 class Server:
     def __init__(self, mesh_for_side, budget_bytes, n_slots=4, slot_capacity=64, max_steps=10,
                  tuning=None, direct_min_side=None, direct_workers=4, batch_max_running=None,
-                 direct_use_graph=True):
+                 direct_use_graph=True, direct_group=True, direct_streams=4, group_iters=0):
         import torch
         self.torch = torch
         # A batched workgroup holds its CU for a whole problem; with the direct
@@ -132,8 +137,20 @@ class Server:
         self.direct_min_side = direct_min_side
         self.direct_use_graph = direct_use_graph
         nd = direct_workers if direct_min_side is not None else 0
-        self.direct_streams = [torch.cuda.Stream() for _ in range(nd)]
+        # grouped lane: the running direct requests' inner iterations share
+        # launches (lf_group); their own work (assembly, pass turns) goes to a
+        # few streams, worker k on stream k % direct_streams
+        self.group = None
+        if nd and direct_group:
+            self.group_stream = torch.cuda.Stream()
+            self.group = L.Group(nd, iters_per_block=group_iters, stream=self.group_stream)
+            ns = max(1, min(nd, int(direct_streams)))
+            pool = [torch.cuda.Stream() for _ in range(ns)]
+            self.direct_streams = [pool[k % ns] for k in range(nd)]
+        else:
+            self.direct_streams = [torch.cuda.Stream() for _ in range(nd)]
         self.direct_slot: List[Optional[_Direct]] = [None] * nd
+        self.draining = []                            # direct results on their way to the host
         self.idle: Dict[tuple, List[object]] = collections.defaultdict(list)   # key -> idle problems
         self.meshes: Dict[int, object] = {}          # side -> L.Mesh
         self.mesh_bytes: Dict[int, int] = {}
@@ -289,7 +306,7 @@ class Server:
 
     def _anything_live(self):
         return bool(self.ready) or any(d is not None for d in self.direct_slot) or \
-            any(s is not None for s in self.slot_live)
+            any(s is not None for s in self.slot_live) or bool(self.draining)
 
     # -------------------------------------------------------------- batched lane
     def _launch(self):
@@ -345,9 +362,17 @@ class Server:
                 P = L.Problem(mesh, req.bcs, req.DT, req.dt, self._opts(True, mesh), stream=st)
             else:
                 P.reset(req.bcs, req.DT, req.dt)
-            self._upload_T(P, req.T0)
             snap = torch.empty((req.steps, mesh.n_cells), dtype=torch.float64, device="cuda")
-            P.step_begin(req.steps, snap)        # the whole run; _step_direct advances it
+            if self.group is not None:
+                # T0 goes up on the lane's stream and the group copies it into
+                # the problem there: no wait on the host
+                h = torch.from_numpy(np.ascontiguousarray(req.T0, dtype=np.float64)).pin_memory()
+                T0 = torch.empty(h.shape, dtype=torch.float64, device="cuda")
+                T0.copy_(h, non_blocking=True)
+                self.group.add(P, req.steps, snap, T0=T0)   # the whole run; _step_direct advances the group
+            else:
+                self._upload_T(P, req.T0)
+                P.step_begin(req.steps, snap)        # the whole run; _step_direct advances it
         req.launched = self.now()
         self.direct_slot[k] = _Direct(req, P, snap, snap_bytes, key, k, 0, [])
 
@@ -356,6 +381,38 @@ class Server:
         work allows (lf_step_poll: no waiting) and finish those whose last step
         is done."""
         torch = self.torch
+        if self.group is not None:
+            # snapshots on their way to the host: finished once their copy is
+            for item in list(self.draining):
+                ev, req, snap, host, snap_bytes = item
+                if not ev.query():
+                    continue
+                self.draining.remove(item)
+                req.snapshots = host.numpy().reshape(req.steps, -1)
+                self._finish(req, snap_bytes)
+            done = self.group.poll()
+            if not done:
+                return
+            by_problem = {id(d.problem): k for k, d in enumerate(self.direct_slot) if d is not None}
+            for P, stats in done:
+                k = by_problem[id(P)]
+                d = self.direct_slot[k]
+                req = d.req
+                self.idle[d.key].append(d.problem)
+                self.direct_slot[k] = None
+                if any(st["nonfinite"] for st in stats):
+                    req.error = "direct lane: non-finite residual"
+                    self._finish(req, d.snap_bytes)
+                    continue
+                req.stats = stats
+                st = self.direct_streams[k]
+                host = torch.empty(d.snap.shape, dtype=d.snap.dtype, pin_memory=True)
+                with torch.cuda.stream(st):
+                    host.copy_(d.snap, non_blocking=True)
+                    ev = torch.cuda.Event()
+                    ev.record(st)
+                self.draining.append((ev, req, d.snap, host, d.snap_bytes))
+            return
         for k, d in enumerate(self.direct_slot):
             if d is None:
                 continue
@@ -408,6 +465,9 @@ class Server:
         return self.finished
 
     def close(self):
+        if self.group is not None:
+            self.group.close()
+            self.group = None
         for key in list(self.idle):
             self._close_idle(key)
         for b in self.batches:
