@@ -457,10 +457,9 @@ lf_status lf_batch_stats(lf_batch *batch, lf_solve_stats *stats, double *elapsed
  * Several LF_PREC_MIXED problems (diagonal preconditioner, orthogonal meshes,
  * FP64 products one row per thread: lf_problem_amul_walk reports 0) stepped
  * together, for many mid-size problems at once, each too small to fill the
- * GPU (the serving stream's large requests): the inner FP32 iterations of
- * every member that is iterating run as one launch per kernel (each member
- * keeps its own workgroups, rows and partial sums), the assembly and the
- * refinement's outer work run on each member's own stream.  Members join and
+ * GPU (the serving stream's large requests): every kernel of their steps runs
+ * as one launch for all members that need it at that point (each member keeps
+ * its own workgroups, rows and partial sums), on the group's stream.  Members join and
  * leave at any time: lf_group_add starts a member's run of n_steps steps,
  * lf_group_poll advances every member as far as finished device work allows
  * (event queries only; it never waits) and hands back the members whose runs
@@ -480,13 +479,13 @@ lf_status lf_group_create(int32_t max_members, int32_t iters_per_block, void *de
 /* LF_ESTATE if members are still running (the group is kept). */
 lf_status lf_group_destroy(lf_group *group);    /* NULL-safe */
 /* Start n_steps >= 1 steps of problem p from T0 (device, N doubles in the
- * mesh's cell order, copied on the problem's stream; NULL: from its current
- * T).  T0 is not checked (a non-finite value ends the first step with a
- * non-finite residual) and must stay valid until the problem's stream has
- * copied it.  snapshots (device, [n_steps][N] in the mesh's cell order, may
+ * mesh's cell order, copied by the group's next launch, after the work
+ * already queued on the problem's stream; NULL: from its current T).  T0 is
+ * not checked (a non-finite value ends the first step with a non-finite
+ * residual).  T0, snapshots and stats must stay valid until the member is
+ * handed back.  snapshots (device, [n_steps][N] in the mesh's cell order, may
  * be NULL) receive T after each step; stats (host, [n_steps], may be NULL)
- * receive each step's stats; both must stay valid until the member is handed
- * back by lf_group_poll.
+ * receive each step's stats.
  * LF_EINVAL: a problem the group cannot run (see above) or on another device;
  * LF_ESTATE: the problem runs already (here, in another group or an
  * lf_step_begin run); LF_EBUDGET: the group is full. */

@@ -229,16 +229,27 @@ struct RBLayout {
     const double *__restrict__ delta;    // [6 nr]
 };
 
-// One problem of a group launch (several problems' inner FP32 iterations in
-// one launch per kernel): its parameters, layout (kind 0: the sliced rows mr;
-// K > 0: K bands with offsets d) and vectors.
-struct InnerMember {
+// One problem of a group launch (the work of several problems' steps in one
+// launch per kernel): its parameters, layout (kind 0: the sliced rows mr with
+// per-face and per-entry factors; K > 0: K bands with offsets d and per-slot
+// factors), mesh arrays, boundary conditions and vectors.
+struct MemberDesc {
     SolverParams sp;
     int32_t kind;
     int32_t n;
     int32_t d[4];
+    int32_t diag_pc;
+    double rdt, DT;
     MeshRows mr;
-    const float *coef32, *sig32;
+    const double *mag_sf, *delta, *emag_sf, *edelta;
+    const int32_t *bface_start, *bface_list, *bface_patch;
+    const double *bmag_sf, *bdelta, *V;
+    const int32_t *patch_type;
+    const double *patch_value;
+    const int32_t *iperm;      // solver row -> mesh cell (null: the mesh's order)
+    double *T, *coef, *diagB, *srcB, *r, *rD, *p;
+    const float *coef32;
+    float *coef32w, *sig32;
     float *r32, *p32, *d32, *q32;
     double *part;
     PcgState *st;
@@ -253,6 +264,26 @@ struct GroupLaunch {
     int32_t slot[kGroupMax];
     int32_t begin[kGroupMax + 1];
 };
+
+// calls fn(layout) with a group member's layout object
+template <class Fn>
+__device__ __forceinline__ void with_member_layout(const MemberDesc &m, Fn &&fn) {
+    switch (m.kind) {
+        case 0: fn(SellLayout{m.mr, m.mag_sf, m.delta, m.emag_sf, m.edelta}); break;
+        case 1: fn(BandLayout<1>{m.n, {m.d[0]}, m.mag_sf, m.delta}); break;
+        case 2: fn(BandLayout<2>{m.n, {m.d[0], m.d[1]}, m.mag_sf, m.delta}); break;
+        case 3: fn(BandLayout<3>{m.n, {m.d[0], m.d[1], m.d[2]}, m.mag_sf, m.delta}); break;
+        default: fn(BandLayout<4>{m.n, {m.d[0], m.d[1], m.d[2], m.d[3]}, m.mag_sf, m.delta}); break;
+    }
+}
+
+// the member of a group launch that workgroup b belongs to (members' first
+// workgroups in gl.begin)
+__device__ __forceinline__ int32_t group_member(const GroupLaunch &gl, int32_t b) {
+    int32_t i = 0;
+    while (i + 1 < gl.n && b >= gl.begin[i + 1]) ++i;
+    return i;
+}
 
 // Row c's entries: coefficient slot, column and whether the entry may hold a
 // face (else its term is zero; slot and column are then clamped in range)

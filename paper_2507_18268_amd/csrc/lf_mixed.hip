@@ -106,11 +106,18 @@ __device__ __forceinline__ void scale_row(const RBLayout &L, int32_t c, double s
 }
 
 template <class Lay>
+__device__ __forceinline__ void mx_scale(int32_t blk, const SolverParams &sp, const Lay &L,
+                                         const float *__restrict__ sig32, const double *__restrict__ coef,
+                                         float *__restrict__ coef32) {
+    const int32_t c = blk * kCellBlock + static_cast<int32_t>(threadIdx.x);
+    if (c < sp.n) scale_row(L, c, static_cast<double>(sig32[c]), sig32, coef, coef32);
+}
+
+template <class Lay>
 __global__ void __launch_bounds__(kCellBlock)
 k_mx_scale(SolverParams sp, Lay L, const float *__restrict__ sig32, const double *__restrict__ coef,
            float *__restrict__ coef32) {
-    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
-    if (c < sp.n) scale_row(L, c, static_cast<double>(sig32[c]), sig32, coef, coef32);
+    mx_scale(static_cast<int32_t>(blockIdx.x), sp, L, sig32, coef, coef32);
 }
 
 // first inner iteration of a pass: p = rs, or, continuing the previous pass's
@@ -237,18 +244,24 @@ k_mx_update(SolverParams sp, const float *__restrict__ q32, const float *__restr
 
 // T += d = (y + alpha p) / s in FP64, alpha p being the last inner update
 // when it is still pending
-__global__ void __launch_bounds__(kCellBlock)
-k_mx_correct(SolverParams sp, double *__restrict__ T, const float *__restrict__ d32, const float *__restrict__ p32,
-             const float *__restrict__ sig32, const PcgState *__restrict__ st) {
+__device__ __forceinline__ void mx_correct(int32_t blk, const SolverParams &sp, double *__restrict__ T,
+                                           const float *__restrict__ d32, const float *__restrict__ p32,
+                                           const float *__restrict__ sig32, const PcgState *__restrict__ st) {
     if (st->done) return;
     const bool pend = st->inner_pend != 0;
     const float alpha = static_cast<float>(st->alpha);
-    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+    const int32_t c = blk * kCellBlock + static_cast<int32_t>(threadIdx.x);
     if (c < sp.n) {
         float y = d32[c];
         if (pend) y += alpha * p32[c];
         T[c] += static_cast<double>(y) / static_cast<double>(sig32[c]);
     }
+}
+
+__global__ void __launch_bounds__(kCellBlock)
+k_mx_correct(SolverParams sp, double *__restrict__ T, const float *__restrict__ d32, const float *__restrict__ p32,
+             const float *__restrict__ sig32, const PcgState *__restrict__ st) {
+    mx_correct(static_cast<int32_t>(blockIdx.x), sp, T, d32, p32, sig32, st);
 }
 
 // one row of a pass end: from ax = (A T)_c, the FP64 residual r and the start
@@ -271,21 +284,31 @@ __device__ __forceinline__ void pass_end_row(int64_t c, double ax, double db, bo
 
 // true residual r = b - A T in FP64 and the start of the next pass (above)
 template <class Lay>
-__global__ void __launch_bounds__(kCellBlock)
-k_mx_residual(SolverParams sp, Lay L, const double *__restrict__ diagB, const double *__restrict__ coef,
-              const double *__restrict__ srcB, const double *__restrict__ T, const float *__restrict__ p32,
-              float *__restrict__ r32, float *__restrict__ d32, double *__restrict__ part,
-              const PcgState *__restrict__ st) {
+__device__ __forceinline__ void mx_residual(int32_t blk, const SolverParams &sp, const Lay &L,
+                                            const double *__restrict__ diagB, const double *__restrict__ coef,
+                                            const double *__restrict__ srcB, const double *__restrict__ T,
+                                            const float *__restrict__ p32, float *__restrict__ r32,
+                                            float *__restrict__ d32, double *__restrict__ part,
+                                            const PcgState *__restrict__ st) {
     if (st->done) return;
     const bool keep = st->inner_iter > 0;
-    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+    const int32_t c = blk * kCellBlock + static_cast<int32_t>(threadIdx.x);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (c < sp.n) {
         const double db = diagB[c];
         pass_end_row(c, layout_dot(L, c, coef, T, db * T[c]), db, keep, srcB, p32, r32, d32, acc);
     }
     const int slots[4] = {kPartSumR, kPartSumR32, kPartWr32, kPartRp32};
-    write_partials<4>(part, sp.grid, slots, acc);
+    write_partials_at<4>(part, sp.grid, blk, slots, acc);
+}
+
+template <class Lay>
+__global__ void __launch_bounds__(kCellBlock)
+k_mx_residual(SolverParams sp, Lay L, const double *__restrict__ diagB, const double *__restrict__ coef,
+              const double *__restrict__ srcB, const double *__restrict__ T, const float *__restrict__ p32,
+              float *__restrict__ r32, float *__restrict__ d32, double *__restrict__ part,
+              const PcgState *__restrict__ st) {
+    mx_residual(static_cast<int32_t>(blockIdx.x), sp, L, diagB, coef, srcB, T, p32, r32, d32, part, st);
 }
 
 // the same residual by the row walk (sp.grid_amul workgroups)
@@ -438,52 +461,36 @@ __global__ void __launch_bounds__(kFinBlock) k_mx_finalize(SolverParams sp, cons
 // per member.  Each problem's arithmetic and sums are therefore those of its
 // own launches, whatever else shares the launch.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int32_t group_member(const GroupLaunch &gl, int32_t b) {
-    int32_t i = 0;
-    while (i + 1 < gl.n && b >= gl.begin[i + 1]) ++i;
-    return i;
-}
-
 __global__ void __launch_bounds__(kCellBlock)
-k_grp_direction(const InnerMember *__restrict__ tab, GroupLaunch gl) {
+k_grp_direction(const MemberDesc *__restrict__ tab, GroupLaunch gl) {
     const int32_t b = static_cast<int32_t>(blockIdx.x), i = group_member(gl, b);
-    const InnerMember &m = tab[gl.slot[i]];
+    const MemberDesc &m = tab[gl.slot[i]];
     mx_direction(b - gl.begin[i], m.sp, m.r32, m.p32, m.d32, m.st);
 }
 
 __global__ void __launch_bounds__(kCellBlock)
-k_grp_amul_dot(const InnerMember *__restrict__ tab, GroupLaunch gl) {
+k_grp_amul_dot(const MemberDesc *__restrict__ tab, GroupLaunch gl) {
     const int32_t b = static_cast<int32_t>(blockIdx.x), i = group_member(gl, b);
-    const InnerMember &m = tab[gl.slot[i]];
+    const MemberDesc &m = tab[gl.slot[i]];
     const int32_t blk = b - gl.begin[i];
-    switch (m.kind) {
-        case 0: {
-            SellLayout L{m.mr, nullptr, nullptr, nullptr, nullptr};
-            mx_amul_dot(blk, m.sp, L, m.coef32, m.p32, m.q32, m.part, m.st);
-            break;
-        }
-        case 1: mx_amul_dot(blk, m.sp, BandLayout<1>{m.n, {m.d[0]}, nullptr, nullptr}, m.coef32, m.p32, m.q32, m.part, m.st); break;
-        case 2: mx_amul_dot(blk, m.sp, BandLayout<2>{m.n, {m.d[0], m.d[1]}, nullptr, nullptr}, m.coef32, m.p32, m.q32, m.part, m.st); break;
-        case 3: mx_amul_dot(blk, m.sp, BandLayout<3>{m.n, {m.d[0], m.d[1], m.d[2]}, nullptr, nullptr}, m.coef32, m.p32, m.q32, m.part, m.st); break;
-        default: mx_amul_dot(blk, m.sp, BandLayout<4>{m.n, {m.d[0], m.d[1], m.d[2], m.d[3]}, nullptr, nullptr}, m.coef32, m.p32, m.q32, m.part, m.st); break;
-    }
+    with_member_layout(m, [&](auto L) { mx_amul_dot(blk, m.sp, L, m.coef32, m.p32, m.q32, m.part, m.st); });
 }
 
 __global__ void __launch_bounds__(kCellBlock)
-k_grp_update(const InnerMember *__restrict__ tab, GroupLaunch gl) {
+k_grp_update(const MemberDesc *__restrict__ tab, GroupLaunch gl) {
     const int32_t b = static_cast<int32_t>(blockIdx.x), i = group_member(gl, b);
-    const InnerMember &m = tab[gl.slot[i]];
+    const MemberDesc &m = tab[gl.slot[i]];
     mx_update(b - gl.begin[i], m.sp, m.q32, m.sig32, m.r32, m.part, m.st);
 }
 
 template <int Mode>
-__global__ void __launch_bounds__(kFinBlock) k_grp_finalize(const InnerMember *__restrict__ tab, GroupLaunch gl) {
-    const InnerMember &m = tab[gl.slot[blockIdx.x]];
+__global__ void __launch_bounds__(kFinBlock) k_grp_finalize(const MemberDesc *__restrict__ tab, GroupLaunch gl) {
+    const MemberDesc &m = tab[gl.slot[blockIdx.x]];
     mx_finalize<Mode>(m.sp, m.part, m.st);
 }
 
 // every member's solver state into out[slot]
-__global__ void k_grp_gather(const InnerMember *__restrict__ tab, GroupLaunch gl, PcgState *__restrict__ out) {
+__global__ void k_grp_gather(const MemberDesc *__restrict__ tab, GroupLaunch gl, PcgState *__restrict__ out) {
     const int32_t i = static_cast<int32_t>(blockIdx.x);
     const int32_t n = static_cast<int32_t>(sizeof(PcgState) / sizeof(int32_t));
     const int32_t *src = reinterpret_cast<const int32_t *>(tab[gl.slot[i]].st);
@@ -491,8 +498,54 @@ __global__ void k_grp_gather(const InnerMember *__restrict__ tab, GroupLaunch gl
     for (int32_t t = threadIdx.x; t < n; t += blockDim.x) dst[t] = src[t];
 }
 
+// the refinement's outer work of the launch's members (cell grids: gl.begin
+// from each member's sp.grid; finalize: one workgroup per member)
+__global__ void __launch_bounds__(kCellBlock)
+k_grp_scale(const MemberDesc *__restrict__ tab, GroupLaunch gl) {
+    const int32_t b = static_cast<int32_t>(blockIdx.x), i = group_member(gl, b);
+    const MemberDesc &m = tab[gl.slot[i]];
+    const int32_t blk = b - gl.begin[i];
+    with_member_layout(m, [&](auto L) { mx_scale(blk, m.sp, L, m.sig32, m.coef, m.coef32w); });
+}
+
+__global__ void __launch_bounds__(kCellBlock)
+k_grp_correct(const MemberDesc *__restrict__ tab, GroupLaunch gl) {
+    const int32_t b = static_cast<int32_t>(blockIdx.x), i = group_member(gl, b);
+    const MemberDesc &m = tab[gl.slot[i]];
+    mx_correct(b - gl.begin[i], m.sp, m.T, m.d32, m.p32, m.sig32, m.st);
+}
+
+__global__ void __launch_bounds__(kCellBlock)
+k_grp_residual(const MemberDesc *__restrict__ tab, GroupLaunch gl) {
+    const int32_t b = static_cast<int32_t>(blockIdx.x), i = group_member(gl, b);
+    const MemberDesc &m = tab[gl.slot[i]];
+    const int32_t blk = b - gl.begin[i];
+    with_member_layout(m, [&](auto L) {
+        mx_residual(blk, m.sp, L, m.diagB, m.coef, m.srcB, m.T, m.p32, m.r32, m.d32, m.part, m.st);
+    });
+}
+
+void launch_group_scale(const MemberDesc *tab, const GroupLaunch &cells, hipStream_t s) {
+    hipLaunchKernelGGL(k_grp_scale, dim3(static_cast<unsigned>(cells.begin[cells.n])), dim3(kCellBlock), 0, s, tab,
+                       cells);
+}
+
+void launch_group_pass_start(const MemberDesc *tab, const GroupLaunch &gl, hipStream_t s) {
+    hipLaunchKernelGGL(k_grp_finalize<kMxInnerStart>, dim3(static_cast<unsigned>(gl.n)), dim3(kFinBlock), 0, s,
+                       tab, gl);
+}
+
+// the end of a refinement pass: correction, FP64 residual, outer check
+void launch_group_pass_end(const MemberDesc *tab, const GroupLaunch &cells, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(cells.begin[cells.n]));
+    hipLaunchKernelGGL(k_grp_correct, grid, dim3(kCellBlock), 0, s, tab, cells);
+    hipLaunchKernelGGL(k_grp_residual, grid, dim3(kCellBlock), 0, s, tab, cells);
+    hipLaunchKernelGGL(k_grp_finalize<kMxOuter>, dim3(static_cast<unsigned>(cells.n)), dim3(kFinBlock), 0, s, tab,
+                       cells);
+}
+
 // one inner iteration of the launch's members (grid sizes from gl)
-void launch_group_iteration(const InnerMember *tab, const GroupLaunch &gl, hipStream_t s) {
+void launch_group_iteration(const MemberDesc *tab, const GroupLaunch &gl, hipStream_t s) {
     const dim3 blk(kCellBlock), fin(kFinBlock), cells(static_cast<unsigned>(gl.begin[gl.n])),
         each(static_cast<unsigned>(gl.n));
     hipLaunchKernelGGL(k_grp_direction, cells, blk, 0, s, tab, gl);
@@ -502,20 +555,49 @@ void launch_group_iteration(const InnerMember *tab, const GroupLaunch &gl, hipSt
     hipLaunchKernelGGL(k_grp_finalize<kMxBeta>, each, fin, 0, s, tab, gl);
 }
 
-void launch_group_gather(const InnerMember *tab, const GroupLaunch &gl, PcgState *out, hipStream_t s) {
+void launch_group_gather(const MemberDesc *tab, const GroupLaunch &gl, PcgState *out, hipStream_t s) {
     hipLaunchKernelGGL(k_grp_gather, dim3(static_cast<unsigned>(gl.n)), dim3(64), 0, s, tab, gl, out);
 }
 
-// the descriptor of a problem's inner solve
-InnerMember inner_member(const lf_problem *P) {
-    InnerMember m{};
+// the descriptor of a problem in a group
+MemberDesc member_desc(const lf_problem *P) {
+    MemberDesc m{};
     const lf_mesh *msh = P->mesh;
     m.sp = P->sp;
     m.kind = P->banded ? msh->n_bands : 0;
     m.n = msh->N;
     for (int k = 0; k < 4; ++k) m.d[k] = k < msh->n_bands ? msh->band_d[k] : 0;
+    m.diag_pc = P->opts.precond == LF_PC_DIAGONAL ? 1 : 0;
+    m.rdt = 1.0 / P->dt;
+    m.DT = P->DT;
     m.mr = mesh_rows(msh);
+    if (P->banded) {
+        m.mag_sf = msh->band_mag_sf;
+        m.delta = msh->band_delta;
+    } else {
+        m.mag_sf = msh->mag_sf;
+        m.delta = msh->delta;
+        m.emag_sf = msh->emag_sf;
+        m.edelta = msh->edelta;
+    }
+    m.bface_start = msh->rbface_start;
+    m.bface_list = msh->rbface_list;
+    m.bface_patch = msh->bface_patch;
+    m.bmag_sf = msh->bmag_sf;
+    m.bdelta = msh->bdelta;
+    m.V = msh->V;
+    m.patch_type = P->patch_type;
+    m.patch_value = P->patch_value;
+    m.iperm = msh->iperm;
+    m.T = P->T;
+    m.coef = P->coef;
+    m.diagB = P->diagB;
+    m.srcB = P->srcB;
+    m.r = P->r;
+    m.rD = P->rD;
+    m.p = P->p;
     m.coef32 = P->coef32;
+    m.coef32w = P->coef32;
     m.sig32 = P->sig32;
     m.r32 = P->r32;
     m.p32 = P->p32;
@@ -769,25 +851,6 @@ lf_status mixed_advance(lf_problem *P, SolveCtx &c, bool *finished, lf_solve_sta
     LF_HIP(hipGetLastError());
     if (adaptive) c.k = predicted_inner(P, pass + 1);
     return mixed_block(P, c);
-}
-
-// the enqueued work of a problem's step in a group (on its own stream): the
-// assembly, the start of the solve and of its first refinement pass; and
-// between passes, the end of one pass and the start of the next (no-ops once
-// the solve is done)
-lf_status mixed_enqueue_step_start(lf_problem *P, hipStream_t s) {
-    LF_TRY(launch_assemble_setup(P, s));
-    launch_fin<kFinStart>(P, s);
-    launch_pass_start(P, s);
-    LF_HIP(hipGetLastError());
-    return LF_OK;
-}
-
-lf_status mixed_enqueue_pass_turn(lf_problem *P, hipStream_t s) {
-    launch_pass_end(P, s);
-    launch_pass_start(P, s);
-    LF_HIP(hipGetLastError());
-    return LF_OK;
 }
 
 }  // namespace lf

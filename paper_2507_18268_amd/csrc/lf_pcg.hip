@@ -29,19 +29,18 @@ namespace lf {
 // residual rs = r / s rounded to FP32, y = 0, and the partial sums of s|rs|
 // (the L1 norm of the residual the inner solve sees) and rs.rs.
 template <class Lay, bool kFull, bool kSetup, bool kMixed>
-__global__ void __launch_bounds__(kCellBlock)
-k_assemble(SolverParams sp, double rdt, double DT, Lay L, const int32_t *__restrict__ bface_start,
-           const int32_t *__restrict__ bface_list, const int32_t *__restrict__ bface_patch,
-           const double *__restrict__ bmag_sf, const double *__restrict__ bdelta,
-           const int32_t *__restrict__ patch_type, const double *__restrict__ patch_value,
-           const double *__restrict__ V, const double *__restrict__ T, double *__restrict__ coef,
-           double *__restrict__ upper, double *__restrict__ diag, double *__restrict__ source,
-           double *__restrict__ diagB, double *__restrict__ srcB, double *__restrict__ int_coeff,
-           double *__restrict__ bou_coeff, int32_t diag_pc, double *__restrict__ r, double *__restrict__ rD,
-           double *__restrict__ part, const PcgState *__restrict__ st, float *__restrict__ sig32,
-           float *__restrict__ r32, float *__restrict__ d32, double *__restrict__ p,
-           const double *__restrict__ lap_src, const double *__restrict__ T_old) {
-    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+__device__ __forceinline__ void assemble_rows(
+    int32_t blk, const SolverParams &sp, double rdt, double DT, const Lay &L, const int32_t *__restrict__ bface_start,
+    const int32_t *__restrict__ bface_list, const int32_t *__restrict__ bface_patch,
+    const double *__restrict__ bmag_sf, const double *__restrict__ bdelta, const int32_t *__restrict__ patch_type,
+    const double *__restrict__ patch_value, const double *__restrict__ V, const double *__restrict__ T,
+    double *__restrict__ coef, double *__restrict__ upper, double *__restrict__ diag, double *__restrict__ source,
+    double *__restrict__ diagB, double *__restrict__ srcB, double *__restrict__ int_coeff,
+    double *__restrict__ bou_coeff, int32_t diag_pc, double *__restrict__ r, double *__restrict__ rD,
+    double *__restrict__ part, const PcgState *__restrict__ st, float *__restrict__ sig32, float *__restrict__ r32,
+    float *__restrict__ d32, double *__restrict__ p, const double *__restrict__ lap_src,
+    const double *__restrict__ T_old) {
+    const int32_t c = blk * kCellBlock + static_cast<int32_t>(threadIdx.x);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const double x_avg = kSetup ? st->x_avg : 0.0;
     if (c < sp.n) {
@@ -104,21 +103,45 @@ k_assemble(SolverParams sp, double rdt, double DT, Lay L, const int32_t *__restr
     }
     if (kSetup && kMixed) {
         const int slots[5] = {kPartSumR, kPartNf, kPartWr, kPartSumR32, kPartWr32};
-        write_partials<5>(part, sp.grid, slots, acc);
+        write_partials_at<5>(part, sp.grid, blk, slots, acc);
     } else if (kSetup) {
         double a3[3] = {acc[0], acc[1], acc[2]};
         const int slots[3] = {kPartSumR, kPartNf, kPartWr};
-        write_partials<3>(part, sp.grid, slots, a3);
+        write_partials_at<3>(part, sp.grid, blk, slots, a3);
     }
 }
 
-// partial sums of x0 = T (its mean enters the normalisation factor)
+template <class Lay, bool kFull, bool kSetup, bool kMixed>
 __global__ void __launch_bounds__(kCellBlock)
-k_sum_x(SolverParams sp, const double *__restrict__ T, double *__restrict__ part) {
-    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+k_assemble(SolverParams sp, double rdt, double DT, Lay L, const int32_t *__restrict__ bface_start,
+           const int32_t *__restrict__ bface_list, const int32_t *__restrict__ bface_patch,
+           const double *__restrict__ bmag_sf, const double *__restrict__ bdelta,
+           const int32_t *__restrict__ patch_type, const double *__restrict__ patch_value,
+           const double *__restrict__ V, const double *__restrict__ T, double *__restrict__ coef,
+           double *__restrict__ upper, double *__restrict__ diag, double *__restrict__ source,
+           double *__restrict__ diagB, double *__restrict__ srcB, double *__restrict__ int_coeff,
+           double *__restrict__ bou_coeff, int32_t diag_pc, double *__restrict__ r, double *__restrict__ rD,
+           double *__restrict__ part, const PcgState *__restrict__ st, float *__restrict__ sig32,
+           float *__restrict__ r32, float *__restrict__ d32, double *__restrict__ p,
+           const double *__restrict__ lap_src, const double *__restrict__ T_old) {
+    assemble_rows<Lay, kFull, kSetup, kMixed>(static_cast<int32_t>(blockIdx.x), sp, rdt, DT, L, bface_start,
+                                              bface_list, bface_patch, bmag_sf, bdelta, patch_type, patch_value, V,
+                                              T, coef, upper, diag, source, diagB, srcB, int_coeff, bou_coeff,
+                                              diag_pc, r, rD, part, st, sig32, r32, d32, p, lap_src, T_old);
+}
+
+// partial sums of x0 = T (its mean enters the normalisation factor)
+__device__ __forceinline__ void sum_x_rows(int32_t blk, const SolverParams &sp, const double *__restrict__ T,
+                                           double *__restrict__ part) {
+    const int32_t c = blk * kCellBlock + static_cast<int32_t>(threadIdx.x);
     double acc[1] = {c < sp.n ? T[c] : 0.0};
     const int slots[1] = {kPartSumX};
-    write_partials<1>(part, sp.grid, slots, acc);
+    write_partials_at<1>(part, sp.grid, blk, slots, acc);
+}
+
+__global__ void __launch_bounds__(kCellBlock)
+k_sum_x(SolverParams sp, const double *__restrict__ T, double *__restrict__ part) {
+    sum_x_rows(static_cast<int32_t>(blockIdx.x), sp, T, part);
 }
 
 // y = A x (diag x first, then the row's entries in order)
@@ -657,8 +680,8 @@ k_rb_upper(int32_t F, RBForm rf, const int32_t *__restrict__ owner, const int32_
 // ---------------------------------------------------------------------------
 
 template <int Mode>
-__global__ void __launch_bounds__(kFinBlock) k_finalize(SolverParams sp, const double *__restrict__ part,
-                                                       PcgState *__restrict__ st) {
+__device__ __forceinline__ void finalize_state(const SolverParams &sp, const double *__restrict__ part,
+                                               PcgState *__restrict__ st) {
     const int32_t G = sp.grid;
     if (Mode == kFinMean) {
         double v[1];
@@ -780,6 +803,54 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(SolverParams sp, const d
             }
         }
     }
+}
+
+template <int Mode>
+__global__ void __launch_bounds__(kFinBlock) k_finalize(SolverParams sp, const double *__restrict__ part,
+                                                       PcgState *__restrict__ st) {
+    finalize_state<Mode>(sp, part, st);
+}
+
+// ---------------------------------------------------------------------------
+// The start of a step for several group members in one launch per kernel
+// (the precision form's: x0 sums, mean, assembly fused with the start of the
+// solve; then, after the FP32 scaling, the initial decision).  Member i takes
+// workgroups gl.begin[i] .. (its own cell grid) or workgroup i (finalize).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kCellBlock) k_grp_sum_x(const MemberDesc *__restrict__ tab, GroupLaunch gl) {
+    const int32_t b = static_cast<int32_t>(blockIdx.x), i = group_member(gl, b);
+    const MemberDesc &m = tab[gl.slot[i]];
+    sum_x_rows(b - gl.begin[i], m.sp, m.T, m.part);
+}
+
+template <int Mode>
+__global__ void __launch_bounds__(kFinBlock) k_grp_fin(const MemberDesc *__restrict__ tab, GroupLaunch gl) {
+    const MemberDesc &m = tab[gl.slot[blockIdx.x]];
+    finalize_state<Mode>(m.sp, m.part, m.st);
+}
+
+__global__ void __launch_bounds__(kCellBlock) k_grp_assemble(const MemberDesc *__restrict__ tab, GroupLaunch gl) {
+    const int32_t b = static_cast<int32_t>(blockIdx.x), i = group_member(gl, b);
+    const MemberDesc &m = tab[gl.slot[i]];
+    const int32_t blk = b - gl.begin[i];
+    with_member_layout(m, [&](auto L) {
+        assemble_rows<decltype(L), false, true, true>(blk, m.sp, m.rdt, m.DT, L, m.bface_start, m.bface_list,
+                                                      m.bface_patch, m.bmag_sf, m.bdelta, m.patch_type,
+                                                      m.patch_value, m.V, m.T, m.coef, nullptr, nullptr, nullptr,
+                                                      m.diagB, m.srcB, nullptr, nullptr, m.diag_pc, m.r, m.rD,
+                                                      m.part, m.st, m.sig32, m.r32, m.d32, m.p, nullptr, nullptr);
+    });
+}
+
+void launch_group_setup(const MemberDesc *tab, const GroupLaunch &cells, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(cells.begin[cells.n]));
+    hipLaunchKernelGGL(k_grp_sum_x, grid, dim3(kCellBlock), 0, s, tab, cells);
+    hipLaunchKernelGGL(k_grp_fin<kFinMean>, dim3(static_cast<unsigned>(cells.n)), dim3(kFinBlock), 0, s, tab, cells);
+    hipLaunchKernelGGL(k_grp_assemble, grid, dim3(kCellBlock), 0, s, tab, cells);
+}
+
+void launch_group_fin_start(const MemberDesc *tab, const GroupLaunch &gl, hipStream_t s) {
+    hipLaunchKernelGGL(k_grp_fin<kFinStart>, dim3(static_cast<unsigned>(gl.n)), dim3(kFinBlock), 0, s, tab, gl);
 }
 
 // Per-kernel timing only: keeps the GPU busy for `ticks` of its constant-rate

@@ -91,11 +91,16 @@ lf_status launch_assemble_setup(lf_problem *P, hipStream_t s);
 void launch_mx_scale(lf_problem *P, hipStream_t s);
 lf_status launch_amul_inner_hook(lf_problem *P, const float *x, float *y);
 // groups (lf_group.hip): inner iterations of several problems per launch
-InnerMember inner_member(const lf_problem *P);
-void launch_group_iteration(const InnerMember *tab, const GroupLaunch &gl, hipStream_t s);
-void launch_group_gather(const InnerMember *tab, const GroupLaunch &gl, PcgState *out, hipStream_t s);
-lf_status mixed_enqueue_step_start(lf_problem *P, hipStream_t s);
-lf_status mixed_enqueue_pass_turn(lf_problem *P, hipStream_t s);
+MemberDesc member_desc(const lf_problem *P);
+// launches over the members of gl (cells: each member's sp.grid workgroups;
+// inner: its sp.grid_mx; finalize: one per member)
+void launch_group_setup(const MemberDesc *tab, const GroupLaunch &cells, hipStream_t s);
+void launch_group_scale(const MemberDesc *tab, const GroupLaunch &cells, hipStream_t s);
+void launch_group_fin_start(const MemberDesc *tab, const GroupLaunch &gl, hipStream_t s);
+void launch_group_pass_start(const MemberDesc *tab, const GroupLaunch &gl, hipStream_t s);
+void launch_group_pass_end(const MemberDesc *tab, const GroupLaunch &cells, hipStream_t s);
+void launch_group_iteration(const MemberDesc *tab, const GroupLaunch &inner, hipStream_t s);
+void launch_group_gather(const MemberDesc *tab, const GroupLaunch &gl, PcgState *out, hipStream_t s);
 // non-orthogonal meshes: boundary values and gradient of T, then P->lap_src
 // (lf_grad.hip); runs before the assembly of each step
 void launch_nonorth_source(lf_problem *P, hipStream_t s);

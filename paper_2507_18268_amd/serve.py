@@ -25,10 +25,10 @@ Large requests can instead take the direct lane: up to direct_workers of them
 at a time, each with its own pool of problems, run all their steps with the
 multi-kernel solver (many workgroups per problem, coefficients in the band
 layout where the mesh allows), T being copied after each step into the
-snapshot buffer.  By default the lane is a group (lf_group): the inner FP32
-iterations of every running direct request go out as one launch per kernel,
-so a mid-size request no longer pays a dependent launch per kernel of its own;
-its assembly and pass turns run on one of a few lane streams.  A request's run
+snapshot buffer.  By default the lane is a group (lf_group): every kernel of
+the running direct requests' steps goes out as one launch for all of them that
+need it, so a mid-size request no longer pays a dependent launch per kernel of
+its own; T0 goes up and the snapshots come down on a few lane streams.  A request's run
 starts when it is admitted (lf_group_add) and every scheduling pass advances
 the group as far as its finished device work allows (lf_group_poll, which
 never waits), so a small request does not wait for a large one's steps.
@@ -137,8 +137,8 @@ class Server:
         self.direct_min_side = direct_min_side
         self.direct_use_graph = direct_use_graph
         nd = direct_workers if direct_min_side is not None else 0
-        # grouped lane: the running direct requests' inner iterations share
-        # launches (lf_group); their own work (assembly, pass turns) goes to a
+        # grouped lane: the running direct requests' kernels share launches
+        # (lf_group, on its own stream); their uploads and downloads go to a
         # few streams, worker k on stream k % direct_streams
         self.group = None
         if nd and direct_group:
