@@ -47,6 +47,7 @@ MIXED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mx_amul_graded256.j
 GRAD_SOURCES = ["paper_2507_18268_amd/csrc/lf_grad.hip"]
 GRAD_LABEL = "256^3 box graded in z (ratio 10) and skewed"
 GRAD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_grad_band_skewed256.json")
+GRAD_ROWS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_grad_rows_permuted192.json")
 
 
 def kernel_source_hash(sources=None):
@@ -417,8 +418,9 @@ def run_grad(L, torch, p, label, launches=20):
     gbps = nbytes / (us * 1e-6) / 1e9
     kname = f"k_grad_band<{K}>" if K else "k_grad_rows"
     traffic = None
-    if os.path.exists(GRAD_TRAFFIC_FILE):
-        with open(GRAD_TRAFFIC_FILE) as f:
+    tfile = GRAD_TRAFFIC_FILE if K else GRAD_ROWS_TRAFFIC_FILE
+    if os.path.exists(tfile):
+        with open(tfile) as f:
             tr = json.load(f)
         # counters taken on this kernel source and size only
         if (tr.get("source_sha256") == kernel_source_hash(GRAD_SOURCES) and tr.get("n_cells") == N
