@@ -198,7 +198,13 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
         }
     }
     P->sp.n_red = m->two_colour ? m->n_red : m->N;
-    if (P->rb) P->sp.grid_amul = cell_blocks(m->n_red);   // the pair product: one thread per red-black pair
+    if (P->rb) {
+        // the pair kernels (product, update with the forward sweep, backward
+        // sweep): one thread per red-black pair; the |r| and w.r partials of
+        // an iteration then number the pair workgroups
+        P->sp.grid_amul = cell_blocks(m->n_red);
+        P->sp.grid_upd = P->sp.grid_amul;
+    }
     P->sp.max_outer = opts.max_outer > 0 ? opts.max_outer : 50;
     P->sp.inner_tol = opts.inner_tol > 0.0 ? opts.inner_tol : 1e-5;
     P->sp.inner_restart = opts.inner_restart ? 1 : 0;

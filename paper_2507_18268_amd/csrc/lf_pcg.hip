@@ -537,6 +537,49 @@ k_dic_forward_rb(SolverParams sp, RBLayout L, const double *__restrict__ coef, c
     w[c] = wc;
 }
 
+// The same forward sweep fused with the iteration's update of r on the
+// two-colour band layout (one thread per red-black pair, sp.grid_amul
+// workgroups): the black row's r -= alpha q is written here, the red rows' by
+// the backward sweep that follows, so the red neighbours' updated r (the
+// value the separate update would have stored, the same expression) is formed
+// here from the old r and q.  Partial sums of the black rows' |r| go to the
+// |r| slot; the backward sweep adds the red rows' to them.
+__global__ void __launch_bounds__(kCellBlock)
+k_dic_update_forward_rb(SolverParams sp, RBLayout L, const double *__restrict__ coef,
+                        const double *__restrict__ rD, const double *__restrict__ q, double *__restrict__ r,
+                        double *__restrict__ w, double *__restrict__ part, const PcgState *__restrict__ st) {
+    if (st->done) return;
+    const int32_t nr = L.f.nr;
+    const double alpha = st->alpha;
+    const int32_t u = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+    double acc[1] = {0.0};
+    if (u < nr) {
+        const int32_t c = nr + u;
+        const double rc = r[c] - alpha * __builtin_nontemporal_load(&q[c]);
+        r[c] = rc;
+        acc[0] = fabs(rc);
+        const double rd = rD[c];
+        double wc = rd * rc;
+        int64_t slot[6];
+        int32_t col[6];
+        bool ok[6];
+        rb_row(L.f, c, slot, col, ok);
+        double a[6], ro[6], rdo[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            a[j] = coef[slot[j]];
+            rdo[j] = rD[col[j]];
+            ro[j] = r[col[j]] - alpha * q[col[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            if (ok[j]) wc -= rd * a[j] * (rdo[j] * ro[j]);
+        w[c] = wc;
+    }
+    const int slots[1] = {kPartSumR};
+    write_partials<1>(part, sp.grid, slots, acc);
+}
+
 // backward sweep on red rows; every row contributes its w.r partial
 __global__ void __launch_bounds__(kCellBlock)
 k_dic_backward_rb(SolverParams sp, RBLayout L, const double *__restrict__ coef, const double *__restrict__ rD,
@@ -621,14 +664,17 @@ k_amul_dot_rb(SolverParams sp, RBLayout L, const double *__restrict__ diagB, con
 // with the w.r partial sums of the red row and of the black row nr + u (its
 // w from the forward sweep); sp.grid_amul workgroups (the slot's further
 // partials hold the zeros the update wrote)
+// kUpdate: after k_dic_update_forward_rb, the red row's r -= alpha q first,
+// and the red rows' |r| added to the black rows' partial sums of the block
+template <bool kUpdate>
 __global__ void __launch_bounds__(kCellBlock)
 k_dic_backward_rb_pair(SolverParams sp, RBLayout L, const double *__restrict__ coef,
-                       const double *__restrict__ rD, const double *__restrict__ r, double *__restrict__ w,
-                       double *__restrict__ part, const PcgState *__restrict__ st) {
+                       const double *__restrict__ rD, const double *__restrict__ q, double *__restrict__ r,
+                       double *__restrict__ w, double *__restrict__ part, const PcgState *__restrict__ st) {
     if (st->done) return;
     const int32_t nr = L.f.nr;
     const int32_t u = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
-    double acc[1] = {0.0};
+    double acc[2] = {0.0, 0.0};
     if (u < nr) {
         int64_t slot[6];
         int32_t col[6];
@@ -640,7 +686,13 @@ k_dic_backward_rb_pair(SolverParams sp, RBLayout L, const double *__restrict__ c
             a[j] = coef[slot[j]];
             wo[j] = w[col[j]];
         }
-        const double rd = rD[u], rc = r[u];
+        const double rd = rD[u];
+        double rc = r[u];
+        if (kUpdate) {
+            rc = rc - st->alpha * __builtin_nontemporal_load(&q[u]);
+            r[u] = rc;
+            acc[1] = fabs(rc);
+        }
         double wc = rd * rc;
 #pragma unroll
         for (int j = 5; j >= 0; --j)
@@ -648,8 +700,20 @@ k_dic_backward_rb_pair(SolverParams sp, RBLayout L, const double *__restrict__ c
         w[u] = wc;
         acc[0] = wc * rc + w[nr + u] * r[nr + u];
     }
-    const int slots[1] = {kPartWr};
-    write_partials<1>(part, sp.grid, slots, acc);
+    if (kUpdate) {
+        // the block's |r| partial: its black rows' (written by the forward
+        // sweep, same workgroup index) plus its red rows'
+        const double black = part[kPartSumR * sp.grid + blockIdx.x];
+        block_sum<kCellBlock, 2>(acc);
+        if (threadIdx.x == 0) {
+            part[kPartWr * sp.grid + blockIdx.x] = acc[0];
+            part[kPartSumR * sp.grid + blockIdx.x] = black + acc[1];
+        }
+    } else {
+        double a1[1] = {acc[0]};
+        const int slots[1] = {kPartWr};
+        write_partials<1>(part, sp.grid, slots, a1);
+    }
 }
 
 // face-order copy of the two-colour band coefficients: upper_f at its slot
@@ -994,8 +1058,8 @@ static void launch_dic_sweeps(lf_problem *P, hipStream_t s) {
         const dim3 gb(static_cast<unsigned>(std::max<int32_t>(1, (nb + kCellBlock - 1) / kCellBlock)));
         LF_LAUNCH(P, LF_K_DIC_FORWARD, s, k_dic_forward_rb, gb, dim3(kCellBlock), 0, s, P->sp, rb_layout(m),
                   P->coef, P->rD, P->r, P->w, P->state);
-        LF_LAUNCH(P, LF_K_DIC_BACKWARD, s, k_dic_backward_rb_pair, gb, dim3(kCellBlock), 0, s, P->sp,
-                  rb_layout(m), P->coef, P->rD, P->r, P->w, P->part, P->state);
+        LF_LAUNCH(P, LF_K_DIC_BACKWARD, s, k_dic_backward_rb_pair<false>, gb, dim3(kCellBlock), 0, s, P->sp,
+                  rb_layout(m), P->coef, P->rD, P->q, P->r, P->w, P->part, P->state);
         return;
     }
     LF_LAUNCH(P, LF_K_DIC_FORWARD, s, k_dic_forward, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, mesh_rows(m),
@@ -1059,6 +1123,20 @@ static lf_status launch_iteration(lf_problem *P, hipStream_t s) {
                   P->diagB, P->coef, P->p, P->q, P->part, P->state);
     });
     launch_fin<kFinAlpha>(P, s);
+    if (P->rb && !diag_pc) {
+        // red-black DIC on the two-colour band layout: the update of r fused
+        // into the two sweeps
+        const lf_mesh *m = P->mesh;
+        const dim3 gb(static_cast<unsigned>(P->sp.grid_amul));
+        LF_LAUNCH(P, LF_K_DIC_FORWARD, s, k_dic_update_forward_rb, gb, dim3(kCellBlock), 0, s, P->sp, rb_layout(m),
+                  P->coef, P->rD, P->q, P->r, P->w, P->part, P->state);
+        LF_LAUNCH(P, LF_K_DIC_BACKWARD, s, k_dic_backward_rb_pair<true>, gb, dim3(kCellBlock), 0, s, P->sp,
+                  rb_layout(m), P->coef, P->rD, P->q, P->r, P->w, P->part, P->state);
+        launch_fin<kFinBeta>(P, s);
+        launch_direction(P, s);
+        LF_HIP(hipGetLastError());
+        return LF_OK;
+    }
     if (diag_pc) {
         LF_LAUNCH(P, LF_K_UPDATE, s, k_update<true>, dim3(static_cast<unsigned>(P->sp.grid_upd)),
                   dim3(kCellBlock), 0, s, P->sp, P->q, P->r,
