@@ -250,13 +250,16 @@ __device__ __forceinline__ bool is_face(const Rec &r) { return r.x != 0.0 || r.y
 // of L2 at 256^3).  Consecutive threads take consecutive c.  kNT writes the
 // gradient past the caches (a result for the caller, not read again here; 2%
 // faster at 256^3); the correction, which reads it next, keeps it cached.
+// Component i of cell c goes to grad[i gcs + c ges]: the caller's xyz rows
+// (gcs 1, ges 3), or one array per component for the correction (gcs n,
+// ges 1), whose loads are then contiguous.
 template <int K, int R, bool kNT>
 __global__ void __launch_bounds__(kGradBlock)
 k_grad_band(int32_t n, BandOffsets bo, const double *__restrict__ T, const double *__restrict__ Tb,
             const double *__restrict__ snb, const double *__restrict__ gband,
             const int32_t *__restrict__ bface_start, const int32_t *__restrict__ bface_list,
             const double *__restrict__ gbface, const double *__restrict__ V, double *__restrict__ grad,
-            double *__restrict__ bgrad) {
+            double *__restrict__ bgrad, int64_t gcs, int64_t ges) {
     const int64_t D = bo.d[K - 1];
     const int64_t g = die_block(blockIdx.x, gridDim.x) * kGradBlock + threadIdx.x;
     const int64_t chunk = g / D;
@@ -319,13 +322,13 @@ k_grad_band(int32_t n, BandOffsets bo, const double *__restrict__ T, const doubl
         gy /= v;
         gz /= v;
         if (kNT) {
-            __builtin_nontemporal_store(gx, grad + 3 * c);
-            __builtin_nontemporal_store(gy, grad + 3 * c + 1);
-            __builtin_nontemporal_store(gz, grad + 3 * c + 2);
+            __builtin_nontemporal_store(gx, grad + c * ges);
+            __builtin_nontemporal_store(gy, grad + gcs + c * ges);
+            __builtin_nontemporal_store(gz, grad + 2 * gcs + c * ges);
         } else {
-            grad[3 * c] = gx;
-            grad[3 * c + 1] = gy;
-            grad[3 * c + 2] = gz;
+            grad[c * ges] = gx;
+            grad[gcs + c * ges] = gy;
+            grad[2 * gcs + c * ges] = gz;
         }
         if (bgrad) {
             for (int32_t k = b0; k < b1; ++k) {
@@ -362,7 +365,8 @@ static BandOffsets mesh_bands(const lf_mesh *m) {
 // the band path's launch (1 <= n_bands <= 4, checked by the callers); nt: the
 // gradient is written past the caches
 static void launch_grad_band(const lf_mesh *m, const double *T, const double *Tb, const double *snb, double *grad,
-                             double *bgrad, bool nt, hipStream_t s) {
+                             double *bgrad, bool nt, hipStream_t s, bool by_component = false) {
+    const int64_t gcs = by_component ? m->N : 1, ges = by_component ? 1 : 3;
     const BandOffsets bo = mesh_bands(m);
     const int K = bo.k;
     const int64_t D = bo.d[K - 1];
@@ -371,7 +375,7 @@ static void launch_grad_band(const lf_mesh *m, const double *T, const double *Tb
 #define LF_GRAD_BAND_NT(KK, RR, NT)                                                                      \
     if (K == KK && R == RR && nt == NT)                                                                  \
         hipLaunchKernelGGL((k_grad_band<KK, RR, NT>), grid, block, 0, s, m->N, bo, T, Tb, snb, m->gband,  \
-                           m->bface_start, m->bface_list, m->gbface, m->V, grad, bgrad);
+                           m->bface_start, m->bface_list, m->gbface, m->V, grad, bgrad, gcs, ges);
 #define LF_GRAD_BAND(KK, RR) LF_GRAD_BAND_NT(KK, RR, false) LF_GRAD_BAND_NT(KK, RR, true)
 #define LF_GRAD_BAND_R(KK) LF_GRAD_BAND(KK, 1) LF_GRAD_BAND(KK, 2)
     LF_GRAD_BAND_R(1)
@@ -412,6 +416,7 @@ template <int K, int R>
 __global__ void __launch_bounds__(kGradBlock)
 k_nonorth_band(int32_t n, BandOffsets bo, double DT, const double *__restrict__ g, const double *__restrict__ gkband,
                const double *__restrict__ band_mag_sf, const double *__restrict__ V, double *__restrict__ lap_src) {
+    // g: one array per component (g[i n + c])
     const int64_t D = bo.d[K - 1];
     const int64_t t = die_block(blockIdx.x, gridDim.x) * kGradBlock + threadIdx.x;
     const int64_t chunk = t / D;
@@ -424,9 +429,9 @@ k_nonorth_band(int32_t n, BandOffsets bo, double DT, const double *__restrict__ 
     if (c - D >= 0) {
         carry = load_rec(gkband, top + c - D);
         carry_mg = band_mag_sf[top + c - D];
-        for (int i = 0; i < 3; ++i) carry_g[i] = g[3 * (c - D) + i];
+        for (int i = 0; i < 3; ++i) carry_g[i] = g[i * static_cast<int64_t>(n) + c - D];
     }
-    double gc[3] = {g[3 * c], g[3 * c + 1], g[3 * c + 2]};
+    double gc[3] = {g[c], g[n + c], g[2 * static_cast<int64_t>(n) + c]};
 #pragma unroll
     for (int r = 0; r < R; ++r, c += D) {
         if (c >= n) break;
@@ -443,12 +448,12 @@ k_nonorth_band(int32_t n, BandOffsets bo, double DT, const double *__restrict__ 
                 const bool in = cl >= 0;
                 lo[k] = in ? load_rec(gkband, static_cast<int64_t>(k) * n + cl) : none;
                 lmg[k] = in ? band_mag_sf[static_cast<int64_t>(k) * n + cl] : 0.0;
-                for (int i = 0; i < 3; ++i) glo[k][i] = in ? g[3 * cl + i] : 0.0;
+                for (int i = 0; i < 3; ++i) glo[k][i] = in ? g[i * static_cast<int64_t>(n) + cl] : 0.0;
             }
             const bool in = cu < n;
             up[k] = in ? load_rec(gkband, static_cast<int64_t>(k) * n + c) : none;
             umg[k] = in ? band_mag_sf[static_cast<int64_t>(k) * n + c] : 0.0;
-            for (int i = 0; i < 3; ++i) gup[k][i] = in ? g[3 * cu + i] : 0.0;
+            for (int i = 0; i < 3; ++i) gup[k][i] = in ? g[i * static_cast<int64_t>(n) + cu] : 0.0;
         }
         double div = 0.0;
 #pragma unroll
@@ -526,7 +531,7 @@ void launch_nonorth_source(lf_problem *P, hipStream_t s) {
         hipLaunchKernelGGL(k_nonorth_bvalues, dim3((m->B + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m->B,
                            m->rbface_cell, m->bface_patch, P->patch_type, P->patch_value, P->T, P->Tb);
     if (m->gkband) {
-        launch_grad_band(m, P->T, P->Tb, nullptr, P->grad3, nullptr, false, s);
+        launch_grad_band(m, P->T, P->Tb, nullptr, P->grad3, nullptr, false, s, true);
         const BandOffsets bo = mesh_bands(m);
         const int64_t D = bo.d[bo.k - 1];
         const int R = grad_walk_rows(m->N, D);

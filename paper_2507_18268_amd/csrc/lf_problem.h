@@ -140,7 +140,7 @@ struct lf_problem {
     // non-orthogonal meshes: the gradient of T at assembly (solver order) and
     // the Laplacian's explicit source built from it
     bool nonorth = false;
-    double *grad3 = nullptr;                   // [3N]
+    double *grad3 = nullptr;                   // [3N]: by component on band-form meshes, else xyz per cell
     double *lap_src = nullptr;                 // [N]
     double *T_old = nullptr;                   // [N] T at the start of the step (corrector passes)
     double *snb = nullptr;                     // [B] normal gradient of T on the boundary faces
