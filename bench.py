@@ -457,13 +457,22 @@ def run_serving(L, torch, args):
                           arrival=(r.arrival if rate else 0.0)) for r in rs]
 
     tuning = autotune.load()
+    lane = autotune.serving_params()
+    tuned_lane = (autotune.load(form="serving") is not None and args.serve_direct_min < 0
+                  and args.serve_group_iters < 0)
+    if args.serve_direct_min < 0:
+        args.serve_direct_min = lane["direct_min_side"]
+    if args.serve_group_iters < 0:
+        args.serve_group_iters = lane["group_iters"]
     out = {"workload": f"{args.serve_requests} requests, side log-uniform [16,96], DT log-uniform "
                        f"[1e-4,1e-2], dt 1e-3, 10 steps, snapshots returned, mixed FP32/FP64: "
                        f"batched kernel, large sides on the multi-kernel solver",
            "tuning": tuning["block_threads"] if tuning else None,
            "budget_GiB": args.serve_budget_gib, "slots": args.serve_slots,
            "direct_min_side": args.serve_direct_min or None, "direct_workers": args.serve_direct_workers,
-           "direct_lane": "alone (lf_step_begin)" if args.serve_direct_alone else "group (lf_group)"}
+           "direct_lane": "alone (lf_step_begin)" if args.serve_direct_alone else "group (lf_group)",
+           "group_iters": args.serve_group_iters,
+           "lane_source": "autotuned" if tuned_lane else "default"}
     sides = sorted({r.n for r in base})
     cells = sum(r.n ** 3 for r in base)
 
@@ -558,16 +567,17 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-capacity", type=int, default=64)
-    ap.add_argument("--serve-direct-min", type=int, default=24,
-                    help="requests with at least this cube side run on the multi-kernel solver (0 = never)")
+    ap.add_argument("--serve-direct-min", type=int, default=-1,
+                    help="requests with at least this cube side run on the multi-kernel solver "
+                         "(0 = never, -1 = the autotuned threshold)")
     ap.add_argument("--serve-direct-workers", type=int, default=32)
     ap.add_argument("--serve-direct-no-graph", action="store_true")
     ap.add_argument("--serve-direct-alone", action="store_true",
                     help="direct lane without the group: each request alone (lf_step_begin/poll)")
     ap.add_argument("--serve-direct-streams", type=int, default=4,
                     help="streams of the grouped direct lane's own work (assembly, pass turns)")
-    ap.add_argument("--serve-group-iters", type=int, default=0,
-                    help="inner iterations per group block (0: the library default)")
+    ap.add_argument("--serve-group-iters", type=int, default=-1,
+                    help="inner iterations per group block (0: the library default, -1: autotuned)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()

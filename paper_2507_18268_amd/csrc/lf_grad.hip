@@ -161,6 +161,41 @@ __global__ void k_grad_to_rows(int32_t n, const int32_t *__restrict__ iperm, con
     if (r < n) Ts[r] = T[iperm[r]];
 }
 
+// The internal faces' part of row r's gradient sum over its W slots of the
+// row layout (W = the slice's width): every slot's record, column and
+// neighbour value are loaded before any is used, so a thread has all its
+// row's loads in flight at once; slots past the row's length (padding within
+// the slice, in bounds) are loaded and skipped.  Terms are added in slot
+// order, the order of the plain loop.
+template <int W>
+__device__ __forceinline__ void grad_row_faces(int64_t idx0, int32_t len, double Tr,
+                                               const double *__restrict__ Ts, const int32_t *__restrict__ scol,
+                                               const double *__restrict__ gerec, double &gx, double &gy,
+                                               double &gz) {
+    Rec q[W];
+    int32_t col[W];
+    double To[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        q[j] = load_rec(gerec, idx0 + static_cast<int64_t>(kSlice) * j);
+        col[j] = scol[idx0 + static_cast<int64_t>(kSlice) * j];
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j) To[j] = Ts[col[j]];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        if (j < len) {
+            // lower face (negated record): s = w (T_P - T_r) + T_r, g -= S s;
+            // owned face: s = w (T_r - T_N) + T_N, g += S s
+            const double w = fabs(q[j].w);
+            const double s = signbit(q[j].w) ? w * (To[j] - Tr) + Tr : w * (Tr - To[j]) + To[j];
+            gx += q[j].x * s;
+            gy += q[j].y * s;
+            gz += q[j].z * s;
+        }
+    }
+}
+
 // Meshes without band form: one solver row per thread over the row layout,
 // whose entries are the row's lower faces then its owned faces, each in
 // ascending face order (the face loop's order); then the row's boundary faces
@@ -177,23 +212,33 @@ k_grad_rows(int32_t n, const double *__restrict__ Ts, const double *__restrict__
     // iperm null: the gradient stays in the solver's order (or the orders agree)
     const int64_t r = static_cast<int64_t>(blockIdx.x) * kGradBlock + threadIdx.x;
     if (r >= n) return;
-    const int64_t idx0 = soff[r / kSlice] + r % kSlice;
+    const int32_t o0 = soff[r / kSlice];
+    const int64_t idx0 = o0 + r % kSlice;
+    const int32_t width = (soff[r / kSlice + 1] - o0) / kSlice;
     const int32_t len = rlen[r];
     const double Tr = Ts[r];
     const double v = V[r];
     const int32_t b0 = rbface_start[r], b1 = rbface_start[r + 1];
     double gx = 0.0, gy = 0.0, gz = 0.0;
-    for (int32_t j = 0; j < len; ++j) {
-        const int64_t idx = idx0 + static_cast<int64_t>(kSlice) * j;
-        const Rec q = load_rec(gerec, idx);
-        const double To = Ts[scol[idx]];
-        // lower face (negated record): s = w (T_P - T_r) + T_r, g -= S s;
-        // owned face: s = w (T_r - T_N) + T_N, g += S s
-        const double w = fabs(q.w);
-        const double s = signbit(q.w) ? w * (To - Tr) + Tr : w * (Tr - To) + To;
-        gx += q.x * s;
-        gy += q.y * s;
-        gz += q.z * s;
+    switch (width) {
+        case 0: break;
+        case 1: grad_row_faces<1>(idx0, len, Tr, Ts, scol, gerec, gx, gy, gz); break;
+        case 2: grad_row_faces<2>(idx0, len, Tr, Ts, scol, gerec, gx, gy, gz); break;
+        case 3: grad_row_faces<3>(idx0, len, Tr, Ts, scol, gerec, gx, gy, gz); break;
+        case 4: grad_row_faces<4>(idx0, len, Tr, Ts, scol, gerec, gx, gy, gz); break;
+        case 5: grad_row_faces<5>(idx0, len, Tr, Ts, scol, gerec, gx, gy, gz); break;
+        case 6: grad_row_faces<6>(idx0, len, Tr, Ts, scol, gerec, gx, gy, gz); break;
+        default:
+            for (int32_t j = 0; j < len; ++j) {
+                const int64_t idx = idx0 + static_cast<int64_t>(kSlice) * j;
+                const Rec q = load_rec(gerec, idx);
+                const double To = Ts[scol[idx]];
+                const double w = fabs(q.w);
+                const double s = signbit(q.w) ? w * (To - Tr) + Tr : w * (Tr - To) + To;
+                gx += q.x * s;
+                gy += q.y * s;
+                gz += q.z * s;
+            }
     }
     for (int32_t k = b0; k < b1; ++k) {
         const int32_t b = rbface_list[k];
@@ -487,44 +532,87 @@ k_nonorth_band(int32_t n, BandOffsets bo, double DT, const double *__restrict__ 
     }
 }
 
-// row layout (solver order): lower entries hold -k_f and -w_f, so their
+// one entry's correction flux: lower entries hold -k_f and -w_f, so their
 // (negated) flux is added; the weight's sign bit picks the interpolation side
+__device__ __forceinline__ double nonorth_entry(const Rec &q, double ox, double oy, double oz, double gx, double gy,
+                                                double gz) {
+    const double w = fabs(q.w);
+    double fx, fy, fz;
+    if (signbit(q.w)) {                     // lower face: g_f = w (g_o - g_r) + g_r
+        fx = w * (ox - gx) + gx;
+        fy = w * (oy - gy) + gy;
+        fz = w * (oz - gz) + gz;
+    } else {                                // owned face: g_f = w (g_r - g_o) + g_o
+        fx = w * (gx - ox) + ox;
+        fy = w * (gy - oy) + oy;
+        fz = w * (gz - oz) + oz;
+    }
+    return q.x * fx + q.y * fy + q.z * fz;
+}
+
+// the row's W slots loaded before any is used (as grad_row_faces does), the
+// fluxes added in slot order
+template <int W>
+__device__ __forceinline__ double nonorth_row_faces(int64_t idx0, int32_t len, double DT, double gx, double gy,
+                                                    double gz, const double *__restrict__ g,
+                                                    const int32_t *__restrict__ scol,
+                                                    const double *__restrict__ gkerec,
+                                                    const double *__restrict__ emag_sf) {
+    Rec q[W];
+    int32_t col[W];
+    double mg[W], o[W][3];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        const int64_t idx = idx0 + static_cast<int64_t>(kSlice) * j;
+        q[j] = load_rec(gkerec, idx);
+        col[j] = scol[idx];
+        mg[j] = emag_sf[idx];
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j)
+        for (int i = 0; i < 3; ++i) o[j][i] = g[3 * static_cast<int64_t>(col[j]) + i];
+    double div = 0.0;
+#pragma unroll
+    for (int j = 0; j < W; ++j)
+        if (j < len) div += (DT * mg[j]) * nonorth_entry(q[j], o[j][0], o[j][1], o[j][2], gx, gy, gz);
+    return div;
+}
+
+// row layout (solver order)
 __global__ void __launch_bounds__(kGradBlock)
 k_nonorth_rows(int32_t n, double DT, const double *__restrict__ g, const int32_t *__restrict__ soff,
                const int32_t *__restrict__ scol, const uint8_t *__restrict__ rlen, const double *__restrict__ gkerec,
                const double *__restrict__ emag_sf, const double *__restrict__ V, double *__restrict__ lap_src) {
     const int64_t r = static_cast<int64_t>(blockIdx.x) * kGradBlock + threadIdx.x;
     if (r >= n) return;
-    const int64_t idx0 = soff[r / kSlice] + r % kSlice;
+    const int32_t o0 = soff[r / kSlice];
+    const int64_t idx0 = o0 + r % kSlice;
+    const int32_t width = (soff[r / kSlice + 1] - o0) / kSlice;
     const int32_t len = rlen[r];
     const double gx = g[3 * r], gy = g[3 * r + 1], gz = g[3 * r + 2];
     const double v = V[r];
     double div = 0.0;
-    for (int32_t j = 0; j < len; ++j) {
-        const int64_t idx = idx0 + static_cast<int64_t>(kSlice) * j;
-        const Rec q = load_rec(gkerec, idx);
-        const int64_t o = scol[idx];
-        const double mg = emag_sf[idx];
-        const double ox = g[3 * o], oy = g[3 * o + 1], oz = g[3 * o + 2];
-        const double w = fabs(q.w);
-        double fx, fy, fz;
-        if (signbit(q.w)) {                     // lower face: g_f = w (g_o - g_r) + g_r
-            fx = w * (ox - gx) + gx;
-            fy = w * (oy - gy) + gy;
-            fz = w * (oz - gz) + gz;
-        } else {                                // owned face: g_f = w (g_r - g_o) + g_o
-            fx = w * (gx - ox) + ox;
-            fy = w * (gy - oy) + oy;
-            fz = w * (gz - oz) + oz;
-        }
-        const double corr = q.x * fx + q.y * fy + q.z * fz;
-        div += (DT * mg) * corr;
+    switch (width) {
+        case 0: break;
+        case 1: div = nonorth_row_faces<1>(idx0, len, DT, gx, gy, gz, g, scol, gkerec, emag_sf); break;
+        case 2: div = nonorth_row_faces<2>(idx0, len, DT, gx, gy, gz, g, scol, gkerec, emag_sf); break;
+        case 3: div = nonorth_row_faces<3>(idx0, len, DT, gx, gy, gz, g, scol, gkerec, emag_sf); break;
+        case 4: div = nonorth_row_faces<4>(idx0, len, DT, gx, gy, gz, g, scol, gkerec, emag_sf); break;
+        case 5: div = nonorth_row_faces<5>(idx0, len, DT, gx, gy, gz, g, scol, gkerec, emag_sf); break;
+        case 6: div = nonorth_row_faces<6>(idx0, len, DT, gx, gy, gz, g, scol, gkerec, emag_sf); break;
+        default:
+            for (int32_t j = 0; j < len; ++j) {
+                const int64_t idx = idx0 + static_cast<int64_t>(kSlice) * j;
+                const int64_t o = scol[idx];
+                div += (DT * emag_sf[idx]) *
+                       nonorth_entry(load_rec(gkerec, idx), g[3 * o], g[3 * o + 1], g[3 * o + 2], gx, gy, gz);
+            }
     }
     div /= v;
     lap_src[r] = 0.0 - v * div;
 }
 
-void launch_nonorth_source(lf_problem *P, hipStream_t s) {
+void launch_nonorth_source(lf_problem *P, hipStream_t s, bool correction) {
     const lf_mesh *m = P->mesh;
     const dim3 block(kGradBlock), grid((m->N + kGradBlock - 1) / kGradBlock);
     if (m->B > 0)
@@ -532,6 +620,7 @@ void launch_nonorth_source(lf_problem *P, hipStream_t s) {
                            m->rbface_cell, m->bface_patch, P->patch_type, P->patch_value, P->T, P->Tb);
     if (m->gkband) {
         launch_grad_band(m, P->T, P->Tb, nullptr, P->grad3, nullptr, false, s, true);
+        if (!correction) return;
         const BandOffsets bo = mesh_bands(m);
         const int64_t D = bo.d[bo.k - 1];
         const int R = grad_walk_rows(m->N, D);

@@ -28,7 +28,62 @@ namespace lf {
 // pass of the scaled inner system: s = sqrt(diag) rounded to FP32, the scaled
 // residual rs = r / s rounded to FP32, y = 0, and the partial sums of s|rs|
 // (the L1 norm of the residual the inner solve sees) and rs.rs.
-template <class Lay, bool kFull, bool kSetup, bool kMixed>
+// kNonorth (band meshes created non-orthogonal): the laplacian's explicit
+// non-orthogonal source is computed here from the face records and the
+// gradient (g, by component) instead of being read from a separate pass.
+
+// The explicit non-orthogonal source of cell c on a band mesh: for each face,
+// DT |S_f| k_f . (w g_P + (1 - w) g_N) with the face's owner-side weight,
+// subtracted for the cell's lower faces (taken k = K-1 .. 0) and added for its
+// owned faces (k = 0 .. K-1), the face loop's order; the sum divided by V and
+// multiplied back, as the separate correction pass does term for term.  gk
+// holds one record (k_x, k_y, k_z, w) per band slot.
+template <int K>
+__device__ __forceinline__ double band_nonorth_source(const BandLayout<K> &L, int32_t c, double DT, double v,
+                                                      const double *__restrict__ g,
+                                                      const double *__restrict__ gk) {
+    const int64_t n = L.n;
+    const double gc0 = g[c], gc1 = g[n + c], gc2 = g[2 * n + c];
+    double div = 0.0;
+#pragma unroll
+    for (int k = K - 1; k >= 0; --k) {      // lower faces (owner c - d_k): flux subtracted
+        const bool ok = c >= L.d[k];
+        const int64_t cl = ok ? c - L.d[k] : c;
+        const int64_t slot = static_cast<int64_t>(k) * n + cl;
+        const double mg = L.mag_sf[slot];
+        const double2 qa = reinterpret_cast<const double2 *>(gk)[2 * slot];
+        const double2 qb = reinterpret_cast<const double2 *>(gk)[2 * slot + 1];
+        const double o0 = g[cl], o1 = g[n + cl], o2 = g[2 * n + cl];
+        if (ok && mg > 0.0) {
+            const double fx = qb.y * (o0 - gc0) + gc0;
+            const double fy = qb.y * (o1 - gc1) + gc1;
+            const double fz = qb.y * (o2 - gc2) + gc2;
+            const double corr = qa.x * fx + qa.y * fy + qb.x * fz;
+            div -= (DT * mg) * corr;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {           // owned faces (neighbour c + d_k): flux added
+        const bool ok = c + static_cast<int64_t>(L.d[k]) < n;
+        const int64_t cu = ok ? c + L.d[k] : c;
+        const int64_t slot = static_cast<int64_t>(k) * n + c;
+        const double mg = L.mag_sf[slot];
+        const double2 qa = reinterpret_cast<const double2 *>(gk)[2 * slot];
+        const double2 qb = reinterpret_cast<const double2 *>(gk)[2 * slot + 1];
+        const double u0 = g[cu], u1 = g[n + cu], u2 = g[2 * n + cu];
+        if (ok && mg > 0.0) {
+            const double fx = qb.y * (gc0 - u0) + u0;
+            const double fy = qb.y * (gc1 - u1) + u1;
+            const double fz = qb.y * (gc2 - u2) + u2;
+            const double corr = qa.x * fx + qa.y * fy + qb.x * fz;
+            div += (DT * mg) * corr;
+        }
+    }
+    div /= v;
+    return 0.0 - v * div;
+}
+
+template <class Lay, bool kFull, bool kSetup, bool kMixed, bool kNonorth = false>
 __device__ __forceinline__ void assemble_rows(
     int32_t blk, const SolverParams &sp, double rdt, double DT, const Lay &L, const int32_t *__restrict__ bface_start,
     const int32_t *__restrict__ bface_list, const int32_t *__restrict__ bface_patch,
@@ -39,7 +94,8 @@ __device__ __forceinline__ void assemble_rows(
     double *__restrict__ bou_coeff, int32_t diag_pc, double *__restrict__ r, double *__restrict__ rD,
     double *__restrict__ part, const PcgState *__restrict__ st, float *__restrict__ sig32, float *__restrict__ r32,
     float *__restrict__ d32, double *__restrict__ p, const double *__restrict__ lap_src,
-    const double *__restrict__ T_old) {
+    const double *__restrict__ T_old, const double *__restrict__ nb_g = nullptr,
+    const double *__restrict__ nb_gk = nullptr) {
     const int32_t c = blk * kCellBlock + static_cast<int32_t>(threadIdx.x);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const double x_avg = kSetup ? st->x_avg : 0.0;
@@ -53,7 +109,11 @@ __device__ __forceinline__ void assemble_rows(
         // source (null on orthogonal meshes) is subtracted from the ddt source,
         // which uses T at the start of the step (T_old; null: T itself)
         const double xo = T_old ? T_old[c] : xc;
-        const double s = lap_src ? (rdt * xo) * v - lap_src[c] : (rdt * xo) * v;
+        double s;
+        if constexpr (kNonorth)
+            s = (rdt * xo) * v - band_nonorth_source(L, c, DT, v, nb_g, nb_gk);
+        else
+            s = lap_src ? (rdt * xo) * v - lap_src[c] : (rdt * xo) * v;
         double db = d, sb = s;
         for (int32_t i = bface_start[c]; i < bface_start[c + 1]; ++i) {
             const int32_t b = bface_list[i];
@@ -111,7 +171,7 @@ __device__ __forceinline__ void assemble_rows(
     }
 }
 
-template <class Lay, bool kFull, bool kSetup, bool kMixed>
+template <class Lay, bool kFull, bool kSetup, bool kMixed, bool kNonorth = false>
 __global__ void __launch_bounds__(kCellBlock)
 k_assemble(SolverParams sp, double rdt, double DT, Lay L, const int32_t *__restrict__ bface_start,
            const int32_t *__restrict__ bface_list, const int32_t *__restrict__ bface_patch,
@@ -123,11 +183,12 @@ k_assemble(SolverParams sp, double rdt, double DT, Lay L, const int32_t *__restr
            double *__restrict__ bou_coeff, int32_t diag_pc, double *__restrict__ r, double *__restrict__ rD,
            double *__restrict__ part, const PcgState *__restrict__ st, float *__restrict__ sig32,
            float *__restrict__ r32, float *__restrict__ d32, double *__restrict__ p,
-           const double *__restrict__ lap_src, const double *__restrict__ T_old) {
-    assemble_rows<Lay, kFull, kSetup, kMixed>(static_cast<int32_t>(blockIdx.x), sp, rdt, DT, L, bface_start,
-                                              bface_list, bface_patch, bmag_sf, bdelta, patch_type, patch_value, V,
-                                              T, coef, upper, diag, source, diagB, srcB, int_coeff, bou_coeff,
-                                              diag_pc, r, rD, part, st, sig32, r32, d32, p, lap_src, T_old);
+           const double *__restrict__ lap_src, const double *__restrict__ T_old,
+           const double *__restrict__ nb_g, const double *__restrict__ nb_gk) {
+    assemble_rows<Lay, kFull, kSetup, kMixed, kNonorth>(
+        static_cast<int32_t>(blockIdx.x), sp, rdt, DT, L, bface_start, bface_list, bface_patch, bmag_sf, bdelta,
+        patch_type, patch_value, V, T, coef, upper, diag, source, diagB, srcB, int_coeff, bou_coeff, diag_pc, r, rD,
+        part, st, sig32, r32, d32, p, lap_src, T_old, nb_g, nb_gk);
 }
 
 // partial sums of x0 = T (its mean enters the normalisation factor)
@@ -984,20 +1045,40 @@ void carve_problem(Carver &cv, const lf_mesh *m, const lf_solver_opts &o, lf_pro
 
 MeshRows mesh_rows(const lf_mesh *m) { return MeshRows{m->soff, m->scol, m->sface, m->rlen}; }
 
+template <class Lay>
+struct IsBandLayout : std::false_type {};
+template <int K>
+struct IsBandLayout<BandLayout<K>> : std::true_type {};
+
 template <bool kFull, bool kSetup, bool kMixed>
 static void launch_assemble_t(lf_problem *P, hipStream_t s) {
     const lf_mesh *m = P->mesh;
     const double rdt = 1.0 / P->dt;
     const bool diag_pc = P->opts.precond == LF_PC_DIAGONAL;
-    if (P->nonorth) launch_nonorth_source(P, s);
+    // band meshes: the correction's source is formed inside the assembly
+    // (the gradient pass still runs first)
+    const bool fused = P->nonorth && P->banded && !P->rb && m->gkband;
+    if (P->nonorth) launch_nonorth_source(P, s, !fused);
     with_layout(P, [&](auto lay) {
-        auto kern = k_assemble<decltype(lay), kFull, kSetup, kMixed>;
+        using Lay = decltype(lay);
+        const double *T_old = kSetup && P->nonorth && P->opts.n_nonorth_corr > 0 ? P->T_old : nullptr;
+        if constexpr (IsBandLayout<Lay>::value) {
+            if (fused) {
+                auto kern = k_assemble<Lay, kFull, kSetup, kMixed, true>;
+                LF_LAUNCH(P, LF_K_ASSEMBLE, s, kern, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, rdt, P->DT, lay,
+                          m->rbface_start, m->rbface_list, m->bface_patch, m->bmag_sf, m->bdelta, P->patch_type,
+                          P->patch_value, m->V, P->T, P->coef, P->upper, P->diag, P->source, P->diagB, P->srcB,
+                          P->int_coeff, P->bou_coeff, diag_pc ? 1 : 0, P->r, P->rD, P->part, P->state, P->sig32,
+                          P->r32, P->d32, P->p, nullptr, T_old, P->grad3, m->gkband);
+                return;
+            }
+        }
+        auto kern = k_assemble<Lay, kFull, kSetup, kMixed>;
         LF_LAUNCH(P, LF_K_ASSEMBLE, s, kern, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, rdt, P->DT, lay,
                   m->rbface_start, m->rbface_list, m->bface_patch, m->bmag_sf, m->bdelta, P->patch_type,
                   P->patch_value, m->V, P->T, P->coef, P->upper, P->diag, P->source, P->diagB, P->srcB,
                   P->int_coeff, P->bou_coeff, diag_pc ? 1 : 0, P->r, P->rD, P->part, P->state, P->sig32,
-                  P->r32, P->d32, P->p, P->nonorth ? P->lap_src : nullptr,
-                  kSetup && P->nonorth && P->opts.n_nonorth_corr > 0 ? P->T_old : nullptr);
+                  P->r32, P->d32, P->p, P->nonorth ? P->lap_src : nullptr, T_old, nullptr, nullptr);
     });
     if (kFull && P->rb && m->F > 0)
         hipLaunchKernelGGL(k_rb_upper, dim3(static_cast<unsigned>((m->F + kCellBlock - 1) / kCellBlock)),

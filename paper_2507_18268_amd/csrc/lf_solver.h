@@ -101,9 +101,10 @@ void launch_group_pass_start(const MemberDesc *tab, const GroupLaunch &gl, hipSt
 void launch_group_pass_end(const MemberDesc *tab, const GroupLaunch &cells, hipStream_t s);
 void launch_group_iteration(const MemberDesc *tab, const GroupLaunch &inner, hipStream_t s);
 void launch_group_gather(const MemberDesc *tab, const GroupLaunch &gl, PcgState *out, hipStream_t s);
-// non-orthogonal meshes: boundary values and gradient of T, then P->lap_src
-// (lf_grad.hip); runs before the assembly of each step
-void launch_nonorth_source(lf_problem *P, hipStream_t s);
+// non-orthogonal meshes: boundary values and gradient of T, then (correction:
+// on band meshes the assembly can form it instead) P->lap_src (lf_grad.hip);
+// runs before the assembly of each step
+void launch_nonorth_source(lf_problem *P, hipStream_t s, bool correction = true);
 lf_status launch_problem_grad(lf_problem *P, double *grad, double *bgrad);
 // A solve is driven in two halves so that one host loop can drive several
 // problems on their own streams: *_start enqueues the set-up and the first

@@ -25,3 +25,23 @@ def test_gpus_other_than_one_are_refused():
     r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], capture_output=True, text=True,
                        cwd=bench.ROOT, timeout=120)
     assert r.returncode != 0 and "one GPU" in r.stdout
+
+
+def test_serving_parameters_from_the_cache(tmp_path, monkeypatch):
+    """The serving loop's lane threshold and group iterations come from the
+    autotuner's cache for this architecture, else from the stated default."""
+    import json
+    from paper_2507_18268_amd import autotune
+    monkeypatch.setattr(autotune, "arch_key", lambda: "gfx950")
+    path = str(tmp_path / "cache.json")
+    assert autotune.serving_params(path) == autotune.SERVING_DEFAULT
+    with open(path, "w") as f:
+        json.dump({"gfx942/serving": {"direct_min_side": 40, "group_iters": 4}}, f)
+    assert autotune.serving_params(path) == autotune.SERVING_DEFAULT     # another GPU's
+    with open(path, "w") as f:
+        json.dump({"gfx950/serving": {"direct_min_side": 20, "group_iters": 1}}, f)
+    assert autotune.serving_params(path) == {"direct_min_side": 20, "group_iters": 1}
+    autotune._store("mixed", {"block_threads": [512] * len(autotune.BUCKETS)}, path, None)
+    with open(path) as f:
+        data = json.load(f)
+    assert set(data) == {"gfx950/serving", "gfx950/mixed"}                 # one form kept beside the other

@@ -122,11 +122,12 @@ def test_direct_lane_alone_equals_in_mix_and_matches_oracle(L, oracle):
 
 
 def test_direct_lane_at_served_sizes(L, oracle):
-    """Sides 32..48 on the direct lane (the serving stream sends sides >= 32
-    there), next to small batched requests: every step of the large requests
-    against the oracle's step from the same T, and alone = in the mix bitwise."""
+    """Sides 16..48 on the direct lane (the tuned threshold sends every side
+    of the serving stream, 16..96, there), next to small batched requests:
+    every step of the direct-lane requests against the oracle's step from the
+    same T, and alone = in the mix bitwise."""
     from paper_2507_18268_amd.serve import Request
-    sides = (32, 40, 48, 12, 9, 36)
+    sides = (32, 40, 48, 12, 9, 36, 16, 23)
     def reqs():
         rng = np.random.default_rng(21)
         out = []
@@ -136,9 +137,9 @@ def test_direct_lane_at_served_sizes(L, oracle):
                                T0=synth.initial_field(n ** 3, 8000 + i), bcs=synth.fixed_x_bcs(),
                                arrival=0.0005 * i))
         return out
-    mix, _ = serve(L, reqs(), budget=16 << 30, direct_min_side=32, direct_workers=3)
+    mix, _ = serve(L, reqs(), budget=16 << 30, direct_min_side=16, direct_workers=3)
     assert len(mix) == len(sides) and all(r.error is None for r in mix.values())
-    for rid in (0, 1, 2, 5):
+    for rid in (0, 1, 2, 5, 6, 7):
         r = mix[rid]
         mesh = mesh_for_side(r.n)
         T_prev = r.T0
@@ -147,7 +148,7 @@ def test_direct_lane_at_served_sizes(L, oracle):
             assert max_rel(r.snapshots[s], ref) <= 1e-8, (r.n, s)
             assert r.stats[s]["converged"] == 1
             T_prev = r.snapshots[s]
-    for rid in (0, 2):
-        alone, _ = serve(L, [reqs()[rid]], slots=1, cap=1, budget=16 << 30, direct_min_side=32,
+    for rid in (0, 2, 6):
+        alone, _ = serve(L, [reqs()[rid]], slots=1, cap=1, budget=16 << 30, direct_min_side=16,
                          direct_workers=1)
         assert np.array_equal(alone[rid].snapshots, mix[rid].snapshots)
