@@ -515,7 +515,8 @@ __device__ __forceinline__ double band_walk(const BandLayout<K> &L, const T *__r
 // ---------------------------------------------------------------------------
 // Block walk over a box's band layout: three bands with offsets 1, nx, nx ny,
 // i.e. row c = ix + nx iy + nx ny iz, with nx and N multiples of W.  The rows
-// are cut into tiles of kBwY x-lines by kBwZ planes; thread t of tile g takes
+// are cut into tiles of bw_lines(W) x-lines by bw_planes(W) planes; thread t
+// of tile g takes
 // the W x-adjacent rows c .. c + W - 1 (ix = W t) of each of the tile's
 // lines, so every array is read 16 bytes per lane (W = 2 doubles, W = 4
 // floats).  A row's y- and z-neighbours inside the thread's rows come from
@@ -595,6 +596,7 @@ template <class T, int W, bool kStream, bool kUnitDiag, class Fn>
 __device__ __forceinline__ void box_walk(const BandLayout<3> &L, const BoxWalk &bw, const T *__restrict__ diag,
                                          const T *__restrict__ coef, const T *__restrict__ x, Fn &&fn) {
     typedef Lanes<T, W> R;
+    constexpr int kBwY = bw_lines(W), kBwZ = bw_planes(W);
     const int64_t n = L.n, d1 = L.d[1], d2 = L.d[2];
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBwBlock + threadIdx.x;
     const int64_t g = i / bw.hx, t = i - g * bw.hx;
