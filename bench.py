@@ -372,18 +372,21 @@ def run_paper_sweep(L, torch, sides=PAPER_SIDES, steps=PAPER_STEPS, preconds=("d
     return out
 
 
-def grad_bytes(n_cells, n_faces, n_bfaces, n_bands=0, reordered=False):
+def grad_bytes(n_cells, n_faces, n_bfaces, n_bands=0, reordered=False, boundary_gradient=True):
     """Algorithmic bytes of one Gauss-gradient call.  Both paths: per cell T,
     V, the gradient (3 doubles) and the boundary-list start; per boundary face
-    its list entry, T_b, snGrad_b, its 32-byte record and the boundary
-    gradient.  Band path: one 32-byte record per band slot (n_bands per cell).
-    Row path: the row length per cell and, per internal face, on each of its
-    two rows a 32-byte record and a column index; a mesh kept in Morton order
-    adds the field's copy into that order (label, read, write) and the
-    label of each row's mesh cell."""
+    its list entry, T_b and its 32-byte record, and with boundary_gradient
+    also snGrad_b and the boundary gradient (3 doubles).  Band path: one
+    32-byte record per band slot (n_bands per cell).  Row path: the row length
+    per cell and, per internal face, on each of its two rows a 32-byte record
+    and a column index; a mesh kept in Morton order adds the field's copy into
+    that order (label, read, write) and the label of each row's mesh cell (the
+    gradient's round trip through a scratch array in the solver's order, 48 B
+    per cell, is not counted)."""
+    per_bface = 76 if boundary_gradient else 44
     if n_bands:
-        return 44 * n_cells + 32 * n_bands * n_cells + 76 * n_bfaces
-    return 45 * n_cells + 72 * n_faces + 76 * n_bfaces + (24 * n_cells if reordered else 0)
+        return 44 * n_cells + 32 * n_bands * n_cells + per_bface * n_bfaces
+    return 45 * n_cells + 72 * n_faces + per_bface * n_bfaces + (24 * n_cells if reordered else 0)
 
 
 def run_grad(L, torch, p, label, launches=20):
@@ -413,7 +416,31 @@ def run_grad(L, torch, p, label, launches=20):
     torch.cuda.synchronize()
     us = e0.elapsed_time(e1) * 1e3 / launches
     K = m.n_bands
+    # the same kernel as the corrected time step runs it: T and the gradient
+    # in the solver's order, no boundary gradient (3 steps with per-kernel
+    # timing; the step's other kernels are timed too)
+    prob = L.Problem(m, p.bcs, p.DT, p.dt)
+    prob.set_T(torch.from_numpy(p.T0).cuda())
+    prob.step(1)
+    prob.profile(True)
+    prob.step(3)
+    torch.cuda.synchronize()
+    prof = prob.profile_read()
+    prob.profile(False)
+    prob.close()
     m.close()
+    in_step = None
+    if "grad" in prof:
+        ms, cnt = prof["grad"]
+        us_s = 1e3 * ms / cnt
+        b_s = grad_bytes(N, F, B, K, False, boundary_gradient=False)
+        g_s = b_s / (us_s * 1e-6) / 1e9
+        in_step = {"kernel": (f"k_grad_band<{K}>" if K else "k_grad_rows") + " in the corrected step (solver order)",
+                   "launches": cnt, "avg_us": us_s, "algorithmic_bytes": b_s, "achieved_GBps": g_s,
+                   "frac": g_s / HBM_PEAK_GBS}
+        if "nonorth" in prof:
+            ms, cnt = prof["nonorth"]
+            in_step["correction_divergence_avg_us"] = 1e3 * ms / cnt
     nbytes = grad_bytes(N, F, B, K, reordered)
     gbps = nbytes / (us * 1e-6) / 1e9
     kname = f"k_grad_band<{K}>" if K else "k_grad_rows"
@@ -431,7 +458,8 @@ def run_grad(L, torch, p, label, launches=20):
             "algorithmic_bytes": nbytes, "achieved_GBps": gbps, "peak_GBps": HBM_PEAK_GBS,
             "frac": gbps / HBM_PEAK_GBS, "traffic": traffic,
             "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": gbps / HBM_PEAK_GBS, "traffic": traffic}}
+                         "frac": gbps / HBM_PEAK_GBS, "traffic": traffic},
+            "in_step": in_step}
 
 
 def run_serving(L, torch, args):

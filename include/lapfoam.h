@@ -256,7 +256,8 @@ lf_status lf_mesh_get_addressing(const lf_mesh *mesh, int32_t *owner_start, int3
  * are device outputs.  bgrad may be NULL (then snGrad_b is not read).  The
  * work is ordered on the mesh's stream and the call returns without waiting.
  * On a mesh kept in Morton order (lf_mesh_cell_order) T is first copied into
- * that order in a scratch array of the mesh: calls on one mesh must stay on
+ * that order and the gradient is formed in it, both in scratch arrays of the
+ * mesh, then gathered back to the mesh's order: calls on one mesh must stay on
  * its stream (not concurrent from several threads).
  * LF_EINVAL: NULL mesh, T, grad, or Tb (B > 0), or snGrad_b with bgrad given;
  * a mesh created without face centres. */
@@ -532,7 +533,12 @@ lf_status lf_group_poll(lf_group *group, lf_problem **finished, int32_t max_fini
 #define LF_K_AMG_RESTRICT 17    /* multigrid: residual summed over the aggregates */
 #define LF_K_AMG_PROLONG 18     /* multigrid: coarse correction added back */
 #define LF_K_AMG_GALERKIN 19    /* multigrid: coarse matrices (once per step) */
-#define LF_NUM_KERNEL_CLASSES 20
+#define LF_K_GRAD 20            /* non-orthogonal meshes: the gradient of T before
+                                   each assembly (solver order) */
+#define LF_K_NONORTH 21         /* non-orthogonal meshes without band form: the
+                                   correction fluxes' divergence (band meshes form
+                                   it inside the assembly) */
+#define LF_NUM_KERNEL_CLASSES 22
 lf_status lf_profile_enable(lf_problem *problem, int32_t on);
 lf_status lf_profile_read(lf_problem *problem, int32_t n_classes, double *total_ms, int64_t *launches);
 

@@ -161,6 +161,20 @@ __global__ void k_grad_to_rows(int32_t n, const int32_t *__restrict__ iperm, con
     if (r < n) Ts[r] = T[iperm[r]];
 }
 
+// the gradient back in the mesh's order: grad[c] = gs[perm[c]] (each thread
+// gathers one row's three components and writes its cell's contiguously; a
+// scatter of rows to their cells wrote partial cache lines at random)
+__global__ void k_grad_from_rows(int32_t n, const int32_t *__restrict__ perm, const double *__restrict__ gs,
+                                 double *__restrict__ grad) {
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const int64_t r = perm[c];
+    const double gx = gs[3 * r], gy = gs[3 * r + 1], gz = gs[3 * r + 2];
+    grad[3 * c] = gx;
+    grad[3 * c + 1] = gy;
+    grad[3 * c + 2] = gz;
+}
+
 // The internal faces' part of row r's gradient sum over its W slots of the
 // row layout (W = the slice's width): every slot's record, column and
 // neighbour value are loaded before any is used, so a thread has all its
@@ -292,19 +306,18 @@ __device__ __forceinline__ bool is_face(const Rec &r) { return r.x != 0.0 || r.y
 // (D = d_{K-1}, one z layer of a box): the face it owns on that band is the
 // next cell's lower face there, so its record and T[c] are carried in
 // registers instead of being fetched again a whole layer later (by then out
-// of L2 at 256^3).  Consecutive threads take consecutive c.  kNT writes the
-// gradient past the caches (a result for the caller, not read again here; 2%
-// faster at 256^3); the correction, which reads it next, keeps it cached.
-// Component i of cell c goes to grad[i gcs + c ges]: the caller's xyz rows
-// (gcs 1, ges 3), or one array per component for the correction (gcs n,
-// ges 1), whose loads are then contiguous.
-template <int K, int R, bool kNT>
+// of L2 at 256^3).  Consecutive threads take consecutive c.  The caller's
+// gradient (kStep false) goes to xyz rows grad[3c + i], written past the
+// caches (a result for the caller, not read again here; 2% faster at 256^3);
+// the corrected step's (kStep true) to one array per component, grad[i n + c],
+// kept cached for the correction, which reads it next with contiguous loads.
+template <int K, int R, bool kStep>
 __global__ void __launch_bounds__(kGradBlock)
 k_grad_band(int32_t n, BandOffsets bo, const double *__restrict__ T, const double *__restrict__ Tb,
             const double *__restrict__ snb, const double *__restrict__ gband,
             const int32_t *__restrict__ bface_start, const int32_t *__restrict__ bface_list,
             const double *__restrict__ gbface, const double *__restrict__ V, double *__restrict__ grad,
-            double *__restrict__ bgrad, int64_t gcs, int64_t ges) {
+            double *__restrict__ bgrad) {
     const int64_t D = bo.d[K - 1];
     const int64_t g = die_block(blockIdx.x, gridDim.x) * kGradBlock + threadIdx.x;
     const int64_t chunk = g / D;
@@ -366,14 +379,14 @@ k_grad_band(int32_t n, BandOffsets bo, const double *__restrict__ T, const doubl
         gx /= v;
         gy /= v;
         gz /= v;
-        if (kNT) {
-            __builtin_nontemporal_store(gx, grad + c * ges);
-            __builtin_nontemporal_store(gy, grad + gcs + c * ges);
-            __builtin_nontemporal_store(gz, grad + 2 * gcs + c * ges);
+        if (kStep) {
+            grad[c] = gx;
+            grad[n + c] = gy;
+            grad[2 * static_cast<int64_t>(n) + c] = gz;
         } else {
-            grad[c * ges] = gx;
-            grad[gcs + c * ges] = gy;
-            grad[2 * gcs + c * ges] = gz;
+            __builtin_nontemporal_store(gx, grad + 3 * c);
+            __builtin_nontemporal_store(gy, grad + 3 * c + 1);
+            __builtin_nontemporal_store(gz, grad + 3 * c + 2);
         }
         if (bgrad) {
             for (int32_t k = b0; k < b1; ++k) {
@@ -407,20 +420,20 @@ static BandOffsets mesh_bands(const lf_mesh *m) {
     return BandOffsets{m->n_bands, {m->band_d[0], m->band_d[1], m->band_d[2], m->band_d[3]}};
 }
 
-// the band path's launch (1 <= n_bands <= 4, checked by the callers); nt: the
-// gradient is written past the caches
+// the band path's launch (1 <= n_bands <= 4, checked by the callers); step:
+// the corrected step's gradient (one cached array per component), else the
+// caller's (xyz rows written past the caches)
 static void launch_grad_band(const lf_mesh *m, const double *T, const double *Tb, const double *snb, double *grad,
-                             double *bgrad, bool nt, hipStream_t s, bool by_component = false) {
-    const int64_t gcs = by_component ? m->N : 1, ges = by_component ? 1 : 3;
+                             double *bgrad, bool step, hipStream_t s) {
     const BandOffsets bo = mesh_bands(m);
     const int K = bo.k;
     const int64_t D = bo.d[K - 1];
     const int R = grad_walk_rows(m->N, D);
     const dim3 grid(static_cast<unsigned>(grad_walk_groups(m->N, D, R))), block(kGradBlock);
 #define LF_GRAD_BAND_NT(KK, RR, NT)                                                                      \
-    if (K == KK && R == RR && nt == NT)                                                                  \
+    if (K == KK && R == RR && step == NT)                                                                \
         hipLaunchKernelGGL((k_grad_band<KK, RR, NT>), grid, block, 0, s, m->N, bo, T, Tb, snb, m->gband,  \
-                           m->bface_start, m->bface_list, m->gbface, m->V, grad, bgrad, gcs, ges);
+                           m->bface_start, m->bface_list, m->gbface, m->V, grad, bgrad);
 #define LF_GRAD_BAND(KK, RR) LF_GRAD_BAND_NT(KK, RR, false) LF_GRAD_BAND_NT(KK, RR, true)
 #define LF_GRAD_BAND_R(KK) LF_GRAD_BAND(KK, 1) LF_GRAD_BAND(KK, 2)
     LF_GRAD_BAND_R(1)
@@ -619,7 +632,10 @@ void launch_nonorth_source(lf_problem *P, hipStream_t s, bool correction) {
         hipLaunchKernelGGL(k_nonorth_bvalues, dim3((m->B + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m->B,
                            m->rbface_cell, m->bface_patch, P->patch_type, P->patch_value, P->T, P->Tb);
     if (m->gkband) {
-        launch_grad_band(m, P->T, P->Tb, nullptr, P->grad3, nullptr, false, s, true);
+        {
+            ProfScope ps(P, LF_K_GRAD, s);
+            launch_grad_band(m, P->T, P->Tb, nullptr, P->grad3, nullptr, true, s);
+        }
         if (!correction) return;
         const BandOffsets bo = mesh_bands(m);
         const int64_t D = bo.d[bo.k - 1];
@@ -627,8 +643,8 @@ void launch_nonorth_source(lf_problem *P, hipStream_t s, bool correction) {
         const dim3 wgrid(static_cast<unsigned>(grad_walk_groups(m->N, D, R)));
 #define LF_NONORTH_BAND(KK, RR)                                                                              \
         if (bo.k == KK && R == RR)                                                                           \
-            hipLaunchKernelGGL((k_nonorth_band<KK, RR>), wgrid, block, 0, s, m->N, bo, P->DT, P->grad3,      \
-                               m->gkband, m->band_mag_sf, m->V, P->lap_src);
+            LF_LAUNCH(P, LF_K_NONORTH, s, (k_nonorth_band<KK, RR>), wgrid, block, 0, s, m->N, bo, P->DT,     \
+                      P->grad3, m->gkband, m->band_mag_sf, m->V, P->lap_src);
 #define LF_NONORTH_BAND_R(KK) LF_NONORTH_BAND(KK, 1) LF_NONORTH_BAND(KK, 2)
         LF_NONORTH_BAND_R(1)
         LF_NONORTH_BAND_R(2)
@@ -638,10 +654,10 @@ void launch_nonorth_source(lf_problem *P, hipStream_t s, bool correction) {
 #undef LF_NONORTH_BAND
     } else {
         // the gradient in the solver's order (T is kept in it): no copy, no scatter
-        hipLaunchKernelGGL(k_grad_rows, grid, block, 0, s, m->N, P->T, P->Tb, nullptr, m->soff, m->scol, m->rlen,
-                           m->gerec, m->rbface_start, m->rbface_list, m->gbface, m->V, nullptr, P->grad3, nullptr);
-        hipLaunchKernelGGL(k_nonorth_rows, grid, block, 0, s, m->N, P->DT, P->grad3, m->soff, m->scol, m->rlen,
-                           m->gkerec, m->emag_sf, m->V, P->lap_src);
+        LF_LAUNCH(P, LF_K_GRAD, s, k_grad_rows, grid, block, 0, s, m->N, P->T, P->Tb, nullptr, m->soff, m->scol,
+                  m->rlen, m->gerec, m->rbface_start, m->rbface_list, m->gbface, m->V, nullptr, P->grad3, nullptr);
+        LF_LAUNCH(P, LF_K_NONORTH, s, k_nonorth_rows, grid, block, 0, s, m->N, P->DT, P->grad3, m->soff, m->scol,
+                  m->rlen, m->gkerec, m->emag_sf, m->V, P->lap_src);
     }
 }
 
@@ -676,7 +692,7 @@ lf_status launch_problem_grad(lf_problem *P, double *grad, double *bgrad) {
     }
     if (m->gband) {
         if (m->n_bands < 1 || m->n_bands > kMaxBands) { set_error("bad band count %d", m->n_bands); return LF_EINVAL; }
-        launch_grad_band(m, P->T, P->Tb, P->snb, grad, bgrad, true, s);
+        launch_grad_band(m, P->T, P->Tb, P->snb, grad, bgrad, false, s);
     } else {
         // T is kept in the solver's order: no copy; rows write to their mesh cells
         hipLaunchKernelGGL(k_grad_rows, dim3((m->N + kGradBlock - 1) / kGradBlock), dim3(kGradBlock), 0, s, m->N,
@@ -705,18 +721,22 @@ extern "C" lf_status lf_grad(const lf_mesh *m, const double *T, const double *Tb
     const dim3 block(kGradBlock);
     if (!m->gband) {
         const dim3 grid((m->N + kGradBlock - 1) / kGradBlock);
-        const double *Ts = T;
-        if (m->iperm) {
+        if (!m->iperm) {
+            hipLaunchKernelGGL(k_grad_rows, grid, block, 0, m->stream, m->N, T, Tb, snb, m->soff, m->scol, m->rlen,
+                               m->gerec, m->rbface_start, m->rbface_list, m->gbface, m->V, nullptr, grad, bgrad);
+        } else {
+            // T into the solver's order, the gradient in it, then back to the mesh's order
             hipLaunchKernelGGL(k_grad_to_rows, grid, block, 0, m->stream, m->N, m->iperm, T, m->gT);
-            Ts = m->gT;
+            hipLaunchKernelGGL(k_grad_rows, grid, block, 0, m->stream, m->N, m->gT, Tb, snb, m->soff, m->scol,
+                               m->rlen, m->gerec, m->rbface_start, m->rbface_list, m->gbface, m->V, nullptr, m->gG,
+                               bgrad);
+            hipLaunchKernelGGL(k_grad_from_rows, grid, block, 0, m->stream, m->N, m->perm, m->gG, grad);
         }
-        hipLaunchKernelGGL(k_grad_rows, grid, block, 0, m->stream, m->N, Ts, Tb, snb, m->soff, m->scol, m->rlen,
-                           m->gerec, m->rbface_start, m->rbface_list, m->gbface, m->V, m->iperm, grad, bgrad);
         LF_HIP(hipGetLastError());
         return LF_OK;
     }
     if (m->n_bands < 1 || m->n_bands > kMaxBands) { set_error("bad band count %d", m->n_bands); return LF_EINVAL; }
-    launch_grad_band(m, T, Tb, snb, grad, bgrad, true, m->stream);
+    launch_grad_band(m, T, Tb, snb, grad, bgrad, false, m->stream);
     LF_HIP(hipGetLastError());
     return LF_OK;
 }
@@ -770,7 +790,7 @@ extern "C" lf_status lf_grad_noalloc(const lf_mesh *m, const double *T, const do
     if (m->gband) {
         // the band form reads T in place: no scratch
         if (m->n_bands < 1 || m->n_bands > kMaxBands) { set_error("bad band count %d", m->n_bands); return LF_EINVAL; }
-        launch_grad_band(m, T, Tb, snb, grad, bgrad, true, m->stream);
+        launch_grad_band(m, T, Tb, snb, grad, bgrad, false, m->stream);
         LF_HIP(hipGetLastError());
         return LF_OK;
     }

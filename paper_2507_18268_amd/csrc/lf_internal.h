@@ -178,10 +178,12 @@ struct lf_mesh {
     // Without band form the records are also kept per entry of the row layout
     // (gerec, in the solver's row order; an entry whose face has the row's cell
     // as neighbour stores -S_f and -w_f, the sign bit of w marking it), and
-    // a reordered mesh keeps a scratch copy of the field in the solver's order.
+    // a reordered mesh keeps scratch copies of the field and its gradient in
+    // the solver's order.
     double *gface = nullptr;                              // [4F], or null
     double *gerec = nullptr;                              // [4*n_entries], or null
     double *gT = nullptr;                                 // [N], or null
+    double *gG = nullptr;                                 // [3N], or null
     double *gband = nullptr;                              // [4*n_bands*N], or null
     double *gbface = nullptr;                             // [4B], or null
     // Non-orthogonal meshes (LF_MESH_NON_ORTHOGONAL with face centres): the

@@ -344,7 +344,7 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, i
         rb_mag = cv.take<double>(6 * static_cast<size_t>(rb_nr));
         rb_delta = cv.take<double>(6 * static_cast<size_t>(rb_nr));
     }
-    double *gface = nullptr, *gband = nullptr, *gbface = nullptr, *gerec = nullptr, *gT = nullptr;
+    double *gface = nullptr, *gband = nullptr, *gbface = nullptr, *gerec = nullptr, *gT = nullptr, *gG = nullptr;
     double *gkface = nullptr, *gkerec = nullptr, *gkband = nullptr;
     if (grad) {
         if (K > 0) {
@@ -353,7 +353,10 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, i
         } else {
             gface = cv.take<double>(4 * static_cast<size_t>(F));
             gerec = cv.take<double>(4 * static_cast<size_t>(E));
-            if (reorder) gT = cv.take<double>(N);
+            if (reorder) {
+                gT = cv.take<double>(N);
+                gG = cv.take<double>(3 * static_cast<size_t>(N));
+            }
             if (skew) {
                 gkface = cv.take<double>(4 * static_cast<size_t>(F));
                 gkerec = cv.take<double>(4 * static_cast<size_t>(E));
@@ -372,7 +375,7 @@ static void carve_mesh(Carver &cv, int32_t N, int32_t F, int32_t B, int64_t E, i
     sc.Cf = grad ? cv.take<double>(3 * static_cast<size_t>(std::min<int64_t>(std::max(F, 1), kGeomChunk)))
                  : nullptr;
     if (m) {
-        m->gface = gface; m->gband = gband; m->gbface = gbface; m->gerec = gerec; m->gT = gT;
+        m->gface = gface; m->gband = gband; m->gbface = gbface; m->gerec = gerec; m->gT = gT; m->gG = gG;
         m->gkface = gkface; m->gkerec = gkerec; m->gkband = gkband;
         m->owner = owner; m->neighbour = neighbour; m->owner_start = owner_start;
         m->losort = losort; m->losort_start = losort_start; m->bface_start = bface_start;

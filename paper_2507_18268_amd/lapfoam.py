@@ -136,7 +136,7 @@ _SIGS = {
 KERNEL_CLASSES = ["assemble", "sum_x", "commit", "direction", "amul_dot", "update", "dic_rd",
                   "dic_forward", "dic_backward", "mixed_residual", "mixed_correct",
                   "inner_direction", "inner_amul_dot", "inner_update", "mixed_prep", "finalize",
-                  "amg_smooth", "amg_restrict", "amg_prolong", "amg_galerkin"]
+                  "amg_smooth", "amg_restrict", "amg_prolong", "amg_galerkin", "grad", "nonorth"]
 
 
 def lib():

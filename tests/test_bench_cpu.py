@@ -11,6 +11,9 @@ def test_gradient_bytes_per_launch():
     # row path: 45 B per cell, 72 B per internal face, 76 B per boundary face (+24 B per cell reordered)
     assert bench.grad_bytes(N, F, B) == 45 * N + 72 * F + 76 * B
     assert bench.grad_bytes(N, F, B, 0, True) - bench.grad_bytes(N, F, B) == 24 * N
+    # as the corrected step runs it: no snGrad_b and no boundary gradient (44 B per boundary face)
+    assert bench.grad_bytes(N, F, B, 3, boundary_gradient=False) == 44 * N + 96 * N + 44 * B
+    assert bench.grad_bytes(N, F, B, boundary_gradient=False) == 45 * N + 72 * F + 44 * B
 
 
 def test_amul_bytes_per_launch():
