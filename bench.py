@@ -663,7 +663,8 @@ def main():
     torch.cuda.synchronize()
     layout_name = "bands" if prob.layout() == L.LF_LAYOUT_BANDS else "rows"
     walk = prob.amul_form()
-    amul_form = {0: "one row per thread", 1: "row walk", 2: "block walk of the box"}[walk]
+    amul_form = {0: "one row per thread", 1: "row walk", 2: "block walk of the box",
+                 3: "two red-black pairs per lane"}[walk]
     log(f"[bench] device mesh + problem ready in {time.perf_counter() - t:.1f} s "
         f"(workspaces {mesh.ws_bytes / 2**30:.2f} + {prob.ws_bytes / 2**30:.2f} GiB, {layout_name} layout{', Amul by the ' + amul_form if walk else ''})")
 
@@ -719,7 +720,7 @@ def main():
         # neighbours are implicit (c + d_k), so no face addresses
         per_launch = amul_bytes(N, F, addressed=(layout_name != "bands"))
         achieved = per_launch / (us * 1e-6) / 1e9
-        kname = {0: "k_amul_dot", 1: "k_amul_dot_walk", 2: "k_amul_dot_box"}[walk]
+        kname = {0: "k_amul_dot", 1: "k_amul_dot_walk", 2: "k_amul_dot_box", 3: "k_amul_dot_rb2"}[walk]
         roof = {"kernel": f"{kname} (q = A p with p.q partials)", "bound": "hbm",
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,

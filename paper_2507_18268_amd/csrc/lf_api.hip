@@ -204,6 +204,17 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
         // an iteration then number the pair workgroups
         P->sp.grid_amul = cell_blocks(m->n_red);
         P->sp.grid_upd = P->sp.grid_amul;
+        // the product with two pairs per lane where x-lines hold a multiple of
+        // four cells, under the row walk's rule (its partials number its own
+        // workgroups; the sweeps keep one pair per thread)
+        const RBForm rf = rb_form(m);
+        if (rb2_form(rf) && opts.amul_walk != LF_WALK_OFF) {
+            const int32_t wb = rb2_blocks(rf.nr);
+            if (opts.amul_walk == LF_WALK_ON || wb >= kWalkMinBlocks) {
+                P->rb2 = true;
+                P->sp.grid_amul = wb;
+            }
+        }
     }
     P->sp.max_outer = opts.max_outer > 0 ? opts.max_outer : 50;
     P->sp.inner_tol = opts.inner_tol > 0.0 ? opts.inner_tol : 1e-5;
@@ -291,7 +302,7 @@ lf_status lf_problem_layout(const lf_problem *P, int32_t *layout) {
 lf_status lf_problem_amul_walk(const lf_problem *P, int32_t *walk) {
     clear_error();
     if (!P || !walk) { set_error("NULL argument"); return LF_EINVAL; }
-    *walk = P->box ? 2 : (P->walk ? 1 : 0);
+    *walk = P->box ? 2 : (P->walk ? 1 : (P->rb2 ? 3 : 0));
     return LF_OK;
 }
 

@@ -586,6 +586,126 @@ __device__ __forceinline__ void lanes_store_stream(T *__restrict__ a, int64_t i,
     __builtin_nontemporal_store(x, reinterpret_cast<V *>(a + i));
 }
 
+// The product of the two-colour band layout with two red-black pairs per
+// lane: lane t takes the pairs u = 2t and u + 1 (the same x-line, since h is
+// even), so every array is read 16 bytes per lane (red slots, p of both
+// colours, the diagonal; the y and z entries at u -+ h and u -+ H likewise).
+// The x entries a pair's rows need from outside the lane's two pairs (p and
+// the red slots +x and -x at u - 1 or u + 2) come from the adjacent lane when
+// it holds the adjacent pairs, else from memory; a black row's x coefficients
+// are its red neighbours' slots, which the lane has loaded as the red rows'
+// own.  Each row's sum is the pair kernel's term for term (absent entries as
+// zero coefficients times the row's own p), so the product is bitwise the
+// same.  Every lane of a wave must run it (the lane exchanges).
+inline bool rb2_form(const RBForm &f) { return f.h % 2 == 0 && f.nr % 2 == 0; }
+
+inline int32_t rb2_blocks(int32_t nr) { return static_cast<int32_t>((nr / 2 + kCellBlock - 1) / kCellBlock); }
+
+template <class Fn>
+__device__ __forceinline__ void rb2_product(const RBForm &f, const double *__restrict__ diagB,
+                                            const double *__restrict__ coef, const double *__restrict__ p,
+                                            Fn &&fn) {
+    typedef Lanes<double, 2> R;
+    const int64_t nr = f.nr, h = f.h, H = f.H;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * kCellBlock + threadIdx.x;
+    const int64_t u = 2 * t;
+    const bool tv = u < nr;
+    const int key = tv ? static_cast<int>(u) : -8;
+    const bool below_ok = lane_from_below(key, -1000) == key - 2;
+    const bool above_ok = lane_from_above(key, -1000) == key + 2;
+    const R z = lanes_zero<double, 2>();
+    const int32_t par = tv ? rb_par(f, static_cast<int32_t>(u)) : 0;
+    const int64_t pos = tv ? u % h : 0;
+    // own values: red slots 0..5, p of both colours, diagonals
+    R sl[6], pr = z, pb = z, dr = z, db = z;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) sl[j] = z;
+    if (tv) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) sl[j] = lanes_load<double, 2>(coef, j * nr + u);
+        pr = lanes_load<double, 2>(p, u);
+        pb = lanes_load<double, 2>(p, nr + u);
+        dr = lanes_load<double, 2, true>(diagB, u);
+        db = lanes_load<double, 2, true>(diagB, nr + u);
+    }
+    // the adjacent lanes' values at u - 1 and u + 2 (p of both colours, the
+    // red slots +x at u - 1 and -x at u + 2)
+    double pb_m1 = lane_from_below(pb.v[1]), pr_m1 = lane_from_below(pr.v[1]), s3_m1 = lane_from_below(sl[3].v[1]);
+    double pb_p2 = lane_from_above(pb.v[0]), pr_p2 = lane_from_above(pr.v[0]), s2_p2 = lane_from_above(sl[2].v[0]);
+    if (!tv) return;
+    if (!below_ok && pos >= 2) {
+        pb_m1 = p[nr + u - 1];
+        pr_m1 = p[u - 1];
+        s3_m1 = coef[3 * nr + u - 1];
+    }
+    if (!above_ok && pos + 2 <= h - 1) {
+        pb_p2 = p[nr + u + 2];
+        pr_p2 = p[u + 2];
+        s2_p2 = coef[2 * nr + u + 2];
+    }
+    // y and z entries: black p and the mirrored red slots (black rows) one
+    // line or plane down and up, and the red p there
+    const bool zlo = H > 0 && u >= H, zhi = H > 0 && u + H < nr;
+    const bool ylo = u >= h, yhi = u + h < nr;
+    R pbz0 = z, pbz1 = z, pby0 = z, pby1 = z, prz0 = z, prz1 = z, pry0 = z, pry1 = z;
+    R bz0 = z, bz1 = z, by0 = z, by1 = z;
+    if (zlo) {
+        pbz0 = lanes_load<double, 2>(p, nr + u - H);
+        prz0 = lanes_load<double, 2>(p, u - H);
+        bz0 = lanes_load<double, 2>(coef, 5 * nr + u - H);
+    }
+    if (ylo) {
+        pby0 = lanes_load<double, 2>(p, nr + u - h);
+        pry0 = lanes_load<double, 2>(p, u - h);
+        by0 = lanes_load<double, 2>(coef, 4 * nr + u - h);
+    }
+    if (yhi) {
+        pby1 = lanes_load<double, 2>(p, nr + u + h);
+        pry1 = lanes_load<double, 2>(p, u + h);
+        by1 = lanes_load<double, 2>(coef, nr + u + h);
+    }
+    if (zhi) {
+        pbz1 = lanes_load<double, 2>(p, nr + u + H);
+        prz1 = lanes_load<double, 2>(p, u + H);
+        bz1 = lanes_load<double, 2>(coef, u + H);
+    }
+    R qr, qb;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int64_t pk = pos + k;
+        // validity of the x entries (the pair kernel's rules)
+        const bool rxlo = pk + par - 1 >= 0, rxhi = pk + par <= h - 1;
+        const bool bxlo = pk >= par, bxhi = pk + 1 - par <= h - 1;
+        // red row u + k: black p at u + k + par - 1 and u + k + par
+        const double rpx_lo = par ? pb.v[k] : (k == 0 ? pb_m1 : pb.v[0]);
+        const double rpx_hi = par ? (k == 0 ? pb.v[1] : pb_p2) : pb.v[k];
+        // black row u + k: red p and the red slots -x / +x of the red cells at
+        // u + k - par (its -x neighbour, slot +x) and u + k + 1 - par (slot -x)
+        const double bpx_lo = par ? (k == 0 ? pr_m1 : pr.v[0]) : pr.v[k];
+        const double bpx_hi = par ? pr.v[k] : (k == 0 ? pr.v[1] : pr_p2);
+        const double bax_lo = par ? (k == 0 ? s3_m1 : sl[3].v[0]) : sl[3].v[k];
+        const double bax_hi = par ? sl[2].v[k] : (k == 0 ? sl[2].v[1] : s2_p2);
+        const double own_b = pb.v[k], own_r = pr.v[k];
+        const double ra[6] = {zlo ? sl[0].v[k] : 0.0, ylo ? sl[1].v[k] : 0.0, rxlo ? sl[2].v[k] : 0.0,
+                              rxhi ? sl[3].v[k] : 0.0, yhi ? sl[4].v[k] : 0.0, zhi ? sl[5].v[k] : 0.0};
+        const double rx[6] = {zlo ? pbz0.v[k] : own_b, ylo ? pby0.v[k] : own_b, rxlo ? rpx_lo : own_b,
+                              rxhi ? rpx_hi : own_b, yhi ? pby1.v[k] : own_b, zhi ? pbz1.v[k] : own_b};
+        const double ba[6] = {zlo ? bz0.v[k] : 0.0, ylo ? by0.v[k] : 0.0, bxlo ? bax_lo : 0.0,
+                              bxhi ? bax_hi : 0.0, yhi ? by1.v[k] : 0.0, zhi ? bz1.v[k] : 0.0};
+        const double bx[6] = {zlo ? prz0.v[k] : own_r, ylo ? pry0.v[k] : own_r, bxlo ? bpx_lo : own_r,
+                              bxhi ? bpx_hi : own_r, yhi ? pry1.v[k] : own_r, zhi ? prz1.v[k] : own_r};
+        double a = dr.v[k] * pr.v[k], b = db.v[k] * pb.v[k];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            a += ra[j] * rx[j];
+            b += ba[j] * bx[j];
+        }
+        qr.v[k] = a;
+        qb.v[k] = b;
+    }
+    fn(u, qr, qb, pr, pb);
+}
+
 // The walk: calls fn(c, y, x, diag) for the thread's groups of W rows
 // (c .. c + W - 1; lines in order, within a line the planes in order), y = A x
 // with the diagonal term first (kUnitDiag: a matrix with unit diagonal, x

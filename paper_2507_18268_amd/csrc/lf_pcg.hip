@@ -721,6 +721,40 @@ k_amul_dot_rb(SolverParams sp, RBLayout L, const double *__restrict__ diagB, con
     write_partials<1>(part, sp.grid, slots, acc);
 }
 
+// q = A p on the two-colour band layout, two red-black pairs per lane
+// (rb2_product; sp.grid_amul workgroups), with partial sums of p.q
+__global__ void __launch_bounds__(kCellBlock)
+k_amul_dot_rb2(SolverParams sp, RBLayout L, const double *__restrict__ diagB, const double *__restrict__ coef,
+               const double *__restrict__ p, double *__restrict__ q, double *__restrict__ part,
+               const PcgState *__restrict__ st) {
+    if (st->done) return;
+    typedef Lanes<double, 2> R;
+    const int64_t nr = L.f.nr;
+    double acc[1] = {0.0};
+    rb2_product(L.f, diagB, coef, p, [&](int64_t u, const R &qr, const R &qb, const R &pr, const R &pb) {
+        lanes_store_stream(q, u, qr);
+        lanes_store_stream(q, nr + u, qb);
+        acc[0] += qr.v[0] * pr.v[0] + qb.v[0] * pb.v[0];
+        acc[0] += qr.v[1] * pr.v[1] + qb.v[1] * pb.v[1];
+    });
+    const int slots[1] = {kPartPq};
+    write_partials<1>(part, sp.grid, slots, acc);
+}
+
+// the product alone (test hook)
+__global__ void __launch_bounds__(kCellBlock)
+k_amul_rb2(RBLayout L, const double *__restrict__ diagB, const double *__restrict__ coef,
+           const double *__restrict__ x, double *__restrict__ y) {
+    typedef Lanes<double, 2> R;
+    const int64_t nr = L.f.nr;
+    rb2_product(L.f, diagB, coef, x, [&](int64_t u, const R &qr, const R &qb, const R &, const R &) {
+        y[u] = qr.v[0];
+        y[u + 1] = qr.v[1];
+        y[nr + u] = qb.v[0];
+        y[nr + u + 1] = qb.v[1];
+    });
+}
+
 // backward sweep on the red rows, one thread per half-index u (red row u),
 // with the w.r partial sums of the red row and of the black row nr + u (its
 // w from the forward sweep); sp.grid_amul workgroups (the slot's further
@@ -1196,8 +1230,12 @@ static lf_status launch_iteration(lf_problem *P, hipStream_t s) {
             }
         }
         if constexpr (std::is_same_v<decltype(lay), RBLayout>) {
-            LF_LAUNCH(P, LF_K_AMUL_DOT, s, k_amul_dot_rb, dim3(static_cast<unsigned>(P->sp.grid_amul)),
-                      dim3(kCellBlock), 0, s, P->sp, lay, P->diagB, P->coef, P->p, P->q, P->part, P->state);
+            if (P->rb2)
+                LF_LAUNCH(P, LF_K_AMUL_DOT, s, k_amul_dot_rb2, dim3(static_cast<unsigned>(P->sp.grid_amul)),
+                          dim3(kCellBlock), 0, s, P->sp, lay, P->diagB, P->coef, P->p, P->q, P->part, P->state);
+            else
+                LF_LAUNCH(P, LF_K_AMUL_DOT, s, k_amul_dot_rb, dim3(static_cast<unsigned>(P->sp.grid_amul)),
+                          dim3(kCellBlock), 0, s, P->sp, lay, P->diagB, P->coef, P->p, P->q, P->part, P->state);
             return;
         }
         LF_LAUNCH(P, LF_K_AMUL_DOT, s, k_amul_dot<decltype(lay)>, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, lay,
@@ -1208,7 +1246,7 @@ static lf_status launch_iteration(lf_problem *P, hipStream_t s) {
         // red-black DIC on the two-colour band layout: the update of r fused
         // into the two sweeps
         const lf_mesh *m = P->mesh;
-        const dim3 gb(static_cast<unsigned>(P->sp.grid_amul));
+        const dim3 gb(static_cast<unsigned>(P->sp.grid_upd));
         LF_LAUNCH(P, LF_K_DIC_FORWARD, s, k_dic_update_forward_rb, gb, dim3(kCellBlock), 0, s, P->sp, rb_layout(m),
                   P->coef, P->rD, P->q, P->r, P->w, P->part, P->state);
         LF_LAUNCH(P, LF_K_DIC_BACKWARD, s, k_dic_backward_rb_pair<true>, gb, dim3(kCellBlock), 0, s, P->sp,
@@ -1381,6 +1419,13 @@ lf_status launch_precondition_hook(lf_problem *P) {
 
 lf_status launch_amul_hook(lf_problem *P, const double *x, double *y) {
     with_layout(P, [&](auto lay) {
+        if constexpr (std::is_same_v<decltype(lay), RBLayout>) {
+            if (P->rb2) {
+                hipLaunchKernelGGL(k_amul_rb2, dim3(static_cast<unsigned>(P->sp.grid_amul)), dim3(kCellBlock), 0,
+                                   P->stream, lay, P->diagB, P->coef, x, y);
+                return;
+            }
+        }
         if constexpr (std::is_same_v<decltype(lay), BandLayout<3>>) {
             if (P->box) {
                 hipLaunchKernelGGL(k_amul_box, dim3(static_cast<unsigned>(P->bw.blocks)), dim3(kBwBlock), 0,

@@ -572,11 +572,13 @@ class Problem:
         return lf_problem_layout(self.h)
 
     def amul_walk(self):
-        """True if the FP64 matrix-vector product runs as a walk (row or block)."""
+        """True if the FP64 matrix-vector product runs as a walk (row or block)
+        or, with DIC on the two-colour layout, with two pairs per lane."""
         return bool(lf_problem_amul_walk(self.h))
 
     def amul_form(self):
-        """0 one row per thread, 1 the row walk, 2 the block walk of a box."""
+        """0 one row per thread, 1 the row walk, 2 the block walk of a box,
+        3 DIC's product on the two-colour layout with two red-black pairs per lane."""
         return lf_problem_amul_walk(self.h)
 
     def reset(self, bcs, DT, dt):

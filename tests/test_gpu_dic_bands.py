@@ -121,3 +121,56 @@ def test_rb_form_only_where_it_applies(L):
     assert P.layout() == L.LF_LAYOUT_ROWS
     P.close()
     m.close()
+
+
+# x-lines of a multiple of four cells (two red-black pairs per lane): boxes,
+# a line and an xz box; 260 cells per line put a line's pairs on two waves
+# (lanes at a wave's edge load their x-neighbours) and 8 lines on 17 waves
+WALK_MESHES = [(n, mm) for n, mm in MESHES if n in ("rb_16x10x6_graded", "rb_4x4x4", "rb_line_12",
+                                                   "rb_xz_8x1x5")]
+WALK_MESHES.append(("rb_4x4x20", _rb(4, 4, 20)))
+WALK_MESHES.append(("rb_260x4x2_graded", _rb(260, 4, 2, 3.0)))
+
+
+@pytest.mark.parametrize("name,mm", WALK_MESHES, ids=[n for n, _ in WALK_MESHES])
+def test_rb_walk_product_bitwise_and_steps(L, oracle, name, mm):
+    """The product with two red-black pairs per lane: bitwise the oracle's;
+    steps within 1e-8 of the oracle's sequential DIC and of the steps with
+    one pair per thread, iterations within one."""
+    import torch
+    mesh, new_of_old = mm
+    T0 = synth.initial_field(mesh.n_cells, 13, new_of_old=new_of_old)
+    steps = 3
+    _, so, snaps = oracle.run(mesh, synth.fixed_x_bcs(), DT, dt, steps, T0, pc=oracle.PC_DIC, keep_all=True)
+    out = {}
+    for walk in (L.LF_WALK_ON, L.LF_WALK_OFF):
+        m, P = _problem(L, mesh, amul_walk=walk)
+        assert P.layout() == L.LF_LAYOUT_BANDS
+        assert P.amul_form() == (3 if walk == L.LF_WALK_ON else 0), name
+        if walk == L.LF_WALK_ON:
+            P.set_T(T0)
+            P.assemble()
+            o = oracle.assemble(mesh, synth.fixed_x_bcs(), DT, dt, T0)
+            x = np.random.default_rng(7).uniform(-1.0, 1.0, mesh.n_cells)
+            xd = torch.from_numpy(x).cuda()
+            yd = torch.empty_like(xd)
+            P.amul(xd, yd)
+            torch.cuda.synchronize()
+            assert np.array_equal(yd.cpu().numpy(), oracle.amul(mesh, o["diag_b"], o["upper"], x)), name
+        P.set_T(T0)
+        Ts, st = [], []
+        for s in range(steps):
+            s1, _ = P.step(1)
+            st += s1
+            Ts.append(P.get_T())
+        out[walk] = (Ts, st)
+        P.close()
+        m.close()
+    Tw, sw = out[L.LF_WALK_ON]
+    Tp, sp = out[L.LF_WALK_OFF]
+    for s in range(steps):
+        assert max_rel(Tw[s], snaps[s]) <= T_TOL, (name, s, max_rel(Tw[s], snaps[s]))
+        assert abs(sw[s]["n_iter"] - so[s]["n_iter"]) <= 1, (name, s)
+        assert sw[s]["converged"] == 1
+        assert max_rel(Tw[s], Tp[s]) <= T_TOL, (name, s)
+        assert abs(sw[s]["n_iter"] - sp[s]["n_iter"]) <= 1, (name, s)
