@@ -601,21 +601,44 @@ inline bool rb2_form(const RBForm &f) { return f.h % 2 == 0 && f.nr % 2 == 0; }
 
 inline int32_t rb2_blocks(int32_t nr) { return static_cast<int32_t>((nr / 2 + kCellBlock - 1) / kCellBlock); }
 
+// a lane's pairs u, u + 1 and where their neighbours are: tv (the lane has
+// pairs), the adjacent lanes holding pairs u - 2 and u + 2 (below_ok,
+// above_ok), the line's parity and u's position in it, and which of the y and
+// z neighbours exist (they are the same for both pairs, h and H being even)
+struct Rb2Lane {
+    int64_t u, pos;
+    int32_t par;
+    bool tv, below_ok, above_ok, zlo, zhi, ylo, yhi;
+};
+
+__device__ __forceinline__ Rb2Lane rb2_lane(const RBForm &f) {
+    Rb2Lane l;
+    const int64_t nr = f.nr, h = f.h, H = f.H;
+    l.u = 2 * (static_cast<int64_t>(blockIdx.x) * kCellBlock + threadIdx.x);
+    l.tv = l.u < nr;
+    const int key = l.tv ? static_cast<int>(l.u) : -8;
+    l.below_ok = lane_from_below(key, -1000) == key - 2;
+    l.above_ok = lane_from_above(key, -1000) == key + 2;
+    l.par = l.tv ? rb_par(f, static_cast<int32_t>(l.u)) : 0;
+    l.pos = l.tv ? l.u % h : 0;
+    l.zlo = H > 0 && l.u >= H;
+    l.zhi = H > 0 && l.u + H < nr;
+    l.ylo = l.u >= h;
+    l.yhi = l.u + h < nr;
+    return l;
+}
+
 template <class Fn>
 __device__ __forceinline__ void rb2_product(const RBForm &f, const double *__restrict__ diagB,
                                             const double *__restrict__ coef, const double *__restrict__ p,
                                             Fn &&fn) {
     typedef Lanes<double, 2> R;
     const int64_t nr = f.nr, h = f.h, H = f.H;
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * kCellBlock + threadIdx.x;
-    const int64_t u = 2 * t;
-    const bool tv = u < nr;
-    const int key = tv ? static_cast<int>(u) : -8;
-    const bool below_ok = lane_from_below(key, -1000) == key - 2;
-    const bool above_ok = lane_from_above(key, -1000) == key + 2;
+    const Rb2Lane l = rb2_lane(f);
+    const int64_t u = l.u, pos = l.pos;
+    const bool tv = l.tv, below_ok = l.below_ok, above_ok = l.above_ok;
+    const int32_t par = l.par;
     const R z = lanes_zero<double, 2>();
-    const int32_t par = tv ? rb_par(f, static_cast<int32_t>(u)) : 0;
-    const int64_t pos = tv ? u % h : 0;
     // own values: red slots 0..5, p of both colours, diagonals
     R sl[6], pr = z, pb = z, dr = z, db = z;
 #pragma unroll
@@ -645,8 +668,7 @@ __device__ __forceinline__ void rb2_product(const RBForm &f, const double *__res
     }
     // y and z entries: black p and the mirrored red slots (black rows) one
     // line or plane down and up, and the red p there
-    const bool zlo = H > 0 && u >= H, zhi = H > 0 && u + H < nr;
-    const bool ylo = u >= h, yhi = u + h < nr;
+    const bool zlo = l.zlo, zhi = l.zhi, ylo = l.ylo, yhi = l.yhi;
     R pbz0 = z, pbz1 = z, pby0 = z, pby1 = z, prz0 = z, prz1 = z, pry0 = z, pry1 = z;
     R bz0 = z, bz1 = z, by0 = z, by1 = z;
     if (zlo) {

@@ -755,6 +755,166 @@ k_amul_rb2(RBLayout L, const double *__restrict__ diagB, const double *__restric
     });
 }
 
+// k_dic_update_forward_rb with two red-black pairs per lane (the lanes and
+// partial sums of k_amul_dot_rb2): the black rows u, u + 1 take their red
+// neighbours' rD, updated r and mirrored slots as 16-byte loads one line or
+// plane away, and their x-neighbours from the lane's red pair (slots -x and
+// +x, which it loads) or the adjacent lane's; each row's recurrence is the pair
+// kernel's term for term
+__global__ void __launch_bounds__(kCellBlock)
+k_dic_update_forward_rb2(SolverParams sp, RBLayout L, const double *__restrict__ coef,
+                         const double *__restrict__ rD, const double *__restrict__ q, double *__restrict__ r,
+                         double *__restrict__ w, double *__restrict__ part, const PcgState *__restrict__ st) {
+    if (st->done) return;
+    typedef Lanes<double, 2> R;
+    const RBForm &f = L.f;
+    const int64_t nr = f.nr, h = f.h, H = f.H;
+    const double alpha = st->alpha;
+    const Rb2Lane l = rb2_lane(f);
+    const int64_t u = l.u, pos = l.pos;
+    const int32_t par = l.par;
+    const R z = lanes_zero<double, 2>();
+    // the lane's red pair: rD, updated r, slots -x and +x
+    R rdr = z, rrr = z, s2 = z, s3 = z;
+    if (l.tv) {
+        rdr = lanes_load<double, 2>(rD, u);
+        const R r0 = lanes_load<double, 2>(r, u), q0 = lanes_load<double, 2>(q, u);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) rrr.v[k] = r0.v[k] - alpha * q0.v[k];
+        s2 = lanes_load<double, 2>(coef, 2 * nr + u);
+        s3 = lanes_load<double, 2>(coef, 3 * nr + u);
+    }
+    double rd_m1 = lane_from_below(rdr.v[1]), rr_m1 = lane_from_below(rrr.v[1]), s3_m1 = lane_from_below(s3.v[1]);
+    double rd_p2 = lane_from_above(rdr.v[0]), rr_p2 = lane_from_above(rrr.v[0]), s2_p2 = lane_from_above(s2.v[0]);
+    double acc[1] = {0.0};
+    if (l.tv) {
+        if (!l.below_ok && pos >= 2) {
+            rd_m1 = rD[u - 1];
+            rr_m1 = r[u - 1] - alpha * q[u - 1];
+            s3_m1 = coef[3 * nr + u - 1];
+        }
+        if (!l.above_ok && pos + 2 <= h - 1) {
+            rd_p2 = rD[u + 2];
+            rr_p2 = r[u + 2] - alpha * q[u + 2];
+            s2_p2 = coef[2 * nr + u + 2];
+        }
+        // red neighbours one plane down (slot +z), one line down (+y), one line
+        // up (-y), one plane up (-z): rD, updated r, the mirrored slot
+        const int64_t off[4] = {-H, -h, h, H};
+        const int slot[4] = {5, 4, 1, 0};
+        const bool has[4] = {l.zlo, l.ylo, l.yhi, l.zhi};
+        R nrd[4], nrr[4], nsl[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            nrd[i] = nrr[i] = nsl[i] = z;
+            if (has[i]) {
+                const int64_t v = u + off[i];
+                nrd[i] = lanes_load<double, 2>(rD, v);
+                const R r0 = lanes_load<double, 2>(r, v), q0 = lanes_load<double, 2>(q, v);
+#pragma unroll
+                for (int k = 0; k < 2; ++k) nrr[i].v[k] = r0.v[k] - alpha * q0.v[k];
+                nsl[i] = lanes_load<double, 2>(coef, slot[i] * nr + v);
+            }
+        }
+        const R rb = lanes_load<double, 2>(r, nr + u), qb = lanes_load<double, 2, true>(q, nr + u);
+        const R rdb = lanes_load<double, 2>(rD, nr + u);
+        R rc, wv;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int64_t pk = pos + k;
+            const double c = rb.v[k] - alpha * qb.v[k];
+            rc.v[k] = c;
+            acc[0] += fabs(c);
+            const double rd = rdb.v[k];
+            double wc = rd * c;
+            // x entries: the red cells at u + k - par (slot +x) and u + k + 1 - par (slot -x)
+            const double a2 = par ? (k == 0 ? s3_m1 : s3.v[0]) : s3.v[k];
+            const double d2 = par ? (k == 0 ? rd_m1 : rdr.v[0]) : rdr.v[k];
+            const double o2 = par ? (k == 0 ? rr_m1 : rrr.v[0]) : rrr.v[k];
+            const double a3 = par ? s2.v[k] : (k == 0 ? s2.v[1] : s2_p2);
+            const double d3 = par ? rdr.v[k] : (k == 0 ? rdr.v[1] : rd_p2);
+            const double o3 = par ? rrr.v[k] : (k == 0 ? rrr.v[1] : rr_p2);
+            const bool ok[6] = {l.zlo, l.ylo, pk >= par, pk + 1 - par <= h - 1, l.yhi, l.zhi};
+            const double a[6] = {nsl[0].v[k], nsl[1].v[k], a2, a3, nsl[2].v[k], nsl[3].v[k]};
+            const double rdo[6] = {nrd[0].v[k], nrd[1].v[k], d2, d3, nrd[2].v[k], nrd[3].v[k]};
+            const double ro[6] = {nrr[0].v[k], nrr[1].v[k], o2, o3, nrr[2].v[k], nrr[3].v[k]};
+#pragma unroll
+            for (int j = 0; j < 6; ++j)
+                if (ok[j]) wc -= rd * a[j] * (rdo[j] * ro[j]);
+            wv.v[k] = wc;
+        }
+        *reinterpret_cast<typename R::vec *>(r + nr + u) = typename R::vec{rc.v[0], rc.v[1]};
+        *reinterpret_cast<typename R::vec *>(w + nr + u) = typename R::vec{wv.v[0], wv.v[1]};
+    }
+    const int slots[1] = {kPartSumR};
+    write_partials<1>(part, sp.grid, slots, acc);
+}
+
+// k_dic_backward_rb_pair<true> with two red-black pairs per lane: the red rows
+// u, u + 1 (their update of r, then the backward sweep from their black
+// neighbours' w), with the w.r partials of the lane's red and black rows and
+// the red rows' |r| added to the forward kernel's partial of the same workgroup
+__global__ void __launch_bounds__(kCellBlock)
+k_dic_backward_rb2(SolverParams sp, RBLayout L, const double *__restrict__ coef, const double *__restrict__ rD,
+                   const double *__restrict__ q, double *__restrict__ r, double *__restrict__ w,
+                   double *__restrict__ part, const PcgState *__restrict__ st) {
+    if (st->done) return;
+    typedef Lanes<double, 2> R;
+    const RBForm &f = L.f;
+    const int64_t nr = f.nr, h = f.h, H = f.H;
+    const double alpha = st->alpha;
+    const Rb2Lane l = rb2_lane(f);
+    const int64_t u = l.u, pos = l.pos;
+    const int32_t par = l.par;
+    const R z = lanes_zero<double, 2>();
+    const R wb = l.tv ? lanes_load<double, 2>(w, nr + u) : z;
+    double wb_m1 = lane_from_below(wb.v[1]), wb_p2 = lane_from_above(wb.v[0]);
+    double acc[2] = {0.0, 0.0};
+    if (l.tv) {
+        if (!l.below_ok && pos >= 2) wb_m1 = w[nr + u - 1];
+        if (!l.above_ok && pos + 2 <= h - 1) wb_p2 = w[nr + u + 2];
+        R sl[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) sl[j] = lanes_load<double, 2>(coef, j * nr + u);
+        const int64_t off[4] = {-H, -h, h, H};
+        const bool has[4] = {l.zlo, l.ylo, l.yhi, l.zhi};
+        R nw[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) nw[i] = has[i] ? lanes_load<double, 2>(w, nr + u + off[i]) : z;
+        const R rdr = lanes_load<double, 2>(rD, u), rr = lanes_load<double, 2>(r, u);
+        const R qr = lanes_load<double, 2, true>(q, u);
+        const R rbk = lanes_load<double, 2>(r, nr + u);
+        R rcv, wv;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int64_t pk = pos + k;
+            const double c = rr.v[k] - alpha * qr.v[k];
+            rcv.v[k] = c;
+            acc[1] += fabs(c);
+            const double rd = rdr.v[k];
+            double wc = rd * c;
+            // x entries: the black cells at u + k + par - 1 and u + k + par
+            const double w2 = par ? wb.v[k] : (k == 0 ? wb_m1 : wb.v[0]);
+            const double w3 = par ? (k == 0 ? wb.v[1] : wb_p2) : wb.v[k];
+            const bool ok[6] = {l.zlo, l.ylo, pk + par - 1 >= 0, pk + par <= h - 1, l.yhi, l.zhi};
+            const double wo[6] = {nw[0].v[k], nw[1].v[k], w2, w3, nw[2].v[k], nw[3].v[k]};
+#pragma unroll
+            for (int j = 5; j >= 0; --j)
+                if (ok[j]) wc -= rd * sl[j].v[k] * wo[j];
+            wv.v[k] = wc;
+            acc[0] += wc * c + wb.v[k] * rbk.v[k];
+        }
+        *reinterpret_cast<typename R::vec *>(r + u) = typename R::vec{rcv.v[0], rcv.v[1]};
+        *reinterpret_cast<typename R::vec *>(w + u) = typename R::vec{wv.v[0], wv.v[1]};
+    }
+    const double black = part[kPartSumR * sp.grid + blockIdx.x];
+    block_sum<kCellBlock, 2>(acc);
+    if (threadIdx.x == 0) {
+        part[kPartWr * sp.grid + blockIdx.x] = acc[0];
+        part[kPartSumR * sp.grid + blockIdx.x] = black + acc[1];
+    }
+}
+
 // backward sweep on the red rows, one thread per half-index u (red row u),
 // with the w.r partial sums of the red row and of the black row nr + u (its
 // w from the forward sweep); sp.grid_amul workgroups (the slot's further
@@ -1247,10 +1407,17 @@ static lf_status launch_iteration(lf_problem *P, hipStream_t s) {
         // into the two sweeps
         const lf_mesh *m = P->mesh;
         const dim3 gb(static_cast<unsigned>(P->sp.grid_upd));
-        LF_LAUNCH(P, LF_K_DIC_FORWARD, s, k_dic_update_forward_rb, gb, dim3(kCellBlock), 0, s, P->sp, rb_layout(m),
-                  P->coef, P->rD, P->q, P->r, P->w, P->part, P->state);
-        LF_LAUNCH(P, LF_K_DIC_BACKWARD, s, k_dic_backward_rb_pair<true>, gb, dim3(kCellBlock), 0, s, P->sp,
-                  rb_layout(m), P->coef, P->rD, P->q, P->r, P->w, P->part, P->state);
+        if (P->rb2) {
+            LF_LAUNCH(P, LF_K_DIC_FORWARD, s, k_dic_update_forward_rb2, gb, dim3(kCellBlock), 0, s, P->sp,
+                      rb_layout(m), P->coef, P->rD, P->q, P->r, P->w, P->part, P->state);
+            LF_LAUNCH(P, LF_K_DIC_BACKWARD, s, k_dic_backward_rb2, gb, dim3(kCellBlock), 0, s, P->sp, rb_layout(m),
+                      P->coef, P->rD, P->q, P->r, P->w, P->part, P->state);
+        } else {
+            LF_LAUNCH(P, LF_K_DIC_FORWARD, s, k_dic_update_forward_rb, gb, dim3(kCellBlock), 0, s, P->sp,
+                      rb_layout(m), P->coef, P->rD, P->q, P->r, P->w, P->part, P->state);
+            LF_LAUNCH(P, LF_K_DIC_BACKWARD, s, k_dic_backward_rb_pair<true>, gb, dim3(kCellBlock), 0, s, P->sp,
+                      rb_layout(m), P->coef, P->rD, P->q, P->r, P->w, P->part, P->state);
+        }
         launch_fin<kFinBeta>(P, s);
         launch_direction(P, s);
         LF_HIP(hipGetLastError());
