@@ -569,6 +569,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="graded_256")
     ap.add_argument("--n", type=int, default=None, help="override the cube side (testing only)")
+    ap.add_argument("--precond", choices=["config", "diagonal", "dic", "amg"], default="config",
+                    help="the main leg's preconditioner (default: the config's; for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-roofline-pass", action="store_true")
@@ -652,7 +654,8 @@ def main():
     if args.skewed_only:
         print(json.dumps({"skewed": run_config_leg(L, torch, args.config, args.steps, skew=True)}), flush=True)
         return
-    precond = L.LF_PC_DIC if p.precond == "dic" else L.LF_PC_DIAGONAL
+    pc_name = p.precond if args.precond == "config" else args.precond
+    precond = {"dic": L.LF_PC_DIC, "amg": L.LF_PC_AMG}.get(pc_name, L.LF_PC_DIAGONAL)
     precision = L.LF_PREC_MIXED if p.precision == "mixed" else L.LF_PREC_FP64
     opts = L.make_opts(tol=synth.TOL, rel_tol=synth.REL_TOL, max_iter=synth.MAX_ITER,
                        precond=precond, precision=precision)
@@ -694,7 +697,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {round(N ** (1 / 3))}^3 box, z expansion ratio "
                                f"{synth.CONFIGS[args.config]['z_ratio']}, DT={p.DT}, dt={p.dt}, "
-                               f"implicit Euler, PCG {p.precond}, tol {synth.TOL}",
+                               f"implicit Euler, PCG {pc_name}, tol {synth.TOL}",
                    "n_cells": N, "n_faces": F, "precision": p.precision, "layout": layout_name,
                    "amul": amul_form},
         "iters_per_step_mean": total_iters / len(stats),

@@ -728,15 +728,26 @@ __device__ __forceinline__ void rb2_product(const RBForm &f, const double *__res
     fn(u, qr, qb, pr, pb);
 }
 
+// The vector the walk multiplies: by default read from memory; a source may
+// instead form each value from other arrays (vec(i): the W values at i, i a
+// multiple of W; one(i): the value at i), as long as it gives the value the
+// vector would hold.
+template <class T, int W>
+struct MemX {
+    const T *__restrict__ x;
+    __device__ __forceinline__ Lanes<T, W> vec(int64_t i) const { return lanes_load<T, W>(x, i); }
+    __device__ __forceinline__ T one(int64_t i) const { return x[i]; }
+};
+
 // The walk: calls fn(c, y, x, diag) for the thread's groups of W rows
 // (c .. c + W - 1; lines in order, within a line the planes in order), y = A x
 // with the diagonal term first (kUnitDiag: a matrix with unit diagonal, x
 // first, diag = 1, `diag` not read).  kStream streams diag past the caches.
 // All lanes of a wave run the lane exchanges, so the caller must not branch
 // around the call.
-template <class T, int W, bool kStream, bool kUnitDiag, class Fn>
-__device__ __forceinline__ void box_walk(const BandLayout<3> &L, const BoxWalk &bw, const T *__restrict__ diag,
-                                         const T *__restrict__ coef, const T *__restrict__ x, Fn &&fn) {
+template <class T, int W, bool kStream, bool kUnitDiag, class XS, class Fn>
+__device__ __forceinline__ void box_walk_xs(const BandLayout<3> &L, const BoxWalk &bw, const T *__restrict__ diag,
+                                            const T *__restrict__ coef, const XS &x, Fn &&fn) {
     typedef Lanes<T, W> R;
     constexpr int kBwY = bw_lines(W), kBwZ = bw_planes(W);
     const int64_t n = L.n, d1 = L.d[1], d2 = L.d[2];
@@ -758,10 +769,10 @@ __device__ __forceinline__ void box_walk(const BandLayout<3> &L, const BoxWalk &
         const int64_t c = base + k * d2;
         xc[k] = alo[k] = xlo[k] = z;
         if (tv && c < n) {
-            xc[k] = lanes_load<T, W>(x, c);
+            xc[k] = x.vec(c);
             if (c >= d1) {
                 alo[k] = lanes_load<T, W>(coef, n + c - d1);
-                xlo[k] = lanes_load<T, W>(x, c - d1);
+                xlo[k] = x.vec(c - d1);
             } else {
                 xlo[k] = xc[k];
             }
@@ -779,7 +790,7 @@ __device__ __forceinline__ void box_walk(const BandLayout<3> &L, const BoxWalk &
             ok[k] = line && c < n;
             xup[k] = dg[k] = a0[k] = a1[k] = a2[k] = z;
             if (ok[k]) {
-                xup[k] = lanes_load<T, W>(x, c < n - d1 ? c + d1 : c);
+                xup[k] = x.vec(c < n - d1 ? c + d1 : c);
                 if (!kUnitDiag) dg[k] = lanes_load<T, W, kStream>(diag, c);
                 a0[k] = lanes_load<T, W>(coef, c);
                 // the band-1 coefficient is read by this thread only (the next
@@ -792,11 +803,11 @@ __device__ __forceinline__ void box_walk(const BandLayout<3> &L, const BoxWalk &
         R a2lo0 = z, xzlo0 = xc[0], xzhi_top = xc[kBwZ - 1];
         if (ok[0] && c0 >= d2) {
             a2lo0 = lanes_load<T, W>(coef, 2 * n + c0 - d2);
-            xzlo0 = lanes_load<T, W>(x, c0 - d2);
+            xzlo0 = x.vec(c0 - d2);
         }
         {
             const int64_t ct = c0 + (kBwZ - 1) * d2;
-            if (ok[kBwZ - 1] && ct < n - d2) xzhi_top = lanes_load<T, W>(x, ct + d2);
+            if (ok[kBwZ - 1] && ct < n - d2) xzhi_top = x.vec(ct + d2);
         }
 #pragma unroll
         for (int k = 0; k < kBwZ; ++k) {
@@ -809,13 +820,13 @@ __device__ __forceinline__ void box_walk(const BandLayout<3> &L, const BoxWalk &
             if (ok[k] && !below_ok) {
                 if (c >= 1) {
                     a0lo = coef[c - 1];
-                    xm1 = x[c - 1];
+                    xm1 = x.one(c - 1);
                 } else {
                     a0lo = T(0);
                     xm1 = xc[k].v[0];
                 }
             }
-            if (ok[k] && !above_ok) xpw = c < n - W ? x[c + W] : xc[k].v[W - 1];
+            if (ok[k] && !above_ok) xpw = c < n - W ? x.one(c + W) : xc[k].v[W - 1];
             const R &a2lo = k == 0 ? a2lo0 : a2[k - 1];
             const R &xzlo = k == 0 ? xzlo0 : xc[k - 1];
             const R &xzhi = c < n - d2 ? (k + 1 < kBwZ ? xc[k + 1] : xzhi_top) : xc[k];
@@ -840,6 +851,12 @@ __device__ __forceinline__ void box_walk(const BandLayout<3> &L, const BoxWalk &
             xc[k] = xup[k];
         }
     }
+}
+
+template <class T, int W, bool kStream, bool kUnitDiag, class Fn>
+__device__ __forceinline__ void box_walk(const BandLayout<3> &L, const BoxWalk &bw, const T *__restrict__ diag,
+                                         const T *__restrict__ coef, const T *__restrict__ x, Fn &&fn) {
+    box_walk_xs<T, W, kStream, kUnitDiag>(L, bw, diag, coef, MemX<T, W>{x}, fn);
 }
 
 // ---------------------------------------------------------------------------

@@ -139,6 +139,10 @@ struct lf_problem {
     // band matrix) and two work vectors of level 0
     std::vector<lf::AmgLevel> amg;
     double *amg_t1 = nullptr, *amg_t2 = nullptr;   // [N]
+    // per level (0: the problem's box): its block walk, and 0 none, 1 the
+    // sweeps walk, 2 the restriction too (all sides even)
+    std::vector<lf::BoxWalk> amg_bw;
+    std::vector<int8_t> amg_walk;
     double *upper = nullptr;                   // [F] face order (test hook copy)
     double *coef = nullptr;                    // [n_entries] row layout or [n_bands N] bands
     double *int_coeff = nullptr, *bou_coeff = nullptr;

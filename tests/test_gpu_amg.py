@@ -25,14 +25,18 @@ def L():
     return lapfoam()
 
 
-BOXES = [(12, 10, 8, 4.0), (24, 20, 18, 10.0), (40, 33, 17, 3.0), (2, 2, 2, 1.0), (64, 64, 64, 10.0)]
+# sides even and odd; the levels of a box with even x-lines take the block
+# walk (and the restriction too when all its sides are even): 64^3 on every
+# level, 130x4x4 with x-lines wider than a wavefront's rows
+BOXES = [(12, 10, 8, 4.0), (24, 20, 18, 10.0), (40, 33, 17, 3.0), (2, 2, 2, 1.0), (64, 64, 64, 10.0),
+         (130, 4, 4, 2.0)]
 IDS = ["x".join(str(v) for v in b[:3]) for b in BOXES]
 
 
-def _run_hook(L, mesh, T0, pc, layout=None):
+def _run_hook(L, mesh, T0, pc, layout=None, **kw):
     import torch
     m = L.Mesh(mesh)
-    opts = L.make_opts(precond=pc) if layout is None else L.make_opts(precond=pc, layout=layout)
+    opts = L.make_opts(precond=pc, **kw) if layout is None else L.make_opts(precond=pc, layout=layout, **kw)
     P = L.Problem(m, synth.fixed_x_bcs(), DT, dt, opts)
     P.set_T(T0)
     P.assemble()
@@ -47,12 +51,16 @@ def _run_hook(L, mesh, T0, pc, layout=None):
     return r, out
 
 
+@pytest.mark.parametrize("walk", [0, 1, 2], ids=["auto", "walk", "nowalk"])
 @pytest.mark.parametrize("box", BOXES, ids=IDS)
-def test_amg_cycle_bitwise(L, oracle, box):
+def test_amg_cycle_bitwise(L, oracle, box, walk):
+    """One application bitwise the oracle's cycle with the sweeps, the
+    restriction and the prolongation by the block walk on every level with
+    even x-lines (LF_WALK_ON), on none (LF_WALK_OFF), and as chosen by size."""
     nx, ny, nz, ratio = box
     mesh = synth.box_mesh(nx, ny, nz, z_ratio=ratio)
     T0 = synth.initial_field(mesh.n_cells, 17)
-    r, w = _run_hook(L, mesh, T0, L.LF_PC_AMG)
+    r, w = _run_hook(L, mesh, T0, L.LF_PC_AMG, amul_walk=walk)
     A = oracle.assemble(mesh, synth.fixed_x_bcs(), DT, dt, T0)
     lc, ag = synth.box_aggregation((nx, ny, nz))
     want = oracle.amg_apply(mesh, A["diag_b"], A["upper"], r, lc, ag)
@@ -89,7 +97,8 @@ def test_diagonal_application_bitwise(L, oracle):
                                                ((33, 30, 28, 1.0), 3, 1e-2, 0.2),
                                                ((12, 10, 8, 4.0), 3, 5e-3, 2e-3)],
                          ids=["graded_24x20x18", "paper_dt_33x30x28", "two_levels_12x10x8"])
-def test_amg_steps_match_oracle(L, oracle, box, steps, DTs, dts):
+@pytest.mark.parametrize("walk", [0, 1], ids=["auto", "walk"])
+def test_amg_steps_match_oracle(L, oracle, box, steps, DTs, dts, walk):
     nx, ny, nz, ratio = box
     mesh = synth.box_mesh(nx, ny, nz, z_ratio=ratio)
     T0 = synth.initial_field(mesh.n_cells, 20)
@@ -97,7 +106,7 @@ def test_amg_steps_match_oracle(L, oracle, box, steps, DTs, dts):
     _, so, snaps = oracle.run_amg(mesh, synth.fixed_x_bcs(), DTs, dts, steps, T0, lc, ag, keep_all=True)
     _, sd, _ = oracle.run(mesh, synth.fixed_x_bcs(), DTs, dts, steps, T0)
     m = L.Mesh(mesh)
-    P = L.Problem(m, synth.fixed_x_bcs(), DTs, dts, L.make_opts(precond=L.LF_PC_AMG))
+    P = L.Problem(m, synth.fixed_x_bcs(), DTs, dts, L.make_opts(precond=L.LF_PC_AMG, amul_walk=walk))
     P.set_T(T0)
     for s in range(steps):
         st, _ = P.step(1)
