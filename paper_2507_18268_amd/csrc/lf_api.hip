@@ -217,6 +217,8 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
             }
         }
     }
+    P->fold = opts.precision == LF_PREC_FP64 && opts.precond == LF_PC_DIAGONAL && !P->rb &&
+              P->sp.grid_amul <= kFoldPartials && P->sp.grid_upd <= kFoldPartials;
     P->sp.max_outer = opts.max_outer > 0 ? opts.max_outer : 50;
     P->sp.inner_tol = opts.inner_tol > 0.0 ? opts.inner_tol : 1e-5;
     P->sp.inner_restart = opts.inner_restart ? 1 : 0;

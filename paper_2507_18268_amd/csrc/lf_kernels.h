@@ -77,21 +77,22 @@ __device__ __forceinline__ void write_partials(double *__restrict__ part, int32_
 // part[t], part[t + 1024], ... of each slot in that order; the loads of
 // a group (kU per slot, every slot) are issued together, so the serial chain
 // waits once per group: one or two groups at the sizes used here.
-template <int NQ>
+// (BS: the threads of the workgroup that sums; the result is in every thread)
+template <int NQ, int BS = kFinBlock>
 __device__ __forceinline__ void reduce_partials(const double *__restrict__ part, int32_t stride, int32_t G,
                                                 const int (&slot)[NQ], double (&out)[NQ]) {
     constexpr int kU = NQ == 1 ? 32 : (NQ == 2 ? 16 : 8);
     double s[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) s[q] = 0.0;
-    for (int32_t i0 = threadIdx.x; i0 < G; i0 += kU * kFinBlock) {
+    for (int32_t i0 = threadIdx.x; i0 < G; i0 += kU * BS) {
         double v[NQ][kU];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const double *__restrict__ src = part + static_cast<int64_t>(slot[q]) * stride;
 #pragma unroll
             for (int j = 0; j < kU; ++j) {
-                const int32_t i = i0 + j * kFinBlock;
+                const int32_t i = i0 + j * BS;
                 v[q][j] = i < G ? src[i] : 0.0;
             }
         }
@@ -103,7 +104,7 @@ __device__ __forceinline__ void reduce_partials(const double *__restrict__ part,
     }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) out[q] = s[q];
-    block_sum<kFinBlock, NQ>(out);
+    block_sum<BS, NQ>(out);
 }
 
 // the usual case: G partials per slot, slots G apart

@@ -353,6 +353,109 @@ k_update(SolverParams sp, const double *__restrict__ q, double *__restrict__ r, 
     write_partials<2>(part, sp.grid, slots, acc);
 }
 
+// ---------------------------------------------------------------------------
+// Small solves with the diagonal preconditioner (at most kFoldPartials
+// partials per slot): the decisions of k_finalize<kFinAlpha> and <kFinBeta>
+// are taken inside the update and direction kernels, by every workgroup from
+// the same partials in the same order, so all take the same one, and
+// workgroup 0 records them in the state.  A state value that workgroup 0
+// overwrites during a launch is read by the others from the copy the update
+// made (wArA_prev, n_iter_prev, conv_prev); `done` is read once per workgroup,
+// and a workgroup that already sees workgroup 0's new value takes the decision
+// that value records.  Two dependent launches fewer per iteration, which is
+// what an iteration costs on a small mesh.
+// ---------------------------------------------------------------------------
+// the state's done flag as one value for the whole workgroup
+__device__ __forceinline__ bool group_done(const PcgState *__restrict__ st) {
+    __shared__ int32_t s_done;
+    if (threadIdx.x == 0) s_done = st->done;
+    __syncthreads();
+    return s_done != 0;
+}
+
+// k_finalize<kFinAlpha> then k_update<true>
+__global__ void __launch_bounds__(kCellBlock)
+k_update_fold(SolverParams sp, const double *__restrict__ q, double *__restrict__ r, const double *__restrict__ rD,
+              double *__restrict__ part, PcgState *__restrict__ st) {
+    if (group_done(st)) return;
+    double v[1];
+    const int ps[1] = {kPartPq};
+    reduce_partials<1, kCellBlock>(part, sp.grid, sp.grid_amul, ps, v);
+    const double pq = v[0], wArA = st->wArA;
+    const bool bad = !isfinite(pq), sing = !bad && fabs(pq) / st->nf < 1e-300;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (bad || sing) {
+        if (lead) {
+            if (bad)
+                st->nonfinite = 1;
+            else
+                st->singular = 1;
+            st->done = 1;
+        }
+        return;
+    }
+    const double alpha = wArA / pq;
+    if (lead) {
+        st->alpha = alpha;
+        st->wArA_prev = wArA;
+        st->n_iter_prev = st->n_iter;
+        st->conv_prev = st->converged;
+    }
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < kUpdRows; ++j) {
+        const int32_t c = cell_row<kUpdRows>(j);
+        if (c >= sp.n) continue;
+        const double rc = r[c] - alpha * __builtin_nontemporal_load(&q[c]);
+        r[c] = rc;
+        acc[0] += fabs(rc);
+        const double wc = rD[c] * rc;
+        acc[1] += wc * rc;
+    }
+    const int slots[2] = {kPartSumR, kPartWr};
+    write_partials<2>(part, sp.grid, slots, acc);
+}
+
+// k_finalize<kFinBeta> then k_direction<true> (never the first direction)
+__global__ void __launch_bounds__(kCellBlock)
+k_direction_fold(SolverParams sp, const double *__restrict__ rD, const double *__restrict__ r,
+                 double *__restrict__ p, double *__restrict__ x, const double *__restrict__ part,
+                 PcgState *__restrict__ st) {
+    if (group_done(st)) return;
+    double v[2];
+    const int ps[2] = {kPartSumR, kPartWr};
+    reduce_partials<2, kCellBlock>(part, sp.grid, sp.grid_upd, ps, v);
+    const double res = v[0] / st->nf;
+    const int32_t k = st->n_iter_prev + 1;
+    const bool conv = (k < sp.max_iter) ? check_conv(res, st->res0, sp.tol, sp.rel_tol) : (st->conv_prev != 0);
+    const bool cont = (k < sp.max_iter && !conv) || k < sp.min_iter;
+    const bool bad = !isfinite(res) || !isfinite(v[1]);
+    const double beta = v[1] / st->wArA_prev;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->res = res;
+        st->n_iter = k;
+        st->converged = conv ? 1 : 0;
+        if (bad) {
+            st->nonfinite = 1;
+            st->done = 1;
+        } else if (!cont) {
+            st->done = 1;
+        } else {
+            st->beta = beta;
+            st->wArA = v[1];
+        }
+    }
+    if (bad || !cont) return;
+    const double alpha = st->alpha;
+    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+    if (c < sp.n) {
+        const double wc = __builtin_nontemporal_load(&rD[c]) * r[c];
+        const double pc = p[c];
+        __builtin_nontemporal_store(__builtin_nontemporal_load(&x[c]) + alpha * pc, &x[c]);
+        p[c] = wc + beta * pc;
+    }
+}
+
 // end of a solve: the update x += alpha p of the last counted iteration is
 // still pending unless the solve stopped at a singular or non-finite point
 // (then the pending update was applied by the last direction kernel)
@@ -1401,6 +1504,14 @@ static lf_status launch_iteration(lf_problem *P, hipStream_t s) {
         LF_LAUNCH(P, LF_K_AMUL_DOT, s, k_amul_dot<decltype(lay)>, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, lay,
                   P->diagB, P->coef, P->p, P->q, P->part, P->state);
     });
+    if (P->fold) {
+        LF_LAUNCH(P, LF_K_UPDATE, s, k_update_fold, dim3(static_cast<unsigned>(P->sp.grid_upd)), dim3(kCellBlock), 0,
+                  s, P->sp, P->q, P->r, P->rD, P->part, P->state);
+        LF_LAUNCH(P, LF_K_DIRECTION, s, k_direction_fold, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->rD, P->r,
+                  P->p, P->T, P->part, P->state);
+        LF_HIP(hipGetLastError());
+        return LF_OK;
+    }
     launch_fin<kFinAlpha>(P, s);
     if (P->rb && !diag_pc) {
         // red-black DIC on the two-colour band layout: the update of r fused

@@ -45,6 +45,11 @@ struct PcgState {
     int32_t inner_pend;   // y += alpha p of the last inner update not applied yet
     int32_t inner_cont;   // this pass continues the previous one's CG (keeps its direction)
     int32_t pad3;
+    // small solves (decisions taken inside the update and direction kernels):
+    // wArA, n_iter and converged as the iteration's update found them
+    double wArA_prev;
+    int32_t n_iter_prev;
+    int32_t conv_prev;
 };
 
 // Block walk of a box's band layout (the tiles, lanes and rows are described
@@ -79,6 +84,10 @@ inline bool box_walk_plan(int32_t n, int32_t K, const int32_t *d, int32_t W, Box
 }
 
 constexpr int kMaxGraphLog = 6;   // largest captured block: 64 iterations
+// FP64 solves with the diagonal preconditioner whose product and update write
+// at most this many partials per slot take the iteration's decisions inside
+// the update and direction kernels (every workgroup sums the partials)
+constexpr int32_t kFoldPartials = 512;
 
 struct SolverParams {
     double tol, rel_tol;
@@ -135,6 +144,8 @@ struct lf_problem {
     bool box32 = false;                        // the FP32 inner product too (mixed; 4 rows per lane)
     lf::BoxWalk bw32{};
     bool rb2 = false;                          // DIC's product on the two-colour layout: two pairs per lane
+    bool fold = false;                         // small diagonal FP64 solves: the iteration's reductions folded
+                                               // into the update and direction kernels
     // multigrid preconditioner: coarse levels 1.. (level 0 is the problem's own
     // band matrix) and two work vectors of level 0
     std::vector<lf::AmgLevel> amg;
