@@ -338,9 +338,25 @@ k_mx_residual_box(SolverParams sp, BandLayout<3> L, BoxWalk bw, const double *__
     const bool keep = st->inner_iter > 0;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     typedef Lanes<double, 2> R;
+    typedef float F2 __attribute__((ext_vector_type(2)));
     box_walk<double, 2, true, false>(L, bw, diagB, coef, T, [&](int64_t c, const R &ax, const R &, const R &db) {
-        pass_end_row(c, ax.v[0], db.v[0], keep, srcB, p32, r32, d32, acc);
-        pass_end_row(c + 1, ax.v[1], db.v[1], keep, srcB, p32, r32, d32, acc);
+        // the two rows as pass_end_row takes them, with 16- and 8-byte accesses
+        const R b = lanes_load<double, 2>(srcB, c);
+        const F2 pp = keep ? *reinterpret_cast<const F2 *>(p32 + c) : F2{0.0f, 0.0f};
+        F2 rs2;
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            const double rc = b.v[w] - ax.v[w];
+            acc[0] += fabs(rc);
+            const double sg = static_cast<float>(sqrt(db.v[w]));
+            const float rs = static_cast<float>(rc / sg);
+            rs2[w] = rs;
+            acc[1] += fabs(sg * static_cast<double>(rs));
+            acc[2] += static_cast<double>(rs) * static_cast<double>(rs);
+            if (keep) acc[3] += static_cast<double>(rs) * static_cast<double>(pp[w]);
+        }
+        *reinterpret_cast<F2 *>(r32 + c) = rs2;
+        *reinterpret_cast<F2 *>(d32 + c) = F2{0.0f, 0.0f};
     });
     const int slots[4] = {kPartSumR, kPartSumR32, kPartWr32, kPartRp32};
     write_partials<4, kBwBlock>(part, sp.grid, slots, acc);
@@ -693,10 +709,61 @@ lf_status launch_amul_inner_hook(lf_problem *P, const float *x, float *y) {
     return LF_OK;
 }
 
+// k_mx_scale on a band layout whose first offset is 1 and whose other offsets
+// and row count are even, two rows (c, c + 1, c even) per thread: 16-byte
+// loads of the coefficients, 8-byte accesses of s and of the FP32 result;
+// each value by scale_row's expression
+template <int K>
+__global__ void __launch_bounds__(kCellBlock)
+k_mx_scale2(BandLayout<K> L, const float *__restrict__ sig32, const double *__restrict__ coef,
+            float *__restrict__ coef32) {
+    typedef float F2 __attribute__((ext_vector_type(2)));
+    typedef double D2 __attribute__((ext_vector_type(2)));
+    const int64_t n = L.n;
+    const int64_t c = 2 * (static_cast<int64_t>(blockIdx.x) * kCellBlock + threadIdx.x);
+    if (c >= n) return;
+    const F2 sv = *reinterpret_cast<const F2 *>(sig32 + c);
+    const double sc[2] = {static_cast<double>(sv.x), static_cast<double>(sv.y)};
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t d = L.d[k], slot = static_cast<int64_t>(k) * n + c;
+        const D2 a = *reinterpret_cast<const D2 *>(coef + slot);
+        double sn[2];
+        if (k == 0) {
+            // neighbours c + 1 (the pair's own) and c + 2
+            sn[0] = static_cast<double>(sv.y);
+            sn[1] = c + 1 < n - 1 ? static_cast<double>(sig32[c + 2]) : 1.0;
+        } else if (c + 1 < n - d) {
+            const F2 nv = *reinterpret_cast<const F2 *>(sig32 + c + d);
+            sn[0] = static_cast<double>(nv.x);
+            sn[1] = static_cast<double>(nv.y);
+        } else {
+            sn[0] = c < n - d ? static_cast<double>(sig32[c + d]) : 1.0;
+            sn[1] = 1.0;
+        }
+        F2 o;
+        o.x = static_cast<float>(a.x / (sc[0] * sn[0]));
+        o.y = static_cast<float>(a.y / (sc[1] * sn[1]));
+        *reinterpret_cast<F2 *>(coef32 + slot) = o;
+    }
+}
+
 void launch_mx_scale(lf_problem *P, hipStream_t s) {
     with_layout(P, [&](auto lay) {
-        LF_LAUNCH(P, LF_K_MIXED_PREP, s, k_mx_scale<decltype(lay)>, cell_grid(P), dim3(kCellBlock), 0, s, P->sp,
-                  lay, P->sig32, P->coef, P->coef32);
+        using Lay = decltype(lay);
+        constexpr int K = WalkBands<Lay>::value;
+        if constexpr (K > 0) {
+            bool pairs = lay.n % 2 == 0 && lay.d[0] == 1;
+            for (int k = 1; k < K; ++k) pairs = pairs && lay.d[k] % 2 == 0;
+            if (pairs) {
+                const dim3 g(static_cast<unsigned>((lay.n / 2 + kCellBlock - 1) / kCellBlock));
+                LF_LAUNCH(P, LF_K_MIXED_PREP, s, k_mx_scale2<K>, g, dim3(kCellBlock), 0, s, lay, P->sig32, P->coef,
+                          P->coef32);
+                return;
+            }
+        }
+        LF_LAUNCH(P, LF_K_MIXED_PREP, s, k_mx_scale<Lay>, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, lay,
+                  P->sig32, P->coef, P->coef32);
     });
 }
 
