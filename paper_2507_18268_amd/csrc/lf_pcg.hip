@@ -858,32 +858,102 @@ k_amul_rb2(RBLayout L, const double *__restrict__ diagB, const double *__restric
     });
 }
 
-// k_dic_update_forward_rb with two red-black pairs per lane (the lanes and
-// partial sums of k_amul_dot_rb2): the black rows u, u + 1 take their red
-// neighbours' rD, updated r and mirrored slots as 16-byte loads one line or
-// plane away, and their x-neighbours from the lane's red pair (slots -x and
-// +x, which it loads) or the adjacent lane's; each row's recurrence is the pair
-// kernel's term for term
+// k_dic_rd_rb with two red-black pairs per lane: red rows 1/diag, black rows
+// 1/(diag - sum over their red neighbours, in the row's order, of a^2 / the
+// neighbour's diag), neighbours as in k_dic_forward_rb2
 __global__ void __launch_bounds__(kCellBlock)
-k_dic_update_forward_rb2(SolverParams sp, RBLayout L, const double *__restrict__ coef,
-                         const double *__restrict__ rD, const double *__restrict__ q, double *__restrict__ r,
-                         double *__restrict__ w, double *__restrict__ part, const PcgState *__restrict__ st) {
-    if (st->done) return;
+k_dic_rd_rb2(RBLayout L, const double *__restrict__ diagB, const double *__restrict__ coef,
+             double *__restrict__ rD) {
     typedef Lanes<double, 2> R;
     const RBForm &f = L.f;
     const int64_t nr = f.nr, h = f.h, H = f.H;
-    const double alpha = st->alpha;
     const Rb2Lane l = rb2_lane(f);
     const int64_t u = l.u, pos = l.pos;
     const int32_t par = l.par;
     const R z = lanes_zero<double, 2>();
-    // the lane's red pair: rD, updated r, slots -x and +x
+    R dr = z, s2 = z, s3 = z;
+    if (l.tv) {
+        dr = lanes_load<double, 2>(diagB, u);
+        s2 = lanes_load<double, 2>(coef, 2 * nr + u);
+        s3 = lanes_load<double, 2>(coef, 3 * nr + u);
+    }
+    double d_m1 = lane_from_below(dr.v[1]), s3_m1 = lane_from_below(s3.v[1]);
+    double d_p2 = lane_from_above(dr.v[0]), s2_p2 = lane_from_above(s2.v[0]);
+    if (!l.tv) return;
+    if (!l.below_ok && pos >= 2) {
+        d_m1 = diagB[u - 1];
+        s3_m1 = coef[3 * nr + u - 1];
+    }
+    if (!l.above_ok && pos + 2 <= h - 1) {
+        d_p2 = diagB[u + 2];
+        s2_p2 = coef[2 * nr + u + 2];
+    }
+    const int64_t off[4] = {-H, -h, h, H};
+    const int slot[4] = {5, 4, 1, 0};
+    const bool has[4] = {l.zlo, l.ylo, l.yhi, l.zhi};
+    R nd[4], nsl[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        nd[i] = nsl[i] = z;
+        if (has[i]) {
+            nd[i] = lanes_load<double, 2>(diagB, u + off[i]);
+            nsl[i] = lanes_load<double, 2>(coef, slot[i] * nr + u + off[i]);
+        }
+    }
+    const R db = lanes_load<double, 2>(diagB, nr + u);
+    R rr, rb;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int64_t pk = pos + k;
+        rr.v[k] = 1.0 / dr.v[k];
+        const double a2 = par ? (k == 0 ? s3_m1 : s3.v[0]) : s3.v[k];
+        const double g2 = par ? (k == 0 ? d_m1 : dr.v[0]) : dr.v[k];
+        const double a3 = par ? s2.v[k] : (k == 0 ? s2.v[1] : s2_p2);
+        const double g3 = par ? dr.v[k] : (k == 0 ? dr.v[1] : d_p2);
+        const bool ok[6] = {l.zlo, l.ylo, pk >= par, pk + 1 - par <= h - 1, l.yhi, l.zhi};
+        const double a[6] = {nsl[0].v[k], nsl[1].v[k], a2, a3, nsl[2].v[k], nsl[3].v[k]};
+        const double dg[6] = {nd[0].v[k], nd[1].v[k], g2, g3, nd[2].v[k], nd[3].v[k]};
+        double d = db.v[k];
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            if (ok[j]) d -= a[j] * a[j] / dg[j];
+        rb.v[k] = 1.0 / d;
+    }
+    *reinterpret_cast<typename R::vec *>(rD + u) = typename R::vec{rr.v[0], rr.v[1]};
+    *reinterpret_cast<typename R::vec *>(rD + nr + u) = typename R::vec{rb.v[0], rb.v[1]};
+}
+
+// k_dic_update_forward_rb (kUpdate) or k_dic_forward_rb with two red-black
+// pairs per lane (the lanes and partial sums of k_amul_dot_rb2): the black
+// rows u, u + 1 take their red neighbours' rD, r (updated: r - alpha q) and
+// mirrored slots as 16-byte loads one line or plane away, and their
+// x-neighbours from the lane's red pair (slots -x and +x, which it loads) or
+// the adjacent lane's; each row's recurrence is the pair kernel's term for
+// term
+template <bool kUpdate>
+__global__ void __launch_bounds__(kCellBlock)
+k_dic_forward_rb2(SolverParams sp, RBLayout L, const double *__restrict__ coef, const double *__restrict__ rD,
+                  const double *__restrict__ q, double *__restrict__ r, double *__restrict__ w,
+                  double *__restrict__ part, const PcgState *__restrict__ st) {
+    if (st->done) return;
+    typedef Lanes<double, 2> R;
+    const RBForm &f = L.f;
+    const int64_t nr = f.nr, h = f.h, H = f.H;
+    const double alpha = kUpdate ? st->alpha : 0.0;
+    const Rb2Lane l = rb2_lane(f);
+    const int64_t u = l.u, pos = l.pos;
+    const int32_t par = l.par;
+    const R z = lanes_zero<double, 2>();
+    // the red r a black row uses: updated (the value the update kernel would
+    // store), or as it is
+    auto upd = [&](double rv, double qv) { return kUpdate ? rv - alpha * qv : rv; };
+    // the lane's red pair: rD, r, slots -x and +x
     R rdr = z, rrr = z, s2 = z, s3 = z;
     if (l.tv) {
         rdr = lanes_load<double, 2>(rD, u);
-        const R r0 = lanes_load<double, 2>(r, u), q0 = lanes_load<double, 2>(q, u);
+        const R r0 = lanes_load<double, 2>(r, u), q0 = kUpdate ? lanes_load<double, 2>(q, u) : z;
 #pragma unroll
-        for (int k = 0; k < 2; ++k) rrr.v[k] = r0.v[k] - alpha * q0.v[k];
+        for (int k = 0; k < 2; ++k) rrr.v[k] = upd(r0.v[k], q0.v[k]);
         s2 = lanes_load<double, 2>(coef, 2 * nr + u);
         s3 = lanes_load<double, 2>(coef, 3 * nr + u);
     }
@@ -893,12 +963,12 @@ k_dic_update_forward_rb2(SolverParams sp, RBLayout L, const double *__restrict__
     if (l.tv) {
         if (!l.below_ok && pos >= 2) {
             rd_m1 = rD[u - 1];
-            rr_m1 = r[u - 1] - alpha * q[u - 1];
+            rr_m1 = upd(r[u - 1], kUpdate ? q[u - 1] : 0.0);
             s3_m1 = coef[3 * nr + u - 1];
         }
         if (!l.above_ok && pos + 2 <= h - 1) {
             rd_p2 = rD[u + 2];
-            rr_p2 = r[u + 2] - alpha * q[u + 2];
+            rr_p2 = upd(r[u + 2], kUpdate ? q[u + 2] : 0.0);
             s2_p2 = coef[2 * nr + u + 2];
         }
         // red neighbours one plane down (slot +z), one line down (+y), one line
@@ -913,21 +983,21 @@ k_dic_update_forward_rb2(SolverParams sp, RBLayout L, const double *__restrict__
             if (has[i]) {
                 const int64_t v = u + off[i];
                 nrd[i] = lanes_load<double, 2>(rD, v);
-                const R r0 = lanes_load<double, 2>(r, v), q0 = lanes_load<double, 2>(q, v);
+                const R r0 = lanes_load<double, 2>(r, v), q0 = kUpdate ? lanes_load<double, 2>(q, v) : z;
 #pragma unroll
-                for (int k = 0; k < 2; ++k) nrr[i].v[k] = r0.v[k] - alpha * q0.v[k];
+                for (int k = 0; k < 2; ++k) nrr[i].v[k] = upd(r0.v[k], q0.v[k]);
                 nsl[i] = lanes_load<double, 2>(coef, slot[i] * nr + v);
             }
         }
-        const R rb = lanes_load<double, 2>(r, nr + u), qb = lanes_load<double, 2, true>(q, nr + u);
+        const R rb = lanes_load<double, 2>(r, nr + u), qb = kUpdate ? lanes_load<double, 2, true>(q, nr + u) : z;
         const R rdb = lanes_load<double, 2>(rD, nr + u);
         R rc, wv;
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             const int64_t pk = pos + k;
-            const double c = rb.v[k] - alpha * qb.v[k];
+            const double c = upd(rb.v[k], qb.v[k]);
             rc.v[k] = c;
-            acc[0] += fabs(c);
+            if (kUpdate) acc[0] += fabs(c);
             const double rd = rdb.v[k];
             double wc = rd * c;
             // x entries: the red cells at u + k - par (slot +x) and u + k + 1 - par (slot -x)
@@ -946,17 +1016,21 @@ k_dic_update_forward_rb2(SolverParams sp, RBLayout L, const double *__restrict__
                 if (ok[j]) wc -= rd * a[j] * (rdo[j] * ro[j]);
             wv.v[k] = wc;
         }
-        *reinterpret_cast<typename R::vec *>(r + nr + u) = typename R::vec{rc.v[0], rc.v[1]};
+        if (kUpdate) *reinterpret_cast<typename R::vec *>(r + nr + u) = typename R::vec{rc.v[0], rc.v[1]};
         *reinterpret_cast<typename R::vec *>(w + nr + u) = typename R::vec{wv.v[0], wv.v[1]};
     }
-    const int slots[1] = {kPartSumR};
-    write_partials<1>(part, sp.grid, slots, acc);
+    if (kUpdate) {
+        const int slots[1] = {kPartSumR};
+        write_partials<1>(part, sp.grid, slots, acc);
+    }
 }
 
-// k_dic_backward_rb_pair<true> with two red-black pairs per lane: the red rows
-// u, u + 1 (their update of r, then the backward sweep from their black
-// neighbours' w), with the w.r partials of the lane's red and black rows and
-// the red rows' |r| added to the forward kernel's partial of the same workgroup
+// k_dic_backward_rb_pair with two red-black pairs per lane: the red rows u,
+// u + 1 (kUpdate: their update of r first), then the backward sweep from their
+// black neighbours' w, with the w.r partials of the lane's red and black rows
+// and (kUpdate) the red rows' |r| added to the forward kernel's partial of the
+// same workgroup
+template <bool kUpdate>
 __global__ void __launch_bounds__(kCellBlock)
 k_dic_backward_rb2(SolverParams sp, RBLayout L, const double *__restrict__ coef, const double *__restrict__ rD,
                    const double *__restrict__ q, double *__restrict__ r, double *__restrict__ w,
@@ -965,7 +1039,7 @@ k_dic_backward_rb2(SolverParams sp, RBLayout L, const double *__restrict__ coef,
     typedef Lanes<double, 2> R;
     const RBForm &f = L.f;
     const int64_t nr = f.nr, h = f.h, H = f.H;
-    const double alpha = st->alpha;
+    const double alpha = kUpdate ? st->alpha : 0.0;
     const Rb2Lane l = rb2_lane(f);
     const int64_t u = l.u, pos = l.pos;
     const int32_t par = l.par;
@@ -985,15 +1059,15 @@ k_dic_backward_rb2(SolverParams sp, RBLayout L, const double *__restrict__ coef,
 #pragma unroll
         for (int i = 0; i < 4; ++i) nw[i] = has[i] ? lanes_load<double, 2>(w, nr + u + off[i]) : z;
         const R rdr = lanes_load<double, 2>(rD, u), rr = lanes_load<double, 2>(r, u);
-        const R qr = lanes_load<double, 2, true>(q, u);
+        const R qr = kUpdate ? lanes_load<double, 2, true>(q, u) : z;
         const R rbk = lanes_load<double, 2>(r, nr + u);
         R rcv, wv;
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             const int64_t pk = pos + k;
-            const double c = rr.v[k] - alpha * qr.v[k];
+            const double c = kUpdate ? rr.v[k] - alpha * qr.v[k] : rr.v[k];
             rcv.v[k] = c;
-            acc[1] += fabs(c);
+            if (kUpdate) acc[1] += fabs(c);
             const double rd = rdr.v[k];
             double wc = rd * c;
             // x entries: the black cells at u + k + par - 1 and u + k + par
@@ -1007,14 +1081,20 @@ k_dic_backward_rb2(SolverParams sp, RBLayout L, const double *__restrict__ coef,
             wv.v[k] = wc;
             acc[0] += wc * c + wb.v[k] * rbk.v[k];
         }
-        *reinterpret_cast<typename R::vec *>(r + u) = typename R::vec{rcv.v[0], rcv.v[1]};
+        if (kUpdate) *reinterpret_cast<typename R::vec *>(r + u) = typename R::vec{rcv.v[0], rcv.v[1]};
         *reinterpret_cast<typename R::vec *>(w + u) = typename R::vec{wv.v[0], wv.v[1]};
     }
-    const double black = part[kPartSumR * sp.grid + blockIdx.x];
-    block_sum<kCellBlock, 2>(acc);
-    if (threadIdx.x == 0) {
-        part[kPartWr * sp.grid + blockIdx.x] = acc[0];
-        part[kPartSumR * sp.grid + blockIdx.x] = black + acc[1];
+    if (kUpdate) {
+        const double black = part[kPartSumR * sp.grid + blockIdx.x];
+        block_sum<kCellBlock, 2>(acc);
+        if (threadIdx.x == 0) {
+            part[kPartWr * sp.grid + blockIdx.x] = acc[0];
+            part[kPartSumR * sp.grid + blockIdx.x] = black + acc[1];
+        }
+    } else {
+        double a1[1] = {acc[0]};
+        const int slots[1] = {kPartWr};
+        write_partials<1>(part, sp.grid, slots, a1);
     }
 }
 
@@ -1431,6 +1511,17 @@ template void launch_fin<kFinStart>(lf_problem *P, hipStream_t s);
 // rows with the w.r partials of all rows)
 static void launch_dic_sweeps(lf_problem *P, hipStream_t s) {
     const lf_mesh *m = P->mesh;
+    if (P->rb && P->rb2) {
+        // the iteration kernels' two-pairs-per-lane form without the update
+        // (its w.r partials fill the first sp.grid_upd entries; the assembly
+        // wrote zeros in the others)
+        const dim3 gb(static_cast<unsigned>(P->sp.grid_upd));
+        LF_LAUNCH(P, LF_K_DIC_FORWARD, s, k_dic_forward_rb2<false>, gb, dim3(kCellBlock), 0, s, P->sp, rb_layout(m),
+                  P->coef, P->rD, P->q, P->r, P->w, P->part, P->state);
+        LF_LAUNCH(P, LF_K_DIC_BACKWARD, s, k_dic_backward_rb2<false>, gb, dim3(kCellBlock), 0, s, P->sp,
+                  rb_layout(m), P->coef, P->rD, P->q, P->r, P->w, P->part, P->state);
+        return;
+    }
     if (P->rb) {
         const int32_t nb = m->N - m->n_red;
         const dim3 gb(static_cast<unsigned>(std::max<int32_t>(1, (nb + kCellBlock - 1) / kCellBlock)));
@@ -1455,7 +1546,10 @@ static lf_status launch_setup(lf_problem *P, hipStream_t s) {
         launch_amg_galerkin(P, s);
         launch_amg_cycle(P, s);
     } else if (!diag_pc) {
-        if (P->rb)
+        if (P->rb2)
+            LF_LAUNCH(P, LF_K_DIC_RD, s, k_dic_rd_rb2, dim3(static_cast<unsigned>(P->sp.grid_upd)), dim3(kCellBlock),
+                      0, s, rb_layout(m), P->diagB, P->coef, P->rD);
+        else if (P->rb)
             LF_LAUNCH(P, LF_K_DIC_RD, s, k_dic_rd_rb, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, rb_layout(m),
                       P->diagB, P->coef, P->rD);
         else
@@ -1519,10 +1613,10 @@ static lf_status launch_iteration(lf_problem *P, hipStream_t s) {
         const lf_mesh *m = P->mesh;
         const dim3 gb(static_cast<unsigned>(P->sp.grid_upd));
         if (P->rb2) {
-            LF_LAUNCH(P, LF_K_DIC_FORWARD, s, k_dic_update_forward_rb2, gb, dim3(kCellBlock), 0, s, P->sp,
+            LF_LAUNCH(P, LF_K_DIC_FORWARD, s, k_dic_forward_rb2<true>, gb, dim3(kCellBlock), 0, s, P->sp,
                       rb_layout(m), P->coef, P->rD, P->q, P->r, P->w, P->part, P->state);
-            LF_LAUNCH(P, LF_K_DIC_BACKWARD, s, k_dic_backward_rb2, gb, dim3(kCellBlock), 0, s, P->sp, rb_layout(m),
-                      P->coef, P->rD, P->q, P->r, P->w, P->part, P->state);
+            LF_LAUNCH(P, LF_K_DIC_BACKWARD, s, k_dic_backward_rb2<true>, gb, dim3(kCellBlock), 0, s, P->sp,
+                      rb_layout(m), P->coef, P->rD, P->q, P->r, P->w, P->part, P->state);
         } else {
             LF_LAUNCH(P, LF_K_DIC_FORWARD, s, k_dic_update_forward_rb, gb, dim3(kCellBlock), 0, s, P->sp,
                       rb_layout(m), P->coef, P->rD, P->q, P->r, P->w, P->part, P->state);
@@ -1683,7 +1777,10 @@ lf_status launch_precondition_hook(lf_problem *P) {
         launch_amg_galerkin(P, s);
         launch_amg_cycle(P, s);
     } else {
-        if (P->rb)
+        if (P->rb2)
+            hipLaunchKernelGGL(k_dic_rd_rb2, dim3(static_cast<unsigned>(P->sp.grid_upd)), dim3(kCellBlock), 0, s,
+                               rb_layout(m), P->diagB, P->coef, P->rD);
+        else if (P->rb)
             hipLaunchKernelGGL(k_dic_rd_rb, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, rb_layout(m), P->diagB,
                                P->coef, P->rD);
         else

@@ -73,10 +73,18 @@ def test_amg_cycle_bitwise(L, oracle, box, walk):
                                               synth.red_black_numbering(synth.box_mesh(16, 10, 6))[0]), None),
     ("rows_redblack_16x10x6", synth.renumber(synth.box_mesh(16, 10, 6, z_ratio=3.0),
                                              synth.red_black_numbering(synth.box_mesh(16, 10, 6))[0]), 1),
+    # the two-colour band layout with two red-black pairs per lane (DIC diagonal and sweeps)
+    ("pairs_redblack_16x10x6", synth.renumber(synth.box_mesh(16, 10, 6, z_ratio=3.0),
+                                              synth.red_black_numbering(synth.box_mesh(16, 10, 6))[0]), "pairs"),
+    ("pairs_redblack_260x4x3", synth.renumber(synth.box_mesh(260, 4, 3, z_ratio=2.0),
+                                              synth.red_black_numbering(synth.box_mesh(260, 4, 3))[0]), "pairs"),
 ])
 def test_dic_application_bitwise(L, oracle, name, mesh, layout):
     T0 = synth.initial_field(mesh.n_cells, 18)
-    r, w = _run_hook(L, mesh, T0, L.LF_PC_DIC, layout)
+    if layout == "pairs":
+        r, w = _run_hook(L, mesh, T0, L.LF_PC_DIC, amul_walk=L.LF_WALK_ON)
+    else:
+        r, w = _run_hook(L, mesh, T0, L.LF_PC_DIC, layout)
     A = oracle.assemble(mesh, synth.fixed_x_bcs(), DT, dt, T0)
     rd = oracle.dic_rd(mesh, A["diag_b"], A["upper"])
     want = oracle.precondition(mesh, oracle.PC_DIC, A["upper"], rd, r)
