@@ -356,6 +356,24 @@ def test_edge_cases_match_oracle(L, oracle, case):
         assert all(s["n_iter"] >= 7 for s in sg)
 
 
+@pytest.mark.parametrize("n", [6, 72], ids=["folded_reductions_6", "finalize_kernels_72"])
+def test_singular_break_matches_oracle(L, oracle, n):
+    """T0 = 0 with all walls zeroGradient gives r0 = 0 exactly; minIter = 1 forces
+    one iteration, whose direction is 0: p.Ap = 0 breaks the loop as singular,
+    no iteration counted, T unchanged.  6^3 takes the iteration's decisions
+    inside the update and direction kernels, 72^3 in the one-workgroup
+    finalize kernels."""
+    mesh = synth.box_mesh(n, n, n)
+    T0 = np.zeros(mesh.n_cells)
+    Tg, sg = run_gpu(L, mesh, synth.all_zero_gradient(), 1e-3, 1e-3, T0, 2, min_iter=1)
+    _, so, _ = oracle.run(mesh, synth.all_zero_gradient(), 1e-3, 1e-3, 2, T0, keep_all=True, min_iter=1)
+    for s in range(2):
+        assert so[s]["singular"] == 1 and so[s]["n_iter"] == 0
+        assert sg[s]["singular"] == 1 and sg[s]["n_iter"] == 0, sg[s]
+        assert sg[s]["nonfinite"] == 0
+        assert np.array_equal(Tg[s], T0)
+
+
 def test_determinism_and_graph_equivalence(L):
     """No atomics in floating point: two runs, with or without graphs, are bitwise equal."""
     p = synth.build_config("permuted_192", n=22, steps=4)
