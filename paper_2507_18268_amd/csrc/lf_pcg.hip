@@ -858,6 +858,208 @@ k_amul_rb2(RBLayout L, const double *__restrict__ diagB, const double *__restric
     });
 }
 
+// The assembly on the two-colour band layout with two red-black pairs per lane
+// (the lanes of k_amul_dot_rb2; orthogonal meshes, T_old not used): a red
+// row's six slot factors (delta, |S|) are 16-byte loads of its own slots, a
+// black row's are its red neighbours' mirrored slots (one line or plane away,
+// the lane's red pair, or the adjacent lane's), and the neighbours' x0 = T
+// likewise; each row's coefficients, lapDiag, boundary fold and (kSetup) A x0,
+// residual and normalisation terms come from the one-row kernel's expressions
+// in its order, so the matrix is bitwise the same.  kSetup: the partial sums
+// per workgroup, and zeros in each slot's further entries up to the cell
+// grid's count (the reduction that follows reads that many).
+template <bool kFull, bool kSetup>
+__global__ void __launch_bounds__(kCellBlock)
+k_assemble_rb2(SolverParams sp, double rdt, double DT, RBLayout L, const int32_t *__restrict__ bface_start,
+               const int32_t *__restrict__ bface_list, const int32_t *__restrict__ bface_patch,
+               const double *__restrict__ bmag_sf, const double *__restrict__ bdelta,
+               const int32_t *__restrict__ patch_type, const double *__restrict__ patch_value,
+               const double *__restrict__ V, const double *__restrict__ T, double *__restrict__ coef,
+               double *__restrict__ diag, double *__restrict__ source, double *__restrict__ diagB,
+               double *__restrict__ srcB, double *__restrict__ int_coeff, double *__restrict__ bou_coeff,
+               double *__restrict__ r, double *__restrict__ part, const PcgState *__restrict__ st) {
+    typedef Lanes<double, 2> R;
+    typedef typename R::vec RV;
+    const RBForm &f = L.f;
+    const int64_t nr = f.nr, h = f.h, H = f.H;
+    const Rb2Lane l = rb2_lane(f);
+    const int64_t u = l.u, pos = l.pos;
+    const int32_t par = l.par;
+    const R z = lanes_zero<double, 2>();
+    const double x_avg = kSetup ? st->x_avg : 0.0;
+    R dl[6], ms[6], tr = z, tb = z;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) dl[j] = ms[j] = z;
+    if (l.tv) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            dl[j] = lanes_load<double, 2>(L.delta, j * nr + u);
+            ms[j] = lanes_load<double, 2>(L.mag_sf, j * nr + u);
+        }
+        tr = lanes_load<double, 2>(T, u);
+        tb = lanes_load<double, 2>(T, nr + u);
+    }
+    // the adjacent lanes': slot +x factors and T at u - 1, slot -x factors and T at u + 2
+    double d3m = lane_from_below(dl[3].v[1]), m3m = lane_from_below(ms[3].v[1]);
+    double tbm = lane_from_below(tb.v[1]), trm = lane_from_below(tr.v[1]);
+    double d2p = lane_from_above(dl[2].v[0]), m2p = lane_from_above(ms[2].v[0]);
+    double tbp = lane_from_above(tb.v[0]), trp = lane_from_above(tr.v[0]);
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (l.tv) {
+        if (!l.below_ok && pos >= 2) {
+            d3m = L.delta[3 * nr + u - 1];
+            m3m = L.mag_sf[3 * nr + u - 1];
+            tbm = T[nr + u - 1];
+            trm = T[u - 1];
+        }
+        if (!l.above_ok && pos + 2 <= h - 1) {
+            d2p = L.delta[2 * nr + u + 2];
+            m2p = L.mag_sf[2 * nr + u + 2];
+            tbp = T[nr + u + 2];
+            trp = T[u + 2];
+        }
+        // one plane down, one line down, one line up, one plane up: the red
+        // neighbours' mirrored slots (+z, +y, -y, -z) and T of both colours
+        const int64_t off[4] = {-H, -h, h, H};
+        const int slot[4] = {5, 4, 1, 0};
+        const bool has[4] = {l.zlo, l.ylo, l.yhi, l.zhi};
+        R ndl[4], nms[4], ntb[4], ntr[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            ndl[i] = nms[i] = ntb[i] = ntr[i] = z;
+            if (has[i]) {
+                const int64_t v = u + off[i];
+                ndl[i] = lanes_load<double, 2>(L.delta, slot[i] * nr + v);
+                nms[i] = lanes_load<double, 2>(L.mag_sf, slot[i] * nr + v);
+                ntb[i] = lanes_load<double, 2>(T, nr + v);
+                ntr[i] = lanes_load<double, 2>(T, v);
+            }
+        }
+        const R vr = lanes_load<double, 2>(V, u), vb = lanes_load<double, 2>(V, nr + u);
+        R ca[6], dd[2], ss[2], dbv[2], sbv[2], rv[2];
+        // q = 0: the red rows u, u + 1; q = 1: the black rows nr + u, nr + u + 1
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int64_t pk = pos + k;
+                const int64_t c = (q == 0 ? 0 : nr) + u + k;
+                bool ok[6];
+                double fd[6], fm[6], xv[6];
+                const double own = q == 0 ? tb.v[k] : tr.v[k];   // x of an absent entry
+                if (q == 0) {
+                    const bool o6[6] = {l.zlo, l.ylo, pk + par - 1 >= 0, pk + par <= h - 1, l.yhi, l.zhi};
+#pragma unroll
+                    for (int j = 0; j < 6; ++j) {
+                        ok[j] = o6[j];
+                        fd[j] = dl[j].v[k];
+                        fm[j] = ms[j].v[k];
+                    }
+                    xv[0] = ntb[0].v[k];
+                    xv[1] = ntb[1].v[k];
+                    xv[2] = par ? tb.v[k] : (k == 0 ? tbm : tb.v[0]);
+                    xv[3] = par ? (k == 0 ? tb.v[1] : tbp) : tb.v[k];
+                    xv[4] = ntb[2].v[k];
+                    xv[5] = ntb[3].v[k];
+                } else {
+                    const bool o6[6] = {l.zlo, l.ylo, pk >= par, pk + 1 - par <= h - 1, l.yhi, l.zhi};
+#pragma unroll
+                    for (int j = 0; j < 6; ++j) ok[j] = o6[j];
+                    fd[0] = ndl[0].v[k];
+                    fm[0] = nms[0].v[k];
+                    fd[1] = ndl[1].v[k];
+                    fm[1] = nms[1].v[k];
+                    fd[2] = par ? (k == 0 ? d3m : dl[3].v[0]) : dl[3].v[k];
+                    fm[2] = par ? (k == 0 ? m3m : ms[3].v[0]) : ms[3].v[k];
+                    fd[3] = par ? dl[2].v[k] : (k == 0 ? dl[2].v[1] : d2p);
+                    fm[3] = par ? ms[2].v[k] : (k == 0 ? ms[2].v[1] : m2p);
+                    fd[4] = ndl[2].v[k];
+                    fm[4] = nms[2].v[k];
+                    fd[5] = ndl[3].v[k];
+                    fm[5] = nms[3].v[k];
+                    xv[0] = ntr[0].v[k];
+                    xv[1] = ntr[1].v[k];
+                    xv[2] = par ? (k == 0 ? trm : tr.v[0]) : tr.v[k];
+                    xv[3] = par ? tr.v[k] : (k == 0 ? tr.v[1] : trp);
+                    xv[4] = ntr[2].v[k];
+                    xv[5] = ntr[3].v[k];
+                }
+                double a[6], lap_diag = 0.0;
+#pragma unroll
+                for (int j = 0; j < 6; ++j) {
+                    const double dlj = ok[j] ? fd[j] : 0.0, msj = ok[j] ? fm[j] : 0.0;
+                    const double lap_upper = dlj * (DT * msj);
+                    a[j] = -lap_upper;
+                    lap_diag -= lap_upper;
+                    if (!ok[j]) xv[j] = own;
+                }
+                if (q == 0) {
+#pragma unroll
+                    for (int j = 0; j < 6; ++j) ca[j].v[k] = a[j];
+                }
+                const double vv = q == 0 ? vr.v[k] : vb.v[k];
+                const double xc = q == 0 ? tr.v[k] : tb.v[k];
+                const double d = rdt * vv - lap_diag;
+                const double src = (rdt * xc) * vv;
+                double db = d, sb = src;
+                for (int32_t i = bface_start[c]; i < bface_start[c + 1]; ++i) {
+                    const int32_t b = bface_list[i];
+                    const int32_t pt = bface_patch[b];
+                    if (patch_type[pt] == LF_BC_FIXED_VALUE) {
+                        const double g = DT * bmag_sf[b];
+                        const double ic = g * bdelta[b];
+                        const double bc = g * (bdelta[b] * patch_value[pt]);
+                        db += ic;
+                        sb += bc;
+                        if (kFull) { int_coeff[b] = ic; bou_coeff[b] = bc; }
+                    } else if (kFull) {
+                        int_coeff[b] = 0.0;
+                        bou_coeff[b] = 0.0;
+                    }
+                }
+                dd[q].v[k] = d;
+                ss[q].v[k] = src;
+                dbv[q].v[k] = db;
+                sbv[q].v[k] = sb;
+                if (kSetup) {
+                    double ax = db * xc, sa = db;
+#pragma unroll
+                    for (int j = 0; j < 6; ++j) {
+                        ax += a[j] * xv[j];
+                        sa += a[j];
+                    }
+                    const double rc = sb - ax;
+                    const double pa = sa * x_avg;
+                    rv[q].v[k] = rc;
+                    acc[0] += fabs(rc);
+                    acc[1] += fabs(ax - pa) + fabs(sb - pa);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 6; ++j) *reinterpret_cast<RV *>(coef + j * nr + u) = RV{ca[j].v[0], ca[j].v[1]};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int64_t c0 = (q == 0 ? 0 : nr) + u;
+            if (kFull) {
+                *reinterpret_cast<RV *>(diag + c0) = RV{dd[q].v[0], dd[q].v[1]};
+                *reinterpret_cast<RV *>(source + c0) = RV{ss[q].v[0], ss[q].v[1]};
+            }
+            *reinterpret_cast<RV *>(diagB + c0) = RV{dbv[q].v[0], dbv[q].v[1]};
+            *reinterpret_cast<RV *>(srcB + c0) = RV{sbv[q].v[0], sbv[q].v[1]};
+            if (kSetup) *reinterpret_cast<RV *>(r + c0) = RV{rv[q].v[0], rv[q].v[1]};
+        }
+    }
+    if (kSetup) {
+        const int slots[3] = {kPartSumR, kPartNf, kPartWr};
+        write_partials<3>(part, sp.grid, slots, acc);
+        if (threadIdx.x == 0)
+            for (int64_t j = gridDim.x + static_cast<int64_t>(blockIdx.x); j < sp.grid; j += gridDim.x)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) part[static_cast<int64_t>(slots[q]) * sp.grid + j] = 0.0;
+    }
+}
+
 // k_dic_rd_rb with two red-black pairs per lane: red rows 1/diag, black rows
 // 1/(diag - sum over their red neighbours, in the row's order, of a^2 / the
 // neighbour's diag), neighbours as in k_dic_forward_rb2
@@ -1447,6 +1649,16 @@ static void launch_assemble_t(lf_problem *P, hipStream_t s) {
                           P->patch_value, m->V, P->T, P->coef, P->upper, P->diag, P->source, P->diagB, P->srcB,
                           P->int_coeff, P->bou_coeff, diag_pc ? 1 : 0, P->r, P->rD, P->part, P->state, P->sig32,
                           P->r32, P->d32, P->p, nullptr, T_old, P->grad3, m->gkband);
+                return;
+            }
+        }
+        if constexpr (std::is_same_v<Lay, RBLayout> && !kMixed) {
+            if (P->rb2 && !P->nonorth && !diag_pc) {
+                auto kern = k_assemble_rb2<kFull, kSetup>;
+                LF_LAUNCH(P, LF_K_ASSEMBLE, s, kern, dim3(static_cast<unsigned>(P->sp.grid_upd)), dim3(kCellBlock),
+                          0, s, P->sp, rdt, P->DT, lay, m->rbface_start, m->rbface_list, m->bface_patch, m->bmag_sf,
+                          m->bdelta, P->patch_type, P->patch_value, m->V, P->T, P->coef, P->diag, P->source,
+                          P->diagB, P->srcB, P->int_coeff, P->bou_coeff, P->r, P->part, P->state);
                 return;
             }
         }

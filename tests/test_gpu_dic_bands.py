@@ -134,9 +134,10 @@ WALK_MESHES.append(("rb_260x4x2_graded", _rb(260, 4, 2, 3.0)))
 
 @pytest.mark.parametrize("name,mm", WALK_MESHES, ids=[n for n, _ in WALK_MESHES])
 def test_rb_walk_product_bitwise_and_steps(L, oracle, name, mm):
-    """The product with two red-black pairs per lane: bitwise the oracle's;
-    steps within 1e-8 of the oracle's sequential DIC and of the steps with
-    one pair per thread, iterations within one."""
+    """The assembly and the product with two red-black pairs per lane: matrix
+    and product bitwise the oracle's; steps within 1e-8 of the oracle's
+    sequential DIC and of the steps with one pair per thread, iterations
+    within one."""
     import torch
     mesh, new_of_old = mm
     T0 = synth.initial_field(mesh.n_cells, 13, new_of_old=new_of_old)
@@ -151,6 +152,10 @@ def test_rb_walk_product_bitwise_and_steps(L, oracle, name, mm):
             P.set_T(T0)
             P.assemble()
             o = oracle.assemble(mesh, synth.fixed_x_bcs(), DT, dt, T0)
+            # the assembly in the same form: the matrix bitwise the oracle's
+            g = P.matrix()
+            for key in ("diag", "upper", "source", "diag_b", "source_b", "int_coeff", "bou_coeff"):
+                assert np.array_equal(g[key], o[key]), (name, key)
             x = np.random.default_rng(7).uniform(-1.0, 1.0, mesh.n_cells)
             xd = torch.from_numpy(x).cuda()
             yd = torch.empty_like(xd)
