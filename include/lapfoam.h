@@ -333,8 +333,9 @@ lf_status lf_problem_layout(const lf_problem *problem, int32_t *layout);
  * inner FP32 products of LF_PREC_MIXED take the block walk too when nx is a
  * multiple of 4 (four rows per lane), else the row walk; with 1 the row walk.
  * 3: DIC on the two-colour band layout with x-lines of a multiple of four
- * cells, the product of its iterations with two red-black pairs per lane
- * (16-byte loads), under the same rule as the row walk.
+ * cells: the product, the sweeps, the DIC diagonal and the assembly with two
+ * red-black pairs per lane (16-byte loads), under the same rule as the row
+ * walk.
  * All forms give bitwise the same product. */
 lf_status lf_problem_amul_walk(const lf_problem *problem, int32_t *walk);
 

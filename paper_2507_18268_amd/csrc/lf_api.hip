@@ -204,9 +204,9 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
         // an iteration then number the pair workgroups
         P->sp.grid_amul = cell_blocks(m->n_red);
         P->sp.grid_upd = P->sp.grid_amul;
-        // the product and the sweeps with two pairs per lane where x-lines hold
-        // a multiple of four cells, under the row walk's rule (their partials
-        // number their workgroups)
+        // the product, the sweeps, the DIC diagonal and the assembly with two
+        // pairs per lane where x-lines hold a multiple of four cells, under the
+        // row walk's rule (their partials number their workgroups)
         const RBForm rf = rb_form(m);
         if (rb2_form(rf) && opts.amul_walk != LF_WALK_OFF) {
             const int32_t wb = rb2_blocks(rf.nr);

@@ -143,7 +143,7 @@ struct lf_problem {
     lf::BoxWalk bw{};                          // its plan (2 rows per lane)
     bool box32 = false;                        // the FP32 inner product too (mixed; 4 rows per lane)
     lf::BoxWalk bw32{};
-    bool rb2 = false;                          // DIC's product on the two-colour layout: two pairs per lane
+    bool rb2 = false;                          // DIC's kernels on the two-colour layout: two pairs per lane
     bool fold = false;                         // small diagonal FP64 solves: the iteration's reductions folded
                                                // into the update and direction kernels
     // multigrid preconditioner: coarse levels 1.. (level 0 is the problem's own

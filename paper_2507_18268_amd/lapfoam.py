@@ -578,7 +578,7 @@ class Problem:
 
     def amul_form(self):
         """0 one row per thread, 1 the row walk, 2 the block walk of a box,
-        3 DIC's product on the two-colour layout with two red-black pairs per lane."""
+        3 DIC's kernels on the two-colour layout with two red-black pairs per lane."""
         return lf_problem_amul_walk(self.h)
 
     def reset(self, bcs, DT, dt):
