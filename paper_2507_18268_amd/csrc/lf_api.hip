@@ -292,6 +292,7 @@ lf_status lf_problem_reset(lf_problem *P, const lf_patch_bc *bcs, double DT, dou
     P->dt = dt;
     P->assembled = false;
     P->scaled32 = false;
+    P->sumx_valid = false;
     return LF_OK;
 }
 
@@ -362,6 +363,7 @@ lf_status lf_set_T(lf_problem *P, const double *T, int32_t on_device) {
     clear_error();
     if (!P || !T) { set_error("NULL argument"); return LF_EINVAL; }
     if (async_running(P)) { set_error("a run is in flight (lf_step_begin or a group)"); return LF_ESTATE; }
+    P->sumx_valid = false;
     const int32_t N = P->mesh->N;
     if (!on_device) {
         for (int32_t c = 0; c < N; ++c)

@@ -458,13 +458,26 @@ k_direction_fold(SolverParams sp, const double *__restrict__ rD, const double *_
 
 // end of a solve: the update x += alpha p of the last counted iteration is
 // still pending unless the solve stopped at a singular or non-finite point
-// (then the pending update was applied by the last direction kernel)
+// (then the pending update was applied by the last direction kernel).  The
+// same launch writes k_sum_x's partial sums of the new x (same workgroups,
+// same values), which the next solve's mean takes instead of a pass of its own.
 __global__ void __launch_bounds__(kCellBlock)
-k_commit(SolverParams sp, double *__restrict__ x, const double *__restrict__ p, const PcgState *__restrict__ st) {
-    if (st->n_iter < 1 || st->singular || st->nonfinite) return;
+k_commit(SolverParams sp, double *__restrict__ x, const double *__restrict__ p, double *__restrict__ part,
+         const PcgState *__restrict__ st) {
+    const bool apply = !(st->n_iter < 1 || st->singular || st->nonfinite);
     const double alpha = st->alpha;
     const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
-    if (c < sp.n) x[c] += alpha * p[c];
+    double acc[1] = {0.0};
+    if (c < sp.n) {
+        double xc = x[c];
+        if (apply) {
+            xc += alpha * p[c];
+            x[c] = xc;
+        }
+        acc[0] = xc;
+    }
+    const int slots[1] = {kPartSumX};
+    write_partials<1>(part, sp.grid, slots, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1695,7 +1708,10 @@ void launch_fin(lf_problem *P, hipStream_t s) {
 
 // mean of x0 = T, then the assembly fused with the start of the solve
 lf_status launch_assemble_setup(lf_problem *P, hipStream_t s) {
-    LF_LAUNCH(P, LF_K_SETUP1, s, k_sum_x, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->T, P->part);
+    // the partial sums of T: written by the last solve's commit when nothing
+    // has written T since, else taken here
+    if (!P->sumx_valid) LF_LAUNCH(P, LF_K_SETUP1, s, k_sum_x, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->T, P->part);
+    P->sumx_valid = false;
     launch_fin<kFinMean>(P, s);
     if (P->opts.precision == LF_PREC_MIXED) {
         launch_assemble_t<false, true, true>(P, s);
@@ -1962,8 +1978,10 @@ lf_status fp64_advance(lf_problem *P, SolveCtx &c, bool *finished, lf_solve_stat
     }
     if (P->h_state->done) {
         prof_lead(P, s);
-        LF_LAUNCH(P, LF_K_COMMIT, s, k_commit, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->T, P->p, P->state);
+        LF_LAUNCH(P, LF_K_COMMIT, s, k_commit, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->T, P->p, P->part,
+                  P->state);
         LF_HIP(hipGetLastError());
+        P->sumx_valid = true;
         LF_HIP(hipEventRecord(P->ev[2], s));
         c.stage = 1;
         return LF_OK;

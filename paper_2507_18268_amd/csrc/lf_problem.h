@@ -144,6 +144,8 @@ struct lf_problem {
     bool box32 = false;                        // the FP32 inner product too (mixed; 4 rows per lane)
     lf::BoxWalk bw32{};
     bool rb2 = false;                          // DIC's kernels on the two-colour layout: two pairs per lane
+    bool sumx_valid = false;                   // the part array holds the partial sums of the current T
+                                               // (written by the FP64 commit; any other write of T clears it)
     bool fold = false;                         // small diagonal FP64 solves: the iteration's reductions folded
                                                // into the update and direction kernels
     // multigrid preconditioner: coarse levels 1.. (level 0 is the problem's own
