@@ -58,25 +58,28 @@ def kernel_source_hash(sources=None):
     return h.hexdigest()
 
 
-def amul_bytes(n_cells, n_faces, value_bytes=8, addressed=True):
+def amul_bytes(n_cells, n_faces, value_bytes=8, addressed=True, unit_diag=False):
     """Algorithmic bytes of one LDU product: x, diag and Ax once per cell, the
     coefficient once per face and, when the faces are addressed (owner and
     neighbour lists), their two int32 addresses.  A structured numbering (the
     band layout) needs no addresses: the neighbour of row c across band k is
-    c + d_k."""
-    return 3 * value_bytes * n_cells + (value_bytes + (8 if addressed else 0)) * n_faces
+    c + d_k.  A matrix with unit diagonal (the Jacobi-scaled one) has no
+    diagonal to read."""
+    per_cell = 2 if unit_diag else 3
+    return per_cell * value_bytes * n_cells + (value_bytes + (8 if addressed else 0)) * n_faces
 
 
-def layout_bytes(mesh, layout_name, value_bytes=8):
+def layout_bytes(mesh, layout_name, value_bytes=8, unit_diag=False):
     """Bytes one LDU product must move in the layout it runs in: p, diag and Ap
-    per cell plus, for the band layout, one coefficient per band slot (no
-    indices); for the row layout, per stored entry its coefficient and int32
-    column, and one uint8 row length per cell."""
+    per cell (no diag with a unit diagonal) plus, for the band layout, one
+    coefficient per band slot (no indices); for the row layout, per stored
+    entry its coefficient and int32 column, and one uint8 row length per
+    cell."""
     import numpy as np
     N = mesh.n_cells
     if layout_name == "bands":
         K = np.unique(mesh.neighbour.astype(np.int64) - mesh.owner).size
-        return 3 * value_bytes * N + value_bytes * K * N
+        return (2 if unit_diag else 3) * value_bytes * N + value_bytes * K * N
     rl = np.bincount(mesh.owner, minlength=N) + np.bincount(mesh.neighbour, minlength=N)
     pad = (-N) % 64
     E = int(np.concatenate([rl, np.zeros(pad, rl.dtype)]).reshape(-1, 64).max(axis=1).sum()) * 64
@@ -667,7 +670,8 @@ def main():
     layout_name = "bands" if prob.layout() == L.LF_LAYOUT_BANDS else "rows"
     walk = prob.amul_form()
     amul_form = {0: "one row per thread", 1: "row walk", 2: "block walk of the box",
-                 3: "two red-black pairs per lane"}[walk]
+                 3: "two red-black pairs per lane",
+                 4: "block walk of the box (solve on the Jacobi-scaled matrix)"}[walk]
     log(f"[bench] device mesh + problem ready in {time.perf_counter() - t:.1f} s "
         f"(workspaces {mesh.ws_bytes / 2**30:.2f} + {prob.ws_bytes / 2**30:.2f} GiB, {layout_name} layout{', Amul by the ' + amul_form if walk else ''})")
 
@@ -721,20 +725,24 @@ def main():
         us = ka["avg_us"]
         # algorithmic bytes of the product as it runs: the band layout's
         # neighbours are implicit (c + d_k), so no face addresses
-        per_launch = amul_bytes(N, F, addressed=(layout_name != "bands"))
+        unit = walk == 4
+        per_launch = amul_bytes(N, F, addressed=(layout_name != "bands"), unit_diag=unit)
         achieved = per_launch / (us * 1e-6) / 1e9
-        kname = {0: "k_amul_dot", 1: "k_amul_dot_walk", 2: "k_amul_dot_box", 3: "k_amul_dot_rb2"}[walk]
-        roof = {"kernel": f"{kname} (q = A p with p.q partials)", "bound": "hbm",
+        kname = {0: "k_amul_dot", 1: "k_amul_dot_walk", 2: "k_amul_dot_box", 3: "k_amul_dot_rb2",
+                 4: "k_amul_dot_box_scaled"}[walk]
+        what = "q~ = (S A S) p~" if unit else "q = A p"
+        roof = {"kernel": f"{kname} ({what} with p.q partials)", "bound": "hbm",
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                 "algorithmic_bytes_per_launch": per_launch,
-                "algorithmic_bytes": "24 B/cell (p, diag, q) + 8 B/face (coefficient)"
+                "algorithmic_bytes": ("16 B/cell (p, q; unit diagonal)" if unit else "24 B/cell (p, diag, q)")
+                                     + " + 8 B/face (coefficient)"
                                      + ("" if layout_name == "bands" else " + 8 B/face (two int32 addresses)"),
                 "avg_launch_us": us, "largest_total_time_kernel": dom}
-        face_addr = amul_bytes(N, F, addressed=True)
+        face_addr = amul_bytes(N, F, addressed=True, unit_diag=unit)
         roof["face_addressed_bytes_per_launch"] = face_addr
         roof["face_addressed_frac"] = face_addr / (us * 1e-6) / 1e9 / HBM_PEAK_GBS
-        lb = layout_bytes(p.mesh, layout_name)
+        lb = layout_bytes(p.mesh, layout_name, unit_diag=unit)
         roof["layout"] = layout_name
         roof["layout_bytes_per_launch"] = lb
         roof["layout_GBps"] = lb / (us * 1e-6) / 1e9

@@ -336,7 +336,16 @@ lf_status lf_problem_layout(const lf_problem *problem, int32_t *layout);
  * cells: the product, the sweeps, the DIC diagonal and the assembly with two
  * red-black pairs per lane (16-byte loads), under the same rule as the row
  * walk.
- * All forms give bitwise the same product. */
+ * 4: form 2, and the FP64 solve with the diagonal preconditioner, where its
+ * iteration's reductions are not folded into the update and direction (more
+ * than 512 partials per slot), runs CG on the Jacobi-scaled system
+ * S A S y = S b, S = diag(1/sqrt(diagB)) (unit diagonal; the same iterates as
+ * the diagonally preconditioned CG of A in exact arithmetic, with the
+ * residual norm still taken of b - A x): the iteration's product reads no
+ * diagonal and its direction update no reciprocal, 16 bytes fewer per cell
+ * and iteration; the scaled coefficients are formed once per solve.
+ * lf_amul multiplies by A in every form.
+ * All forms give bitwise the same product A x. */
 lf_status lf_problem_amul_walk(const lf_problem *problem, int32_t *walk);
 
 /* T[N]: on_device = 1 means a device pointer (copied on the handle's stream),
@@ -542,7 +551,9 @@ lf_status lf_group_poll(lf_group *group, lf_problem **finished, int32_t max_fini
 #define LF_K_NONORTH 21         /* non-orthogonal meshes without band form: the
                                    correction fluxes' divergence (band meshes form
                                    it inside the assembly) */
-#define LF_NUM_KERNEL_CLASSES 22
+#define LF_K_SCALE 22           /* FP64 solves in product form 4: the coefficients
+                                   of the Jacobi-scaled matrix (once per solve) */
+#define LF_NUM_KERNEL_CLASSES 23
 lf_status lf_profile_enable(lf_problem *problem, int32_t on);
 lf_status lf_profile_read(lf_problem *problem, int32_t n_classes, double *total_ms, int64_t *launches);
 

@@ -219,6 +219,10 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
     }
     P->fold = opts.precision == LF_PREC_FP64 && opts.precond == LF_PC_DIAGONAL && !P->rb &&
               P->sp.grid_amul <= kFoldPartials && P->sp.grid_upd <= kFoldPartials;
+    // larger diagonal FP64 solves on the block walk iterate on the Jacobi-scaled
+    // matrix (its coefficients carved by carve_problem for every FP64 diagonal
+    // problem of a three-band layout)
+    P->scaled = P->box && !P->fold && opts.precision == LF_PREC_FP64 && opts.precond == LF_PC_DIAGONAL;
     P->sp.max_outer = opts.max_outer > 0 ? opts.max_outer : 50;
     P->sp.inner_tol = opts.inner_tol > 0.0 ? opts.inner_tol : 1e-5;
     P->sp.inner_restart = opts.inner_restart ? 1 : 0;
@@ -306,7 +310,7 @@ lf_status lf_problem_layout(const lf_problem *P, int32_t *layout) {
 lf_status lf_problem_amul_walk(const lf_problem *P, int32_t *walk) {
     clear_error();
     if (!P || !walk) { set_error("NULL argument"); return LF_EINVAL; }
-    *walk = P->box ? 2 : (P->walk ? 1 : (P->rb2 ? 3 : 0));
+    *walk = P->scaled ? 4 : (P->box ? 2 : (P->walk ? 1 : (P->rb2 ? 3 : 0)));
     return LF_OK;
 }
 

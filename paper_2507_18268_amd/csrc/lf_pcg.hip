@@ -95,7 +95,7 @@ __device__ __forceinline__ void assemble_rows(
     double *__restrict__ part, const PcgState *__restrict__ st, float *__restrict__ sig32, float *__restrict__ r32,
     float *__restrict__ d32, double *__restrict__ p, const double *__restrict__ lap_src,
     const double *__restrict__ T_old, const double *__restrict__ nb_g = nullptr,
-    const double *__restrict__ nb_gk = nullptr) {
+    const double *__restrict__ nb_gk = nullptr, double *__restrict__ xs = nullptr) {
     const int32_t c = blk * kCellBlock + static_cast<int32_t>(threadIdx.x);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const double x_avg = kSetup ? st->x_avg : 0.0;
@@ -138,10 +138,22 @@ __device__ __forceinline__ void assemble_rows(
             row_amul_sum(L, c, coef, rcf, T, ax, sa);
             const double rc = sb - ax;
             const double pa = sa * x_avg;
-            if (!kMixed) r[c] = rc;
+            if (!kMixed && diag_pc != 2) r[c] = rc;
             acc[0] = fabs(rc);
             acc[1] = fabs(ax - pa) + fabs(sb - pa);
-            if (diag_pc && !kMixed) {       // the precision form keeps only the FP32 rD
+            if (diag_pc == 2 && !kMixed) {
+                // the start of CG on the Jacobi-scaled system: r~ = r / sd, the
+                // first direction p~ = r~, x~ = sd x0 (sd = sqrt(diagB), kept in
+                // rD); w.r = r~.r~
+                const double sd = sqrt(db);
+                const double rt = rc / sd;
+                rD[c] = sd;
+                r[c] = rt;
+                p[c] = rt;
+                xs[c] = sd * xc;
+                acc[2] = rt * rt;
+            }
+            if (diag_pc == 1 && !kMixed) {  // the precision form keeps only the FP32 rD
                 const double rd = 1.0 / db;
                 rD[c] = rd;
                 const double wc = rd * rc;
@@ -184,11 +196,11 @@ k_assemble(SolverParams sp, double rdt, double DT, Lay L, const int32_t *__restr
            double *__restrict__ part, const PcgState *__restrict__ st, float *__restrict__ sig32,
            float *__restrict__ r32, float *__restrict__ d32, double *__restrict__ p,
            const double *__restrict__ lap_src, const double *__restrict__ T_old,
-           const double *__restrict__ nb_g, const double *__restrict__ nb_gk) {
+           const double *__restrict__ nb_g, const double *__restrict__ nb_gk, double *__restrict__ xs) {
     assemble_rows<Lay, kFull, kSetup, kMixed, kNonorth>(
         static_cast<int32_t>(blockIdx.x), sp, rdt, DT, L, bface_start, bface_list, bface_patch, bmag_sf, bdelta,
         patch_type, patch_value, V, T, coef, upper, diag, source, diagB, srcB, int_coeff, bou_coeff, diag_pc, r, rD,
-        part, st, sig32, r32, d32, p, lap_src, T_old, nb_g, nb_gk);
+        part, st, sig32, r32, d32, p, lap_src, T_old, nb_g, nb_gk, xs);
 }
 
 // partial sums of x0 = T (its mean enters the normalisation factor)
@@ -475,6 +487,108 @@ k_commit(SolverParams sp, double *__restrict__ x, const double *__restrict__ p, 
             x[c] = xc;
         }
         acc[0] = xc;
+    }
+    const int slots[1] = {kPartSumX};
+    write_partials<1>(part, sp.grid, slots, acc);
+}
+
+// ---------------------------------------------------------------------------
+// Diagonal FP64 solves on the block walk (not folded): CG on the Jacobi-scaled
+// system.  With sd = sqrt(diagB) and S = diag(1/sd), the diagonally
+// preconditioned CG of A (w = r / diagB) and plain CG on S A S, whose diagonal
+// is 1, have the same iterates under x~ = sd x, r~ = r / sd, p~ = sd p,
+// q~ = S A S p~ = q / sd: w.r = r~.r~, p.q = p~.q~, hence the same alpha and
+// beta.  The assembly's set-up writes sd (into rD), r~, p~ = r~ and x~ (into
+// w); the iteration's product then reads no diagonal and its direction update
+// no reciprocal; the convergence test still takes the L1 norm of the residual
+// of A, sum |sd r~|; the commit writes T = x~ / sd.
+// ---------------------------------------------------------------------------
+
+// coefficients of S A S in the band layout: slot k of row c holds
+// a / (sd_c sd_{c+d_k}), 0 where the band has no face (two rows per thread, N
+// even as on every box with the block walk)
+__global__ void __launch_bounds__(kCellBlock)
+k_scale_coef(BandLayout<3> L, const double *__restrict__ sd, const double *__restrict__ coef,
+             double *__restrict__ coefS) {
+    typedef Lanes<double, 2> R;
+    const int64_t c = 2 * (static_cast<int64_t>(blockIdx.x) * kCellBlock + threadIdx.x);
+    if (c >= L.n) return;
+    const R s = lanes_load<double, 2>(sd, c);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int64_t o = k * L.n + c;
+        const R a = lanes_load<double, 2, true>(coef, o);
+        R y;
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            const int64_t j = c + w + L.d[k];
+            y.v[w] = j < L.n ? a.v[w] / (s.v[w] * sd[j]) : 0.0;
+        }
+        lanes_store_stream(coefS, o, y);
+    }
+}
+
+// q~ = (S A S) p~ and the partial sums of q~.p~ by the block walk
+__global__ void __launch_bounds__(kBwBlock)
+k_amul_dot_box_scaled(SolverParams sp, BandLayout<3> L, BoxWalk bw, const double *__restrict__ coefS,
+                      const double *__restrict__ p, double *__restrict__ q, double *__restrict__ part,
+                      const PcgState *__restrict__ st) {
+    if (st->done) return;
+    double acc[1] = {0.0};
+    typedef Lanes<double, 2> R;
+    box_walk<double, 2, false, true>(L, bw, nullptr, coefS, p, [&](int64_t c, const R &qc, const R &pc, const R &) {
+        lanes_store_stream(q, c, qc);
+        acc[0] += qc.v[0] * pc.v[0];
+        acc[0] += qc.v[1] * pc.v[1];
+    });
+    const int slots[1] = {kPartPq};
+    write_partials<1, kBwBlock>(part, sp.grid, slots, acc);
+}
+
+// r~ -= alpha q~; partial sums of |sd r~| (the residual of A) and of r~.r~
+// (w.r); kUpdRows rows per thread like k_update<true>
+__global__ void __launch_bounds__(kCellBlock)
+k_update_scaled(SolverParams sp, const double *__restrict__ q, double *__restrict__ r, const double *__restrict__ sd,
+                double *__restrict__ part, const PcgState *__restrict__ st) {
+    if (st->done) return;
+    const double alpha = st->alpha;
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < kUpdRows; ++j) {
+        const int32_t c = cell_row<kUpdRows>(j);
+        if (c >= sp.n) continue;
+        const double rc = r[c] - alpha * __builtin_nontemporal_load(&q[c]);
+        r[c] = rc;
+        acc[0] += fabs(__builtin_nontemporal_load(&sd[c]) * rc);
+        acc[1] += rc * rc;
+    }
+    const int slots[2] = {kPartSumR, kPartWr};
+    write_partials<2>(part, sp.grid, slots, acc);
+}
+
+// end of a scaled solve: T = (x~ + alpha p~) / sd (the last pending update as
+// in k_commit); T untouched when no iteration ran; partial sums of the new T
+__global__ void __launch_bounds__(kCellBlock)
+k_commit_scaled(SolverParams sp, double *__restrict__ T, const double *__restrict__ xs,
+                const double *__restrict__ p, const double *__restrict__ sd, double *__restrict__ part,
+                const PcgState *__restrict__ st) {
+    const bool moved = st->n_iter >= 1;
+    const bool apply = !(st->n_iter < 1 || st->singular || st->nonfinite);
+    const double alpha = st->alpha;
+    const int32_t c = static_cast<int32_t>(blockIdx.x) * kCellBlock + static_cast<int32_t>(threadIdx.x);
+    double acc[1] = {0.0};
+    if (c < sp.n) {
+        double tc;
+        if (moved) {
+            // x~, p~ and sd are not read again before the next solve writes them
+            double xc = __builtin_nontemporal_load(&xs[c]);
+            if (apply) xc += alpha * __builtin_nontemporal_load(&p[c]);
+            tc = xc / __builtin_nontemporal_load(&sd[c]);
+            T[c] = tc;
+        } else {
+            tc = T[c];
+        }
+        acc[0] = tc;
     }
     const int slots[1] = {kPartSumX};
     write_partials<1>(part, sp.grid, slots, acc);
@@ -1623,7 +1737,13 @@ void carve_problem(Carver &cv, const lf_mesh *m, const lf_solver_opts &o, lf_pro
         T_old = cv.take<double>(N);
     }
     if (m->gface || m->gband) snb = cv.take<double>(B);
+    // the Jacobi-scaled coefficients of diagonal FP64 solves on the block walk
+    // (lf_problem_create decides; every problem that may take it has them)
+    double *coefS = nullptr;
+    if (o.precision == LF_PREC_FP64 && o.precond == LF_PC_DIAGONAL && use_bands(m, o) && m->n_bands == 3)
+        coefS = cv.take<double>(3 * N);
     if (P) {
+        P->coefS = coefS;
         P->grad3 = grad3; P->lap_src = lap_src; P->T_old = T_old; P->snb = snb;
         P->patch_type = pt; P->patch_value = pv;
         P->T = vec[0]; P->r = vec[1]; P->p = vec[2]; P->q = vec[3]; P->w = vec[4]; P->rD = vec[5];
@@ -1650,6 +1770,11 @@ static void launch_assemble_t(lf_problem *P, hipStream_t s) {
     // band meshes: the correction's source is formed inside the assembly
     // (the gradient pass still runs first)
     const bool fused = P->nonorth && P->banded && !P->rb && m->gkband;
+    // the set-up's form: 0 DIC or multigrid (r only), 1 diagonal (r, rD, p = w),
+    // 2 diagonal on the Jacobi-scaled system (the scaled r, p and x into w)
+    const bool js = kSetup && !kMixed && P->scaled;
+    const int32_t pc_mode = diag_pc ? (js ? 2 : 1) : 0;
+    double *xs = js ? P->w : nullptr;
     if (P->nonorth) launch_nonorth_source(P, s, !fused);
     with_layout(P, [&](auto lay) {
         using Lay = decltype(lay);
@@ -1660,8 +1785,8 @@ static void launch_assemble_t(lf_problem *P, hipStream_t s) {
                 LF_LAUNCH(P, LF_K_ASSEMBLE, s, kern, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, rdt, P->DT, lay,
                           m->rbface_start, m->rbface_list, m->bface_patch, m->bmag_sf, m->bdelta, P->patch_type,
                           P->patch_value, m->V, P->T, P->coef, P->upper, P->diag, P->source, P->diagB, P->srcB,
-                          P->int_coeff, P->bou_coeff, diag_pc ? 1 : 0, P->r, P->rD, P->part, P->state, P->sig32,
-                          P->r32, P->d32, P->p, nullptr, T_old, P->grad3, m->gkband);
+                          P->int_coeff, P->bou_coeff, pc_mode, P->r, P->rD, P->part, P->state, P->sig32,
+                          P->r32, P->d32, P->p, nullptr, T_old, P->grad3, m->gkband, xs);
                 return;
             }
         }
@@ -1679,8 +1804,8 @@ static void launch_assemble_t(lf_problem *P, hipStream_t s) {
         LF_LAUNCH(P, LF_K_ASSEMBLE, s, kern, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, rdt, P->DT, lay,
                   m->rbface_start, m->rbface_list, m->bface_patch, m->bmag_sf, m->bdelta, P->patch_type,
                   P->patch_value, m->V, P->T, P->coef, P->upper, P->diag, P->source, P->diagB, P->srcB,
-                  P->int_coeff, P->bou_coeff, diag_pc ? 1 : 0, P->r, P->rD, P->part, P->state, P->sig32,
-                  P->r32, P->d32, P->p, P->nonorth ? P->lap_src : nullptr, T_old, nullptr, nullptr);
+                  P->int_coeff, P->bou_coeff, pc_mode, P->r, P->rD, P->part, P->state, P->sig32,
+                  P->r32, P->d32, P->p, P->nonorth ? P->lap_src : nullptr, T_old, nullptr, nullptr, xs);
     });
     if (kFull && P->rb && m->F > 0)
         hipLaunchKernelGGL(k_rb_upper, dim3(static_cast<unsigned>((m->F + kCellBlock - 1) / kCellBlock)),
@@ -1719,13 +1844,22 @@ lf_status launch_assemble_setup(lf_problem *P, hipStream_t s) {
         P->scaled32 = true;
     } else {
         launch_assemble_t<false, true, false>(P, s);
+        if (P->scaled) {
+            const lf_mesh *m = P->mesh;
+            const unsigned g = static_cast<unsigned>((m->N / 2 + kCellBlock - 1) / kCellBlock);
+            LF_LAUNCH(P, LF_K_SCALE, s, k_scale_coef, dim3(g), dim3(kCellBlock), 0, s, band_layout<3>(m), P->rD,
+                      P->coef, P->coefS);
+        }
     }
     LF_HIP(hipGetLastError());
     return LF_OK;
 }
 
 static void launch_direction(lf_problem *P, hipStream_t s) {
-    if (P->opts.precond == LF_PC_DIAGONAL)
+    if (P->scaled)          // p~ = r~ + beta p~, x~ += alpha p~ (x~ in w)
+        LF_LAUNCH(P, LF_K_DIRECTION, s, k_direction<false>, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->rD,
+                  P->r, P->r, P->p, P->w, P->state);
+    else if (P->opts.precond == LF_PC_DIAGONAL)
         LF_LAUNCH(P, LF_K_DIRECTION, s, k_direction<true>, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->rD, P->r,
                   P->w, P->p, P->T, P->state);
     else
@@ -1800,6 +1934,11 @@ static lf_status launch_iteration(lf_problem *P, hipStream_t s) {
     const bool diag_pc = P->opts.precond == LF_PC_DIAGONAL;
     with_layout(P, [&](auto lay) {
         if constexpr (std::is_same_v<decltype(lay), BandLayout<3>>) {
+            if (P->scaled) {
+                LF_LAUNCH(P, LF_K_AMUL_DOT, s, k_amul_dot_box_scaled, dim3(static_cast<unsigned>(P->bw.blocks)),
+                          dim3(kBwBlock), 0, s, P->sp, lay, P->bw, P->coefS, P->p, P->q, P->part, P->state);
+                return;
+            }
             if (P->box) {
                 LF_LAUNCH(P, LF_K_AMUL_DOT, s, k_amul_dot_box, dim3(static_cast<unsigned>(P->bw.blocks)),
                           dim3(kBwBlock), 0, s, P->sp, lay, P->bw, P->diagB, P->coef, P->p, P->q, P->part, P->state);
@@ -1856,7 +1995,10 @@ static lf_status launch_iteration(lf_problem *P, hipStream_t s) {
         LF_HIP(hipGetLastError());
         return LF_OK;
     }
-    if (diag_pc) {
+    if (P->scaled) {
+        LF_LAUNCH(P, LF_K_UPDATE, s, k_update_scaled, dim3(static_cast<unsigned>(P->sp.grid_upd)),
+                  dim3(kCellBlock), 0, s, P->sp, P->q, P->r, P->rD, P->part, P->state);
+    } else if (diag_pc) {
         LF_LAUNCH(P, LF_K_UPDATE, s, k_update<true>, dim3(static_cast<unsigned>(P->sp.grid_upd)),
                   dim3(kCellBlock), 0, s, P->sp, P->q, P->r,
                   P->rD, P->part, P->state);
@@ -1978,8 +2120,12 @@ lf_status fp64_advance(lf_problem *P, SolveCtx &c, bool *finished, lf_solve_stat
     }
     if (P->h_state->done) {
         prof_lead(P, s);
-        LF_LAUNCH(P, LF_K_COMMIT, s, k_commit, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->T, P->p, P->part,
-                  P->state);
+        if (P->scaled)
+            LF_LAUNCH(P, LF_K_COMMIT, s, k_commit_scaled, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->T, P->w,
+                      P->p, P->rD, P->part, P->state);
+        else
+            LF_LAUNCH(P, LF_K_COMMIT, s, k_commit, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->T, P->p,
+                      P->part, P->state);
         LF_HIP(hipGetLastError());
         P->sumx_valid = true;
         LF_HIP(hipEventRecord(P->ev[2], s));

@@ -148,6 +148,10 @@ struct lf_problem {
                                                // (written by the FP64 commit; any other write of T clears it)
     bool fold = false;                         // small diagonal FP64 solves: the iteration's reductions folded
                                                // into the update and direction kernels
+    bool scaled = false;                       // diagonal FP64 solves on the block walk (not folded): CG on
+                                               // the Jacobi-scaled matrix; during a solve rD holds sqrt(diagB),
+                                               // r, p, q the scaled vectors and w the scaled iterate
+    double *coefS = nullptr;                   // [3N] its off-diagonal band coefficients
     // multigrid preconditioner: coarse levels 1.. (level 0 is the problem's own
     // band matrix) and two work vectors of level 0
     std::vector<lf::AmgLevel> amg;

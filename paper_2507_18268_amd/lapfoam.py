@@ -136,7 +136,8 @@ _SIGS = {
 KERNEL_CLASSES = ["assemble", "sum_x", "commit", "direction", "amul_dot", "update", "dic_rd",
                   "dic_forward", "dic_backward", "mixed_residual", "mixed_correct",
                   "inner_direction", "inner_amul_dot", "inner_update", "mixed_prep", "finalize",
-                  "amg_smooth", "amg_restrict", "amg_prolong", "amg_galerkin", "grad", "nonorth"]
+                  "amg_smooth", "amg_restrict", "amg_prolong", "amg_galerkin", "grad", "nonorth",
+                  "scale"]
 
 
 def lib():
@@ -578,7 +579,8 @@ class Problem:
 
     def amul_form(self):
         """0 one row per thread, 1 the row walk, 2 the block walk of a box,
-        3 DIC's kernels on the two-colour layout with two red-black pairs per lane."""
+        3 DIC's kernels on the two-colour layout with two red-black pairs per lane,
+        4 the block walk with the FP64 diagonal solve on the Jacobi-scaled matrix."""
         return lf_problem_amul_walk(self.h)
 
     def reset(self, bcs, DT, dt):

@@ -61,9 +61,10 @@ def test_full_size_matrix_and_amul_bitwise(L, oracle, cfg):
 def test_full_size_steps_match_oracle(L, oracle, cfg, steps):
     p = synth.build_config(cfg, steps=steps)
     m, P, pc = _problem(L, p)
-    # the forms the benchmark times: the block walk, one row per thread on the
-    # row layout, DIC's walk along z of the two-colour layout
-    assert P.amul_form() == {"graded_256": 2, "permuted_192": 0, "graded_256_dic": 3}[cfg]
+    # the forms the benchmark times: the block walk with the solve on the
+    # Jacobi-scaled matrix, one row per thread on the row layout, DIC's
+    # kernels with two red-black pairs per lane on the two-colour layout
+    assert P.amul_form() == {"graded_256": 4, "permuted_192": 0, "graded_256_dic": 3}[cfg]
     P.set_T(p.T0)
     sg, _ = P.step(steps)                  # one call for all steps, as the benchmark does
     Tg = P.get_T()
