@@ -86,7 +86,9 @@ typedef int32_t lf_status;
                               2048 workgroups of 512 threads, 8 rows each),
                               else one row per thread; the FP64 products of a
                               box then take the block walk
-                              (lf_problem_amul_walk) */
+                              (lf_problem_amul_walk), and so they do on any
+                              box that gives the block walk at least 2048
+                              workgroups of 256 threads (4.2 M cells and up) */
 #define LF_WALK_ON 1       /* the row walk whenever the layout allows it (tests) */
 #define LF_WALK_OFF 2      /* always one row per thread */
 

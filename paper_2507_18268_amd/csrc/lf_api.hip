@@ -177,16 +177,17 @@ lf_status lf_problem_create(const lf_mesh *m, const lf_patch_bc *bcs, double DT,
     if (P->banded && m->n_bands >= 2 && opts.amul_walk != LF_WALK_OFF) {
         // the walk's partials must fit the p.q slot of both solvers' reductions
         const int32_t wb = walk_blocks(m->N, m->band_d[1]);
-        if ((opts.amul_walk == LF_WALK_ON || wb >= kWalkMinBlocks) && wb <= P->sp.grid_mx) {
+        BoxWalk bw, bw32;
+        const bool box_plan = box_walk_plan(m->N, m->n_bands, m->band_d, 2, &bw);
+        if ((opts.amul_walk == LF_WALK_ON || wb >= kWalkMinBlocks || (box_plan && bw.blocks >= kBoxMinBlocks)) &&
+            wb <= P->sp.grid_mx) {
             P->walk = true;
             P->sp.grid_amul = wb;
             P->sp.grid_mx_amul = wb;
         }
         // the products of a box take the block walk: two FP64 rows or four
         // FP32 rows per lane (its partials must fit the same slots)
-        BoxWalk bw, bw32;
-        if (P->walk && box_walk_plan(m->N, m->n_bands, m->band_d, 2, &bw) && bw.blocks <= P->sp.grid_mx &&
-            bw.blocks <= P->sp.grid) {
+        if (P->walk && box_plan && bw.blocks <= P->sp.grid_mx && bw.blocks <= P->sp.grid) {
             P->box = true;
             P->bw = bw;
             P->sp.grid_amul = bw.blocks;

@@ -60,6 +60,9 @@ struct PcgState {
 constexpr int bw_lines(int) { return 2; }
 constexpr int bw_planes(int W) { return W == 2 ? 2 : 1; }
 constexpr int kBwBlock = 256;       // threads of a block-walk workgroup
+// a box takes the block walk from this many of its workgroups (4.2 M cells and
+// up) whatever the row walk's workgroup count
+constexpr int kBoxMinBlocks = 2048;
 
 // host-side plan of a block walk with W x-adjacent rows per lane
 struct BoxWalk {

@@ -142,3 +142,19 @@ def test_scaled_corrected_steps_on_skewed_box(L, oracle):
         assert abs(st[0]["n_iter"] - so[s]["n_iter"]) <= 3, (s, st[0], so[s])
     P.close()
     m.close()
+
+
+def test_scaled_by_default_on_a_4m_box(L, oracle):
+    """A 170x160x160 box (4.35 M cells, 2125 block-walk workgroups) takes the
+    block walk and the scaled solve with the default options (the row walk
+    alone would not fill the GPU): one step against the oracle's."""
+    mesh = synth.box_mesh(170, 160, 160, z_ratio=10.0)
+    T0 = synth.initial_field(mesh.n_cells, 35)
+    m, P, form, Ts, st = _steps(L, mesh, DT, dt, T0, 1)
+    assert form == 4, form
+    P.close()
+    m.close()
+    To, so, _ = oracle.run(mesh, synth.fixed_x_bcs(), DT, dt, 1, T0)
+    assert max_rel(Ts[0], To) <= T_TOL, max_rel(Ts[0], To)
+    assert abs(st[0]["n_iter"] - so[0]["n_iter"]) <= 1, (st[0], so[0])
+    assert st[0]["converged"] == 1
