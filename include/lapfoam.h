@@ -330,8 +330,9 @@ lf_status lf_problem_layout(const lf_problem *problem, int32_t *layout);
 
 /* How the problem's FP64 matrix-vector products run: 0 one row per thread,
  * 1 the row walk, 2 the block walk of a box (a band layout with offsets 1, nx,
- * nx ny, nx even and N even, whenever the row walk is chosen for it: two
- * x-adjacent rows per lane, two lines by two planes per thread).  With 2 the
+ * nx ny, nx even and N even, whenever the row walk is chosen for it or the
+ * block walk has at least 2048 workgroups: two x-adjacent rows per lane, two
+ * lines by two planes per thread).  With 2 the
  * inner FP32 products of LF_PREC_MIXED take the block walk too when nx is a
  * multiple of 4 (four rows per lane), else the row walk; with 1 the row walk.
  * 3: DIC on the two-colour band layout with x-lines of a multiple of four

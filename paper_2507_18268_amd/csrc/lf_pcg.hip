@@ -546,21 +546,32 @@ k_amul_dot_box_scaled(SolverParams sp, BandLayout<3> L, BoxWalk bw, const double
 }
 
 // r~ -= alpha q~; partial sums of |sd r~| (the residual of A) and of r~.r~
-// (w.r); kUpdRows rows per thread like k_update<true>
+// (w.r); kUpdRows rows per thread like k_update<true>, two adjacent rows per
+// 16-byte access (N is even on every box with the block walk)
 __global__ void __launch_bounds__(kCellBlock)
 k_update_scaled(SolverParams sp, const double *__restrict__ q, double *__restrict__ r, const double *__restrict__ sd,
                 double *__restrict__ part, const PcgState *__restrict__ st) {
     if (st->done) return;
+    typedef Lanes<double, 2> R;
+    typedef Lanes<double, 2>::vec V;
     const double alpha = st->alpha;
     double acc[2] = {0.0, 0.0};
 #pragma unroll
-    for (int j = 0; j < kUpdRows; ++j) {
-        const int32_t c = cell_row<kUpdRows>(j);
+    for (int j = 0; j < kUpdRows / 2; ++j) {
+        const int64_t c = 2 * static_cast<int64_t>(cell_row<kUpdRows / 2>(j));
         if (c >= sp.n) continue;
-        const double rc = r[c] - alpha * __builtin_nontemporal_load(&q[c]);
-        r[c] = rc;
-        acc[0] += fabs(__builtin_nontemporal_load(&sd[c]) * rc);
-        acc[1] += rc * rc;
+        const R qc = lanes_load<double, 2, true>(q, c);
+        const R sc = lanes_load<double, 2, true>(sd, c);
+        const R r0 = lanes_load<double, 2>(r, c);
+        V y;
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            const double rc = r0.v[w] - alpha * qc.v[w];
+            y[w] = rc;
+            acc[0] += fabs(sc.v[w] * rc);
+            acc[1] += rc * rc;
+        }
+        *reinterpret_cast<V *>(r + c) = y;
     }
     const int slots[2] = {kPartSumR, kPartWr};
     write_partials<2>(part, sp.grid, slots, acc);
