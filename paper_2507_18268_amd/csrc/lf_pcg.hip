@@ -577,6 +577,42 @@ k_update_scaled(SolverParams sp, const double *__restrict__ q, double *__restric
     write_partials<2>(part, sp.grid, slots, acc);
 }
 
+// p~ = r~ + beta p~ with the deferred x~ += alpha p~ of the iteration before,
+// as k_direction does for w = r~ (scaled solve): kUpdRows rows per thread,
+// two adjacent rows per 16-byte access, on the update's grid
+__global__ void __launch_bounds__(kCellBlock)
+k_direction_scaled(SolverParams sp, const double *__restrict__ r, double *__restrict__ p, double *__restrict__ xs,
+                   const PcgState *__restrict__ st) {
+    if (st->done) return;
+    typedef Lanes<double, 2> R;
+    typedef Lanes<double, 2>::vec V;
+    const bool first = st->n_iter == 0;
+    const double beta = st->beta, alpha = st->alpha;
+#pragma unroll
+    for (int j = 0; j < kUpdRows / 2; ++j) {
+        const int64_t c = 2 * static_cast<int64_t>(cell_row<kUpdRows / 2>(j));
+        if (c >= sp.n) continue;
+        const R rc = lanes_load<double, 2>(r, c);
+        V pn;
+        if (first) {
+#pragma unroll
+            for (int w = 0; w < 2; ++w) pn[w] = rc.v[w];
+        } else {
+            const R pc = lanes_load<double, 2>(p, c);
+            const R xc = lanes_load<double, 2, true>(xs, c);
+            V xn;
+#pragma unroll
+            for (int w = 0; w < 2; ++w) {
+                xn[w] = xc.v[w] + alpha * pc.v[w];
+                pn[w] = rc.v[w] + beta * pc.v[w];
+            }
+            // x~ is next needed an iteration later: past the caches
+            __builtin_nontemporal_store(xn, reinterpret_cast<V *>(xs + c));
+        }
+        *reinterpret_cast<V *>(p + c) = pn;
+    }
+}
+
 // end of a scaled solve: T = (x~ + alpha p~) / sd (the last pending update as
 // in k_commit); T untouched when no iteration ran; partial sums of the new T
 __global__ void __launch_bounds__(kCellBlock)
@@ -1868,8 +1904,8 @@ lf_status launch_assemble_setup(lf_problem *P, hipStream_t s) {
 
 static void launch_direction(lf_problem *P, hipStream_t s) {
     if (P->scaled)          // p~ = r~ + beta p~, x~ += alpha p~ (x~ in w)
-        LF_LAUNCH(P, LF_K_DIRECTION, s, k_direction<false>, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->rD,
-                  P->r, P->r, P->p, P->w, P->state);
+        LF_LAUNCH(P, LF_K_DIRECTION, s, k_direction_scaled, dim3(static_cast<unsigned>(P->sp.grid_upd)),
+                  dim3(kCellBlock), 0, s, P->sp, P->r, P->p, P->w, P->state);
     else if (P->opts.precond == LF_PC_DIAGONAL)
         LF_LAUNCH(P, LF_K_DIRECTION, s, k_direction<true>, cell_grid(P), dim3(kCellBlock), 0, s, P->sp, P->rD, P->r,
                   P->w, P->p, P->T, P->state);
