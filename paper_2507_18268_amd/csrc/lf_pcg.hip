@@ -505,25 +505,30 @@ k_commit(SolverParams sp, double *__restrict__ x, const double *__restrict__ p, 
 // ---------------------------------------------------------------------------
 
 // coefficients of S A S in the band layout: slot k of row c holds
-// a / (sd_c sd_{c+d_k}), 0 where the band has no face (two rows per thread, N
-// even as on every box with the block walk)
+// a / (sd_c sd_{c+d_k}), 0 where the band has no face.  Two rows per thread;
+// on every box with the block walk N, nx and nx ny are even (offsets 1, nx,
+// nx ny), so the y and z neighbours' sd are 16-byte loads too, and row c's x
+// neighbour is the thread's own row c + 1
 __global__ void __launch_bounds__(kCellBlock)
 k_scale_coef(BandLayout<3> L, const double *__restrict__ sd, const double *__restrict__ coef,
              double *__restrict__ coefS) {
     typedef Lanes<double, 2> R;
+    const int64_t n = L.n;
     const int64_t c = 2 * (static_cast<int64_t>(blockIdx.x) * kCellBlock + threadIdx.x);
-    if (c >= L.n) return;
+    if (c >= n) return;
     const R s = lanes_load<double, 2>(sd, c);
+    R sn[3];
+    sn[0].v[0] = s.v[1];
+    sn[0].v[1] = c + 2 < n ? sd[c + 2] : 1.0;
+#pragma unroll
+    for (int k = 1; k < 3; ++k) sn[k] = c + L.d[k] < n ? lanes_load<double, 2>(sd, c + L.d[k]) : s;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const int64_t o = k * L.n + c;
+        const int64_t o = k * n + c;
         const R a = lanes_load<double, 2, true>(coef, o);
         R y;
 #pragma unroll
-        for (int w = 0; w < 2; ++w) {
-            const int64_t j = c + w + L.d[k];
-            y.v[w] = j < L.n ? a.v[w] / (s.v[w] * sd[j]) : 0.0;
-        }
+        for (int w = 0; w < 2; ++w) y.v[w] = c + w + L.d[k] < n ? a.v[w] / (s.v[w] * sn[k].v[w]) : 0.0;
         lanes_store_stream(coefS, o, y);
     }
 }
