@@ -158,3 +158,32 @@ def test_scaled_by_default_on_a_4m_box(L, oracle):
     assert max_rel(Ts[0], To) <= T_TOL, max_rel(Ts[0], To)
     assert abs(st[0]["n_iter"] - so[0]["n_iter"]) <= 1, (st[0], so[0])
     assert st[0]["converged"] == 1
+
+
+def test_scaled_step_begin_poll_equals_step(L):
+    """lf_step_begin / lf_step_poll on a problem in the scaled form: bitwise the
+    snapshots and stats of stepping one step at a time."""
+    import torch
+    mesh = synth.box_mesh(130, 97, 91, z_ratio=4.0)
+    N = mesh.n_cells
+    T0 = synth.initial_field(N, 36)
+    steps = 3
+    m, A, form, ref, sref = _steps(L, mesh, DT, dt, T0, steps, amul_walk=L.LF_WALK_ON)
+    assert form == 4
+    B = L.Problem(m, synth.fixed_x_bcs(), DT, dt, L.make_opts(amul_walk=L.LF_WALK_ON))
+    B.set_T(T0)
+    snap = torch.empty(steps * N, dtype=torch.float64, device="cuda")
+    B.step_begin(steps, snap)
+    while True:
+        done, finished, stats, status = B.step_poll()
+        if finished:
+            break
+    assert status == L.LF_OK and done == steps
+    got = snap.view(steps, N).cpu().numpy()
+    for s in range(steps):
+        assert np.array_equal(got[s], ref[s]), s
+        assert stats[s]["n_iter"] == sref[s]["n_iter"]
+        assert stats[s]["final_residual"] == sref[s]["final_residual"]
+    A.close()
+    B.close()
+    m.close()
